@@ -1,0 +1,350 @@
+"""FP64 CPU oracle for the SpeedyGS structural-formation (RD) step.
+
+TEST INFRASTRUCTURE ONLY: this package is imported by ``tests/``, by
+``__graft_entry__.smoke()`` and by the CPU-baseline leg of ``bench.py``, and by
+nothing else.  It never imports the HIP package, and the HIP package never
+imports it.  The arithmetic lives in ``oracle.c`` (plain C, FP64, built with
+gcc, no contraction); this module only marshals numpy arrays.
+
+Each function names the paper passage it follows; see ``oracle.c`` for the
+formulas.  Parity-unpinned constants (near plane 0.2, low-pass dilation 0.3,
+3-sigma radius, alpha bounds 1/255 and 0.99, transmittance floor 1e-4, colour
+offset 1/2, background 0, field-of-view clamp 1.3) are conventions: the paper
+does not state them.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+NCH = 59
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SRC = [os.path.join(HERE, "oracle.c"), os.path.join(HERE, "oracle_mlp.c")]
+
+TW_DEFAULT = 16
+TH_DEFAULT = 16
+
+
+def build() -> str:
+    """Compile liboracle.so with gcc (FP64, no floating-point contraction)."""
+    srcs = [s for s in SRC if os.path.exists(s)]
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-o", LIB + ".tmp", *srcs, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        stale = (not os.path.exists(LIB)) or any(
+            os.path.exists(s) and os.path.getmtime(s) > os.path.getmtime(LIB) for s in SRC)
+        if stale:
+            build()
+        _lib = C.CDLL(LIB)
+        _declare(_lib)
+    return _lib
+
+
+P = C.c_void_p
+I64 = C.c_int64
+I32 = C.c_int32
+U64 = C.c_uint64
+F32 = C.c_float
+F64 = C.c_double
+
+
+def _declare(L):
+    sig = {
+        "orc_uniform": (F32, [U64, U64, U64]),
+        "orc_exp_dl": (F32, [F32]),
+        "orc_fakequant": (None, [I64, I64, P, P, P, P]),
+        "orc_mask": (None, [I64, C.c_int, P, P, U64, U64, F64, P, P]),
+        "orc_rate_proxy": (None, [I64, I64, P, P, P, I64, F64, P, P, P, P, P, P, P]),
+        "orc_fakequant_bwd": (None, [I64, I64, P, P, P, C.c_int, P, F64, P, P, P, P]),
+        "orc_decide": (None, [I64, I64, P, I32, P, I32, I32, I32, I32, P, P, P, P, P, P]),
+        "orc_bin": (I64, [I64, I32, P, P, P, I32, I32, I32, I32, P, P, P]),
+        "orc_forward": (I64, [I64, I64, P, P, I32, P, I32, I32, I32, I32, P, P, P, P,
+                              P, P, P, P]),
+        "orc_forward_brute": (I64, [I64, I64, P, P, I32, P, I32, I32, P, P, P, P, P]),
+        "orc_backward": (None, [I64, I64, P, P, I32, P, I32, I32, I32, I32, P, P, P, P,
+                                P, P, P, P]),
+        "orc_project64": (None, [I64, I64, P, I32, P, I32, I32, P, P]),
+        "orc_l1": (F64, [I64, P, P, P]),
+        "orc_sh_basis": (None, [I64, P, P]),
+        "orc_fixed_length_bits": (I64, [I64, I64, P, P, P, P, P]),
+        "orc_fixed_length_pack": (None, [I64, I64, P, P, P, P, P]),
+        "orc_fixed_length_unpack": (None, [I64, I64, P, P, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        if not hasattr(L, name):
+            continue
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    try:
+        from . import mlp as _mlp  # noqa: F401  (declares the MLP entry points)
+        _mlp._declare(L)
+    except ImportError:
+        pass
+
+
+def _p(a: np.ndarray | None):
+    if a is None:
+        return None
+    assert a.flags.c_contiguous, "oracle arrays must be C-contiguous"
+    return a.ctypes.data
+
+
+# --------------------------------------------------------------------------
+# a1-a3, a12: quantizer, mask, rate proxy
+# --------------------------------------------------------------------------
+
+def uniform(seed: int, step: int, i: int) -> float:
+    return float(lib().orc_uniform(seed, step, i))
+
+
+def exp_dl(x: float) -> float:
+    return float(lib().orc_exp_dl(np.float32(x)))
+
+
+def fakequant(y: np.ndarray, q: np.ndarray, n: int):
+    """Sec. 3.3.1 uniform quantizer: k = rint(y/q), yhat = fl32(k q)."""
+    y = np.ascontiguousarray(y, np.float32)
+    q = np.ascontiguousarray(q, np.float32)
+    npad = y.shape[1]
+    yhat = y.copy()
+    k = np.zeros(y.shape, np.int32)
+    lib().orc_fakequant(n, npad, _p(y), _p(q), _p(yhat), _p(k))
+    return yhat, k
+
+
+def mask(n: int, mode: int, given: np.ndarray | None, score: np.ndarray | None,
+         seed: int = 0, step: int = 0, tau: float = 1.0):
+    """Sec. 3.3.1 retention mask. mode 0 given, 1 Gumbel-sigmoid, 2 keep all."""
+    given = np.ascontiguousarray(given if given is not None else np.ones(n, np.uint8), np.uint8)
+    score = np.ascontiguousarray(score if score is not None else np.zeros(n, np.float32), np.float32)
+    mh = np.zeros(n, np.uint8)
+    ms = np.zeros(n, np.float64)
+    lib().orc_mask(n, mode, _p(given), _p(score), seed, step, tau, _p(mh), _p(ms))
+    return mh, ms
+
+
+def rate_proxy(y: np.ndarray, q: np.ndarray, mhat: np.ndarray, n: int, n_hat: int,
+               lam: float = 0.0):
+    """Sec. 3.3.1: R_proxy = L_mask * L_quant (and its gradient when lam != 0)."""
+    y = np.ascontiguousarray(y, np.float32)
+    q = np.ascontiguousarray(q, np.float32)
+    mhat = np.ascontiguousarray(mhat, np.uint8)
+    npad = y.shape[1]
+    out3 = np.zeros(3)
+    amin = np.zeros(NCH, np.int32)
+    amax = np.zeros(NCH, np.int32)
+    cj = np.zeros(NCH)
+    gy = np.zeros(y.shape)
+    gq = np.zeros(NCH)
+    gm = np.zeros(n)
+    lib().orc_rate_proxy(n, npad, _p(y), _p(q), _p(mhat), n_hat, lam, _p(out3), _p(amin),
+                         _p(amax), _p(cj), _p(gy), _p(gq), _p(gm))
+    return dict(R=out3[0], Lq=out3[1], Lm=out3[2], argmin=amin, argmax=amax, c=cj,
+                gy=gy, gq=gq, gm=gm)
+
+
+def fakequant_bwd(y, q, gyhat, mode, msoft, tau, gmhat, n):
+    y = np.ascontiguousarray(y, np.float32)
+    q = np.ascontiguousarray(q, np.float32)
+    gyhat = np.ascontiguousarray(gyhat, np.float64)
+    msoft = np.ascontiguousarray(msoft, np.float64)
+    gmhat = np.ascontiguousarray(gmhat, np.float64)
+    gy = np.zeros(y.shape)
+    gq = np.zeros(NCH)
+    gs = np.zeros(n)
+    lib().orc_fakequant_bwd(n, y.shape[1], _p(y), _p(q), _p(gyhat), mode, _p(msoft), tau,
+                            _p(gmhat), _p(gy), _p(gq), _p(gs))
+    return gy, gq, gs
+
+
+# --------------------------------------------------------------------------
+# a4-a7: decision layer, binning, sort order, ranges
+# --------------------------------------------------------------------------
+
+@dataclass
+class Structure:
+    valid: np.ndarray   # int32 [V][n]
+    tz: np.ndarray      # float32 [V][n]
+    pxy: np.ndarray     # float32 [V][n][2]
+    span: np.ndarray    # int32 [V][n][4]  x0, x1, y0, y1 (inclusive)
+    radius: np.ndarray  # int32 [V][n]
+    tiles: np.ndarray   # int32 [V][n]
+    keys: np.ndarray    # uint64 [P]  (global tile << 32) | bits(t_z)
+    vals: np.ndarray    # uint32 [P]  Gaussian index
+    ranges: np.ndarray  # uint32 [V*tiles][2]
+    TW: int
+    TH: int
+
+
+def decide(yhat: np.ndarray, n: int, cams: np.ndarray, W: int, H: int,
+           TW: int = TW_DEFAULT, TH: int = TH_DEFAULT) -> Structure:
+    yhat = np.ascontiguousarray(yhat, np.float32)
+    cams = np.ascontiguousarray(cams, np.float32)
+    V = cams.shape[0]
+    valid = np.zeros((V, n), np.int32)
+    tz = np.zeros((V, n), np.float32)
+    pxy = np.zeros((V, n, 2), np.float32)
+    span = np.zeros((V, n, 4), np.int32)
+    radius = np.zeros((V, n), np.int32)
+    tiles = np.zeros((V, n), np.int32)
+    L = lib()
+    L.orc_decide(n, yhat.shape[1], _p(yhat), V, _p(cams), W, H, TW, TH, _p(valid), _p(tz),
+                 _p(pxy), _p(span), _p(radius), _p(tiles))
+    Pn = L.orc_bin(n, V, _p(valid), _p(tz), _p(span), W, H, TW, TH, None, None, None)
+    GW, GH = (W + TW - 1) // TW, (H + TH - 1) // TH
+    keys = np.zeros(max(Pn, 1), np.uint64)
+    vals = np.zeros(max(Pn, 1), np.uint32)
+    ranges = np.zeros((V * GW * GH, 2), np.uint32)
+    L.orc_bin(n, V, _p(valid), _p(tz), _p(span), W, H, TW, TH, _p(keys), _p(vals), _p(ranges))
+    return Structure(valid, tz, pxy, span, radius, tiles, keys[:Pn], vals[:Pn], ranges, TW, TH)
+
+
+# --------------------------------------------------------------------------
+# a8-a11: render forward / backward, L1
+# --------------------------------------------------------------------------
+
+def forward(p64: np.ndarray, mask64: np.ndarray, n: int, cams: np.ndarray, W: int, H: int,
+            st: Structure):
+    """Sec. 3.1 compositing over the (tile, depth) lists. FP64."""
+    p64 = np.ascontiguousarray(p64, np.float64)
+    mask64 = np.ascontiguousarray(mask64, np.float64)
+    cams = np.ascontiguousarray(cams, np.float32)
+    V = cams.shape[0]
+    img = np.zeros((V, 3, H, W))
+    T = np.zeros((V, H, W))
+    last = np.zeros((V, H, W), np.int32)
+    margin = np.zeros((V, H, W), np.uint8)
+    vals = st.vals if st.vals.size else np.zeros(1, np.uint32)
+    E = lib().orc_forward(n, p64.shape[1], _p(p64), _p(mask64), V, _p(cams), W, H, st.TW, st.TH,
+                          _p(st.valid), _p(st.span), _p(vals), _p(st.ranges), _p(img), _p(T),
+                          _p(last), _p(margin))
+    return dict(image=img, T=T, last=last, margin=margin, evals=int(E))
+
+
+def forward_brute(p64, mask64, n, cams, W, H, st: Structure):
+    """Definition: every pixel composites ALL splats in global depth order."""
+    p64 = np.ascontiguousarray(p64, np.float64)
+    mask64 = np.ascontiguousarray(mask64, np.float64)
+    cams = np.ascontiguousarray(cams, np.float32)
+    V = cams.shape[0]
+    img = np.zeros((V, 3, H, W))
+    T = np.zeros((V, H, W))
+    E = lib().orc_forward_brute(n, p64.shape[1], _p(p64), _p(mask64), V, _p(cams), W, H,
+                                _p(st.valid), _p(st.tz), _p(st.span), _p(img), _p(T))
+    return dict(image=img, T=T, evals=int(E))
+
+
+def backward(p64, mask64, n, cams, W, H, st: Structure, dimage, want_splat: bool = False):
+    p64 = np.ascontiguousarray(p64, np.float64)
+    mask64 = np.ascontiguousarray(mask64, np.float64)
+    cams = np.ascontiguousarray(cams, np.float32)
+    dimage = np.ascontiguousarray(dimage, np.float64)
+    V = cams.shape[0]
+    gp = np.zeros(p64.shape)
+    gm = np.zeros(n)
+    gs = np.zeros((V, n, 10)) if want_splat else None
+    vals = st.vals if st.vals.size else np.zeros(1, np.uint32)
+    lib().orc_backward(n, p64.shape[1], _p(p64), _p(mask64), V, _p(cams), W, H, st.TW, st.TH,
+                       _p(st.valid), _p(st.span), _p(vals), _p(st.ranges), _p(dimage), _p(gp),
+                       _p(gm), _p(gs))
+    return gp, gm, gs
+
+
+def project64(p64, n, cams, W, H, st: Structure):
+    p64 = np.ascontiguousarray(p64, np.float64)
+    cams = np.ascontiguousarray(cams, np.float32)
+    V = cams.shape[0]
+    out = np.zeros((V, n, 9))
+    lib().orc_project64(n, p64.shape[1], _p(p64), V, _p(cams), W, H, _p(st.valid), _p(out))
+    return out
+
+
+def l1(image: np.ndarray, target: np.ndarray):
+    image = np.ascontiguousarray(image, np.float64)
+    target = np.ascontiguousarray(target, np.float32)
+    d = np.zeros(image.shape)
+    D = lib().orc_l1(image.size, _p(image), _p(target), _p(d))
+    return float(D), d
+
+
+def sh_basis(dirs: np.ndarray) -> np.ndarray:
+    dirs = np.ascontiguousarray(dirs, np.float64)
+    Y = np.zeros((dirs.shape[0], 16))
+    lib().orc_sh_basis(dirs.shape[0], _p(dirs), _p(Y))
+    return Y
+
+
+# --------------------------------------------------------------------------
+# Sec. 3.4.1: channel-wise fixed-length code length
+# --------------------------------------------------------------------------
+
+def fixed_length_bits(k: np.ndarray, mhat: np.ndarray, n: int):
+    k = np.ascontiguousarray(k, np.int32)
+    mhat = np.ascontiguousarray(mhat, np.uint8)
+    kmin = np.zeros(NCH, np.int32)
+    kmax = np.zeros(NCH, np.int32)
+    width = np.zeros(NCH, np.int32)
+    bits = lib().orc_fixed_length_bits(n, k.shape[1], _p(k), _p(mhat), _p(kmin), _p(kmax),
+                                       _p(width))
+    return int(bits), kmin, kmax, width
+
+
+def fixed_length_roundtrip(k: np.ndarray, mhat: np.ndarray, n: int):
+    bits, kmin, kmax, width = fixed_length_bits(k, mhat, n)
+    payload = bits - NCH * 72
+    buf = np.zeros((payload + 7) // 8 + 1, np.uint8)
+    L = lib()
+    L.orc_fixed_length_pack(n, k.shape[1], _p(np.ascontiguousarray(k, np.int32)),
+                            _p(np.ascontiguousarray(mhat, np.uint8)), _p(kmin), _p(width), _p(buf))
+    out = np.zeros_like(k, dtype=np.int32)
+    L.orc_fixed_length_unpack(n, k.shape[1], _p(buf), _p(np.ascontiguousarray(mhat, np.uint8)),
+                              _p(kmin), _p(width), _p(out))
+    return out, buf, bits
+
+
+# --------------------------------------------------------------------------
+# One whole RD step (plain rate proxy): loss = L1(render) + lam * R_proxy
+# --------------------------------------------------------------------------
+
+def rd_step(params, qstep, score, given_mask, cams, W, H, target, n, n_hat, lam,
+            mask_mode=0, seed=0, step=0, tau=1.0, TW=TW_DEFAULT, TH=TH_DEFAULT,
+            dimage=None):
+    """Forward and backward of D_render + lam * R_proxy [Sec. 3.3.2 total loss].
+
+    ``dimage`` overrides dL/dimage (to feed both sides the same upstream
+    gradient when L1's sign decision sits at a rounding margin).
+    """
+    yhat, k = fakequant(params, qstep, n)
+    mh, ms = mask(n, mask_mode, given_mask, score, seed, step, tau)
+    rp = rate_proxy(params, qstep, mh, n, n_hat, lam)
+    st = decide(yhat, n, cams, W, H, TW, TH)
+    p64 = yhat.astype(np.float64)
+    m64 = mh.astype(np.float64)
+    fw = forward(p64, m64, n, cams, W, H, st)
+    D, d_img = l1(fw["image"], target)
+    if dimage is not None:
+        d_img = np.asarray(dimage, np.float64)
+    gyhat, gmh, _ = backward(p64, m64, n, cams, W, H, st, d_img)
+    gmh_total = gmh + rp["gm"]
+    gy, gq, gs = fakequant_bwd(params, qstep, gyhat, mask_mode, ms, tau, gmh_total, n)
+    gy = gy + rp["gy"]
+    gq = gq + rp["gq"]
+    return dict(yhat=yhat, k=k, mhat=mh, msoft=ms, rate=rp, st=st, fw=fw, D=D,
+                loss=D + lam * rp["R"], dimage=d_img, gyhat=gyhat, gmhat=gmh,
+                gmhat_total=gmh_total, gy=gy, gq=gq, gs=gs)
