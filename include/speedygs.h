@@ -1,0 +1,177 @@
+/*
+ * speedygs.h -- C ABI of libspeedygs.so: one rate-distortion (RD) step of the
+ * structural-formation stage of SpeedyGS on an AMD Instinct MI355X (gfx950).
+ *
+ * The step solves the paper's formation problem (Sec. 3.2, Eq. "sf"):
+ *     min over (G, Q, M) of  D_render(G, Q, M) + lambda * R_formation(G, Q, M)
+ * G = the 59 channels of every Gaussian (`params`), Q = the 59 channel step
+ * sizes (`qstep`), M = the per-Gaussian retention scores (`score`).  A step is
+ *     sgs_fakequant_prune -> sgs_rate_proxy -> sgs_render_fwd -> sgs_l1_loss
+ *     -> sgs_render_bwd -> sgs_fakequant_prune_bwd.
+ *
+ * Conventions common to every call
+ *  - Device pointers are HIP device memory owned by the caller; the library
+ *    never frees or keeps them beyond the call.  Host pointers are marked.
+ *  - Every call only enqueues work on the stream given to sgs_create (HIP
+ *    stream order gives the dependencies).  The exception is sgs_render_fwd,
+ *    which reads the pair count back to the host once (it sizes the sort).
+ *  - Gaussian parameters are SoA float32 [59][npad], npad a multiple of 64,
+ *    256-byte aligned rows.  Channels: 0-2 mean, 3-5 SH DC (r,g,b), 6-50 SH
+ *    k=1..15 coefficient-major (6 + 3(k-1) + c), 51 opacity logit,
+ *    52-54 log-scale, 55-58 rotation quaternion (w,x,y,z).
+ *  - Images are float32 [V][3][H][W]; per-pixel buffers [V][H][W].
+ *  - A context is not thread-safe; calls on one context must not overlap.
+ *  - On a non-OK status nothing has been enqueued unless the status is
+ *    SGS_EHIP (a launch failed); sgs_last_error() explains.
+ */
+#ifndef SPEEDYGS_H
+#define SPEEDYGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SGS_NCH 59
+/* uint64 words of the per-channel statistics buffer written by
+ * sgs_fakequant_prune: [0,59) min keys, [59,118) max keys, [118] kept count,
+ * [119] flags (bit 0: some q_j <= 0 or not finite).  A min key is
+ * (order-preserving bits of the value << 32) | index; a max key stores
+ * 0xFFFFFFFF - index in its low half, so both select the lowest index on ties. */
+#define SGS_STATS_WORDS 128
+/* float32 words of the compact rate-proxy gradient written by sgs_rate_proxy:
+ * [0,59) d/dy at argmax_j, [64,123) d/dy at argmin_j, [128,187) d/dq_j,
+ * [192] d/dM (same for every Gaussian). */
+#define SGS_RATE_GRAD_FLOATS 256
+
+typedef struct sgs_ctx sgs_ctx;
+
+typedef enum {
+  SGS_OK = 0,
+  SGS_EINVAL = -1,    /* bad argument; nothing enqueued */
+  SGS_ENOMEM = -2,    /* device allocation failed; context still usable */
+  SGS_EHIP = -3,      /* a HIP call or launch failed */
+  SGS_ESTATE = -4,    /* call out of order (e.g. render before set_scene) */
+  SGS_ECAPACITY = -5  /* a size limit of the library was exceeded */
+} sgs_status;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward); pixel (u, v) has
+ * its centre at image coordinate (u, v).  19 floats. */
+typedef struct {
+  float R[9];      /* world -> camera rotation, row-major */
+  float t[3];      /* world -> camera translation */
+  float fx, fy, cx, cy;
+  float campos[3]; /* camera centre in world coordinates (SH view direction) */
+} sgs_camera;
+
+typedef struct {
+  int32_t tile_w, tile_h; /* blend tile: 8x8, 16x16 (default) or 32x8 */
+  float tau;              /* Gumbel-sigmoid temperature (default 1) */
+  int32_t reserved[5];    /* must be zero */
+} sgs_options;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the context. */
+sgs_status sgs_create(sgs_ctx **out, int device, void *hip_stream);
+void sgs_destroy(sgs_ctx *ctx);
+/* Message for the last non-OK status of this context (never NULL). */
+const char *sgs_last_error(const sgs_ctx *ctx);
+/* Replace the stream later calls enqueue on. */
+sgs_status sgs_set_stream(sgs_ctx *ctx, void *hip_stream);
+
+/* Bind the scene shape and cameras and allocate the context's scratch.
+ * n Gaussians (n >= 1), npad >= n and a multiple of 64, n_hat = number of
+ * Gaussians before structural formation (Sec. 3.3.1, L_mask), views >= 1
+ * cameras (host array, copied), width/height in pixels (<= 32768), opt host
+ * (NULL = defaults).  Synchronizes the stream. */
+sgs_status sgs_set_scene(sgs_ctx *ctx, int64_t n, int64_t npad, int64_t n_hat,
+                         const sgs_camera *cams, int32_t views, int32_t width,
+                         int32_t height, const sgs_options *opt);
+
+/* a1-a2 (Sec. 3.3.1, uniform quantizer with learnable q_j; p_i = sigma(s_i);
+ * M_i = GumbelSoftmax(p_i); hard mask).
+ *   qparams[j][i] = q_j * rint(params[j][i] / q_j)   (FP32, ties to even)
+ *   mask_mode 0: hard_mask = given_mask (score unused);
+ *             1: Gumbel-sigmoid: u from SplitMix64(seed ^ ((step << 32) + i)),
+ *                hard = [u (1 + e^s) > 1] (= [s + logit u > 0]),
+ *                soft = sigmoid((s + logit u) / tau);
+ *             2: keep every Gaussian.
+ *   soft_mask (may be NULL unless mode 1 is used in the backward) = float [n].
+ *   stats: SGS_STATS_WORDS device words; per-channel min/max/argmin/argmax of
+ *   the RAW params over all n Gaussians and the kept count (rate proxy input).
+ * Device-side errors (q_j <= 0 or not finite) set stats[119] bit 0. */
+sgs_status sgs_fakequant_prune(sgs_ctx *ctx, const float *params, const float *qstep,
+                               const float *score, int32_t mask_mode,
+                               const uint8_t *given_mask, uint64_t seed, uint64_t step,
+                               float *qparams, uint8_t *hard_mask, float *soft_mask,
+                               uint64_t *stats);
+
+/* a3 (Sec. 3.3.1, Eqs. L_j, L_quant, L_mask, R_proxy):
+ *   c_j = max(1, ceil(fl32(max_j - min_j) / q_j)),  L_j = log2 c_j,
+ *   L_quant = sum_j L_j,  L_mask = kept / n_hat,  R = L_mask * L_quant.
+ * out3 (device float[3]) = {R, L_quant, L_mask}.  If rate_grad is not NULL it
+ * receives the gradient of rate_weight * R in compact form (see
+ * SGS_RATE_GRAD_FLOATS), straight through the ceil. */
+sgs_status sgs_rate_proxy(sgs_ctx *ctx, const uint64_t *stats, const float *qstep,
+                          float rate_weight, float *out3, float *rate_grad);
+
+/* a4-a8 (Sec. 3.1: project, tile-bin, depth-sort, composite front to back).
+ * Every view of the scene is rendered.  final_T and last (entries of the
+ * pixel's tile list consumed before termination) are kept for the backward.
+ * eval_count (device uint64, may be NULL) is INCREMENTED by the number of
+ * in-support Gaussian-pixel evaluations.  Splats whose hard mask is 0 are
+ * binned and visited but contribute alpha 0 (masked rasterization).
+ * Synchronizes the stream once (pair count). */
+sgs_status sgs_render_fwd(sgs_ctx *ctx, const float *qparams, const uint8_t *hard_mask,
+                          float *image, float *final_T, uint32_t *last,
+                          uint64_t *eval_count);
+
+/* a9 (Supp. "Training Objective", L1 part): loss[0] = mean |image - target|,
+ * dL_dimage = scale * sign(image - target) / (3 V H W), sign(0) = 0.
+ * `scale` is the upstream gradient of the loss (1 for a plain step). */
+sgs_status sgs_l1_loss(sgs_ctx *ctx, const float *image, const float *target,
+                       float scale, float *loss, float *dL_dimage);
+
+/* a10-a11: gradient of the rendered images w.r.t. qparams [59][npad]
+ * (overwritten) and the hard mask (grad_hard_mask float [n], overwritten).
+ * Must follow sgs_render_fwd of the same qparams / hard_mask on this context. */
+sgs_status sgs_render_bwd(sgs_ctx *ctx, const float *qparams, const uint8_t *hard_mask,
+                          const float *final_T, const uint32_t *last,
+                          const float *dL_dimage, float *grad_qparams,
+                          float *grad_hard_mask);
+
+/* a12: quantizer and mask backward.
+ *   grad_params = grad_qparams (straight through) [+ rate gradient];
+ *   grad_qstep_j = sum_i grad_qparams_ij (k_ij - params_ij / q_j) [+ rate];
+ *   grad_score_i = (grad_hard_mask_i [+ rate]) soft_i (1 - soft_i) / tau in
+ *   mask mode 1, else 0.
+ * rate_grad/stats (both or neither) add the rate-proxy gradient.  Outputs are
+ * overwritten; grad_params may alias grad_qparams. */
+sgs_status sgs_fakequant_prune_bwd(sgs_ctx *ctx, const float *params, const float *qstep,
+                                   const float *soft_mask, int32_t mask_mode,
+                                   const float *rate_grad, const uint64_t *stats,
+                                   const float *grad_qparams, const float *grad_hard_mask,
+                                   float *grad_params, float *grad_qstep, float *grad_score);
+
+/* Host-side query (synchronizes the stream): pairs of the last render and the
+ * device flags word of `stats` (may be NULL). */
+sgs_status sgs_query(sgs_ctx *ctx, const uint64_t *stats, int64_t *pairs_last,
+                     uint64_t *flags);
+
+/* Inspection for tests: copy the last render's structure into caller device
+ * buffers.  tile_ids/vals: uint32 [cap] (sorted pairs), ranges uint32
+ * [V*tiles][2], spans int32 [V][n][4] (x0,x1,y0,y1; all -1 when culled),
+ * depth float [V][n], splats float [V][n][12] (px, py, A, B, C, opacity,
+ * r, g, b, mask, 0, 0).  Any pointer may be NULL. */
+sgs_status sgs_copy_structure(sgs_ctx *ctx, uint32_t *tile_ids, uint32_t *vals,
+                              int64_t cap, uint32_t *ranges, int32_t *spans,
+                              float *depth, float *splats);
+/* Per-(view, Gaussian) splat gradients of the last render_bwd:
+ * float [V][n][12] (px, py, A, B, C, opacity, r, g, b, mask, 0, 0). */
+sgs_status sgs_copy_splat_grads(sgs_ctx *ctx, float *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPEEDYGS_H */

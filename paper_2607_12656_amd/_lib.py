@@ -1,0 +1,192 @@
+"""ctypes binding of libspeedygs.so (declared in include/speedygs.h).
+
+Argument marshalling only: every step of the RD path runs in the library's
+HIP kernels.  Device buffers are passed as raw pointers (``tensor.data_ptr()``
+of torch CUDA tensors); the stream is torch's current HIP stream.  Loading
+fails loudly when the library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspeedygs.so")
+
+NCH = 59
+STATS_WORDS = 128
+RATE_GRAD_FLOATS = 256
+SPLAT_FIELDS = 12
+
+SGS_OK, SGS_EINVAL, SGS_ENOMEM, SGS_EHIP, SGS_ESTATE, SGS_ECAPACITY = 0, -1, -2, -3, -4, -5
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ECAPACITY"}
+
+
+class SgsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class sgs_camera(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("fx", C.c_float),
+                ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+                ("campos", C.c_float * 3)]
+
+
+class sgs_options(C.Structure):
+    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("tau", C.c_float),
+                ("reserved", C.c_int32 * 5)]
+
+
+P = C.c_void_p
+I64 = C.c_int64
+I32 = C.c_int32
+U64 = C.c_uint64
+F32 = C.c_float
+
+_SIGS = {
+    "sgs_create": [C.POINTER(P), C.c_int, P],
+    "sgs_destroy": [P],
+    "sgs_last_error": [P],
+    "sgs_set_stream": [P, P],
+    "sgs_set_scene": [P, I64, I64, I64, P, I32, I32, I32, P],
+    "sgs_fakequant_prune": [P, P, P, P, I32, P, U64, U64, P, P, P, P],
+    "sgs_rate_proxy": [P, P, P, F32, P, P],
+    "sgs_render_fwd": [P, P, P, P, P, P, P],
+    "sgs_l1_loss": [P, P, P, F32, P, P],
+    "sgs_render_bwd": [P, P, P, P, P, P, P, P],
+    "sgs_fakequant_prune_bwd": [P, P, P, P, I32, P, P, P, P, P, P, P],
+    "sgs_query": [P, P, C.POINTER(I64), C.POINTER(U64)],
+    "sgs_copy_structure": [P, P, P, I64, P, P, P, P],
+    "sgs_copy_splat_grads": [P, P],
+}
+EXPORTS = tuple(_SIGS)
+
+_lib = None
+
+
+def lib(path: str | None = None):
+    """Load libspeedygs.so (no compute call is made)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libspeedygs.so not built ({p}); run __graft_entry__.build()")
+    L = C.CDLL(p)
+    for name, args in _SIGS.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_char_p if name == "sgs_last_error" else (None if name == "sgs_destroy" else C.c_int)
+    if path is None:
+        _lib = L
+    return L
+
+
+def _ptr(x) -> int | None:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def cameras(cams: np.ndarray):
+    cams = np.ascontiguousarray(cams, np.float32)
+    arr = (sgs_camera * cams.shape[0])()
+    C.memmove(arr, cams.ctypes.data, cams.nbytes)
+    return arr
+
+
+class Context:
+    """One library context bound to a device and torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self._torch = torch
+        self.L = lib()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        h = P()
+        self._check(self.L.sgs_create(C.byref(h), device, P(stream.cuda_stream)), None)
+        self.h = h
+
+    def _check(self, st: int, h=None):
+        if st != SGS_OK:
+            msg = self.L.sgs_last_error(h if h is not None else getattr(self, "h", None))
+            raise SgsError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.sgs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self._check(self.L.sgs_set_stream(self.h, P(stream.cuda_stream)), self.h)
+
+    # ---- the C ABI, one method per entry point -----------------------------
+    def set_scene(self, n, npad, n_hat, cams, width, height, tile=(16, 16), tau=1.0):
+        cams = np.ascontiguousarray(cams, np.float32)
+        arr = cameras(cams)
+        opt = sgs_options(tile[0], tile[1], tau, (C.c_int32 * 5)())
+        self.V, self.W, self.H, self.n, self.npad = cams.shape[0], width, height, n, npad
+        self.tile = tile
+        self._check(self.L.sgs_set_scene(self.h, n, npad, n_hat, arr, cams.shape[0], width,
+                                         height, C.byref(opt)), self.h)
+
+    def fakequant_prune(self, params, qstep, score, mask_mode, given_mask, seed, step,
+                        qparams, hard_mask, soft_mask, stats):
+        self._check(self.L.sgs_fakequant_prune(
+            self.h, _ptr(params), _ptr(qstep), _ptr(score), mask_mode, _ptr(given_mask),
+            seed, step, _ptr(qparams), _ptr(hard_mask), _ptr(soft_mask), _ptr(stats)), self.h)
+
+    def rate_proxy(self, stats, qstep, rate_weight, out3, rate_grad=None):
+        self._check(self.L.sgs_rate_proxy(self.h, _ptr(stats), _ptr(qstep), rate_weight,
+                                          _ptr(out3), _ptr(rate_grad)), self.h)
+
+    def render_fwd(self, qparams, hard_mask, image, final_T, last, eval_count=None):
+        self._check(self.L.sgs_render_fwd(self.h, _ptr(qparams), _ptr(hard_mask), _ptr(image),
+                                          _ptr(final_T), _ptr(last), _ptr(eval_count)), self.h)
+
+    def l1_loss(self, image, target, loss, dL_dimage, scale=1.0):
+        self._check(self.L.sgs_l1_loss(self.h, _ptr(image), _ptr(target), scale, _ptr(loss),
+                                       _ptr(dL_dimage)), self.h)
+
+    def render_bwd(self, qparams, hard_mask, final_T, last, dL_dimage, grad_qparams,
+                   grad_hard_mask):
+        self._check(self.L.sgs_render_bwd(self.h, _ptr(qparams), _ptr(hard_mask), _ptr(final_T),
+                                          _ptr(last), _ptr(dL_dimage), _ptr(grad_qparams),
+                                          _ptr(grad_hard_mask)), self.h)
+
+    def fakequant_prune_bwd(self, params, qstep, soft_mask, mask_mode, rate_grad, stats,
+                            grad_qparams, grad_hard_mask, grad_params, grad_qstep, grad_score):
+        self._check(self.L.sgs_fakequant_prune_bwd(
+            self.h, _ptr(params), _ptr(qstep), _ptr(soft_mask), mask_mode, _ptr(rate_grad),
+            _ptr(stats), _ptr(grad_qparams), _ptr(grad_hard_mask), _ptr(grad_params),
+            _ptr(grad_qstep), _ptr(grad_score)), self.h)
+
+    def query(self, stats=None):
+        pairs = I64()
+        flags = U64()
+        st = self.L.sgs_query(self.h, _ptr(stats), C.byref(pairs), C.byref(flags))
+        self._check(st, self.h)
+        return int(pairs.value), int(flags.value)
+
+    def copy_structure(self, tile_ids=None, vals=None, cap=0, ranges=None, spans=None,
+                       depth=None, splats=None):
+        self._check(self.L.sgs_copy_structure(self.h, _ptr(tile_ids), _ptr(vals), cap,
+                                              _ptr(ranges), _ptr(spans), _ptr(depth),
+                                              _ptr(splats)), self.h)
+
+    def copy_splat_grads(self, out):
+        self._check(self.L.sgs_copy_splat_grads(self.h, _ptr(out)), self.h)

@@ -1,0 +1,400 @@
+// C ABI of libspeedygs (declared in include/speedygs.h): argument checks,
+// scratch ownership and the order of the launches.  No exception crosses the
+// ABI; every failure is a status code plus a message in the context.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "sgs_internal.h"
+
+namespace {
+
+sgs_status fail(sgs_ctx *c, sgs_status s, const char *fmt, ...) {
+  if (c) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->err, sizeof(c->err), fmt, ap);
+    va_end(ap);
+  }
+  return s;
+}
+
+sgs_status hip_fail(sgs_ctx *c, hipError_t e, const char *where) {
+  return fail(c, e == hipErrorOutOfMemory ? SGS_ENOMEM : SGS_EHIP, "%s: %s", where,
+              hipGetErrorString(e));
+}
+
+#define SGS_HIP(call, where)                         \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return hip_fail(c, e_, where); \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) count = 1;
+  return hipMalloc((void **)p, sizeof(T) * (size_t)count);
+}
+
+template <typename T>
+void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+void free_scene(sgs_ctx *c) {
+  dfree(c->d_cams);
+  dfree(c->rec);
+  for (int k = 0; k < 2; ++k) {
+    dfree(c->depth_key[k]);
+    dfree(c->depth_val[k]);
+    dfree(c->tile_key[k]);
+    dfree(c->pair_val[k]);
+  }
+  dfree(c->touched);
+  dfree(c->offsets);
+  dfree(c->splat_grad);
+  dfree(c->ranges);
+  dfree(c->scan_tmp);
+  dfree(c->sort_hist);
+  dfree(c->red_tmp);
+  dfree(c->d_pairs_total);
+  c->scan_tmp_words = c->sort_hist_words = c->red_tmp_words = 0;
+  c->pair_cap = 0;
+  c->scene_set = false;
+  c->rendered = false;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+hipError_t grow_pairs(sgs_ctx *c, int64_t P) {
+  if (P <= c->pair_cap) return hipSuccess;
+  const int64_t cap = P + P / 8 + 1024;
+  for (int k = 0; k < 2; ++k) {
+    dfree(c->tile_key[k]);
+    dfree(c->pair_val[k]);
+  }
+  c->pair_cap = 0;
+  for (int k = 0; k < 2; ++k) {
+    hipError_t e = dalloc(&c->tile_key[k], cap);
+    if (e != hipSuccess) return e;
+    e = dalloc(&c->pair_val[k], cap);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t nb = (cap + 4095) / 4096;
+  const int64_t hist = nb * 256 + 1;
+  const int64_t scan = (hist + 4095) / 4096 + 1;
+  hipError_t e = ensure_tmp(c, scan > c->scan_tmp_words ? scan : c->scan_tmp_words, hist);
+  if (e != hipSuccess) return e;
+  c->pair_cap = cap;
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+sgs_status sgs_create(sgs_ctx **out, int device, void *hip_stream) {
+  if (!out) return SGS_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SGS_EINVAL;
+  sgs_ctx *c = new (std::nothrow) sgs_ctx();
+  if (!c) return SGS_ENOMEM;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_pairs_total, sizeof(uint32_t), hipHostMallocDefault) !=
+          hipSuccess) {
+    delete c;
+    return SGS_EHIP;
+  }
+  *out = c;
+  return SGS_OK;
+}
+
+void sgs_destroy(sgs_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
+  free_scene(c);
+  if (c->h_pairs_total) (void)hipHostFree(c->h_pairs_total);
+  delete c;
+}
+
+const char *sgs_last_error(const sgs_ctx *c) { return c ? c->err : "null context"; }
+
+sgs_status sgs_set_stream(sgs_ctx *c, void *hip_stream) {
+  if (!c) return SGS_EINVAL;
+  c->stream = (hipStream_t)hip_stream;
+  return SGS_OK;
+}
+
+sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
+                         const sgs_camera *cams, int32_t views, int32_t width, int32_t height,
+                         const sgs_options *opt) {
+  if (!c) return SGS_EINVAL;
+  if (n < 1 || npad < n || npad % 64 != 0 || n_hat < 1)
+    return fail(c, SGS_EINVAL, "set_scene: need n >= 1, npad >= n, npad %% 64 == 0, n_hat >= 1");
+  if (!cams || views < 1 || width < 1 || height < 1 || width > 32768 || height > 32768)
+    return fail(c, SGS_EINVAL, "set_scene: bad cameras or image size");
+  if ((int64_t)views * n >= (int64_t)1 << 31)
+    return fail(c, SGS_ECAPACITY, "set_scene: views * n must stay below 2^31");
+  int tw = 16, th = 16;
+  float tau = 1.0f;
+  if (opt) {
+    if (opt->tile_w || opt->tile_h) {
+      tw = opt->tile_w;
+      th = opt->tile_h;
+    }
+    if (opt->tau != 0.0f) tau = opt->tau;
+    for (int k = 0; k < 5; ++k)
+      if (opt->reserved[k] != 0) return fail(c, SGS_EINVAL, "set_scene: reserved options must be 0");
+  }
+  if (!((tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 32 && th == 8)))
+    return fail(c, SGS_EINVAL, "set_scene: tile shape must be 8x8, 16x16 or 32x8");
+  if (!(tau > 0.0f)) return fail(c, SGS_EINVAL, "set_scene: tau must be > 0");
+  SGS_HIP(hipSetDevice(c->device), "hipSetDevice");
+  if (c->stream) SGS_HIP(hipStreamSynchronize(c->stream), "sync"); else SGS_HIP(hipDeviceSynchronize(), "sync");
+  free_scene(c);
+  c->n = n;
+  c->npad = npad;
+  c->n_hat = n_hat;
+  c->V = views;
+  c->W = width;
+  c->H = height;
+  c->TW = tw;
+  c->TH = th;
+  c->tau = tau;
+  c->GW = (width + tw - 1) / tw;
+  c->GH = (height + th - 1) / th;
+  c->tiles_per_view = (int64_t)c->GW * c->GH;
+  c->total_tiles = c->tiles_per_view * views;
+  c->vn = (int64_t)views * n;
+  const int64_t vn = c->vn;
+  hipError_t e = hipSuccess;
+#define SGS_ALLOC(p, cnt)                                   \
+  do {                                                      \
+    e = dalloc(&(p), (cnt));                                \
+    if (e != hipSuccess) { free_scene(c); return hip_fail(c, e, "set_scene alloc"); } \
+  } while (0)
+  SGS_ALLOC(c->d_cams, views);
+  SGS_ALLOC(c->rec, 3 * vn);
+  for (int k = 0; k < 2; ++k) {
+    SGS_ALLOC(c->depth_key[k], vn);
+    SGS_ALLOC(c->depth_val[k], vn);
+  }
+  SGS_ALLOC(c->touched, vn);
+  SGS_ALLOC(c->offsets, vn + 1);
+  SGS_ALLOC(c->splat_grad, vn * SGS_SGRAD);
+  SGS_ALLOC(c->ranges, c->total_tiles);
+  SGS_ALLOC(c->d_pairs_total, 1);
+  const int64_t red = ((n + 2047) / 2048) * SGS_NCH + (int64_t)views * 3 * width * height / 2048 + 64;
+  SGS_ALLOC(c->red_tmp, red);
+  c->red_tmp_words = red;
+#undef SGS_ALLOC
+  const int64_t nb = (vn + 4095) / 4096;
+  const int64_t hist = nb * 256 + 1;
+  const int64_t scan = ((hist > vn ? hist : vn) + 4095) / 4096 + 1;
+  e = ensure_tmp(c, scan, hist);
+  if (e != hipSuccess) { free_scene(c); return hip_fail(c, e, "set_scene alloc"); }
+  // initial pair capacity: 4 tiles per splat
+  e = grow_pairs(c, 4 * vn);
+  if (e != hipSuccess) { free_scene(c); return hip_fail(c, e, "set_scene alloc"); }
+  SGS_HIP(hipMemcpy(c->d_cams, cams, sizeof(sgs_camera) * views, hipMemcpyHostToDevice),
+          "set_scene camera copy");
+  c->scene_set = true;
+  c->rendered = false;
+  return SGS_OK;
+}
+
+sgs_status sgs_fakequant_prune(sgs_ctx *c, const float *params, const float *qstep,
+                               const float *score, int32_t mask_mode, const uint8_t *given_mask,
+                               uint64_t seed, uint64_t step, float *qparams, uint8_t *hard_mask,
+                               float *soft_mask, uint64_t *stats) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "fakequant_prune: set_scene first");
+  if (!params || !qstep || !qparams || !hard_mask || !stats)
+    return fail(c, SGS_EINVAL, "fakequant_prune: null pointer");
+  if (!aligned(params, 16) || !aligned(qparams, 16))
+    return fail(c, SGS_EINVAL, "fakequant_prune: parameter rows must be 16-byte aligned");
+  if (mask_mode < 0 || mask_mode > 2) return fail(c, SGS_EINVAL, "fakequant_prune: mask_mode");
+  if (mask_mode == 0 && !given_mask) return fail(c, SGS_EINVAL, "fakequant_prune: given_mask");
+  if (mask_mode == 1 && !score) return fail(c, SGS_EINVAL, "fakequant_prune: score");
+  SGS_HIP(launch_fakequant_prune(c, params, qstep, score, mask_mode, given_mask, seed, step,
+                                 qparams, hard_mask, soft_mask, stats),
+          "fakequant_prune");
+  return SGS_OK;
+}
+
+sgs_status sgs_rate_proxy(sgs_ctx *c, const uint64_t *stats, const float *qstep,
+                          float rate_weight, float *out3, float *rate_grad) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "rate_proxy: set_scene first");
+  if (!stats || !qstep || !out3) return fail(c, SGS_EINVAL, "rate_proxy: null pointer");
+  SGS_HIP(launch_rate_proxy(c, stats, qstep, rate_weight, out3, rate_grad), "rate_proxy");
+  return SGS_OK;
+}
+
+sgs_status sgs_render_fwd(sgs_ctx *c, const float *qparams, const uint8_t *hard_mask,
+                          float *image, float *final_T, uint32_t *last, uint64_t *eval_count) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "render_fwd: set_scene first");
+  if (!qparams || !hard_mask || !image || !final_T || !last)
+    return fail(c, SGS_EINVAL, "render_fwd: null pointer");
+  SGS_HIP(launch_preprocess(c, qparams, hard_mask), "render_fwd preprocess");
+  SGS_HIP(launch_depth_order(c), "render_fwd depth order");
+  SGS_HIP(hipMemcpyAsync(c->h_pairs_total, c->d_pairs_total, sizeof(uint32_t),
+                         hipMemcpyDeviceToHost, c->stream),
+          "render_fwd pair count");
+  SGS_HIP(hipStreamSynchronize(c->stream), "render_fwd pair count");
+  c->pairs = *c->h_pairs_total;
+  hipError_t e = grow_pairs(c, c->pairs);
+  if (e != hipSuccess) return hip_fail(c, e, "render_fwd pair buffers");
+  SGS_HIP(launch_bin_pairs(c), "render_fwd binning");
+  SGS_HIP(launch_blend_fwd(c, image, final_T, last, eval_count), "render_fwd blend");
+  c->rendered = true;
+  return SGS_OK;
+}
+
+sgs_status sgs_l1_loss(sgs_ctx *c, const float *image, const float *target, float scale,
+                       float *loss, float *dL_dimage) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "l1_loss: set_scene first");
+  if (!image || !target || !loss || !dL_dimage) return fail(c, SGS_EINVAL, "l1_loss: null pointer");
+  SGS_HIP(launch_l1(c, image, target, scale, loss, dL_dimage), "l1_loss");
+  return SGS_OK;
+}
+
+sgs_status sgs_render_bwd(sgs_ctx *c, const float *qparams, const uint8_t *hard_mask,
+                          const float *final_T, const uint32_t *last, const float *dL_dimage,
+                          float *grad_qparams, float *grad_hard_mask) {
+  if (!c) return SGS_EINVAL;
+  if (!c->rendered) return fail(c, SGS_ESTATE, "render_bwd: render_fwd first");
+  if (!qparams || !hard_mask || !final_T || !last || !dL_dimage || !grad_qparams ||
+      !grad_hard_mask)
+    return fail(c, SGS_EINVAL, "render_bwd: null pointer");
+  (void)hard_mask;  // the mask is held in the splat records of the forward
+  SGS_HIP(launch_blend_bwd(c, final_T, last, dL_dimage), "render_bwd blend");
+  SGS_HIP(launch_preprocess_bwd(c, qparams, grad_qparams, grad_hard_mask), "render_bwd project");
+  return SGS_OK;
+}
+
+sgs_status sgs_fakequant_prune_bwd(sgs_ctx *c, const float *params, const float *qstep,
+                                   const float *soft_mask, int32_t mask_mode,
+                                   const float *rate_grad, const uint64_t *stats,
+                                   const float *grad_qparams, const float *grad_hard_mask,
+                                   float *grad_params, float *grad_qstep, float *grad_score) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "fakequant_prune_bwd: set_scene first");
+  if (!params || !qstep || !grad_qparams || !grad_hard_mask || !grad_params || !grad_qstep ||
+      !grad_score)
+    return fail(c, SGS_EINVAL, "fakequant_prune_bwd: null pointer");
+  if ((rate_grad == nullptr) != (stats == nullptr))
+    return fail(c, SGS_EINVAL, "fakequant_prune_bwd: rate_grad and stats go together");
+  if (mask_mode == 1 && !soft_mask)
+    return fail(c, SGS_EINVAL, "fakequant_prune_bwd: soft_mask needed in mask mode 1");
+  if (mask_mode < 0 || mask_mode > 2) return fail(c, SGS_EINVAL, "fakequant_prune_bwd: mask_mode");
+  SGS_HIP(launch_fakequant_bwd(c, params, qstep, soft_mask, mask_mode, rate_grad, stats,
+                               grad_qparams, grad_hard_mask, grad_params, grad_qstep, grad_score),
+          "fakequant_prune_bwd");
+  return SGS_OK;
+}
+
+sgs_status sgs_query(sgs_ctx *c, const uint64_t *stats, int64_t *pairs_last, uint64_t *flags) {
+  if (!c) return SGS_EINVAL;
+  SGS_HIP(hipSetDevice(c->device), "hipSetDevice");
+  SGS_HIP(hipStreamSynchronize(c->stream), "query sync");
+  if (pairs_last) *pairs_last = c->pairs;
+  if (flags) {
+    *flags = 0;
+    if (stats)
+      SGS_HIP(hipMemcpy(flags, stats + 119, sizeof(uint64_t), hipMemcpyDeviceToHost), "query flags");
+  }
+  if (flags && (*flags & 1ull)) return fail(c, SGS_EINVAL, "a step size q_j was <= 0 or not finite");
+  return SGS_OK;
+}
+
+sgs_status sgs_copy_structure(sgs_ctx *c, uint32_t *tile_ids, uint32_t *vals, int64_t cap,
+                              uint32_t *ranges, int32_t *spans, float *depth, float *splats);
+sgs_status sgs_copy_splat_grads(sgs_ctx *c, float *out);
+
+}  // extern "C"
+
+// ---- inspection ----------------------------------------------------------
+namespace {
+
+__global__ void k_export(int64_t vn, const float4 *__restrict__ rec,
+                         const uint32_t *__restrict__ touched, int32_t *__restrict__ spans,
+                         float *__restrict__ depth, float *__restrict__ splats,
+                         const uint32_t *__restrict__ dkey_unsorted) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= vn) return;
+  const float4 a = rec[s], b = rec[vn + s], cc = rec[2 * vn + s];
+  const bool valid = touched[s] != 0;
+  if (spans) {
+    const uint32_t sx = __float_as_uint(b.z), sy = __float_as_uint(b.w);
+    spans[4 * s + 0] = valid ? (int)(sx & 0xFFFF) : -1;
+    spans[4 * s + 1] = valid ? (int)(sx >> 16) : -1;
+    spans[4 * s + 2] = valid ? (int)(sy & 0xFFFF) : -1;
+    spans[4 * s + 3] = valid ? (int)(sy >> 16) : -1;
+  }
+  (void)dkey_unsorted;
+  if (depth) depth[s] = 0.0f;
+  if (splats) {
+    float *o = splats + 12 * s;
+    o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+    o[4] = b.x; o[5] = b.y; o[6] = cc.x; o[7] = cc.y; o[8] = cc.z; o[9] = cc.w;
+    o[10] = 0.0f; o[11] = 0.0f;
+  }
+}
+
+// depth keys in splat order: scatter the sorted (key, index) pairs back
+__global__ void k_export_depth(int64_t vn, const uint32_t *__restrict__ skey,
+                               const uint32_t *__restrict__ sval, float *__restrict__ depth) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= vn) return;
+  const uint32_t key = skey[k];
+  depth[sval[k]] = key == 0xFFFFFFFFu ? -1.0f : __uint_as_float(key);
+}
+
+}  // namespace
+
+extern "C" sgs_status sgs_copy_structure(sgs_ctx *c, uint32_t *tile_ids, uint32_t *vals,
+                                         int64_t cap, uint32_t *ranges, int32_t *spans,
+                                         float *depth, float *splats) {
+  if (!c) return SGS_EINVAL;
+  if (!c->rendered) return fail(c, SGS_ESTATE, "copy_structure: render_fwd first");
+  const int64_t P = c->pairs;
+  if ((tile_ids || vals) && cap < P) return fail(c, SGS_ECAPACITY, "copy_structure: cap < pairs");
+  if (tile_ids && P)
+    SGS_HIP(hipMemcpyAsync(tile_ids, c->tile_key[c->pair_sorted_buf], 4 * P,
+                           hipMemcpyDeviceToDevice, c->stream), "copy tile ids");
+  if (vals && P)
+    SGS_HIP(hipMemcpyAsync(vals, c->pair_val[c->pair_sorted_buf], 4 * P,
+                           hipMemcpyDeviceToDevice, c->stream), "copy vals");
+  if (ranges)
+    SGS_HIP(hipMemcpyAsync(ranges, c->ranges, 8 * c->total_tiles, hipMemcpyDeviceToDevice,
+                           c->stream), "copy ranges");
+  if (spans || splats) {
+    k_export<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(c->vn, c->rec, c->touched, spans,
+                                                            nullptr, splats, nullptr);
+    SGS_HIP(hipGetLastError(), "copy_structure export");
+  }
+  if (depth) {
+    k_export_depth<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(
+        c->vn, c->depth_key[c->depth_sorted_buf], c->depth_val[c->depth_sorted_buf], depth);
+    SGS_HIP(hipGetLastError(), "copy_structure depth");
+  }
+  return SGS_OK;
+}
+
+extern "C" sgs_status sgs_copy_splat_grads(sgs_ctx *c, float *out) {
+  if (!c || !out) return SGS_EINVAL;
+  SGS_HIP(hipMemcpyAsync(out, c->splat_grad, sizeof(float) * SGS_SGRAD * c->vn,
+                         hipMemcpyDeviceToDevice, c->stream), "copy splat grads");
+  return SGS_OK;
+}

@@ -1,0 +1,267 @@
+// Projection of every Gaussian into every view (paper Sec. 3.1: 3D Gaussians
+// projected onto the image plane; view-dependent colour) and its backward.
+// One thread per Gaussian reads the 59 parameter rows once (coalesced SoA)
+// and loops over the views, so the parameters cross HBM once per step.
+#include "sgs_internal.h"
+
+namespace {
+
+constexpr int kPThreads = 128;
+
+__device__ __forceinline__ void load_cam(const sgs_camera *cams, int v, SgsCam &cam) {
+  const float *src = (const float *)(cams + v);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) cam.R[k] = src[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) cam.t[k] = src[9 + k];
+  cam.fx = src[12];
+  cam.fy = src[13];
+  cam.cx = src[14];
+  cam.cy = src[15];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) cam.campos[k] = src[16 + k];
+}
+
+// Colour of one Gaussian seen from `cam`: sum_k f_k Y_k(dir) + 1/2, clamped at 0.
+__device__ __forceinline__ void colour(const float *y, const SgsCam &cam, float col[3],
+                                       bool clamped[3]) {
+  float dx = y[0] - cam.campos[0], dy = y[1] - cam.campos[1], dz = y[2] - cam.campos[2];
+  const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+  dx *= inv; dy *= inv; dz *= inv;
+  float Y[16];
+  sgs_sh_basis(dx, dy, dz, Y);
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    float s = 0.5f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s = fmaf(y[sgs_sh_channel(k, ch)], Y[k], s);
+    clamped[ch] = s < 0.0f;
+    col[ch] = clamped[ch] ? 0.0f : s;
+  }
+}
+
+__global__ void __launch_bounds__(kPThreads)
+k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
+             const sgs_camera *__restrict__ cams, const float *__restrict__ qp,
+             const uint8_t *__restrict__ hard, float4 *__restrict__ rec,
+             uint32_t *__restrict__ depth_key, uint32_t *__restrict__ depth_val,
+             uint32_t *__restrict__ touched) {
+  const int64_t i = (int64_t)blockIdx.x * kPThreads + threadIdx.x;
+  if (i >= n) return;
+  float y[SGS_NCH];
+#pragma unroll
+  for (int j = 0; j < SGS_NCH; ++j) y[j] = qp[j * npad + i];
+  const float m = hard[i] ? 1.0f : 0.0f;
+  const float opa = 1.0f / (1.0f + __expf(-y[SGS_CH_OPA]));
+  const int64_t vn = (int64_t)V * n;
+  for (int v = 0; v < V; ++v) {
+    SgsCam cam;
+    load_cam(cams, v, cam);
+    SgsProj p;
+    sgs_project(y, cam, W, H, p);
+    const int64_t s = (int64_t)v * n + i;
+    depth_val[s] = (uint32_t)s;
+    if (!p.valid) {
+      depth_key[s] = 0xFFFFFFFFu;
+      touched[s] = 0;
+      rec[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+      rec[vn + s] = make_float4(0.f, 0.f, __int_as_float(-1), __int_as_float(-1));
+      rec[2 * vn + s] = make_float4(0.f, 0.f, 0.f, 0.f);
+      continue;
+    }
+    depth_key[s] = __float_as_uint(p.tz);
+    touched[s] = (uint32_t)((p.x1 / TW - p.x0 / TW + 1) * (p.y1 / TH - p.y0 / TH + 1));
+    const float A = p.c / p.det, B = -p.b / p.det, C = p.a / p.det;
+    float col[3];
+    bool cl[3];
+    colour(y, cam, col, cl);
+    const uint32_t sx = (uint32_t)p.x0 | ((uint32_t)p.x1 << 16);
+    const uint32_t sy = (uint32_t)p.y0 | ((uint32_t)p.y1 << 16);
+    rec[s] = make_float4(p.px, p.py, A, B);
+    rec[vn + s] = make_float4(C, opa, __uint_as_float(sx), __uint_as_float(sy));
+    rec[2 * vn + s] = make_float4(col[0], col[1], col[2], m);
+  }
+}
+
+// Chain rule from the per-view splat gradients (px, py, A, B, C, opacity,
+// r, g, b, mask) to the 59 channels, summed over views.
+__global__ void __launch_bounds__(kPThreads)
+k_preprocess_bwd(int64_t n, int64_t npad, int V, int W, int H,
+                 const sgs_camera *__restrict__ cams, const float *__restrict__ qp,
+                 const uint32_t *__restrict__ touched, const float *__restrict__ sgrad,
+                 float *__restrict__ gout, float *__restrict__ gmask) {
+  const int64_t i = (int64_t)blockIdx.x * kPThreads + threadIdx.x;
+  if (i >= n) return;
+  float y[SGS_NCH], g[SGS_NCH];
+#pragma unroll
+  for (int j = 0; j < SGS_NCH; ++j) {
+    y[j] = qp[j * npad + i];
+    g[j] = 0.0f;
+  }
+  float gm = 0.0f;
+  const float opa = 1.0f / (1.0f + __expf(-y[SGS_CH_OPA]));
+  for (int v = 0; v < V; ++v) {
+    const int64_t s = (int64_t)v * n + i;
+    if (touched[s] == 0) continue;
+    const float4 g0 = *(const float4 *)(sgrad + s * SGS_SGRAD);
+    const float4 g1 = *(const float4 *)(sgrad + s * SGS_SGRAD + 4);
+    const float4 g2 = *(const float4 *)(sgrad + s * SGS_SGRAD + 8);
+    const float gpx = g0.x, gpy = g0.y, gA = g0.z, gB = g0.w;
+    const float gC = g1.x, gop = g1.y;
+    const float gcol[3] = {g1.z, g1.w, g2.x};
+    gm += g2.y;
+    SgsCam cam;
+    load_cam(cams, v, cam);
+    SgsProj p;
+    sgs_project(y, cam, W, H, p);
+    // opacity
+    g[SGS_CH_OPA] += gop * opa * (1.0f - opa);
+    // colour and view direction
+    {
+      float vx = y[0] - cam.campos[0], vy = y[1] - cam.campos[1], vz = y[2] - cam.campos[2];
+      const float dist = sqrtf(vx * vx + vy * vy + vz * vz);
+      const float inv = 1.0f / dist;
+      const float dx = vx * inv, dy = vy * inv, dz = vz * inv;
+      float Y[16], GY[16][3];
+      sgs_sh_basis(dx, dy, dz, Y);
+      sgs_sh_grad(dx, dy, dz, GY);
+      float gd0 = 0.f, gd1 = 0.f, gd2 = 0.f;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        float raw = 0.5f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) raw = fmaf(y[sgs_sh_channel(k, ch)], Y[k], raw);
+        if (raw < 0.0f) continue;
+        const float gc = gcol[ch];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const int chan = sgs_sh_channel(k, ch);
+          g[chan] = fmaf(gc, Y[k], g[chan]);
+          const float f = gc * y[chan];
+          gd0 = fmaf(f, GY[k][0], gd0);
+          gd1 = fmaf(f, GY[k][1], gd1);
+          gd2 = fmaf(f, GY[k][2], gd2);
+        }
+      }
+      const float dd = gd0 * dx + gd1 * dy + gd2 * dz;
+      g[0] += (gd0 - dx * dd) * inv;
+      g[1] += (gd1 - dy * dd) * inv;
+      g[2] += (gd2 - dz * dd) * inv;
+    }
+    // conic (A, B, C) = (c, -b, a) / det  ->  Sigma' entries (a, b, c)
+    const float a = p.a, b = p.b, c = p.c;
+    const float id2 = 1.0f / (p.det * p.det);
+    const float ga = (-c * c * gA + b * c * gB - b * b * gC) * id2;
+    const float gb = (2.0f * b * c * gA - (a * c + b * b) * gB + 2.0f * a * b * gC) * id2;
+    const float gc = (-b * b * gA + a * b * gB - a * a * gC) * id2;
+    // a = T0 S T0^T, b = T0 S T1^T, c = T1 S T1^T
+    const float *Sg = p.Sg;
+    const float S[9] = {Sg[0], Sg[1], Sg[2], Sg[1], Sg[3], Sg[4], Sg[2], Sg[4], Sg[5]};
+    float ST0[3], ST1[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      ST0[r] = S[3 * r] * p.T0[0] + S[3 * r + 1] * p.T0[1] + S[3 * r + 2] * p.T0[2];
+      ST1[r] = S[3 * r] * p.T1[0] + S[3 * r + 1] * p.T1[1] + S[3 * r + 2] * p.T1[2];
+    }
+    float gT0[3], gT1[3], gS[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      gT0[r] = 2.0f * ga * ST0[r] + gb * ST1[r];
+      gT1[r] = gb * ST0[r] + 2.0f * gc * ST1[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        gS[3 * r + q] = ga * p.T0[r] * p.T0[q] + 0.5f * gb * (p.T0[r] * p.T1[q] + p.T1[r] * p.T0[q]) +
+                        gc * p.T1[r] * p.T1[q];
+    // Sigma = M M^T  ->  dM = 2 dSigma M
+    float gM[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        gM[3 * r + q] = 2.0f * (gS[3 * r] * p.M[q] + gS[3 * r + 1] * p.M[3 + q] +
+                                gS[3 * r + 2] * p.M[6 + q]);
+    // M = Rq diag(S)
+    float gR[9];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        gR[3 * r + q] = gM[3 * r + q] * p.S[q];
+        acc += gM[3 * r + q] * p.Rq[3 * r + q];
+      }
+      g[SGS_CH_SCALE + q] += acc * p.S[q];
+    }
+    // rotation of the unit quaternion (w, x, y, z)
+    {
+      const float w = p.qh[0], x = p.qh[1], yq = p.qh[2], z = p.qh[3];
+      const float gw = 2.0f * (-z * gR[1] + yq * gR[2] + z * gR[3] - x * gR[5] - yq * gR[6] + x * gR[7]);
+      const float gx = 2.0f * (yq * gR[1] + z * gR[2] + yq * gR[3] - w * gR[5] + z * gR[6] + w * gR[7]) -
+                       4.0f * x * (gR[4] + gR[8]);
+      const float gy = 2.0f * (x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] + z * gR[7]) -
+                       4.0f * yq * (gR[0] + gR[8]);
+      const float gz = 2.0f * (-w * gR[1] + x * gR[2] + w * gR[3] + yq * gR[5] + x * gR[6] + yq * gR[7]) -
+                       4.0f * z * (gR[0] + gR[4]);
+      const float dot = gw * w + gx * x + gy * yq + gz * z;
+      const float iq = 1.0f / p.qn;
+      g[SGS_CH_ROT + 0] += (gw - w * dot) * iq;
+      g[SGS_CH_ROT + 1] += (gx - x * dot) * iq;
+      g[SGS_CH_ROT + 2] += (gy - yq * dot) * iq;
+      g[SGS_CH_ROT + 3] += (gz - z * dot) * iq;
+    }
+    // T = J R_cam
+    float gJ00 = 0.f, gJ02 = 0.f, gJ11 = 0.f, gJ12 = 0.f;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      gJ00 += gT0[q] * cam.R[q];
+      gJ02 += gT0[q] * cam.R[6 + q];
+      gJ11 += gT1[q] * cam.R[3 + q];
+      gJ12 += gT1[q] * cam.R[6 + q];
+    }
+    const float tz = p.tz, itz = 1.0f / tz, itz2 = itz * itz;
+    float gtx = 0.f, gty = 0.f, gtz = 0.f;
+    gtz -= (gJ00 * cam.fx + gJ11 * cam.fy) * itz2;
+    if (!p.clx) {
+      gtx -= gJ02 * cam.fx * itz2;
+      gtz += gJ02 * 2.0f * cam.fx * p.tx * itz2 * itz;
+    } else {
+      gtz -= gJ02 * p.J02 * itz;   // J02 = -fx u_clamped / tz
+    }
+    if (!p.cly) {
+      gty -= gJ12 * cam.fy * itz2;
+      gtz += gJ12 * 2.0f * cam.fy * p.ty * itz2 * itz;
+    } else {
+      gtz -= gJ12 * p.J12 * itz;
+    }
+    // projected mean
+    gtx += gpx * cam.fx * itz;
+    gty += gpy * cam.fy * itz;
+    gtz -= (gpx * cam.fx * p.tx + gpy * cam.fy * p.ty) * itz2;
+    // t = R mu + t0
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g[k] += cam.R[k] * gtx + cam.R[3 + k] * gty + cam.R[6 + k] * gtz;
+  }
+#pragma unroll
+  for (int j = 0; j < SGS_NCH; ++j) gout[j * npad + i] = g[j];
+  gmask[i] = gm;
+}
+
+}  // namespace
+
+hipError_t launch_preprocess(sgs_ctx *c, const float *qparams, const uint8_t *hard) {
+  k_preprocess<<<sgs_blocks(c->n, kPThreads), kPThreads, 0, c->stream>>>(
+      c->n, c->npad, c->V, c->W, c->H, c->TW, c->TH, c->d_cams, qparams, hard, c->rec,
+      c->depth_key[0], c->depth_val[0], c->touched);
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_bwd(sgs_ctx *c, const float *qparams, float *grad_qparams,
+                                 float *grad_mask) {
+  k_preprocess_bwd<<<sgs_blocks(c->n, kPThreads), kPThreads, 0, c->stream>>>(
+      c->n, c->npad, c->V, c->W, c->H, c->d_cams, qparams, c->touched, c->splat_grad,
+      grad_qparams, grad_mask);
+  return hipGetLastError();
+}

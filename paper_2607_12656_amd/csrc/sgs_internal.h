@@ -1,0 +1,362 @@
+// Internal declarations of libspeedygs: the context, launchers and the
+// device-side helpers shared by the kernels.  Compiled for gfx950 only, with
+// -ffp-contract=off so every floating-point expression is evaluated exactly
+// as written (the discrete decisions below must be reproducible bit for bit).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/speedygs.h"
+
+#define SGS_CH_MU 0
+#define SGS_CH_DC 3
+#define SGS_CH_REST 6
+#define SGS_CH_OPA 51
+#define SGS_CH_SCALE 52
+#define SGS_CH_ROT 55
+
+// Splat-gradient record stride (floats): px, py, A, B, C, opacity, r, g, b,
+// mask, pad, pad.
+#define SGS_SGRAD 12
+
+// Blend conventions (the paper does not state them).
+#define SGS_NEAR 0.2f
+#define SGS_DILATION 0.3f
+#define SGS_ALPHA_MAX 0.99f
+#define SGS_ALPHA_MIN (1.0f / 255.0f)
+#define SGS_T_MIN 1e-4f
+#define SGS_FOV_CLAMP 1.3f
+
+struct sgs_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char err[512] = {0};
+
+  // scene
+  int64_t n = 0, npad = 0, n_hat = 0;
+  int V = 0, W = 0, H = 0;
+  int TW = 16, TH = 16, GW = 0, GH = 0;
+  int64_t tiles_per_view = 0, total_tiles = 0;
+  float tau = 1.0f;
+  bool scene_set = false;
+  bool rendered = false;
+  sgs_camera *d_cams = nullptr;
+
+  // per (view, Gaussian): V*n entries
+  int64_t vn = 0;
+  float4 *rec = nullptr;          // [3][vn]: (px,py,A,B) (C,opa,spanx,spany) (r,g,b,mask)
+  uint32_t *depth_key[2] = {nullptr, nullptr};
+  uint32_t *depth_val[2] = {nullptr, nullptr};
+  uint32_t *touched = nullptr;    // [vn] tiles per splat (0 = culled)
+  uint32_t *offsets = nullptr;    // [vn + 1] exclusive scan in depth order
+  float *splat_grad = nullptr;    // [vn][SGS_SGRAD]
+  int depth_sorted_buf = 0;       // which depth buffer holds the sorted order
+
+  // pairs
+  int64_t pair_cap = 0;
+  int64_t pairs = 0;
+  uint32_t *tile_key[2] = {nullptr, nullptr};
+  uint32_t *pair_val[2] = {nullptr, nullptr};
+  int pair_sorted_buf = 0;
+  uint2 *ranges = nullptr;        // [total_tiles]
+
+  // reusable temporaries
+  uint32_t *scan_tmp = nullptr;   int64_t scan_tmp_words = 0;
+  uint32_t *sort_hist = nullptr;  int64_t sort_hist_words = 0;
+  double *red_tmp = nullptr;      int64_t red_tmp_words = 0;
+  uint32_t *d_pairs_total = nullptr;  // device copy of the pair count
+  uint32_t *h_pairs_total = nullptr;  // pinned host mirror
+};
+
+// ---- launchers (one translation unit each) --------------------------------
+// quant.hip
+hipError_t launch_fakequant_prune(sgs_ctx *c, const float *params, const float *q,
+                                  const float *score, int mode, const uint8_t *given,
+                                  uint64_t seed, uint64_t step, float *qparams,
+                                  uint8_t *hard, float *soft, uint64_t *stats);
+hipError_t launch_rate_proxy(sgs_ctx *c, const uint64_t *stats, const float *q,
+                             float weight, float *out3, float *rate_grad);
+hipError_t launch_fakequant_bwd(sgs_ctx *c, const float *params, const float *q,
+                                const float *soft, int mode, const float *rate_grad,
+                                const uint64_t *stats, const float *gq_in,
+                                const float *gmask_in, float *gparams, float *gqstep,
+                                float *gscore);
+// project.hip
+hipError_t launch_preprocess(sgs_ctx *c, const float *qparams, const uint8_t *hard);
+hipError_t launch_preprocess_bwd(sgs_ctx *c, const float *qparams, float *grad_qparams,
+                                 float *grad_mask);
+// sort.hip
+hipError_t ensure_tmp(sgs_ctx *c, int64_t scan_words, int64_t hist_words);
+hipError_t launch_exclusive_scan(sgs_ctx *c, const uint32_t *in, uint32_t *out,
+                                 int64_t count, uint32_t *total_out);
+// Stable LSD radix sort of 32-bit keys with 32-bit values over bits
+// [0, bits); ping-pongs between buffer 0 and 1; returns the buffer index that
+// holds the result in *which.
+hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2],
+                             int64_t count, int bits, int *which);
+hipError_t launch_bin_pairs(sgs_ctx *c);   // depth order -> pairs -> tile sort -> ranges
+hipError_t launch_depth_order(sgs_ctx *c); // depth sort + scan (writes d_pairs_total)
+// blend.hip
+hipError_t launch_blend_fwd(sgs_ctx *c, float *image, float *final_T, uint32_t *last,
+                            uint64_t *eval_count);
+hipError_t launch_blend_bwd(sgs_ctx *c, const float *final_T, const uint32_t *last,
+                            const float *dL_dimage);
+// loss.hip
+hipError_t launch_l1(sgs_ctx *c, const float *image, const float *target, float scale,
+                     float *loss, float *dimg);
+
+// ---- device helpers ---------------------------------------------------------
+
+// SplitMix64 (Steele, Lea, Flood 2014): the counter hash of the mask noise.
+__device__ __forceinline__ uint64_t sgs_splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+// Uniform in (0,1) with 23 random bits plus one half: exact in FP32.
+__device__ __forceinline__ float sgs_uniform(uint64_t seed, uint64_t step, uint64_t i) {
+  const uint64_t h = sgs_splitmix64(seed ^ ((step << 32) + i));
+  return ((float)(uint32_t)(h >> 41) + 0.5f) * 0x1p-23f;
+}
+
+// FP32 exponential whose result is reproducible on any IEEE machine:
+// Cody-Waite split of x = n ln2 + r, degree-7 Taylor polynomial of e^r in
+// Horner form, scaling by 2^n.  Input clamped to [-80, 80].
+__device__ __forceinline__ float sgs_exp_repro(float x) {
+  x = fminf(fmaxf(x, -80.0f), 80.0f);
+  const float n = rintf(x * 0x1.715476p+0f);
+  const float r = (x - n * 0x1.62e4p-1f) - n * 0x1.7f7d1cp-20f;
+  float p = 1.0f / 5040.0f;
+  p = p * r + 1.0f / 720.0f;
+  p = p * r + 1.0f / 120.0f;
+  p = p * r + 1.0f / 24.0f;
+  p = p * r + 1.0f / 6.0f;
+  p = p * r + 0.5f;
+  p = p * r + 1.0f;
+  p = p * r + 1.0f;
+  return ldexpf(p, (int)n);
+}
+
+// Order-preserving map of float bits to uint32 (for min/max keys).
+__device__ __forceinline__ uint32_t sgs_ord(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ __forceinline__ float sgs_unord(uint32_t o) {
+  const uint32_t u = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+#ifdef __HIP_DEVICE_COMPILE__
+  return __uint_as_float(u);
+#else
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return f;
+#endif
+}
+
+// Projection of one Gaussian into one view.  The fields up to `x1` are the
+// discrete structure (decided in FP32 with a fixed operation order); the rest
+// are the continuous values the blend and the backward use.
+struct SgsCam {
+  float R[9], t[3], fx, fy, cx, cy, campos[3];
+};
+
+struct SgsProj {
+  bool valid;
+  float tz, px, py;
+  int x0, x1, y0, y1;
+  // intermediates (kept for the backward pass)
+  float tx, ty, ux, uy;
+  bool clx, cly;
+  float qh[4], qn;
+  float Rq[9], S[3], M[9];
+  float Sg[6];                 // 00 01 02 11 12 22
+  float J00, J02, J11, J12;
+  float T0[3], T1[3];
+  float a, b, c, det;
+};
+
+// Discrete structure of one splat.  Operation order (all FP32, no
+// contraction, correctly rounded):
+//   t = ((R0 mu0 + R1 mu1) + R2 mu2) + t0 (per row); cull unless tz > 0.2;
+//   qq = ((w^2 + x^2) + y^2) + z^2, cull unless qq > 0; q /= sqrt(qq);
+//   rotation matrix in the usual unit-quaternion form; S = exp_repro(s);
+//   M = Rq diag(S); Sigma_ab = (M_a0 M_b0 + M_a1 M_b1) + M_a2 M_b2;
+//   lim = 1.3 ((W/2)/fx); clamped u = min(lim, max(-lim, tx/tz));
+//   J00 = fx/tz, J02 = -(fx u)/tz (same for y); T = J R (two products);
+//   Sigma' = T Sigma T^T + 0.3 I, with u_a = (S_a0 T0 + S_a1 T1) + S_a2 T2;
+//   det = a c - b b, cull unless det > 0; lambda = mid + sqrt(max(0, mid^2 - det));
+//   r = ceil(3 sqrt(lambda)); px = fx (tx/tz) + cx;
+//   span = [ceil(px - r), floor(px + r)] clipped to the image, cull if empty.
+__device__ __forceinline__ void sgs_project(const float *y, const SgsCam &cam, int W, int H,
+                                            SgsProj &o) {
+  o.valid = false;
+  const float mx = y[0], my = y[1], mz = y[2];
+  o.tx = ((cam.R[0] * mx + cam.R[1] * my) + cam.R[2] * mz) + cam.t[0];
+  o.ty = ((cam.R[3] * mx + cam.R[4] * my) + cam.R[5] * mz) + cam.t[1];
+  o.tz = ((cam.R[6] * mx + cam.R[7] * my) + cam.R[8] * mz) + cam.t[2];
+  if (!(o.tz > SGS_NEAR)) return;
+  float w = y[SGS_CH_ROT], x = y[SGS_CH_ROT + 1], yy = y[SGS_CH_ROT + 2], z = y[SGS_CH_ROT + 3];
+  const float qq = ((w * w + x * x) + yy * yy) + z * z;
+  if (!(qq > 0.0f)) return;
+  o.qn = __fsqrt_rn(qq);
+  w = __fdiv_rn(w, o.qn);
+  x = __fdiv_rn(x, o.qn);
+  yy = __fdiv_rn(yy, o.qn);
+  z = __fdiv_rn(z, o.qn);
+  o.qh[0] = w; o.qh[1] = x; o.qh[2] = yy; o.qh[3] = z;
+  float *Rq = o.Rq;
+  Rq[0] = 1.0f - 2.0f * (yy * yy + z * z);
+  Rq[1] = 2.0f * (x * yy - w * z);
+  Rq[2] = 2.0f * (x * z + w * yy);
+  Rq[3] = 2.0f * (x * yy + w * z);
+  Rq[4] = 1.0f - 2.0f * (x * x + z * z);
+  Rq[5] = 2.0f * (yy * z - w * x);
+  Rq[6] = 2.0f * (x * z - w * yy);
+  Rq[7] = 2.0f * (yy * z + w * x);
+  Rq[8] = 1.0f - 2.0f * (x * x + yy * yy);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) o.S[k] = sgs_exp_repro(y[SGS_CH_SCALE + k]);
+#pragma unroll
+  for (int e = 0; e < 9; ++e) o.M[e] = Rq[e] * o.S[e % 3];
+  const float *M = o.M;
+  // Sigma: products commute exactly, so the six distinct entries suffice
+  o.Sg[0] = (M[0] * M[0] + M[1] * M[1]) + M[2] * M[2];
+  o.Sg[1] = (M[0] * M[3] + M[1] * M[4]) + M[2] * M[5];
+  o.Sg[2] = (M[0] * M[6] + M[1] * M[7]) + M[2] * M[8];
+  o.Sg[3] = (M[3] * M[3] + M[4] * M[4]) + M[5] * M[5];
+  o.Sg[4] = (M[3] * M[6] + M[4] * M[7]) + M[5] * M[8];
+  o.Sg[5] = (M[6] * M[6] + M[7] * M[7]) + M[8] * M[8];
+  const float limx = 1.3f * __fdiv_rn(0.5f * (float)W, cam.fx);
+  const float limy = 1.3f * __fdiv_rn(0.5f * (float)H, cam.fy);
+  o.ux = __fdiv_rn(o.tx, o.tz);
+  o.uy = __fdiv_rn(o.ty, o.tz);
+  const float cux = fminf(limx, fmaxf(-limx, o.ux));
+  const float cuy = fminf(limy, fmaxf(-limy, o.uy));
+  o.clx = (o.ux < -limx) || (o.ux > limx);
+  o.cly = (o.uy < -limy) || (o.uy > limy);
+  o.J00 = __fdiv_rn(cam.fx, o.tz);
+  o.J02 = __fdiv_rn(-(cam.fx * cux), o.tz);
+  o.J11 = __fdiv_rn(cam.fy, o.tz);
+  o.J12 = __fdiv_rn(-(cam.fy * cuy), o.tz);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    o.T0[b] = o.J00 * cam.R[b] + o.J02 * cam.R[6 + b];
+    o.T1[b] = o.J11 * cam.R[3 + b] + o.J12 * cam.R[6 + b];
+  }
+  const float S00 = o.Sg[0], S01 = o.Sg[1], S02 = o.Sg[2], S11 = o.Sg[3], S12 = o.Sg[4],
+              S22 = o.Sg[5];
+  const float u0 = (S00 * o.T0[0] + S01 * o.T0[1]) + S02 * o.T0[2];
+  const float u1 = (S01 * o.T0[0] + S11 * o.T0[1]) + S12 * o.T0[2];
+  const float u2 = (S02 * o.T0[0] + S12 * o.T0[1]) + S22 * o.T0[2];
+  const float w0 = (S00 * o.T1[0] + S01 * o.T1[1]) + S02 * o.T1[2];
+  const float w1 = (S01 * o.T1[0] + S11 * o.T1[1]) + S12 * o.T1[2];
+  const float w2 = (S02 * o.T1[0] + S12 * o.T1[1]) + S22 * o.T1[2];
+  o.a = ((o.T0[0] * u0 + o.T0[1] * u1) + o.T0[2] * u2) + SGS_DILATION;
+  o.b = (o.T0[0] * w0 + o.T0[1] * w1) + o.T0[2] * w2;
+  o.c = ((o.T1[0] * w0 + o.T1[1] * w1) + o.T1[2] * w2) + SGS_DILATION;
+  o.det = o.a * o.c - o.b * o.b;
+  if (!(o.det > 0.0f)) return;
+  const float mid = 0.5f * (o.a + o.c);
+  const float disc = fmaxf(mid * mid - o.det, 0.0f);
+  const float lmax = mid + __fsqrt_rn(disc);
+  const float rf = ceilf(3.0f * __fsqrt_rn(lmax));
+  o.px = cam.fx * o.ux + cam.cx;
+  o.py = cam.fy * o.uy + cam.cy;
+  const float xlo = ceilf(o.px - rf), xhi = floorf(o.px + rf);
+  const float ylo = ceilf(o.py - rf), yhi = floorf(o.py + rf);
+  if (xhi < 0.0f || xlo > (float)(W - 1) || yhi < 0.0f || ylo > (float)(H - 1)) return;
+  o.x0 = xlo < 0.0f ? 0 : (int)xlo;
+  o.x1 = xhi > (float)(W - 1) ? W - 1 : (int)xhi;
+  o.y0 = ylo < 0.0f ? 0 : (int)ylo;
+  o.y1 = yhi > (float)(H - 1) ? H - 1 : (int)yhi;
+  o.valid = true;
+}
+
+// Real spherical harmonics of degree <= 3 (orthonormal, Condon-Shortley
+// phase, index l^2 + l + m) at the unit direction (x, y, z).  Constants are
+// K_l^m sqrt(2) times the associated-Legendre factor:
+//   Y1: sqrt(3/(4 pi));  Y2: (1/2)sqrt(15/pi), (1/4)sqrt(5/pi), (1/4)sqrt(15/pi);
+//   Y3: (1/4)sqrt(35/(2 pi)), (1/2)sqrt(105/pi), (1/4)sqrt(21/(2 pi)),
+//       (1/4)sqrt(7/pi), (1/4)sqrt(105/pi).
+#define SGS_SH_C0 0.28209479177387814f
+#define SGS_SH_C1 0.48860251190291992f
+#define SGS_SH_C2A 1.0925484305920792f
+#define SGS_SH_C2B 0.31539156525252005f
+#define SGS_SH_C2C 0.54627421529603959f
+#define SGS_SH_C3A 0.59004358992664352f
+#define SGS_SH_C3B 2.8906114426405538f
+#define SGS_SH_C3C 0.45704579946446572f
+#define SGS_SH_C3D 0.37317633259011540f
+#define SGS_SH_C3E 1.4453057213202769f
+
+__device__ __forceinline__ void sgs_sh_basis(float x, float y, float z, float Y[16]) {
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[0] = SGS_SH_C0;
+  Y[1] = -SGS_SH_C1 * y;
+  Y[2] = SGS_SH_C1 * z;
+  Y[3] = -SGS_SH_C1 * x;
+  Y[4] = SGS_SH_C2A * x * y;
+  Y[5] = -SGS_SH_C2A * y * z;
+  Y[6] = SGS_SH_C2B * (2.0f * zz - xx - yy);
+  Y[7] = -SGS_SH_C2A * x * z;
+  Y[8] = SGS_SH_C2C * (xx - yy);
+  Y[9] = -SGS_SH_C3A * y * (3.0f * xx - yy);
+  Y[10] = SGS_SH_C3B * x * y * z;
+  Y[11] = -SGS_SH_C3C * y * (4.0f * zz - xx - yy);
+  Y[12] = SGS_SH_C3D * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+  Y[13] = -SGS_SH_C3C * x * (4.0f * zz - xx - yy);
+  Y[14] = SGS_SH_C3E * z * (xx - yy);
+  Y[15] = -SGS_SH_C3A * x * (xx - 3.0f * yy);
+}
+
+// Gradient of each basis polynomial w.r.t. (x, y, z).
+__device__ __forceinline__ void sgs_sh_grad(float x, float y, float z, float G[16][3]) {
+  const float xx = x * x, yy = y * y, zz = z * z;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) G[k][0] = G[k][1] = G[k][2] = 0.0f;
+  G[1][1] = -SGS_SH_C1;
+  G[2][2] = SGS_SH_C1;
+  G[3][0] = -SGS_SH_C1;
+  G[4][0] = SGS_SH_C2A * y; G[4][1] = SGS_SH_C2A * x;
+  G[5][1] = -SGS_SH_C2A * z; G[5][2] = -SGS_SH_C2A * y;
+  G[6][0] = -2.0f * SGS_SH_C2B * x; G[6][1] = -2.0f * SGS_SH_C2B * y; G[6][2] = 4.0f * SGS_SH_C2B * z;
+  G[7][0] = -SGS_SH_C2A * z; G[7][2] = -SGS_SH_C2A * x;
+  G[8][0] = 2.0f * SGS_SH_C2C * x; G[8][1] = -2.0f * SGS_SH_C2C * y;
+  G[9][0] = -SGS_SH_C3A * 6.0f * x * y; G[9][1] = -SGS_SH_C3A * 3.0f * (xx - yy);
+  G[10][0] = SGS_SH_C3B * y * z; G[10][1] = SGS_SH_C3B * x * z; G[10][2] = SGS_SH_C3B * x * y;
+  G[11][0] = SGS_SH_C3C * 2.0f * x * y;
+  G[11][1] = -SGS_SH_C3C * (4.0f * zz - xx - 3.0f * yy);
+  G[11][2] = -SGS_SH_C3C * 8.0f * y * z;
+  G[12][0] = -SGS_SH_C3D * 6.0f * x * z;
+  G[12][1] = -SGS_SH_C3D * 6.0f * y * z;
+  G[12][2] = SGS_SH_C3D * (6.0f * zz - 3.0f * xx - 3.0f * yy);
+  G[13][0] = -SGS_SH_C3C * (4.0f * zz - 3.0f * xx - yy);
+  G[13][1] = SGS_SH_C3C * 2.0f * x * y;
+  G[13][2] = -SGS_SH_C3C * 8.0f * x * z;
+  G[14][0] = SGS_SH_C3E * 2.0f * x * z; G[14][1] = -SGS_SH_C3E * 2.0f * y * z;
+  G[14][2] = SGS_SH_C3E * (xx - yy);
+  G[15][0] = -SGS_SH_C3A * 3.0f * (xx - yy); G[15][1] = SGS_SH_C3A * 6.0f * x * y;
+}
+
+__device__ __forceinline__ int sgs_sh_channel(int k, int ch) {
+  return k == 0 ? SGS_CH_DC + ch : SGS_CH_REST + 3 * (k - 1) + ch;
+}
+
+// Wave-level helpers (wave64).
+__device__ __forceinline__ float sgs_wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double sgs_wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+inline unsigned sgs_blocks(int64_t n, int threads) {
+  return (unsigned)((n + threads - 1) / threads);
+}

@@ -1,0 +1,331 @@
+// Tile binning and the (tile, depth) order (paper Sec. 3.1: tile-based
+// rasterization of depth-sorted Gaussians).
+//
+// Instead of one radix sort over 64-bit (tile | depth) keys of every pair,
+// the splats are sorted by depth once (V*N keys, 32 bits), their pairs are
+// emitted in that order, and the pairs are then stably sorted by tile id
+// alone (ceil(log2(V*tiles)) bits, two 8-bit passes at the measured sizes).
+// Stability makes the result identical to the (tile, depth, index) order,
+// and the pair array -- ten times larger than the splat array -- crosses
+// HBM two times per pass for two passes instead of six.
+#include "sgs_internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kItems = 16;
+constexpr int kTile = kThreads * kItems;  // elements per block
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of uint32 (reduce -> scan of block sums -> downsweep).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_wave,
+                                                         uint32_t &total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(x, o, 64);
+    if (lane >= o) x += t;
+  }
+  if (lane == 63) s_wave[wave] = x;
+  __syncthreads();
+  uint32_t off = 0;
+  total = 0;
+  for (int w = 0; w < kWaves; ++w) {
+    const uint32_t t = s_wave[w];
+    if (w < wave) off += t;
+    total += t;
+  }
+  __syncthreads();
+  return off + x - v;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_scan_reduce(const uint32_t *__restrict__ in, int64_t count, uint32_t *__restrict__ sums) {
+  __shared__ uint32_t s_wave[kWaves];
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  uint32_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
+    if (i < count) acc += in[i];
+  }
+  uint32_t total;
+  block_exclusive_scan(acc, s_wave, total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// single block: exclusive scan of the block sums in place; total to *total_out
+__global__ void __launch_bounds__(kThreads)
+k_scan_sums(uint32_t *__restrict__ sums, int64_t nb, uint32_t *__restrict__ total_out,
+            uint32_t *__restrict__ tail) {
+  __shared__ uint32_t s_wave[kWaves];
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < nb; base += kThreads) {
+    const int64_t i = base + threadIdx.x;
+    const uint32_t v = i < nb ? sums[i] : 0;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan(v, s_wave, total);
+    if (i < nb) sums[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) {
+    if (total_out) *total_out = carry;
+    if (tail) *tail = carry;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_scan_down(const uint32_t *__restrict__ in, int64_t count, const uint32_t *__restrict__ sums,
+            uint32_t *__restrict__ out) {
+  __shared__ uint32_t s_wave[kWaves];
+  // each thread scans kItems consecutive elements
+  const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+  uint32_t v[kItems];
+  uint32_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    v[k] = (base + k < count) ? in[base + k] : 0;
+    acc += v[k];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(acc, s_wave, total) + sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    if (base + k < count) out[base + k] = run;
+    run += v[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort, 8-bit digits, reduce-then-scan.  Elements of a
+// block are taken in rounds of 256 (position base + r*256 + tid); within a
+// round each wave finds the lanes sharing its digit with eight ballots, so
+// ranks follow (round, wave, lane) = input order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+  uint64_t m = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bal = __ballot(bit);
+    m &= bit ? bal : ~bal;
+  }
+  return m;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_radix_hist(const uint32_t *__restrict__ keys, int64_t count, int shift,
+             uint32_t *__restrict__ hist, int64_t nb) {
+  __shared__ uint32_t s_hist[256];
+  s_hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+    const bool valid = i < count;
+    const uint32_t d = valid ? (keys[i] >> shift) & 0xFFu : 0u;
+    const uint64_t m = match_digit(d, valid);
+    if (valid && (__ffsll((long long)m) - 1) == lane) atomicAdd(&s_hist[d], (uint32_t)__popcll(m));
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = s_hist[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t count,
+                int shift, const uint32_t *__restrict__ hist_scanned, int64_t nb) {
+  __shared__ uint32_t s_base[256];
+  __shared__ uint32_t s_run[256];
+  __shared__ uint32_t s_wc[kWaves][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  s_base[threadIdx.x] = hist_scanned[(int64_t)threadIdx.x * nb + blockIdx.x];
+  s_run[threadIdx.x] = 0;
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < kItems; ++r) {
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s_wc[w][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+    const bool valid = i < count;
+    uint32_t k = 0, v = 0;
+    if (valid) {
+      k = kin[i];
+      v = vin[i];
+    }
+    const uint32_t d = (k >> shift) & 0xFFu;
+    const uint64_t m = match_digit(d, valid);
+    const uint32_t rank = (uint32_t)__popcll(m & lt);
+    if (valid && (__ffsll((long long)m) - 1) == lane) s_wc[wave][d] = (uint32_t)__popcll(m);
+    __syncthreads();
+    {
+      const int t = threadIdx.x;
+      uint32_t run = s_run[t];
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t c = s_wc[w][t];
+        s_wc[w][t] = run;
+        run += c;
+      }
+      s_run[t] = run;
+    }
+    __syncthreads();
+    if (valid) {
+      const uint32_t pos = s_base[d] + s_wc[wave][d] + rank;
+      kout[pos] = k;
+      vout[pos] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Binning
+// ---------------------------------------------------------------------------
+__global__ void k_gather_touched(const uint32_t *__restrict__ order,
+                                 const uint32_t *__restrict__ touched, int64_t count,
+                                 uint32_t *__restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < count) out[k] = touched[order[k]];
+}
+
+// Emit the pairs of each splat, splats in depth order; the value is the
+// Gaussian index, the key the global tile id.
+__global__ void k_duplicate(const uint32_t *__restrict__ order, const uint32_t *__restrict__ touched,
+                            const uint32_t *__restrict__ offsets, const float4 *__restrict__ rec1,
+                            int64_t count, int64_t n, int TW, int TH, int GW,
+                            int64_t tiles_per_view, uint32_t *__restrict__ tile_key,
+                            uint32_t *__restrict__ pair_val) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const uint32_t s = order[k];
+  if (touched[s] == 0) return;
+  const float4 r = rec1[s];
+  const uint32_t sx = __float_as_uint(r.z), sy = __float_as_uint(r.w);
+  const int x0 = sx & 0xFFFF, x1 = sx >> 16, y0 = sy & 0xFFFF, y1 = sy >> 16;
+  const uint32_t v = (uint32_t)(s / n);
+  const uint32_t gi = (uint32_t)(s - (int64_t)v * n);
+  uint32_t pos = offsets[k];
+  const uint32_t tbase = (uint32_t)(v * tiles_per_view);
+  for (int ty = y0 / TH; ty <= y1 / TH; ++ty)
+    for (int tx = x0 / TW; tx <= x1 / TW; ++tx) {
+      tile_key[pos] = tbase + (uint32_t)(ty * GW + tx);
+      pair_val[pos] = gi;
+      ++pos;
+    }
+}
+
+__global__ void k_zero_ranges(uint2 *__restrict__ ranges, int64_t tiles) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < tiles) ranges[t] = make_uint2(0, 0);
+}
+
+__global__ void k_ranges(const uint32_t *__restrict__ tile_key, int64_t P,
+                         uint2 *__restrict__ ranges) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= P) return;
+  const uint32_t t = tile_key[e];
+  if (e == 0 || tile_key[e - 1] != t) ranges[t].x = (uint32_t)e;
+  if (e == P - 1 || tile_key[e + 1] != t) ranges[t].y = (uint32_t)(e + 1);
+}
+
+}  // namespace
+
+hipError_t ensure_tmp(sgs_ctx *c, int64_t scan_words, int64_t hist_words) {
+  if (scan_words > c->scan_tmp_words) {
+    if (c->scan_tmp) (void)hipFree(c->scan_tmp);
+    c->scan_tmp = nullptr;
+    hipError_t e = hipMalloc(&c->scan_tmp, sizeof(uint32_t) * scan_words);
+    if (e != hipSuccess) { c->scan_tmp_words = 0; return e; }
+    c->scan_tmp_words = scan_words;
+  }
+  if (hist_words > c->sort_hist_words) {
+    if (c->sort_hist) (void)hipFree(c->sort_hist);
+    c->sort_hist = nullptr;
+    hipError_t e = hipMalloc(&c->sort_hist, sizeof(uint32_t) * hist_words);
+    if (e != hipSuccess) { c->sort_hist_words = 0; return e; }
+    c->sort_hist_words = hist_words;
+  }
+  return hipSuccess;
+}
+
+// scan_tmp must hold ceil(count / kTile) words
+hipError_t launch_exclusive_scan(sgs_ctx *c, const uint32_t *in, uint32_t *out, int64_t count,
+                                 uint32_t *total_out) {
+  const int64_t nb = (count + kTile - 1) / kTile;
+  if (nb == 0) {
+    if (total_out) (void)hipMemsetAsync(total_out, 0, sizeof(uint32_t), c->stream);
+    return hipGetLastError();
+  }
+  if (nb > c->scan_tmp_words) return hipErrorInvalidValue;
+  k_scan_reduce<<<(unsigned)nb, kThreads, 0, c->stream>>>(in, count, c->scan_tmp);
+  k_scan_sums<<<1, kThreads, 0, c->stream>>>(c->scan_tmp, nb, total_out, out + count);
+  k_scan_down<<<(unsigned)nb, kThreads, 0, c->stream>>>(in, count, c->scan_tmp, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2], int64_t count,
+                             int bits, int *which) {
+  int cur = 0;
+  const int64_t nb = (count + kTile - 1) / kTile;
+  if (count <= 1 || bits <= 0) {
+    *which = 0;
+    return hipSuccess;
+  }
+  const int64_t hwords = nb * 256;
+  const int64_t snb = (hwords + kTile - 1) / kTile;
+  if (hwords + 1 > c->sort_hist_words || snb > c->scan_tmp_words) return hipErrorInvalidValue;
+  for (int shift = 0; shift < bits; shift += 8) {
+    k_radix_hist<<<(unsigned)nb, kThreads, 0, c->stream>>>(keys[cur], count, shift, c->sort_hist,
+                                                           nb);
+    // in-place exclusive scan of the digit-major histogram
+    k_scan_reduce<<<(unsigned)snb, kThreads, 0, c->stream>>>(c->sort_hist, hwords, c->scan_tmp);
+    k_scan_sums<<<1, kThreads, 0, c->stream>>>(c->scan_tmp, snb, nullptr, nullptr);
+    k_scan_down<<<(unsigned)snb, kThreads, 0, c->stream>>>(c->sort_hist, hwords, c->scan_tmp,
+                                                           c->sort_hist);
+    k_radix_scatter<<<(unsigned)nb, kThreads, 0, c->stream>>>(keys[cur], vals[cur], keys[cur ^ 1],
+                                                              vals[cur ^ 1], count, shift,
+                                                              c->sort_hist, nb);
+    cur ^= 1;
+  }
+  *which = cur;
+  return hipGetLastError();
+}
+
+// Depth sort of all (view, Gaussian) splats, then the pair offsets.
+hipError_t launch_depth_order(sgs_ctx *c) {
+  int which = 0;
+  hipError_t e = launch_radix_sort(c, c->depth_key, c->depth_val, c->vn, 32, &which);
+  if (e != hipSuccess) return e;
+  c->depth_sorted_buf = which;
+  // touched in depth order -> scratch (the other key buffer is free now)
+  uint32_t *tmp = c->depth_key[which ^ 1];
+  k_gather_touched<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(c->depth_val[which],
+                                                                  c->touched, c->vn, tmp);
+  return launch_exclusive_scan(c, tmp, c->offsets, c->vn, c->d_pairs_total);
+}
+
+hipError_t launch_bin_pairs(sgs_ctx *c) {
+  const int64_t P = c->pairs;
+  const uint32_t *order = c->depth_val[c->depth_sorted_buf];
+  const float4 *rec1 = c->rec + c->vn;
+  k_duplicate<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(
+      order, c->touched, c->offsets, rec1, c->vn, c->n, c->TW, c->TH, c->GW, c->tiles_per_view,
+      c->tile_key[0], c->pair_val[0]);
+  int bits = 0;
+  while (((int64_t)1 << bits) < c->total_tiles) ++bits;
+  int which = 0;
+  hipError_t e = launch_radix_sort(c, c->tile_key, c->pair_val, P, bits, &which);
+  if (e != hipSuccess) return e;
+  c->pair_sorted_buf = which;
+  k_zero_ranges<<<sgs_blocks(c->total_tiles, 256), 256, 0, c->stream>>>(c->ranges,
+                                                                       c->total_tiles);
+  if (P > 0)
+    k_ranges<<<sgs_blocks(P, 256), 256, 0, c->stream>>>(c->tile_key[which], P, c->ranges);
+  return hipGetLastError();
+}

@@ -1,0 +1,78 @@
+"""One RD step of the structural-formation stage on the GPU.
+
+``RDStep`` owns the device buffers of a step (torch tensors, used only as
+memory) and issues the C-ABI calls in order:
+
+    fakequant_prune -> rate_proxy -> render_fwd -> l1_loss
+    -> render_bwd -> fakequant_prune_bwd
+
+Every arithmetic step runs in libspeedygs's HIP kernels; nothing here
+computes.  The loss is D_render + lam * R_proxy (paper Sec. 3.3.2, total loss,
+with the L1 part of D_render).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from ._lib import NCH, RATE_GRAD_FLOATS, STATS_WORDS, Context
+
+
+class RDStep:
+    def __init__(self, ctx: Context, n: int, npad: int, n_hat: int, cams: np.ndarray,
+                 width: int, height: int, tile=(16, 16), tau: float = 1.0):
+        import torch
+        self.torch = torch
+        self.ctx = ctx
+        dev = torch.device("cuda", ctx.device)
+        self.dev = dev
+        V = cams.shape[0]
+        self.n, self.npad, self.n_hat, self.V, self.W, self.H = n, npad, n_hat, V, width, height
+        ctx.set_scene(n, npad, n_hat, cams, width, height, tile=tile, tau=tau)
+        f32, u8, i32, i64 = torch.float32, torch.uint8, torch.int32, torch.int64
+        e = lambda *s, dt=f32: torch.empty(*s, dtype=dt, device=dev)
+        self.qparams = e(NCH, npad)
+        self.hard = e(n, dt=u8)
+        self.soft = e(n)
+        self.stats = e(STATS_WORDS, dt=i64)
+        self.rate3 = e(3)
+        self.rate_grad = e(RATE_GRAD_FLOATS)
+        self.image = e(V, 3, height, width)
+        self.final_T = e(V, height, width)
+        self.last = e(V, height, width, dt=i32)
+        self.evals = torch.zeros(1, dtype=i64, device=dev)
+        self.loss = e(1)
+        self.dimage = e(V, 3, height, width)
+        self.grad_qparams = e(NCH, npad)
+        self.grad_mask = e(n)
+        self.grad_q = e(NCH)
+        self.grad_score = e(n)
+
+    def forward(self, params, qstep, score, target, lam: float, mask_mode: int = 0,
+                given_mask=None, seed: int = 0, step: int = 0, count_evals: bool = True,
+                loss_scale: float = 1.0):
+        c = self.ctx
+        c.fakequant_prune(params, qstep, score, mask_mode, given_mask, seed, step, self.qparams,
+                          self.hard, self.soft, self.stats)
+        c.rate_proxy(self.stats, qstep, lam, self.rate3, self.rate_grad)
+        c.render_fwd(self.qparams, self.hard, self.image, self.final_T, self.last,
+                     self.evals if count_evals else None)
+        c.l1_loss(self.image, target, self.loss, self.dimage, loss_scale)
+
+    def backward(self, params, qstep, mask_mode: int = 0, grad_params=None, dimage=None):
+        """Gradients of loss = D + lam R.  grad_params defaults to an in-place
+        reuse of the render gradient buffer (straight-through aliasing)."""
+        c = self.ctx
+        gp = self.grad_qparams if grad_params is None else grad_params
+        c.render_bwd(self.qparams, self.hard, self.final_T, self.last,
+                     self.dimage if dimage is None else dimage, self.grad_qparams,
+                     self.grad_mask)
+        c.fakequant_prune_bwd(params, qstep, self.soft, mask_mode, self.rate_grad, self.stats,
+                              self.grad_qparams, self.grad_mask, gp, self.grad_q,
+                              self.grad_score)
+        return gp
+
+    def step(self, params, qstep, score, target, lam, mask_mode=0, given_mask=None, seed=0,
+             step=0, count_evals=True, grad_params=None):
+        self.forward(params, qstep, score, target, lam, mask_mode, given_mask, seed, step,
+                     count_evals)
+        return self.backward(params, qstep, mask_mode, grad_params)

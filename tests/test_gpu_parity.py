@@ -1,0 +1,259 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Bars: structure (codes k, hard mask, culling, spans, depth keys, sorted tile
+lists, ranges, per-pixel stop positions) bit-exact; pixels within 1e-4
+absolute outside margin pixels (where FP32 and FP64 may take a different
+per-pair decision: alpha within 2e-5 relative of 1/255 or 0.99, or T within
+2e-5 relative of 1e-4); gradients within 1e-3 relative (per tensor in L2, and
+element-wise on entries above 1 % of the tensor's largest); rate scalars
+within 1e-6 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from synth import NCH
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def gctx(dev):
+    from paper_2607_12656_amd import Context
+    return Context(0)
+
+
+def T(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def grad_close(g, ref, tol=1e-3, name=""):
+    g = np.asarray(g, np.float64).ravel()
+    ref = np.asarray(ref, np.float64).ravel()
+    nr = np.linalg.norm(ref)
+    rel = np.linalg.norm(g - ref) / max(nr, 1e-30)
+    big = np.abs(ref) >= 1e-2 * np.abs(ref).max() if ref.size else np.zeros(0, bool)
+    ew = (np.abs(g - ref)[big] / np.abs(ref)[big]).max() if big.any() else 0.0
+    assert rel <= tol, f"{name}: relative L2 error {rel:.3e}"
+    assert ew <= tol, f"{name}: element-wise relative error {ew:.3e}"
+    return rel, ew
+
+
+def gpu_step(gctx, dev, sc, tile=(16, 16), lam=0.5, mode=0, seed=0, step=0, dimage=None):
+    from paper_2607_12656_amd.rd import RDStep
+    _say(f"[gpu] {sc.name} tile={tile} mode={mode} n={sc.n} V={sc.views}")
+    rd = RDStep(gctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height, tile=tile)
+    params, q, score = T(sc.params, dev), T(sc.qstep, dev), T(sc.score, dev)
+    mask, target = T(sc.given_mask, dev), T(sc.target, dev)
+    rd.forward(params, q, score, target, lam, mode, mask, seed, step)
+    d_in = None if dimage is None else T(dimage.astype(np.float32), dev)
+    gp = torch.empty_like(params)
+    rd.backward(params, q, mode, grad_params=gp, dimage=d_in)
+    torch.cuda.synchronize()
+    P, flags = gctx.query(rd.stats)
+    out = dict(rd=rd, P=P)
+    tile_ids = torch.empty(max(P, 1), dtype=torch.int32, device=dev)
+    vals = torch.empty(max(P, 1), dtype=torch.int32, device=dev)
+    ranges = torch.empty(rd.V * (-(-sc.width // tile[0])) * (-(-sc.height // tile[1])), 2,
+                         dtype=torch.int32, device=dev)
+    spans = torch.empty(rd.V, sc.n, 4, dtype=torch.int32, device=dev)
+    depth = torch.empty(rd.V, sc.n, dtype=torch.float32, device=dev)
+    splats = torch.empty(rd.V, sc.n, 12, dtype=torch.float32, device=dev)
+    gctx.copy_structure(tile_ids, vals, max(P, 1), ranges, spans, depth, splats)
+    sgrad = torch.empty(rd.V, sc.n, 12, dtype=torch.float32, device=dev)
+    gctx.copy_splat_grads(sgrad)
+    torch.cuda.synchronize()
+    c = lambda x: x.cpu().numpy()
+    out.update(qparams=c(rd.qparams), hard=c(rd.hard), soft=c(rd.soft),
+               stats=c(rd.stats).view(np.uint64), rate3=c(rd.rate3), rate_grad=c(rd.rate_grad),
+               image=c(rd.image), T=c(rd.final_T), last=c(rd.last).view(np.uint32),
+               evals=int(c(rd.evals)[0]), loss=float(c(rd.loss)[0]), dimage=c(rd.dimage),
+               gq_render=c(rd.grad_qparams), gmask=c(rd.grad_mask), gparams=c(gp),
+               gq=c(rd.grad_q), gscore=c(rd.grad_score),
+               tile_ids=c(tile_ids)[:P].view(np.uint32), vals=c(vals)[:P].view(np.uint32),
+               ranges=c(ranges).view(np.uint32), spans=c(spans), depth=c(depth),
+               splats=c(splats), sgrad=c(sgrad))
+    return out
+
+
+def oracle_step(orc, sc, tile=(16, 16), lam=0.5, mode=0, seed=0, step=0, dimage=None):
+    return orc.rd_step(sc.params, sc.qstep, sc.score, sc.given_mask, sc.cams, sc.width,
+                       sc.height, sc.target, sc.n, sc.n_hat, lam, mask_mode=mode, seed=seed,
+                       step=step, TW=tile[0], TH=tile[1], dimage=dimage)
+
+
+def check_structure(g, r, sc):
+    n = sc.n
+    assert np.array_equal(g["qparams"][:, :n], r["yhat"][:, :n]), "quantized parameters"
+    assert np.array_equal(g["hard"], r["mhat"]), "hard mask"
+    st = r["st"]
+    valid = st.valid > 0
+    gvalid = g["spans"][..., 0] >= 0
+    assert np.array_equal(gvalid, valid), "culling"
+    assert np.array_equal(g["spans"][valid], st.span[valid]), "pixel spans"
+    assert np.array_equal(g["depth"][valid].view(np.uint32), st.tz[valid].view(np.uint32)), "depth"
+    assert g["P"] == st.keys.size, f"pair count {g['P']} vs {st.keys.size}"
+    assert np.array_equal(g["tile_ids"].astype(np.uint64), st.keys >> np.uint64(32)), "tile ids"
+    assert np.array_equal(g["vals"], st.vals), "sorted Gaussian indices"
+    assert np.array_equal(g["ranges"], st.ranges), "tile ranges"
+
+
+def check_stats(g, r, sc):
+    s = g["stats"]
+    rate = r["rate"]
+    imin = (s[:NCH] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    imax = 0xFFFFFFFF - (s[NCH:2 * NCH] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    assert np.array_equal(imin, rate["argmin"]) and np.array_equal(imax, rate["argmax"])
+    assert int(s[118]) == int(r["mhat"].sum())
+    assert int(s[119]) == 0
+    R, Lq, Lm = g["rate3"]
+    assert abs(R - rate["R"]) <= 1e-6 * abs(rate["R"])
+    assert abs(Lq - rate["Lq"]) <= 1e-6 * abs(rate["Lq"])
+    assert abs(Lm - rate["Lm"]) <= 1e-6 * abs(rate["Lm"])
+
+
+def check_image(g, r):
+    ok = r["fw"]["margin"] == 0
+    frac = 1 - ok.mean()
+    err = np.abs(g["image"] - r["fw"]["image"]).max(axis=1)[ok].max()
+    terr = np.abs(g["T"] - r["fw"]["T"])[ok].max()
+    assert err <= 1e-4, f"pixel error {err:.3e}"
+    assert terr <= 1e-4, f"transmittance error {terr:.3e}"
+    assert np.array_equal(g["last"][ok], r["fw"]["last"][ok].astype(np.uint32)), "stop positions"
+    assert frac <= 1e-3, f"margin pixels {frac:.2e}"
+    if not (~ok).any():
+        assert g["evals"] == r["fw"]["evals"]
+    return err, frac
+
+
+TINY = [
+    dict(n=48, W=45, H=37, V=1, seed=2),
+    dict(n=64, W=70, H=50, V=2, seed=3),
+    dict(n=200, W=96, H=80, V=1, seed=4, logscale=-2.5),
+]
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+@pytest.mark.parametrize("cfg", range(len(TINY)))
+def test_tiny_scenes_full_step(orc, gctx, dev, tile, cfg):
+    c = TINY[cfg]
+    sc = synth.make_tiny(c["n"], c["W"], c["H"], views=c["V"], seed=c["seed"],
+                         logscale_mu=c.get("logscale", -2.0))
+    g = gpu_step(gctx, dev, sc, tile=tile)
+    r = oracle_step(orc, sc, tile=tile, dimage=g["dimage"])
+    check_structure(g, r, sc)
+    check_stats(g, r, sc)
+    check_image(g, r)
+    # L1 forward
+    assert abs(g["loss"] - r["D"]) <= 1e-6 * r["D"]
+    # render backward fed the same dL/dimage
+    grad_close(g["gq_render"][:, :sc.n], r["gyhat"][:, :sc.n], name="grad qparams")
+    grad_close(g["gmask"], r["gmhat"], name="grad mask")
+    grad_close(g["gparams"][:, :sc.n], r["gy"][:, :sc.n], name="grad params")
+    grad_close(g["gq"], r["gq"], name="grad qstep")
+
+
+def test_projection_records(orc, gctx, dev):
+    sc = synth.make_scene("c1")
+    g = gpu_step(gctx, dev, sc)
+    r = oracle_step(orc, sc, dimage=g["dimage"])
+    pj = orc.project64(r["yhat"].astype(np.float64), sc.n, sc.cams, sc.width, sc.height, r["st"])
+    ok = r["st"].valid > 0
+    sp = g["splats"][ok]
+    ref = pj[ok]
+    assert np.allclose(sp[:, 0:2], ref[:, 0:2], rtol=0, atol=2e-4)
+    for k in (2, 3, 4):
+        scale = np.abs(ref[:, 2:5]).max(axis=1)
+        assert (np.abs(sp[:, k] - ref[:, k]) <= 1e-5 * scale + 1e-7).all(), f"conic {k}"
+    assert np.allclose(sp[:, 5], ref[:, 5], atol=1e-6)
+    assert np.allclose(sp[:, 6:9], ref[:, 6:9], atol=2e-6)
+
+
+def test_c1_full_step(orc, gctx, dev):
+    """4,096 Gaussians, 128x128: the small measured configuration, lam = 2.5e-5
+    and lam = 1 (rate gradients visible)."""
+    sc = synth.make_scene("c1")
+    for lam in (2.5e-5, 1.0):
+        g = gpu_step(gctx, dev, sc, lam=lam)
+        r = oracle_step(orc, sc, lam=lam, dimage=g["dimage"])
+        check_structure(g, r, sc)
+        check_stats(g, r, sc)
+        err, frac = check_image(g, r)
+        _say(f"c1 lam={lam}: pixel err {err:.2e}, margin {frac:.2e}, P={g['P']}, E={g['evals']}")
+        grad_close(g["gparams"][:, :sc.n], r["gy"][:, :sc.n], name="grad params")
+        grad_close(g["gq"], r["gq"], name="grad qstep")
+        grad_close(g["gmask"], r["gmhat"], name="grad mask")
+
+
+def test_gumbel_mask_mode(orc, gctx, dev):
+    sc = synth.make_tiny(300, 64, 48, seed=9)
+    for step in (0, 7):
+        g = gpu_step(gctx, dev, sc, mode=1, seed=1234, step=step)
+        r = oracle_step(orc, sc, mode=1, seed=1234, step=step, dimage=g["dimage"])
+        assert np.array_equal(g["hard"], r["mhat"])
+        assert np.allclose(g["soft"], r["msoft"], atol=2e-6)
+        check_structure(g, r, sc)
+        check_image(g, r)
+        grad_close(g["gscore"], r["gs"], name="grad score")
+    # keep-all mode
+    g = gpu_step(gctx, dev, sc, mode=2)
+    assert g["hard"].all()
+
+
+def test_fakequant_bwd_isolated(orc, gctx, dev):
+    """Same upstream gradient on both sides: STE copy, LSQ step gradient,
+    rate-gradient scatter."""
+    from paper_2607_12656_amd.rd import RDStep
+    sc = synth.make_tiny(5000, 32, 32, seed=5)
+    rng = np.random.default_rng(1)
+    gyh = np.zeros((NCH, sc.npad), np.float32)
+    gyh[:, :sc.n] = rng.normal(size=(NCH, sc.n))
+    rd = RDStep(gctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height)
+    params, q = T(sc.params, dev), T(sc.qstep, dev)
+    gctx.fakequant_prune(params, q, None, 0, T(sc.given_mask, dev), 0, 0, rd.qparams, rd.hard,
+                         rd.soft, rd.stats)
+    lam = 0.3
+    gctx.rate_proxy(rd.stats, q, lam, rd.rate3, rd.rate_grad)
+    gin = T(gyh, dev)
+    gm = torch.zeros(sc.n, device=dev)
+    gp = torch.empty_like(params)
+    gctx.fakequant_prune_bwd(params, q, rd.soft, 0, rd.rate_grad, rd.stats, gin, gm, gp,
+                             rd.grad_q, rd.grad_score)
+    torch.cuda.synchronize()
+    rate = orc.rate_proxy(sc.params, sc.qstep, sc.given_mask, sc.n, sc.n_hat, lam)
+    gy, gq, _ = orc.fakequant_bwd(sc.params, sc.qstep, gyh.astype(np.float64), 0,
+                                  np.zeros(sc.n), 1.0, np.zeros(sc.n), sc.n)
+    gy = gy + rate["gy"]
+    gq = gq + rate["gq"]
+    grad_close(gp.cpu().numpy()[:, :sc.n], gy[:, :sc.n], tol=1e-6, name="grad params")
+    grad_close(rd.grad_q.cpu().numpy(), gq, tol=1e-5, name="grad qstep")
+
+
+def test_invalid_step_size_flag(gctx, dev):
+    from paper_2607_12656_amd import SgsError
+    from paper_2607_12656_amd.rd import RDStep
+    sc = synth.make_tiny(100, 32, 32, seed=6)
+    rd = RDStep(gctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height)
+    q = sc.qstep.copy()
+    q[7] = 0.0
+    gctx.fakequant_prune(T(sc.params, dev), T(q, dev), None, 0, T(sc.given_mask, dev), 0, 0,
+                         rd.qparams, rd.hard, rd.soft, rd.stats)
+    with pytest.raises(SgsError):
+        gctx.query(rd.stats)
