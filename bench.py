@@ -1,0 +1,179 @@
+#!/usr/bin/env python
+"""Benchmark of one RD step (forward + backward) of SpeedyGS's structural
+formation on one MI355X.
+
+Workload (the measured configuration): plain rate proxy, 1,000,000 Gaussians
+(clustered: 3-component mixture), one 1297x840 camera on the radius-4 ring,
+learned per-channel steps initialised to 2^-6, 20 % of the Gaussians pruned
+by a given mask, L1 distortion against a seeded random target,
+lambda = 2.5e-5.  Inputs are synthetic (seeded), resident in HBM before the
+timed region.
+
+A step = fake-quantize + mask + channel statistics, rate proxy, projection,
+depth sort, pair emission, tile sort, ranges, blend, L1, blend backward,
+projection backward, quantizer/mask backward.
+
+Prints one JSON line: ms/step, Gaussian-pixel evaluations per second
+(E / step time, E = in-support (Gaussian, pixel) evaluations of the forward,
+the set the backward re-walks), the roofline of the dominant kernel group
+(HIP events on the library's stream over the timed region) and the FP64
+oracle timed on the host as a CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+# Algorithmic work per unit ("Roofline model").
+NCH = 59
+FLOP_PER_EVAL_FWD = 24     # support test excluded; exp counted as one flop
+FLOP_PER_EVAL_BWD = 62
+
+
+def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int):
+    """(bound, algorithmic amount per launch, unit) of one kernel group."""
+    pix = V * W * H
+    if g == "fakequant":
+        return "hbm", n * (NCH * 4 * 2 + 1 + 1 + 4), "B"      # y in, yhat out, mask in/out, soft
+    if g == "preprocess":
+        return "hbm", n * (NCH * 4 + 1) + V * n * (48 + 12), "B"
+    if g == "depth_sort":
+        return "hbm", V * n * 16, "B"
+    if g == "scan":
+        return "hbm", V * n * 16, "B"
+    if g == "duplicate":
+        return "hbm", V * n * 12 + P * 8, "B"
+    if g == "tile_sort":
+        return "hbm", P * 16, "B"
+    if g == "ranges":
+        return "hbm", P * 4, "B"
+    if g == "blend_fwd":
+        return "alu", E * FLOP_PER_EVAL_FWD, "FLOP"
+    if g == "l1":
+        return "hbm", pix * 3 * 12, "B"
+    if g == "grad_clear":
+        return "hbm", V * n * 48, "B"
+    if g == "blend_bwd":
+        return "alu", E * FLOP_PER_EVAL_BWD, "FLOP"
+    if g == "preprocess_bwd":
+        return "hbm", n * (NCH * 4 * 2 + 4) + V * n * 48, "B"
+    if g == "fakequant_bwd":
+        return "hbm", n * (NCH * 4 * 3 + 4 * 3), "B"
+    return "hbm", 0, "B"
+
+
+def cpu_baseline(sc, lam, budget_s: float):
+    """The FP64 oracle, as it stands, on the same workload: the full step
+    (forward + backward) on the same scene and camera.  Single-threaded."""
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    r = oracle.rd_step(sc.params, sc.qstep, sc.score, sc.given_mask, sc.cams, sc.width,
+                       sc.height, sc.target, sc.n, sc.n_hat, lam)
+    dt = time.perf_counter() - t0
+    E = r["fw"]["evals"]
+    return {"value": E / dt, "unit": "Gaussian-pixel evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full RD step (fwd+bwd) of the measured workload, "
+                      f"{E} evals in {dt:.1f} s, single thread",
+            "s_per_step": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=60.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2607_12656_amd import Context
+    from paper_2607_12656_amd.rd import RDStep
+
+    sc = synth.make_scene(args.workload)
+    lam = 2.5e-5
+    dev = torch.device("cuda", 0)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    params, q, score = t(sc.params), t(sc.qstep), t(sc.score)
+    mask, target = t(sc.given_mask), t(sc.target)
+    ctx = Context(0)
+    rd = RDStep(ctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height)
+    def step(count=False):
+        # the straight-through gradient is written in place over the render
+        # gradient buffer (the C ABI allows grad_params == grad_qparams)
+        rd.forward(params, q, score, target, lam, 0, mask, 0, 0, count_evals=count)
+        rd.backward(params, q, 0)
+
+    # evaluation count of one step (deterministic)
+    rd.evals.zero_()
+    step(count=True)
+    torch.cuda.synchronize()
+    E = int(rd.evals.item())
+    P, _ = ctx.query()
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = E / (ms * 1e-3)
+
+    kernels = {}
+    for g, (tot, cnt) in prof.items():
+        if cnt:
+            kernels[g] = round(tot / cnt, 4)
+    dom = max(kernels, key=kernels.get)
+    bound, amount, unit = group_work(dom, sc.n, sc.views, P, E, sc.width, sc.height)
+    dur = kernels[dom] * 1e-3
+    if unit == "B":
+        achieved, peak, ru = amount / dur / 1e9, HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved, peak, ru = amount / dur / 1e12, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
+    roof = {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
+            "unit": ru, "frac": round(achieved / peak, 5), "traffic": None}
+    line = {
+        "metric": "RD-step ms/iter & Gaussian-pixel evals/s (fwd+bwd), learned vs plain rate",
+        "value": round(value, 1), "unit": "Gaussian-pixel evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: plain RD step, {sc.n} Gaussians (clustered), "
+                               f"{sc.views} view {sc.width}x{sc.height}, 20% pruned, "
+                               f"lambda 2.5e-5, tile 16x16",
+                   "gaussians": sc.n, "views": sc.views, "width": sc.width,
+                   "height": sc.height, "pairs": P, "evals_per_step": E},
+        "roofline": roof,
+        "kernel_ms": kernels,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(sc, lam, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

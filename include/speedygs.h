@@ -171,6 +171,32 @@ sgs_status sgs_copy_structure(sgs_ctx *ctx, uint32_t *tile_ids, uint32_t *vals,
  * float [V][n][12] (px, py, A, B, C, opacity, r, g, b, mask, 0, 0). */
 sgs_status sgs_copy_splat_grads(sgs_ctx *ctx, float *out);
 
+/* Kernel-group timing with HIP events recorded on the context's stream around
+ * each group's launches (no extra synchronization inside a step).  Groups: */
+enum {
+  SGS_PROF_FAKEQUANT = 0,  /* a1-a3 quantize, mask, channel statistics */
+  SGS_PROF_RATE = 1,       /* a3 rate proxy */
+  SGS_PROF_PREPROCESS = 2, /* a4 projection */
+  SGS_PROF_DEPTH_SORT = 3, /* a6 depth radix sort of the splats */
+  SGS_PROF_SCAN = 4,       /* a5 pair offsets */
+  SGS_PROF_DUPLICATE = 5,  /* a5 pair emission */
+  SGS_PROF_TILE_SORT = 6,  /* a6 stable tile radix sort of the pairs */
+  SGS_PROF_RANGES = 7,     /* a7 tile ranges */
+  SGS_PROF_BLEND_FWD = 8,  /* a8 */
+  SGS_PROF_L1 = 9,         /* a9 */
+  SGS_PROF_GRAD_CLEAR = 10,/* a10 clearing of the splat-gradient accumulators */
+  SGS_PROF_BLEND_BWD = 11, /* a10 */
+  SGS_PROF_PREPROCESS_BWD = 12, /* a11 */
+  SGS_PROF_FAKEQUANT_BWD = 13,  /* a12 */
+  SGS_PROF_GROUPS = 14
+};
+/* enable != 0 starts recording (and clears earlier records); 0 stops. */
+sgs_status sgs_profile_enable(sgs_ctx *ctx, int32_t enable);
+/* Synchronizes the stream, then returns per group the summed duration in ms
+ * and the number of timed launches (host arrays of SGS_PROF_GROUPS entries)
+ * and clears the records. */
+sgs_status sgs_profile_read(sgs_ctx *ctx, double *ms_total, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

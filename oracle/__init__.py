@@ -322,14 +322,9 @@ def fixed_length_roundtrip(k: np.ndarray, mhat: np.ndarray, n: int):
 # One whole RD step (plain rate proxy): loss = L1(render) + lam * R_proxy
 # --------------------------------------------------------------------------
 
-def rd_step(params, qstep, score, given_mask, cams, W, H, target, n, n_hat, lam,
-            mask_mode=0, seed=0, step=0, tau=1.0, TW=TW_DEFAULT, TH=TH_DEFAULT,
-            dimage=None):
-    """Forward and backward of D_render + lam * R_proxy [Sec. 3.3.2 total loss].
-
-    ``dimage`` overrides dL/dimage (to feed both sides the same upstream
-    gradient when L1's sign decision sits at a rounding margin).
-    """
+def rd_forward(params, qstep, score, given_mask, cams, W, H, target, n, n_hat, lam,
+               mask_mode=0, seed=0, step=0, tau=1.0, TW=TW_DEFAULT, TH=TH_DEFAULT):
+    """Forward of D_render + lam * R_proxy [Sec. 3.3.2 total loss]."""
     yhat, k = fakequant(params, qstep, n)
     mh, ms = mask(n, mask_mode, given_mask, score, seed, step, tau)
     rp = rate_proxy(params, qstep, mh, n, n_hat, lam)
@@ -338,13 +333,31 @@ def rd_step(params, qstep, score, given_mask, cams, W, H, target, n, n_hat, lam,
     m64 = mh.astype(np.float64)
     fw = forward(p64, m64, n, cams, W, H, st)
     D, d_img = l1(fw["image"], target)
-    if dimage is not None:
-        d_img = np.asarray(dimage, np.float64)
-    gyhat, gmh, _ = backward(p64, m64, n, cams, W, H, st, d_img)
+    return dict(params=params, qstep=qstep, cams=cams, W=W, H=H, n=n, lam=lam,
+                mask_mode=mask_mode, tau=tau, yhat=yhat, k=k, mhat=mh, msoft=ms, rate=rp,
+                st=st, p64=p64, m64=m64, fw=fw, D=D, loss=D + lam * rp["R"], dimage=d_img)
+
+
+def rd_backward(s, dimage=None):
+    """Backward of rd_forward's loss; ``dimage`` overrides dL/dimage (to feed
+    both sides the same upstream gradient)."""
+    d_img = s["dimage"] if dimage is None else np.asarray(dimage, np.float64)
+    n = s["n"]
+    gyhat, gmh, _ = backward(s["p64"], s["m64"], n, s["cams"], s["W"], s["H"], s["st"], d_img)
+    rp = s["rate"]
     gmh_total = gmh + rp["gm"]
-    gy, gq, gs = fakequant_bwd(params, qstep, gyhat, mask_mode, ms, tau, gmh_total, n)
-    gy = gy + rp["gy"]
-    gq = gq + rp["gq"]
-    return dict(yhat=yhat, k=k, mhat=mh, msoft=ms, rate=rp, st=st, fw=fw, D=D,
-                loss=D + lam * rp["R"], dimage=d_img, gyhat=gyhat, gmhat=gmh,
-                gmhat_total=gmh_total, gy=gy, gq=gq, gs=gs)
+    gy, gq, gs = fakequant_bwd(s["params"], s["qstep"], gyhat, s["mask_mode"], s["msoft"],
+                               s["tau"], gmh_total, n)
+    out = dict(s)
+    out.update(dimage=d_img, gyhat=gyhat, gmhat=gmh, gmhat_total=gmh_total,
+               gy=gy + rp["gy"], gq=gq + rp["gq"], gs=gs)
+    return out
+
+
+def rd_step(params, qstep, score, given_mask, cams, W, H, target, n, n_hat, lam,
+            mask_mode=0, seed=0, step=0, tau=1.0, TW=TW_DEFAULT, TH=TH_DEFAULT,
+            dimage=None):
+    """Forward and backward of D_render + lam * R_proxy [Sec. 3.3.2 total loss]."""
+    s = rd_forward(params, qstep, score, given_mask, cams, W, H, target, n, n_hat, lam,
+                   mask_mode, seed, step, tau, TW, TH)
+    return rd_backward(s, dimage)

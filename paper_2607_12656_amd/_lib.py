@@ -62,7 +62,12 @@ _SIGS = {
     "sgs_query": [P, P, C.POINTER(I64), C.POINTER(U64)],
     "sgs_copy_structure": [P, P, P, I64, P, P, P, P],
     "sgs_copy_splat_grads": [P, P],
+    "sgs_profile_enable": [P, I32],
+    "sgs_profile_read": [P, P, P],
 }
+PROF_GROUPS = ("fakequant", "rate", "preprocess", "depth_sort", "scan", "duplicate",
+               "tile_sort", "ranges", "blend_fwd", "l1", "grad_clear", "blend_bwd",
+               "preprocess_bwd", "fakequant_bwd")
 EXPORTS = tuple(_SIGS)
 
 _lib = None
@@ -190,3 +195,12 @@ class Context:
 
     def copy_splat_grads(self, out):
         self._check(self.L.sgs_copy_splat_grads(self.h, _ptr(out)), self.h)
+
+    def profile_enable(self, on: bool = True):
+        self._check(self.L.sgs_profile_enable(self.h, 1 if on else 0), self.h)
+
+    def profile_read(self) -> dict:
+        ms = (C.c_double * len(PROF_GROUPS))()
+        cnt = (C.c_int64 * len(PROF_GROUPS))()
+        self._check(self.L.sgs_profile_read(self.h, ms, cnt), self.h)
+        return {g: (float(ms[k]), int(cnt[k])) for k, g in enumerate(PROF_GROUPS)}

@@ -121,6 +121,11 @@ void sgs_destroy(sgs_ctx *c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
   free_scene(c);
+  for (auto &r : c->prof_recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : c->ev_free) (void)hipEventDestroy(e);
   if (c->h_pairs_total) (void)hipHostFree(c->h_pairs_total);
   delete c;
 }
@@ -192,7 +197,9 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   SGS_ALLOC(c->splat_grad, vn * SGS_SGRAD);
   SGS_ALLOC(c->ranges, c->total_tiles);
   SGS_ALLOC(c->d_pairs_total, 1);
-  const int64_t red = ((n + 2047) / 2048) * SGS_NCH + (int64_t)views * 3 * width * height / 2048 + 64;
+  const int64_t red_q = quant_partial_words(n);
+  const int64_t red_l1 = (int64_t)views * 3 * width * height / 2048 + 64;
+  const int64_t red = (red_q > red_l1 ? red_q : red_l1) + 64;
   SGS_ALLOC(c->red_tmp, red);
   c->red_tmp_words = red;
 #undef SGS_ALLOC
@@ -318,6 +325,37 @@ sgs_status sgs_query(sgs_ctx *c, const uint64_t *stats, int64_t *pairs_last, uin
   return SGS_OK;
 }
 
+sgs_status sgs_profile_enable(sgs_ctx *c, int32_t enable) {
+  if (!c) return SGS_EINVAL;
+  SGS_HIP(hipStreamSynchronize(c->stream), "profile sync");
+  for (auto &r : c->prof_recs) {
+    c->ev_free.push_back(r.a);
+    c->ev_free.push_back(r.b);
+  }
+  c->prof_recs.clear();
+  c->prof = enable != 0;
+  return SGS_OK;
+}
+
+sgs_status sgs_profile_read(sgs_ctx *c, double *ms_total, int64_t *launches) {
+  if (!c || !ms_total || !launches) return SGS_EINVAL;
+  SGS_HIP(hipStreamSynchronize(c->stream), "profile sync");
+  for (int g = 0; g < SGS_PROF_GROUPS; ++g) {
+    ms_total[g] = 0.0;
+    launches[g] = 0;
+  }
+  for (auto &r : c->prof_recs) {
+    float ms = 0.0f;
+    SGS_HIP(hipEventElapsedTime(&ms, r.a, r.b), "profile elapsed");
+    ms_total[r.group] += ms;
+    launches[r.group] += 1;
+    c->ev_free.push_back(r.a);
+    c->ev_free.push_back(r.b);
+  }
+  c->prof_recs.clear();
+  return SGS_OK;
+}
+
 sgs_status sgs_copy_structure(sgs_ctx *c, uint32_t *tile_ids, uint32_t *vals, int64_t cap,
                               uint32_t *ranges, int32_t *spans, float *depth, float *splats);
 sgs_status sgs_copy_splat_grads(sgs_ctx *c, float *out);
@@ -333,7 +371,7 @@ __global__ void k_export(int64_t vn, const float4 *__restrict__ rec,
                          const uint32_t *__restrict__ dkey_unsorted) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= vn) return;
-  const float4 a = rec[s], b = rec[vn + s], cc = rec[2 * vn + s];
+  const float4 a = rec[3 * s], b = rec[3 * s + 1], cc = rec[3 * s + 2];
   const bool valid = touched[s] != 0;
   if (spans) {
     const uint32_t sx = __float_as_uint(b.z), sy = __float_as_uint(b.w);

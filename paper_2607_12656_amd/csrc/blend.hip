@@ -1,26 +1,37 @@
 // Front-to-back alpha compositing over the per-tile depth-ordered lists
 // (paper Sec. 3.1, compositing equation) and its reverse-order backward.
 //
-// One workgroup per tile, one thread per pixel.  A workgroup stages a batch
-// of splat records in LDS (one gather per thread), then every pixel walks the
-// batch.  All lanes read the same LDS entry at the same time (broadcast, no
-// bank conflicts).  A pixel stops when T (1 - alpha~) would fall below 1e-4;
-// the workgroup stops when all its pixels have stopped (barrier count).
+// One workgroup per tile.  Each wave64 owns an 8x8 pixel sub-tile (a
+// 16x16 tile is four of them), one pixel per lane.  The workgroup stages a
+// batch of 48-byte splat records in LDS (one gather per thread, one cache
+// line per record); a wave skips every staged splat whose pixel span misses
+// its sub-tile (a wave-uniform branch) and stops walking once all its pixels
+// have terminated.  All lanes read the same LDS record at the same time
+// (broadcast, no bank conflicts).  A pixel stops when T (1 - alpha~) would
+// fall below 1e-4; the workgroup stops when every pixel has stopped.
+//
 // The backward walks the same list from each pixel's stop position towards
 // the front, recovers T by division with the same (1 - alpha~) the forward
-// multiplied by, reduces the ten splat gradients over the wave with
-// shuffles and issues one set of atomics per (splat, wave).
+// multiplied by, and reduces the ten per-splat gradients of a wave with a
+// transposing butterfly (17 shuffles for all ten values); ten lanes then
+// issue one atomic each.
 #include "sgs_internal.h"
 
 namespace {
 
 struct SplatLds {
   float4 a;  // px, py, A, B
-  float4 b;  // C, opacity, spanx, spany
+  float4 b;  // C, opacity, spanx (x0 | x1 << 16), spany
   float4 c;  // r, g, b, mask
 };
 
-// alpha of splat `s` at pixel (fx, fy); the forward and the backward call the
+__device__ __forceinline__ bool span_meets(const SplatLds &s, int sx0, int sy0) {
+  const uint32_t sx = __float_as_uint(s.b.z), sy = __float_as_uint(s.b.w);
+  return (int)(sx & 0xFFFF) <= sx0 + 7 && (int)(sx >> 16) >= sx0 &&
+         (int)(sy & 0xFFFF) <= sy0 + 7 && (int)(sy >> 16) >= sy0;
+}
+
+// alpha of splat `s` at pixel (px, py); the forward and the backward call the
 // same code so both see bit-identical values.  Returns false when the pixel is
 // outside the splat's pixel span, the exponent is positive or alpha < 1/255.
 __device__ __forceinline__ bool splat_alpha(const SplatLds &s, int px, int py, float fx,
@@ -48,18 +59,22 @@ template <int TW, int TH>
 __global__ void __launch_bounds__(TW * TH)
 k_blend_fwd(int64_t n, int W, int H, int GW, int64_t tiles_per_view,
             const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
-            const float4 *__restrict__ rec, int64_t vn, float *__restrict__ image,
+            const float4 *__restrict__ rec, float *__restrict__ image,
             float *__restrict__ final_T, uint32_t *__restrict__ last,
             unsigned long long *__restrict__ eval_count) {
   constexpr int BS = TW * TH;
+  constexpr int SUBW = TW / 8;
   __shared__ SplatLds sh[BS];
   __shared__ unsigned long long s_ev[BS / 64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t tile = blockIdx.x;
   const int v = (int)(tile / tiles_per_view);
   const int t = (int)(tile - (int64_t)v * tiles_per_view);
   const int tx = t % GW, ty = t / GW;
-  const int px = tx * TW + (int)(threadIdx.x % TW);
-  const int py = ty * TH + (int)(threadIdx.x / TW);
+  const int sx0 = tx * TW + (wave % SUBW) * 8;
+  const int sy0 = ty * TH + (wave / SUBW) * 8;
+  const int px = sx0 + (lane & 7);
+  const int py = sy0 + (lane >> 3);
   const bool inside = px < W && py < H;
   const float fx = (float)px, fy = (float)py;
   const uint2 rg = ranges[tile];
@@ -72,34 +87,38 @@ k_blend_fwd(int64_t n, int W, int H, int GW, int64_t tiles_per_view,
     if (__syncthreads_count(done ? 1 : 0) == BS) break;
     const uint32_t e = b + threadIdx.x;
     if (e < rg.y) {
-      const int64_t s = base + vals[e];
-      sh[threadIdx.x].a = rec[s];
-      sh[threadIdx.x].b = rec[vn + s];
-      sh[threadIdx.x].c = rec[2 * vn + s];
+      const float4 *r = rec + 3 * (base + vals[e]);
+      sh[threadIdx.x].a = r[0];
+      sh[threadIdx.x].b = r[1];
+      sh[threadIdx.x].c = r[2];
     }
     __syncthreads();
+    if (__ballot(!done) == 0ull) continue;
     const int cnt = (int)min((uint32_t)BS, rg.y - b);
-    if (!done) {
-      for (int k = 0; k < cnt; ++k) {
-        const SplatLds &s = sh[k];
+    for (int k = 0; k < cnt; ++k) {
+      const SplatLds &s = sh[k];
+      if (!span_meets(s, sx0, sy0)) continue;
+      if (!done) {
         bool in_span, clamped;
         float alpha, G, dx, dy;
         const bool ok = splat_alpha(s, px, py, fx, fy, in_span, alpha, G, clamped, dx, dy);
         evals += in_span ? 1u : 0u;
-        if (!ok) continue;
-        const float at = s.c.w * alpha;
-        const float Tn = T * (1.0f - at);
-        if (Tn < SGS_T_MIN) {
-          done = true;
-          stop = b - rg.x + (uint32_t)k;
-          break;
+        if (ok) {
+          const float at = s.c.w * alpha;
+          const float Tn = T * (1.0f - at);
+          if (Tn < SGS_T_MIN) {
+            done = true;
+            stop = b - rg.x + (uint32_t)k;
+          } else {
+            const float w = at * T;
+            C0 = fmaf(s.c.x, w, C0);
+            C1 = fmaf(s.c.y, w, C1);
+            C2 = fmaf(s.c.z, w, C2);
+            T = Tn;
+          }
         }
-        const float w = at * T;
-        C0 = fmaf(s.c.x, w, C0);
-        C1 = fmaf(s.c.y, w, C1);
-        C2 = fmaf(s.c.z, w, C2);
-        T = Tn;
       }
+      if (__ballot(!done) == 0ull) break;
     }
   }
   if (inside) {
@@ -115,7 +134,7 @@ k_blend_fwd(int64_t n, int W, int H, int GW, int64_t tiles_per_view,
     unsigned long long ev = evals;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) ev += __shfl_xor(ev, o, 64);
-    if ((threadIdx.x & 63) == 0) s_ev[threadIdx.x >> 6] = ev;
+    if (lane == 0) s_ev[wave] = ev;
     __syncthreads();
     if (threadIdx.x == 0) {
       unsigned long long tot = 0;
@@ -125,24 +144,71 @@ k_blend_fwd(int64_t n, int W, int H, int GW, int64_t tiles_per_view,
   }
 }
 
+// Sum each of v[0..15] over the 64 lanes of the wave.  After the call lane L
+// holds the total of value ((L>>5)&1)*8 + ((L>>4)&1)*4 + ((L>>3)&1)*2 +
+// ((L>>2)&1) (lanes sharing L>>2 hold the same total).
+__device__ __forceinline__ float wave_transpose_sum16(float v[16], int lane) {
+  float r8[8], r4[4], r2[2];
+  {
+    const bool hi = lane & 32;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const float mine = hi ? v[8 + i] : v[i];
+      const float send = hi ? v[i] : v[8 + i];
+      r8[i] = mine + __shfl_xor(send, 32, 64);
+    }
+  }
+  {
+    const bool hi = lane & 16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float mine = hi ? r8[4 + i] : r8[i];
+      const float send = hi ? r8[i] : r8[4 + i];
+      r4[i] = mine + __shfl_xor(send, 16, 64);
+    }
+  }
+  {
+    const bool hi = lane & 8;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const float mine = hi ? r4[2 + i] : r4[i];
+      const float send = hi ? r4[i] : r4[2 + i];
+      r2[i] = mine + __shfl_xor(send, 8, 64);
+    }
+  }
+  float x;
+  {
+    const bool hi = lane & 4;
+    const float mine = hi ? r2[1] : r2[0];
+    const float send = hi ? r2[0] : r2[1];
+    x = mine + __shfl_xor(send, 4, 64);
+  }
+  x += __shfl_xor(x, 2, 64);
+  x += __shfl_xor(x, 1, 64);
+  return x;
+}
+
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW * TH)
 k_blend_bwd(int64_t n, int W, int H, int GW, int64_t tiles_per_view,
             const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
-            const float4 *__restrict__ rec, int64_t vn, const float *__restrict__ final_T,
+            const float4 *__restrict__ rec, const float *__restrict__ final_T,
             const uint32_t *__restrict__ last, const float *__restrict__ dimg,
             float *__restrict__ sgrad) {
   constexpr int BS = TW * TH;
+  constexpr int SUBW = TW / 8;
   __shared__ SplatLds sh[BS];
   __shared__ uint32_t s_gid[BS];
   __shared__ uint32_t s_max[BS / 64];
-  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t tile = blockIdx.x;
   const int v = (int)(tile / tiles_per_view);
   const int t = (int)(tile - (int64_t)v * tiles_per_view);
   const int tx = t % GW, ty = t / GW;
-  const int px = tx * TW + (int)(threadIdx.x % TW);
-  const int py = ty * TH + (int)(threadIdx.x / TW);
+  const int sx0 = tx * TW + (wave % SUBW) * 8;
+  const int sy0 = ty * TH + (wave / SUBW) * 8;
+  const int px = sx0 + (lane & 7);
+  const int py = sy0 + (lane >> 3);
   const bool inside = px < W && py < H;
   const float fx = (float)px, fy = (float)py;
   const uint2 rg = ranges[tile];
@@ -158,41 +224,46 @@ k_blend_bwd(int64_t n, int W, int H, int GW, int64_t tiles_per_view,
     g1 = dimg[((int64_t)v * 3 + 1) * plane + pix];
     g2 = dimg[((int64_t)v * 3 + 2) * plane + pix];
   }
-  // furthest list position any pixel of the tile reached
-  uint32_t mx = my_last;
+  // furthest list position reached by any pixel of the wave / workgroup
+  uint32_t wave_reach = my_last;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
-  if (lane == 0) s_max[threadIdx.x >> 6] = mx;
+  for (int o = 32; o > 0; o >>= 1) wave_reach = max(wave_reach, (uint32_t)__shfl_xor(wave_reach, o, 64));
+  if (lane == 0) s_max[wave] = wave_reach;
   __syncthreads();
   uint32_t reach = 0;
   for (int w = 0; w < BS / 64; ++w) reach = max(reach, s_max[w]);
-  float B0 = 0.f, B1 = 0.f, B2 = 0.f;  // colour seen behind the current splat
   if (reach == 0) return;
+  float B0 = 0.f, B1 = 0.f, B2 = 0.f;  // colour seen behind the current splat
   const uint32_t nbatch = (reach + BS - 1) / BS;
+  const int vidx = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 +
+                   ((lane >> 2) & 1);
   for (int bi = (int)nbatch - 1; bi >= 0; --bi) {
-    const uint32_t b0 = rg.x + (uint32_t)bi * BS;
-    const int cnt = (int)min((uint32_t)BS, rg.y - b0);
+    const uint32_t p0 = (uint32_t)bi * BS;
+    const int cnt = (int)min((uint32_t)BS, rg.y - rg.x - p0);
     __syncthreads();
     if ((int)threadIdx.x < cnt) {
-      const uint32_t gi = vals[b0 + threadIdx.x];
-      const int64_t s = base + gi;
+      const uint32_t gi = vals[rg.x + p0 + threadIdx.x];
+      const float4 *r = rec + 3 * (base + gi);
       s_gid[threadIdx.x] = gi;
-      sh[threadIdx.x].a = rec[s];
-      sh[threadIdx.x].b = rec[vn + s];
-      sh[threadIdx.x].c = rec[2 * vn + s];
+      sh[threadIdx.x].a = r[0];
+      sh[threadIdx.x].b = r[1];
+      sh[threadIdx.x].c = r[2];
     }
     __syncthreads();
-    for (int k = cnt - 1; k >= 0; --k) {
-      const uint32_t pos = (uint32_t)bi * BS + (uint32_t)k;
+    if (p0 >= wave_reach) continue;
+    const int kstart = (int)min((uint32_t)cnt, wave_reach - p0) - 1;
+    for (int k = kstart; k >= 0; --k) {
       const SplatLds &s = sh[k];
+      if (!span_meets(s, sx0, sy0)) continue;
+      const uint32_t pos = p0 + (uint32_t)k;
       bool in_span = false, clamped = false, ok = false;
       float alpha = 0.f, G = 0.f, dx = 0.f, dy = 0.f;
       if (inside && pos < my_last)
         ok = splat_alpha(s, px, py, fx, fy, in_span, alpha, G, clamped, dx, dy);
       if (__ballot(ok) == 0ull) continue;
-      float d[10];
+      float d[16];
 #pragma unroll
-      for (int q = 0; q < 10; ++q) d[q] = 0.0f;
+      for (int q = 0; q < 16; ++q) d[q] = 0.0f;
       if (ok) {
         const float m = s.c.w;
         const float at = m * alpha;
@@ -218,33 +289,30 @@ k_blend_bwd(int64_t n, int W, int H, int GW, int64_t tiles_per_view,
         B2 = s.c.z * at + (1.0f - at) * B2;
         T = Tb;
       }
-#pragma unroll
-      for (int q = 0; q < 10; ++q) d[q] = sgs_wave_sum(d[q]);
-      if (lane == 0) {
-        float *dst = sgrad + (base + s_gid[k]) * SGS_SGRAD;
-#pragma unroll
-        for (int q = 0; q < 10; ++q)
-          if (d[q] != 0.0f) unsafeAtomicAdd(dst + q, d[q]);
-      }
+      const float tot = wave_transpose_sum16(d, lane);
+      if ((lane & 3) == 0 && vidx < 10 && tot != 0.0f)
+        unsafeAtomicAdd(sgrad + (base + s_gid[k]) * SGS_SGRAD + vidx, tot);
     }
   }
 }
 
 template <int TW, int TH>
 hipError_t fwd_t(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint64_t *ec) {
+  SgsProfScope ps(c, SGS_PROF_BLEND_FWD);
   const uint32_t *vals = c->pair_val[c->pair_sorted_buf];
   k_blend_fwd<TW, TH><<<(unsigned)c->total_tiles, TW * TH, 0, c->stream>>>(
-      c->n, c->W, c->H, c->GW, c->tiles_per_view, c->ranges, vals, c->rec, c->vn, image,
-      final_T, last, (unsigned long long *)ec);
+      c->n, c->W, c->H, c->GW, c->tiles_per_view, c->ranges, vals, c->rec, image, final_T, last,
+      (unsigned long long *)ec);
   return hipGetLastError();
 }
 
 template <int TW, int TH>
 hipError_t bwd_t(sgs_ctx *c, const float *final_T, const uint32_t *last, const float *dimg) {
+  SgsProfScope ps(c, SGS_PROF_BLEND_BWD);
   const uint32_t *vals = c->pair_val[c->pair_sorted_buf];
   k_blend_bwd<TW, TH><<<(unsigned)c->total_tiles, TW * TH, 0, c->stream>>>(
-      c->n, c->W, c->H, c->GW, c->tiles_per_view, c->ranges, vals, c->rec, c->vn, final_T, last,
-      dimg, c->splat_grad);
+      c->n, c->W, c->H, c->GW, c->tiles_per_view, c->ranges, vals, c->rec, final_T, last, dimg,
+      c->splat_grad);
   return hipGetLastError();
 }
 
@@ -266,7 +334,10 @@ hipError_t launch_blend_fwd(sgs_ctx *c, float *image, float *final_T, uint32_t *
 hipError_t launch_blend_bwd(sgs_ctx *c, const float *final_T, const uint32_t *last,
                             const float *dimg) {
   const int64_t words = c->vn * SGS_SGRAD;
-  k_zero_f32<<<sgs_blocks(words, 256), 256, 0, c->stream>>>(c->splat_grad, words);
+  {
+    SgsProfScope ps(c, SGS_PROF_GRAD_CLEAR);
+    k_zero_f32<<<sgs_blocks(words, 256), 256, 0, c->stream>>>(c->splat_grad, words);
+  }
   if (c->TW == 16 && c->TH == 16) return bwd_t<16, 16>(c, final_T, last, dimg);
   if (c->TW == 8 && c->TH == 8) return bwd_t<8, 8>(c, final_T, last, dimg);
   if (c->TW == 32 && c->TH == 8) return bwd_t<32, 8>(c, final_T, last, dimg);

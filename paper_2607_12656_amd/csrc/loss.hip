@@ -56,6 +56,7 @@ hipError_t launch_l1(sgs_ctx *c, const float *image, const float *target, float 
   const int64_t per = (int64_t)kThreads * kItems;
   const int nb = (int)((count + per - 1) / per);
   if (nb > c->red_tmp_words) return hipErrorInvalidValue;
+  SgsProfScope ps(c, SGS_PROF_L1);
   k_l1<<<nb, kThreads, 0, c->stream>>>(image, target, count, (float)((double)scale / (double)count), dimg,
                                        c->red_tmp);
   k_l1_finish<<<1, kThreads, 0, c->stream>>>(c->red_tmp, nb, count, loss);

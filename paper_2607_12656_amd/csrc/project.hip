@@ -53,7 +53,6 @@ k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
   for (int j = 0; j < SGS_NCH; ++j) y[j] = qp[j * npad + i];
   const float m = hard[i] ? 1.0f : 0.0f;
   const float opa = 1.0f / (1.0f + __expf(-y[SGS_CH_OPA]));
-  const int64_t vn = (int64_t)V * n;
   for (int v = 0; v < V; ++v) {
     SgsCam cam;
     load_cam(cams, v, cam);
@@ -64,9 +63,9 @@ k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
     if (!p.valid) {
       depth_key[s] = 0xFFFFFFFFu;
       touched[s] = 0;
-      rec[s] = make_float4(0.f, 0.f, 0.f, 0.f);
-      rec[vn + s] = make_float4(0.f, 0.f, __int_as_float(-1), __int_as_float(-1));
-      rec[2 * vn + s] = make_float4(0.f, 0.f, 0.f, 0.f);
+      rec[3 * s] = make_float4(0.f, 0.f, 0.f, 0.f);
+      rec[3 * s + 1] = make_float4(0.f, 0.f, __int_as_float(-1), __int_as_float(-1));
+      rec[3 * s + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
       continue;
     }
     depth_key[s] = __float_as_uint(p.tz);
@@ -77,9 +76,9 @@ k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
     colour(y, cam, col, cl);
     const uint32_t sx = (uint32_t)p.x0 | ((uint32_t)p.x1 << 16);
     const uint32_t sy = (uint32_t)p.y0 | ((uint32_t)p.y1 << 16);
-    rec[s] = make_float4(p.px, p.py, A, B);
-    rec[vn + s] = make_float4(C, opa, __uint_as_float(sx), __uint_as_float(sy));
-    rec[2 * vn + s] = make_float4(col[0], col[1], col[2], m);
+    rec[3 * s] = make_float4(p.px, p.py, A, B);
+    rec[3 * s + 1] = make_float4(C, opa, __uint_as_float(sx), __uint_as_float(sy));
+    rec[3 * s + 2] = make_float4(col[0], col[1], col[2], m);
   }
 }
 
@@ -252,6 +251,7 @@ k_preprocess_bwd(int64_t n, int64_t npad, int V, int W, int H,
 }  // namespace
 
 hipError_t launch_preprocess(sgs_ctx *c, const float *qparams, const uint8_t *hard) {
+  SgsProfScope ps(c, SGS_PROF_PREPROCESS);
   k_preprocess<<<sgs_blocks(c->n, kPThreads), kPThreads, 0, c->stream>>>(
       c->n, c->npad, c->V, c->W, c->H, c->TW, c->TH, c->d_cams, qparams, hard, c->rec,
       c->depth_key[0], c->depth_val[0], c->touched);
@@ -260,6 +260,7 @@ hipError_t launch_preprocess(sgs_ctx *c, const float *qparams, const uint8_t *ha
 
 hipError_t launch_preprocess_bwd(sgs_ctx *c, const float *qparams, float *grad_qparams,
                                  float *grad_mask) {
+  SgsProfScope ps(c, SGS_PROF_PREPROCESS_BWD);
   k_preprocess_bwd<<<sgs_blocks(c->n, kPThreads), kPThreads, 0, c->stream>>>(
       c->n, c->npad, c->V, c->W, c->H, c->d_cams, qparams, c->touched, c->splat_grad,
       grad_qparams, grad_mask);

@@ -1,118 +1,167 @@
 // Fake quantization, retention mask, channel statistics, rate proxy and the
-// quantizer/mask backward (paper Sec. 3.3.1).  All three kernels stream the
-// SoA parameters once: HBM-bound, so each thread owns whole Gaussians and
-// walks the 59 channel rows (coalesced across the wave).
+// quantizer/mask backward (paper Sec. 3.3.1).
+//
+// The parameter passes are HBM-bound streams over the SoA rows.  A block owns
+// kQItems * 256 consecutive Gaussians and walks the 59 channel rows one after
+// the other (loads coalesced across the wave); per-channel reductions (range
+// keys, step-size gradient) are done once per block and channel, written as
+// per-block partials, and finished by one block per channel.  No contended
+// atomics.
 #include "sgs_internal.h"
 
 namespace {
 
 constexpr int kQThreads = 256;
 constexpr int kQWaves = kQThreads / 64;
+constexpr int kQItems = 4;
+constexpr int kQPer = kQThreads * kQItems;  // Gaussians per block
+// partial record per block: [0,59) min keys, [59,118) max keys, [118] kept
+constexpr int kPartWords = 120;
 
-__global__ void k_stats_init(uint64_t *stats) {
-  const int t = threadIdx.x;
-  if (t < SGS_NCH) {
-    stats[t] = ~0ull;      // min keys
-    stats[SGS_NCH + t] = 0; // max keys
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(v, off, 64);
+    v = o < v ? o : v;
   }
-  if (t >= 2 * SGS_NCH && t < SGS_STATS_WORDS) stats[t] = 0;
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
 }
 
-// One pass over params: qparams, hard/soft mask, per-channel min/max keys,
-// kept count.  Grid-stride over Gaussians so the number of atomics per
-// channel is the number of blocks, not the number of Gaussians.
+// Pass 1: qparams, hard/soft mask; per-block range keys and kept count.
 __global__ void __launch_bounds__(kQThreads)
 k_fakequant_prune(int64_t n, int64_t npad, const float *__restrict__ params,
                   const float *__restrict__ q, const float *__restrict__ score, int mode,
                   const uint8_t *__restrict__ given, uint64_t seed, uint64_t step, float tau,
                   float *__restrict__ qparams, uint8_t *__restrict__ hard,
-                  float *__restrict__ soft, uint64_t *__restrict__ stats) {
+                  float *__restrict__ soft, uint64_t *__restrict__ part) {
   __shared__ uint64_t s_min[kQWaves][SGS_NCH];
   __shared__ uint64_t s_max[kQWaves][SGS_NCH];
   __shared__ uint32_t s_kept[kQWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t kept = 0;
-  // per-thread running extremes would need 2*59 registers; instead each
-  // channel is reduced per wave on the fly and merged in LDS.
-  for (int j = threadIdx.x; j < kQWaves * SGS_NCH; j += kQThreads) {
-    (&s_min[0][0])[j] = ~0ull;
-    (&s_max[0][0])[j] = 0ull;
-  }
-  __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x < SGS_NCH) {
-    const float qj = q[threadIdx.x];
-    if (!(qj > 0.0f) || !(qj < INFINITY)) atomicOr((unsigned long long *)&stats[119], 1ull);
-  }
-  const int64_t stride = (int64_t)gridDim.x * kQThreads;
-  for (int64_t base = (int64_t)blockIdx.x * kQThreads; base < n; base += stride) {
-    const int64_t i = base + threadIdx.x;
-    const bool act = i < n;
-    for (int j = 0; j < SGS_NCH; ++j) {
-      const float qj = q[j];
-      float yv = 0.0f;
-      uint64_t kmin = ~0ull, kmax = 0ull;
-      if (act) {
-        yv = params[j * npad + i];
-        const float k = rintf(__fdiv_rn(yv, qj));
-        qparams[j * npad + i] = k * qj;
-        const uint64_t o = (uint64_t)sgs_ord(yv) << 32;
-        kmin = o | (uint64_t)(uint32_t)i;
-        kmax = o | (uint64_t)(0xFFFFFFFFu - (uint32_t)i);
-      }
+  const int64_t base = (int64_t)blockIdx.x * kQPer + threadIdx.x;
+  for (int j = 0; j < SGS_NCH; ++j) {
+    const float qj = q[j];
+    uint64_t kmin = ~0ull, kmax = 0ull;
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t a = __shfl_xor(kmin, off, 64);
-        const uint64_t b = __shfl_xor(kmax, off, 64);
+    for (int it = 0; it < kQItems; ++it) {
+      const int64_t i = base + (int64_t)it * kQThreads;
+      if (i < n) {
+        const float yv = params[j * npad + i];
+        qparams[j * npad + i] = rintf(__fdiv_rn(yv, qj)) * qj;
+        const uint64_t o = (uint64_t)sgs_ord(yv) << 32;
+        const uint64_t a = o | (uint64_t)(uint32_t)i;
+        const uint64_t b = o | (uint64_t)(0xFFFFFFFFu - (uint32_t)i);
         kmin = a < kmin ? a : kmin;
         kmax = b > kmax ? b : kmax;
       }
-      if (lane == 0) {
-        if (kmin < s_min[wave][j]) s_min[wave][j] = kmin;
-        if (kmax > s_max[wave][j]) s_max[wave][j] = kmax;
-      }
     }
-    if (act) {
-      uint8_t m;
-      float sm;
-      if (mode == 0) {
-        m = given[i] ? 1 : 0;
-        sm = (float)m;
-      } else if (mode == 2) {
-        m = 1;
-        sm = 1.0f;
-      } else {
-        const float u = sgs_uniform(seed, step, (uint64_t)i);
-        const float s = score[i];
-        const float e = sgs_exp_repro(s);
-        m = (u * (1.0f + e)) > 1.0f ? 1 : 0;
-        const float l = logf(u) - logf(1.0f - u);
-        sm = 1.0f / (1.0f + __expf(-(s + l) / tau));
-      }
-      hard[i] = m;
-      if (soft) soft[i] = sm;
-      kept += m;
+    kmin = wave_min_u64(kmin);
+    kmax = wave_max_u64(kmax);
+    if (lane == 0) {
+      s_min[wave][j] = kmin;
+      s_max[wave][j] = kmax;
     }
   }
-  // kept count
-  uint32_t kw = kept;
+  uint32_t kept = 0;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) kw += __shfl_xor(kw, off, 64);
-  if (lane == 0) s_kept[wave] = kw;
+  for (int it = 0; it < kQItems; ++it) {
+    const int64_t i = base + (int64_t)it * kQThreads;
+    if (i >= n) continue;
+    uint8_t m;
+    float sm;
+    if (mode == 0) {
+      m = given[i] ? 1 : 0;
+      sm = (float)m;
+    } else if (mode == 2) {
+      m = 1;
+      sm = 1.0f;
+    } else {
+      const float u = sgs_uniform(seed, step, (uint64_t)i);
+      const float s = score[i];
+      const float e = sgs_exp_repro(s);
+      m = (u * (1.0f + e)) > 1.0f ? 1 : 0;
+      const float l = logf(u) - logf(1.0f - u);
+      sm = 1.0f / (1.0f + __expf(-(s + l) / tau));
+    }
+    hard[i] = m;
+    if (soft) soft[i] = sm;
+    kept += m;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) kept += __shfl_xor(kept, off, 64);
+  if (lane == 0) s_kept[wave] = kept;
   __syncthreads();
+  uint64_t *dst = part + (int64_t)blockIdx.x * kPartWords;
   if (threadIdx.x < SGS_NCH) {
     const int j = threadIdx.x;
     uint64_t a = s_min[0][j], b = s_max[0][j];
+#pragma unroll
     for (int w = 1; w < kQWaves; ++w) {
       a = s_min[w][j] < a ? s_min[w][j] : a;
       b = s_max[w][j] > b ? s_max[w][j] : b;
     }
-    atomicMin((unsigned long long *)&stats[j], (unsigned long long)a);
-    atomicMax((unsigned long long *)&stats[SGS_NCH + j], (unsigned long long)b);
+    dst[j] = a;
+    dst[SGS_NCH + j] = b;
   }
   if (threadIdx.x == 64) {
     uint32_t t = 0;
+#pragma unroll
     for (int w = 0; w < kQWaves; ++w) t += s_kept[w];
-    atomicAdd((unsigned long long *)&stats[118], (unsigned long long)t);
+    dst[118] = t;
+  }
+}
+
+// Pass 2: block j reduces channel j over the block partials; block 0 also
+// the kept count and the step-size validity flag.
+__global__ void __launch_bounds__(kQThreads)
+k_stats_finish(int nblocks, const uint64_t *__restrict__ part, const float *__restrict__ q,
+               uint64_t *__restrict__ stats) {
+  __shared__ uint64_t s_a[kQWaves], s_b[kQWaves], s_c[kQWaves];
+  const int j = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint64_t a = ~0ull, b = 0ull, cnt = 0;
+  for (int k = threadIdx.x; k < nblocks; k += kQThreads) {
+    const uint64_t *p = part + (int64_t)k * kPartWords;
+    a = p[j] < a ? p[j] : a;
+    b = p[SGS_NCH + j] > b ? p[SGS_NCH + j] : b;
+    cnt += p[118];
+  }
+  a = wave_min_u64(a);
+  b = wave_max_u64(b);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+  if (lane == 0) {
+    s_a[wave] = a;
+    s_b[wave] = b;
+    s_c[wave] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  uint64_t ra = s_a[0], rb = s_b[0], rc = 0;
+  for (int w = 0; w < kQWaves; ++w) {
+    ra = s_a[w] < ra ? s_a[w] : ra;
+    rb = s_b[w] > rb ? s_b[w] : rb;
+    rc += s_c[w];
+  }
+  stats[j] = ra;
+  stats[SGS_NCH + j] = rb;
+  if (j == 0) {
+    stats[118] = rc;
+    uint64_t flags = 0;
+    for (int c = 0; c < SGS_NCH; ++c) {
+      const float qc = q[c];
+      if (!(qc > 0.0f) || !(qc < INFINITY)) flags |= 1ull;
+    }
+    stats[119] = flags;
+    for (int w = 120; w < SGS_STATS_WORDS; ++w) stats[w] = 0;
   }
 }
 
@@ -154,61 +203,71 @@ __global__ void k_rate_proxy(const uint64_t *__restrict__ stats, const float *__
   }
 }
 
-// Backward, pass 1: straight-through copy, per-block FP64 partial sums of the
-// learned-step-size gradient sum_i g_ij (k_ij - y_ij / q_j), score gradient.
-constexpr int kBItems = 8;  // Gaussians per thread per block
+// Backward pass 1: straight-through copy (skipped when aliased) and, per
+// block and channel, sum_i g_ij (k_ij q_j - y_ij) in FP64 (the learned-step
+// gradient before the division by q_j).  k q - y is formed with one fused
+// multiply-add, so the small residual is exact.
 __global__ void __launch_bounds__(kQThreads)
 k_fakequant_bwd(int64_t n, int64_t npad, const float *__restrict__ params,
                 const float *__restrict__ q, const float *__restrict__ gq_in,
                 float *__restrict__ gparams, double *__restrict__ partial) {
-  __shared__ double s_red[kQWaves];
+  __shared__ double s_red[kQWaves][SGS_NCH];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t base = (int64_t)blockIdx.x * kQThreads * kBItems;
+  const int64_t base = (int64_t)blockIdx.x * kQPer + threadIdx.x;
   const bool copy = gparams != gq_in;
   for (int j = 0; j < SGS_NCH; ++j) {
     const float qj = q[j];
-    double acc = 0.0;
+    float acc = 0.0f;
 #pragma unroll
-    for (int it = 0; it < kBItems; ++it) {
-      const int64_t i = base + (int64_t)it * kQThreads + threadIdx.x;
+    for (int it = 0; it < kQItems; ++it) {
+      const int64_t i = base + (int64_t)it * kQThreads;
       if (i < n) {
         const float g = gq_in[j * npad + i];
         const float yv = params[j * npad + i];
-        const float r = __fdiv_rn(yv, qj);
-        acc += (double)g * ((double)rintf(r) - (double)yv / (double)qj);
+        const float k = rintf(__fdiv_rn(yv, qj));
+        acc = fmaf(g, fmaf(k, qj, -yv), acc);
         if (copy) gparams[j * npad + i] = g;
       }
     }
-    acc = sgs_wave_sum_d(acc);
-    if (lane == 0) s_red[wave] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int w = 0; w < kQWaves; ++w) t += s_red[w];
-      partial[(int64_t)blockIdx.x * SGS_NCH + j] = t;
-    }
-    __syncthreads();
+    const double s = sgs_wave_sum_d((double)acc);
+    if (lane == 0) s_red[wave][j] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < SGS_NCH) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kQWaves; ++w) t += s_red[w][threadIdx.x];
+    partial[(int64_t)blockIdx.x * SGS_NCH + threadIdx.x] = t;
   }
 }
 
-// Backward, pass 2 (one block): fixed-order sum of the partials + the rate
-// proxy's step gradient; scatter of the rate gradient at argmax/argmin.
-__global__ void k_fakequant_bwd_finish(int nblocks, const double *__restrict__ partial,
-                                       const float *__restrict__ rate_grad,
-                                       const uint64_t *__restrict__ stats, int64_t npad,
-                                       float *__restrict__ gparams, float *__restrict__ gqstep) {
-  const int j = threadIdx.x;
-  if (j >= SGS_NCH) return;
+// Backward pass 2: block j sums channel j's partials (fixed order per
+// thread, then a tree), divides by q_j, adds the rate proxy's step gradient
+// and scatters its parameter gradient at argmax_j / argmin_j.
+__global__ void __launch_bounds__(kQThreads)
+k_fakequant_bwd_finish(int nblocks, const double *__restrict__ partial,
+                       const float *__restrict__ q, const float *__restrict__ rate_grad,
+                       const uint64_t *__restrict__ stats, int64_t npad,
+                       float *__restrict__ gparams, float *__restrict__ gqstep) {
+  __shared__ double s_w[kQWaves];
+  const int j = blockIdx.x;
   double t = 0.0;
-  for (int b = 0; b < nblocks; ++b) t += partial[(int64_t)b * SGS_NCH + j];
+  for (int b = threadIdx.x; b < nblocks; b += kQThreads) t += partial[(int64_t)b * SGS_NCH + j];
+  t = sgs_wave_sum_d(t);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double tot = 0.0;
+  for (int w = 0; w < kQWaves; ++w) tot += s_w[w];
+  tot /= (double)q[j];
   if (rate_grad) {
-    t += (double)rate_grad[128 + j];
+    tot += (double)rate_grad[128 + j];
     const uint32_t imin = (uint32_t)(stats[j] & 0xFFFFFFFFull);
     const uint32_t imax = 0xFFFFFFFFu - (uint32_t)(stats[SGS_NCH + j] & 0xFFFFFFFFull);
     gparams[j * npad + imax] += rate_grad[j];
     gparams[j * npad + imin] += rate_grad[64 + j];
   }
-  gqstep[j] = (float)t;
+  gqstep[j] = (float)tot;
 }
 
 __global__ void k_score_bwd(int64_t n, int mode, float tau, const float *__restrict__ soft,
@@ -227,21 +286,29 @@ __global__ void k_score_bwd(int64_t n, int mode, float tau, const float *__restr
 
 }  // namespace
 
+int64_t quant_partial_words(int64_t n) {
+  const int64_t nb = (n + kQPer - 1) / kQPer;
+  return nb * (kPartWords > SGS_NCH ? kPartWords : SGS_NCH);
+}
+
 hipError_t launch_fakequant_prune(sgs_ctx *c, const float *params, const float *q,
                                   const float *score, int mode, const uint8_t *given,
                                   uint64_t seed, uint64_t step, float *qparams,
                                   uint8_t *hard, float *soft, uint64_t *stats) {
-  k_stats_init<<<1, SGS_STATS_WORDS, 0, c->stream>>>(stats);
-  const int64_t want = (c->n + kQThreads - 1) / kQThreads;
-  const unsigned blocks = (unsigned)(want < 2048 ? want : 2048);
-  k_fakequant_prune<<<blocks, kQThreads, 0, c->stream>>>(c->n, c->npad, params, q, score, mode,
-                                                         given, seed, step, c->tau, qparams,
-                                                         hard, soft, stats);
+  SgsProfScope ps(c, SGS_PROF_FAKEQUANT);
+  const int nb = (int)((c->n + kQPer - 1) / kQPer);
+  if ((int64_t)nb * kPartWords > c->red_tmp_words) return hipErrorInvalidValue;
+  uint64_t *part = (uint64_t *)c->red_tmp;
+  k_fakequant_prune<<<nb, kQThreads, 0, c->stream>>>(c->n, c->npad, params, q, score, mode, given,
+                                                     seed, step, c->tau, qparams, hard, soft,
+                                                     part);
+  k_stats_finish<<<SGS_NCH, kQThreads, 0, c->stream>>>(nb, part, q, stats);
   return hipGetLastError();
 }
 
 hipError_t launch_rate_proxy(sgs_ctx *c, const uint64_t *stats, const float *q, float weight,
                              float *out3, float *rate_grad) {
+  SgsProfScope ps(c, SGS_PROF_RATE);
   k_rate_proxy<<<1, 64, 0, c->stream>>>(stats, q, c->n_hat, weight, out3, rate_grad);
   return hipGetLastError();
 }
@@ -251,13 +318,13 @@ hipError_t launch_fakequant_bwd(sgs_ctx *c, const float *params, const float *q,
                                 const uint64_t *stats, const float *gq_in,
                                 const float *gmask_in, float *gparams, float *gqstep,
                                 float *gscore) {
-  const int64_t per = (int64_t)kQThreads * kBItems;
-  const int nb = (int)((c->n + per - 1) / per);
+  const int nb = (int)((c->n + kQPer - 1) / kQPer);
   if ((int64_t)nb * SGS_NCH > c->red_tmp_words) return hipErrorInvalidValue;
+  SgsProfScope ps(c, SGS_PROF_FAKEQUANT_BWD);
   k_fakequant_bwd<<<nb, kQThreads, 0, c->stream>>>(c->n, c->npad, params, q, gq_in, gparams,
                                                    c->red_tmp);
-  k_fakequant_bwd_finish<<<1, 64, 0, c->stream>>>(nb, c->red_tmp, rate_grad, stats, c->npad,
-                                                  gparams, gqstep);
+  k_fakequant_bwd_finish<<<SGS_NCH, kQThreads, 0, c->stream>>>(nb, c->red_tmp, q, rate_grad,
+                                                               stats, c->npad, gparams, gqstep);
   k_score_bwd<<<sgs_blocks(c->n, 256), 256, 0, c->stream>>>(c->n, mode, c->tau, soft, gmask_in,
                                                             rate_grad, gscore);
   return hipGetLastError();

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/speedygs.h"
 
 #define SGS_CH_MU 0
@@ -45,7 +47,7 @@ struct sgs_ctx {
 
   // per (view, Gaussian): V*n entries
   int64_t vn = 0;
-  float4 *rec = nullptr;          // [3][vn]: (px,py,A,B) (C,opa,spanx,spany) (r,g,b,mask)
+  float4 *rec = nullptr;          // [vn][3]: (px,py,A,B) (C,opa,spanx,spany) (r,g,b,mask)
   uint32_t *depth_key[2] = {nullptr, nullptr};
   uint32_t *depth_val[2] = {nullptr, nullptr};
   uint32_t *touched = nullptr;    // [vn] tiles per splat (0 = culled)
@@ -67,10 +69,51 @@ struct sgs_ctx {
   double *red_tmp = nullptr;      int64_t red_tmp_words = 0;
   uint32_t *d_pairs_total = nullptr;  // device copy of the pair count
   uint32_t *h_pairs_total = nullptr;  // pinned host mirror
+
+  // kernel-group timing
+  struct ProfRec {
+    int group;
+    hipEvent_t a, b;
+  };
+  bool prof = false;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<ProfRec> prof_recs;
+};
+
+// Records a pair of HIP events around the launches in its scope when the
+// context's profiling is on.
+struct SgsProfScope {
+  sgs_ctx *c;
+  int g;
+  hipEvent_t a = nullptr;
+  static hipEvent_t get(sgs_ctx *c) {
+    hipEvent_t e = nullptr;
+    if (!c->ev_free.empty()) {
+      e = c->ev_free.back();
+      c->ev_free.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+  SgsProfScope(sgs_ctx *ctx, int group) : c(ctx), g(group) {
+    if (c->prof) {
+      a = get(c);
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~SgsProfScope() {
+    if (!a) return;
+    hipEvent_t b = get(c);
+    if (!b) return;
+    (void)hipEventRecord(b, c->stream);
+    c->prof_recs.push_back({g, a, b});
+  }
 };
 
 // ---- launchers (one translation unit each) --------------------------------
 // quant.hip
+int64_t quant_partial_words(int64_t n);  // FP64/u64 scratch words the quantizer passes need
 hipError_t launch_fakequant_prune(sgs_ctx *c, const float *params, const float *q,
                                   const float *score, int mode, const uint8_t *given,
                                   uint64_t seed, uint64_t step, float *qparams,

@@ -197,7 +197,7 @@ __global__ void k_gather_touched(const uint32_t *__restrict__ order,
 // Emit the pairs of each splat, splats in depth order; the value is the
 // Gaussian index, the key the global tile id.
 __global__ void k_duplicate(const uint32_t *__restrict__ order, const uint32_t *__restrict__ touched,
-                            const uint32_t *__restrict__ offsets, const float4 *__restrict__ rec1,
+                            const uint32_t *__restrict__ offsets, const float4 *__restrict__ rec,
                             int64_t count, int64_t n, int TW, int TH, int GW,
                             int64_t tiles_per_view, uint32_t *__restrict__ tile_key,
                             uint32_t *__restrict__ pair_val) {
@@ -205,7 +205,7 @@ __global__ void k_duplicate(const uint32_t *__restrict__ order, const uint32_t *
   if (k >= count) return;
   const uint32_t s = order[k];
   if (touched[s] == 0) return;
-  const float4 r = rec1[s];
+  const float4 r = rec[3 * (int64_t)s + 1];
   const uint32_t sx = __float_as_uint(r.z), sy = __float_as_uint(r.w);
   const int x0 = sx & 0xFFFF, x1 = sx >> 16, y0 = sy & 0xFFFF, y1 = sy >> 16;
   const uint32_t v = (uint32_t)(s / n);
@@ -259,7 +259,7 @@ hipError_t launch_exclusive_scan(sgs_ctx *c, const uint32_t *in, uint32_t *out, 
                                  uint32_t *total_out) {
   const int64_t nb = (count + kTile - 1) / kTile;
   if (nb == 0) {
-    if (total_out) (void)hipMemsetAsync(total_out, 0, sizeof(uint32_t), c->stream);
+    k_scan_sums<<<1, kThreads, 0, c->stream>>>(c->scan_tmp, 0, total_out, out);
     return hipGetLastError();
   }
   if (nb > c->scan_tmp_words) return hipErrorInvalidValue;
@@ -300,9 +300,13 @@ hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2], i
 // Depth sort of all (view, Gaussian) splats, then the pair offsets.
 hipError_t launch_depth_order(sgs_ctx *c) {
   int which = 0;
-  hipError_t e = launch_radix_sort(c, c->depth_key, c->depth_val, c->vn, 32, &which);
-  if (e != hipSuccess) return e;
+  {
+    SgsProfScope ps(c, SGS_PROF_DEPTH_SORT);
+    hipError_t e = launch_radix_sort(c, c->depth_key, c->depth_val, c->vn, 32, &which);
+    if (e != hipSuccess) return e;
+  }
   c->depth_sorted_buf = which;
+  SgsProfScope ps(c, SGS_PROF_SCAN);
   // touched in depth order -> scratch (the other key buffer is free now)
   uint32_t *tmp = c->depth_key[which ^ 1];
   k_gather_touched<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(c->depth_val[which],
@@ -313,16 +317,22 @@ hipError_t launch_depth_order(sgs_ctx *c) {
 hipError_t launch_bin_pairs(sgs_ctx *c) {
   const int64_t P = c->pairs;
   const uint32_t *order = c->depth_val[c->depth_sorted_buf];
-  const float4 *rec1 = c->rec + c->vn;
-  k_duplicate<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(
-      order, c->touched, c->offsets, rec1, c->vn, c->n, c->TW, c->TH, c->GW, c->tiles_per_view,
-      c->tile_key[0], c->pair_val[0]);
+  {
+    SgsProfScope ps(c, SGS_PROF_DUPLICATE);
+    k_duplicate<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(
+        order, c->touched, c->offsets, c->rec, c->vn, c->n, c->TW, c->TH, c->GW,
+        c->tiles_per_view, c->tile_key[0], c->pair_val[0]);
+  }
   int bits = 0;
   while (((int64_t)1 << bits) < c->total_tiles) ++bits;
   int which = 0;
-  hipError_t e = launch_radix_sort(c, c->tile_key, c->pair_val, P, bits, &which);
-  if (e != hipSuccess) return e;
+  {
+    SgsProfScope ps(c, SGS_PROF_TILE_SORT);
+    hipError_t e = launch_radix_sort(c, c->tile_key, c->pair_val, P, bits, &which);
+    if (e != hipSuccess) return e;
+  }
   c->pair_sorted_buf = which;
+  SgsProfScope ps(c, SGS_PROF_RANGES);
   k_zero_ranges<<<sgs_blocks(c->total_tiles, 256), 256, 0, c->stream>>>(c->ranges,
                                                                        c->total_tiles);
   if (P > 0)
