@@ -36,8 +36,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 # Algorithmic work per unit ("Roofline model").
 NCH = 59
-FLOP_PER_EVAL_FWD = 24     # support test excluded; exp counted as one flop
-FLOP_PER_EVAL_BWD = 62
+FLOP_PER_EVAL_FWD = 24     # offsets 2, quadratic form 9, exp 2, alpha/T 5, colour 6
+FLOP_PER_EVAL_BWD = 60     # alpha recompute 15, T and dalpha 12, 10 gradients 23, back colour 10
 
 
 def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int):
