@@ -171,6 +171,55 @@ sgs_status sgs_copy_structure(sgs_ctx *ctx, uint32_t *tile_ids, uint32_t *vals,
  * float [V][n][12] (px, py, A, B, C, opacity, r, g, b, mask, 0, 0). */
 sgs_status sgs_copy_splat_grads(sgs_ctx *ctx, float *out);
 
+/* ---- a13: learned rate estimator -----------------------------------------
+ * A per-Gaussian MLP 64 -> 128 -> 128 -> 1 (ReLU hidden layers, linear
+ * output) estimating the bits a Gaussian costs under the paper's channel-wise
+ * fixed-length coder (Sec. 3.4.1); it stands beside the range-based rate
+ * proxy of Sec. 3.3.1:  R_learned = (1/n_hat) sum_i M_i f(x_i),
+ * x_ij = log2(1 + (params_ij - min_j) / q_j) for the 59 channels (min_j from
+ * the statistics of sgs_fakequant_prune), padded with 5 zeros.
+ * theta: float32 [SGS_MLP_PARAMS] master weights, concatenated row-major
+ *   W1[64][128] (in, out), b1[128], W2[128][128], b2[128], w3[128], b3.
+ * packed: SGS_MLP_PACKED_BYTES of device memory holding the BF16 copy of W1
+ *   and W2 in the matrix-core fragment order (written by sgs_rate_mlp_pack).
+ * BF16 inputs, weights and first hidden activation; FP32 accumulation. */
+#define SGS_MLP_PARAMS 24961
+#define SGS_MLP_PACKED_BYTES 98304
+
+/* packed <- BF16 fragments of theta (round to nearest even). */
+sgs_status sgs_rate_mlp_pack(sgs_ctx *ctx, const float *theta, void *packed);
+/* out_R (device float[1]) = R_learned; per_gaussian (float [n], may be NULL)
+ * receives f(x_i).  Features are computed from params on the fly. */
+sgs_status sgs_rate_mlp_fwd(sgs_ctx *ctx, const void *packed, const float *theta,
+                            const float *params, const float *qstep, const uint64_t *stats,
+                            const uint8_t *hard_mask, float *out_R, float *per_gaussian);
+/* Gradient of rate_weight * R_learned, recomputing the forward (no stored
+ * activations), ADDED into grad_params [59][npad] and grad_qstep [59]
+ * (channel minima held fixed), and dR/dM_i = f_i / n_hat added into
+ * grad_hard_mask (may be NULL) and, in mask mode 1, through the
+ * straight-through Gumbel-sigmoid into grad_score (may be NULL).  Call after
+ * sgs_fakequant_prune_bwd. */
+sgs_status sgs_rate_mlp_bwd(sgs_ctx *ctx, const void *packed, const float *theta,
+                            const float *params, const float *qstep, const uint64_t *stats,
+                            const uint8_t *hard_mask, const float *soft_mask,
+                            int32_t mask_mode, float rate_weight, float *grad_params,
+                            float *grad_qstep, float *grad_score, float *grad_hard_mask);
+/* f over given feature rows: X BF16 [rows][64] (8-byte aligned), out float [rows]. */
+sgs_status sgs_rate_mlp_infer(sgs_ctx *ctx, const void *packed, const float *theta,
+                              const uint16_t *X, int64_t rows, float *out);
+/* Bytes of the caller-provided device workspace a training step on `rows`
+ * rows needs. */
+int64_t sgs_rate_mlp_train_scratch_bytes(int64_t rows);
+/* One training step on rows feature vectors X (BF16 [rows][64]) with targets
+ * (float [rows]): loss[0] = mean (f - target)^2, grad_theta (float
+ * [SGS_MLP_PARAMS]) = its gradient; if lr > 0, Adam (beta 0.9 / 0.999,
+ * eps 1e-8, bias-corrected with `step` >= 1) updates theta, adam_m, adam_v in
+ * place and re-packs `packed`.  rows must be a positive multiple of 8. */
+sgs_status sgs_rate_mlp_train_step(sgs_ctx *ctx, float *theta, float *adam_m, float *adam_v,
+                                   void *packed, const uint16_t *X, const float *target,
+                                   int64_t rows, float lr, int64_t step, float *loss,
+                                   float *grad_theta, void *scratch);
+
 /* Kernel-group timing with HIP events recorded on the context's stream around
  * each group's launches (no extra synchronization inside a step).  Groups: */
 enum {
@@ -188,7 +237,10 @@ enum {
   SGS_PROF_BLEND_BWD = 11, /* a10 */
   SGS_PROF_PREPROCESS_BWD = 12, /* a11 */
   SGS_PROF_FAKEQUANT_BWD = 13,  /* a12 */
-  SGS_PROF_GROUPS = 14
+  SGS_PROF_MLP_FWD = 14,   /* a13 learned rate, forward / inference */
+  SGS_PROF_MLP_BWD = 15,   /* a13 learned rate, backward */
+  SGS_PROF_MLP_TRAIN = 16, /* a13 training step */
+  SGS_PROF_GROUPS = 17
 };
 /* enable != 0 starts recording (and clears earlier records); 0 stops. */
 sgs_status sgs_profile_enable(sgs_ctx *ctx, int32_t enable);

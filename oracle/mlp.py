@@ -133,16 +133,18 @@ def channel_min(params, n):
     return params[:NCH, :n].min(axis=1).astype(np.float32)
 
 
-def learned_rate(params, qstep, mhat, n, n_hat, w, mirror=True):
-    """R_learned = (1/N_hat) sum_i M_i f(x_i) and its gradient w.r.t. the raw
-    parameters, the steps and the hard mask (channel minima held fixed)."""
+def learned_rate(params, qstep, mhat, n, n_hat, w, mirror=True, weight=1.0):
+    """R_learned = (1/N_hat) sum_i M_i f(x_i) and the gradient of weight * R
+    w.r.t. the raw parameters, the steps and the hard mask (channel minima
+    held fixed).  The weight enters before the BF16 rounding of dz2, as on
+    the GPU."""
     params = np.ascontiguousarray(params, np.float32)
     mmin = channel_min(params, n)
     X = features(params, qstep, mmin, n, mirror)
     f = forward(X, w, mirror)
     m = mhat.astype(np.float64)
     R = float((m * f).sum() / n_hat)
-    _, dX = backward(X, w, m / n_hat, mirror, want_dx=True)
+    _, dX = backward(X, w, weight * m / n_hat, mirror, want_dx=True)
     u = (params[:NCH, :n].astype(np.float64) - mmin[:, None].astype(np.float64)) \
         / qstep[:, None].astype(np.float64)
     dxdu = 1.0 / ((1.0 + u) * math.log(2.0))
@@ -150,5 +152,5 @@ def learned_rate(params, qstep, mhat, n, n_hat, w, mirror=True):
     gy = np.zeros(params.shape)
     gy[:NCH, :n] = gx * dxdu / qstep[:, None].astype(np.float64)
     gq = -(gx * dxdu * u).sum(axis=1) / qstep.astype(np.float64)
-    gm = f / n_hat
+    gm = weight * f / n_hat
     return dict(R=R, f=f, X=X, gy=gy, gq=gq, gm=gm)

@@ -64,10 +64,18 @@ _SIGS = {
     "sgs_copy_splat_grads": [P, P],
     "sgs_profile_enable": [P, I32],
     "sgs_profile_read": [P, P, P],
+    "sgs_rate_mlp_pack": [P, P, P],
+    "sgs_rate_mlp_fwd": [P, P, P, P, P, P, P, P, P],
+    "sgs_rate_mlp_bwd": [P, P, P, P, P, P, P, P, I32, F32, P, P, P, P],
+    "sgs_rate_mlp_infer": [P, P, P, P, I64, P],
+    "sgs_rate_mlp_train_scratch_bytes": [I64],
+    "sgs_rate_mlp_train_step": [P, P, P, P, P, P, P, I64, F32, I64, P, P, P],
 }
 PROF_GROUPS = ("fakequant", "rate", "preprocess", "depth_sort", "scan", "duplicate",
                "tile_sort", "ranges", "blend_fwd", "l1", "grad_clear", "blend_bwd",
-               "preprocess_bwd", "fakequant_bwd")
+               "preprocess_bwd", "fakequant_bwd", "mlp_fwd", "mlp_bwd", "mlp_train")
+MLP_PARAMS = 24961
+MLP_PACKED_BYTES = 98304
 EXPORTS = tuple(_SIGS)
 
 _lib = None
@@ -85,7 +93,8 @@ def lib(path: str | None = None):
     for name, args in _SIGS.items():
         f = getattr(L, name)
         f.argtypes = args
-        f.restype = C.c_char_p if name == "sgs_last_error" else (None if name == "sgs_destroy" else C.c_int)
+        f.restype = {"sgs_last_error": C.c_char_p, "sgs_destroy": None,
+                     "sgs_rate_mlp_train_scratch_bytes": C.c_int64}.get(name, C.c_int)
     if path is None:
         _lib = L
     return L
@@ -195,6 +204,36 @@ class Context:
 
     def copy_splat_grads(self, out):
         self._check(self.L.sgs_copy_splat_grads(self.h, _ptr(out)), self.h)
+
+    # ---- learned rate estimator --------------------------------------------
+    def rate_mlp_pack(self, theta, packed):
+        self._check(self.L.sgs_rate_mlp_pack(self.h, _ptr(theta), _ptr(packed)), self.h)
+
+    def rate_mlp_fwd(self, packed, theta, params, qstep, stats, hard_mask, out_R,
+                     per_gaussian=None):
+        self._check(self.L.sgs_rate_mlp_fwd(self.h, _ptr(packed), _ptr(theta), _ptr(params),
+                                            _ptr(qstep), _ptr(stats), _ptr(hard_mask),
+                                            _ptr(out_R), _ptr(per_gaussian)), self.h)
+
+    def rate_mlp_bwd(self, packed, theta, params, qstep, stats, hard_mask, soft_mask, mask_mode,
+                     rate_weight, grad_params, grad_qstep, grad_score=None, grad_hard_mask=None):
+        self._check(self.L.sgs_rate_mlp_bwd(
+            self.h, _ptr(packed), _ptr(theta), _ptr(params), _ptr(qstep), _ptr(stats),
+            _ptr(hard_mask), _ptr(soft_mask), mask_mode, rate_weight, _ptr(grad_params),
+            _ptr(grad_qstep), _ptr(grad_score), _ptr(grad_hard_mask)), self.h)
+
+    def rate_mlp_infer(self, packed, theta, X, rows, out):
+        self._check(self.L.sgs_rate_mlp_infer(self.h, _ptr(packed), _ptr(theta), _ptr(X), rows,
+                                              _ptr(out)), self.h)
+
+    def rate_mlp_train_scratch_bytes(self, rows) -> int:
+        return int(self.L.sgs_rate_mlp_train_scratch_bytes(rows))
+
+    def rate_mlp_train_step(self, theta, adam_m, adam_v, packed, X, target, rows, lr, step,
+                            loss, grad_theta, scratch):
+        self._check(self.L.sgs_rate_mlp_train_step(
+            self.h, _ptr(theta), _ptr(adam_m), _ptr(adam_v), _ptr(packed), _ptr(X),
+            _ptr(target), rows, lr, step, _ptr(loss), _ptr(grad_theta), _ptr(scratch)), self.h)
 
     def profile_enable(self, on: bool = True):
         self._check(self.L.sgs_profile_enable(self.h, 1 if on else 0), self.h)

@@ -199,7 +199,9 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   SGS_ALLOC(c->d_pairs_total, 1);
   const int64_t red_q = quant_partial_words(n);
   const int64_t red_l1 = (int64_t)views * 3 * width * height / 2048 + 64;
-  const int64_t red = (red_q > red_l1 ? red_q : red_l1) + 64;
+  const int64_t red_mlp = (int64_t)mlp_grid(n) * 64;
+  int64_t red = red_q > red_l1 ? red_q : red_l1;
+  red = (red > red_mlp ? red : red_mlp) + 64;
   SGS_ALLOC(c->red_tmp, red);
   c->red_tmp_words = red;
 #undef SGS_ALLOC
@@ -322,6 +324,83 @@ sgs_status sgs_query(sgs_ctx *c, const uint64_t *stats, int64_t *pairs_last, uin
       SGS_HIP(hipMemcpy(flags, stats + 119, sizeof(uint64_t), hipMemcpyDeviceToHost), "query flags");
   }
   if (flags && (*flags & 1ull)) return fail(c, SGS_EINVAL, "a step size q_j was <= 0 or not finite");
+  return SGS_OK;
+}
+
+sgs_status sgs_rate_mlp_pack(sgs_ctx *c, const float *theta, void *packed) {
+  if (!c) return SGS_EINVAL;
+  if (!theta || !packed || !aligned(packed, 16))
+    return fail(c, SGS_EINVAL, "rate_mlp_pack: null or misaligned pointer");
+  SGS_HIP(launch_mlp_pack(c, theta, packed), "rate_mlp_pack");
+  return SGS_OK;
+}
+
+sgs_status sgs_rate_mlp_fwd(sgs_ctx *c, const void *packed, const float *theta,
+                            const float *params, const float *qstep, const uint64_t *stats,
+                            const uint8_t *hard_mask, float *out_R, float *per_gaussian) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "rate_mlp_fwd: set_scene first");
+  if (!packed || !theta || !params || !qstep || !stats || !hard_mask || !out_R)
+    return fail(c, SGS_EINVAL, "rate_mlp_fwd: null pointer");
+  if (!aligned(packed, 16)) return fail(c, SGS_EINVAL, "rate_mlp_fwd: packed must be 16-byte aligned");
+  SGS_HIP(launch_mlp_rate_fwd(c, packed, theta, params, qstep, stats, hard_mask, out_R,
+                              per_gaussian),
+          "rate_mlp_fwd");
+  return SGS_OK;
+}
+
+sgs_status sgs_rate_mlp_bwd(sgs_ctx *c, const void *packed, const float *theta,
+                            const float *params, const float *qstep, const uint64_t *stats,
+                            const uint8_t *hard_mask, const float *soft_mask, int32_t mask_mode,
+                            float rate_weight, float *grad_params, float *grad_qstep,
+                            float *grad_score, float *grad_hard_mask) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "rate_mlp_bwd: set_scene first");
+  if (!packed || !theta || !params || !qstep || !stats || !hard_mask || !grad_params ||
+      !grad_qstep)
+    return fail(c, SGS_EINVAL, "rate_mlp_bwd: null pointer");
+  if (mask_mode < 0 || mask_mode > 2) return fail(c, SGS_EINVAL, "rate_mlp_bwd: mask_mode");
+  if (mask_mode == 1 && grad_score && !soft_mask)
+    return fail(c, SGS_EINVAL, "rate_mlp_bwd: soft_mask needed for the score gradient");
+  if (!aligned(packed, 16)) return fail(c, SGS_EINVAL, "rate_mlp_bwd: packed must be 16-byte aligned");
+  SGS_HIP(launch_mlp_rate_bwd(c, packed, theta, params, qstep, stats, hard_mask, soft_mask,
+                              mask_mode, rate_weight, grad_params, grad_qstep,
+                              mask_mode == 1 ? grad_score : nullptr, grad_hard_mask),
+          "rate_mlp_bwd");
+  return SGS_OK;
+}
+
+sgs_status sgs_rate_mlp_infer(sgs_ctx *c, const void *packed, const float *theta,
+                              const uint16_t *X, int64_t rows, float *out) {
+  if (!c) return SGS_EINVAL;
+  if (!packed || !theta || !X || !out || rows < 1)
+    return fail(c, SGS_EINVAL, "rate_mlp_infer: null pointer or rows < 1");
+  if (!aligned(X, 8) || !aligned(packed, 16))
+    return fail(c, SGS_EINVAL, "rate_mlp_infer: misaligned pointer");
+  SGS_HIP(launch_mlp_infer(c, packed, theta, X, rows, out), "rate_mlp_infer");
+  return SGS_OK;
+}
+
+int64_t sgs_rate_mlp_train_scratch_bytes(int64_t rows) {
+  return rows < 1 ? 0 : mlp_train_scratch_bytes(rows);
+}
+
+sgs_status sgs_rate_mlp_train_step(sgs_ctx *c, float *theta, float *adam_m, float *adam_v,
+                                   void *packed, const uint16_t *X, const float *target,
+                                   int64_t rows, float lr, int64_t step, float *loss,
+                                   float *grad_theta, void *scratch) {
+  if (!c) return SGS_EINVAL;
+  if (!theta || !packed || !X || !target || !loss || !grad_theta || !scratch)
+    return fail(c, SGS_EINVAL, "rate_mlp_train_step: null pointer");
+  if (rows < 8 || rows % 8 != 0 || rows > ((int64_t)1 << 26))
+    return fail(c, SGS_EINVAL, "rate_mlp_train_step: rows must be a multiple of 8 in [8, 2^26]");
+  if (lr > 0.0f && (!adam_m || !adam_v || step < 1))
+    return fail(c, SGS_EINVAL, "rate_mlp_train_step: Adam needs moments and step >= 1");
+  if (!aligned(X, 8) || !aligned(packed, 16) || !aligned(scratch, 256))
+    return fail(c, SGS_EINVAL, "rate_mlp_train_step: misaligned pointer");
+  SGS_HIP(launch_mlp_train_step(c, theta, adam_m, adam_v, packed, X, target, rows, lr, step, loss,
+                                grad_theta, scratch),
+          "rate_mlp_train_step");
   return SGS_OK;
 }
 

@@ -1,0 +1,729 @@
+// Learned rate estimator: a per-Gaussian MLP 64 -> 128 -> 128 -> 1 on the
+// BF16 matrix cores (FP32 accumulation), standing beside the range-based
+// rate proxy (paper Sec. 3.3.1) as an estimate of the bits of the paper's
+// channel-wise fixed-length coder (Sec. 3.4.1).
+//
+// Formulation.  Every layer is computed transposed, H_out^T = W^T H_in^T,
+// with v_mfma_f32_32x32x8bf16_1k: A = 32 rows of W^T (a pre-swizzled BF16
+// fragment per lane, staged in LDS), B = 8 x 32 slice of H_in^T, D = 32 x 32
+// tile of H_out^T.  In the accumulator layout lane l holds batch column l%32
+// and output rows 8(i/4) + 4(l/32) + i%4 (i = 0..15), which is exactly the B
+// operand layout of the next layer's k-steps (rows 8s + 4(l/32) + 0..3), so
+// activations never leave registers between layers.  The same holds for the
+// backward to the inputs (dH1^T = W2 dZ2^T, dX^T = W1 dZ1^T).  Weight
+// gradients (training) are split-K GEMMs over the batch on transposed
+// activations written by the row kernel.
+#include "sgs_internal.h"
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int MI = 64, MH = 128;
+constexpr int kOffW1 = 0, kOffB1 = MI * MH, kOffW2 = kOffB1 + MH, kOffB2 = kOffW2 + MH * MH,
+              kOffW3 = kOffB2 + MH, kOffB3 = kOffW3 + MH, kParams = kOffB3 + 1;
+static_assert(kParams == SGS_MLP_PARAMS, "parameter count");
+// packed fragment arrays (bf16x4 per lane)
+constexpr int kF1 = 4 * 8 * 64;    // W1^T tiles  [t out 4][s in 8][lane]
+constexpr int kF2 = 4 * 16 * 64;   // W2^T tiles  [t out 4][s in 16][lane]
+constexpr int kF2B = 4 * 16 * 64;  // W2 tiles    [t in 4][s out 16][lane]
+constexpr int kF1B = 2 * 16 * 64;  // W1 tiles    [t in 2][s out 16][lane]
+constexpr int kPacked = kF1 + kF2 + kF2B + kF1B;
+static_assert(kPacked * 8 == SGS_MLP_PACKED_BYTES, "packed size");
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ float rbf(float f) { return bf2f(f2bf(f)); }
+__device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
+  bf16x4 r;
+  r[0] = (short)f2bf(a);
+  r[1] = (short)f2bf(b);
+  r[2] = (short)f2bf(c);
+  r[3] = (short)f2bf(d);
+  return r;
+}
+__device__ __forceinline__ f32x16 mfma(bf16x4 a, bf16x4 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x16 zero16() {
+  f32x16 z;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) z[i] = 0.0f;
+  return z;
+}
+// output row of accumulator element i for lane l, within a 32-row tile
+__device__ __forceinline__ int drow(int i, int lane) { return 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3); }
+
+// fp32 master weights -> BF16 fragments
+__global__ void k_mlp_pack(const float *__restrict__ th, bf16x4 *__restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kPacked) return;
+  const float *W1 = th + kOffW1, *W2 = th + kOffW2;
+  int r = e, lane, s, t;
+  float v[4];
+  if (r < kF1) {
+    lane = r & 63; s = (r >> 6) & 7; t = r >> 9;
+    for (int j = 0; j < 4; ++j) v[j] = W1[(8 * s + 4 * (lane >> 5) + j) * MH + 32 * t + (lane & 31)];
+  } else if ((r -= kF1) < kF2) {
+    lane = r & 63; s = (r >> 6) & 15; t = r >> 10;
+    for (int j = 0; j < 4; ++j) v[j] = W2[(8 * s + 4 * (lane >> 5) + j) * MH + 32 * t + (lane & 31)];
+  } else if ((r -= kF2) < kF2B) {
+    lane = r & 63; s = (r >> 6) & 15; t = r >> 10;
+    for (int j = 0; j < 4; ++j) v[j] = W2[(32 * t + (lane & 31)) * MH + 8 * s + 4 * (lane >> 5) + j];
+  } else {
+    r -= kF2B;
+    lane = r & 63; s = (r >> 6) & 15; t = r >> 10;
+    for (int j = 0; j < 4; ++j) v[j] = W1[(32 * t + (lane & 31)) * MH + 8 * s + 4 * (lane >> 5) + j];
+  }
+  out[e] = pack4(v[0], v[1], v[2], v[3]);
+}
+
+struct MlpLds {
+  bf16x4 F1[4][8][64];
+  bf16x4 F2[4][16][64];
+  float b1[MH], b2[MH], w3[MH];
+  float b3;
+};
+struct MlpLdsBwd {
+  MlpLds f;
+  bf16x4 F2B[4][16][64];
+  bf16x4 F1B[2][16][64];
+};
+
+__device__ void load_lds(MlpLds &L, const bf16x4 *__restrict__ packed, const float *__restrict__ th) {
+  bf16x4 *d1 = &L.F1[0][0][0];
+  for (int e = threadIdx.x; e < kF1 + kF2; e += blockDim.x) d1[e] = packed[e];  // F1 then F2
+  for (int k = threadIdx.x; k < MH; k += blockDim.x) {
+    L.b1[k] = th[kOffB1 + k];
+    L.b2[k] = th[kOffB2 + k];
+    L.w3[k] = rbf(th[kOffW3 + k]);
+  }
+  if (threadIdx.x == 0) L.b3 = th[kOffB3];
+}
+__device__ void load_lds_bwd(MlpLdsBwd &L, const bf16x4 *__restrict__ packed,
+                             const float *__restrict__ th) {
+  load_lds(L.f, packed, th);
+  bf16x4 *d = &L.F2B[0][0][0];
+  for (int e = threadIdx.x; e < kF2B + kF1B; e += blockDim.x) d[e] = packed[kF1 + kF2 + e];
+}
+
+// Forward of one 32-row tile held by a wave.  xb[s]: B fragments of X^T.
+// Leaves pre-activations (with bias) in z1, z2; returns f for row lane%32.
+__device__ __forceinline__ float tile_fwd(const MlpLds &L, const bf16x4 xb[8], int lane,
+                                          f32x16 z1[4], f32x16 z2[4], bf16x4 hb[16]) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) z1[t] = zero16();
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) z1[t] = mfma(L.F1[t][s][lane], xb[s], z1[t]);
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      float h[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = 4 * g + j;
+        const float z = z1[t][i] + L.b1[32 * t + drow(i, lane)];
+        z1[t][i] = z;
+        h[j] = fmaxf(z, 0.0f);
+      }
+      hb[4 * t + g] = pack4(h[0], h[1], h[2], h[3]);
+    }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) z2[t] = zero16();
+#pragma unroll
+  for (int s = 0; s < 16; ++s)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) z2[t] = mfma(L.F2[t][s][lane], hb[s], z2[t]);
+  float p = 0.0f;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int o = 32 * t + drow(i, lane);
+      const float z = z2[t][i] + L.b2[o];
+      z2[t][i] = z;
+      p = fmaf(fmaxf(z, 0.0f), L.w3[o], p);
+    }
+  p += __shfl_xor(p, 32, 64);
+  return p + L.b3;
+}
+
+// Features of one row for k-step s: channels 8s + 4(l/32) + 0..3.
+__device__ __forceinline__ bf16x4 feature_frag(const float *__restrict__ y, int64_t npad, int64_t r,
+                                               bool valid, const float *__restrict__ q,
+                                               const float *s_min, int s, int lane) {
+  float v[4];
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) {
+    const int j = 8 * s + 4 * (lane >> 5) + jj;
+    float x = 0.0f;
+    if (valid && j < SGS_NCH) {
+      const float u = (y[j * npad + r] - s_min[j]) / q[j];
+      x = log2f(1.0f + u);
+    }
+    v[jj] = x;
+  }
+  return pack4(v[0], v[1], v[2], v[3]);
+}
+
+__device__ __forceinline__ void load_mins(float *s_min, const uint64_t *__restrict__ stats) {
+  for (int j = threadIdx.x; j < SGS_NCH; j += blockDim.x)
+    s_min[j] = sgs_unord((uint32_t)(stats[j] >> 32));
+}
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+// In-loop forward: R partials = sum_r M_r f(x_r) per block (FP64), f optional.
+__global__ void __launch_bounds__(kThreads)
+k_mlp_rate_fwd(int64_t n, int64_t npad, const bf16x4 *__restrict__ packed,
+               const float *__restrict__ th, const float *__restrict__ y,
+               const float *__restrict__ q, const uint64_t *__restrict__ stats,
+               const uint8_t *__restrict__ hard, float *__restrict__ fout,
+               double *__restrict__ partial) {
+  __shared__ MlpLds L;
+  __shared__ float s_min[SGS_NCH];
+  __shared__ double s_red[kWaves];
+  load_lds(L, packed, th);
+  load_mins(s_min, stats);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t ntiles = (n + 31) / 32;
+  double acc = 0.0;
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < ntiles;
+       tile += (int64_t)gridDim.x * kWaves) {
+    // keep the weight fragments in LDS: without this the loop-invariant
+    // fragment reads are hoisted into ~200 registers and the kernel spills
+    __asm__ volatile("" ::: "memory");
+    const int64_t r = tile * 32 + (lane & 31);
+    const bool valid = r < n;
+    bf16x4 xb[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) xb[s] = feature_frag(y, npad, r, valid, q, s_min, s, lane);
+    f32x16 z1[4], z2[4];
+    bf16x4 hb[16];
+    const float f = tile_fwd(L, xb, lane, z1, z2, hb);
+    if (valid && lane < 32) {
+      if (fout) fout[r] = f;
+      if (hard[r]) acc += (double)f;
+    }
+  }
+  acc = sgs_wave_sum_d(acc);
+  if (lane == 0) s_red[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kWaves; ++w) t += s_red[w];
+    partial[blockIdx.x] = t;
+  }
+}
+
+__global__ void k_mlp_rate_finish(int nb, const double *__restrict__ partial, int64_t n_hat,
+                                  float *__restrict__ outR) {
+  __shared__ double s_w[kWaves];
+  double t = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) t += partial[b];
+  t = sgs_wave_sum_d(t);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / 64); ++w) s += s_w[w];
+    outR[0] = (float)(s / (double)n_hat);
+  }
+}
+
+// In-loop backward of weight * R, R = (1/N_hat) sum_r M_r f(x_r), through the
+// MLP to the features, then to the raw parameters and the steps (channel
+// minima held fixed); dR/dM_r = f_r / N_hat.  Adds into grad_params,
+// per-block step partials, grad_score (mask mode 1) / grad_hard_mask.
+__global__ void __launch_bounds__(kThreads)
+k_mlp_rate_bwd(int64_t n, int64_t npad, int64_t n_hat, float weight, float tau, int mode,
+               const bf16x4 *__restrict__ packed, const float *__restrict__ th,
+               const float *__restrict__ y, const float *__restrict__ q,
+               const uint64_t *__restrict__ stats, const uint8_t *__restrict__ hard,
+               const float *__restrict__ soft, float *__restrict__ gparams,
+               float *__restrict__ gscore, float *__restrict__ gmask,
+               double *__restrict__ qpartial) {
+  __shared__ MlpLdsBwd L;
+  __shared__ float s_min[SGS_NCH];
+  __shared__ float s_q[SGS_NCH];
+  __shared__ double s_gq[kWaves][64];
+  load_lds_bwd(L, packed, th);
+  load_mins(s_min, stats);
+  for (int j = threadIdx.x; j < SGS_NCH; j += blockDim.x) s_q[j] = q[j];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float ln2 = 0.69314718055994531f;
+  const float cscale = weight / (float)n_hat;
+  float gq[32];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) gq[k] = 0.0f;
+  const int64_t ntiles = (n + 31) / 32;
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < ntiles;
+       tile += (int64_t)gridDim.x * kWaves) {
+    // keep the weight fragments in LDS: without this the loop-invariant
+    // fragment reads are hoisted into ~200 registers and the kernel spills
+    __asm__ volatile("" ::: "memory");
+    const int64_t r = tile * 32 + (lane & 31);
+    const bool valid = r < n;
+    bf16x4 xb[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) xb[s] = feature_frag(y, npad, r, valid, s_q, s_min, s, lane);
+    f32x16 z1[4], z2[4];
+    bf16x4 hb[16];
+    const float f = tile_fwd(L.f, xb, lane, z1, z2, hb);
+    const bool m = valid && hard[r];
+    const float c = m ? cscale : 0.0f;
+    // mask gradient
+    if (valid && lane < 32) {
+      const float gmv = cscale * f;
+      if (gmask) gmask[r] += gmv;
+      if (mode == 1 && gscore) {
+        const float sm = soft[r];
+        gscore[r] += gmv * sm * (1.0f - sm) / tau;
+      }
+    }
+    if (__ballot(m) == 0ull) continue;
+    // dz2 = c w3 [z2 > 0]  (BF16, B operand layout)
+    bf16x4 dzb[16];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int i = 4 * g + j;
+          v[j] = z2[t][i] > 0.0f ? c * L.f.w3[32 * t + drow(i, lane)] : 0.0f;
+        }
+        dzb[4 * t + g] = pack4(v[0], v[1], v[2], v[3]);
+      }
+    // dh1^T = W2 dZ2^T ; dz1 = dh1 [z1 > 0]
+    f32x16 dh[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) dh[t] = zero16();
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) dh[t] = mfma(L.F2B[t][s][lane], dzb[s], dh[t]);
+    bf16x4 d1b[16];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int i = 4 * g + j;
+          v[j] = z1[t][i] > 0.0f ? dh[t][i] : 0.0f;
+        }
+        d1b[4 * t + g] = pack4(v[0], v[1], v[2], v[3]);
+      }
+    // dX^T = W1 dZ1^T
+    f32x16 dx[2];
+    dx[0] = zero16();
+    dx[1] = zero16();
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      dx[0] = mfma(L.F1B[0][s][lane], d1b[s], dx[0]);
+      dx[1] = mfma(L.F1B[1][s][lane], d1b[s], dx[1]);
+    }
+    // chain to y and q: x = log2(1 + u), u = (y - m) / q
+    if (valid) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int j = 32 * t + drow(i, lane);
+          if (j < SGS_NCH) {
+            const float qj = s_q[j];
+            const float u = (y[j * npad + r] - s_min[j]) / qj;
+            const float dxdu = 1.0f / ((1.0f + u) * ln2);
+            const float g = dx[t][i] * dxdu;
+            gparams[j * npad + r] += g / qj;
+            gq[16 * t + i] -= g * u / qj;
+          }
+        }
+    }
+  }
+  // reduce the step gradient: lanes sharing lane>>5 hold the same channels
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    float v = gq[k];
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    gq[k] = v;
+  }
+  if ((lane & 31) == 0) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) s_gq[wave][32 * t + drow(i, lane)] = (double)gq[16 * t + i];
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double s = 0.0;
+    for (int w = 0; w < kWaves; ++w) s += s_gq[w][threadIdx.x];
+    qpartial[(int64_t)blockIdx.x * 64 + threadIdx.x] = s;
+  }
+}
+
+__global__ void k_mlp_q_finish(int nb, const double *__restrict__ qpartial,
+                               float *__restrict__ gqstep) {
+  const int j = threadIdx.x;
+  if (j >= SGS_NCH) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += qpartial[(int64_t)b * 64 + j];
+  gqstep[j] += (float)s;
+}
+
+// Inference over given feature rows X [B][64] (BF16) -> f [B].
+__global__ void __launch_bounds__(kThreads)
+k_mlp_infer(int64_t B, const bf16x4 *__restrict__ packed, const float *__restrict__ th,
+            const uint16_t *__restrict__ X, float *__restrict__ fout) {
+  __shared__ MlpLds L;
+  load_lds(L, packed, th);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t ntiles = (B + 31) / 32;
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < ntiles;
+       tile += (int64_t)gridDim.x * kWaves) {
+    // keep the weight fragments in LDS: without this the loop-invariant
+    // fragment reads are hoisted into ~200 registers and the kernel spills
+    __asm__ volatile("" ::: "memory");
+    const int64_t r = tile * 32 + (lane & 31);
+    const bool valid = r < B;
+    bf16x4 xb[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      if (valid) {
+        xb[s] = *(const bf16x4 *)(X + r * MI + 8 * s + 4 * (lane >> 5));
+      } else {
+        xb[s] = pack4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+    f32x16 z1[4], z2[4];
+    bf16x4 hb[16];
+    const float f = tile_fwd(L, xb, lane, z1, z2, hb);
+    if (valid && lane < 32) fout[r] = f;
+  }
+}
+
+// Training, pass 1 (per row): forward, loss, df = scale (f - t), dz2, dz1;
+// writes the transposed operands of the weight-gradient GEMMs.
+__global__ void __launch_bounds__(kThreads)
+k_mlp_train_rows(int64_t B, float scale, const bf16x4 *__restrict__ packed,
+                 const float *__restrict__ th, const uint16_t *__restrict__ X,
+                 const float *__restrict__ target, uint16_t *__restrict__ XT,
+                 uint16_t *__restrict__ H1T, uint16_t *__restrict__ DZ2T,
+                 uint16_t *__restrict__ DZ1T, float *__restrict__ H2T, float *__restrict__ df,
+                 double *__restrict__ loss_partial) {
+  __shared__ MlpLdsBwd L;
+  __shared__ double s_red[kWaves];
+  load_lds_bwd(L, packed, th);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t ntiles = (B + 31) / 32;
+  double lacc = 0.0;
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < ntiles;
+       tile += (int64_t)gridDim.x * kWaves) {
+    // keep the weight fragments in LDS: without this the loop-invariant
+    // fragment reads are hoisted into ~200 registers and the kernel spills
+    __asm__ volatile("" ::: "memory");
+    const int64_t r = tile * 32 + (lane & 31);
+    const bool valid = r < B;
+    bf16x4 xb[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      if (valid) {
+        xb[s] = *(const bf16x4 *)(X + r * MI + 8 * s + 4 * (lane >> 5));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) XT[(int64_t)(8 * s + 4 * (lane >> 5) + j) * B + r] = (uint16_t)xb[s][j];
+      } else {
+        xb[s] = pack4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+    f32x16 z1[4], z2[4];
+    bf16x4 hb[16];
+    const float f = tile_fwd(L.f, xb, lane, z1, z2, hb);
+    float c = 0.0f;
+    if (valid) {
+      const float d = f - target[r];
+      c = scale * d;
+      if (lane < 32) {
+        lacc += (double)d * (double)d;
+        df[r] = c;
+      }
+    }
+    bf16x4 dzb[16];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int i = 4 * g + j;
+          const int o = 32 * t + drow(i, lane);
+          v[j] = z2[t][i] > 0.0f ? c * L.f.w3[o] : 0.0f;
+          if (valid) {
+            H2T[(int64_t)o * B + r] = fmaxf(z2[t][i], 0.0f);
+            H1T[(int64_t)o * B + r] = (uint16_t)hb[4 * t + g][j];
+          }
+        }
+        dzb[4 * t + g] = pack4(v[0], v[1], v[2], v[3]);
+        if (valid) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            DZ2T[(int64_t)(32 * t + drow(4 * g + j, lane)) * B + r] = (uint16_t)dzb[4 * t + g][j];
+        }
+      }
+    f32x16 dh[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) dh[t] = zero16();
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) dh[t] = mfma(L.F2B[t][s][lane], dzb[s], dh[t]);
+    if (valid) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const float v = z1[t][i] > 0.0f ? dh[t][i] : 0.0f;
+          DZ1T[(int64_t)(32 * t + drow(i, lane)) * B + r] = f2bf(v);
+        }
+    }
+  }
+  lacc = sgs_wave_sum_d(lacc);
+  if (lane == 0) s_red[wave] = lacc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kWaves; ++w) t += s_red[w];
+    loss_partial[blockIdx.x] = t;
+  }
+}
+
+// Training, pass 2: split-K GEMMs over the batch.
+//   dW2^T [128 out][128 in] = DZ2T [128][B] . H1 [B][128]
+//   dW1^T [128 out][ 64 in] = DZ1T [128][B] . X  [B][64]
+// Wave w owns output rows 32w..32w+31 of both (4 + 2 tiles of 32 x 32).
+// Block b covers batch rows [b*chunk, (b+1)*chunk).  Partials [blocks][24][32][32].
+__global__ void __launch_bounds__(kThreads)
+k_mlp_wgrad(int64_t B, int64_t chunk, const uint16_t *__restrict__ XT,
+            const uint16_t *__restrict__ H1T, const uint16_t *__restrict__ DZ2T,
+            const uint16_t *__restrict__ DZ1T, float *__restrict__ partial) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  f32x16 acc[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) acc[k] = zero16();
+  const int64_t k0 = (int64_t)blockIdx.x * chunk;
+  const int64_t k1 = min(B, k0 + chunk);
+  const int row = 32 * wave + (lane & 31);
+  for (int64_t kb = k0; kb < k1; kb += 8) {
+    const int64_t k = kb + 4 * (lane >> 5);
+    bf16x4 a2, a1, bh[4], bx[2];
+    if (k + 3 < k1) {
+      a2 = *(const bf16x4 *)(DZ2T + (int64_t)row * B + k);
+      a1 = *(const bf16x4 *)(DZ1T + (int64_t)row * B + k);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) bh[u] = *(const bf16x4 *)(H1T + (int64_t)(32 * u + (lane & 31)) * B + k);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) bx[u] = *(const bf16x4 *)(XT + (int64_t)(32 * u + (lane & 31)) * B + k);
+    } else {
+      // ragged tail: element-wise with zero fill
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool ok = k + j < k1;
+        a2[j] = ok ? (short)DZ2T[(int64_t)row * B + k + j] : (short)0;
+        a1[j] = ok ? (short)DZ1T[(int64_t)row * B + k + j] : (short)0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) bh[u][j] = ok ? (short)H1T[(int64_t)(32 * u + (lane & 31)) * B + k + j] : (short)0;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) bx[u][j] = ok ? (short)XT[(int64_t)(32 * u + (lane & 31)) * B + k + j] : (short)0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = mfma(a2, bh[u], acc[u]);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) acc[4 + u] = mfma(a1, bx[u], acc[4 + u]);
+  }
+  float *dst = partial + (int64_t)blockIdx.x * 24 * 1024;
+#pragma unroll
+  for (int u = 0; u < 6; ++u) {
+    const int tileid = (u < 4) ? (wave * 4 + u) : (16 + wave * 2 + (u - 4));
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dst[(int64_t)tileid * 1024 + drow(i, lane) * 32 + (lane & 31)] = acc[u][i];
+  }
+}
+
+// Training, pass 3: fixed-order sums -> gradient of the flat parameter vector.
+//   blocks [0, 24): one weight tile each (sum over the GEMM partials);
+//   blocks [24, 24 + 385): bias / w3 entries as sums over the batch.
+__global__ void __launch_bounds__(kThreads)
+k_mlp_grad_finish(int64_t B, int nchunks, const float *__restrict__ partial,
+                  const uint16_t *__restrict__ H1T, const uint16_t *__restrict__ DZ2T,
+                  const uint16_t *__restrict__ DZ1T, const float *__restrict__ H2T,
+                  const float *__restrict__ df, float *__restrict__ g) {
+  const int b = blockIdx.x;
+  if (b < 24) {
+    for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
+      double s = 0.0;
+      for (int c = 0; c < nchunks; ++c) s += partial[((int64_t)c * 24 + b) * 1024 + e];
+      const int i = e >> 5, j = e & 31;  // tile row (out), column (in)
+      if (b < 16) {
+        const int out = 32 * (b >> 2) + i, in = 32 * (b & 3) + j;
+        g[kOffW2 + in * MH + out] = (float)s;
+      } else {
+        const int t = b - 16;
+        const int out = 32 * (t >> 1) + i, in = 32 * (t & 1) + j;
+        g[kOffW1 + in * MH + out] = (float)s;
+      }
+    }
+    return;
+  }
+  __shared__ double s_w[kThreads / 64];
+  const int k = b - 24;  // 0..127 db1, 128..255 db2, 256..383 dw3, 384 db3
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < B; r += blockDim.x) {
+    if (k < 128) s += (double)bf2f(DZ1T[(int64_t)k * B + r]);
+    else if (k < 256) s += (double)bf2f(DZ2T[(int64_t)(k - 128) * B + r]);
+    else if (k < 384) s += (double)df[r] * (double)H2T[(int64_t)(k - 256) * B + r];
+    else s += (double)df[r];
+  }
+  s = sgs_wave_sum_d(s);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) t += s_w[w];
+    if (k < 128) g[kOffB1 + k] = (float)t;
+    else if (k < 256) g[kOffB2 + (k - 128)] = (float)t;
+    else if (k < 384) g[kOffW3 + (k - 256)] = (float)t;
+    else g[kOffB3] = (float)t;
+  }
+  (void)H1T;
+}
+
+__global__ void k_mlp_loss_finish(int nb, const double *__restrict__ partial, int64_t B,
+                                  float *__restrict__ loss) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += partial[b];
+  loss[0] = (float)(s / (double)B);
+}
+
+// Adam on the FP32 master parameters.
+__global__ void k_adam(int count, float *__restrict__ w, float *__restrict__ m,
+                       float *__restrict__ v, const float *__restrict__ g, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const float gk = g[k];
+  const float mk = b1 * m[k] + (1.0f - b1) * gk;
+  const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+  m[k] = mk;
+  v[k] = vk;
+  w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+}  // namespace
+
+hipError_t launch_mlp_pack(sgs_ctx *c, const float *theta, void *packed) {
+  k_mlp_pack<<<sgs_blocks(kPacked, 256), 256, 0, c->stream>>>(theta, (bf16x4 *)packed);
+  return hipGetLastError();
+}
+
+int mlp_grid(int64_t rows) {
+  const int64_t tiles = (rows + 31) / 32;
+  const int64_t want = (tiles + kWaves - 1) / kWaves;
+  return (int)(want < 1024 ? (want < 1 ? 1 : want) : 1024);
+}
+
+hipError_t launch_mlp_rate_fwd(sgs_ctx *c, const void *packed, const float *theta,
+                               const float *params, const float *q, const uint64_t *stats,
+                               const uint8_t *hard, float *outR, float *fout) {
+  SgsProfScope ps(c, SGS_PROF_MLP_FWD);
+  const int nb = mlp_grid(c->n);
+  if (nb > c->red_tmp_words) return hipErrorInvalidValue;
+  k_mlp_rate_fwd<<<nb, kThreads, 0, c->stream>>>(c->n, c->npad, (const bf16x4 *)packed, theta,
+                                                 params, q, stats, hard, fout, c->red_tmp);
+  k_mlp_rate_finish<<<1, kThreads, 0, c->stream>>>(nb, c->red_tmp, c->n_hat, outR);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_rate_bwd(sgs_ctx *c, const void *packed, const float *theta,
+                               const float *params, const float *q, const uint64_t *stats,
+                               const uint8_t *hard, const float *soft, int mode, float weight,
+                               float *gparams, float *gqstep, float *gscore, float *gmask) {
+  SgsProfScope ps(c, SGS_PROF_MLP_BWD);
+  const int nb = mlp_grid(c->n);
+  if ((int64_t)nb * 64 > c->red_tmp_words) return hipErrorInvalidValue;
+  k_mlp_rate_bwd<<<nb, kThreads, 0, c->stream>>>(c->n, c->npad, c->n_hat, weight, c->tau, mode,
+                                                 (const bf16x4 *)packed, theta, params, q, stats,
+                                                 hard, soft, gparams, gscore, gmask, c->red_tmp);
+  k_mlp_q_finish<<<1, 64, 0, c->stream>>>(nb, c->red_tmp, gqstep);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_infer(sgs_ctx *c, const void *packed, const float *theta,
+                            const uint16_t *X, int64_t B, float *fout) {
+  SgsProfScope ps(c, SGS_PROF_MLP_FWD);
+  k_mlp_infer<<<mlp_grid(B), kThreads, 0, c->stream>>>(B, (const bf16x4 *)packed, theta, X, fout);
+  return hipGetLastError();
+}
+
+int64_t mlp_train_scratch_bytes(int64_t B) {
+  const int64_t chunks = (B + 2047) / 2048;
+  return B * (64 + 3 * 128) * 2 + B * 128 * 4 + B * 4 + chunks * 24 * 1024 * 4 + 4096 * 8 + 256;
+}
+
+hipError_t launch_mlp_train_step(sgs_ctx *c, float *theta, float *m, float *v, void *packed,
+                                 const uint16_t *X, const float *target, int64_t B, float lr,
+                                 int64_t step, float *loss, float *gtheta, void *scratch) {
+  SgsProfScope ps(c, SGS_PROF_MLP_TRAIN);
+  char *p = (char *)scratch;
+  auto take = [&](int64_t bytes) {
+    char *r = p;
+    p += (bytes + 255) / 256 * 256;
+    return (void *)r;
+  };
+  uint16_t *XT = (uint16_t *)take(B * 64 * 2);
+  uint16_t *H1T = (uint16_t *)take(B * 128 * 2);
+  uint16_t *DZ2T = (uint16_t *)take(B * 128 * 2);
+  uint16_t *DZ1T = (uint16_t *)take(B * 128 * 2);
+  float *H2T = (float *)take(B * 128 * 4);
+  float *df = (float *)take(B * 4);
+  const int64_t chunk = 2048;
+  const int nchunks = (int)((B + chunk - 1) / chunk);
+  float *part = (float *)take((int64_t)nchunks * 24 * 1024 * 4);
+  const int nb = mlp_grid(B);
+  double *lpart = (double *)take(4096 * 8);
+  if (nb > 4096) return hipErrorInvalidValue;
+  k_mlp_train_rows<<<nb, kThreads, 0, c->stream>>>(B, 2.0f / (float)B, (const bf16x4 *)packed,
+                                                   theta, X, target, XT, H1T, DZ2T, DZ1T, H2T,
+                                                   df, lpart);
+  k_mlp_loss_finish<<<1, 64, 0, c->stream>>>(nb, lpart, B, loss);
+  k_mlp_wgrad<<<nchunks, kThreads, 0, c->stream>>>(B, chunk, XT, H1T, DZ2T, DZ1T, part);
+  k_mlp_grad_finish<<<24 + 385, kThreads, 0, c->stream>>>(B, nchunks, part, H1T, DZ2T, DZ1T, H2T,
+                                                          df, gtheta);
+  if (lr != 0.0f) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = (float)(1.0 - pow(0.9, (double)step));
+    const float c2 = (float)(1.0 - pow(0.999, (double)step));
+    k_adam<<<sgs_blocks(kParams, 256), 256, 0, c->stream>>>(kParams, theta, m, v, gtheta, lr, b1,
+                                                           b2, eps, c1, c2);
+    k_mlp_pack<<<sgs_blocks(kPacked, 256), 256, 0, c->stream>>>(theta, (bf16x4 *)packed);
+  }
+  return hipGetLastError();
+}

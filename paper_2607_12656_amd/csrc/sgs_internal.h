@@ -145,6 +145,22 @@ hipError_t launch_blend_fwd(sgs_ctx *c, float *image, float *final_T, uint32_t *
                             uint64_t *eval_count);
 hipError_t launch_blend_bwd(sgs_ctx *c, const float *final_T, const uint32_t *last,
                             const float *dL_dimage);
+// mlp.hip
+int mlp_grid(int64_t rows);  // blocks of the row kernels (partials per block)
+int64_t mlp_train_scratch_bytes(int64_t B);
+hipError_t launch_mlp_pack(sgs_ctx *c, const float *theta, void *packed);
+hipError_t launch_mlp_rate_fwd(sgs_ctx *c, const void *packed, const float *theta,
+                               const float *params, const float *q, const uint64_t *stats,
+                               const uint8_t *hard, float *outR, float *fout);
+hipError_t launch_mlp_rate_bwd(sgs_ctx *c, const void *packed, const float *theta,
+                               const float *params, const float *q, const uint64_t *stats,
+                               const uint8_t *hard, const float *soft, int mode, float weight,
+                               float *gparams, float *gqstep, float *gscore, float *gmask);
+hipError_t launch_mlp_infer(sgs_ctx *c, const void *packed, const float *theta,
+                            const uint16_t *X, int64_t B, float *fout);
+hipError_t launch_mlp_train_step(sgs_ctx *c, float *theta, float *m, float *v, void *packed,
+                                 const uint16_t *X, const float *target, int64_t B, float lr,
+                                 int64_t step, float *loss, float *gtheta, void *scratch);
 // loss.hip
 hipError_t launch_l1(sgs_ctx *c, const float *image, const float *target, float scale,
                      float *loss, float *dimg);
