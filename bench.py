@@ -2,22 +2,27 @@
 """Benchmark of one RD step (forward + backward) of SpeedyGS's structural
 formation on one MI355X.
 
-Workload (the measured configuration): plain rate proxy, 1,000,000 Gaussians
-(clustered: 3-component mixture), one 1297x840 camera on the radius-4 ring,
-learned per-channel steps initialised to 2^-6, 20 % of the Gaussians pruned
-by a given mask, L1 distortion against a seeded random target,
-lambda = 2.5e-5.  Inputs are synthetic (seeded), resident in HBM before the
-timed region.
+Default workload (the measured configuration): plain rate proxy, 1,000,000
+Gaussians (clustered: 3-component mixture), one 1297x840 camera on the
+radius-4 ring, learned per-channel steps initialised to 2^-6, 20 % pruned by
+a given mask, L1 distortion against a seeded random target, lambda 2.5e-5,
+16x16 tiles.  `--workload c3`: 3,000,000 Gaussians, 8 views of 1600x1060,
+tile shape from the autotuner.  Inputs are synthetic (seeded) and resident
+in HBM before the timed region.
 
 A step = fake-quantize + mask + channel statistics, rate proxy, projection,
 depth sort, pair emission, tile sort, ranges, blend, L1, blend backward,
-projection backward, quantizer/mask backward.
+projection backward, quantizer/mask backward (all in libspeedygs kernels).
+The pair capacity is reserved once, so a step never synchronizes.
 
 Prints one JSON line: ms/step, Gaussian-pixel evaluations per second
 (E / step time, E = in-support (Gaussian, pixel) evaluations of the forward,
 the set the backward re-walks), the roofline of the dominant kernel group
-(HIP events on the library's stream over the timed region) and the FP64
-oracle timed on the host as a CPU baseline.
+(HIP events recorded on the library's stream around every kernel group over
+the timed region), the same step replayed from a HIP graph, the learned-rate
+step (MLP in the loop, forward + recompute backward) timed beside it, the
+MLP's training / inference throughput, and the FP64 oracle timed on the host
+as a CPU baseline.
 """
 from __future__ import annotations
 
@@ -33,23 +38,23 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 
-# Algorithmic work per unit ("Roofline model").
+# Algorithmic work per unit ("Kernels and their rooflines").
 NCH = 59
 FLOP_PER_EVAL_FWD = 24     # offsets 2, quadratic form 9, exp 2, alpha/T 5, colour 6
 FLOP_PER_EVAL_BWD = 60     # alpha recompute 15, T and dalpha 12, 10 gradients 23, back colour 10
+MLP_FLOP_PER_ROW = 2 * (64 * 128 + 128 * 128 + 128)
 
 
 def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int):
     """(bound, algorithmic amount per launch, unit) of one kernel group."""
     pix = V * W * H
     if g == "fakequant":
-        return "hbm", n * (NCH * 4 * 2 + 1 + 1 + 4), "B"      # y in, yhat out, mask in/out, soft
+        return "hbm", n * (NCH * 4 * 2 + 1 + 1 + 4), "B"
     if g == "preprocess":
         return "hbm", n * (NCH * 4 + 1) + V * n * (48 + 12), "B"
-    if g == "depth_sort":
-        return "hbm", V * n * 16, "B"
-    if g == "scan":
+    if g in ("depth_sort", "scan"):
         return "hbm", V * n * 16, "B"
     if g == "duplicate":
         return "hbm", V * n * 12 + P * 8, "B"
@@ -72,10 +77,21 @@ def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int):
     return "hbm", 0, "B"
 
 
-def cpu_baseline(sc, lam, budget_s: float):
-    """The FP64 oracle, as it stands, on the same workload: the full step
-    (forward + backward) on the same scene and camera.  Single-threaded."""
-    import numpy as np
+def roofline(g, ms, n, V, P, E, W, H):
+    bound, amount, unit = group_work(g, n, V, P, E, W, H)
+    dur = ms * 1e-3
+    if unit == "B":
+        achieved, peak, ru = amount / dur / 1e9, HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved, peak, ru = amount / dur / 1e12, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
+    return {"bound": bound, "kernel": g, "achieved": round(achieved, 3), "peak": peak,
+            "unit": ru, "frac": round(achieved / peak, 5), "traffic": None,
+            "algorithmic_per_launch": amount, "avg_launch_ms": round(ms, 4)}
+
+
+def cpu_baseline(sc, lam):
+    """The FP64 oracle, as it stands, on the same workload: one full step
+    (forward + backward) on the same scene and camera, single-threaded."""
     import oracle
     t0 = time.perf_counter()
     r = oracle.rd_step(sc.params, sc.qstep, sc.score, sc.given_mask, sc.cams, sc.width,
@@ -85,7 +101,7 @@ def cpu_baseline(sc, lam, budget_s: float):
     return {"value": E / dt, "unit": "Gaussian-pixel evals/s", "cores": 1, "kind": "oracle",
             "sample": f"one full RD step (fwd+bwd) of the measured workload, "
                       f"{E} evals in {dt:.1f} s, single thread",
-            "s_per_step": dt}
+            "s_per_step": round(dt, 3)}
 
 
 def main():
@@ -93,9 +109,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c2", choices=("c2", "c3"))
+    ap.add_argument("--tile", default=None, help="16x16 | 8x8 | 32x8 | auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=60.0)
+    ap.add_argument("--no-extras", action="store_true", help="skip graph / learned / MLP legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -112,50 +129,56 @@ def main():
     sc = synth.make_scene(args.workload)
     lam = 2.5e-5
     dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream(dev)
+    torch.cuda.set_stream(stream)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     params, q, score = t(sc.params), t(sc.qstep), t(sc.score)
     mask, target = t(sc.given_mask), t(sc.target)
-    ctx = Context(0)
-    rd = RDStep(ctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height)
-    def step(count=False):
+    ctx = Context(0, stream=stream)
+
+    def plain_step(rd, count=False):
         # the straight-through gradient is written in place over the render
         # gradient buffer (the C ABI allows grad_params == grad_qparams)
         rd.forward(params, q, score, target, lam, 0, mask, 0, 0, count_evals=count)
         rd.backward(params, q, 0)
 
-    # evaluation count of one step (deterministic)
+    tile_choice = args.tile or ("16x16" if args.workload == "c2" else "auto")
+    tune = None
+    if tile_choice == "auto":
+        from paper_2607_12656_amd import autotune
+        tune = autotune.tune(ctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height,
+                             plain_step, reps=2)
+        tile = tune["tile"]
+    else:
+        tile = tuple(int(v) for v in tile_choice.split("x"))
+    rd = RDStep(ctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height, tile=tile)
+
+    # evaluation count and pair count of one step (deterministic)
     rd.evals.zero_()
-    step(count=True)
+    plain_step(rd, count=True)
     torch.cuda.synchronize()
     E = int(rd.evals.item())
     P, _ = ctx.query()
+    ctx.reserve_pairs(P + P // 8 + 4096)      # no host synchronization inside a step
     for _ in range(args.warmup):
-        step()
+        plain_step(rd)
+    ctx.query()
     torch.cuda.synchronize()
     ctx.profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        plain_step(rd)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.profile_read()
     ctx.profile_enable(False)
+    ctx.query()                                # raises if the capacity overflowed
     ms = (t1 - t0) * 1e3 / args.steps
     value = E / (ms * 1e-3)
-
-    kernels = {}
-    for g, (tot, cnt) in prof.items():
-        if cnt:
-            kernels[g] = round(tot / cnt, 4)
+    kernels = {g: round(tot / cnt, 4) for g, (tot, cnt) in prof.items() if cnt}
     dom = max(kernels, key=kernels.get)
-    bound, amount, unit = group_work(dom, sc.n, sc.views, P, E, sc.width, sc.height)
-    dur = kernels[dom] * 1e-3
-    if unit == "B":
-        achieved, peak, ru = amount / dur / 1e9, HBM_PEAK_GBS, "GB/s"
-    else:
-        achieved, peak, ru = amount / dur / 1e12, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
-    roof = {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
-            "unit": ru, "frac": round(achieved / peak, 5), "traffic": None}
+    roof = roofline(dom, kernels[dom], sc.n, sc.views, P, E, sc.width, sc.height)
+
     line = {
         "metric": "RD-step ms/iter & Gaussian-pixel evals/s (fwd+bwd), learned vs plain rate",
         "value": round(value, 1), "unit": "Gaussian-pixel evals/s", "n_gpus": 1,
@@ -163,15 +186,119 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: plain RD step, {sc.n} Gaussians (clustered), "
-                               f"{sc.views} view {sc.width}x{sc.height}, 20% pruned, "
-                               f"lambda 2.5e-5, tile 16x16",
+                               f"{sc.views} view(s) {sc.width}x{sc.height}, 20% pruned, "
+                               f"lambda 2.5e-5, tile {tile[0]}x{tile[1]}",
                    "gaussians": sc.n, "views": sc.views, "width": sc.width,
-                   "height": sc.height, "pairs": P, "evals_per_step": E},
+                   "height": sc.height, "tile": f"{tile[0]}x{tile[1]}", "pairs": P,
+                   "evals_per_step": E},
         "roofline": roof,
         "kernel_ms": kernels,
     }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(sc, lam, args.cpu_budget)
+    if tune is not None:
+        line["autotune_ms"] = tune["ms"]
+
+    if not args.no_extras:
+        # the same step replayed from a HIP graph
+        ctx.graph_begin()
+        plain_step(rd)
+        graph = ctx.graph_end()
+        for _ in range(2):
+            graph.launch(stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.launch(stream)
+        torch.cuda.synchronize()
+        gms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ctx.query()
+        graph.close()
+        line["graph_ms_per_step"] = round(gms, 4)
+        line["graph_value"] = round(E / (gms * 1e-3), 1)
+
+        # learned rate in the loop: MLP forward + recompute backward replace
+        # the range proxy's gradient; the proxy is still evaluated (forward)
+        theta = torch.empty(24961, dtype=torch.float32, device=dev)
+        gen = torch.Generator(device="cpu").manual_seed(7)
+        theta.copy_((torch.rand(24961, generator=gen) * 2 - 1) * 0.2)
+        packed = torch.empty(98304 // 4, dtype=torch.int32, device=dev)
+        ctx.rate_mlp_pack(theta, packed)
+        Rl = torch.empty(1, dtype=torch.float32, device=dev)
+
+        def learned_step():
+            c = ctx
+            c.fakequant_prune(params, q, score, 0, mask, 0, 0, rd.qparams, rd.hard, rd.soft,
+                              rd.stats)
+            c.rate_proxy(rd.stats, q, 0.0, rd.rate3, None)
+            c.rate_mlp_fwd(packed, theta, params, q, rd.stats, rd.hard, Rl, None)
+            c.render_fwd(rd.qparams, rd.hard, rd.image, rd.final_T, rd.last, None)
+            c.l1_loss(rd.image, target, rd.loss, rd.dimage)
+            c.render_bwd(rd.qparams, rd.hard, rd.final_T, rd.last, rd.dimage, rd.grad_qparams,
+                         rd.grad_mask)
+            c.fakequant_prune_bwd(params, q, rd.soft, 0, None, None, rd.grad_qparams,
+                                  rd.grad_mask, rd.grad_qparams, rd.grad_q, rd.grad_score)
+            c.rate_mlp_bwd(packed, theta, params, q, rd.stats, rd.hard, rd.soft, 0, lam,
+                           rd.grad_qparams, rd.grad_q, rd.grad_score, None)
+
+        for _ in range(args.warmup):
+            learned_step()
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            learned_step()
+        torch.cuda.synchronize()
+        lms = (time.perf_counter() - t0) * 1e3 / args.steps
+        lprof = ctx.profile_read()
+        ctx.profile_enable(False)
+        ctx.query()
+        lk = {g: round(tot / cnt, 4) for g, (tot, cnt) in lprof.items() if cnt}
+        mf = lk.get("mlp_fwd", 0.0)
+        line["learned_rate"] = {
+            "ms_per_step": round(lms, 4), "value": round(E / (lms * 1e-3), 1),
+            "mlp_fwd_ms": mf, "mlp_bwd_ms": lk.get("mlp_bwd", 0.0),
+            "mlp_fwd_tflops": round(sc.n * MLP_FLOP_PER_ROW / (mf * 1e-3) / 1e12, 2) if mf else None,
+            "plain_ms_per_step": round(ms, 4)}
+
+        # MLP alone: one training step on 65,536 rows, inference over 3M rows
+        B = 65536
+        Xtr = torch.randint(0, 1 << 14, (B, 64), dtype=torch.int16, device=dev)
+        ttr = torch.rand(B, device=dev) * 100 + 200
+        m_ = torch.zeros_like(theta)
+        v_ = torch.zeros_like(theta)
+        g_ = torch.empty_like(theta)
+        lo = torch.empty(1, device=dev)
+        scratch = torch.empty(ctx.rate_mlp_train_scratch_bytes(B), dtype=torch.uint8, device=dev)
+        th2 = theta.clone()
+        for s in range(1, 4):
+            ctx.rate_mlp_train_step(th2, m_, v_, packed, Xtr, ttr, B, 1e-4, s, lo, g_, scratch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(4, 4 + args.steps):
+            ctx.rate_mlp_train_step(th2, m_, v_, packed, Xtr, ttr, B, 1e-4, s, lo, g_, scratch)
+        torch.cuda.synchronize()
+        tms = (time.perf_counter() - t0) * 1e3 / args.steps
+        Ni = 3_000_000
+        Xin = torch.randint(0, 1 << 14, (Ni, 64), dtype=torch.int16, device=dev)
+        fo = torch.empty(Ni, device=dev)
+        ctx.rate_mlp_pack(theta, packed)
+        ctx.rate_mlp_infer(packed, theta, Xin, Ni, fo)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.rate_mlp_infer(packed, theta, Xin, Ni, fo)
+        torch.cuda.synchronize()
+        ims = (time.perf_counter() - t0) * 1e3 / args.steps
+        line["mlp"] = {
+            "train_step_ms_65536_rows": round(tms, 4),
+            "train_tflops": round(3 * B * MLP_FLOP_PER_ROW / (tms * 1e-3) / 1e12, 2),
+            "infer_ms_3M_rows": round(ims, 4),
+            "infer_tflops": round(Ni * MLP_FLOP_PER_ROW / (ims * 1e-3) / 1e12, 2),
+            "infer_mfma_frac": round(Ni * MLP_FLOP_PER_ROW / (ims * 1e-3) / 1e12
+                                     / BF16_MFMA_PEAK_TFLOPS, 4)}
+        del Xin, fo, Xtr, scratch
+
+    if not args.no_cpu_baseline and args.workload == "c2":
+        line["cpu_baseline"] = cpu_baseline(sc, lam)
     print(json.dumps(line), flush=True)
 
 

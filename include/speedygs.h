@@ -155,9 +155,29 @@ sgs_status sgs_fakequant_prune_bwd(sgs_ctx *ctx, const float *params, const floa
                                    float *grad_params, float *grad_qstep, float *grad_score);
 
 /* Host-side query (synchronizes the stream): pairs of the last render and the
- * device flags word of `stats` (may be NULL). */
+ * device flags word of `stats` (may be NULL).  Returns SGS_EINVAL when the
+ * flags report an invalid step size, SGS_ECAPACITY (once, then cleared) when
+ * a render since the last query exceeded a reserved pair capacity; the
+ * caller reserves more and reruns the step. */
 sgs_status sgs_query(sgs_ctx *ctx, const uint64_t *stats, int64_t *pairs_last,
                      uint64_t *flags);
+
+/* Fix the (tile, Gaussian) pair capacity (allocating it now; 0 returns to
+ * the default mode).  With a fixed capacity sgs_render_fwd never
+ * synchronizes: the pair count stays on the device, grids are sized by the
+ * capacity, pairs beyond it are dropped and reported by sgs_query. Required
+ * for graph capture.  Synchronizes the stream. */
+sgs_status sgs_reserve_pairs(sgs_ctx *ctx, int64_t capacity);
+
+/* HIP-graph capture of the calls made on this context between begin and end
+ * (any of the entry points above except set_scene / reserve_pairs / query /
+ * profile_read, which synchronize).  Needs a reserved pair capacity and a
+ * non-null stream.  The graph replays the same pointers and sizes. */
+typedef struct sgs_graph sgs_graph;
+sgs_status sgs_graph_begin(sgs_ctx *ctx);
+sgs_status sgs_graph_end(sgs_ctx *ctx, sgs_graph **out);
+sgs_status sgs_graph_launch(sgs_graph *graph, void *hip_stream);
+void sgs_graph_destroy(sgs_graph *graph);
 
 /* Inspection for tests: copy the last render's structure into caller device
  * buffers.  tile_ids/vals: uint32 [cap] (sorted pairs), ranges uint32

@@ -64,6 +64,11 @@ _SIGS = {
     "sgs_copy_splat_grads": [P, P],
     "sgs_profile_enable": [P, I32],
     "sgs_profile_read": [P, P, P],
+    "sgs_reserve_pairs": [P, I64],
+    "sgs_graph_begin": [P],
+    "sgs_graph_end": [P, C.POINTER(P)],
+    "sgs_graph_launch": [P, P],
+    "sgs_graph_destroy": [P],
     "sgs_rate_mlp_pack": [P, P, P],
     "sgs_rate_mlp_fwd": [P, P, P, P, P, P, P, P, P],
     "sgs_rate_mlp_bwd": [P, P, P, P, P, P, P, P, I32, F32, P, P, P, P],
@@ -93,7 +98,7 @@ def lib(path: str | None = None):
     for name, args in _SIGS.items():
         f = getattr(L, name)
         f.argtypes = args
-        f.restype = {"sgs_last_error": C.c_char_p, "sgs_destroy": None,
+        f.restype = {"sgs_last_error": C.c_char_p, "sgs_destroy": None, "sgs_graph_destroy": None,
                      "sgs_rate_mlp_train_scratch_bytes": C.c_int64}.get(name, C.c_int)
     if path is None:
         _lib = L
@@ -113,6 +118,29 @@ def cameras(cams: np.ndarray):
     arr = (sgs_camera * cams.shape[0])()
     C.memmove(arr, cams.ctypes.data, cams.nbytes)
     return arr
+
+
+class Graph:
+    """An instantiated HIP graph of captured library calls."""
+
+    def __init__(self, L, h):
+        self.L, self.h = L, h
+
+    def launch(self, stream):
+        st = self.L.sgs_graph_launch(self.h, P(stream.cuda_stream))
+        if st != SGS_OK:
+            raise SgsError(st, "graph launch failed")
+
+    def close(self):
+        if self.h:
+            self.L.sgs_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Context:
@@ -204,6 +232,18 @@ class Context:
 
     def copy_splat_grads(self, out):
         self._check(self.L.sgs_copy_splat_grads(self.h, _ptr(out)), self.h)
+
+    # ---- device-side pair count and graph capture ----------------------------
+    def reserve_pairs(self, capacity: int):
+        self._check(self.L.sgs_reserve_pairs(self.h, capacity), self.h)
+
+    def graph_begin(self):
+        self._check(self.L.sgs_graph_begin(self.h), self.h)
+
+    def graph_end(self) -> "Graph":
+        g = P()
+        self._check(self.L.sgs_graph_end(self.h, C.byref(g)), self.h)
+        return Graph(self.L, g)
 
     # ---- learned rate estimator --------------------------------------------
     def rate_mlp_pack(self, theta, packed):

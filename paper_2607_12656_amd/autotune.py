@@ -1,0 +1,67 @@
+"""Tile-shape autotuner for the RD step.
+
+The support rule is pixel-exact, so every candidate tile shape renders the
+same image and gradients (the tiles only change the work decomposition):
+the tuner may pick on speed alone.  Each candidate is timed over whole
+forward + backward steps with HIP events on the step's stream; results are
+cached per (device, N, views, width, height) in a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+CANDIDATES = ((16, 16), (8, 8), (32, 8))
+
+
+def _key(dev_name, n, V, W, H):
+    return f"{dev_name}|n{n}|v{V}|{W}x{H}"
+
+
+def tune(ctx, n, npad, n_hat, cams, width, height, step_fn, reps: int = 3,
+         cache_path: str | None = None, candidates=CANDIDATES) -> dict:
+    """step_fn(rd) runs one full step on an RDStep bound to ctx.
+    Returns {"tile": (tw, th), "ms": {"16x16": ..., ...}, "cached": bool}."""
+    import torch
+
+    from .rd import RDStep
+    dev_name = torch.cuda.get_device_name(ctx.device)
+    key = _key(dev_name, n, cams.shape[0], width, height)
+    if cache_path and os.path.exists(cache_path):
+        try:
+            cache = json.load(open(cache_path))
+        except (OSError, ValueError):
+            cache = {}
+        if key in cache:
+            e = cache[key]
+            return {"tile": tuple(e["tile"]), "ms": e["ms"], "cached": True}
+    timings = {}
+    stream = torch.cuda.current_stream(ctx.device)
+    for tile in candidates:
+        rd = RDStep(ctx, n, npad, n_hat, cams, width, height, tile=tile)
+        step_fn(rd)                      # warm-up (allocates the pair buffers)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            step_fn(rd)
+        b.record(stream)
+        b.synchronize()
+        timings[f"{tile[0]}x{tile[1]}"] = a.elapsed_time(b) / reps
+        del rd
+    best = min(timings, key=timings.get)
+    tile = tuple(int(v) for v in best.split("x"))
+    if cache_path:
+        cache = {}
+        if os.path.exists(cache_path):
+            try:
+                cache = json.load(open(cache_path))
+            except (OSError, ValueError):
+                cache = {}
+        cache[key] = {"tile": list(tile), "ms": timings}
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(tmp, cache_path)
+    return {"tile": tile, "ms": timings, "cached": False}

@@ -196,7 +196,10 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   SGS_ALLOC(c->offsets, vn + 1);
   SGS_ALLOC(c->splat_grad, vn * SGS_SGRAD);
   SGS_ALLOC(c->ranges, c->total_tiles);
-  SGS_ALLOC(c->d_pairs_total, 1);
+  SGS_ALLOC(c->d_pairs_total, 4);
+  e = hipMemset(c->d_pairs_total, 0, 4 * sizeof(uint32_t));
+  if (e != hipSuccess) { free_scene(c); return hip_fail(c, e, "set_scene clear"); }
+  c->fixed_cap = false;
   const int64_t red_q = quant_partial_words(n);
   const int64_t red_l1 = (int64_t)views * 3 * width * height / 2048 + 64;
   const int64_t red_mlp = (int64_t)mlp_grid(n) * 64;
@@ -256,13 +259,15 @@ sgs_status sgs_render_fwd(sgs_ctx *c, const float *qparams, const uint8_t *hard_
     return fail(c, SGS_EINVAL, "render_fwd: null pointer");
   SGS_HIP(launch_preprocess(c, qparams, hard_mask), "render_fwd preprocess");
   SGS_HIP(launch_depth_order(c), "render_fwd depth order");
-  SGS_HIP(hipMemcpyAsync(c->h_pairs_total, c->d_pairs_total, sizeof(uint32_t),
-                         hipMemcpyDeviceToHost, c->stream),
-          "render_fwd pair count");
-  SGS_HIP(hipStreamSynchronize(c->stream), "render_fwd pair count");
-  c->pairs = *c->h_pairs_total;
-  hipError_t e = grow_pairs(c, c->pairs);
-  if (e != hipSuccess) return hip_fail(c, e, "render_fwd pair buffers");
+  if (!c->fixed_cap) {
+    SGS_HIP(hipMemcpyAsync(c->h_pairs_total, c->d_pairs_total, sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, c->stream),
+            "render_fwd pair count");
+    SGS_HIP(hipStreamSynchronize(c->stream), "render_fwd pair count");
+    c->pairs = *c->h_pairs_total;
+    hipError_t e = grow_pairs(c, c->pairs);
+    if (e != hipSuccess) return hip_fail(c, e, "render_fwd pair buffers");
+  }
   SGS_HIP(launch_bin_pairs(c), "render_fwd binning");
   SGS_HIP(launch_blend_fwd(c, image, final_T, last, eval_count), "render_fwd blend");
   c->rendered = true;
@@ -317,14 +322,101 @@ sgs_status sgs_query(sgs_ctx *c, const uint64_t *stats, int64_t *pairs_last, uin
   if (!c) return SGS_EINVAL;
   SGS_HIP(hipSetDevice(c->device), "hipSetDevice");
   SGS_HIP(hipStreamSynchronize(c->stream), "query sync");
-  if (pairs_last) *pairs_last = c->pairs;
+  bool overflow = false;
+  if (c->fixed_cap && c->d_pairs_total) {
+    uint32_t counts[3];
+    SGS_HIP(hipMemcpy(counts, c->d_pairs_total, sizeof(counts), hipMemcpyDeviceToHost),
+            "query counts");
+    c->pairs = counts[1];
+    overflow = counts[2] != 0;
+    if (pairs_last) *pairs_last = counts[0];
+    if (overflow) {
+      const uint32_t zero = 0;
+      SGS_HIP(hipMemcpy(c->d_pairs_total + 2, &zero, sizeof(zero), hipMemcpyHostToDevice),
+              "query clear");
+    }
+  } else if (pairs_last) {
+    *pairs_last = c->pairs;
+  }
   if (flags) {
     *flags = 0;
     if (stats)
       SGS_HIP(hipMemcpy(flags, stats + 119, sizeof(uint64_t), hipMemcpyDeviceToHost), "query flags");
   }
   if (flags && (*flags & 1ull)) return fail(c, SGS_EINVAL, "a step size q_j was <= 0 or not finite");
+  if (overflow)
+    return fail(c, SGS_ECAPACITY, "pair capacity %lld exceeded (%lld pairs): reserve more and rerun",
+                (long long)c->cap_limit, (long long)(pairs_last ? *pairs_last : 0));
   return SGS_OK;
+}
+
+sgs_status sgs_reserve_pairs(sgs_ctx *c, int64_t capacity) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "reserve_pairs: set_scene first");
+  if (capacity < 0 || capacity >= ((int64_t)1 << 32) - 1)
+    return fail(c, SGS_EINVAL, "reserve_pairs: capacity out of range");
+  if (c->capturing) return fail(c, SGS_ESTATE, "reserve_pairs: not during graph capture");
+  SGS_HIP(hipSetDevice(c->device), "hipSetDevice");
+  SGS_HIP(hipStreamSynchronize(c->stream), "reserve sync");
+  if (capacity == 0) {
+    c->fixed_cap = false;
+    return SGS_OK;
+  }
+  hipError_t e = grow_pairs(c, capacity);
+  if (e != hipSuccess) return hip_fail(c, e, "reserve_pairs");
+  SGS_HIP(hipMemset(c->d_pairs_total, 0, 4 * sizeof(uint32_t)), "reserve clear");
+  c->cap_limit = capacity;
+  c->fixed_cap = true;
+  return SGS_OK;
+}
+
+struct sgs_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+sgs_status sgs_graph_begin(sgs_ctx *c) {
+  if (!c) return SGS_EINVAL;
+  if (!c->fixed_cap) return fail(c, SGS_ESTATE, "graph_begin: reserve a pair capacity first");
+  if (!c->stream) return fail(c, SGS_ESTATE, "graph_begin: the null stream cannot be captured");
+  if (c->capturing) return fail(c, SGS_ESTATE, "graph_begin: already capturing");
+  SGS_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "graph_begin");
+  c->capturing = true;
+  return SGS_OK;
+}
+
+sgs_status sgs_graph_end(sgs_ctx *c, sgs_graph **out) {
+  if (!c || !out) return SGS_EINVAL;
+  *out = nullptr;
+  if (!c->capturing) return fail(c, SGS_ESTATE, "graph_end: not capturing");
+  c->capturing = false;
+  sgs_graph *g = new (std::nothrow) sgs_graph();
+  if (!g) return SGS_ENOMEM;
+  hipError_t e = hipStreamEndCapture(c->stream, &g->graph);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(c, e, "graph_end capture");
+  }
+  e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g->graph);
+    delete g;
+    return hip_fail(c, e, "graph_end instantiate");
+  }
+  *out = g;
+  return SGS_OK;
+}
+
+sgs_status sgs_graph_launch(sgs_graph *g, void *hip_stream) {
+  if (!g || !g->exec) return SGS_EINVAL;
+  return hipGraphLaunch(g->exec, (hipStream_t)hip_stream) == hipSuccess ? SGS_OK : SGS_EHIP;
+}
+
+void sgs_graph_destroy(sgs_graph *g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
 }
 
 sgs_status sgs_rate_mlp_pack(sgs_ctx *c, const float *theta, void *packed) {

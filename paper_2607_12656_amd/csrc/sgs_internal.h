@@ -67,8 +67,11 @@ struct sgs_ctx {
   uint32_t *scan_tmp = nullptr;   int64_t scan_tmp_words = 0;
   uint32_t *sort_hist = nullptr;  int64_t sort_hist_words = 0;
   double *red_tmp = nullptr;      int64_t red_tmp_words = 0;
-  uint32_t *d_pairs_total = nullptr;  // device copy of the pair count
+  uint32_t *d_pairs_total = nullptr;  // [0] pair count, [1] count clamped to capacity, [2] overflow
   uint32_t *h_pairs_total = nullptr;  // pinned host mirror
+  bool fixed_cap = false;             // pair capacity fixed by the caller: no host sync per step
+  int64_t cap_limit = 0;              // the reserved capacity (buffers may be larger)
+  bool capturing = false;             // the stream is being captured into a HIP graph
 
   // kernel-group timing
   struct ProfRec {
@@ -97,7 +100,7 @@ struct SgsProfScope {
     return e;
   }
   SgsProfScope(sgs_ctx *ctx, int group) : c(ctx), g(group) {
-    if (c->prof) {
+    if (c->prof && !c->capturing) {
       a = get(c);
       if (a) (void)hipEventRecord(a, c->stream);
     }
@@ -137,7 +140,7 @@ hipError_t launch_exclusive_scan(sgs_ctx *c, const uint32_t *in, uint32_t *out,
 // [0, bits); ping-pongs between buffer 0 and 1; returns the buffer index that
 // holds the result in *which.
 hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2],
-                             int64_t count, int bits, int *which);
+                             int64_t count, int bits, int *which, const uint32_t *dcount);
 hipError_t launch_bin_pairs(sgs_ctx *c);   // depth order -> pairs -> tile sort -> ranges
 hipError_t launch_depth_order(sgs_ctx *c); // depth sort + scan (writes d_pairs_total)
 // blend.hip

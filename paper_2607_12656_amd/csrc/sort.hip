@@ -117,13 +117,19 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
 }
 
 __global__ void __launch_bounds__(kThreads)
-k_radix_hist(const uint32_t *__restrict__ keys, int64_t count, int shift,
-             uint32_t *__restrict__ hist, int64_t nb) {
+k_radix_hist(const uint32_t *__restrict__ keys, int64_t count_static,
+             const uint32_t *__restrict__ dcount, int shift, uint32_t *__restrict__ hist,
+             int64_t nb) {
   __shared__ uint32_t s_hist[256];
+  const int64_t count = dcount ? (int64_t)*dcount : count_static;
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  if (base >= count) {  // grid sized for a capacity, not the live count
+    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = 0;
+    return;
+  }
   s_hist[threadIdx.x] = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int64_t base = (int64_t)blockIdx.x * kTile;
   for (int r = 0; r < kItems; ++r) {
     const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
     const bool valid = i < count;
@@ -137,15 +143,18 @@ k_radix_hist(const uint32_t *__restrict__ keys, int64_t count, int shift,
 
 __global__ void __launch_bounds__(kThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-                uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t count,
-                int shift, const uint32_t *__restrict__ hist_scanned, int64_t nb) {
+                uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                int64_t count_static, const uint32_t *__restrict__ dcount, int shift,
+                const uint32_t *__restrict__ hist_scanned, int64_t nb) {
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_run[256];
   __shared__ uint32_t s_wc[kWaves][256];
+  const int64_t count = dcount ? (int64_t)*dcount : count_static;
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  if (base >= count) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   s_base[threadIdx.x] = hist_scanned[(int64_t)threadIdx.x * nb + blockIdx.x];
   s_run[threadIdx.x] = 0;
-  const int64_t base = (int64_t)blockIdx.x * kTile;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int r = 0; r < kItems; ++r) {
 #pragma unroll
@@ -199,12 +208,14 @@ __global__ void k_gather_touched(const uint32_t *__restrict__ order,
 __global__ void k_duplicate(const uint32_t *__restrict__ order, const uint32_t *__restrict__ touched,
                             const uint32_t *__restrict__ offsets, const float4 *__restrict__ rec,
                             int64_t count, int64_t n, int TW, int TH, int GW,
-                            int64_t tiles_per_view, uint32_t *__restrict__ tile_key,
+                            int64_t tiles_per_view, int64_t cap, uint32_t *__restrict__ tile_key,
                             uint32_t *__restrict__ pair_val) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= count) return;
   const uint32_t s = order[k];
   if (touched[s] == 0) return;
+  // beyond the pair capacity (reported by the count clamp): drop the splat
+  if ((int64_t)offsets[k] + touched[s] > cap) return;
   const float4 r = rec[3 * (int64_t)s + 1];
   const uint32_t sx = __float_as_uint(r.z), sy = __float_as_uint(r.w);
   const int x0 = sx & 0xFFFF, x1 = sx >> 16, y0 = sy & 0xFFFF, y1 = sy >> 16;
@@ -225,13 +236,23 @@ __global__ void k_zero_ranges(uint2 *__restrict__ ranges, int64_t tiles) {
   if (t < tiles) ranges[t] = make_uint2(0, 0);
 }
 
-__global__ void k_ranges(const uint32_t *__restrict__ tile_key, int64_t P,
-                         uint2 *__restrict__ ranges) {
+__global__ void k_ranges(const uint32_t *__restrict__ tile_key, int64_t P_static,
+                         const uint32_t *__restrict__ dcount, uint2 *__restrict__ ranges) {
+  const int64_t P = dcount ? (int64_t)*dcount : P_static;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= P) return;
   const uint32_t t = tile_key[e];
   if (e == 0 || tile_key[e - 1] != t) ranges[t].x = (uint32_t)e;
   if (e == P - 1 || tile_key[e + 1] != t) ranges[t].y = (uint32_t)(e + 1);
+}
+
+// counts[0] = total pairs (from the scan); counts[1] = min(total, cap);
+// counts[2] |= 1 when the total exceeded the capacity.
+__global__ void k_clamp_count(uint32_t *__restrict__ counts, int64_t cap) {
+  if (threadIdx.x != 0) return;
+  const int64_t total = counts[0];
+  counts[1] = (uint32_t)(total < cap ? total : cap);
+  if (total > cap) counts[2] |= 1u;
 }
 
 }  // namespace
@@ -270,7 +291,7 @@ hipError_t launch_exclusive_scan(sgs_ctx *c, const uint32_t *in, uint32_t *out, 
 }
 
 hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2], int64_t count,
-                             int bits, int *which) {
+                             int bits, int *which, const uint32_t *dcount) {
   int cur = 0;
   const int64_t nb = (count + kTile - 1) / kTile;
   if (count <= 1 || bits <= 0) {
@@ -281,16 +302,16 @@ hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2], i
   const int64_t snb = (hwords + kTile - 1) / kTile;
   if (hwords + 1 > c->sort_hist_words || snb > c->scan_tmp_words) return hipErrorInvalidValue;
   for (int shift = 0; shift < bits; shift += 8) {
-    k_radix_hist<<<(unsigned)nb, kThreads, 0, c->stream>>>(keys[cur], count, shift, c->sort_hist,
-                                                           nb);
+    k_radix_hist<<<(unsigned)nb, kThreads, 0, c->stream>>>(keys[cur], count, dcount, shift,
+                                                           c->sort_hist, nb);
     // in-place exclusive scan of the digit-major histogram
     k_scan_reduce<<<(unsigned)snb, kThreads, 0, c->stream>>>(c->sort_hist, hwords, c->scan_tmp);
     k_scan_sums<<<1, kThreads, 0, c->stream>>>(c->scan_tmp, snb, nullptr, nullptr);
     k_scan_down<<<(unsigned)snb, kThreads, 0, c->stream>>>(c->sort_hist, hwords, c->scan_tmp,
                                                            c->sort_hist);
     k_radix_scatter<<<(unsigned)nb, kThreads, 0, c->stream>>>(keys[cur], vals[cur], keys[cur ^ 1],
-                                                              vals[cur ^ 1], count, shift,
-                                                              c->sort_hist, nb);
+                                                              vals[cur ^ 1], count, dcount,
+                                                              shift, c->sort_hist, nb);
     cur ^= 1;
   }
   *which = cur;
@@ -302,7 +323,7 @@ hipError_t launch_depth_order(sgs_ctx *c) {
   int which = 0;
   {
     SgsProfScope ps(c, SGS_PROF_DEPTH_SORT);
-    hipError_t e = launch_radix_sort(c, c->depth_key, c->depth_val, c->vn, 32, &which);
+    hipError_t e = launch_radix_sort(c, c->depth_key, c->depth_val, c->vn, 32, &which, nullptr);
     if (e != hipSuccess) return e;
   }
   c->depth_sorted_buf = which;
@@ -314,21 +335,28 @@ hipError_t launch_depth_order(sgs_ctx *c) {
   return launch_exclusive_scan(c, tmp, c->offsets, c->vn, c->d_pairs_total);
 }
 
+// Pairs -> stable tile sort -> ranges.  With a fixed pair capacity the pair
+// count never leaves the device: grids are sized by the capacity and every
+// kernel reads the live count (clamped to the capacity, overflow flagged).
 hipError_t launch_bin_pairs(sgs_ctx *c) {
-  const int64_t P = c->pairs;
+  const bool dev = c->fixed_cap;
+  const int64_t cap = dev ? c->cap_limit : c->pair_cap;
+  const int64_t P = dev ? cap : c->pairs;
+  const uint32_t *dcount = dev ? c->d_pairs_total + 1 : nullptr;
   const uint32_t *order = c->depth_val[c->depth_sorted_buf];
   {
     SgsProfScope ps(c, SGS_PROF_DUPLICATE);
+    if (dev) k_clamp_count<<<1, 64, 0, c->stream>>>(c->d_pairs_total, cap);
     k_duplicate<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(
         order, c->touched, c->offsets, c->rec, c->vn, c->n, c->TW, c->TH, c->GW,
-        c->tiles_per_view, c->tile_key[0], c->pair_val[0]);
+        c->tiles_per_view, cap, c->tile_key[0], c->pair_val[0]);
   }
   int bits = 0;
   while (((int64_t)1 << bits) < c->total_tiles) ++bits;
   int which = 0;
   {
     SgsProfScope ps(c, SGS_PROF_TILE_SORT);
-    hipError_t e = launch_radix_sort(c, c->tile_key, c->pair_val, P, bits, &which);
+    hipError_t e = launch_radix_sort(c, c->tile_key, c->pair_val, P, bits, &which, dcount);
     if (e != hipSuccess) return e;
   }
   c->pair_sorted_buf = which;
@@ -336,6 +364,7 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
   k_zero_ranges<<<sgs_blocks(c->total_tiles, 256), 256, 0, c->stream>>>(c->ranges,
                                                                        c->total_tiles);
   if (P > 0)
-    k_ranges<<<sgs_blocks(P, 256), 256, 0, c->stream>>>(c->tile_key[which], P, c->ranges);
+    k_ranges<<<sgs_blocks(P, 256), 256, 0, c->stream>>>(c->tile_key[which], P, dcount,
+                                                        c->ranges);
   return hipGetLastError();
 }
