@@ -113,6 +113,11 @@ def main():
     ap.add_argument("--tile", default=None, help="16x16 | 8x8 | 32x8 | auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip graph / learned / MLP legs")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 256 MiB device copy first (scale for HBM counters)")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
+                    help="rocprofv3 HBM bytes per launch (used only while the kernel source "
+                         "is unchanged since the counters were taken)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -135,6 +140,12 @@ def main():
     params, q, score = t(sc.params), t(sc.qstep), t(sc.score)
     mask, target = t(sc.given_mask), t(sc.target)
     ctx = Context(0, stream=stream)
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def plain_step(rd, count=False):
         # the straight-through gradient is written in place over the render
@@ -178,6 +189,16 @@ def main():
     kernels = {g: round(tot / cnt, 4) for g, (tot, cnt) in prof.items() if cnt}
     dom = max(kernels, key=kernels.get)
     roof = roofline(dom, kernels[dom], sc.n, sc.views, P, E, sc.width, sc.height)
+    if args.traffic and os.path.exists(args.traffic):
+        import hashlib
+        tr = json.load(open(args.traffic))
+        ent = tr.get(f"{args.workload}:{dom}")
+        if ent:
+            src = os.path.join(ROOT, ent["kernel_file"])
+            cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+            if cur == ent["kernel_sha256_16"]:
+                roof["traffic"] = ent["bytes_per_launch"]
+                roof["traffic_source"] = ent["source"] + " (profiles/hbm_traffic_*.md)"
 
     line = {
         "metric": "RD-step ms/iter & Gaussian-pixel evals/s (fwd+bwd), learned vs plain rate",

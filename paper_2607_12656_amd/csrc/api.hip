@@ -85,7 +85,7 @@ hipError_t grow_pairs(sgs_ctx *c, int64_t P) {
     if (e != hipSuccess) return e;
   }
   const int64_t nb = (cap + 4095) / 4096;
-  const int64_t hist = nb * 256 + 1;
+  const int64_t hist = 2 * nb * 256 + 1;   // raw and scanned digit counts
   const int64_t scan = (hist + 4095) / 4096 + 1;
   hipError_t e = ensure_tmp(c, scan > c->scan_tmp_words ? scan : c->scan_tmp_words, hist);
   if (e != hipSuccess) return e;
@@ -209,7 +209,7 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   c->red_tmp_words = red;
 #undef SGS_ALLOC
   const int64_t nb = (vn + 4095) / 4096;
-  const int64_t hist = nb * 256 + 1;
+  const int64_t hist = 2 * nb * 256 + 1;   // raw and scanned digit counts
   const int64_t scan = ((hist > vn ? hist : vn) + 4095) / 4096 + 1;
   e = ensure_tmp(c, scan, hist);
   if (e != hipSuccess) { free_scene(c); return hip_fail(c, e, "set_scene alloc"); }

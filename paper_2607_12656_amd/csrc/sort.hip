@@ -128,12 +128,20 @@ k_radix_hist(const uint32_t *__restrict__ keys, int64_t count_static,
     return;
   }
   s_hist[threadIdx.x] = 0;
+  // all loads of the block in flight at once
+  uint32_t kr[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+    kr[r] = i < count ? keys[i] : 0u;
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63;
+#pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
     const bool valid = i < count;
-    const uint32_t d = valid ? (keys[i] >> shift) & 0xFFu : 0u;
+    const uint32_t d = (kr[r] >> shift) & 0xFFu;
     const uint64_t m = match_digit(d, valid);
     if (valid && (__ffsll((long long)m) - 1) == lane) atomicAdd(&s_hist[d], (uint32_t)__popcll(m));
   }
@@ -141,32 +149,50 @@ k_radix_hist(const uint32_t *__restrict__ keys, int64_t count_static,
   hist[(int64_t)threadIdx.x * nb + blockIdx.x] = s_hist[threadIdx.x];
 }
 
+// Scatter of one pass.  The block first places its elements in LDS in digit
+// order (stable), then writes each digit's run to its global position with
+// consecutive threads on consecutive addresses (coalesced).
 __global__ void __launch_bounds__(kThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                 uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                 int64_t count_static, const uint32_t *__restrict__ dcount, int shift,
-                const uint32_t *__restrict__ hist_scanned, int64_t nb) {
+                const uint32_t *__restrict__ hist_raw, const uint32_t *__restrict__ hist_scanned,
+                int64_t nb) {
   __shared__ uint32_t s_base[256];
+  __shared__ uint32_t s_loff[256];
   __shared__ uint32_t s_run[256];
   __shared__ uint32_t s_wc[kWaves][256];
+  __shared__ uint32_t s_wave[kWaves];
+  __shared__ uint32_t s_key[kTile];
+  __shared__ uint32_t s_val[kTile];
   const int64_t count = dcount ? (int64_t)*dcount : count_static;
   const int64_t base = (int64_t)blockIdx.x * kTile;
   if (base >= count) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   s_base[threadIdx.x] = hist_scanned[(int64_t)threadIdx.x * nb + blockIdx.x];
+  {
+    uint32_t tot;
+    s_loff[threadIdx.x] =
+        block_exclusive_scan(hist_raw[(int64_t)threadIdx.x * nb + blockIdx.x], s_wave, tot);
+  }
   s_run[threadIdx.x] = 0;
+  // all loads of the block in flight at once
+  uint32_t kr[kItems], vr[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+    kr[r] = i < count ? kin[i] : 0u;
+    vr[r] = i < count ? vin[i] : 0u;
+  }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
   for (int r = 0; r < kItems; ++r) {
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) s_wc[w][threadIdx.x] = 0;
     __syncthreads();
     const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
     const bool valid = i < count;
-    uint32_t k = 0, v = 0;
-    if (valid) {
-      k = kin[i];
-      v = vin[i];
-    }
+    const uint32_t k = kr[r], v = vr[r];
     const uint32_t d = (k >> shift) & 0xFFu;
     const uint64_t m = match_digit(d, valid);
     const uint32_t rank = (uint32_t)__popcll(m & lt);
@@ -185,11 +211,19 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
     }
     __syncthreads();
     if (valid) {
-      const uint32_t pos = s_base[d] + s_wc[wave][d] + rank;
-      kout[pos] = k;
-      vout[pos] = v;
+      const uint32_t lp = s_loff[d] + s_wc[wave][d] + rank;  // < kTile
+      s_key[lp] = k;
+      s_val[lp] = v;
     }
     __syncthreads();
+  }
+  const int nloc = (int)min((int64_t)kTile, count - base);
+  for (int p = threadIdx.x; p < nloc; p += kThreads) {
+    const uint32_t k = s_key[p];
+    const uint32_t d = (k >> shift) & 0xFFu;
+    const uint32_t pos = s_base[d] + ((uint32_t)p - s_loff[d]);
+    kout[pos] = k;
+    vout[pos] = s_val[p];
   }
 }
 
@@ -203,32 +237,66 @@ __global__ void k_gather_touched(const uint32_t *__restrict__ order,
   if (k < count) out[k] = touched[order[k]];
 }
 
-// Emit the pairs of each splat, splats in depth order; the value is the
-// Gaussian index, the key the global tile id.
-__global__ void k_duplicate(const uint32_t *__restrict__ order, const uint32_t *__restrict__ touched,
-                            const uint32_t *__restrict__ offsets, const float4 *__restrict__ rec,
-                            int64_t count, int64_t n, int TW, int TH, int GW,
-                            int64_t tiles_per_view, int64_t cap, uint32_t *__restrict__ tile_key,
-                            uint32_t *__restrict__ pair_val) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= count) return;
-  const uint32_t s = order[k];
-  if (touched[s] == 0) return;
-  // beyond the pair capacity (reported by the count clamp): drop the splat
-  if ((int64_t)offsets[k] + touched[s] > cap) return;
-  const float4 r = rec[3 * (int64_t)s + 1];
-  const uint32_t sx = __float_as_uint(r.z), sy = __float_as_uint(r.w);
-  const int x0 = sx & 0xFFFF, x1 = sx >> 16, y0 = sy & 0xFFFF, y1 = sy >> 16;
-  const uint32_t v = (uint32_t)(s / n);
-  const uint32_t gi = (uint32_t)(s - (int64_t)v * n);
-  uint32_t pos = offsets[k];
-  const uint32_t tbase = (uint32_t)(v * tiles_per_view);
-  for (int ty = y0 / TH; ty <= y1 / TH; ++ty)
-    for (int tx = x0 / TW; tx <= x1 / TW; ++tx) {
-      tile_key[pos] = tbase + (uint32_t)(ty * GW + tx);
-      pair_val[pos] = gi;
-      ++pos;
+// Emit the pairs of the splats in depth order; the value is the Gaussian
+// index, the key the global tile id.  Load-balanced: a block takes 256
+// consecutive splats, stages their pair offsets in LDS, and its threads
+// emit consecutive pairs (finding the owning splat by binary search), so the
+// writes are contiguous.  Pairs at or beyond `cap` are not written (the
+// count clamp reports the overflow); all pairs below it are.
+constexpr int kDupSplats = 256;
+__global__ void __launch_bounds__(kDupSplats)
+k_duplicate(const uint32_t *__restrict__ order, const uint32_t *__restrict__ touched,
+            const uint32_t *__restrict__ offsets, const float4 *__restrict__ rec, int64_t count,
+            int64_t n, int TW, int TH, int GW, int64_t tiles_per_view, int64_t cap,
+            uint32_t *__restrict__ tile_key, uint32_t *__restrict__ pair_val) {
+  __shared__ uint32_t s_off[kDupSplats];   // pair offset relative to the block's first
+  __shared__ uint32_t s_tile0[kDupSplats]; // global id of the first tile of the rectangle
+  __shared__ uint16_t s_w[kDupSplats];     // tiles per rectangle row
+  __shared__ uint32_t s_gi[kDupSplats];
+  __shared__ uint32_t s_total;
+  const int64_t k0 = (int64_t)blockIdx.x * kDupSplats;
+  const int64_t k = k0 + threadIdx.x;
+  const uint32_t base = offsets[k0];
+  uint32_t off = 0xFFFFFFFFu, tile0 = 0, gi = 0;
+  uint16_t w = 1;
+  if (k < count) {
+    off = offsets[k] - base;
+    const uint32_t s = order[k];
+    if (touched[s] != 0) {
+      const float4 r = rec[3 * (int64_t)s + 1];
+      const uint32_t sx = __float_as_uint(r.z), sy = __float_as_uint(r.w);
+      const int tx0 = (int)(sx & 0xFFFF) / TW, tx1 = (int)(sx >> 16) / TW;
+      const int ty0 = (int)(sy & 0xFFFF) / TH;
+      const uint32_t v = (uint32_t)(s / n);
+      gi = (uint32_t)(s - (int64_t)v * n);
+      w = (uint16_t)(tx1 - tx0 + 1);
+      tile0 = (uint32_t)(v * tiles_per_view) + (uint32_t)(ty0 * GW + tx0);
     }
+  }
+  s_off[threadIdx.x] = off;
+  s_tile0[threadIdx.x] = tile0;
+  s_w[threadIdx.x] = w;
+  s_gi[threadIdx.x] = gi;
+  if (threadIdx.x == kDupSplats - 1 || k == count - 1) {
+    if (k < count) s_total = offsets[k] - base + touched[order[k]];
+  }
+  __syncthreads();
+  const uint32_t total = s_total;
+  for (uint32_t p = threadIdx.x; p < total; p += kDupSplats) {
+    if ((int64_t)base + p >= cap) break;
+    // last splat j with s_off[j] <= p (offsets are non-decreasing; splats
+    // with no pairs share the next one's offset and are skipped by <=)
+    int lo = 0, hi = kDupSplats - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t e = p - s_off[lo];
+    const uint32_t wj = s_w[lo];
+    const uint32_t t = s_tile0[lo] + (e / wj) * (uint32_t)GW + (e % wj);
+    tile_key[base + p] = t;
+    pair_val[base + p] = s_gi[lo];
+  }
 }
 
 __global__ void k_zero_ranges(uint2 *__restrict__ ranges, int64_t tiles) {
@@ -236,14 +304,43 @@ __global__ void k_zero_ranges(uint2 *__restrict__ ranges, int64_t tiles) {
   if (t < tiles) ranges[t] = make_uint2(0, 0);
 }
 
+// Tile ranges from the sorted tile ids.  A thread owns 4 consecutive ids
+// (one 16-byte load) plus the id before them; a run boundary between
+// positions e-1 and e sets the end of the earlier tile and the start of the
+// later one.
+__device__ __forceinline__ void range_edge(uint2 *__restrict__ ranges, uint32_t tiles,
+                                           uint32_t prev, uint32_t cur, int64_t e) {
+  if (prev == cur) return;
+  if (prev < tiles) ranges[prev].y = (uint32_t)e;
+  if (cur < tiles) ranges[cur].x = (uint32_t)e;
+}
+
 __global__ void k_ranges(const uint32_t *__restrict__ tile_key, int64_t P_static,
-                         const uint32_t *__restrict__ dcount, uint2 *__restrict__ ranges) {
+                         const uint32_t *__restrict__ dcount, uint32_t tiles,
+                         uint2 *__restrict__ ranges) {
   const int64_t P = dcount ? (int64_t)*dcount : P_static;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= P) return;
-  const uint32_t t = tile_key[e];
-  if (e == 0 || tile_key[e - 1] != t) ranges[t].x = (uint32_t)e;
-  if (e == P - 1 || tile_key[e + 1] != t) ranges[t].y = (uint32_t)(e + 1);
+  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (e0 >= P) return;
+  uint32_t v[4];
+  if (e0 + 3 < P) {
+    const uint4 q = *(const uint4 *)(tile_key + e0);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = e0 + j < P ? tile_key[e0 + j] : 0xFFFFFFFFu;
+  }
+  // sentinel 0xFFFFFFFF (>= tiles) stands for "before the first / after the last"
+  uint32_t prev = e0 == 0 ? 0xFFFFFFFFu : tile_key[e0 - 1];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (e0 + j >= P) break;
+    range_edge(ranges, tiles, prev, v[j], e0 + j);
+    prev = v[j];
+  }
+  if (e0 + 3 >= P - 1) {  // this thread holds the last id
+    const uint32_t last = tile_key[P - 1];
+    if (last < tiles) ranges[last].y = (uint32_t)P;
+  }
 }
 
 // counts[0] = total pairs (from the scan); counts[1] = min(total, cap);
@@ -300,18 +397,20 @@ hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2], i
   }
   const int64_t hwords = nb * 256;
   const int64_t snb = (hwords + kTile - 1) / kTile;
-  if (hwords + 1 > c->sort_hist_words || snb > c->scan_tmp_words) return hipErrorInvalidValue;
+  if (2 * hwords + 1 > c->sort_hist_words || snb > c->scan_tmp_words)
+    return hipErrorInvalidValue;
+  uint32_t *hraw = c->sort_hist, *hscan = c->sort_hist + hwords;
   for (int shift = 0; shift < bits; shift += 8) {
-    k_radix_hist<<<(unsigned)nb, kThreads, 0, c->stream>>>(keys[cur], count, dcount, shift,
-                                                           c->sort_hist, nb);
-    // in-place exclusive scan of the digit-major histogram
-    k_scan_reduce<<<(unsigned)snb, kThreads, 0, c->stream>>>(c->sort_hist, hwords, c->scan_tmp);
+    k_radix_hist<<<(unsigned)nb, kThreads, 0, c->stream>>>(keys[cur], count, dcount, shift, hraw,
+                                                           nb);
+    // exclusive scan of the digit-major histogram (raw counts kept for the
+    // block-local placement)
+    k_scan_reduce<<<(unsigned)snb, kThreads, 0, c->stream>>>(hraw, hwords, c->scan_tmp);
     k_scan_sums<<<1, kThreads, 0, c->stream>>>(c->scan_tmp, snb, nullptr, nullptr);
-    k_scan_down<<<(unsigned)snb, kThreads, 0, c->stream>>>(c->sort_hist, hwords, c->scan_tmp,
-                                                           c->sort_hist);
+    k_scan_down<<<(unsigned)snb, kThreads, 0, c->stream>>>(hraw, hwords, c->scan_tmp, hscan);
     k_radix_scatter<<<(unsigned)nb, kThreads, 0, c->stream>>>(keys[cur], vals[cur], keys[cur ^ 1],
                                                               vals[cur ^ 1], count, dcount,
-                                                              shift, c->sort_hist, nb);
+                                                              shift, hraw, hscan, nb);
     cur ^= 1;
   }
   *which = cur;
@@ -347,7 +446,7 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
   {
     SgsProfScope ps(c, SGS_PROF_DUPLICATE);
     if (dev) k_clamp_count<<<1, 64, 0, c->stream>>>(c->d_pairs_total, cap);
-    k_duplicate<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(
+    k_duplicate<<<sgs_blocks(c->vn, kDupSplats), kDupSplats, 0, c->stream>>>(
         order, c->touched, c->offsets, c->rec, c->vn, c->n, c->TW, c->TH, c->GW,
         c->tiles_per_view, cap, c->tile_key[0], c->pair_val[0]);
   }
@@ -364,7 +463,7 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
   k_zero_ranges<<<sgs_blocks(c->total_tiles, 256), 256, 0, c->stream>>>(c->ranges,
                                                                        c->total_tiles);
   if (P > 0)
-    k_ranges<<<sgs_blocks(P, 256), 256, 0, c->stream>>>(c->tile_key[which], P, dcount,
-                                                        c->ranges);
+    k_ranges<<<sgs_blocks((P + 3) / 4, 256), 256, 0, c->stream>>>(c->tile_key[which], P, dcount,
+                                                        (uint32_t)c->total_tiles, c->ranges);
   return hipGetLastError();
 }
