@@ -79,6 +79,9 @@ def _declare(L):
         "orc_backward": (None, [I64, I64, P, P, I32, P, I32, I32, I32, I32, P, P, P, P,
                                 P, P, P, P]),
         "orc_project64": (None, [I64, I64, P, I32, P, I32, I32, P, P]),
+        "orc_tile_counts": (None, [I64, I32, P, P, I32, I32, I32, I32, P]),
+        "orc_tile_list": (I64, [I64, I32, I64, P, P, P, I32, I32, I32, P]),
+        "orc_pixels_brute": (I64, [I64, I64, P, P, I32, P, I32, I32, P, P, P, I64, P, P, P]),
         "orc_l1": (F64, [I64, P, P, P]),
         "orc_sh_basis": (None, [I64, P, P]),
         "orc_fixed_length_bits": (I64, [I64, I64, P, P, P, P, P]),
@@ -193,7 +196,9 @@ class Structure:
 
 
 def decide(yhat: np.ndarray, n: int, cams: np.ndarray, W: int, H: int,
-           TW: int = TW_DEFAULT, TH: int = TH_DEFAULT) -> Structure:
+           TW: int = TW_DEFAULT, TH: int = TH_DEFAULT, bin_pairs: bool = True) -> Structure:
+    """Decision layer for every (view, Gaussian); with bin_pairs the sorted
+    (tile, depth, index) pair list too (skip it where it would not fit)."""
     yhat = np.ascontiguousarray(yhat, np.float32)
     cams = np.ascontiguousarray(cams, np.float32)
     V = cams.shape[0]
@@ -208,6 +213,12 @@ def decide(yhat: np.ndarray, n: int, cams: np.ndarray, W: int, H: int,
                  _p(pxy), _p(span), _p(radius), _p(tiles))
     Pn = L.orc_bin(n, V, _p(valid), _p(tz), _p(span), W, H, TW, TH, None, None, None)
     GW, GH = (W + TW - 1) // TW, (H + TH - 1) // TH
+    if not bin_pairs:
+        e = np.zeros(0, np.uint32)
+        st = Structure(valid, tz, pxy, span, radius, tiles, e.astype(np.uint64), e,
+                       np.zeros((0, 2), np.uint32), TW, TH)
+        st.pairs = int(Pn)
+        return st
     keys = np.zeros(max(Pn, 1), np.uint64)
     vals = np.zeros(max(Pn, 1), np.uint32)
     ranges = np.zeros((V * GW * GH, 2), np.uint32)
@@ -281,6 +292,43 @@ def l1(image: np.ndarray, target: np.ndarray):
     d = np.zeros(image.shape)
     D = lib().orc_l1(image.size, _p(image), _p(target), _p(d))
     return float(D), d
+
+
+def tile_counts(st: Structure, n: int, V: int, W: int, H: int) -> np.ndarray:
+    """Pairs per tile from the spans (orc_bin's rule, no pair list)."""
+    GW, GH = (W + st.TW - 1) // st.TW, (H + st.TH - 1) // st.TH
+    out = np.zeros(V * GW * GH, np.int64)
+    lib().orc_tile_counts(n, V, _p(st.valid), _p(st.span), W, H, st.TW, st.TH, _p(out))
+    return out
+
+
+def tile_list(st: Structure, n: int, view: int, tile_in_view: int, W: int) -> np.ndarray:
+    """Gaussians of one tile in (depth, index) order."""
+    L = lib()
+    cnt = L.orc_tile_list(n, view, tile_in_view, _p(st.valid), _p(st.tz), _p(st.span), W,
+                          st.TW, st.TH, None)
+    out = np.zeros(max(cnt, 1), np.uint32)
+    L.orc_tile_list(n, view, tile_in_view, _p(st.valid), _p(st.tz), _p(st.span), W, st.TW,
+                    st.TH, _p(out))
+    return out[:cnt]
+
+
+def pixels_brute(p64, mask64, n, cams, W, H, st: Structure, pix: np.ndarray):
+    """Colour and T of sampled pixels pix [k][3] = (view, u, v) by brute force."""
+    p64 = np.ascontiguousarray(p64, np.float64)
+    mask64 = np.ascontiguousarray(mask64, np.float64)
+    cams = np.ascontiguousarray(cams, np.float32)
+    pix = np.ascontiguousarray(pix, np.int32)
+    if pix.size and not ((pix[:, 0] >= 0).all() and (pix[:, 0] < cams.shape[0]).all()
+                         and (pix[:, 1] >= 0).all() and (pix[:, 1] < W).all()
+                         and (pix[:, 2] >= 0).all() and (pix[:, 2] < H).all()):
+        raise ValueError("sampled pixel outside the views")
+    out = np.zeros((pix.shape[0], 4))
+    margin = np.zeros(pix.shape[0], np.uint8)
+    E = lib().orc_pixels_brute(n, p64.shape[1], _p(p64), _p(mask64), cams.shape[0], _p(cams), W,
+                               H, _p(st.valid), _p(st.tz), _p(st.span), pix.shape[0], _p(pix),
+                               _p(out), _p(margin))
+    return out, margin, int(E)
 
 
 def sh_basis(dirs: np.ndarray) -> np.ndarray:

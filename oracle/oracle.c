@@ -973,6 +973,125 @@ void orc_backward(int64_t n, int64_t npad, const double *p, const double *mask,
   free(pj);
 }
 
+/* Number of (tile, Gaussian) pairs of every tile, from the pixel spans
+ * (same rule as orc_bin, without materialising the pairs).  counts
+ * [V*tiles] is overwritten. */
+void orc_tile_counts(int64_t n, int32_t V, const int32_t *valid, const int32_t *span,
+                     int32_t W, int32_t H, int32_t TW, int32_t TH, int64_t *counts) {
+  int GW = (W + TW - 1) / TW, GH = (H + TH - 1) / TH;
+  int64_t tpv = (int64_t)GW * GH;
+  for (int64_t t = 0; t < V * tpv; ++t) counts[t] = 0;
+  for (int v = 0; v < V; ++v)
+    for (int64_t i = 0; i < n; ++i) {
+      int64_t s = (int64_t)v * n + i;
+      if (!valid[s]) continue;
+      for (int ty = span[4 * s + 2] / TH; ty <= span[4 * s + 3] / TH; ++ty)
+        for (int tx = span[4 * s] / TW; tx <= span[4 * s + 1] / TW; ++tx)
+          counts[v * tpv + (int64_t)ty * GW + tx] += 1;
+    }
+}
+
+/* The Gaussians listed for one tile, in (depth bits, index) order; returns
+ * the count (out may be NULL to count only). */
+int64_t orc_tile_list(int64_t n, int32_t view, int64_t tile_in_view, const int32_t *valid,
+                      const float *tz, const int32_t *span, int32_t W, int32_t TW, int32_t TH,
+                      uint32_t *out) {
+  int GW = (W + TW - 1) / TW;
+  int tx = (int)(tile_in_view % GW), ty = (int)(tile_in_view / GW);
+  int X0 = tx * TW, X1 = X0 + TW - 1, Y0 = ty * TH, Y1 = Y0 + TH - 1;
+  int64_t cnt = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t s = (int64_t)view * n + i;
+    if (!valid[s]) continue;
+    const int32_t *sp = span + 4 * s;
+    if (sp[0] <= X1 && sp[1] >= X0 && sp[2] <= Y1 && sp[3] >= Y0) {
+      if (out) out[cnt] = (uint32_t)i;
+      ++cnt;
+    }
+  }
+  if (out) {
+    g_sort_tz = tz + (int64_t)view * n;
+    int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(cnt > 0 ? cnt : 1));
+    for (int64_t k = 0; k < cnt; ++k) tmp[k] = out[k];
+    qsort(tmp, (size_t)cnt, sizeof(int64_t), idx_cmp);
+    for (int64_t k = 0; k < cnt; ++k) out[k] = (uint32_t)tmp[k];
+    free(tmp);
+  }
+  return cnt;
+}
+
+/* Brute-force colour and transmittance of sampled pixels: each pixel walks
+ * every valid splat of its view in global (depth bits, index) order and the
+ * support rule alone selects candidates [Sec. 3.1, compositing equation].
+ * pix [npix][3] = (view, u, v); out [npix][4] = (r, g, b, T), margin [npix]. */
+int64_t orc_pixels_brute(int64_t n, int64_t npad, const double *p, const double *mask,
+                         int32_t V, const float *cams, int32_t W, int32_t H,
+                         const int32_t *valid, const float *tz, const int32_t *span,
+                         int64_t npix, const int32_t *pix, double *out, uint8_t *margin) {
+  int64_t evals = 0;
+  int64_t *ord = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  uint32_t *list = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+  pj64 *pj = (pj64 *)calloc((size_t)n, sizeof(pj64));
+  int64_t *vpix = (int64_t *)malloc(sizeof(int64_t) * (size_t)(npix > 0 ? npix : 1));
+  int64_t *sat = (int64_t *)malloc(sizeof(int64_t) * (size_t)(W + 1) * (size_t)(H + 1));
+  for (int v = 0; v < V; ++v) {
+    int64_t nv = 0;
+    for (int64_t k = 0; k < npix; ++k)
+      if (pix[3 * k] == v) vpix[nv++] = k;
+    if (!nv) continue;
+    /* summed-area table of the view's sampled pixels: one lookup per span */
+    for (int64_t k = 0; k < (int64_t)(W + 1) * (H + 1); ++k) sat[k] = 0;
+    for (int64_t k = 0; k < nv; ++k)
+      sat[(int64_t)(pix[3 * vpix[k] + 2] + 1) * (W + 1) + pix[3 * vpix[k] + 1] + 1] += 1;
+    for (int y = 1; y <= H; ++y)
+      for (int x = 1; x <= W; ++x)
+        sat[(int64_t)y * (W + 1) + x] += sat[(int64_t)(y - 1) * (W + 1) + x] +
+                                         sat[(int64_t)y * (W + 1) + x - 1] -
+                                         sat[(int64_t)(y - 1) * (W + 1) + x - 1];
+    const orc_cam *c = (const orc_cam *)(cams + 19 * v);
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      if (!valid[(int64_t)v * n + i]) continue;
+      /* a splat whose span holds none of the sampled pixels is skipped by
+         the support rule at every one of them: leave it out of the walk */
+      const int32_t *sp = span + 4 * ((int64_t)v * n + i);
+      int x0 = sp[0] < 0 ? 0 : sp[0], x1 = sp[1] >= W ? W - 1 : sp[1];
+      int y0 = sp[2] < 0 ? 0 : sp[2], y1 = sp[3] >= H ? H - 1 : sp[3];
+      if (x0 > x1 || y0 > y1) continue;
+      int64_t inside = sat[(int64_t)(y1 + 1) * (W + 1) + x1 + 1] -
+                       sat[(int64_t)y0 * (W + 1) + x1 + 1] -
+                       sat[(int64_t)(y1 + 1) * (W + 1) + x0] + sat[(int64_t)y0 * (W + 1) + x0];
+      if (!inside) continue;
+      ord[cnt++] = i;
+      pj64_tmp m;
+      proj64(p, npad, i, c, W, H, &pj[i], &m);
+    }
+    g_sort_tz = tz + (int64_t)v * n;
+    qsort(ord, (size_t)cnt, sizeof(int64_t), idx_cmp);
+    for (int64_t k = 0; k < cnt; ++k) list[k] = (uint32_t)ord[k];
+    /* blend_pixel indexes splats as view * n + i; give it a one-view table */
+    blend_ctx bc = {pj, span + (int64_t)v * n * 4, mask, n};
+    for (int64_t k = 0; k < npix; ++k) {
+      if (pix[3 * k] != v) continue;
+      double col[3], T;
+      int mg = 0;
+      blend_pixel(&bc, 0, pix[3 * k + 1], pix[3 * k + 2], list, cnt, col, &T, &evals, &mg,
+                  NULL, NULL);
+      out[4 * k] = col[0];
+      out[4 * k + 1] = col[1];
+      out[4 * k + 2] = col[2];
+      out[4 * k + 3] = T;
+      margin[k] = (uint8_t)mg;
+    }
+  }
+  free(pj);
+  free(vpix);
+  free(sat);
+  free(ord);
+  free(list);
+  return evals;
+}
+
 /* Projection only (FP64): fields px, py, A, B, C, opacity, r, g, b per
    (view, Gaussian) -> out [V][n][9]; invalid entries are left at zero. */
 void orc_project64(int64_t n, int64_t npad, const double *p, int32_t V,

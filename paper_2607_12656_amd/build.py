@@ -2,7 +2,11 @@
 
 Every translation unit is compiled with -ffp-contract=off (floating-point
 expressions evaluated exactly as written: the discrete decisions of the
-projection must be reproducible bit for bit) and with packed FP32 disabled.
+projection must be reproducible bit for bit), with FP32 division and sqrt
+correctly rounded (-fhip-fp32-correctly-rounded-divide-sqrt, which makes
+plain `/` and `sqrtf` IEEE operations; the `__fsqrt_rn` intrinsic is not
+correctly rounded on this toolchain and is not used), and with packed FP32
+disabled.
 """
 from __future__ import annotations
 
@@ -20,8 +24,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
-    "-fno-gpu-flush-denormals-to-zero", "-Xclang", "-target-feature", "-Xclang",
-    "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+    "-fhip-fp32-correctly-rounded-divide-sqrt", "-fno-gpu-flush-denormals-to-zero",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall",
+    "-Wno-unused-function", "-Wno-unused-result",
 ]
 
 

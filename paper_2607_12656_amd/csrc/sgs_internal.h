@@ -241,7 +241,9 @@ struct SgsProj {
 };
 
 // Discrete structure of one splat.  Operation order (all FP32, no
-// contraction, correctly rounded):
+// contraction, correctly rounded: `sqrtf` and `__fdiv_rn`; the `__fsqrt_rn`
+// intrinsic is off by one ulp on a sizeable fraction of inputs and would move
+// ceil(3 sqrt(lambda)) where 3 sqrt(lambda) lands next to an integer):
 //   t = ((R0 mu0 + R1 mu1) + R2 mu2) + t0 (per row); cull unless tz > 0.2;
 //   qq = ((w^2 + x^2) + y^2) + z^2, cull unless qq > 0; q /= sqrt(qq);
 //   rotation matrix in the usual unit-quaternion form; S = exp_repro(s);
@@ -263,7 +265,7 @@ __device__ __forceinline__ void sgs_project(const float *y, const SgsCam &cam, i
   float w = y[SGS_CH_ROT], x = y[SGS_CH_ROT + 1], yy = y[SGS_CH_ROT + 2], z = y[SGS_CH_ROT + 3];
   const float qq = ((w * w + x * x) + yy * yy) + z * z;
   if (!(qq > 0.0f)) return;
-  o.qn = __fsqrt_rn(qq);
+  o.qn = sqrtf(qq);
   w = __fdiv_rn(w, o.qn);
   x = __fdiv_rn(x, o.qn);
   yy = __fdiv_rn(yy, o.qn);
@@ -323,8 +325,8 @@ __device__ __forceinline__ void sgs_project(const float *y, const SgsCam &cam, i
   if (!(o.det > 0.0f)) return;
   const float mid = 0.5f * (o.a + o.c);
   const float disc = fmaxf(mid * mid - o.det, 0.0f);
-  const float lmax = mid + __fsqrt_rn(disc);
-  const float rf = ceilf(3.0f * __fsqrt_rn(lmax));
+  const float lmax = mid + sqrtf(disc);
+  const float rf = ceilf(3.0f * sqrtf(lmax));
   o.px = cam.fx * o.ux + cam.cx;
   o.py = cam.fy * o.uy + cam.cy;
   const float xlo = ceilf(o.px - rf), xhi = floorf(o.px + rf);

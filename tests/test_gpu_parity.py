@@ -286,3 +286,102 @@ def test_full_size_1m_workload(orc, gctx, dev):
     grad_close(g["gq_render"][:, :sc.n], r["gyhat"][:, :sc.n], name="grad qparams")
     grad_close(g["gmask"], r["gmhat"], name="grad mask")
     grad_close(g["gq"], r["gq"], name="grad qstep")
+
+
+def test_full_size_3m_8views_sampled(orc, gctx, dev):
+    """3M Gaussians x 8 views of 1600x1060 in the bench's launch configuration
+    (16x16 tiles, reserved pair capacity, about 5.5e8 pairs).  Full check of
+    what the oracle can afford at this size: quantized parameters, hard mask,
+    rate scalars, every (view, Gaussian)'s culling, span and depth, the pair
+    count and every tile's range; sampled checks of the rest: the sorted lists
+    of 24 tiles (the heaviest, the ragged bottom row, random ones) and the
+    colour and transmittance of 24 pixels per view by brute force."""
+    from paper_2607_12656_amd.rd import RDStep
+    sc = synth.make_scene("c3")
+    n, V, W, H = sc.n, sc.views, sc.width, sc.height
+    lam = 2.5e-5
+    _say(f"[gpu] c3 n={n} V={V} {W}x{H}")
+    yh, _ = orc.fakequant(sc.params, sc.qstep, n)
+    lite = orc.decide(yh, n, sc.cams, W, H, 16, 16, bin_pairs=False)
+    cnt = orc.tile_counts(lite, n, V, W, H)
+    assert cnt.sum() == lite.pairs
+
+    rd = RDStep(gctx, n, sc.npad, sc.n_hat, sc.cams, W, H, tile=(16, 16))
+    gctx.reserve_pairs(lite.pairs + lite.pairs // 8 + 4096)
+    params, q, score = T(sc.params, dev), T(sc.qstep, dev), T(sc.score, dev)
+    mask, target = T(sc.given_mask, dev), T(sc.target, dev)
+    rd.forward(params, q, score, target, lam, 0, mask, 0, 0)
+    torch.cuda.synchronize()
+    P, _ = gctx.query(rd.stats)
+    assert P == lite.pairs, f"pair count {P} vs {lite.pairs}"
+
+    assert np.array_equal(rd.qparams[:, :n].cpu().numpy(), yh[:, :n]), "quantized parameters"
+    assert np.array_equal(rd.hard.cpu().numpy(), sc.given_mask), "hard mask"
+    rp = orc.rate_proxy(sc.params, sc.qstep, sc.given_mask, n, sc.n_hat)
+    R, Lq, Lm = rd.rate3.cpu().numpy()
+    for a, b in ((R, rp["R"]), (Lq, rp["Lq"]), (Lm, rp["Lm"])):
+        assert abs(a - b) <= 1e-6 * abs(b)
+
+    GW, GH = -(-W // 16), -(-H // 16)
+    tile_ids = torch.empty(P, dtype=torch.int32, device=dev)
+    vals = torch.empty(P, dtype=torch.int32, device=dev)
+    ranges = torch.empty(V * GW * GH, 2, dtype=torch.int32, device=dev)
+    spans = torch.empty(V, n, 4, dtype=torch.int32, device=dev)
+    depth = torch.empty(V, n, dtype=torch.float32, device=dev)
+    splats = torch.empty(V, n, 12, dtype=torch.float32, device=dev)
+    gctx.copy_structure(tile_ids, vals, P, ranges, spans, depth, splats)
+    torch.cuda.synchronize()
+    del splats
+
+    valid = lite.valid > 0
+    gsp = spans.cpu().numpy()
+    assert np.array_equal(gsp[..., 0] >= 0, valid), "culling"
+    assert np.array_equal(gsp[valid], lite.span[valid]), "pixel spans"
+    del gsp
+    assert np.array_equal(depth.cpu().numpy()[valid].view(np.uint32),
+                          lite.tz[valid].view(np.uint32)), "depth"
+
+    rg = ranges.cpu().numpy().astype(np.int64)
+    nz = cnt > 0
+    start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+    assert np.array_equal(rg[nz, 0], start[nz]) and np.array_equal(rg[nz, 1] - rg[nz, 0], cnt[nz]), \
+        "tile ranges"
+    assert (rg[~nz, 0] == rg[~nz, 1]).all(), "empty tiles"
+
+    rng = np.random.default_rng(7)
+    tpv = GW * GH
+    heavy = int(np.argmax(cnt))
+    bottom = [v * tpv + (GH - 1) * GW + tx for v, tx in ((0, 0), (3, GW // 2), (7, GW - 1))]
+    pick = [heavy] + [t for t in bottom if cnt[t] > 0] + list(rng.choice(np.flatnonzero(nz), 20,
+                                                                        replace=False))
+    for t in pick:
+        b, e = int(rg[t, 0]), int(rg[t, 1])
+        assert (tile_ids[b:e] == t).all().item(), f"tile ids of tile {t}"
+        got = vals[b:e].cpu().numpy().view(np.uint32)
+        ref = orc.tile_list(lite, n, t // tpv, t % tpv, W)
+        assert np.array_equal(got, ref), f"sorted list of tile {t} ({e - b} pairs)"
+    _say(f"c3: P={P}, heaviest tile {heavy} with {cnt[heavy]} pairs, {len(pick)} tile lists equal")
+    del tile_ids, vals
+
+    per = 24
+    hv, ht = heavy // tpv, heavy % tpv
+    px = []
+    for v in range(V):
+        u = rng.integers(0, W, per)
+        y = rng.integers(0, H, per)
+        u[:2], y[:2] = (0, W - 1), (H - 1, H - 1)          # corners of the ragged row
+        if v == hv:                                        # inside the heaviest tile
+            u[2:6] = (ht % GW) * 16 + rng.integers(0, 16, 4)
+            y[2:6] = np.minimum((ht // GW) * 16 + rng.integers(0, 16, 4), H - 1)
+        px.append(np.stack([np.full(per, v), u, y], 1))
+    px = np.concatenate(px)
+    out, mg, _ = orc.pixels_brute(yh.astype(np.float64), sc.given_mask.astype(np.float64), n,
+                                  sc.cams, W, H, lite, px)
+    img = rd.image.cpu().numpy()
+    Tg = rd.final_T.cpu().numpy()
+    ok = mg == 0
+    assert ok.mean() >= 0.9, f"too many margin pixels ({(~ok).sum()})"
+    g = np.concatenate([img[px[:, 0], :, px[:, 2], px[:, 1]], Tg[px[:, 0], px[:, 2], px[:, 1]][:, None]], 1)
+    err = np.abs(g - out)[ok].max()
+    _say(f"c3: {ok.sum()} sampled pixels, max error {err:.2e}")
+    assert err <= 1e-4, f"sampled pixel error {err:.3e}"

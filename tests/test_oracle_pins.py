@@ -533,3 +533,32 @@ def test_rd_step_composition(orc):
                      sc.height, sc.target, sc.n, sc.n_hat, lam, mask_mode=1, seed=3)
     ms = r1["msoft"]
     assert np.allclose(r1["gs"], r1["gmhat_total"] * ms * (1 - ms))
+
+
+def test_sampled_oracle_helpers_agree_with_full_binning(orc):
+    """Per-tile counts, single-tile lists and brute-force sampled pixels (the
+    oracle's tools for full-size sampled parity) equal the full binning and
+    the brute-force image."""
+    sc = _tiny(n=80, W=70, H=50, V=2, seed=9)
+    yh, _ = orc.fakequant(sc.params, sc.qstep, sc.n)
+    st = orc.decide(yh, sc.n, sc.cams, sc.width, sc.height, 16, 8)
+    lite = orc.decide(yh, sc.n, sc.cams, sc.width, sc.height, 16, 8, bin_pairs=False)
+    assert lite.pairs == st.keys.size
+    cnt = orc.tile_counts(lite, sc.n, 2, sc.width, sc.height)
+    assert np.array_equal(cnt, (st.ranges[:, 1] - st.ranges[:, 0]).astype(np.int64))
+    GW = -(-sc.width // 16)
+    tpv = GW * (-(-sc.height // 8))
+    for t in range(2 * tpv):
+        b, e = st.ranges[t]
+        lst = orc.tile_list(lite, sc.n, t // tpv, t % tpv, sc.width)
+        assert np.array_equal(lst, st.vals[b:e])
+    p64 = yh.astype(np.float64)
+    m = sc.given_mask.astype(np.float64)
+    full = orc.forward_brute(p64, m, sc.n, sc.cams, sc.width, sc.height, st)
+    rng = np.random.default_rng(0)
+    pix = np.stack([rng.integers(0, 2, 60), rng.integers(0, sc.width, 60),
+                    rng.integers(0, sc.height, 60)], 1)
+    out, _, _ = orc.pixels_brute(p64, m, sc.n, sc.cams, sc.width, sc.height, lite, pix)
+    for k, (v, u, y) in enumerate(pix):
+        assert np.array_equal(out[k, :3], full["image"][v, :, y, u])
+        assert out[k, 3] == full["T"][v, y, u]
