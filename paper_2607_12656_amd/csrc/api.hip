@@ -84,10 +84,8 @@ hipError_t grow_pairs(sgs_ctx *c, int64_t P) {
     e = dalloc(&c->pair_val[k], cap);
     if (e != hipSuccess) return e;
   }
-  const int64_t nb = (cap + 4095) / 4096;
-  const int64_t hist = 2 * nb * 256 + 1;   // raw and scanned digit counts
-  const int64_t scan = (hist + 4095) / 4096 + 1;
-  hipError_t e = ensure_tmp(c, scan > c->scan_tmp_words ? scan : c->scan_tmp_words, hist);
+  const int64_t hist = radix_hist_words(cap);
+  hipError_t e = ensure_tmp(c, c->scan_tmp_words, hist);
   if (e != hipSuccess) return e;
   c->pair_cap = cap;
   return hipSuccess;
@@ -208,9 +206,8 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   SGS_ALLOC(c->red_tmp, red);
   c->red_tmp_words = red;
 #undef SGS_ALLOC
-  const int64_t nb = (vn + 4095) / 4096;
-  const int64_t hist = 2 * nb * 256 + 1;   // raw and scanned digit counts
-  const int64_t scan = ((hist > vn ? hist : vn) + 4095) / 4096 + 1;
+  const int64_t hist = radix_hist_words(vn);
+  const int64_t scan = (vn + 4095) / 4096 + 1;
   e = ensure_tmp(c, scan, hist);
   if (e != hipSuccess) { free_scene(c); return hip_fail(c, e, "set_scene alloc"); }
   // initial pair capacity: 4 tiles per splat

@@ -134,6 +134,7 @@ hipError_t launch_preprocess_bwd(sgs_ctx *c, const float *qparams, float *grad_q
                                  float *grad_mask);
 // sort.hip
 hipError_t ensure_tmp(sgs_ctx *c, int64_t scan_words, int64_t hist_words);
+int64_t radix_hist_words(int64_t count);   // sort_hist words a radix sort of count needs
 hipError_t launch_exclusive_scan(sgs_ctx *c, const uint32_t *in, uint32_t *out,
                                  int64_t count, uint32_t *total_out);
 // Stable LSD radix sort of 32-bit keys with 32-bit values over bits
@@ -200,6 +201,16 @@ __device__ __forceinline__ float sgs_exp_repro(float x) {
   p = p * r + 1.0f;
   p = p * r + 1.0f;
   return ldexpf(p, (int)n);
+}
+
+// Workgroups are dispatched to the eight XCDs round-robin (hardware id i runs
+// on XCD i % 8, each XCD with its own L2).  Logical id of hardware id i in a
+// grid of nb blocks such that every XCD takes one contiguous range of logical
+// blocks: neighbouring blocks, which touch neighbouring memory (the two
+// halves of a cache line at a write boundary), then share an L2.
+__device__ __forceinline__ int64_t sgs_xcd_block(int64_t i, int64_t nb) {
+  const int64_t x = i & 7, k = i >> 3, per = nb >> 3, rem = nb & 7;
+  return x * per + (x < rem ? x : rem) + k;
 }
 
 // Order-preserving map of float bits to uint32 (for min/max keys).

@@ -16,6 +16,7 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kItems = 16;
 constexpr int kTile = kThreads * kItems;  // elements per block
+constexpr int kChunk = 64;                 // histogram rows per chunk of the digit scan
 
 // ---------------------------------------------------------------------------
 // Exclusive scan of uint32 (reduce -> scan of block sums -> downsweep).
@@ -116,18 +117,23 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
   return m;
 }
 
+// Block histogram of one digit.  Lanes count into 32 sub-histograms (eight
+// lanes each, rows padded to 257 words so that equal digits of different
+// sub-histograms sit in different banks): the pass over the high digit sees
+// long runs of equal digits, and same-address LDS atomics serialize.
 __global__ void __launch_bounds__(kThreads)
 k_radix_hist(const uint32_t *__restrict__ keys, int64_t count_static,
-             const uint32_t *__restrict__ dcount, int shift, uint32_t *__restrict__ hist,
-             int64_t nb) {
-  __shared__ uint32_t s_hist[256];
+             const uint32_t *__restrict__ dcount, int shift, uint32_t *__restrict__ hist) {
+  __shared__ uint32_t s_sub[kThreads / 8][257];
   const int64_t count = dcount ? (int64_t)*dcount : count_static;
-  const int64_t base = (int64_t)blockIdx.x * kTile;
+  const int64_t blk = sgs_xcd_block(blockIdx.x, gridDim.x);
+  const int64_t base = blk * kTile;
   if (base >= count) {  // grid sized for a capacity, not the live count
-    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = 0;
+    hist[blk * 256 + threadIdx.x] = 0;
     return;
   }
-  s_hist[threadIdx.x] = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 8; ++w) s_sub[w][threadIdx.x] = 0;
   // all loads of the block in flight at once
   uint32_t kr[kItems];
 #pragma unroll
@@ -136,17 +142,69 @@ k_radix_hist(const uint32_t *__restrict__ keys, int64_t count_static,
     kr[r] = i < count ? keys[i] : 0u;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
+  uint32_t *mine = s_sub[threadIdx.x >> 3];
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
-    const bool valid = i < count;
-    const uint32_t d = (kr[r] >> shift) & 0xFFu;
-    const uint64_t m = match_digit(d, valid);
-    if (valid && (__ffsll((long long)m) - 1) == lane) atomicAdd(&s_hist[d], (uint32_t)__popcll(m));
+    if (i < count) atomicAdd(&mine[(kr[r] >> shift) & 0xFFu], 1u);
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = s_hist[threadIdx.x];
+  uint32_t tot = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 8; ++w) tot += s_sub[w][threadIdx.x];
+  hist[blk * 256 + threadIdx.x] = tot;
+}
+
+// Digit offsets from the block-major histogram rows H[b][d]: the position of
+// block b's first element with digit d is
+//   sum_{d' < d} total[d'] + sum_{b' < b} H[b'][d].
+// Rows are grouped in chunks of kChunk; every access below reads or writes
+// whole 1 KB rows (coalesced), unlike a scan over a digit-major table, whose
+// per-block stores and loads are 4 bytes each, a row apart.
+__global__ void __launch_bounds__(kThreads)
+k_hist_chunk_sums(const uint32_t *__restrict__ H, int64_t nb, uint32_t *__restrict__ CS) {
+  const int64_t g = blockIdx.x;
+  const int64_t b0 = g * kChunk, b1 = min(nb, b0 + kChunk);
+  uint32_t s = 0;
+#pragma unroll 8
+  for (int64_t b = b0; b < b1; ++b) s += H[b * 256 + threadIdx.x];
+  CS[g * 256 + threadIdx.x] = s;
+}
+
+// One block per digit: exclusive scan of the chunk sums over chunks (in
+// place) and the digit total.
+__global__ void __launch_bounds__(kThreads)
+k_hist_chunk_scan(uint32_t *__restrict__ CS, int64_t ng, uint32_t *__restrict__ total) {
+  __shared__ uint32_t s_wave[kWaves];
+  const int d = blockIdx.x;
+  const int64_t per = (ng + kThreads - 1) / kThreads;
+  const int64_t g0 = min(ng, (int64_t)threadIdx.x * per), g1 = min(ng, g0 + per);
+  uint32_t s = 0;
+  for (int64_t g = g0; g < g1; ++g) s += CS[g * 256 + d];
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan(s, s_wave, tot);
+  for (int64_t g = g0; g < g1; ++g) {
+    const uint32_t v = CS[g * 256 + d];
+    CS[g * 256 + d] = run;
+    run += v;
+  }
+  if (threadIdx.x == 0) total[d] = tot;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_hist_chunk_down(const uint32_t *__restrict__ H, int64_t nb, const uint32_t *__restrict__ CB,
+                  const uint32_t *__restrict__ total, uint32_t *__restrict__ O) {
+  __shared__ uint32_t s_wave[kWaves];
+  const int64_t g = blockIdx.x;
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan(total[threadIdx.x], s_wave, tot) + CB[g * 256 + threadIdx.x];
+  const int64_t b0 = g * kChunk, b1 = min(nb, b0 + kChunk);
+#pragma unroll 8
+  for (int64_t b = b0; b < b1; ++b) {
+    const uint32_t v = H[b * 256 + threadIdx.x];
+    O[b * 256 + threadIdx.x] = run;
+    run += v;
+  }
 }
 
 // Scatter of one pass.  The block first places its elements in LDS in digit
@@ -156,8 +214,7 @@ __global__ void __launch_bounds__(kThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                 uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                 int64_t count_static, const uint32_t *__restrict__ dcount, int shift,
-                const uint32_t *__restrict__ hist_raw, const uint32_t *__restrict__ hist_scanned,
-                int64_t nb) {
+                const uint32_t *__restrict__ hist_raw, const uint32_t *__restrict__ hist_scanned) {
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_loff[256];
   __shared__ uint32_t s_run[256];
@@ -166,14 +223,14 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
   __shared__ uint32_t s_key[kTile];
   __shared__ uint32_t s_val[kTile];
   const int64_t count = dcount ? (int64_t)*dcount : count_static;
-  const int64_t base = (int64_t)blockIdx.x * kTile;
+  const int64_t blk = sgs_xcd_block(blockIdx.x, gridDim.x);
+  const int64_t base = blk * kTile;
   if (base >= count) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  s_base[threadIdx.x] = hist_scanned[(int64_t)threadIdx.x * nb + blockIdx.x];
+  s_base[threadIdx.x] = hist_scanned[blk * 256 + threadIdx.x];
   {
     uint32_t tot;
-    s_loff[threadIdx.x] =
-        block_exclusive_scan(hist_raw[(int64_t)threadIdx.x * nb + blockIdx.x], s_wave, tot);
+    s_loff[threadIdx.x] = block_exclusive_scan(hist_raw[blk * 256 + threadIdx.x], s_wave, tot);
   }
   s_run[threadIdx.x] = 0;
   // all loads of the block in flight at once
@@ -372,6 +429,12 @@ hipError_t ensure_tmp(sgs_ctx *c, int64_t scan_words, int64_t hist_words) {
   return hipSuccess;
 }
 
+int64_t radix_hist_words(int64_t count) {
+  const int64_t nb = (count + kTile - 1) / kTile;
+  const int64_t ng = (nb + kChunk - 1) / kChunk;
+  return 2 * nb * 256 + ng * 256 + 256 + 1;
+}
+
 // scan_tmp must hold ceil(count / kTile) words
 hipError_t launch_exclusive_scan(sgs_ctx *c, const uint32_t *in, uint32_t *out, int64_t count,
                                  uint32_t *total_out) {
@@ -396,21 +459,20 @@ hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2], i
     return hipSuccess;
   }
   const int64_t hwords = nb * 256;
-  const int64_t snb = (hwords + kTile - 1) / kTile;
-  if (2 * hwords + 1 > c->sort_hist_words || snb > c->scan_tmp_words)
-    return hipErrorInvalidValue;
-  uint32_t *hraw = c->sort_hist, *hscan = c->sort_hist + hwords;
+  const int64_t ng = (nb + kChunk - 1) / kChunk;
+  if (radix_hist_words(count) > c->sort_hist_words) return hipErrorInvalidValue;
+  uint32_t *hraw = c->sort_hist, *hscan = hraw + hwords, *chunk = hscan + hwords;
+  uint32_t *total = chunk + ng * 256;
   for (int shift = 0; shift < bits; shift += 8) {
-    k_radix_hist<<<(unsigned)nb, kThreads, 0, c->stream>>>(keys[cur], count, dcount, shift, hraw,
-                                                           nb);
-    // exclusive scan of the digit-major histogram (raw counts kept for the
-    // block-local placement)
-    k_scan_reduce<<<(unsigned)snb, kThreads, 0, c->stream>>>(hraw, hwords, c->scan_tmp);
-    k_scan_sums<<<1, kThreads, 0, c->stream>>>(c->scan_tmp, snb, nullptr, nullptr);
-    k_scan_down<<<(unsigned)snb, kThreads, 0, c->stream>>>(hraw, hwords, c->scan_tmp, hscan);
+    k_radix_hist<<<(unsigned)nb, kThreads, 0, c->stream>>>(keys[cur], count, dcount, shift, hraw);
+    // digit offsets of every block (raw counts kept for the block-local
+    // placement)
+    k_hist_chunk_sums<<<(unsigned)ng, kThreads, 0, c->stream>>>(hraw, nb, chunk);
+    k_hist_chunk_scan<<<256, kThreads, 0, c->stream>>>(chunk, ng, total);
+    k_hist_chunk_down<<<(unsigned)ng, kThreads, 0, c->stream>>>(hraw, nb, chunk, total, hscan);
     k_radix_scatter<<<(unsigned)nb, kThreads, 0, c->stream>>>(keys[cur], vals[cur], keys[cur ^ 1],
                                                               vals[cur ^ 1], count, dcount,
-                                                              shift, hraw, hscan, nb);
+                                                              shift, hraw, hscan);
     cur ^= 1;
   }
   *which = cur;
