@@ -56,6 +56,10 @@ void free_scene(sgs_ctx *c) {
   }
   dfree(c->touched);
   dfree(c->offsets);
+  dfree(c->bin_rec);
+  dfree(c->bin_splat);
+  dfree(c->blk_start);
+  c->blk_start_words = 0;
   dfree(c->splat_grad);
   dfree(c->ranges);
   dfree(c->scan_tmp);
@@ -77,6 +81,8 @@ hipError_t grow_pairs(sgs_ctx *c, int64_t P) {
     dfree(c->tile_key[k]);
     dfree(c->pair_val[k]);
   }
+  dfree(c->blk_start);
+  c->blk_start_words = 0;
   c->pair_cap = 0;
   for (int k = 0; k < 2; ++k) {
     hipError_t e = dalloc(&c->tile_key[k], cap);
@@ -84,6 +90,10 @@ hipError_t grow_pairs(sgs_ctx *c, int64_t P) {
     e = dalloc(&c->pair_val[k], cap);
     if (e != hipSuccess) return e;
   }
+  const int64_t nbs = radix_blocks(cap) + 1;
+  hipError_t eb = dalloc(&c->blk_start, nbs);
+  if (eb != hipSuccess) return eb;
+  c->blk_start_words = nbs;
   const int64_t hist = radix_hist_words(cap);
   hipError_t e = ensure_tmp(c, c->scan_tmp_words, hist);
   if (e != hipSuccess) return e;
@@ -192,6 +202,8 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   }
   SGS_ALLOC(c->touched, vn);
   SGS_ALLOC(c->offsets, vn + 1);
+  SGS_ALLOC(c->bin_rec, vn);
+  SGS_ALLOC(c->bin_splat, vn);
   SGS_ALLOC(c->splat_grad, vn * SGS_SGRAD);
   SGS_ALLOC(c->ranges, c->total_tiles);
   SGS_ALLOC(c->d_pairs_total, 4);
@@ -262,6 +274,8 @@ sgs_status sgs_render_fwd(sgs_ctx *c, const float *qparams, const uint8_t *hard_
             "render_fwd pair count");
     SGS_HIP(hipStreamSynchronize(c->stream), "render_fwd pair count");
     c->pairs = *c->h_pairs_total;
+    if (c->pairs == (int64_t)kPairsSaturated)
+      return fail(c, SGS_ECAPACITY, "render_fwd: 2^32 - 1 or more (tile, Gaussian) pairs");
     hipError_t e = grow_pairs(c, c->pairs);
     if (e != hipSuccess) return hip_fail(c, e, "render_fwd pair buffers");
   }

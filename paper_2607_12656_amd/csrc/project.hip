@@ -45,7 +45,8 @@ k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
              const sgs_camera *__restrict__ cams, const float *__restrict__ qp,
              const uint8_t *__restrict__ hard, float4 *__restrict__ rec,
              uint32_t *__restrict__ depth_key, uint32_t *__restrict__ depth_val,
-             uint32_t *__restrict__ touched) {
+             uint32_t *__restrict__ touched, uint4 *__restrict__ bins, int GW,
+             int64_t tiles_per_view) {
   const int64_t i = (int64_t)blockIdx.x * kPThreads + threadIdx.x;
   if (i >= n) return;
   float y[SGS_NCH];
@@ -63,13 +64,18 @@ k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
     if (!p.valid) {
       depth_key[s] = 0xFFFFFFFFu;
       touched[s] = 0;
+      bins[s] = make_uint4(0u, 1u, 0u, 0u);
       rec[3 * s] = make_float4(0.f, 0.f, 0.f, 0.f);
       rec[3 * s + 1] = make_float4(0.f, 0.f, __int_as_float(-1), __int_as_float(-1));
       rec[3 * s + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
       continue;
     }
     depth_key[s] = __float_as_uint(p.tz);
-    touched[s] = (uint32_t)((p.x1 / TW - p.x0 / TW + 1) * (p.y1 / TH - p.y0 / TH + 1));
+    const int tw = p.x1 / TW - p.x0 / TW + 1, th = p.y1 / TH - p.y0 / TH + 1;
+    touched[s] = (uint32_t)(tw * th);
+    // binning record: first tile id, rectangle width in tiles, Gaussian, pairs
+    bins[s] = make_uint4((uint32_t)(v * tiles_per_view) + (uint32_t)((p.y0 / TH) * GW + p.x0 / TW),
+                         (uint32_t)tw, (uint32_t)i, (uint32_t)(tw * th));
     const float A = p.c / p.det, B = -p.b / p.det, C = p.a / p.det;
     float col[3];
     bool cl[3];
@@ -254,7 +260,7 @@ hipError_t launch_preprocess(sgs_ctx *c, const float *qparams, const uint8_t *ha
   SgsProfScope ps(c, SGS_PROF_PREPROCESS);
   k_preprocess<<<sgs_blocks(c->n, kPThreads), kPThreads, 0, c->stream>>>(
       c->n, c->npad, c->V, c->W, c->H, c->TW, c->TH, c->d_cams, qparams, hard, c->rec,
-      c->depth_key[0], c->depth_val[0], c->touched);
+      c->depth_key[0], c->depth_val[0], c->touched, c->bin_splat, c->GW, c->tiles_per_view);
   return hipGetLastError();
 }
 

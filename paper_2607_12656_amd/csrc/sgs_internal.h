@@ -52,6 +52,8 @@ struct sgs_ctx {
   uint32_t *depth_val[2] = {nullptr, nullptr};
   uint32_t *touched = nullptr;    // [vn] tiles per splat (0 = culled)
   uint32_t *offsets = nullptr;    // [vn + 1] exclusive scan in depth order
+  uint4 *bin_splat = nullptr;     // [vn] (first tile id, width in tiles, Gaussian, pairs)
+  uint4 *bin_rec = nullptr;       // [vn] the same records in depth order
   float *splat_grad = nullptr;    // [vn][SGS_SGRAD]
   int depth_sorted_buf = 0;       // which depth buffer holds the sorted order
 
@@ -61,6 +63,8 @@ struct sgs_ctx {
   uint32_t *tile_key[2] = {nullptr, nullptr};
   uint32_t *pair_val[2] = {nullptr, nullptr};
   int pair_sorted_buf = 0;
+  uint32_t *blk_start = nullptr;  // first splat (depth order) of every block of sorted pairs
+  int64_t blk_start_words = 0;
   uint2 *ranges = nullptr;        // [total_tiles]
 
   // reusable temporaries
@@ -134,14 +138,19 @@ hipError_t launch_preprocess_bwd(sgs_ctx *c, const float *qparams, float *grad_q
                                  float *grad_mask);
 // sort.hip
 hipError_t ensure_tmp(sgs_ctx *c, int64_t scan_words, int64_t hist_words);
+// Pair total reported when the true total does not fit in 32 bits (the
+// offsets are then meaningless and no pair is emitted).
+constexpr uint32_t kPairsSaturated = 0xFFFFFFFFu;
+int64_t radix_blocks(int64_t count);       // blocks of a radix pass over count elements
 int64_t radix_hist_words(int64_t count);   // sort_hist words a radix sort of count needs
 hipError_t launch_exclusive_scan(sgs_ctx *c, const uint32_t *in, uint32_t *out,
                                  int64_t count, uint32_t *total_out);
 // Stable LSD radix sort of 32-bit keys with 32-bit values over bits
-// [0, bits); ping-pongs between buffer 0 and 1; returns the buffer index that
-// holds the result in *which.
+// [shift0, bits) starting in buffer cur0; ping-pongs between buffer 0 and 1;
+// returns the buffer index that holds the result in *which.
 hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2],
-                             int64_t count, int bits, int *which, const uint32_t *dcount);
+                             int64_t count, int bits, int *which, const uint32_t *dcount,
+                             int shift0 = 0, int cur0 = 0);
 hipError_t launch_bin_pairs(sgs_ctx *c);   // depth order -> pairs -> tile sort -> ranges
 hipError_t launch_depth_order(sgs_ctx *c); // depth sort + scan (writes d_pairs_total)
 // blend.hip

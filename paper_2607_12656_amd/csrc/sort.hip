@@ -63,18 +63,19 @@ __global__ void __launch_bounds__(kThreads)
 k_scan_sums(uint32_t *__restrict__ sums, int64_t nb, uint32_t *__restrict__ total_out,
             uint32_t *__restrict__ tail) {
   __shared__ uint32_t s_wave[kWaves];
-  uint32_t carry = 0;
+  uint64_t carry = 0;  // a block sum fits in 32 bits, the total may not
   for (int64_t base = 0; base < nb; base += kThreads) {
     const int64_t i = base + threadIdx.x;
     const uint32_t v = i < nb ? sums[i] : 0;
     uint32_t total;
     const uint32_t ex = block_exclusive_scan(v, s_wave, total);
-    if (i < nb) sums[i] = carry + ex;
+    if (i < nb) sums[i] = (uint32_t)(carry + ex);
     carry += total;
   }
   if (threadIdx.x == 0) {
-    if (total_out) *total_out = carry;
-    if (tail) *tail = carry;
+    const uint32_t t = carry >= kPairsSaturated ? kPairsSaturated : (uint32_t)carry;
+    if (total_out) *total_out = t;
+    if (tail) *tail = t;
   }
 }
 
@@ -207,40 +208,36 @@ k_hist_chunk_down(const uint32_t *__restrict__ H, int64_t nb, const uint32_t *__
   }
 }
 
-// Scatter of one pass.  The block first places its elements in LDS in digit
-// order (stable), then writes each digit's run to its global position with
+// LDS index with one pad word per 16: a thread's run of kItems consecutive
+// elements and a round of consecutive threads both spread over the banks.
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+constexpr int kTilePad = kTile + kTile / 16;
+
+// Scatter of one pass for the block's elements, held in rounds (element
+// base + r*256 + tid in kr[r], vr[r]).  Ranks follow (round, wave, lane) =
+// input order; the block first places its elements in LDS in digit order
+// (stable), then writes each digit's run to its global position with
 // consecutive threads on consecutive addresses (coalesced).
-__global__ void __launch_bounds__(kThreads)
-k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-                uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
-                int64_t count_static, const uint32_t *__restrict__ dcount, int shift,
-                const uint32_t *__restrict__ hist_raw, const uint32_t *__restrict__ hist_scanned) {
+// h_raw / h_scan: this thread's digit (= tid) entries of the block's raw and
+// scanned histogram rows, loaded by the caller ahead of its other work.
+__device__ __forceinline__ void scatter_block(const uint32_t (&kr)[kItems],
+                                              const uint32_t (&vr)[kItems], int64_t base,
+                                              int64_t count, int shift, uint32_t h_raw,
+                                              uint32_t h_scan, uint32_t *__restrict__ kout,
+                                              uint32_t *__restrict__ vout, uint32_t *s_key,
+                                              uint32_t *s_val) {
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_loff[256];
   __shared__ uint32_t s_run[256];
   __shared__ uint32_t s_wc[kWaves][256];
   __shared__ uint32_t s_wave[kWaves];
-  __shared__ uint32_t s_key[kTile];
-  __shared__ uint32_t s_val[kTile];
-  const int64_t count = dcount ? (int64_t)*dcount : count_static;
-  const int64_t blk = sgs_xcd_block(blockIdx.x, gridDim.x);
-  const int64_t base = blk * kTile;
-  if (base >= count) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  s_base[threadIdx.x] = hist_scanned[blk * 256 + threadIdx.x];
+  s_base[threadIdx.x] = h_scan;
   {
     uint32_t tot;
-    s_loff[threadIdx.x] = block_exclusive_scan(hist_raw[blk * 256 + threadIdx.x], s_wave, tot);
+    s_loff[threadIdx.x] = block_exclusive_scan(h_raw, s_wave, tot);
   }
   s_run[threadIdx.x] = 0;
-  // all loads of the block in flight at once
-  uint32_t kr[kItems], vr[kItems];
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
-    kr[r] = i < count ? kin[i] : 0u;
-    vr[r] = i < count ? vin[i] : 0u;
-  }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
@@ -275,6 +272,7 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
     __syncthreads();
   }
   const int nloc = (int)min((int64_t)kTile, count - base);
+#pragma unroll 4
   for (int p = threadIdx.x; p < nloc; p += kThreads) {
     const uint32_t k = s_key[p];
     const uint32_t d = (k >> shift) & 0xFFu;
@@ -284,76 +282,213 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
   }
 }
 
-// ---------------------------------------------------------------------------
-// Binning
-// ---------------------------------------------------------------------------
-__global__ void k_gather_touched(const uint32_t *__restrict__ order,
-                                 const uint32_t *__restrict__ touched, int64_t count,
-                                 uint32_t *__restrict__ out) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < count) out[k] = touched[order[k]];
+__global__ void __launch_bounds__(kThreads)
+k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                int64_t count_static, const uint32_t *__restrict__ dcount, int shift,
+                const uint32_t *__restrict__ hist_raw, const uint32_t *__restrict__ hist_scanned) {
+  __shared__ uint32_t s_key[kTile];
+  __shared__ uint32_t s_val[kTile];
+  const int64_t count = dcount ? (int64_t)*dcount : count_static;
+  const int64_t blk = sgs_xcd_block(blockIdx.x, gridDim.x);
+  const int64_t base = blk * kTile;
+  if (base >= count) return;
+  // all loads of the block in flight at once
+  const uint32_t h_raw = hist_raw[blk * 256 + threadIdx.x];
+  const uint32_t h_scan = hist_scanned[blk * 256 + threadIdx.x];
+  uint32_t kr[kItems], vr[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+    kr[r] = i < count ? kin[i] : 0u;
+    vr[r] = i < count ? vin[i] : 0u;
+  }
+  scatter_block(kr, vr, base, count, shift, h_raw, h_scan, kout, vout, s_key, s_val);
 }
 
-// Emit the pairs of the splats in depth order; the value is the Gaussian
-// index, the key the global tile id.  Load-balanced: a block takes 256
-// consecutive splats, stages their pair offsets in LDS, and its threads
-// emit consecutive pairs (finding the owning splat by binary search), so the
-// writes are contiguous.  Pairs at or beyond `cap` are not written (the
-// count clamp reports the overflow); all pairs below it are.
-constexpr int kDupSplats = 256;
-__global__ void __launch_bounds__(kDupSplats)
-k_duplicate(const uint32_t *__restrict__ order, const uint32_t *__restrict__ touched,
-            const uint32_t *__restrict__ offsets, const float4 *__restrict__ rec, int64_t count,
-            int64_t n, int TW, int TH, int GW, int64_t tiles_per_view, int64_t cap,
-            uint32_t *__restrict__ tile_key, uint32_t *__restrict__ pair_val) {
-  __shared__ uint32_t s_off[kDupSplats];   // pair offset relative to the block's first
-  __shared__ uint32_t s_tile0[kDupSplats]; // global id of the first tile of the rectangle
-  __shared__ uint16_t s_w[kDupSplats];     // tiles per rectangle row
-  __shared__ uint32_t s_gi[kDupSplats];
-  __shared__ uint32_t s_total;
-  const int64_t k0 = (int64_t)blockIdx.x * kDupSplats;
-  const int64_t k = k0 + threadIdx.x;
-  const uint32_t base = offsets[k0];
-  uint32_t off = 0xFFFFFFFFu, tile0 = 0, gi = 0;
-  uint16_t w = 1;
-  if (k < count) {
-    off = offsets[k] - base;
-    const uint32_t s = order[k];
-    if (touched[s] != 0) {
-      const float4 r = rec[3 * (int64_t)s + 1];
-      const uint32_t sx = __float_as_uint(r.z), sy = __float_as_uint(r.w);
-      const int tx0 = (int)(sx & 0xFFFF) / TW, tx1 = (int)(sx >> 16) / TW;
-      const int ty0 = (int)(sy & 0xFFFF) / TH;
-      const uint32_t v = (uint32_t)(s / n);
-      gi = (uint32_t)(s - (int64_t)v * n);
-      w = (uint16_t)(tx1 - tx0 + 1);
-      tile0 = (uint32_t)(v * tiles_per_view) + (uint32_t)(ty0 * GW + tx0);
-    }
+// ---------------------------------------------------------------------------
+// Binning: pair emission fused with the first digit pass
+// ---------------------------------------------------------------------------
+// The pairs of the splats in depth order (key: global tile id, value:
+// Gaussian index) are never written in emission order: the kernels below
+// generate them on the fly from one 16-byte record per splat, once to count
+// the low digit per block and once to scatter them by that digit.
+
+// Binning records in depth order (the only gather of splat data in that
+// order) and the pair counts, input of the offsets scan.
+__global__ void k_gather_bins(const uint32_t *__restrict__ order,
+                              const uint4 *__restrict__ bin_splat, int64_t count,
+                              uint32_t *__restrict__ cnt_out, uint4 *__restrict__ brec) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const uint4 b = bin_splat[order[k]];
+  cnt_out[k] = b.w;
+  brec[k] = b;
+}
+
+// First splat (in depth order) of every block of kTile pairs: the block
+// starting inside splat k's pair range records k.
+__global__ void k_block_starts(const uint32_t *__restrict__ offsets, int64_t vn,
+                               int64_t count_static, const uint32_t *__restrict__ dcount,
+                               uint32_t *__restrict__ bstart) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= vn) return;
+  const int64_t count = dcount ? (int64_t)*dcount : count_static;
+  const int64_t a = offsets[k];
+  const int64_t e = min((int64_t)offsets[k + 1], count);
+  for (int64_t b = (a + kTile - 1) / kTile; b * kTile < e; ++b) bstart[b] = (uint32_t)k;
+}
+
+// Pairs base + tid*kItems + j, j < kItems (those below count) of the
+// depth-ordered emission: key = first tile + row * GW + column inside the
+// splat's tile rectangle (row-major), value = Gaussian index.  The block's
+// splats are [klo, khi] (khi = the splat of the next block's first pair, or
+// the last splat); each of them marks the threads whose first pair it owns,
+// so no thread searches.  When the block spans at most kWin splats their
+// offsets and records are staged in LDS (`win`, 16-byte aligned, kWinWords
+// words, free again on return) and the walk reads nothing else; otherwise
+// it reads them from global memory.  Splats without pairs own no pair and
+// are passed over.
+constexpr int kWin = 512;
+constexpr int kWinWords = 4 * kWin + kWin + 1;
+
+__device__ __forceinline__ void gen_block(const uint32_t *__restrict__ offsets,
+                                          const uint4 *__restrict__ brec,
+                                          const uint32_t *__restrict__ bstart, int64_t blk,
+                                          int64_t base, int64_t count, int64_t vn, int GW,
+                                          uint32_t *win, uint32_t (&key)[kItems],
+                                          uint32_t (&val)[kItems]) {
+  __shared__ uint32_t s_k[kThreads];
+  const int64_t nb_live = (count + kTile - 1) / kTile;
+  const int64_t klo = bstart[blk];
+  const int64_t khi = blk + 1 < nb_live ? (int64_t)bstart[blk + 1] : vn - 1;
+  const int64_t m = khi - klo + 1;
+  const bool staged = m <= kWin;  // uniform over the block
+  uint4 *w_rec = reinterpret_cast<uint4 *>(win);
+  uint32_t *w_off = win + 4 * kWin;
+  if (staged) {
+    for (int i = threadIdx.x; i <= m; i += kThreads) w_off[i] = offsets[klo + i];
+    for (int i = threadIdx.x; i < m; i += kThreads) w_rec[i] = brec[klo + i];
+    __syncthreads();
   }
-  s_off[threadIdx.x] = off;
-  s_tile0[threadIdx.x] = tile0;
-  s_w[threadIdx.x] = w;
-  s_gi[threadIdx.x] = gi;
-  if (threadIdx.x == kDupSplats - 1 || k == count - 1) {
-    if (k < count) s_total = offsets[k] - base + touched[order[k]];
+  for (int64_t i = threadIdx.x; i < m; i += kThreads) {
+    const int64_t a = staged ? w_off[i] : offsets[klo + i];
+    const int64_t e = staged ? w_off[i + 1] : offsets[klo + i + 1];
+    // threads tt whose first pair base + tt*kItems lies in [a, e)
+    int64_t t0 = a <= base ? 0 : (a - base + kItems - 1) / kItems;
+    const int64_t t1 = min((int64_t)kThreads, e <= base ? 0 : (e - base + kItems - 1) / kItems);
+    for (; t0 < t1; ++t0) s_k[t0] = (uint32_t)i;
   }
   __syncthreads();
-  const uint32_t total = s_total;
-  for (uint32_t p = threadIdx.x; p < total; p += kDupSplats) {
-    if ((int64_t)base + p >= cap) break;
-    // last splat j with s_off[j] <= p (offsets are non-decreasing; splats
-    // with no pairs share the next one's offset and are skipped by <=)
-    int lo = 0, hi = kDupSplats - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_off[mid] <= p) lo = mid; else hi = mid - 1;
-    }
-    const uint32_t e = p - s_off[lo];
-    const uint32_t wj = s_w[lo];
-    const uint32_t t = s_tile0[lo] + (e / wj) * (uint32_t)GW + (e % wj);
-    tile_key[base + p] = t;
-    pair_val[base + p] = s_gi[lo];
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    key[j] = 0u;
+    val[j] = 0u;
   }
+  const int64_t p = base + (int64_t)threadIdx.x * kItems;
+  if (p < count) {
+    // pair indices fit in 32 bits (the pair capacity is below 2^32)
+    const uint32_t p32 = (uint32_t)p, n32 = (uint32_t)min(count - p, (int64_t)kItems);
+    int i = (int)s_k[threadIdx.x];  // splat index relative to klo
+    uint4 b = staged ? w_rec[i] : brec[klo + i];
+    uint32_t next = staged ? w_off[i + 1] : offsets[klo + i + 1];
+    const uint32_t e = p32 - (staged ? w_off[i] : offsets[klo + i]);
+    uint32_t row = e / b.y, col = e - row * b.y;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const uint32_t q = p32 + (uint32_t)j;
+      if ((uint32_t)j < n32) {
+        while (q >= next) {  // ends: q < count <= offsets[vn], and i stays below m
+          ++i;
+          b = staged ? w_rec[i] : brec[klo + i];
+          next = staged ? w_off[i + 1] : offsets[klo + i + 1];
+          row = 0;
+          col = 0;
+        }
+        key[j] = b.x + row * (uint32_t)GW + col;
+        val[j] = b.z;
+        if (++col == b.y) {
+          col = 0;
+          ++row;
+        }
+      }
+    }
+  }
+  __syncthreads();  // win and s_k free again
+}
+
+// Low-digit histogram of the generated pairs of each block (sub-histograms
+// as in k_radix_hist).
+__global__ void __launch_bounds__(kThreads)
+k_gen_hist(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ brec,
+           const uint32_t *__restrict__ bstart, int64_t vn, int64_t count_static,
+           const uint32_t *__restrict__ dcount, int GW, uint32_t *__restrict__ hist) {
+  // the sub-histograms double as the generator's LDS window
+  __shared__ __align__(16) uint32_t s_sub[kThreads / 8][257];
+  static_assert((kThreads / 8) * 257 >= kWinWords, "window does not fit");
+  const int64_t count = dcount ? (int64_t)*dcount : count_static;
+  const int64_t blk = sgs_xcd_block(blockIdx.x, gridDim.x);
+  const int64_t base = blk * kTile;
+  if (base >= count) {
+    hist[blk * 256 + threadIdx.x] = 0;
+    return;
+  }
+  const int64_t p = base + (int64_t)threadIdx.x * kItems;
+  uint32_t key[kItems], val[kItems];
+  gen_block(offsets, brec, bstart, blk, base, count, vn, GW, &s_sub[0][0], key, val);
+#pragma unroll
+  for (int w = 0; w < kThreads / 8; ++w) s_sub[w][threadIdx.x] = 0;
+  __syncthreads();
+  uint32_t *mine = s_sub[threadIdx.x >> 3];
+#pragma unroll
+  for (int j = 0; j < kItems; ++j)
+    if (p + j < count) atomicAdd(&mine[key[j] & 0xFFu], 1u);
+  __syncthreads();
+  uint32_t tot = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 8; ++w) tot += s_sub[w][threadIdx.x];
+  hist[blk * 256 + threadIdx.x] = tot;
+}
+
+// Generated pairs of each block scattered by their low digit.  Threads
+// generate runs of kItems consecutive pairs; LDS transposes them into the
+// round layout of scatter_block.
+__global__ void __launch_bounds__(kThreads)
+k_gen_scatter(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ brec,
+              const uint32_t *__restrict__ bstart, int64_t vn, int64_t count_static,
+              const uint32_t *__restrict__ dcount, int GW,
+              const uint32_t *__restrict__ hist_raw, const uint32_t *__restrict__ hist_scanned,
+              uint32_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+  // s_key doubles as the generator's LDS window
+  __shared__ __align__(16) uint32_t s_key[kTilePad];
+  __shared__ uint32_t s_val[kTilePad];
+  static_assert(kTilePad >= kWinWords, "window does not fit");
+  const int64_t count = dcount ? (int64_t)*dcount : count_static;
+  const int64_t blk = sgs_xcd_block(blockIdx.x, gridDim.x);
+  const int64_t base = blk * kTile;
+  if (base >= count) return;
+  const uint32_t h_raw = hist_raw[blk * 256 + threadIdx.x];
+  const uint32_t h_scan = hist_scanned[blk * 256 + threadIdx.x];
+  {
+    uint32_t key[kItems], val[kItems];
+    gen_block(offsets, brec, bstart, blk, base, count, vn, GW, s_key, key, val);
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int li = lds_pad(threadIdx.x * kItems + j);
+      s_key[li] = key[j];
+      s_val[li] = val[j];
+    }
+  }
+  __syncthreads();
+  uint32_t kr[kItems], vr[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int li = lds_pad(r * kThreads + threadIdx.x);
+    kr[r] = s_key[li];
+    vr[r] = s_val[li];
+  }
+  __syncthreads();
+  scatter_block(kr, vr, base, count, 0, h_raw, h_scan, kout, vout, s_key, s_val);
 }
 
 __global__ void k_zero_ranges(uint2 *__restrict__ ranges, int64_t tiles) {
@@ -405,7 +540,8 @@ __global__ void k_ranges(const uint32_t *__restrict__ tile_key, int64_t P_static
 __global__ void k_clamp_count(uint32_t *__restrict__ counts, int64_t cap) {
   if (threadIdx.x != 0) return;
   const int64_t total = counts[0];
-  counts[1] = (uint32_t)(total < cap ? total : cap);
+  // a saturated total leaves the offsets wrapped: emit nothing
+  counts[1] = total == kPairsSaturated ? 0u : (uint32_t)(total < cap ? total : cap);
   if (total > cap) counts[2] |= 1u;
 }
 
@@ -429,6 +565,8 @@ hipError_t ensure_tmp(sgs_ctx *c, int64_t scan_words, int64_t hist_words) {
   return hipSuccess;
 }
 
+int64_t radix_blocks(int64_t count) { return (count + kTile - 1) / kTile; }
+
 int64_t radix_hist_words(int64_t count) {
   const int64_t nb = (count + kTile - 1) / kTile;
   const int64_t ng = (nb + kChunk - 1) / kChunk;
@@ -450,36 +588,60 @@ hipError_t launch_exclusive_scan(sgs_ctx *c, const uint32_t *in, uint32_t *out, 
   return hipGetLastError();
 }
 
+namespace {
+
+struct SortBufs {
+  int64_t nb, ng;
+  uint32_t *hraw, *hscan, *chunk, *total;
+};
+
+bool sort_bufs(sgs_ctx *c, int64_t count, SortBufs &b) {
+  b.nb = (count + kTile - 1) / kTile;
+  b.ng = (b.nb + kChunk - 1) / kChunk;
+  if (radix_hist_words(count) > c->sort_hist_words) return false;
+  b.hraw = c->sort_hist;
+  b.hscan = b.hraw + b.nb * 256;
+  b.chunk = b.hscan + b.nb * 256;
+  b.total = b.chunk + b.ng * 256;
+  return true;
+}
+
+// Digit offsets of every block from the raw block histograms (raw counts kept
+// for the block-local placement).
+void launch_digit_offsets(sgs_ctx *c, const SortBufs &b) {
+  k_hist_chunk_sums<<<(unsigned)b.ng, kThreads, 0, c->stream>>>(b.hraw, b.nb, b.chunk);
+  k_hist_chunk_scan<<<256, kThreads, 0, c->stream>>>(b.chunk, b.ng, b.total);
+  k_hist_chunk_down<<<(unsigned)b.ng, kThreads, 0, c->stream>>>(b.hraw, b.nb, b.chunk, b.total,
+                                                                b.hscan);
+}
+
+}  // namespace
+
+// Passes shift0, shift0 + 8, ... < bits of the stable LSD sort; the data
+// starts in buffer cur0 and *which receives the buffer holding the result.
 hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2], int64_t count,
-                             int bits, int *which, const uint32_t *dcount) {
-  int cur = 0;
-  const int64_t nb = (count + kTile - 1) / kTile;
-  if (count <= 1 || bits <= 0) {
-    *which = 0;
-    return hipSuccess;
-  }
-  const int64_t hwords = nb * 256;
-  const int64_t ng = (nb + kChunk - 1) / kChunk;
-  if (radix_hist_words(count) > c->sort_hist_words) return hipErrorInvalidValue;
-  uint32_t *hraw = c->sort_hist, *hscan = hraw + hwords, *chunk = hscan + hwords;
-  uint32_t *total = chunk + ng * 256;
-  for (int shift = 0; shift < bits; shift += 8) {
-    k_radix_hist<<<(unsigned)nb, kThreads, 0, c->stream>>>(keys[cur], count, dcount, shift, hraw);
-    // digit offsets of every block (raw counts kept for the block-local
-    // placement)
-    k_hist_chunk_sums<<<(unsigned)ng, kThreads, 0, c->stream>>>(hraw, nb, chunk);
-    k_hist_chunk_scan<<<256, kThreads, 0, c->stream>>>(chunk, ng, total);
-    k_hist_chunk_down<<<(unsigned)ng, kThreads, 0, c->stream>>>(hraw, nb, chunk, total, hscan);
-    k_radix_scatter<<<(unsigned)nb, kThreads, 0, c->stream>>>(keys[cur], vals[cur], keys[cur ^ 1],
-                                                              vals[cur ^ 1], count, dcount,
-                                                              shift, hraw, hscan);
+                             int bits, int *which, const uint32_t *dcount, int shift0,
+                             int cur0) {
+  int cur = cur0;
+  *which = cur0;
+  if (count <= 1 || shift0 >= bits) return hipSuccess;
+  SortBufs b;
+  if (!sort_bufs(c, count, b)) return hipErrorInvalidValue;
+  for (int shift = shift0; shift < bits; shift += 8) {
+    k_radix_hist<<<(unsigned)b.nb, kThreads, 0, c->stream>>>(keys[cur], count, dcount, shift,
+                                                             b.hraw);
+    launch_digit_offsets(c, b);
+    k_radix_scatter<<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
+        keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, b.hraw,
+        b.hscan);
     cur ^= 1;
   }
   *which = cur;
   return hipGetLastError();
 }
 
-// Depth sort of all (view, Gaussian) splats, then the pair offsets.
+// Depth sort of all (view, Gaussian) splats, the binning records in depth
+// order, then the pair offsets.
 hipError_t launch_depth_order(sgs_ctx *c) {
   int which = 0;
   {
@@ -489,10 +651,10 @@ hipError_t launch_depth_order(sgs_ctx *c) {
   }
   c->depth_sorted_buf = which;
   SgsProfScope ps(c, SGS_PROF_SCAN);
-  // touched in depth order -> scratch (the other key buffer is free now)
+  // pair counts in depth order -> scratch (the other key buffer is free now)
   uint32_t *tmp = c->depth_key[which ^ 1];
-  k_gather_touched<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(c->depth_val[which],
-                                                                  c->touched, c->vn, tmp);
+  k_gather_bins<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(c->depth_val[which], c->bin_splat,
+                                                               c->vn, tmp, c->bin_rec);
   return launch_exclusive_scan(c, tmp, c->offsets, c->vn, c->d_pairs_total);
 }
 
@@ -504,20 +666,29 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
   const int64_t cap = dev ? c->cap_limit : c->pair_cap;
   const int64_t P = dev ? cap : c->pairs;
   const uint32_t *dcount = dev ? c->d_pairs_total + 1 : nullptr;
-  const uint32_t *order = c->depth_val[c->depth_sorted_buf];
   {
+    // pair emission fused with the pass over the low digit: buffer 1
     SgsProfScope ps(c, SGS_PROF_DUPLICATE);
     if (dev) k_clamp_count<<<1, 64, 0, c->stream>>>(c->d_pairs_total, cap);
-    k_duplicate<<<sgs_blocks(c->vn, kDupSplats), kDupSplats, 0, c->stream>>>(
-        order, c->touched, c->offsets, c->rec, c->vn, c->n, c->TW, c->TH, c->GW,
-        c->tiles_per_view, cap, c->tile_key[0], c->pair_val[0]);
+    if (P > 0) {
+      SortBufs b;
+      if (!sort_bufs(c, P, b) || b.nb + 1 > c->blk_start_words) return hipErrorInvalidValue;
+      k_block_starts<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(c->offsets, c->vn, P, dcount,
+                                                                    c->blk_start);
+      k_gen_hist<<<(unsigned)b.nb, kThreads, 0, c->stream>>>(c->offsets, c->bin_rec, c->blk_start,
+                                                             c->vn, P, dcount, c->GW, b.hraw);
+      launch_digit_offsets(c, b);
+      k_gen_scatter<<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
+          c->offsets, c->bin_rec, c->blk_start, c->vn, P, dcount, c->GW, b.hraw, b.hscan,
+          c->tile_key[1], c->pair_val[1]);
+    }
   }
   int bits = 0;
   while (((int64_t)1 << bits) < c->total_tiles) ++bits;
-  int which = 0;
+  int which = 1;
   {
     SgsProfScope ps(c, SGS_PROF_TILE_SORT);
-    hipError_t e = launch_radix_sort(c, c->tile_key, c->pair_val, P, bits, &which, dcount);
+    hipError_t e = launch_radix_sort(c, c->tile_key, c->pair_val, P, bits, &which, dcount, 8, 1);
     if (e != hipSuccess) return e;
   }
   c->pair_sorted_buf = which;
