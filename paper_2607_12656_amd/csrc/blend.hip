@@ -25,51 +25,58 @@ struct SplatLds {
   float4 c;  // r, g, b, mask
 };
 
-__device__ __forceinline__ bool span_meets(const SplatLds &s, int sx0, int sy0) {
+// Evaluation of splat s at pixel (px, py), branch-free: every lane computes
+// every value and `ok` says whether the pair contributes (pixel inside the
+// splat's pixel span, exponent not positive, alpha >= 1/255).  The forward and
+// the backward call the same code so both see bit-identical values.
+struct SplatEval {
+  bool in_span, ok, clamped;
+  float alpha, G, dx, dy;
+};
+
+__device__ __forceinline__ SplatEval eval_splat(const SplatLds &s, int px, int py, float fx,
+                                                float fy) {
+  SplatEval r;
   const uint32_t sx = __float_as_uint(s.b.z), sy = __float_as_uint(s.b.w);
-  return (int)(sx & 0xFFFF) <= sx0 + 7 && (int)(sx >> 16) >= sx0 &&
-         (int)(sy & 0xFFFF) <= sy0 + 7 && (int)(sy >> 16) >= sy0;
+  r.in_span = (px >= (int)(sx & 0xFFFF)) && (px <= (int)(sx >> 16)) &&
+              (py >= (int)(sy & 0xFFFF)) && (py <= (int)(sy >> 16));
+  r.dx = fx - s.a.x;
+  r.dy = fy - s.a.y;
+  const float q1 = s.a.z * r.dx * r.dx;
+  const float q2 = s.b.x * r.dy * r.dy;
+  const float q3 = s.a.w * r.dx * r.dy;
+  const float power = -0.5f * (q1 + q2) - q3;
+  r.G = __expf(power);
+  const float raw = s.b.y * r.G;
+  r.clamped = raw > SGS_ALPHA_MAX;
+  r.alpha = r.clamped ? SGS_ALPHA_MAX : raw;
+  r.ok = r.in_span && !(power > 0.0f) && r.alpha >= SGS_ALPHA_MIN;
+  return r;
 }
 
-// alpha of splat `s` at pixel (px, py); the forward and the backward call the
-// same code so both see bit-identical values.  Returns false when the pixel is
-// outside the splat's pixel span, the exponent is positive or alpha < 1/255.
-__device__ __forceinline__ bool splat_alpha(const SplatLds &s, int px, int py, float fx,
-                                            float fy, bool &in_span, float &alpha, float &G,
-                                            bool &clamped, float &dx, float &dy) {
-  const uint32_t sx = __float_as_uint(s.b.z), sy = __float_as_uint(s.b.w);
-  in_span = (px >= (int)(sx & 0xFFFF)) && (px <= (int)(sx >> 16)) &&
-            (py >= (int)(sy & 0xFFFF)) && (py <= (int)(sy >> 16));
-  if (!in_span) return false;
-  dx = fx - s.a.x;
-  dy = fy - s.a.y;
-  const float q1 = s.a.z * dx * dx;
-  const float q2 = s.b.x * dy * dy;
-  const float q3 = s.a.w * dx * dy;
-  const float power = -0.5f * (q1 + q2) - q3;
-  if (power > 0.0f) return false;
-  G = __expf(power);
-  const float raw = s.b.y * G;
-  clamped = raw > SGS_ALPHA_MAX;
-  alpha = clamped ? SGS_ALPHA_MAX : raw;
-  return alpha >= SGS_ALPHA_MIN;
+// A 64-bit mask read from LDS, made wave-uniform (held in scalar registers).
+__device__ __forceinline__ uint64_t uniform_mask(uint64_t m) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)m);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(m >> 32));
+  return ((uint64_t)hi << 32) | lo;
 }
 
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW * TH)
-k_blend_fwd(int64_t n, int W, int H, int GW, int64_t tiles_per_view,
-            const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
-            const float4 *__restrict__ rec, float *__restrict__ image,
-            float *__restrict__ final_T, uint32_t *__restrict__ last,
+k_blend_fwd(int n, int W, int H, int GW, int tiles_per_view, const uint2 *__restrict__ ranges,
+            const uint32_t *__restrict__ vals, const float4 *__restrict__ rec,
+            float *__restrict__ image, float *__restrict__ final_T, uint32_t *__restrict__ last,
             unsigned long long *__restrict__ eval_count) {
   constexpr int BS = TW * TH;
+  constexpr int NW = BS / 64;  // waves = 8x8 sub-tiles
   constexpr int SUBW = TW / 8;
   __shared__ SplatLds sh[BS];
-  __shared__ unsigned long long s_ev[BS / 64];
+  __shared__ uint64_t s_meet[NW][NW];  // [sub-tile][64-entry word]: entries meeting the sub-tile
+  __shared__ unsigned long long s_ev[NW];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t tile = blockIdx.x;
-  const int v = (int)(tile / tiles_per_view);
-  const int t = (int)(tile - (int64_t)v * tiles_per_view);
+  const int tile = blockIdx.x;
+  const int v = tile / tiles_per_view;
+  const int t = tile - v * tiles_per_view;
   const int tx = t % GW, ty = t / GW;
   const int sx0 = tx * TW + (wave % SUBW) * 8;
   const int sy0 = ty * TH + (wave / SUBW) * 8;
@@ -83,42 +90,86 @@ k_blend_fwd(int64_t n, int W, int H, int GW, int64_t tiles_per_view,
   bool done = !inside;
   uint32_t stop = rg.y - rg.x;
   uint32_t evals = 0;
-  for (uint32_t b = rg.x; b < rg.y; b += BS) {
-    if (__syncthreads_count(done ? 1 : 0) == BS) break;
+  // the next batch's records, fetched while the current one is walked
+  float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra;
+  auto fetch = [&](uint32_t b) {
     const uint32_t e = b + threadIdx.x;
     if (e < rg.y) {
       const float4 *r = rec + 3 * (base + vals[e]);
-      sh[threadIdx.x].a = r[0];
-      sh[threadIdx.x].b = r[1];
-      sh[threadIdx.x].c = r[2];
+      ra = r[0];
+      rb = r[1];
+      rc = r[2];
+    }
+  };
+  if (rg.x < rg.y) fetch(rg.x);
+  for (uint32_t b = rg.x; b < rg.y; b += BS) {
+    if (__syncthreads_count(done ? 1 : 0) == BS) break;
+    const int cnt = (int)min((uint32_t)BS, rg.y - b);
+    if ((int)threadIdx.x < cnt) {
+      sh[threadIdx.x].a = ra;
+      sh[threadIdx.x].b = rb;
+      sh[threadIdx.x].c = rc;
+    }
+    // which sub-tiles this thread's entry meets, one ballot per sub-tile
+    {
+      const uint32_t sx = __float_as_uint(rb.z), sy = __float_as_uint(rb.w);
+      const bool valid = (int)threadIdx.x < cnt;
+      const int ex0 = (int)(sx & 0xFFFF), ex1 = (int)(sx >> 16);
+      const int ey0 = (int)(sy & 0xFFFF), ey1 = (int)(sy >> 16);
+      const int bx = tx * TW, by = ty * TH;
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const int qx = bx + (j % SUBW) * 8, qy = by + (j / SUBW) * 8;
+        const bool m = valid && ex0 <= qx + 7 && ex1 >= qx && ey0 <= qy + 7 && ey1 >= qy;
+        const uint64_t bal = __ballot(m);
+        if (lane == 0) s_meet[j][wave] = bal;
+      }
     }
     __syncthreads();
+    if (b + BS < rg.y) fetch(b + BS);
     if (__ballot(!done) == 0ull) continue;
-    const int cnt = (int)min((uint32_t)BS, rg.y - b);
-    for (int k = 0; k < cnt; ++k) {
-      const SplatLds &s = sh[k];
-      if (!span_meets(s, sx0, sy0)) continue;
-      if (!done) {
-        bool in_span, clamped;
-        float alpha, G, dx, dy;
-        const bool ok = splat_alpha(s, px, py, fx, fy, in_span, alpha, G, clamped, dx, dy);
-        evals += in_span ? 1u : 0u;
-        if (ok) {
-          const float at = s.c.w * alpha;
-          const float Tn = T * (1.0f - at);
-          if (Tn < SGS_T_MIN) {
-            done = true;
-            stop = b - rg.x + (uint32_t)k;
-          } else {
-            const float w = at * T;
-            C0 = fmaf(s.c.x, w, C0);
-            C1 = fmaf(s.c.y, w, C1);
-            C2 = fmaf(s.c.z, w, C2);
-            T = Tn;
-          }
+    // entries meeting this wave's sub-tile, in list order; the next entry's
+    // record is read from LDS while the current one is composited
+    bool wave_done = false;
+#pragma unroll 1
+    for (int word = 0; word < NW && !wave_done; ++word) {
+      uint64_t m = uniform_mask(s_meet[wave][word]);
+      if (m == 0ull) continue;
+      int k = word * 64 + __builtin_ctzll(m);
+      m &= m - 1;
+      SplatLds cur = sh[k];
+      for (;;) {
+        const bool more = m != 0ull;
+        int kn = k;
+        SplatLds nxt = cur;
+        if (more) {
+          kn = word * 64 + __builtin_ctzll(m);
+          m &= m - 1;
+          nxt = sh[kn];
         }
+        const SplatEval e = eval_splat(cur, px, py, fx, fy);
+        const bool act = !done;
+        evals += (act && e.in_span) ? 1u : 0u;
+        const bool okc = act && e.ok;
+        const float at = cur.c.w * e.alpha;
+        const float Tn = T * (1.0f - at);
+        const bool term = okc && Tn < SGS_T_MIN;
+        const bool contrib = okc && !term;
+        const float w = at * T;
+        C0 = contrib ? fmaf(cur.c.x, w, C0) : C0;
+        C1 = contrib ? fmaf(cur.c.y, w, C1) : C1;
+        C2 = contrib ? fmaf(cur.c.z, w, C2) : C2;
+        T = contrib ? Tn : T;
+        stop = term ? b - rg.x + (uint32_t)k : stop;
+        done = done || term;
+        if (__ballot(!done) == 0ull) {
+          wave_done = true;
+          break;
+        }
+        if (!more) break;
+        cur = nxt;
+        k = kn;
       }
-      if (__ballot(!done) == 0ull) break;
     }
   }
   if (inside) {
@@ -138,34 +189,41 @@ k_blend_fwd(int64_t n, int W, int H, int GW, int64_t tiles_per_view,
     __syncthreads();
     if (threadIdx.x == 0) {
       unsigned long long tot = 0;
-      for (int w = 0; w < BS / 64; ++w) tot += s_ev[w];
+      for (int w = 0; w < NW; ++w) tot += s_ev[w];
       if (tot) atomicAdd(eval_count, tot);
     }
   }
 }
 
-// Sum each of v[0..15] over the 64 lanes of the wave.  After the call lane L
-// holds the total of value ((L>>5)&1)*8 + ((L>>4)&1)*4 + ((L>>3)&1)*2 +
-// ((L>>2)&1) (lanes sharing L>>2 hold the same total).
-__device__ __forceinline__ float wave_transpose_sum16(float v[16], int lane) {
+// Sum each of v[0..15] over the 64 lanes of the wave with a transposing
+// butterfly: every exchange halves the number of values a lane carries, so
+// the sixteen sums cost 8 + 4 cross-half swaps (v_permlane32/16_swap), two
+// DPP exchanges inside a row and two quad reductions.  After the call lane L
+// holds the total of value 4*(L>>4) + 2*((L>>3)&1) + ((L>>2)&1).
+template <int kCtrl>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, 0xF, 0xF, false));
+}
+constexpr int kDppRowRor8 = 0x128;       // lane i <- lane (i + 8) mod 16 within a row
+constexpr int kDppRowHalfMirror = 0x141; // lane i <- lane 7 - i within each eight
+constexpr int kDppQuad2301 = 0x4E;       // lane i <- lane i ^ 2 within a quad
+constexpr int kDppQuad1032 = 0xB1;       // lane i <- lane i ^ 1 within a quad
+
+__device__ __forceinline__ float wave_transpose_sum16(const float v[16], int lane) {
   float r8[8], r4[4], r2[2];
-  {
-    const bool hi = lane & 32;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const float mine = hi ? v[8 + i] : v[i];
-      const float send = hi ? v[i] : v[8 + i];
-      r8[i] = mine + __shfl_xor(send, 32, 64);
-    }
+  for (int i = 0; i < 8; ++i) {
+    // lanes 0-31 end with value i, lanes 32-63 with value 8 + i
+    const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]),
+                                                     __float_as_uint(v[8 + i]), false, false);
+    r8[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
   }
-  {
-    const bool hi = lane & 16;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float mine = hi ? r8[4 + i] : r8[i];
-      const float send = hi ? r8[i] : r8[4 + i];
-      r4[i] = mine + __shfl_xor(send, 16, 64);
-    }
+  for (int i = 0; i < 4; ++i) {
+    // row q (lanes 16q .. 16q + 15) ends with value 4q + i
+    const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(r8[i]),
+                                                     __float_as_uint(r8[4 + i]), false, false);
+    r4[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
   }
   {
     const bool hi = lane & 8;
@@ -173,37 +231,35 @@ __device__ __forceinline__ float wave_transpose_sum16(float v[16], int lane) {
     for (int i = 0; i < 2; ++i) {
       const float mine = hi ? r4[2 + i] : r4[i];
       const float send = hi ? r4[i] : r4[2 + i];
-      r2[i] = mine + __shfl_xor(send, 8, 64);
+      r2[i] = mine + dpp<kDppRowRor8>(send);
     }
   }
-  float x;
-  {
-    const bool hi = lane & 4;
-    const float mine = hi ? r2[1] : r2[0];
-    const float send = hi ? r2[0] : r2[1];
-    x = mine + __shfl_xor(send, 4, 64);
-  }
-  x += __shfl_xor(x, 2, 64);
-  x += __shfl_xor(x, 1, 64);
+  const bool hi = lane & 4;
+  const float mine = hi ? r2[1] : r2[0];
+  const float send = hi ? r2[0] : r2[1];
+  float x = mine + dpp<kDppRowHalfMirror>(send);
+  x += dpp<kDppQuad2301>(x);
+  x += dpp<kDppQuad1032>(x);
   return x;
 }
 
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW * TH)
-k_blend_bwd(int64_t n, int W, int H, int GW, int64_t tiles_per_view,
-            const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
-            const float4 *__restrict__ rec, const float *__restrict__ final_T,
-            const uint32_t *__restrict__ last, const float *__restrict__ dimg,
-            float *__restrict__ sgrad) {
+k_blend_bwd(int n, int W, int H, int GW, int tiles_per_view, const uint2 *__restrict__ ranges,
+            const uint32_t *__restrict__ vals, const float4 *__restrict__ rec,
+            const float *__restrict__ final_T, const uint32_t *__restrict__ last,
+            const float *__restrict__ dimg, float *__restrict__ sgrad) {
   constexpr int BS = TW * TH;
+  constexpr int NW = BS / 64;
   constexpr int SUBW = TW / 8;
   __shared__ SplatLds sh[BS];
   __shared__ uint32_t s_gid[BS];
-  __shared__ uint32_t s_max[BS / 64];
+  __shared__ uint32_t s_max[NW];
+  __shared__ uint64_t s_meet[NW][NW];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t tile = blockIdx.x;
-  const int v = (int)(tile / tiles_per_view);
-  const int t = (int)(tile - (int64_t)v * tiles_per_view);
+  const int tile = blockIdx.x;
+  const int v = tile / tiles_per_view;
+  const int t = tile - v * tiles_per_view;
   const int tx = t % GW, ty = t / GW;
   const int sx0 = tx * TW + (wave % SUBW) * 8;
   const int sy0 = ty * TH + (wave / SUBW) * 8;
@@ -231,67 +287,133 @@ k_blend_bwd(int64_t n, int W, int H, int GW, int64_t tiles_per_view,
   if (lane == 0) s_max[wave] = wave_reach;
   __syncthreads();
   uint32_t reach = 0;
-  for (int w = 0; w < BS / 64; ++w) reach = max(reach, s_max[w]);
+  uint32_t sub_reach[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    sub_reach[w] = s_max[w];
+    reach = max(reach, s_max[w]);
+  }
   if (reach == 0) return;
   float B0 = 0.f, B1 = 0.f, B2 = 0.f;  // colour seen behind the current splat
-  const uint32_t nbatch = (reach + BS - 1) / BS;
-  const int vidx = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 +
-                   ((lane >> 2) & 1);
-  for (int bi = (int)nbatch - 1; bi >= 0; --bi) {
+  const int nbatch = (int)((reach + BS - 1) / BS);
+  const int vidx = 4 * (lane >> 4) + 2 * ((lane >> 3) & 1) + ((lane >> 2) & 1);
+  float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra;
+  uint32_t rgid = 0;
+  auto fetch = [&](int bi) {
+    const uint32_t p = (uint32_t)bi * BS + threadIdx.x;
+    if (p < reach) {
+      rgid = vals[rg.x + p];
+      const float4 *r = rec + 3 * (base + rgid);
+      ra = r[0];
+      rb = r[1];
+      rc = r[2];
+    }
+  };
+  fetch(nbatch - 1);
+  for (int bi = nbatch - 1; bi >= 0; --bi) {
     const uint32_t p0 = (uint32_t)bi * BS;
-    const int cnt = (int)min((uint32_t)BS, rg.y - rg.x - p0);
     __syncthreads();
-    if ((int)threadIdx.x < cnt) {
-      const uint32_t gi = vals[rg.x + p0 + threadIdx.x];
-      const float4 *r = rec + 3 * (base + gi);
-      s_gid[threadIdx.x] = gi;
-      sh[threadIdx.x].a = r[0];
-      sh[threadIdx.x].b = r[1];
-      sh[threadIdx.x].c = r[2];
+    const uint32_t p = p0 + threadIdx.x;
+    const bool valid = p < reach;
+    if (valid) {
+      s_gid[threadIdx.x] = rgid;
+      sh[threadIdx.x].a = ra;
+      sh[threadIdx.x].b = rb;
+      sh[threadIdx.x].c = rc;
+    }
+    // entries meeting each sub-tile before that sub-tile's furthest stop
+    {
+      const uint32_t sx = __float_as_uint(rb.z), sy = __float_as_uint(rb.w);
+      const int ex0 = (int)(sx & 0xFFFF), ex1 = (int)(sx >> 16);
+      const int ey0 = (int)(sy & 0xFFFF), ey1 = (int)(sy >> 16);
+      const int bx = tx * TW, by = ty * TH;
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const int qx = bx + (j % SUBW) * 8, qy = by + (j / SUBW) * 8;
+        const bool m = valid && p < sub_reach[j] && ex0 <= qx + 7 && ex1 >= qx &&
+                       ey0 <= qy + 7 && ey1 >= qy;
+        const uint64_t bal = __ballot(m);
+        if (lane == 0) s_meet[j][wave] = bal;
+      }
     }
     __syncthreads();
-    if (p0 >= wave_reach) continue;
-    const int kstart = (int)min((uint32_t)cnt, wave_reach - p0) - 1;
-    for (int k = kstart; k >= 0; --k) {
-      const SplatLds &s = sh[k];
-      if (!span_meets(s, sx0, sy0)) continue;
-      const uint32_t pos = p0 + (uint32_t)k;
-      bool in_span = false, clamped = false, ok = false;
-      float alpha = 0.f, G = 0.f, dx = 0.f, dy = 0.f;
-      if (inside && pos < my_last)
-        ok = splat_alpha(s, px, py, fx, fy, in_span, alpha, G, clamped, dx, dy);
-      if (__ballot(ok) == 0ull) continue;
-      float d[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) d[q] = 0.0f;
-      if (ok) {
-        const float m = s.c.w;
-        const float at = m * alpha;
-        const float Tb = (at == 0.0f) ? T : T / (1.0f - at);
-        const float dat = Tb * (g0 * (s.c.x - B0) + g1 * (s.c.y - B1) + g2 * (s.c.z - B2));
-        const float wcol = at * Tb;
-        d[6] = g0 * wcol;
-        d[7] = g1 * wcol;
-        d[8] = g2 * wcol;
-        d[9] = dat * alpha;
-        if (!clamped) {
-          const float dal = m * dat;
-          d[5] = dal * G;
-          const float dp = dal * alpha;
-          d[0] = dp * (s.a.z * dx + s.a.w * dy);
-          d[1] = dp * (s.a.w * dx + s.b.x * dy);
-          d[2] = -0.5f * dp * dx * dx;
-          d[3] = -dp * dx * dy;
-          d[4] = -0.5f * dp * dy * dy;
+    if (bi > 0) fetch(bi - 1);
+    // entries meeting this wave's sub-tile before its furthest stop, back to
+    // front; the next entry's record is read while the current one is done
+#pragma unroll 1
+    for (int word = NW - 1; word >= 0; --word) {
+      uint64_t m = uniform_mask(s_meet[wave][word]);
+      if (m == 0ull) continue;
+      int hb = 63 - __builtin_clzll(m);
+      m &= ~(1ull << hb);
+      int k = word * 64 + hb;
+      SplatLds cur = sh[k];
+      uint32_t gid = s_gid[k];
+      for (;;) {
+        const bool more = m != 0ull;
+        int kn = k;
+        SplatLds nxt = cur;
+        uint32_t gidn = gid;
+        if (more) {
+          hb = 63 - __builtin_clzll(m);
+          m &= ~(1ull << hb);
+          kn = word * 64 + hb;
+          nxt = sh[kn];
+          gidn = s_gid[kn];
         }
-        B0 = s.c.x * at + (1.0f - at) * B0;
-        B1 = s.c.y * at + (1.0f - at) * B1;
-        B2 = s.c.z * at + (1.0f - at) * B2;
-        T = Tb;
+        const uint32_t pos = p0 + (uint32_t)k;
+        const SplatEval e = eval_splat(cur, px, py, fx, fy);
+        const bool ok = inside && pos < my_last && e.ok;
+        if (__ballot(ok) != 0ull) {
+          float d[16];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) d[q] = 0.0f;
+          if (ok) {
+            const float mk = cur.c.w;
+            const float at = mk * e.alpha;
+            const float Tb = (at == 0.0f) ? T : T / (1.0f - at);
+            const float dat =
+                Tb * fmaf(g0, cur.c.x - B0, fmaf(g1, cur.c.y - B1, g2 * (cur.c.z - B2)));
+            const float wcol = at * Tb;
+            d[6] = g0 * wcol;
+            d[7] = g1 * wcol;
+            d[8] = g2 * wcol;
+            d[9] = dat * e.alpha;
+            if (!e.clamped) {
+              // moments of dL/dpower over the pixels; the conic enters after
+              // the wave sum: dL/dpx = A Sx + B Sy, dL/dpy = B Sx + C Sy,
+              // dL/dA = -Sxx / 2, dL/dB = -Sxy, dL/dC = -Syy / 2
+              const float dal = mk * dat;
+              d[5] = dal * e.G;
+              const float dp = dal * e.alpha;
+              d[0] = dp * e.dx;
+              d[1] = dp * e.dy;
+              d[2] = d[0] * e.dx;
+              d[3] = d[0] * e.dy;
+              d[4] = d[1] * e.dy;
+            }
+            const float om = 1.0f - at;
+            B0 = fmaf(cur.c.x, at, om * B0);
+            B1 = fmaf(cur.c.y, at, om * B1);
+            B2 = fmaf(cur.c.z, at, om * B2);
+            T = Tb;
+          }
+          const float tot = wave_transpose_sum16(d, lane);
+          // lanes 0-3 hold Sx and lanes 4-7 hold Sy: each reads the other
+          const float other = dpp<kDppRowHalfMirror>(tot);
+          float gv = tot;
+          if (vidx == 0) gv = fmaf(cur.a.z, tot, cur.a.w * other);
+          else if (vidx == 1) gv = fmaf(cur.a.w, other, cur.b.x * tot);
+          else if (vidx == 2 || vidx == 4) gv = -0.5f * tot;
+          else if (vidx == 3) gv = -tot;
+          if ((lane & 3) == 0 && vidx < 10 && gv != 0.0f)
+            unsafeAtomicAdd(sgrad + (base + gid) * SGS_SGRAD + vidx, gv);
+        }
+        if (!more) break;
+        cur = nxt;
+        k = kn;
+        gid = gidn;
       }
-      const float tot = wave_transpose_sum16(d, lane);
-      if ((lane & 3) == 0 && vidx < 10 && tot != 0.0f)
-        unsafeAtomicAdd(sgrad + (base + s_gid[k]) * SGS_SGRAD + vidx, tot);
     }
   }
 }
@@ -301,8 +423,8 @@ hipError_t fwd_t(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint6
   SgsProfScope ps(c, SGS_PROF_BLEND_FWD);
   const uint32_t *vals = c->pair_val[c->pair_sorted_buf];
   k_blend_fwd<TW, TH><<<(unsigned)c->total_tiles, TW * TH, 0, c->stream>>>(
-      c->n, c->W, c->H, c->GW, c->tiles_per_view, c->ranges, vals, c->rec, image, final_T, last,
-      (unsigned long long *)ec);
+      (int)c->n, c->W, c->H, c->GW, (int)c->tiles_per_view, c->ranges, vals, c->rec, image,
+      final_T, last, (unsigned long long *)ec);
   return hipGetLastError();
 }
 
@@ -311,8 +433,8 @@ hipError_t bwd_t(sgs_ctx *c, const float *final_T, const uint32_t *last, const f
   SgsProfScope ps(c, SGS_PROF_BLEND_BWD);
   const uint32_t *vals = c->pair_val[c->pair_sorted_buf];
   k_blend_bwd<TW, TH><<<(unsigned)c->total_tiles, TW * TH, 0, c->stream>>>(
-      c->n, c->W, c->H, c->GW, c->tiles_per_view, c->ranges, vals, c->rec, final_T, last, dimg,
-      c->splat_grad);
+      (int)c->n, c->W, c->H, c->GW, (int)c->tiles_per_view, c->ranges, vals, c->rec, final_T,
+      last, dimg, c->splat_grad);
   return hipGetLastError();
 }
 
