@@ -135,18 +135,8 @@ k_blend_fwd(int n, int W, int H, int GW, int tiles_per_view, const uint2 *__rest
     for (int word = 0; word < NW && !wave_done; ++word) {
       uint64_t m = uniform_mask(s_meet[wave][word]);
       if (m == 0ull) continue;
-      int k = word * 64 + __builtin_ctzll(m);
-      m &= m - 1;
-      SplatLds cur = sh[k];
-      for (;;) {
-        const bool more = m != 0ull;
-        int kn = k;
-        SplatLds nxt = cur;
-        if (more) {
-          kn = word * 64 + __builtin_ctzll(m);
-          m &= m - 1;
-          nxt = sh[kn];
-        }
+      // composite entry k; false once every pixel of the wave has stopped
+      auto step = [&](const SplatLds &cur, int k) -> bool {
         const SplatEval e = eval_splat(cur, px, py, fx, fy);
         const bool act = !done;
         evals += (act && e.in_span) ? 1u : 0u;
@@ -162,13 +152,29 @@ k_blend_fwd(int n, int W, int H, int GW, int tiles_per_view, const uint2 *__rest
         T = contrib ? Tn : T;
         stop = term ? b - rg.x + (uint32_t)k : stop;
         done = done || term;
-        if (__ballot(!done) == 0ull) {
-          wave_done = true;
-          break;
+        return __ballot(!done) != 0ull;
+      };
+      // two register sets in turn: the next record loads while one is used
+      int ka = word * 64 + __builtin_ctzll(m), kb = ka;
+      m &= m - 1;
+      SplatLds ra_ = sh[ka], rb_;
+      for (;;) {
+        bool more = m != 0ull;
+        if (more) {
+          kb = word * 64 + __builtin_ctzll(m);
+          m &= m - 1;
+          rb_ = sh[kb];
         }
+        if (!step(ra_, ka)) { wave_done = true; break; }
         if (!more) break;
-        cur = nxt;
-        k = kn;
+        more = m != 0ull;
+        if (more) {
+          ka = word * 64 + __builtin_ctzll(m);
+          m &= m - 1;
+          ra_ = sh[ka];
+        }
+        if (!step(rb_, kb)) { wave_done = true; break; }
+        if (!more) break;
       }
     }
   }
@@ -297,6 +303,11 @@ k_blend_bwd(int n, int W, int H, int GW, int tiles_per_view, const uint2 *__rest
   float B0 = 0.f, B1 = 0.f, B2 = 0.f;  // colour seen behind the current splat
   const int nbatch = (int)((reach + BS - 1) / BS);
   const int vidx = 4 * (lane >> 4) + 2 * ((lane >> 3) & 1) + ((lane >> 2) & 1);
+  // the lane that adds value vidx to the splat's gradient, and the factor on
+  // its own wave sum for the values the conic does not enter
+  const bool lead = (lane & 3) == 0 && vidx < 10;
+  const float k_self = (vidx == 2 || vidx == 4) ? -0.5f : (vidx == 3 ? -1.0f : 1.0f);
+  float *const gbase = sgrad + base * SGS_SGRAD;
   float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra;
   uint32_t rgid = 0;
   auto fetch = [&](int bi) {
@@ -344,75 +355,80 @@ k_blend_bwd(int n, int W, int H, int GW, int tiles_per_view, const uint2 *__rest
     for (int word = NW - 1; word >= 0; --word) {
       uint64_t m = uniform_mask(s_meet[wave][word]);
       if (m == 0ull) continue;
-      int hb = 63 - __builtin_clzll(m);
-      m &= ~(1ull << hb);
-      int k = word * 64 + hb;
-      SplatLds cur = sh[k];
-      uint32_t gid = s_gid[k];
-      for (;;) {
-        const bool more = m != 0ull;
-        int kn = k;
-        SplatLds nxt = cur;
-        uint32_t gidn = gid;
-        if (more) {
-          hb = 63 - __builtin_clzll(m);
-          m &= ~(1ull << hb);
-          kn = word * 64 + hb;
-          nxt = sh[kn];
-          gidn = s_gid[kn];
-        }
+      // gradient of entry k (record cur, Gaussian gid)
+      auto step = [&](const SplatLds &cur, int k, uint32_t gid) {
         const uint32_t pos = p0 + (uint32_t)k;
         const SplatEval e = eval_splat(cur, px, py, fx, fy);
         const bool ok = inside && pos < my_last && e.ok;
-        if (__ballot(ok) != 0ull) {
-          float d[16];
+        if (__ballot(ok) == 0ull) return;
+        float d[16];
 #pragma unroll
-          for (int q = 0; q < 16; ++q) d[q] = 0.0f;
-          if (ok) {
-            const float mk = cur.c.w;
-            const float at = mk * e.alpha;
-            const float Tb = (at == 0.0f) ? T : T / (1.0f - at);
-            const float dat =
-                Tb * fmaf(g0, cur.c.x - B0, fmaf(g1, cur.c.y - B1, g2 * (cur.c.z - B2)));
-            const float wcol = at * Tb;
-            d[6] = g0 * wcol;
-            d[7] = g1 * wcol;
-            d[8] = g2 * wcol;
-            d[9] = dat * e.alpha;
-            if (!e.clamped) {
-              // moments of dL/dpower over the pixels; the conic enters after
-              // the wave sum: dL/dpx = A Sx + B Sy, dL/dpy = B Sx + C Sy,
-              // dL/dA = -Sxx / 2, dL/dB = -Sxy, dL/dC = -Syy / 2
-              const float dal = mk * dat;
-              d[5] = dal * e.G;
-              const float dp = dal * e.alpha;
-              d[0] = dp * e.dx;
-              d[1] = dp * e.dy;
-              d[2] = d[0] * e.dx;
-              d[3] = d[0] * e.dy;
-              d[4] = d[1] * e.dy;
-            }
-            const float om = 1.0f - at;
-            B0 = fmaf(cur.c.x, at, om * B0);
-            B1 = fmaf(cur.c.y, at, om * B1);
-            B2 = fmaf(cur.c.z, at, om * B2);
-            T = Tb;
+        for (int q = 0; q < 16; ++q) d[q] = 0.0f;
+        if (ok) {
+          const float mk = cur.c.w;
+          const float at = mk * e.alpha;
+          const float om = 1.0f - at;
+          const float Tb = (at == 0.0f) ? T : T / om;  // T in front of this splat
+          const float dat =
+              Tb * fmaf(g0, cur.c.x - B0, fmaf(g1, cur.c.y - B1, g2 * (cur.c.z - B2)));
+          const float wcol = at * Tb;
+          d[6] = g0 * wcol;
+          d[7] = g1 * wcol;
+          d[8] = g2 * wcol;
+          d[9] = dat * e.alpha;
+          if (!e.clamped) {
+            // moments of dL/dpower over the pixels; the conic enters after
+            // the wave sum: dL/dpx = A Sx + B Sy, dL/dpy = B Sx + C Sy,
+            // dL/dA = -Sxx / 2, dL/dB = -Sxy, dL/dC = -Syy / 2
+            const float dal = mk * dat;
+            d[5] = dal * e.G;
+            const float dp = dal * e.alpha;
+            d[0] = dp * e.dx;
+            d[1] = dp * e.dy;
+            d[2] = d[0] * e.dx;
+            d[3] = d[0] * e.dy;
+            d[4] = d[1] * e.dy;
           }
-          const float tot = wave_transpose_sum16(d, lane);
-          // lanes 0-3 hold Sx and lanes 4-7 hold Sy: each reads the other
-          const float other = dpp<kDppRowHalfMirror>(tot);
-          float gv = tot;
-          if (vidx == 0) gv = fmaf(cur.a.z, tot, cur.a.w * other);
-          else if (vidx == 1) gv = fmaf(cur.a.w, other, cur.b.x * tot);
-          else if (vidx == 2 || vidx == 4) gv = -0.5f * tot;
-          else if (vidx == 3) gv = -tot;
-          if ((lane & 3) == 0 && vidx < 10 && gv != 0.0f)
-            unsafeAtomicAdd(sgrad + (base + gid) * SGS_SGRAD + vidx, gv);
+          B0 = fmaf(cur.c.x, at, om * B0);
+          B1 = fmaf(cur.c.y, at, om * B1);
+          B2 = fmaf(cur.c.z, at, om * B2);
+          T = Tb;
         }
+        const float tot = wave_transpose_sum16(d, lane);
+        // lanes 0-3 hold Sx and lanes 4-7 hold Sy: each reads the other
+        const float other = dpp<kDppRowHalfMirror>(tot);
+        const float cs = vidx == 0 ? cur.a.z : (vidx == 1 ? cur.b.x : k_self);
+        const float co = vidx < 2 ? cur.a.w : 0.0f;
+        const float gv = fmaf(cs, tot, co * other);
+        if (lead && gv != 0.0f) unsafeAtomicAdd(gbase + (size_t)gid * SGS_SGRAD + vidx, gv);
+      };
+      // two register sets in turn: the next record loads while one is used
+      int hb = 63 - __builtin_clzll(m);
+      m &= ~(1ull << hb);
+      int ka = word * 64 + hb, kb = ka;
+      SplatLds ra_ = sh[ka], rb_;
+      uint32_t ga = s_gid[ka], gb = ga;
+      for (;;) {
+        bool more = m != 0ull;
+        if (more) {
+          hb = 63 - __builtin_clzll(m);
+          m &= ~(1ull << hb);
+          kb = word * 64 + hb;
+          rb_ = sh[kb];
+          gb = s_gid[kb];
+        }
+        step(ra_, ka, ga);
         if (!more) break;
-        cur = nxt;
-        k = kn;
-        gid = gidn;
+        more = m != 0ull;
+        if (more) {
+          hb = 63 - __builtin_clzll(m);
+          m &= ~(1ull << hb);
+          ka = word * 64 + hb;
+          ra_ = sh[ka];
+          ga = s_gid[ka];
+        }
+        step(rb_, kb, gb);
+        if (!more) break;
       }
     }
   }
