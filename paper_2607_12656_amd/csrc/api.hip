@@ -323,6 +323,8 @@ sgs_status sgs_fakequant_prune_bwd(sgs_ctx *c, const float *params, const float 
   if (mask_mode == 1 && !soft_mask)
     return fail(c, SGS_EINVAL, "fakequant_prune_bwd: soft_mask needed in mask mode 1");
   if (mask_mode < 0 || mask_mode > 2) return fail(c, SGS_EINVAL, "fakequant_prune_bwd: mask_mode");
+  if (!aligned(params, 16) || !aligned(grad_qparams, 16) || !aligned(grad_params, 16))
+    return fail(c, SGS_EINVAL, "fakequant_prune_bwd: parameter rows must be 16-byte aligned");
   SGS_HIP(launch_fakequant_bwd(c, params, qstep, soft_mask, mask_mode, rate_grad, stats,
                                grad_qparams, grad_hard_mask, grad_params, grad_qstep, grad_score),
           "fakequant_prune_bwd");

@@ -2,19 +2,19 @@
 // quantizer/mask backward (paper Sec. 3.3.1).
 //
 // The parameter passes are HBM-bound streams over the SoA rows.  A block owns
-// kQItems * 256 consecutive Gaussians and walks the 59 channel rows one after
-// the other (loads coalesced across the wave); per-channel reductions (range
-// keys, step-size gradient) are done once per block and channel, written as
-// per-block partials, and finished by one block per channel.  No contended
-// atomics.
+// one channel row of a chunk of kRPer consecutive Gaussians (16 per thread,
+// as four 16-byte loads, coalesced across the wave), so the per-channel
+// reductions (range keys, step-size gradient) cost one wave reduction per
+// 16 elements of a thread; they are written as per-chunk partials and
+// finished by one block per channel.  No contended atomics.
 #include "sgs_internal.h"
 
 namespace {
 
 constexpr int kQThreads = 256;
 constexpr int kQWaves = kQThreads / 64;
-constexpr int kQItems = 4;
-constexpr int kQPer = kQThreads * kQItems;  // Gaussians per block
+constexpr int kRVec = 4;                        // float4 loads per thread and row
+constexpr int kRPer = kQThreads * kRVec * 4;    // Gaussians per chunk
 // partial record per block: [0,59) min keys, [59,118) max keys, [118] kept
 constexpr int kPartWords = 120;
 
@@ -35,46 +35,76 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
   return v;
 }
 
-// Pass 1: qparams, hard/soft mask; per-block range keys and kept count.
+// Pass 1, block (chunk, j) for j < 59: qparams of row j and the row's range
+// keys over the chunk; block (chunk, 59): hard/soft mask and kept count.
 __global__ void __launch_bounds__(kQThreads)
 k_fakequant_prune(int64_t n, int64_t npad, const float *__restrict__ params,
                   const float *__restrict__ q, const float *__restrict__ score, int mode,
                   const uint8_t *__restrict__ given, uint64_t seed, uint64_t step, float tau,
                   float *__restrict__ qparams, uint8_t *__restrict__ hard,
                   float *__restrict__ soft, uint64_t *__restrict__ part) {
-  __shared__ uint64_t s_min[kQWaves][SGS_NCH];
-  __shared__ uint64_t s_max[kQWaves][SGS_NCH];
-  __shared__ uint32_t s_kept[kQWaves];
+  __shared__ uint64_t s_a[kQWaves], s_b[kQWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t base = (int64_t)blockIdx.x * kQPer + threadIdx.x;
-  for (int j = 0; j < SGS_NCH; ++j) {
+  const int j = blockIdx.y;
+  const int64_t chunk = blockIdx.x;
+  const int64_t c0 = chunk * kRPer;
+  uint64_t *dst = part + chunk * kPartWords;
+  if (j < SGS_NCH) {
     const float qj = q[j];
+    const float *row = params + j * npad;
+    float *orow = qparams + j * npad;
     uint64_t kmin = ~0ull, kmax = 0ull;
 #pragma unroll
-    for (int it = 0; it < kQItems; ++it) {
-      const int64_t i = base + (int64_t)it * kQThreads;
+    for (int r = 0; r < kRVec; ++r) {
+      const int64_t i = c0 + ((int64_t)r * kQThreads + threadIdx.x) * 4;
       if (i < n) {
-        const float yv = params[j * npad + i];
-        qparams[j * npad + i] = rintf(__fdiv_rn(yv, qj)) * qj;
-        const uint64_t o = (uint64_t)sgs_ord(yv) << 32;
-        const uint64_t a = o | (uint64_t)(uint32_t)i;
-        const uint64_t b = o | (uint64_t)(0xFFFFFFFFu - (uint32_t)i);
-        kmin = a < kmin ? a : kmin;
-        kmax = b > kmax ? b : kmax;
+        // i + 3 < npad (npad % 64 == 0): the 16-byte load stays in the row
+        const float4 y = *reinterpret_cast<const float4 *>(row + i);
+        const float yv[4] = {y.x, y.y, y.z, y.w};
+        float o[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          o[e] = rintf(__fdiv_rn(yv[e], qj)) * qj;
+          if (i + e < n) {
+            const uint64_t ok = (uint64_t)sgs_ord(yv[e]) << 32;
+            const uint64_t a = ok | (uint64_t)(uint32_t)(i + e);
+            const uint64_t b = ok | (uint64_t)(0xFFFFFFFFu - (uint32_t)(i + e));
+            kmin = a < kmin ? a : kmin;
+            kmax = b > kmax ? b : kmax;
+          }
+        }
+        if (i + 3 < n) {
+          *reinterpret_cast<float4 *>(orow + i) = make_float4(o[0], o[1], o[2], o[3]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (i + e < n) orow[i + e] = o[e];
+        }
       }
     }
     kmin = wave_min_u64(kmin);
     kmax = wave_max_u64(kmax);
     if (lane == 0) {
-      s_min[wave][j] = kmin;
-      s_max[wave][j] = kmax;
+      s_a[wave] = kmin;
+      s_b[wave] = kmax;
     }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t a = s_a[0], b = s_b[0];
+#pragma unroll
+      for (int w = 1; w < kQWaves; ++w) {
+        a = s_a[w] < a ? s_a[w] : a;
+        b = s_b[w] > b ? s_b[w] : b;
+      }
+      dst[j] = a;
+      dst[SGS_NCH + j] = b;
+    }
+    return;
   }
   uint32_t kept = 0;
-#pragma unroll
-  for (int it = 0; it < kQItems; ++it) {
-    const int64_t i = base + (int64_t)it * kQThreads;
-    if (i >= n) continue;
+  for (int r = 0; r < kRVec * 4; ++r) {
+    const int64_t i = c0 + (int64_t)r * kQThreads + threadIdx.x;
+    if (i >= n) break;
     uint8_t m;
     float sm;
     if (mode == 0) {
@@ -85,11 +115,11 @@ k_fakequant_prune(int64_t n, int64_t npad, const float *__restrict__ params,
       sm = 1.0f;
     } else {
       const float u = sgs_uniform(seed, step, (uint64_t)i);
-      const float s = score[i];
-      const float e = sgs_exp_repro(s);
+      const float sc = score[i];
+      const float e = sgs_exp_repro(sc);
       m = (u * (1.0f + e)) > 1.0f ? 1 : 0;
       const float l = logf(u) - logf(1.0f - u);
-      sm = 1.0f / (1.0f + __expf(-(s + l) / tau));
+      sm = 1.0f / (1.0f + __expf(-(sc + l) / tau));
     }
     hard[i] = m;
     if (soft) soft[i] = sm;
@@ -97,24 +127,12 @@ k_fakequant_prune(int64_t n, int64_t npad, const float *__restrict__ params,
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) kept += __shfl_xor(kept, off, 64);
-  if (lane == 0) s_kept[wave] = kept;
+  if (lane == 0) s_a[wave] = kept;
   __syncthreads();
-  uint64_t *dst = part + (int64_t)blockIdx.x * kPartWords;
-  if (threadIdx.x < SGS_NCH) {
-    const int j = threadIdx.x;
-    uint64_t a = s_min[0][j], b = s_max[0][j];
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
 #pragma unroll
-    for (int w = 1; w < kQWaves; ++w) {
-      a = s_min[w][j] < a ? s_min[w][j] : a;
-      b = s_max[w][j] > b ? s_max[w][j] : b;
-    }
-    dst[j] = a;
-    dst[SGS_NCH + j] = b;
-  }
-  if (threadIdx.x == 64) {
-    uint32_t t = 0;
-#pragma unroll
-    for (int w = 0; w < kQWaves; ++w) t += s_kept[w];
+    for (int w = 0; w < kQWaves; ++w) t += s_a[w];
     dst[118] = t;
   }
 }
@@ -203,41 +221,59 @@ __global__ void k_rate_proxy(const uint64_t *__restrict__ stats, const float *__
   }
 }
 
-// Backward pass 1: straight-through copy (skipped when aliased) and, per
-// block and channel, sum_i g_ij (k_ij q_j - y_ij) in FP64 (the learned-step
-// gradient before the division by q_j).  k q - y is formed with one fused
-// multiply-add, so the small residual is exact.
+// Backward pass 1, block (chunk, j): straight-through copy of row j
+// (skipped when aliased) and sum_i g_ij (k_ij q_j - y_ij) over the chunk in
+// FP64 (the learned-step gradient before the division by q_j).  k q - y is
+// formed with one fused multiply-add, so the small residual is exact, and its
+// product with g is exact in FP64.
 __global__ void __launch_bounds__(kQThreads)
 k_fakequant_bwd(int64_t n, int64_t npad, const float *__restrict__ params,
                 const float *__restrict__ q, const float *__restrict__ gq_in,
                 float *__restrict__ gparams, double *__restrict__ partial) {
-  __shared__ double s_red[kQWaves][SGS_NCH];
+  __shared__ double s_red[kQWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t base = (int64_t)blockIdx.x * kQPer + threadIdx.x;
+  const int j = blockIdx.y;
+  const int64_t chunk = blockIdx.x;
+  const int64_t c0 = chunk * kRPer;
   const bool copy = gparams != gq_in;
-  for (int j = 0; j < SGS_NCH; ++j) {
-    const float qj = q[j];
-    float acc = 0.0f;
+  const float qj = q[j];
+  const float *yrow = params + j * npad;
+  const float *grow = gq_in + j * npad;
+  float *orow = gparams + j * npad;
+  double acc = 0.0;
 #pragma unroll
-    for (int it = 0; it < kQItems; ++it) {
-      const int64_t i = base + (int64_t)it * kQThreads;
-      if (i < n) {
-        const float g = gq_in[j * npad + i];
-        const float yv = params[j * npad + i];
-        const float k = rintf(__fdiv_rn(yv, qj));
-        acc = fmaf(g, fmaf(k, qj, -yv), acc);
-        if (copy) gparams[j * npad + i] = g;
+  for (int r = 0; r < kRVec; ++r) {
+    const int64_t i = c0 + ((int64_t)r * kQThreads + threadIdx.x) * 4;
+    if (i < n) {
+      const float4 y = *reinterpret_cast<const float4 *>(yrow + i);
+      const float4 g = *reinterpret_cast<const float4 *>(grow + i);
+      const float yv[4] = {y.x, y.y, y.z, y.w}, gv[4] = {g.x, g.y, g.z, g.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (i + e < n) {
+          const float k = rintf(__fdiv_rn(yv[e], qj));
+          acc = fma((double)gv[e], (double)fmaf(k, qj, -yv[e]), acc);
+        }
+      }
+      if (copy) {
+        if (i + 3 < n) {
+          *reinterpret_cast<float4 *>(orow + i) = g;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (i + e < n) orow[i + e] = gv[e];
+        }
       }
     }
-    const double s = sgs_wave_sum_d((double)acc);
-    if (lane == 0) s_red[wave][j] = s;
   }
+  const double s = sgs_wave_sum_d(acc);
+  if (lane == 0) s_red[wave] = s;
   __syncthreads();
-  if (threadIdx.x < SGS_NCH) {
+  if (threadIdx.x == 0) {
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < kQWaves; ++w) t += s_red[w][threadIdx.x];
-    partial[(int64_t)blockIdx.x * SGS_NCH + threadIdx.x] = t;
+    for (int w = 0; w < kQWaves; ++w) t += s_red[w];
+    partial[chunk * SGS_NCH + j] = t;
   }
 }
 
@@ -287,7 +323,7 @@ __global__ void k_score_bwd(int64_t n, int mode, float tau, const float *__restr
 }  // namespace
 
 int64_t quant_partial_words(int64_t n) {
-  const int64_t nb = (n + kQPer - 1) / kQPer;
+  const int64_t nb = (n + kRPer - 1) / kRPer;
   return nb * (kPartWords > SGS_NCH ? kPartWords : SGS_NCH);
 }
 
@@ -296,12 +332,11 @@ hipError_t launch_fakequant_prune(sgs_ctx *c, const float *params, const float *
                                   uint64_t seed, uint64_t step, float *qparams,
                                   uint8_t *hard, float *soft, uint64_t *stats) {
   SgsProfScope ps(c, SGS_PROF_FAKEQUANT);
-  const int nb = (int)((c->n + kQPer - 1) / kQPer);
+  const int nb = (int)((c->n + kRPer - 1) / kRPer);
   if ((int64_t)nb * kPartWords > c->red_tmp_words) return hipErrorInvalidValue;
   uint64_t *part = (uint64_t *)c->red_tmp;
-  k_fakequant_prune<<<nb, kQThreads, 0, c->stream>>>(c->n, c->npad, params, q, score, mode, given,
-                                                     seed, step, c->tau, qparams, hard, soft,
-                                                     part);
+  k_fakequant_prune<<<dim3(nb, SGS_NCH + 1), kQThreads, 0, c->stream>>>(
+      c->n, c->npad, params, q, score, mode, given, seed, step, c->tau, qparams, hard, soft, part);
   k_stats_finish<<<SGS_NCH, kQThreads, 0, c->stream>>>(nb, part, q, stats);
   return hipGetLastError();
 }
@@ -318,11 +353,11 @@ hipError_t launch_fakequant_bwd(sgs_ctx *c, const float *params, const float *q,
                                 const uint64_t *stats, const float *gq_in,
                                 const float *gmask_in, float *gparams, float *gqstep,
                                 float *gscore) {
-  const int nb = (int)((c->n + kQPer - 1) / kQPer);
+  const int nb = (int)((c->n + kRPer - 1) / kRPer);
   if ((int64_t)nb * SGS_NCH > c->red_tmp_words) return hipErrorInvalidValue;
   SgsProfScope ps(c, SGS_PROF_FAKEQUANT_BWD);
-  k_fakequant_bwd<<<nb, kQThreads, 0, c->stream>>>(c->n, c->npad, params, q, gq_in, gparams,
-                                                   c->red_tmp);
+  k_fakequant_bwd<<<dim3(nb, SGS_NCH), kQThreads, 0, c->stream>>>(c->n, c->npad, params, q,
+                                                                  gq_in, gparams, c->red_tmp);
   k_fakequant_bwd_finish<<<SGS_NCH, kQThreads, 0, c->stream>>>(nb, c->red_tmp, q, rate_grad,
                                                                stats, c->npad, gparams, gqstep);
   k_score_bwd<<<sgs_blocks(c->n, 256), 256, 0, c->stream>>>(c->n, mode, c->tau, soft, gmask_in,
