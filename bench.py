@@ -111,6 +111,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", choices=("c2", "c3"))
     ap.add_argument("--tile", default=None, help="16x16 | 8x8 | 32x8 | auto")
+    ap.add_argument("--schedule", default=None, choices=("tile", "stride", "queue"),
+                    help="blend launch schedule when --tile names a shape (default: stride "
+                         "on the 1M workload, where the autotuner picks it, else tile)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip graph / learned / MLP legs")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -159,10 +162,12 @@ def main():
         from paper_2607_12656_amd import autotune
         tune = autotune.tune(ctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height,
                              plain_step, reps=2)
-        tile = tune["tile"]
+        tile, schedule = tune["tile"], tune["schedule"]
     else:
         tile = tuple(int(v) for v in tile_choice.split("x"))
-    rd = RDStep(ctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height, tile=tile)
+        schedule = args.schedule or ("stride" if args.workload == "c2" else "tile")
+    rd = RDStep(ctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height, tile=tile,
+                schedule=schedule)
 
     # evaluation count and pair count of one step (deterministic)
     rd.evals.zero_()
@@ -210,7 +215,7 @@ def main():
                                f"{sc.views} view(s) {sc.width}x{sc.height}, 20% pruned, "
                                f"lambda 2.5e-5, tile {tile[0]}x{tile[1]}",
                    "gaussians": sc.n, "views": sc.views, "width": sc.width,
-                   "height": sc.height, "tile": f"{tile[0]}x{tile[1]}", "pairs": P,
+                   "height": sc.height, "tile": f"{tile[0]}x{tile[1]}", "schedule": schedule, "pairs": P,
                    "evals_per_step": E},
         "roofline": roof,
         "kernel_ms": kernels,

@@ -38,7 +38,10 @@ class sgs_camera(C.Structure):
 
 class sgs_options(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("tau", C.c_float),
-                ("reserved", C.c_int32 * 5)]
+                ("schedule", C.c_int32), ("reserved", C.c_int32 * 4)]
+
+
+SCHEDULES = {"tile": 0, "stride": 1, "queue": 2}
 
 
 P = C.c_void_p
@@ -177,12 +180,16 @@ class Context:
         self._check(self.L.sgs_set_stream(self.h, P(stream.cuda_stream)), self.h)
 
     # ---- the C ABI, one method per entry point -----------------------------
-    def set_scene(self, n, npad, n_hat, cams, width, height, tile=(16, 16), tau=1.0):
+    def set_scene(self, n, npad, n_hat, cams, width, height, tile=(16, 16), tau=1.0,
+                  schedule="tile"):
+        """schedule: blend launch, "tile" (one workgroup per tile), "stride" or
+        "queue" (resident workgroups over the tiles ordered by list length)."""
         cams = np.ascontiguousarray(cams, np.float32)
         arr = cameras(cams)
-        opt = sgs_options(tile[0], tile[1], tau, (C.c_int32 * 5)())
+        opt = sgs_options(tile[0], tile[1], tau, SCHEDULES[schedule], (C.c_int32 * 4)())
         self.V, self.W, self.H, self.n, self.npad = cams.shape[0], width, height, n, npad
         self.tile = tile
+        self.schedule = schedule
         self._check(self.L.sgs_set_scene(self.h, n, npad, n_hat, arr, cams.shape[0], width,
                                          height, C.byref(opt)), self.h)
 

@@ -1,10 +1,14 @@
-"""Tile-shape autotuner for the RD step.
+"""Autotuner for the RD step: tile shape, then blend schedule.
 
 The support rule is pixel-exact, so every candidate tile shape renders the
-same image and gradients (the tiles only change the work decomposition):
-the tuner may pick on speed alone.  Each candidate is timed over whole
-forward + backward steps with HIP events on the step's stream; results are
-cached per (device, N, views, width, height) in a JSON file.
+same image and gradients, and the blend schedule (one workgroup per tile,
+or resident workgroups over the tiles ordered by list length, striding or
+taking them from an atomic queue) only changes which workgroup blends which
+tile: the tuner may pick on speed alone.  The tile shapes are timed with the
+per-tile schedule, then the schedules with the best shape.  Each candidate is
+timed over whole forward + backward steps with HIP events on the step's
+stream; results are cached per (device, N, views, width, height) in a JSON
+file.
 """
 from __future__ import annotations
 
@@ -12,6 +16,7 @@ import json
 import os
 
 CANDIDATES = ((16, 16), (8, 8), (32, 8))
+SCHEDULES = ("tile", "stride", "queue")
 
 
 def _key(dev_name, n, V, W, H):
@@ -19,9 +24,10 @@ def _key(dev_name, n, V, W, H):
 
 
 def tune(ctx, n, npad, n_hat, cams, width, height, step_fn, reps: int = 3,
-         cache_path: str | None = None, candidates=CANDIDATES) -> dict:
-    """step_fn(rd) runs one full step on an RDStep bound to ctx.
-    Returns {"tile": (tw, th), "ms": {"16x16": ..., ...}, "cached": bool}."""
+         cache_path: str | None = None, candidates=CANDIDATES, schedules=SCHEDULES) -> dict:
+    """step_fn(rd) runs one full step on an RDStep bound to ctx.  Returns
+    {"tile": (tw, th), "schedule": name, "ms": {"16x16/tile": ..., ...},
+    "cached": bool}."""
     import torch
 
     from .rd import RDStep
@@ -32,13 +38,15 @@ def tune(ctx, n, npad, n_hat, cams, width, height, step_fn, reps: int = 3,
             cache = json.load(open(cache_path))
         except (OSError, ValueError):
             cache = {}
-        if key in cache:
+        if key in cache and "schedule" in cache[key]:
             e = cache[key]
-            return {"tile": tuple(e["tile"]), "ms": e["ms"], "cached": True}
+            return {"tile": tuple(e["tile"]), "schedule": e["schedule"], "ms": e["ms"],
+                    "cached": True}
     timings = {}
     stream = torch.cuda.current_stream(ctx.device)
-    for tile in candidates:
-        rd = RDStep(ctx, n, npad, n_hat, cams, width, height, tile=tile)
+
+    def run(tile, schedule):
+        rd = RDStep(ctx, n, npad, n_hat, cams, width, height, tile=tile, schedule=schedule)
         step_fn(rd)                      # warm-up (allocates the pair buffers)
         torch.cuda.synchronize()
         a = torch.cuda.Event(enable_timing=True)
@@ -48,10 +56,18 @@ def tune(ctx, n, npad, n_hat, cams, width, height, step_fn, reps: int = 3,
             step_fn(rd)
         b.record(stream)
         b.synchronize()
-        timings[f"{tile[0]}x{tile[1]}"] = a.elapsed_time(b) / reps
+        timings[f"{tile[0]}x{tile[1]}/{schedule}"] = a.elapsed_time(b) / reps
         del rd
+
+    for tile in candidates:
+        run(tile, schedules[0])
     best = min(timings, key=timings.get)
-    tile = tuple(int(v) for v in best.split("x"))
+    tile = tuple(int(v) for v in best.split("/")[0].split("x"))
+    for schedule in schedules[1:]:
+        run(tile, schedule)
+    best = min(timings, key=timings.get)
+    tile = tuple(int(v) for v in best.split("/")[0].split("x"))
+    schedule = best.split("/")[1]
     if cache_path:
         cache = {}
         if os.path.exists(cache_path):
@@ -59,9 +75,9 @@ def tune(ctx, n, npad, n_hat, cams, width, height, step_fn, reps: int = 3,
                 cache = json.load(open(cache_path))
             except (OSError, ValueError):
                 cache = {}
-        cache[key] = {"tile": list(tile), "ms": timings}
+        cache[key] = {"tile": list(tile), "schedule": schedule, "ms": timings}
         tmp = cache_path + ".tmp"
         with open(tmp, "w") as f:
             json.dump(cache, f, indent=1)
         os.replace(tmp, cache_path)
-    return {"tile": tile, "ms": timings, "cached": False}
+    return {"tile": tile, "schedule": schedule, "ms": timings, "cached": False}

@@ -62,6 +62,8 @@ void free_scene(sgs_ctx *c) {
   c->blk_start_words = 0;
   dfree(c->splat_grad);
   dfree(c->ranges);
+  dfree(c->tile_order);
+  dfree(c->tile_bins);
   dfree(c->scan_tmp);
   dfree(c->sort_hist);
   dfree(c->red_tmp);
@@ -156,7 +158,7 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
     return fail(c, SGS_EINVAL, "set_scene: bad cameras or image size");
   if ((int64_t)views * n >= (int64_t)1 << 31)
     return fail(c, SGS_ECAPACITY, "set_scene: views * n must stay below 2^31");
-  int tw = 16, th = 16;
+  int tw = 16, th = 16, schedule = 0;
   float tau = 1.0f;
   if (opt) {
     if (opt->tile_w || opt->tile_h) {
@@ -164,9 +166,11 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
       th = opt->tile_h;
     }
     if (opt->tau != 0.0f) tau = opt->tau;
-    for (int k = 0; k < 5; ++k)
+    schedule = opt->schedule;
+    for (int k = 0; k < 4; ++k)
       if (opt->reserved[k] != 0) return fail(c, SGS_EINVAL, "set_scene: reserved options must be 0");
   }
+  if (schedule < 0 || schedule > 2) return fail(c, SGS_EINVAL, "set_scene: schedule must be 0, 1 or 2");
   if (!((tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 32 && th == 8)))
     return fail(c, SGS_EINVAL, "set_scene: tile shape must be 8x8, 16x16 or 32x8");
   if (!(tau > 0.0f)) return fail(c, SGS_EINVAL, "set_scene: tau must be > 0");
@@ -182,6 +186,7 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   c->TW = tw;
   c->TH = th;
   c->tau = tau;
+  c->schedule = schedule;
   c->GW = (width + tw - 1) / tw;
   c->GH = (height + th - 1) / th;
   c->tiles_per_view = (int64_t)c->GW * c->GH;
@@ -206,6 +211,8 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   SGS_ALLOC(c->bin_splat, vn);
   SGS_ALLOC(c->splat_grad, vn * SGS_SGRAD);
   SGS_ALLOC(c->ranges, c->total_tiles);
+  SGS_ALLOC(c->tile_order, c->total_tiles);
+  SGS_ALLOC(c->tile_bins, SGS_TILE_BINS);
   SGS_ALLOC(c->d_pairs_total, 4);
   e = hipMemset(c->d_pairs_total, 0, 4 * sizeof(uint32_t));
   if (e != hipSuccess) { free_scene(c); return hip_fail(c, e, "set_scene clear"); }
@@ -614,9 +621,18 @@ extern "C" sgs_status sgs_copy_structure(sgs_ctx *c, uint32_t *tile_ids, uint32_
   return SGS_OK;
 }
 
+namespace {
+__global__ void k_export_grads(int64_t count, const double *__restrict__ in,
+                               float *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = (float)in[i];
+}
+}  // namespace
+
 extern "C" sgs_status sgs_copy_splat_grads(sgs_ctx *c, float *out) {
   if (!c || !out) return SGS_EINVAL;
-  SGS_HIP(hipMemcpyAsync(out, c->splat_grad, sizeof(float) * SGS_SGRAD * c->vn,
-                         hipMemcpyDeviceToDevice, c->stream), "copy splat grads");
+  const int64_t count = SGS_SGRAD * c->vn;
+  k_export_grads<<<sgs_blocks(count, 256), 256, 0, c->stream>>>(count, c->splat_grad, out);
+  SGS_HIP(hipGetLastError(), "copy splat grads");
   return SGS_OK;
 }

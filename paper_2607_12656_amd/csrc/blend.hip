@@ -61,20 +61,22 @@ __device__ __forceinline__ uint64_t uniform_mask(uint64_t m) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// One tile of the forward; evals accumulates the thread's in-span pairs.
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH)
-k_blend_fwd(int n, int W, int H, int GW, int tiles_per_view, const uint2 *__restrict__ ranges,
-            const uint32_t *__restrict__ vals, const float4 *__restrict__ rec,
-            float *__restrict__ image, float *__restrict__ final_T, uint32_t *__restrict__ last,
-            unsigned long long *__restrict__ eval_count) {
+__device__ __forceinline__ void blend_fwd_tile(int tile, int n, int W, int H, int GW,
+                                               int tiles_per_view,
+                                               const uint2 *__restrict__ ranges,
+                                               const uint32_t *__restrict__ vals,
+                                               const float4 *__restrict__ rec,
+                                               float *__restrict__ image,
+                                               float *__restrict__ final_T,
+                                               uint32_t *__restrict__ last, uint32_t &evals) {
   constexpr int BS = TW * TH;
   constexpr int NW = BS / 64;  // waves = 8x8 sub-tiles
   constexpr int SUBW = TW / 8;
   __shared__ SplatLds sh[BS];
   __shared__ uint64_t s_meet[NW][NW];  // [sub-tile][64-entry word]: entries meeting the sub-tile
-  __shared__ unsigned long long s_ev[NW];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int tile = blockIdx.x;
   const int v = tile / tiles_per_view;
   const int t = tile - v * tiles_per_view;
   const int tx = t % GW, ty = t / GW;
@@ -89,7 +91,6 @@ k_blend_fwd(int n, int W, int H, int GW, int tiles_per_view, const uint2 *__rest
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
   bool done = !inside;
   uint32_t stop = rg.y - rg.x;
-  uint32_t evals = 0;
   // the next batch's records, fetched while the current one is walked
   float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra;
   auto fetch = [&](uint32_t b) {
@@ -187,7 +188,56 @@ k_blend_fwd(int n, int W, int H, int GW, int tiles_per_view, const uint2 *__rest
     final_T[(int64_t)v * plane + pix] = T;
     last[(int64_t)v * plane + pix] = stop;
   }
+}
+
+// Persistent workers: each workgroup takes tiles from the queue (tiles in the
+// order of `order`, longest lists first) until it runs dry; every workgroup
+// reaches that exit.
+__device__ __forceinline__ int next_tile(uint32_t *head, int total) {
+  __shared__ int s_q;
+  if (threadIdx.x == 0) s_q = (int)atomicAdd(head, 1u);
+  __syncthreads();
+  const int q = s_q;
+  __syncthreads();  // all threads have read s_q before it is written again
+  return q < total ? q : -1;
+}
+
+// Blend schedules.  kPerTile: one workgroup per tile (grid = tiles).
+// kStride: a resident grid, workgroup g taking positions g, g + grid, ... of
+// the length-ordered tile list.  kQueue: a resident grid taking positions of
+// that list from an atomic queue head.  Every workgroup of a persistent grid
+// leaves its loop once the positions run out.
+enum BlendSchedule { kPerTile = 0, kStride = 1, kQueue = 2 };
+
+template <int SCHED>
+__device__ __forceinline__ int first_tile(uint32_t *head, int total) {
+  if (SCHED == kQueue) return next_tile(head, total);
+  return (int)blockIdx.x < total ? (int)blockIdx.x : -1;
+}
+template <int SCHED>
+__device__ __forceinline__ int later_tile(int q, uint32_t *head, int total) {
+  if (SCHED == kPerTile) return -1;
+  if (SCHED == kQueue) return next_tile(head, total);
+  q += (int)gridDim.x;
+  return q < total ? q : -1;
+}
+
+template <int TW, int TH, int SCHED>
+__global__ void __launch_bounds__(TW * TH)
+k_blend_fwd(int total_tiles, const uint32_t *__restrict__ order, uint32_t *__restrict__ head,
+            int n, int W, int H, int GW, int tiles_per_view, const uint2 *__restrict__ ranges,
+            const uint32_t *__restrict__ vals, const float4 *__restrict__ rec,
+            float *__restrict__ image, float *__restrict__ final_T, uint32_t *__restrict__ last,
+            unsigned long long *__restrict__ eval_count) {
+  constexpr int NW = TW * TH / 64;
+  __shared__ unsigned long long s_ev[NW];
+  uint32_t evals = 0;
+  for (int q = first_tile<SCHED>(head, total_tiles); q >= 0;
+       q = later_tile<SCHED>(q, head, total_tiles))
+    blend_fwd_tile<TW, TH>(SCHED == kPerTile ? q : (int)order[q], n, W, H, GW, tiles_per_view,
+                           ranges, vals, rec, image, final_T, last, evals);
   if (eval_count) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     unsigned long long ev = evals;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) ev += __shfl_xor(ev, o, 64);
@@ -250,11 +300,15 @@ __device__ __forceinline__ float wave_transpose_sum16(const float v[16], int lan
 }
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH)
-k_blend_bwd(int n, int W, int H, int GW, int tiles_per_view, const uint2 *__restrict__ ranges,
-            const uint32_t *__restrict__ vals, const float4 *__restrict__ rec,
-            const float *__restrict__ final_T, const uint32_t *__restrict__ last,
-            const float *__restrict__ dimg, float *__restrict__ sgrad) {
+__device__ __forceinline__ void blend_bwd_tile(int tile, int n, int W, int H, int GW,
+                                               int tiles_per_view,
+                                               const uint2 *__restrict__ ranges,
+                                               const uint32_t *__restrict__ vals,
+                                               const float4 *__restrict__ rec,
+                                               const float *__restrict__ final_T,
+                                               const uint32_t *__restrict__ last,
+                                               const float *__restrict__ dimg,
+                                               double *__restrict__ sgrad) {
   constexpr int BS = TW * TH;
   constexpr int NW = BS / 64;
   constexpr int SUBW = TW / 8;
@@ -263,7 +317,6 @@ k_blend_bwd(int n, int W, int H, int GW, int tiles_per_view, const uint2 *__rest
   __shared__ uint32_t s_max[NW];
   __shared__ uint64_t s_meet[NW][NW];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int tile = blockIdx.x;
   const int v = tile / tiles_per_view;
   const int t = tile - v * tiles_per_view;
   const int tx = t % GW, ty = t / GW;
@@ -307,7 +360,9 @@ k_blend_bwd(int n, int W, int H, int GW, int tiles_per_view, const uint2 *__rest
   // its own wave sum for the values the conic does not enter
   const bool lead = (lane & 3) == 0 && vidx < 10;
   const float k_self = (vidx == 2 || vidx == 4) ? -0.5f : (vidx == 3 ? -1.0f : 1.0f);
-  float *const gbase = sgrad + base * SGS_SGRAD;
+  // per-splat sums in FP64: a splat's terms come from many tiles and
+  // cancel, and FP32 sums in arbitrary order lose the small result
+  double *const gbase = sgrad + base * SGS_SGRAD;
   float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra;
   uint32_t rgid = 0;
   auto fetch = [&](int bi) {
@@ -400,7 +455,8 @@ k_blend_bwd(int n, int W, int H, int GW, int tiles_per_view, const uint2 *__rest
         const float cs = vidx == 0 ? cur.a.z : (vidx == 1 ? cur.b.x : k_self);
         const float co = vidx < 2 ? cur.a.w : 0.0f;
         const float gv = fmaf(cs, tot, co * other);
-        if (lead && gv != 0.0f) unsafeAtomicAdd(gbase + (size_t)gid * SGS_SGRAD + vidx, gv);
+        if (lead && gv != 0.0f)
+          unsafeAtomicAdd(gbase + (size_t)gid * SGS_SGRAD + vidx, (double)gv);
       };
       // two register sets in turn: the next record loads while one is used
       int hb = 63 - __builtin_clzll(m);
@@ -434,38 +490,152 @@ k_blend_bwd(int n, int W, int H, int GW, int tiles_per_view, const uint2 *__rest
   }
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int SCHED>
+__global__ void __launch_bounds__(TW * TH)
+k_blend_bwd(int total_tiles, const uint32_t *__restrict__ order, uint32_t *__restrict__ head,
+            int n, int W, int H, int GW, int tiles_per_view, const uint2 *__restrict__ ranges,
+            const uint32_t *__restrict__ vals, const float4 *__restrict__ rec,
+            const float *__restrict__ final_T, const uint32_t *__restrict__ last,
+            const float *__restrict__ dimg, double *__restrict__ sgrad) {
+  for (int q = first_tile<SCHED>(head, total_tiles); q >= 0;
+       q = later_tile<SCHED>(q, head, total_tiles))
+    blend_bwd_tile<TW, TH>(SCHED == kPerTile ? q : (int)order[q], n, W, H, GW, tiles_per_view,
+                           ranges, vals, rec, final_T, last, dimg, sgrad);
+}
+
+// ---------------------------------------------------------------------------
+// Tile order for the persistent blend: tiles bucketed by list length (bucket
+// 0 = empty, bucket b >= 1 holds lengths in [2^(b-1), 2^b)), longest bucket
+// first; the order inside a bucket is whatever the atomics give (each tile's
+// result does not depend on it).  bins: [0,33) counts, [33,66) cursors,
+// [66] forward queue head, [67] backward queue head.
+// ---------------------------------------------------------------------------
+constexpr int kBuckets = 33;
+
+__device__ __forceinline__ int len_bucket(uint2 r) {
+  const uint32_t len = r.y - r.x;
+  return len ? 32 - __clz(len) : 0;
+}
+
+__global__ void k_tile_order_reset(uint32_t *__restrict__ bins) {
+  if (threadIdx.x < SGS_TILE_BINS) bins[threadIdx.x] = 0;
+}
+
+__global__ void __launch_bounds__(256)
+k_tile_order_count(const uint2 *__restrict__ ranges, int tiles, uint32_t *__restrict__ bins) {
+  __shared__ uint32_t s_h[kBuckets];
+  if (threadIdx.x < kBuckets) s_h[threadIdx.x] = 0;
+  __syncthreads();
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < tiles) atomicAdd(&s_h[len_bucket(ranges[t])], 1u);
+  __syncthreads();
+  if (threadIdx.x < kBuckets && s_h[threadIdx.x]) atomicAdd(&bins[threadIdx.x], s_h[threadIdx.x]);
+}
+
+__global__ void __launch_bounds__(256)
+k_tile_order_scatter(const uint2 *__restrict__ ranges, int tiles, uint32_t *__restrict__ bins,
+                     uint32_t *__restrict__ order) {
+  __shared__ uint32_t s_h[kBuckets], s_at[kBuckets];
+  if (threadIdx.x < kBuckets) s_h[threadIdx.x] = 0;
+  __syncthreads();
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = t < tiles ? len_bucket(ranges[t]) : 0;
+  const uint32_t rank = t < tiles ? atomicAdd(&s_h[b], 1u) : 0u;
+  __syncthreads();
+  if (threadIdx.x < kBuckets) {
+    const int k = threadIdx.x;
+    uint32_t start = 0;  // tiles in longer buckets
+    for (int o = k + 1; o < kBuckets; ++o) start += bins[o];
+    s_at[k] = start + (s_h[k] ? atomicAdd(&bins[kBuckets + k], s_h[k]) : 0u);
+  }
+  __syncthreads();
+  if (t < tiles) order[s_at[b] + rank] = (uint32_t)t;
+}
+
+// Workgroups resident on the device for a persistent blend kernel.
+template <typename K>
+int persistent_grid(K kernel, int block, int tiles) {
+  static int per_cu = 0, cus = 0;
+  if (per_cu == 0) {
+    int dev = 0, occ = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, block, 0) != hipSuccess ||
+        occ < 1 || n < 1)
+      return tiles;  // one workgroup per tile still drains the queue
+    per_cu = occ;
+    cus = n;
+  }
+  const int64_t g = (int64_t)per_cu * cus;
+  return (int)(g < tiles ? g : tiles);
+}
+
+template <int TW, int TH, int SCHED>
 hipError_t fwd_t(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint64_t *ec) {
-  SgsProfScope ps(c, SGS_PROF_BLEND_FWD);
   const uint32_t *vals = c->pair_val[c->pair_sorted_buf];
-  k_blend_fwd<TW, TH><<<(unsigned)c->total_tiles, TW * TH, 0, c->stream>>>(
-      (int)c->n, c->W, c->H, c->GW, (int)c->tiles_per_view, c->ranges, vals, c->rec, image,
-      final_T, last, (unsigned long long *)ec);
+  const int tiles = (int)c->total_tiles;
+  const int grid = SCHED == kPerTile ? tiles
+                                     : persistent_grid(k_blend_fwd<TW, TH, SCHED>, TW * TH, tiles);
+  k_blend_fwd<TW, TH, SCHED><<<grid, TW * TH, 0, c->stream>>>(
+      tiles, c->tile_order, c->tile_bins + 66, (int)c->n, c->W, c->H, c->GW,
+      (int)c->tiles_per_view, c->ranges, vals, c->rec, image, final_T, last,
+      (unsigned long long *)ec);
+  return hipGetLastError();
+}
+
+template <int TW, int TH, int SCHED>
+hipError_t bwd_t(sgs_ctx *c, const float *final_T, const uint32_t *last, const float *dimg) {
+  const uint32_t *vals = c->pair_val[c->pair_sorted_buf];
+  const int tiles = (int)c->total_tiles;
+  const int grid = SCHED == kPerTile ? tiles
+                                     : persistent_grid(k_blend_bwd<TW, TH, SCHED>, TW * TH, tiles);
+  k_blend_bwd<TW, TH, SCHED><<<grid, TW * TH, 0, c->stream>>>(
+      tiles, c->tile_order, c->tile_bins + 67, (int)c->n, c->W, c->H, c->GW,
+      (int)c->tiles_per_view, c->ranges, vals, c->rec, final_T, last, dimg, c->splat_grad);
   return hipGetLastError();
 }
 
 template <int TW, int TH>
-hipError_t bwd_t(sgs_ctx *c, const float *final_T, const uint32_t *last, const float *dimg) {
-  SgsProfScope ps(c, SGS_PROF_BLEND_BWD);
-  const uint32_t *vals = c->pair_val[c->pair_sorted_buf];
-  k_blend_bwd<TW, TH><<<(unsigned)c->total_tiles, TW * TH, 0, c->stream>>>(
-      (int)c->n, c->W, c->H, c->GW, (int)c->tiles_per_view, c->ranges, vals, c->rec, final_T,
-      last, dimg, c->splat_grad);
-  return hipGetLastError();
+hipError_t fwd_s(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint64_t *ec) {
+  SgsProfScope ps(c, SGS_PROF_BLEND_FWD);
+  if (c->schedule == kStride) return fwd_t<TW, TH, kStride>(c, image, final_T, last, ec);
+  if (c->schedule == kQueue) return fwd_t<TW, TH, kQueue>(c, image, final_T, last, ec);
+  return fwd_t<TW, TH, kPerTile>(c, image, final_T, last, ec);
 }
 
-__global__ void k_zero_f32(float *__restrict__ p, int64_t count) {
+template <int TW, int TH>
+hipError_t bwd_s(sgs_ctx *c, const float *final_T, const uint32_t *last, const float *dimg) {
+  SgsProfScope ps(c, SGS_PROF_BLEND_BWD);
+  if (c->schedule == kStride) return bwd_t<TW, TH, kStride>(c, final_T, last, dimg);
+  if (c->schedule == kQueue) return bwd_t<TW, TH, kQueue>(c, final_T, last, dimg);
+  return bwd_t<TW, TH, kPerTile>(c, final_T, last, dimg);
+}
+
+// Clears the per-splat gradients and the backward queue head.
+__global__ void k_zero_grad(double *__restrict__ p, int64_t count, uint32_t *__restrict__ head) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) p[i] = 0.0f;
+  if (i < count) p[i] = 0.0;
+  if (i == 0 && head) *head = 0u;
 }
 
 }  // namespace
 
+hipError_t launch_tile_order(sgs_ctx *c) {
+  if (c->schedule == kPerTile) return hipSuccess;
+  const int tiles = (int)c->total_tiles;
+  k_tile_order_reset<<<1, 128, 0, c->stream>>>(c->tile_bins);
+  k_tile_order_count<<<sgs_blocks(tiles, 256), 256, 0, c->stream>>>(c->ranges, tiles,
+                                                                   c->tile_bins);
+  k_tile_order_scatter<<<sgs_blocks(tiles, 256), 256, 0, c->stream>>>(c->ranges, tiles,
+                                                                     c->tile_bins, c->tile_order);
+  return hipGetLastError();
+}
+
 hipError_t launch_blend_fwd(sgs_ctx *c, float *image, float *final_T, uint32_t *last,
                             uint64_t *eval_count) {
-  if (c->TW == 16 && c->TH == 16) return fwd_t<16, 16>(c, image, final_T, last, eval_count);
-  if (c->TW == 8 && c->TH == 8) return fwd_t<8, 8>(c, image, final_T, last, eval_count);
-  if (c->TW == 32 && c->TH == 8) return fwd_t<32, 8>(c, image, final_T, last, eval_count);
+  if (c->TW == 16 && c->TH == 16) return fwd_s<16, 16>(c, image, final_T, last, eval_count);
+  if (c->TW == 8 && c->TH == 8) return fwd_s<8, 8>(c, image, final_T, last, eval_count);
+  if (c->TW == 32 && c->TH == 8) return fwd_s<32, 8>(c, image, final_T, last, eval_count);
   return hipErrorInvalidValue;
 }
 
@@ -474,10 +644,11 @@ hipError_t launch_blend_bwd(sgs_ctx *c, const float *final_T, const uint32_t *la
   const int64_t words = c->vn * SGS_SGRAD;
   {
     SgsProfScope ps(c, SGS_PROF_GRAD_CLEAR);
-    k_zero_f32<<<sgs_blocks(words, 256), 256, 0, c->stream>>>(c->splat_grad, words);
+    k_zero_grad<<<sgs_blocks(words, 256), 256, 0, c->stream>>>(c->splat_grad, words,
+                                                                c->tile_bins + 67);
   }
-  if (c->TW == 16 && c->TH == 16) return bwd_t<16, 16>(c, final_T, last, dimg);
-  if (c->TW == 8 && c->TH == 8) return bwd_t<8, 8>(c, final_T, last, dimg);
-  if (c->TW == 32 && c->TH == 8) return bwd_t<32, 8>(c, final_T, last, dimg);
+  if (c->TW == 16 && c->TH == 16) return bwd_s<16, 16>(c, final_T, last, dimg);
+  if (c->TW == 8 && c->TH == 8) return bwd_s<8, 8>(c, final_T, last, dimg);
+  if (c->TW == 32 && c->TH == 8) return bwd_s<32, 8>(c, final_T, last, dimg);
   return hipErrorInvalidValue;
 }

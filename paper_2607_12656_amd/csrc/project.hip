@@ -93,7 +93,7 @@ k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
 __global__ void __launch_bounds__(kPThreads)
 k_preprocess_bwd(int64_t n, int64_t npad, int V, int W, int H,
                  const sgs_camera *__restrict__ cams, const float *__restrict__ qp,
-                 const uint32_t *__restrict__ touched, const float *__restrict__ sgrad,
+                 const uint32_t *__restrict__ touched, const double *__restrict__ sgrad,
                  float *__restrict__ gout, float *__restrict__ gmask) {
   const int64_t i = (int64_t)blockIdx.x * kPThreads + threadIdx.x;
   if (i >= n) return;
@@ -108,13 +108,12 @@ k_preprocess_bwd(int64_t n, int64_t npad, int V, int W, int H,
   for (int v = 0; v < V; ++v) {
     const int64_t s = (int64_t)v * n + i;
     if (touched[s] == 0) continue;
-    const float4 g0 = *(const float4 *)(sgrad + s * SGS_SGRAD);
-    const float4 g1 = *(const float4 *)(sgrad + s * SGS_SGRAD + 4);
-    const float4 g2 = *(const float4 *)(sgrad + s * SGS_SGRAD + 8);
-    const float gpx = g0.x, gpy = g0.y, gA = g0.z, gB = g0.w;
-    const float gC = g1.x, gop = g1.y;
-    const float gcol[3] = {g1.z, g1.w, g2.x};
-    gm += g2.y;
+    const double2 *gs = (const double2 *)(sgrad + s * SGS_SGRAD);
+    const double2 h0 = gs[0], h1 = gs[1], h2 = gs[2], h3 = gs[3], h4 = gs[4];
+    const float gpx = (float)h0.x, gpy = (float)h0.y, gA = (float)h1.x, gB = (float)h1.y;
+    const float gC = (float)h2.x, gop = (float)h2.y;
+    const float gcol[3] = {(float)h3.x, (float)h3.y, (float)h4.x};
+    gm += (float)h4.y;
     SgsCam cam;
     load_cam(cams, v, cam);
     SgsProj p;

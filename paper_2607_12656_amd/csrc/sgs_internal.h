@@ -41,6 +41,7 @@ struct sgs_ctx {
   int TW = 16, TH = 16, GW = 0, GH = 0;
   int64_t tiles_per_view = 0, total_tiles = 0;
   float tau = 1.0f;
+  int schedule = 0;               // blend launch schedule (sgs_options.schedule)
   bool scene_set = false;
   bool rendered = false;
   sgs_camera *d_cams = nullptr;
@@ -54,7 +55,7 @@ struct sgs_ctx {
   uint32_t *offsets = nullptr;    // [vn + 1] exclusive scan in depth order
   uint4 *bin_splat = nullptr;     // [vn] (first tile id, width in tiles, Gaussian, pairs)
   uint4 *bin_rec = nullptr;       // [vn] the same records in depth order
-  float *splat_grad = nullptr;    // [vn][SGS_SGRAD]
+  double *splat_grad = nullptr;   // [vn][SGS_SGRAD] per-splat gradient sums (FP64 atomics)
   int depth_sorted_buf = 0;       // which depth buffer holds the sorted order
 
   // pairs
@@ -66,6 +67,8 @@ struct sgs_ctx {
   uint32_t *blk_start = nullptr;  // first splat (depth order) of every block of sorted pairs
   int64_t blk_start_words = 0;
   uint2 *ranges = nullptr;        // [total_tiles]
+  uint32_t *tile_order = nullptr; // [total_tiles] blend order, longest lists first
+  uint32_t *tile_bins = nullptr;  // [SGS_TILE_BINS] order counters and blend queue heads
 
   // reusable temporaries
   uint32_t *scan_tmp = nullptr;   int64_t scan_tmp_words = 0;
@@ -154,6 +157,8 @@ hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2],
 hipError_t launch_bin_pairs(sgs_ctx *c);   // depth order -> pairs -> tile sort -> ranges
 hipError_t launch_depth_order(sgs_ctx *c); // depth sort + scan (writes d_pairs_total)
 // blend.hip
+#define SGS_TILE_BINS 68
+hipError_t launch_tile_order(sgs_ctx *c);  // ranges -> blend tile order (longest first)
 hipError_t launch_blend_fwd(sgs_ctx *c, float *image, float *final_T, uint32_t *last,
                             uint64_t *eval_count);
 hipError_t launch_blend_bwd(sgs_ctx *c, const float *final_T, const uint32_t *last,

@@ -698,5 +698,5 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
   if (P > 0)
     k_ranges<<<sgs_blocks((P + 3) / 4, 256), 256, 0, c->stream>>>(c->tile_key[which], P, dcount,
                                                         (uint32_t)c->total_tiles, c->ranges);
-  return hipGetLastError();
+  return launch_tile_order(c);
 }

@@ -61,14 +61,16 @@ def grad_close(g, ref, tol=1e-3, name=""):
     return rel, ew
 
 
-def run_pair(orc, gctx, dev, sc, tile=(16, 16), lam=0.5, mode=0, seed=0, step=0):
+def run_pair(orc, gctx, dev, sc, tile=(16, 16), lam=0.5, mode=0, seed=0, step=0,
+             schedule="tile"):
     """GPU step and oracle step on the same inputs.  Both backward passes get
     the same dL/dimage: the GPU's L1 gradient with the oracle's margin pixels
     zeroed, so no gradient depends on a decision FP32 and FP64 may take
     differently at a kink (alpha clamp, alpha cut-off, termination)."""
     from paper_2607_12656_amd.rd import RDStep
-    _say(f"[gpu] {sc.name} tile={tile} mode={mode} n={sc.n} V={sc.views}")
-    rd = RDStep(gctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height, tile=tile)
+    _say(f"[gpu] {sc.name} tile={tile} schedule={schedule} mode={mode} n={sc.n} V={sc.views}")
+    rd = RDStep(gctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height, tile=tile,
+                schedule=schedule)
     params, q, score = T(sc.params, dev), T(sc.qstep, dev), T(sc.score, dev)
     mask, target = T(sc.given_mask, dev), T(sc.target, dev)
     rd.forward(params, q, score, target, lam, mode, mask, seed, step)
@@ -215,6 +217,19 @@ def test_c1_full_step(orc, gctx, dev):
         grad_close(g["gparams"][:, :sc.n], r["gy"][:, :sc.n], name="grad params")
         grad_close(g["gq"], r["gq"], name="grad qstep")
         grad_close(g["gmask"], r["gmhat"], name="grad mask")
+
+
+@pytest.mark.parametrize("schedule", ["stride", "queue"])
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+def test_persistent_schedules(orc, gctx, dev, tile, schedule):
+    """Resident-workgroup blend schedules (tiles ordered by list length) give
+    the same structure, image and gradients as the oracle; two views."""
+    sc = synth.make_tiny(400, 150, 90, views=2, seed=11)
+    g, r = run_pair(orc, gctx, dev, sc, tile=tile, schedule=schedule)
+    check_structure(g, r, sc)
+    check_image(g, r)
+    grad_close(g["gparams"][:, :sc.n], r["gy"][:, :sc.n], name="grad params")
+    grad_close(g["gmask"], r["gmhat"], name="grad mask")
 
 
 def test_gumbel_mask_mode(orc, gctx, dev):
