@@ -213,16 +213,19 @@ sgs_status sgs_copy_splat_grads(sgs_ctx *ctx, float *out);
 /* packed <- BF16 fragments of theta (round to nearest even). */
 sgs_status sgs_rate_mlp_pack(sgs_ctx *ctx, const float *theta, void *packed);
 /* out_R (device float[1]) = R_learned; per_gaussian (float [n], may be NULL)
- * receives f(x_i).  Features are computed from params on the fly. */
+ * receives f(x_i).  Features are computed from params on the fly; f and the
+ * hidden activation signs are kept in the context for sgs_rate_mlp_bwd. */
 sgs_status sgs_rate_mlp_fwd(sgs_ctx *ctx, const void *packed, const float *theta,
                             const float *params, const float *qstep, const uint64_t *stats,
                             const uint8_t *hard_mask, float *out_R, float *per_gaussian);
-/* Gradient of rate_weight * R_learned, recomputing the forward (no stored
- * activations), ADDED into grad_params [59][npad] and grad_qstep [59]
- * (channel minima held fixed), and dR/dM_i = f_i / n_hat added into
- * grad_hard_mask (may be NULL) and, in mask mode 1, through the
- * straight-through Gumbel-sigmoid into grad_score (may be NULL).  Call after
- * sgs_fakequant_prune_bwd. */
+/* Gradient of rate_weight * R_learned, ADDED into grad_params [59][npad] and
+ * grad_qstep [59] (channel minima held fixed), and dR/dM_i = f_i / n_hat
+ * added into grad_hard_mask (may be NULL) and, in mask mode 1, through the
+ * straight-through Gumbel-sigmoid into grad_score (may be NULL).  Uses f and
+ * the signs of the hidden pre-activations that the last sgs_rate_mlp_fwd
+ * kept in the context (32 B per Gaussian): call it after that forward, on
+ * the same packed, theta, params, qstep and stats (SGS_ESTATE if no forward
+ * ran since set_scene), and after sgs_fakequant_prune_bwd. */
 sgs_status sgs_rate_mlp_bwd(sgs_ctx *ctx, const void *packed, const float *theta,
                             const float *params, const float *qstep, const uint64_t *stats,
                             const uint8_t *hard_mask, const float *soft_mask,

@@ -58,6 +58,9 @@ void free_scene(sgs_ctx *c) {
   dfree(c->offsets);
   dfree(c->bin_rec);
   dfree(c->bin_splat);
+  dfree(c->mlp_f);
+  dfree(c->mlp_signs);
+  c->mlp_saved = false;
   dfree(c->blk_start);
   c->blk_start_words = 0;
   dfree(c->splat_grad);
@@ -209,6 +212,8 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   SGS_ALLOC(c->offsets, vn + 1);
   SGS_ALLOC(c->bin_rec, vn);
   SGS_ALLOC(c->bin_splat, vn);
+  SGS_ALLOC(c->mlp_f, n);
+  SGS_ALLOC(c->mlp_signs, 2 * n);
   SGS_ALLOC(c->splat_grad, vn * SGS_SGRAD);
   SGS_ALLOC(c->ranges, c->total_tiles);
   SGS_ALLOC(c->tile_order, c->total_tiles);
@@ -458,6 +463,7 @@ sgs_status sgs_rate_mlp_fwd(sgs_ctx *c, const void *packed, const float *theta,
   SGS_HIP(launch_mlp_rate_fwd(c, packed, theta, params, qstep, stats, hard_mask, out_R,
                               per_gaussian),
           "rate_mlp_fwd");
+  c->mlp_saved = true;
   return SGS_OK;
 }
 
@@ -475,6 +481,7 @@ sgs_status sgs_rate_mlp_bwd(sgs_ctx *c, const void *packed, const float *theta,
   if (mask_mode == 1 && grad_score && !soft_mask)
     return fail(c, SGS_EINVAL, "rate_mlp_bwd: soft_mask needed for the score gradient");
   if (!aligned(packed, 16)) return fail(c, SGS_EINVAL, "rate_mlp_bwd: packed must be 16-byte aligned");
+  if (!c->mlp_saved) return fail(c, SGS_ESTATE, "rate_mlp_bwd: rate_mlp_fwd first");
   SGS_HIP(launch_mlp_rate_bwd(c, packed, theta, params, qstep, stats, hard_mask, soft_mask,
                               mask_mode, rate_weight, grad_params, grad_qstep,
                               mask_mode == 1 ? grad_score : nullptr, grad_hard_mask),

@@ -95,6 +95,19 @@ struct MlpLdsBwd {
   bf16x4 F1B[2][16][64];
 };
 
+// Backward-only weights: W2 and W1 fragments and w3 (48.5 KB).
+struct MlpLdsB {
+  bf16x4 F2B[4][16][64];
+  bf16x4 F1B[2][16][64];
+  float w3[MH];
+};
+__device__ void load_lds_b(MlpLdsB &L, const bf16x4 *__restrict__ packed,
+                           const float *__restrict__ th) {
+  bf16x4 *d = &L.F2B[0][0][0];
+  for (int e = threadIdx.x; e < kF2B + kF1B; e += blockDim.x) d[e] = packed[kF1 + kF2 + e];
+  for (int k = threadIdx.x; k < MH; k += blockDim.x) L.w3[k] = rbf(th[kOffW3 + k]);
+}
+
 __device__ void load_lds(MlpLds &L, const bf16x4 *__restrict__ packed, const float *__restrict__ th) {
   bf16x4 *d1 = &L.F1[0][0][0];
   for (int e = threadIdx.x; e < kF1 + kF2; e += blockDim.x) d1[e] = packed[e];  // F1 then F2
@@ -156,22 +169,83 @@ __device__ __forceinline__ float tile_fwd(const MlpLds &L, const bf16x4 xb[8], i
   return p + L.b3;
 }
 
-// Features of one row for k-step s: channels 8s + 4(l/32) + 0..3.
-__device__ __forceinline__ bf16x4 feature_frag(const float *__restrict__ y, int64_t npad, int64_t r,
-                                               bool valid, const float *__restrict__ q,
-                                               const float *s_min, int s, int lane) {
-  float v[4];
+// The same forward keeping only the signs of the pre-activations: bit
+// 16t + i of m1 / m2 is [z > 0] of accumulator element i of output tile t of
+// layer 1 / 2, which is all the backward needs of them.  One set of
+// accumulators serves both layers, so the wave holds 64 instead of 128.
+__device__ __forceinline__ float tile_fwd_masks(const MlpLds &L, const bf16x4 xb[8], int lane,
+                                                uint64_t &m1, uint64_t &m2) {
+  f32x16 z[4];
+  bf16x4 hb[16];
 #pragma unroll
-  for (int jj = 0; jj < 4; ++jj) {
-    const int j = 8 * s + 4 * (lane >> 5) + jj;
-    float x = 0.0f;
-    if (valid && j < SGS_NCH) {
-      const float u = (y[j * npad + r] - s_min[j]) / q[j];
-      x = log2f(1.0f + u);
-    }
-    v[jj] = x;
+  for (int t = 0; t < 4; ++t) z[t] = zero16();
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) z[t] = mfma(L.F1[t][s][lane], xb[s], z[t]);
+    // bound the fragments the compiler reads ahead (registers)
+    if ((s & 3) == 3) __asm__ volatile("" ::: "memory");
   }
-  return pack4(v[0], v[1], v[2], v[3]);
+  uint32_t mw[2] = {0u, 0u};  // the two 32-bit halves of m1
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      float h[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = 4 * g + j;
+        const float zz = z[t][i] + L.b1[32 * t + drow(i, lane)];
+        mw[t >> 1] |= zz > 0.0f ? 1u << (16 * (t & 1) + i) : 0u;
+        h[j] = fmaxf(zz, 0.0f);
+      }
+      hb[4 * t + g] = pack4(h[0], h[1], h[2], h[3]);
+    }
+  m1 = (uint64_t)mw[0] | ((uint64_t)mw[1] << 32);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) z[t] = zero16();
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) z[t] = mfma(L.F2[t][s][lane], hb[s], z[t]);
+    // bound the fragments the compiler reads ahead (registers)
+    if ((s & 3) == 3) __asm__ volatile("" ::: "memory");
+  }
+  float p = 0.0f;
+  uint32_t nw[2] = {0u, 0u};  // the two 32-bit halves of m2
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int o = 32 * t + drow(i, lane);
+      const float zz = z[t][i] + L.b2[o];
+      nw[t >> 1] |= zz > 0.0f ? 1u << (16 * (t & 1) + i) : 0u;
+      p = fmaf(fmaxf(zz, 0.0f), L.w3[o], p);
+    }
+  m2 = (uint64_t)nw[0] | ((uint64_t)nw[1] << 32);
+  p += __shfl_xor(p, 32, 64);
+  return p + L.b3;
+}
+
+// Features of the lane's row for all eight k-steps: x = log2(1 + u),
+// u = (y - m) / q for channel 8s + 4(l/32) + jj.  The reciprocal steps rq
+// and the minima come from LDS; rows past n and the padding channels are
+// zero.
+__device__ __forceinline__ void features(const float *__restrict__ y, int64_t npad, int64_t r,
+                                         bool valid, const float *s_rq, const float *s_min,
+                                         int lane, bf16x4 xb[8]) {
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    float v[4];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int j = 8 * s + 4 * (lane >> 5) + jj;
+      float uu = 0.0f;
+      if (valid && j < SGS_NCH) uu = (y[j * npad + r] - s_min[j]) * s_rq[j];
+      v[jj] = __log2f(1.0f + uu);
+    }
+    xb[s] = pack4(v[0], v[1], v[2], v[3]);
+  }
 }
 
 __device__ __forceinline__ void load_mins(float *s_min, const uint64_t *__restrict__ stats) {
@@ -182,18 +256,25 @@ __device__ __forceinline__ void load_mins(float *s_min, const uint64_t *__restri
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
+__device__ __forceinline__ void load_steps(float *s_rq, const float *__restrict__ q) {
+  for (int j = threadIdx.x; j < SGS_NCH; j += blockDim.x) s_rq[j] = 1.0f / q[j];
+}
+
 // In-loop forward: R partials = sum_r M_r f(x_r) per block (FP64), f optional.
-__global__ void __launch_bounds__(kThreads)
+// Keeps f and the activation signs for the backward.
+__global__ void __launch_bounds__(kThreads, 2)
 k_mlp_rate_fwd(int64_t n, int64_t npad, const bf16x4 *__restrict__ packed,
                const float *__restrict__ th, const float *__restrict__ y,
                const float *__restrict__ q, const uint64_t *__restrict__ stats,
                const uint8_t *__restrict__ hard, float *__restrict__ fout,
+               float *__restrict__ fsave, uint4 *__restrict__ signs,
                double *__restrict__ partial) {
   __shared__ MlpLds L;
-  __shared__ float s_min[SGS_NCH];
+  __shared__ float s_min[SGS_NCH], s_rq[SGS_NCH];
   __shared__ double s_red[kWaves];
   load_lds(L, packed, th);
   load_mins(s_min, stats);
+  load_steps(s_rq, q);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t ntiles = (n + 31) / 32;
@@ -206,14 +287,18 @@ k_mlp_rate_fwd(int64_t n, int64_t npad, const bf16x4 *__restrict__ packed,
     const int64_t r = tile * 32 + (lane & 31);
     const bool valid = r < n;
     bf16x4 xb[8];
-#pragma unroll
-    for (int s = 0; s < 8; ++s) xb[s] = feature_frag(y, npad, r, valid, q, s_min, s, lane);
-    f32x16 z1[4], z2[4];
-    bf16x4 hb[16];
-    const float f = tile_fwd(L, xb, lane, z1, z2, hb);
-    if (valid && lane < 32) {
-      if (fout) fout[r] = f;
-      if (hard[r]) acc += (double)f;
+    features(y, npad, r, valid, s_rq, s_min, lane, xb);
+    uint64_t m1, m2;
+    const float f = tile_fwd_masks(L, xb, lane, m1, m2);
+    if (valid) {
+      // what the backward needs of this forward: f and the activation signs
+      signs[2 * r + (lane >> 5)] =
+          make_uint4((uint32_t)m1, (uint32_t)(m1 >> 32), (uint32_t)m2, (uint32_t)(m2 >> 32));
+      if (lane < 32) {
+        fsave[r] = f;
+        if (fout) fout[r] = f;
+        if (hard[r]) acc += (double)f;
+      }
     }
   }
   acc = sgs_wave_sum_d(acc);
@@ -243,26 +328,29 @@ __global__ void k_mlp_rate_finish(int nb, const double *__restrict__ partial, in
 
 // In-loop backward of weight * R, R = (1/N_hat) sum_r M_r f(x_r), through the
 // MLP to the features, then to the raw parameters and the steps (channel
-// minima held fixed); dR/dM_r = f_r / N_hat.  Adds into grad_params,
-// per-block step partials, grad_score (mask mode 1) / grad_hard_mask.
-__global__ void __launch_bounds__(kThreads)
+// minima held fixed); dR/dM_r = f_r / N_hat.  Uses f and the activation
+// signs the forward kept (no forward recompute, so only the backward
+// weights sit in LDS).  Adds into grad_params, per-block step partials,
+// grad_score (mask mode 1) / grad_hard_mask.
+__global__ void __launch_bounds__(kThreads, 2)
 k_mlp_rate_bwd(int64_t n, int64_t npad, int64_t n_hat, float weight, float tau, int mode,
                const bf16x4 *__restrict__ packed, const float *__restrict__ th,
                const float *__restrict__ y, const float *__restrict__ q,
                const uint64_t *__restrict__ stats, const uint8_t *__restrict__ hard,
-               const float *__restrict__ soft, float *__restrict__ gparams,
+               const float *__restrict__ soft, const float *__restrict__ fsave,
+               const uint4 *__restrict__ signs, float *__restrict__ gparams,
                float *__restrict__ gscore, float *__restrict__ gmask,
                double *__restrict__ qpartial) {
-  __shared__ MlpLdsBwd L;
+  __shared__ MlpLdsB L;
   __shared__ float s_min[SGS_NCH];
-  __shared__ float s_q[SGS_NCH];
+  __shared__ float s_rq[SGS_NCH];
   __shared__ double s_gq[kWaves][64];
-  load_lds_bwd(L, packed, th);
+  load_lds_b(L, packed, th);
   load_mins(s_min, stats);
-  for (int j = threadIdx.x; j < SGS_NCH; j += blockDim.x) s_q[j] = q[j];
+  load_steps(s_rq, q);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const float ln2 = 0.69314718055994531f;
+  const float inv_ln2 = 1.4426950408889634f;
   const float cscale = weight / (float)n_hat;
   float gq[32];
 #pragma unroll
@@ -271,21 +359,18 @@ k_mlp_rate_bwd(int64_t n, int64_t npad, int64_t n_hat, float weight, float tau, 
   for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < ntiles;
        tile += (int64_t)gridDim.x * kWaves) {
     // keep the weight fragments in LDS: without this the loop-invariant
-    // fragment reads are hoisted into ~200 registers and the kernel spills
+    // fragment reads are hoisted into registers and the kernel spills
     __asm__ volatile("" ::: "memory");
     const int64_t r = tile * 32 + (lane & 31);
     const bool valid = r < n;
-    bf16x4 xb[8];
-#pragma unroll
-    for (int s = 0; s < 8; ++s) xb[s] = feature_frag(y, npad, r, valid, s_q, s_min, s, lane);
-    f32x16 z1[4], z2[4];
-    bf16x4 hb[16];
-    const float f = tile_fwd(L.f, xb, lane, z1, z2, hb);
     const bool m = valid && hard[r];
-    const float c = m ? cscale : 0.0f;
+    uint4 sg = make_uint4(0u, 0u, 0u, 0u);
+    if (valid) sg = signs[2 * r + (lane >> 5)];
+    const uint64_t m1 = (uint64_t)sg.x | ((uint64_t)sg.y << 32);
+    const uint64_t m2 = (uint64_t)sg.z | ((uint64_t)sg.w << 32);
     // mask gradient
     if (valid && lane < 32) {
-      const float gmv = cscale * f;
+      const float gmv = cscale * fsave[r];
       if (gmask) gmask[r] += gmv;
       if (mode == 1 && gscore) {
         const float sm = soft[r];
@@ -293,6 +378,7 @@ k_mlp_rate_bwd(int64_t n, int64_t npad, int64_t n_hat, float weight, float tau, 
       }
     }
     if (__ballot(m) == 0ull) continue;
+    const float c = m ? cscale : 0.0f;
     // dz2 = c w3 [z2 > 0]  (BF16, B operand layout)
     bf16x4 dzb[16];
 #pragma unroll
@@ -301,58 +387,75 @@ k_mlp_rate_bwd(int64_t n, int64_t npad, int64_t n_hat, float weight, float tau, 
       for (int g = 0; g < 4; ++g) {
         float v[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int i = 4 * g + j;
-          v[j] = z2[t][i] > 0.0f ? c * L.f.w3[32 * t + drow(i, lane)] : 0.0f;
+        for (int jj = 0; jj < 4; ++jj) {
+          const int i = 4 * g + jj;
+          v[jj] = (m2 >> (16 * t + i)) & 1ull ? c * L.w3[32 * t + drow(i, lane)] : 0.0f;
         }
         dzb[4 * t + g] = pack4(v[0], v[1], v[2], v[3]);
       }
-    // dh1^T = W2 dZ2^T ; dz1 = dh1 [z1 > 0]
-    f32x16 dh[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) dh[t] = zero16();
-#pragma unroll
-    for (int s = 0; s < 16; ++s)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) dh[t] = mfma(L.F2B[t][s][lane], dzb[s], dh[t]);
-    bf16x4 d1b[16];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        float v[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int i = 4 * g + j;
-          v[j] = z1[t][i] > 0.0f ? dh[t][i] : 0.0f;
-        }
-        d1b[4 * t + g] = pack4(v[0], v[1], v[2], v[3]);
-      }
-    // dX^T = W1 dZ1^T
+    // dh1^T = W2 dZ2^T, dz1 = dh1 [z1 > 0], dX^T = W1 dZ1^T, by halves of the
+    // 128 hidden units (fewer live accumulators)
     f32x16 dx[2];
     dx[0] = zero16();
     dx[1] = zero16();
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      dx[0] = mfma(L.F1B[0][s][lane], d1b[s], dx[0]);
-      dx[1] = mfma(L.F1B[1][s][lane], d1b[s], dx[1]);
+    for (int half = 0; half < 2; ++half) {
+      f32x16 dh[2];
+      dh[0] = zero16();
+      dh[1] = zero16();
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt)
+          dh[tt] = mfma(L.F2B[2 * half + tt][s][lane], dzb[s], dh[tt]);
+        if ((s & 3) == 3) __asm__ volatile("" ::: "memory");
+      }
+      bf16x4 d1b[8];
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int t = 2 * half + tt;
+          float v[4];
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            const int i = 4 * g + jj;
+            v[jj] = (m1 >> (16 * t + i)) & 1ull ? dh[tt][i] : 0.0f;
+          }
+          d1b[4 * tt + g] = pack4(v[0], v[1], v[2], v[3]);
+        }
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        dx[0] = mfma(L.F1B[0][8 * half + s][lane], d1b[s], dx[0]);
+        dx[1] = mfma(L.F1B[1][8 * half + s][lane], d1b[s], dx[1]);
+      }
     }
-    // chain to y and q: x = log2(1 + u), u = (y - m) / q
+    // chain to y and q: x = log2(1 + u), u = (y - m) / q.  Accumulator
+    // element (t, i) is channel 32t + drow(i, lane); per half of the
+    // channels all loads (y and the read-modify-write of grad_params) first.
+    __builtin_amdgcn_sched_barrier(0);  // keep these loads out of the MFMA section
     if (valid) {
 #pragma unroll
-      for (int t = 0; t < 2; ++t)
+      for (int t = 0; t < 2; ++t) {
+        float yv[16], old[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int j = 32 * t + drow(i, lane);
-          if (j < SGS_NCH) {
-            const float qj = s_q[j];
-            const float u = (y[j * npad + r] - s_min[j]) / qj;
-            const float dxdu = 1.0f / ((1.0f + u) * ln2);
-            const float g = dx[t][i] * dxdu;
-            gparams[j * npad + r] += g / qj;
-            gq[16 * t + i] -= g * u / qj;
+          const bool ok = j < SGS_NCH;
+          yv[i] = ok ? y[j * npad + r] : 0.0f;
+          old[i] = ok ? gparams[j * npad + r] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int j = 32 * t + drow(i, lane);
+          if (t == 0 || j < SGS_NCH) {
+            const float uu = (yv[i] - s_min[j]) * s_rq[j];
+            const float gp = dx[t][i] * __builtin_amdgcn_rcpf(1.0f + uu) * inv_ln2 * s_rq[j];
+            gparams[j * npad + r] = old[i] + gp;
+            gq[16 * t + i] -= gp * uu;
           }
         }
+      }
     }
   }
   // reduce the step gradient: lanes sharing lane>>5 hold the same channels
@@ -387,7 +490,7 @@ __global__ void k_mlp_q_finish(int nb, const double *__restrict__ qpartial,
 }
 
 // Inference over given feature rows X [B][64] (BF16) -> f [B].
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads, 2)
 k_mlp_infer(int64_t B, const bf16x4 *__restrict__ packed, const float *__restrict__ th,
             const uint16_t *__restrict__ X, float *__restrict__ fout) {
   __shared__ MlpLds L;
@@ -411,9 +514,8 @@ k_mlp_infer(int64_t B, const bf16x4 *__restrict__ packed, const float *__restric
         xb[s] = pack4(0.f, 0.f, 0.f, 0.f);
       }
     }
-    f32x16 z1[4], z2[4];
-    bf16x4 hb[16];
-    const float f = tile_fwd(L, xb, lane, z1, z2, hb);
+    uint64_t m1, m2;
+    const float f = tile_fwd_masks(L, xb, lane, m1, m2);
     if (valid && lane < 32) fout[r] = f;
   }
 }
@@ -644,6 +746,26 @@ hipError_t launch_mlp_pack(sgs_ctx *c, const float *theta, void *packed) {
   return hipGetLastError();
 }
 
+// Grid of a grid-stride kernel sized to the workgroups the device holds at
+// once, so no second partial round of workgroups runs at low occupancy.
+template <typename K>
+int resident_grid(K kernel, int64_t rows) {
+  static int cap = 0;
+  if (cap == 0) {
+    int dev = 0, occ = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, kThreads, 0) == hipSuccess &&
+        occ > 0 && cus > 0)
+      cap = occ * cus;
+    else
+      cap = 1024;
+  }
+  const int64_t tiles = (rows + 31) / 32;
+  const int64_t want = (tiles + kWaves - 1) / kWaves;
+  return (int)(want < cap ? (want < 1 ? 1 : want) : cap);
+}
+
 int mlp_grid(int64_t rows) {
   const int64_t tiles = (rows + 31) / 32;
   const int64_t want = (tiles + kWaves - 1) / kWaves;
@@ -654,10 +776,11 @@ hipError_t launch_mlp_rate_fwd(sgs_ctx *c, const void *packed, const float *thet
                                const float *params, const float *q, const uint64_t *stats,
                                const uint8_t *hard, float *outR, float *fout) {
   SgsProfScope ps(c, SGS_PROF_MLP_FWD);
-  const int nb = mlp_grid(c->n);
+  const int nb = resident_grid(k_mlp_rate_fwd, c->n);
   if (nb > c->red_tmp_words) return hipErrorInvalidValue;
   k_mlp_rate_fwd<<<nb, kThreads, 0, c->stream>>>(c->n, c->npad, (const bf16x4 *)packed, theta,
-                                                 params, q, stats, hard, fout, c->red_tmp);
+                                                 params, q, stats, hard, fout, c->mlp_f,
+                                                 c->mlp_signs, c->red_tmp);
   k_mlp_rate_finish<<<1, kThreads, 0, c->stream>>>(nb, c->red_tmp, c->n_hat, outR);
   return hipGetLastError();
 }
@@ -667,11 +790,12 @@ hipError_t launch_mlp_rate_bwd(sgs_ctx *c, const void *packed, const float *thet
                                const uint8_t *hard, const float *soft, int mode, float weight,
                                float *gparams, float *gqstep, float *gscore, float *gmask) {
   SgsProfScope ps(c, SGS_PROF_MLP_BWD);
-  const int nb = mlp_grid(c->n);
+  const int nb = resident_grid(k_mlp_rate_bwd, c->n);
   if ((int64_t)nb * 64 > c->red_tmp_words) return hipErrorInvalidValue;
   k_mlp_rate_bwd<<<nb, kThreads, 0, c->stream>>>(c->n, c->npad, c->n_hat, weight, c->tau, mode,
                                                  (const bf16x4 *)packed, theta, params, q, stats,
-                                                 hard, soft, gparams, gscore, gmask, c->red_tmp);
+                                                 hard, soft, c->mlp_f, c->mlp_signs, gparams,
+                                                 gscore, gmask, c->red_tmp);
   k_mlp_q_finish<<<1, 64, 0, c->stream>>>(nb, c->red_tmp, gqstep);
   return hipGetLastError();
 }

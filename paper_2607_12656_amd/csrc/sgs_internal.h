@@ -74,6 +74,9 @@ struct sgs_ctx {
   uint32_t *scan_tmp = nullptr;   int64_t scan_tmp_words = 0;
   uint32_t *sort_hist = nullptr;  int64_t sort_hist_words = 0;
   double *red_tmp = nullptr;      int64_t red_tmp_words = 0;
+  float *mlp_f = nullptr;         // [n] f of the last learned-rate forward
+  uint4 *mlp_signs = nullptr;     // [2n] its hidden activation signs (two lanes per row)
+  bool mlp_saved = false;         // a learned-rate forward ran since set_scene
   uint32_t *d_pairs_total = nullptr;  // [0] pair count, [1] count clamped to capacity, [2] overflow
   uint32_t *h_pairs_total = nullptr;  // pinned host mirror
   bool fixed_cap = false;             // pair capacity fixed by the caller: no host sync per step
