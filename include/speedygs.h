@@ -247,6 +247,39 @@ sgs_status sgs_rate_mlp_train_step(sgs_ctx *ctx, float *theta, float *adam_m, fl
                                    int64_t rows, float lr, int64_t step, float *loss,
                                    float *grad_theta, void *scratch);
 
+/* Channel-wise fixed-length coding (Sec. 3.4.1: each channel stored with the
+ * fixed bit width its quantization precision gives, plus per-channel
+ * metadata) of the kept Gaussians' quantization codes k_ij = rint(y_ij/q_j)
+ * (the fake quantizer's decision, FP32 division, ties to even).
+ * Stream: a header of 59 sgs_fl_channel records, then the payload,
+ * channel-major, kept Gaussians in index order, each k_ij - kmin_j in
+ * width_j bits LSB first; stream bit b is bit (b & 7) of byte b >> 3 (bit
+ * b & 31 of 32-bit word b >> 5); width_j = ceil(log2(kmax_j - kmin_j + 1))
+ * over the kept Gaussians, 0 for a constant channel or when none is kept.
+ * Its size in bits is payload + 59 * 72 (q f32, kmin i32, width u8). */
+typedef struct {
+  float q;        /* q_j */
+  int32_t kmin;   /* smallest kept code */
+  int32_t width;  /* bits per kept Gaussian, 0..32 */
+} sgs_fl_channel;
+
+/* Encode params (SoA [59][npad], 16-byte aligned), qstep [59] and hard_mask
+ * [n] of the context's scene.  header: device sgs_fl_channel[59]; payload:
+ * device uint32 words, payload_words of them (words past the payload's end
+ * are left untouched); info: device int64[3] receiving {payload bits, kept
+ * Gaussians, flags}, flags bit 0 = a code outside int32 (that value is
+ * stored as 0), bit 1 = payload_words too small (the stream is cut there).
+ * Sync-free; read info afterwards. */
+sgs_status sgs_fl_encode(sgs_ctx *ctx, const float *params, const float *qstep,
+                         const uint8_t *hard_mask, sgs_fl_channel *header, uint32_t *payload,
+                         int64_t payload_words, int64_t *info);
+/* Decode: out [59][out_pad] (device, out_pad >= kept) receives the
+ * dequantized parameters fl32((kmin_j + v) q_j) of the kept Gaussians in
+ * index order (equal to the fake quantizer's output for them).  kept is the
+ * count the encoder reported; payload holds payload_words words. */
+sgs_status sgs_fl_decode(sgs_ctx *ctx, const sgs_fl_channel *header, const uint32_t *payload,
+                         int64_t payload_words, int64_t kept, int64_t out_pad, float *out);
+
 /* Kernel-group timing with HIP events recorded on the context's stream around
  * each group's launches (no extra synchronization inside a step).  Groups: */
 enum {
@@ -267,7 +300,8 @@ enum {
   SGS_PROF_MLP_FWD = 14,   /* a13 learned rate, forward / inference */
   SGS_PROF_MLP_BWD = 15,   /* a13 learned rate, backward */
   SGS_PROF_MLP_TRAIN = 16, /* a13 training step */
-  SGS_PROF_GROUPS = 17
+  SGS_PROF_CODEC = 17,     /* fixed-length encode / decode */
+  SGS_PROF_GROUPS = 18
 };
 /* enable != 0 starts recording (and clears earlier records); 0 stops. */
 sgs_status sgs_profile_enable(sgs_ctx *ctx, int32_t enable);

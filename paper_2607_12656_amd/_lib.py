@@ -78,10 +78,12 @@ _SIGS = {
     "sgs_rate_mlp_infer": [P, P, P, P, I64, P],
     "sgs_rate_mlp_train_scratch_bytes": [I64],
     "sgs_rate_mlp_train_step": [P, P, P, P, P, P, P, I64, F32, I64, P, P, P],
+    "sgs_fl_encode": [P, P, P, P, P, P, I64, P],
+    "sgs_fl_decode": [P, P, P, I64, I64, I64, P],
 }
 PROF_GROUPS = ("fakequant", "rate", "preprocess", "depth_sort", "scan", "duplicate",
                "tile_sort", "ranges", "blend_fwd", "l1", "grad_clear", "blend_bwd",
-               "preprocess_bwd", "fakequant_bwd", "mlp_fwd", "mlp_bwd", "mlp_train")
+               "preprocess_bwd", "fakequant_bwd", "mlp_fwd", "mlp_bwd", "mlp_train", "codec")
 MLP_PARAMS = 24961
 MLP_PACKED_BYTES = 98304
 EXPORTS = tuple(_SIGS)
@@ -268,6 +270,17 @@ class Context:
             self.h, _ptr(packed), _ptr(theta), _ptr(params), _ptr(qstep), _ptr(stats),
             _ptr(hard_mask), _ptr(soft_mask), mask_mode, rate_weight, _ptr(grad_params),
             _ptr(grad_qstep), _ptr(grad_score), _ptr(grad_hard_mask)), self.h)
+
+    def fl_encode(self, params, qstep, hard_mask, header, payload, payload_words, info):
+        """Fixed-length encode (header int32 [59][3]: q bits, kmin, width;
+        info int64 [3]: payload bits, kept, flags)."""
+        self._check(self.L.sgs_fl_encode(self.h, _ptr(params), _ptr(qstep), _ptr(hard_mask),
+                                         _ptr(header), _ptr(payload), payload_words,
+                                         _ptr(info)), self.h)
+
+    def fl_decode(self, header, payload, payload_words, kept, out_pad, out):
+        self._check(self.L.sgs_fl_decode(self.h, _ptr(header), _ptr(payload), payload_words,
+                                         kept, out_pad, _ptr(out)), self.h)
 
     def rate_mlp_infer(self, packed, theta, X, rows, out):
         self._check(self.L.sgs_rate_mlp_infer(self.h, _ptr(packed), _ptr(theta), _ptr(X), rows,

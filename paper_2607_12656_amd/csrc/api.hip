@@ -59,6 +59,8 @@ void free_scene(sgs_ctx *c) {
   dfree(c->bin_rec);
   dfree(c->bin_splat);
   dfree(c->mlp_f);
+  dfree(c->fl_tmp);
+  c->fl_tmp_words = 0;
   dfree(c->mlp_signs);
   c->mlp_saved = false;
   dfree(c->blk_start);
@@ -213,6 +215,8 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   SGS_ALLOC(c->bin_rec, vn);
   SGS_ALLOC(c->bin_splat, vn);
   SGS_ALLOC(c->mlp_f, n);
+  SGS_ALLOC(c->fl_tmp, fl_scratch_words(n));
+  c->fl_tmp_words = fl_scratch_words(n);
   SGS_ALLOC(c->mlp_signs, 2 * n);
   SGS_ALLOC(c->splat_grad, vn * SGS_SGRAD);
   SGS_ALLOC(c->ranges, c->total_tiles);
@@ -340,6 +344,34 @@ sgs_status sgs_fakequant_prune_bwd(sgs_ctx *c, const float *params, const float 
   SGS_HIP(launch_fakequant_bwd(c, params, qstep, soft_mask, mask_mode, rate_grad, stats,
                                grad_qparams, grad_hard_mask, grad_params, grad_qstep, grad_score),
           "fakequant_prune_bwd");
+  return SGS_OK;
+}
+
+sgs_status sgs_fl_encode(sgs_ctx *c, const float *params, const float *qstep,
+                         const uint8_t *hard_mask, sgs_fl_channel *header, uint32_t *payload,
+                         int64_t payload_words, int64_t *info) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "fl_encode: set_scene first");
+  if (!params || !qstep || !hard_mask || !header || !info || (payload_words > 0 && !payload))
+    return fail(c, SGS_EINVAL, "fl_encode: null pointer");
+  if (payload_words < 0) return fail(c, SGS_EINVAL, "fl_encode: payload_words < 0");
+  if (!aligned(params, 16) || !aligned(info, 8))
+    return fail(c, SGS_EINVAL, "fl_encode: params must be 16-byte and info 8-byte aligned");
+  SGS_HIP(launch_fl_encode(c, params, qstep, hard_mask, header, payload, payload_words, info),
+          "fl_encode");
+  return SGS_OK;
+}
+
+sgs_status sgs_fl_decode(sgs_ctx *c, const sgs_fl_channel *header, const uint32_t *payload,
+                         int64_t payload_words, int64_t kept, int64_t out_pad, float *out) {
+  if (!c) return SGS_EINVAL;
+  if (!header || !out || (payload_words > 0 && !payload))
+    return fail(c, SGS_EINVAL, "fl_decode: null pointer");
+  if (kept < 0 || out_pad < kept || payload_words < 0)
+    return fail(c, SGS_EINVAL, "fl_decode: need 0 <= kept <= out_pad, payload_words >= 0");
+  if (kept > (int64_t)INT32_MAX * 4096LL)
+    return fail(c, SGS_ECAPACITY, "fl_decode: kept too large");
+  SGS_HIP(launch_fl_decode(c, header, payload, payload_words, kept, out_pad, out), "fl_decode");
   return SGS_OK;
 }
 

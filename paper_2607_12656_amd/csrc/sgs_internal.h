@@ -74,6 +74,8 @@ struct sgs_ctx {
   uint32_t *scan_tmp = nullptr;   int64_t scan_tmp_words = 0;
   uint32_t *sort_hist = nullptr;  int64_t sort_hist_words = 0;
   double *red_tmp = nullptr;      int64_t red_tmp_words = 0;
+  uint32_t *fl_tmp = nullptr;     // fixed-length encoder scratch
+  int64_t fl_tmp_words = 0;
   float *mlp_f = nullptr;         // [n] f of the last learned-rate forward
   uint4 *mlp_signs = nullptr;     // [2n] its hidden activation signs (two lanes per row)
   bool mlp_saved = false;         // a learned-rate forward ran since set_scene
@@ -161,6 +163,13 @@ hipError_t launch_bin_pairs(sgs_ctx *c);   // depth order -> pairs -> tile sort 
 hipError_t launch_depth_order(sgs_ctx *c); // depth sort + scan (writes d_pairs_total)
 // blend.hip
 #define SGS_TILE_BINS 68
+// codec.hip
+int64_t fl_scratch_words(int64_t n);
+hipError_t launch_fl_encode(sgs_ctx *c, const float *params, const float *q, const uint8_t *hard,
+                            sgs_fl_channel *hdr, uint32_t *payload, int64_t cap_words,
+                            int64_t *out);
+hipError_t launch_fl_decode(sgs_ctx *c, const sgs_fl_channel *hdr, const uint32_t *payload,
+                            int64_t words, int64_t kept, int64_t out_pad, float *out);
 hipError_t launch_tile_order(sgs_ctx *c);  // ranges -> blend tile order (longest first)
 hipError_t launch_blend_fwd(sgs_ctx *c, float *image, float *final_T, uint32_t *last,
                             uint64_t *eval_count);

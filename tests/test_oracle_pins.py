@@ -512,6 +512,14 @@ def test_fixed_length_coder_hand_case_and_round_trip(orc):
     assert (kmin[0], kmax[0]) == (-2, 5)
     assert width[3:].sum() == 0
     assert bits == 4 * (3 + 0 + 4) + 59 * 72
+    # payload bytes written out by hand from the stream definition (channel-
+    # major, kept Gaussians in index order, k - kmin in w bits LSB first):
+    # channel 0, w 3: 5, 0, 7, 2 -> bits 101 000 111 010; channel 2, w 4:
+    # 0, 1, 0, 9 -> 0000 1000 0000 1001 (bit 0 first); bytes C5 05 01 09
+    _, buf, bits2 = orc.fixed_length_roundtrip(k, m, n)
+    assert bits2 - 59 * 72 == 28
+    assert list(buf[:4]) == [0xC5, 0x05, 0x01, 0x09]
+    assert not buf[4:].any()
     rng = np.random.default_rng(0)
     k2 = rng.integers(-300, 300, size=(NCH, 128)).astype(np.int32)
     m2 = (rng.random(100) < 0.7).astype(np.uint8)
