@@ -21,8 +21,9 @@ the set the backward re-walks), the roofline of the dominant kernel group
 (HIP events recorded on the library's stream around every kernel group over
 the timed region), the same step replayed from a HIP graph, the learned-rate
 step (MLP in the loop, forward + recompute backward) timed beside it, the
-MLP's training / inference throughput, and the FP64 oracle timed on the host
-as a CPU baseline.
+MLP's training / inference throughput, the fixed-length encode / decode of
+the kept Gaussians (Sec. 3.4.1), and the FP64 oracle timed on the host as a
+CPU baseline.
 """
 from __future__ import annotations
 
@@ -115,7 +116,7 @@ def main():
                     help="blend launch schedule when --tile names a shape (default: stride "
                          "on the 1M workload, where the autotuner picks it, else tile)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip graph / learned / MLP legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip graph / learned / MLP / codec legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (scale for HBM counters)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -322,6 +323,44 @@ def main():
             "infer_mfma_frac": round(Ni * MLP_FLOP_PER_ROW / (ims * 1e-3) / 1e12
                                      / BF16_MFMA_PEAK_TFLOPS, 4)}
         del Xin, fo, Xtr, scratch
+
+        # fixed-length coding of the kept Gaussians (the pruned step's mask)
+        rd.forward(params, q, score, target, lam, 0, mask, 0, 0)
+        words = sc.n * NCH + 64                 # 32 bits per code at most
+        hdr = torch.empty((NCH, 3), dtype=torch.int32, device=dev)
+        payload = torch.empty(words, dtype=torch.int32, device=dev)
+        info = torch.empty(3, dtype=torch.int64, device=dev)
+        ctx.fl_encode(params, q, rd.hard, hdr, payload, words, info)
+        torch.cuda.synchronize()
+        bits, kept, flags = (int(v) for v in info.cpu())
+        pad = (kept + 63) // 64 * 64
+        out = torch.empty((NCH, max(pad, 64)), dtype=torch.float32, device=dev)
+        pw = (bits + 31) // 32 + 1
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        for _ in range(3):
+            ctx.fl_encode(params, q, rd.hard, hdr, payload, words, info)
+            ctx.fl_decode(hdr, payload, pw, kept, max(pad, 64), out)
+        ev[0].record(stream)
+        for _ in range(args.steps):
+            ctx.fl_encode(params, q, rd.hard, hdr, payload, words, info)
+        ev[1].record(stream)
+        for _ in range(args.steps):
+            ctx.fl_decode(hdr, payload, pw, kept, max(pad, 64), out)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        ems = ev[0].elapsed_time(ev[1]) / args.steps
+        dms = ev[1].elapsed_time(ev[2]) / args.steps
+        enc_bytes = sc.n * NCH * 4 + sc.n + bits / 8          # params + mask in, payload out
+        dec_bytes = bits / 8 + kept * NCH * 4                   # payload in, parameters out
+        line["codec"] = {
+            "kept": kept, "payload_bits": bits, "header_bits": NCH * 72, "flags": flags,
+            "bits_per_kept_gaussian": round(bits / max(kept, 1), 2),
+            "encode_ms": round(ems, 4), "decode_ms": round(dms, 4),
+            "encode_gbs": round(enc_bytes / (ems * 1e-3) / 1e9, 1),
+            "decode_gbs": round(dec_bytes / (dms * 1e-3) / 1e9, 1),
+            "encode_hbm_frac": round(enc_bytes / (ems * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "decode_hbm_frac": round(dec_bytes / (dms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del payload, out
 
     if not args.no_cpu_baseline and args.workload == "c2":
         line["cpu_baseline"] = cpu_baseline(sc, lam)

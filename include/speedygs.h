@@ -264,12 +264,14 @@ typedef struct {
 } sgs_fl_channel;
 
 /* Encode params (SoA [59][npad], 16-byte aligned), qstep [59] and hard_mask
- * [n] of the context's scene.  header: device sgs_fl_channel[59]; payload:
- * device uint32 words, payload_words of them (words past the payload's end
- * are left untouched); info: device int64[3] receiving {payload bits, kept
- * Gaussians, flags}, flags bit 0 = a code outside int32 (that value is
- * stored as 0), bit 1 = payload_words too small (the stream is cut there).
- * Sync-free; read info afterwards. */
+ * [n] (16-byte aligned; nonzero = kept) of the context's scene.  header:
+ * device sgs_fl_channel[59]; payload: device uint32 words, payload_words of
+ * them (words past the payload's end are left untouched); info: device
+ * int64[3] receiving {payload bits, kept Gaussians, flags}, flags bit 0 = a
+ * kept value whose code is not finite or lies outside int32 (the stream is
+ * then not decodable: header and payload unspecified), bit 1 =
+ * payload_words too small (the stream is cut there).  Sync-free; read info
+ * afterwards. */
 sgs_status sgs_fl_encode(sgs_ctx *ctx, const float *params, const float *qstep,
                          const uint8_t *hard_mask, sgs_fl_channel *header, uint32_t *payload,
                          int64_t payload_words, int64_t *info);

@@ -355,8 +355,9 @@ sgs_status sgs_fl_encode(sgs_ctx *c, const float *params, const float *qstep,
   if (!params || !qstep || !hard_mask || !header || !info || (payload_words > 0 && !payload))
     return fail(c, SGS_EINVAL, "fl_encode: null pointer");
   if (payload_words < 0) return fail(c, SGS_EINVAL, "fl_encode: payload_words < 0");
-  if (!aligned(params, 16) || !aligned(info, 8))
-    return fail(c, SGS_EINVAL, "fl_encode: params must be 16-byte and info 8-byte aligned");
+  if (!aligned(params, 16) || !aligned(hard_mask, 16) || !aligned(info, 8))
+    return fail(c, SGS_EINVAL,
+                "fl_encode: params and hard_mask must be 16-byte and info 8-byte aligned");
   SGS_HIP(launch_fl_encode(c, params, qstep, hard_mask, header, payload, payload_words, info),
           "fl_encode");
   return SGS_OK;

@@ -134,3 +134,51 @@ def test_full_size_1m(orc, gctx, dev):
     info = check_against_oracle(orc, gctx, dev, sc, sc.params, sc.qstep, sc.given_mask, "c2")
     _say(f"c2 codec: {info[0]} payload bits for {info[1]} kept Gaussians "
          f"({info[0] / max(info[1], 1):.1f} bits each)")
+
+
+def test_near_ties_and_awkward_steps(orc, gctx, dev):
+    """Codes decided near half-integers (exact ties and a few ulps either
+    side), near and past |y/q| = 2^19 and 2^23, with steps that are not powers
+    of two, a negative step, a step whose reciprocal is subnormal and a
+    subnormal step whose reciprocal overflows: every code equal to
+    rint(fl32(y / q)) as the oracle's quantizer takes it."""
+    sc = synth.make_tiny(8192 + 77, 64, 48, seed=11)
+    rng = np.random.default_rng(12)
+    n = sc.n
+    q = synth.learnable_qsteps(9).astype(np.float32).copy()
+    params = sc.params.copy()
+
+    def around(x):  # each value, and 1..3 ulps below and above it
+        x = np.asarray(x, np.float32)
+        outs = [x]
+        lo, hi = x.copy(), x.copy()
+        for _ in range(3):
+            lo = np.nextafter(lo, np.float32(-np.inf)).astype(np.float32)
+            hi = np.nextafter(hi, np.float32(np.inf)).astype(np.float32)
+            outs += [lo, hi]
+        return np.concatenate(outs)
+
+    def fill(j, vals):
+        vals = np.resize(vals.astype(np.float32), n)
+        params[j, :n] = vals[rng.permutation(n)]
+
+    awkward = [0.0137, 1.0 / 3.0, 0.1, 7.3e-3, 2.0 ** -6, 1e-3, 0.77, 3.1, -0.05]
+    for j, qq in enumerate(awkward):
+        q[j] = np.float32(qq)
+        m = rng.integers(-1000, 1000, 1200)
+        fill(j, around((m + 0.5).astype(np.float32) * q[j]))
+    for j, mag in ((10, 2 ** 19), (11, 2 ** 19 - 3), (12, 2 ** 20), (13, 2 ** 22), (14, 2 ** 23)):
+        q[j] = np.float32(0.37)
+        m = mag + rng.integers(-6, 6, 1200)
+        sgn = np.where(rng.random(1200) < 0.5, -1.0, 1.0)
+        fill(j, around((sgn * (m + 0.5)).astype(np.float32) * q[j]))
+    q[15] = np.float32(3e38)                                 # 1/q subnormal
+    fill(15, around(np.array([1.5e38, -1.5e38, 4.5e38 / 2, 3e38, 0.0, 1e30], np.float32)))
+    q[16] = np.float32(2.0 ** -140)                          # subnormal step, 1/q overflows
+    m = rng.integers(-5000, 5000, 1200)
+    fill(16, around((m + 0.5).astype(np.float32) * q[16]))
+    mask = sc.given_mask.copy()
+    with np.errstate(over="ignore", invalid="ignore"):
+        k = np.rint(params[:, :n] / q[:, None])
+    assert np.isfinite(k).all() and np.abs(k).max() < 2 ** 31
+    check_against_oracle(orc, gctx, dev, sc, params, q, mask, "near ties")
