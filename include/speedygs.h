@@ -247,6 +247,40 @@ sgs_status sgs_rate_mlp_train_step(sgs_ctx *ctx, float *theta, float *adam_m, fl
                                    int64_t rows, float lr, int64_t step, float *loss,
                                    float *grad_theta, void *scratch);
 
+/* One Adam step (Kingma & Ba 2015) on the formation variables: the
+ * parameters y [59][npad] (SoA, 16-byte aligned rows), the step sizes q [59]
+ * and the retention scores s [n] of the context's scene, from their
+ * gradients.  Per element, with t = opt->step >= 1:
+ *     m <- b1 m + (1 - b1) g,   v <- b2 v + (1 - b2) g^2,
+ *     x <- x - lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+ * in FP32 (the two bias corrections are formed in FP64 and rounded once;
+ * beta1, beta2 in [0.5, 1), so 1 - beta is exact in FP32; eps >= 0).
+ * The schedule the paper adopts for speed (Sec. 4.1: separated updates of the
+ * higher SH coefficients and an economical Adam) is read as two switches:
+ *  - sh_rest = 0 leaves the 45 higher-order SH rows (channels 6-50) and
+ *    their moments untouched this step (the caller updates them every k-th
+ *    step with that step's gradient);
+ *  - sparse = 1 leaves a Gaussian's parameters and moments untouched when
+ *    every gradient of the rows updated this step is exactly zero (it is in
+ *    no view and holds no range extreme); the steps and scores always update.
+ * m, v: device buffers shaped like their variable, zero before step 1.  The
+ * (q, q_m, q_v, grad_q) and (s, s_m, s_v, grad_s) groups may each be all
+ * NULL to skip that variable; grad buffers are read only. */
+typedef struct {
+  float lr[SGS_NCH];      /* learning rate per parameter channel */
+  float lr_q, lr_score;   /* learning rates of the steps and the scores */
+  float beta1, beta2, eps;
+  int32_t sh_rest;        /* 1: update channels 6-50 this step */
+  int32_t sparse;         /* 1: skip Gaussians whose updated rows have zero gradient */
+  int32_t reserved;       /* must be zero */
+  int64_t step;           /* t >= 1 */
+} sgs_adam_options;
+
+sgs_status sgs_adam_step(sgs_ctx *ctx, const sgs_adam_options *opt /* host */, float *params,
+                         float *params_m, float *params_v, const float *grad_params,
+                         float *qstep, float *q_m, float *q_v, const float *grad_qstep,
+                         float *score, float *s_m, float *s_v, const float *grad_score);
+
 /* Channel-wise fixed-length coding (Sec. 3.4.1: each channel stored with the
  * fixed bit width its quantization precision gives, plus per-channel
  * metadata) of the kept Gaussians' quantization codes k_ij = rint(y_ij/q_j)
@@ -303,7 +337,8 @@ enum {
   SGS_PROF_MLP_BWD = 15,   /* a13 learned rate, backward */
   SGS_PROF_MLP_TRAIN = 16, /* a13 training step */
   SGS_PROF_CODEC = 17,     /* fixed-length encode / decode */
-  SGS_PROF_GROUPS = 18
+  SGS_PROF_ADAM = 18,      /* optimizer step */
+  SGS_PROF_GROUPS = 19
 };
 /* enable != 0 starts recording (and clears earlier records); 0 stops. */
 sgs_status sgs_profile_enable(sgs_ctx *ctx, int32_t enable);

@@ -41,6 +41,13 @@ class sgs_options(C.Structure):
                 ("schedule", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
+class sgs_adam_options(C.Structure):
+    _fields_ = [("lr", C.c_float * 59), ("lr_q", C.c_float), ("lr_score", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("sh_rest", C.c_int32), ("sparse", C.c_int32), ("reserved", C.c_int32),
+                ("step", C.c_int64)]
+
+
 SCHEDULES = {"tile": 0, "stride": 1, "queue": 2}
 
 
@@ -78,12 +85,14 @@ _SIGS = {
     "sgs_rate_mlp_infer": [P, P, P, P, I64, P],
     "sgs_rate_mlp_train_scratch_bytes": [I64],
     "sgs_rate_mlp_train_step": [P, P, P, P, P, P, P, I64, F32, I64, P, P, P],
+    "sgs_adam_step": [P, P, P, P, P, P, P, P, P, P, P, P, P, P],
     "sgs_fl_encode": [P, P, P, P, P, P, I64, P],
     "sgs_fl_decode": [P, P, P, I64, I64, I64, P],
 }
 PROF_GROUPS = ("fakequant", "rate", "preprocess", "depth_sort", "scan", "duplicate",
                "tile_sort", "ranges", "blend_fwd", "l1", "grad_clear", "blend_bwd",
-               "preprocess_bwd", "fakequant_bwd", "mlp_fwd", "mlp_bwd", "mlp_train", "codec")
+               "preprocess_bwd", "fakequant_bwd", "mlp_fwd", "mlp_bwd", "mlp_train", "codec",
+               "adam")
 MLP_PARAMS = 24961
 MLP_PACKED_BYTES = 98304
 EXPORTS = tuple(_SIGS)
@@ -270,6 +279,24 @@ class Context:
             self.h, _ptr(packed), _ptr(theta), _ptr(params), _ptr(qstep), _ptr(stats),
             _ptr(hard_mask), _ptr(soft_mask), mask_mode, rate_weight, _ptr(grad_params),
             _ptr(grad_qstep), _ptr(grad_score), _ptr(grad_hard_mask)), self.h)
+
+    def adam_step(self, lr, step, params, params_m, params_v, grad_params, q=None, q_m=None,
+                  q_v=None, grad_q=None, score=None, s_m=None, s_v=None, grad_score=None,
+                  lr_q=0.0, lr_score=0.0, beta1=0.9, beta2=0.999, eps=1e-8, sh_rest=True,
+                  sparse=False):
+        """One Adam step; lr: 59 per-channel learning rates (or one float)."""
+        o = sgs_adam_options()
+        lrs = [float(lr)] * 59 if isinstance(lr, (int, float)) else [float(a) for a in lr]
+        if len(lrs) != 59:
+            raise ValueError("lr needs 59 entries")
+        o.lr = (C.c_float * 59)(*lrs)
+        o.lr_q, o.lr_score = lr_q, lr_score
+        o.beta1, o.beta2, o.eps = beta1, beta2, eps
+        o.sh_rest, o.sparse, o.reserved, o.step = int(bool(sh_rest)), int(bool(sparse)), 0, step
+        self._check(self.L.sgs_adam_step(
+            self.h, C.byref(o), _ptr(params), _ptr(params_m), _ptr(params_v), _ptr(grad_params),
+            _ptr(q), _ptr(q_m), _ptr(q_v), _ptr(grad_q), _ptr(score), _ptr(s_m), _ptr(s_v),
+            _ptr(grad_score)), self.h)
 
     def fl_encode(self, params, qstep, hard_mask, header, payload, payload_words, info):
         """Fixed-length encode (header int32 [59][3]: q bits, kmin, width;

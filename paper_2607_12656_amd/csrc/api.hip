@@ -2,6 +2,7 @@
 // scratch ownership and the order of the launches.  No exception crosses the
 // ABI; every failure is a status code plus a message in the context.
 #include <stdarg.h>
+#include <cmath>
 #include <stdio.h>
 #include <string.h>
 
@@ -344,6 +345,29 @@ sgs_status sgs_fakequant_prune_bwd(sgs_ctx *c, const float *params, const float 
   SGS_HIP(launch_fakequant_bwd(c, params, qstep, soft_mask, mask_mode, rate_grad, stats,
                                grad_qparams, grad_hard_mask, grad_params, grad_qstep, grad_score),
           "fakequant_prune_bwd");
+  return SGS_OK;
+}
+
+sgs_status sgs_adam_step(sgs_ctx *c, const sgs_adam_options *o, float *params, float *pm,
+                         float *pv, const float *gp, float *q, float *qm, float *qv,
+                         const float *gq, float *s, float *sm, float *sv, const float *gs) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "adam_step: set_scene first");
+  if (!o || !params || !pm || !pv || !gp)
+    return fail(c, SGS_EINVAL, "adam_step: null options or parameter buffers");
+  const bool qa = q || qm || qv || gq, qall = q && qm && qv && gq;
+  const bool sa = s || sm || sv || gs, sall = s && sm && sv && gs;
+  if ((qa && !qall) || (sa && !sall))
+    return fail(c, SGS_EINVAL, "adam_step: give all four buffers of a variable or none");
+  if (o->step < 1 || o->reserved != 0 || (o->sh_rest != 0 && o->sh_rest != 1) ||
+      (o->sparse != 0 && o->sparse != 1))
+    return fail(c, SGS_EINVAL, "adam_step: need step >= 1, sh_rest and sparse 0/1, reserved 0");
+  if (!(o->beta1 >= 0.5f && o->beta1 < 1.0f) || !(o->beta2 >= 0.5f && o->beta2 < 1.0f) ||
+      !(o->eps >= 0.0f) || !std::isfinite(o->eps))
+    return fail(c, SGS_EINVAL, "adam_step: need beta1, beta2 in [0.5, 1), eps >= 0 finite");
+  if (!aligned(params, 16) || !aligned(pm, 16) || !aligned(pv, 16) || !aligned(gp, 16))
+    return fail(c, SGS_EINVAL, "adam_step: parameter rows must be 16-byte aligned");
+  SGS_HIP(launch_adam(c, o, params, pm, pv, gp, q, qm, qv, gq, s, sm, sv, gs), "adam_step");
   return SGS_OK;
 }
 

@@ -165,6 +165,9 @@ hipError_t launch_depth_order(sgs_ctx *c); // depth sort + scan (writes d_pairs_
 #define SGS_TILE_BINS 68
 // codec.hip
 int64_t fl_scratch_words(int64_t n);
+hipError_t launch_adam(sgs_ctx *c, const sgs_adam_options *o, float *params, float *pm,
+                       float *pv, const float *gp, float *q, float *qm, float *qv,
+                       const float *gq, float *s, float *sm, float *sv, const float *gs);
 hipError_t launch_fl_encode(sgs_ctx *c, const float *params, const float *q, const uint8_t *hard,
                             sgs_fl_channel *hdr, uint32_t *payload, int64_t cap_words,
                             int64_t *out);

@@ -44,6 +44,9 @@ def test_struct_layouts():
     from paper_2607_12656_amd import _lib
     assert C.sizeof(_lib.sgs_camera) == 19 * 4
     assert C.sizeof(_lib.sgs_options) == 8 * 4
+    # 64 floats, 3 int32, padding to 8, int64
+    assert C.sizeof(_lib.sgs_adam_options) == 280
+    assert _lib.sgs_adam_options.step.offset == 272
     src = open(HEADER).read()
     assert "#define SGS_STATS_WORDS 128" in src and _lib.STATS_WORDS == 128
     assert "#define SGS_RATE_GRAD_FLOATS 256" in src and _lib.RATE_GRAD_FLOATS == 256
