@@ -242,6 +242,25 @@ __device__ __forceinline__ int64_t sgs_xcd_block(int64_t i, int64_t nb) {
   return x * per + (x < rem ? x : rem) + k;
 }
 
+// The same for a grid of nb blocks of which only the first nlive logical
+// blocks hold work (grids sized for a capacity): the live range is split
+// over the eight XCDs as above, so each does an equal share whatever the
+// grid size, and the other hardware blocks take the logical blocks nlive,
+// nlive + 1, ... in dispatch order (their rank among them: for each XCD, its
+// blocks dispatched earlier beyond its live share).  A bijection of [0, nb).
+__device__ __forceinline__ int64_t sgs_xcd_block_live(int64_t i, int64_t nb, int64_t nlive) {
+  nlive = nlive < nb ? nlive : nb;
+  const int64_t x = i & 7, k = i >> 3, per = nlive >> 3, rem = nlive & 7;
+  if (k < per + (x < rem ? 1 : 0)) return x * per + (x < rem ? x : rem) + k;
+  int64_t r = 0;
+#pragma unroll
+  for (int xp = 0; xp < 8; ++xp) {
+    const int64_t before = k + (xp < x ? 1 : 0), share = per + (xp < rem ? 1 : 0);
+    r += before > share ? before - share : 0;
+  }
+  return nlive + r;
+}
+
 // Order-preserving map of float bits to uint32 (for min/max keys).
 __device__ __forceinline__ uint32_t sgs_ord(float f) {
   const uint32_t u = __float_as_uint(f);

@@ -127,7 +127,7 @@ k_radix_hist(const uint32_t *__restrict__ keys, int64_t count_static,
              const uint32_t *__restrict__ dcount, int shift, uint32_t *__restrict__ hist) {
   __shared__ uint32_t s_sub[kThreads / 8][257];
   const int64_t count = dcount ? (int64_t)*dcount : count_static;
-  const int64_t blk = sgs_xcd_block(blockIdx.x, gridDim.x);
+  const int64_t blk = sgs_xcd_block_live(blockIdx.x, gridDim.x, (count + kTile - 1) / kTile);
   const int64_t base = blk * kTile;
   if (base >= count) {  // grid sized for a capacity, not the live count
     hist[blk * 256 + threadIdx.x] = 0;
@@ -290,7 +290,7 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
   __shared__ uint32_t s_key[kTile];
   __shared__ uint32_t s_val[kTile];
   const int64_t count = dcount ? (int64_t)*dcount : count_static;
-  const int64_t blk = sgs_xcd_block(blockIdx.x, gridDim.x);
+  const int64_t blk = sgs_xcd_block_live(blockIdx.x, gridDim.x, (count + kTile - 1) / kTile);
   const int64_t base = blk * kTile;
   if (base >= count) return;
   // all loads of the block in flight at once
@@ -427,7 +427,7 @@ k_gen_hist(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ brec,
   __shared__ __align__(16) uint32_t s_sub[kThreads / 8][257];
   static_assert((kThreads / 8) * 257 >= kWinWords, "window does not fit");
   const int64_t count = dcount ? (int64_t)*dcount : count_static;
-  const int64_t blk = sgs_xcd_block(blockIdx.x, gridDim.x);
+  const int64_t blk = sgs_xcd_block_live(blockIdx.x, gridDim.x, (count + kTile - 1) / kTile);
   const int64_t base = blk * kTile;
   if (base >= count) {
     hist[blk * 256 + threadIdx.x] = 0;
@@ -464,7 +464,7 @@ k_gen_scatter(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ br
   __shared__ uint32_t s_val[kTilePad];
   static_assert(kTilePad >= kWinWords, "window does not fit");
   const int64_t count = dcount ? (int64_t)*dcount : count_static;
-  const int64_t blk = sgs_xcd_block(blockIdx.x, gridDim.x);
+  const int64_t blk = sgs_xcd_block_live(blockIdx.x, gridDim.x, (count + kTile - 1) / kTile);
   const int64_t base = blk * kTile;
   if (base >= count) return;
   const uint32_t h_raw = hist_raw[blk * 256 + threadIdx.x];
