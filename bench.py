@@ -105,12 +105,106 @@ def cpu_baseline(sc, lam):
             "s_per_step": round(dt, 3)}
 
 
+def bench_formation(args, sc, ctx, rd, stream, dev, t, tile, schedule, tune):
+    """Full formation iterations at 3M Gaussians x 8 views: RD step on the
+    Gumbel-sigmoid mask, learned rate in the loop (forward + recompute
+    backward), Adam on (y, q, s); the same iterations with the plain proxy.
+    Both start from the same scene; every iteration counts its evaluations.
+    Ends with the rate-estimate error of each rate term against the exact
+    bits of the fixed-length coder on the final state."""
+    import numpy as np
+    import torch
+
+    from paper_2607_12656_amd.formation import Formation
+
+    lam = 2.5e-5
+    K, W = args.steps, args.warmup
+    p0, q0, s0, target = t(sc.params), t(sc.qstep), t(sc.score), t(sc.target)
+    theta = torch.empty(24961, dtype=torch.float32, device=dev)
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    theta.copy_((torch.rand(24961, generator=gen) * 2 - 1) * 0.2)
+    packed = torch.empty(98304 // 4, dtype=torch.int32, device=dev)
+    ctx.rate_mlp_pack(theta, packed)
+    rd.forward(p0, q0, s0, target, lam, 1, None, 5, 0, count_evals=False)
+    P, _ = ctx.query()
+    ctx.reserve_pairs(P + P // 2 + 4096)       # the scene moves; the count is checked after
+    runs = {}
+    for name, mlp in (("learned", (packed, theta)), ("plain", None)):
+        p, q, s = p0.clone(), q0.clone(), s0.clone()
+        f = Formation(rd, p, q, s, target, lam, mask_mode=1, seed=5, mlp=mlp)
+        for _ in range(W):
+            f.iterate()
+        torch.cuda.synchronize()
+        rd.evals.zero_()
+        ctx.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(K):
+            f.iterate(count_evals=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = ctx.profile_read()
+        ctx.profile_enable(False)
+        pairs, _ = ctx.query()                 # raises if the reserved capacity overflowed
+        E = int(rd.evals.item())
+        # the final state: plain proxy, learned estimate and the coder's exact bits
+        c = ctx
+        c.fakequant_prune(p, q, s, 1, None, 5, f.k, rd.qparams, rd.hard, rd.soft, rd.stats)
+        c.rate_proxy(rd.stats, q, 0.0, rd.rate3, None)
+        c.rate_mlp_fwd(packed, theta, p, q, rd.stats, rd.hard, f.R_learned, None)
+        words = sc.n * NCH + 64
+        hdr = torch.empty((NCH, 3), dtype=torch.int32, device=dev)
+        payload = torch.empty(words, dtype=torch.int32, device=dev)
+        info = torch.empty(3, dtype=torch.int64, device=dev)
+        c.fl_encode(p, q, rd.hard, hdr, payload, words, info)
+        torch.cuda.synchronize()
+        bits = int(info[0].item()) + NCH * 72
+        r_plain = float(rd.rate3[0].item()) * sc.n_hat
+        r_learn = float(f.R_learned[0].item()) * sc.n_hat
+        kernels = {g: round(tot / cnt, 4) for g, (tot, cnt) in prof.items() if cnt}
+        runs[name] = {"ms_per_step": round(dt * 1e3 / K, 4), "value": round(E / dt, 1),
+                      "evals": E, "pairs_last": pairs, "kept_last": int(info[1].item()),
+                      "coder_bits_last": bits,
+                      "plain_proxy_error": round(abs(r_plain - bits) / bits, 4),
+                      "learned_error": round(abs(r_learn - bits) / bits, 4),
+                      "kernel_ms": kernels}
+        del payload
+    L = runs["learned"]
+    dom = max(L["kernel_ms"], key=L["kernel_ms"].get)
+    roof = roofline(dom, L["kernel_ms"][dom], sc.n, sc.views, L["pairs_last"],
+                    L["evals"] // K, sc.width, sc.height)
+    line = {
+        "metric": "RD-step ms/iter & Gaussian-pixel evals/s (fwd+bwd), learned vs plain rate",
+        "value": L["value"], "unit": "Gaussian-pixel evals/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": L["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"c5: full formation iteration, {sc.n} Gaussians (clustered), "
+                               f"{sc.views} views {sc.width}x{sc.height}, Gumbel-sigmoid mask, "
+                               f"learned rate in the loop (forward + recompute backward), "
+                               f"Adam on parameters / steps / scores (higher SH every 16th, "
+                               f"sparse), lambda {lam}, {K} iterations, tile "
+                               f"{tile[0]}x{tile[1]}",
+                   "gaussians": sc.n, "views": sc.views, "width": sc.width,
+                   "height": sc.height, "tile": f"{tile[0]}x{tile[1]}", "schedule": schedule,
+                   "mlp_weights": "seeded, untrained (timing does not depend on them)"},
+        "roofline": roof,
+        "learned": L, "plain": runs["plain"],
+        "learned_over_plain_time": round(L["ms_per_step"] / runs["plain"]["ms_per_step"], 4),
+    }
+    if tune is not None:
+        line["autotune_ms"] = tune["ms"]
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 20; 1000 iterations for c5)")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=("c2", "c3"))
+    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c5"),
+                    help="c2: 1M Gaussians, 1 view; c3: 3M Gaussians, 8 views; c5: the full "
+                         "formation iteration at 3M x 8 views (learned rate in the loop, "
+                         "Gumbel-sigmoid mask, Adam), learned vs plain rate")
     ap.add_argument("--tile", default=None, help="16x16 | 8x8 | 32x8 | auto")
     ap.add_argument("--schedule", default=None, choices=("tile", "stride", "queue"),
                     help="blend launch schedule when --tile names a shape (default: stride "
@@ -135,7 +229,9 @@ def main():
     from paper_2607_12656_amd import Context
     from paper_2607_12656_amd.rd import RDStep
 
-    sc = synth.make_scene(args.workload)
+    if args.steps is None:
+        args.steps = 1000 if args.workload == "c5" else 20
+    sc = synth.make_scene("c3" if args.workload == "c5" else args.workload)
     lam = 2.5e-5
     dev = torch.device("cuda", 0)
     stream = torch.cuda.Stream(dev)
@@ -169,6 +265,10 @@ def main():
         schedule = args.schedule or ("stride" if args.workload == "c2" else "tile")
     rd = RDStep(ctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height, tile=tile,
                 schedule=schedule)
+    if args.workload == "c5":
+        print(json.dumps(bench_formation(args, sc, ctx, rd, stream, dev, t, tile, schedule,
+                                         tune)), flush=True)
+        return
 
     # evaluation count and pair count of one step (deterministic)
     rd.evals.zero_()
