@@ -231,6 +231,15 @@ sgs_status sgs_rate_mlp_bwd(sgs_ctx *ctx, const void *packed, const float *theta
                             const uint8_t *hard_mask, const float *soft_mask,
                             int32_t mask_mode, float rate_weight, float *grad_params,
                             float *grad_qstep, float *grad_score, float *grad_hard_mask);
+/* Feature rows of the estimator for chosen Gaussians of the scene (to build
+ * training sets): X[r] = the BF16 features the in-loop forward gives Gaussian
+ * idx[r] (x_j = log2(1 + (y_j - min_j) / q_j), min_j from `stats` of the
+ * last sgs_fakequant_prune on these params and steps; channels 59-63 zero).
+ * idx: device int32 [rows] (an index outside [0, n) gives a zero row);
+ * X: device BF16 [rows][64], 8-byte aligned. */
+sgs_status sgs_rate_mlp_features(sgs_ctx *ctx, const float *params, const float *qstep,
+                                 const uint64_t *stats, const int32_t *idx, int64_t rows,
+                                 uint16_t *X);
 /* f over given feature rows: X BF16 [rows][64] (8-byte aligned), out float [rows]. */
 sgs_status sgs_rate_mlp_infer(sgs_ctx *ctx, const void *packed, const float *theta,
                               const uint16_t *X, int64_t rows, float *out);

@@ -86,6 +86,7 @@ _SIGS = {
     "sgs_rate_mlp_train_scratch_bytes": [I64],
     "sgs_rate_mlp_train_step": [P, P, P, P, P, P, P, I64, F32, I64, P, P, P],
     "sgs_adam_step": [P, P, P, P, P, P, P, P, P, P, P, P, P, P],
+    "sgs_rate_mlp_features": [P, P, P, P, P, I64, P],
     "sgs_fl_encode": [P, P, P, P, P, P, I64, P],
     "sgs_fl_decode": [P, P, P, I64, I64, I64, P],
 }
@@ -308,6 +309,10 @@ class Context:
     def fl_decode(self, header, payload, payload_words, kept, out_pad, out):
         self._check(self.L.sgs_fl_decode(self.h, _ptr(header), _ptr(payload), payload_words,
                                          kept, out_pad, _ptr(out)), self.h)
+
+    def rate_mlp_features(self, params, qstep, stats, idx, rows, X):
+        self._check(self.L.sgs_rate_mlp_features(self.h, _ptr(params), _ptr(qstep), _ptr(stats),
+                                                 _ptr(idx), rows, _ptr(X)), self.h)
 
     def rate_mlp_infer(self, packed, theta, X, rows, out):
         self._check(self.L.sgs_rate_mlp_infer(self.h, _ptr(packed), _ptr(theta), _ptr(X), rows,

@@ -546,6 +546,19 @@ sgs_status sgs_rate_mlp_bwd(sgs_ctx *c, const void *packed, const float *theta,
   return SGS_OK;
 }
 
+sgs_status sgs_rate_mlp_features(sgs_ctx *c, const float *params, const float *qstep,
+                                 const uint64_t *stats, const int32_t *idx, int64_t rows,
+                                 uint16_t *X) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "rate_mlp_features: set_scene first");
+  if (!params || !qstep || !stats || !idx || !X || rows < 0)
+    return fail(c, SGS_EINVAL, "rate_mlp_features: null pointer or rows < 0");
+  if (rows > ((int64_t)1 << 40)) return fail(c, SGS_ECAPACITY, "rate_mlp_features: rows");
+  if (!aligned(X, 8)) return fail(c, SGS_EINVAL, "rate_mlp_features: X must be 8-byte aligned");
+  SGS_HIP(launch_mlp_features(c, params, qstep, stats, idx, rows, X), "rate_mlp_features");
+  return SGS_OK;
+}
+
 sgs_status sgs_rate_mlp_infer(sgs_ctx *c, const void *packed, const float *theta,
                               const uint16_t *X, int64_t rows, float *out) {
   if (!c) return SGS_EINVAL;

@@ -739,7 +739,41 @@ __global__ void k_adam(int count, float *__restrict__ w, float *__restrict__ m,
   w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
 }
 
+// Feature rows of chosen Gaussians: X[r][j] = the in-loop forward's feature
+// of Gaussian idx[r], channel j (0 for j >= 59, and a zero row for an index
+// outside [0, n)): one thread per entry.
+__global__ void __launch_bounds__(256)
+k_mlp_features(int64_t rows, int64_t n, int64_t npad, const float *__restrict__ y,
+               const float *__restrict__ q, const uint64_t *__restrict__ stats,
+               const int32_t *__restrict__ idx, uint16_t *__restrict__ X) {
+  __shared__ float s_min[SGS_NCH], s_rq[SGS_NCH];
+  load_mins(s_min, stats);
+  load_steps(s_rq, q);
+  __syncthreads();
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * 64) return;
+  const int64_t r = e >> 6;
+  const int j = (int)(e & 63);
+  const int64_t i = idx[r];
+  float v = 0.0f;
+  if (j < SGS_NCH && i >= 0 && i < n) {
+    const float uu = (y[j * npad + i] - s_min[j]) * s_rq[j];
+    v = __log2f(1.0f + uu);
+  }
+  X[e] = f2bf(v);
+}
+
 }  // namespace
+
+hipError_t launch_mlp_features(sgs_ctx *c, const float *params, const float *q,
+                               const uint64_t *stats, const int32_t *idx, int64_t rows,
+                               uint16_t *X) {
+  SgsProfScope ps(c, SGS_PROF_MLP_FWD);
+  if (rows > 0)
+    k_mlp_features<<<sgs_blocks(rows * 64, 256), 256, 0, c->stream>>>(rows, c->n, c->npad,
+                                                                      params, q, stats, idx, X);
+  return hipGetLastError();
+}
 
 hipError_t launch_mlp_pack(sgs_ctx *c, const float *theta, void *packed) {
   k_mlp_pack<<<sgs_blocks(kPacked, 256), 256, 0, c->stream>>>(theta, (bf16x4 *)packed);

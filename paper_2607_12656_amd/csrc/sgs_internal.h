@@ -189,6 +189,9 @@ hipError_t launch_mlp_rate_bwd(sgs_ctx *c, const void *packed, const float *thet
                                const float *params, const float *q, const uint64_t *stats,
                                const uint8_t *hard, const float *soft, int mode, float weight,
                                float *gparams, float *gqstep, float *gscore, float *gmask);
+hipError_t launch_mlp_features(sgs_ctx *c, const float *params, const float *q,
+                               const uint64_t *stats, const int32_t *idx, int64_t rows,
+                               uint16_t *X);
 hipError_t launch_mlp_infer(sgs_ctx *c, const void *packed, const float *theta,
                             const uint16_t *X, int64_t B, float *fout);
 hipError_t launch_mlp_train_step(sgs_ctx *c, float *theta, float *m, float *v, void *packed,

@@ -231,3 +231,42 @@ def test_training_on_gpu_and_gain_over_plain_proxy(orc, mlp, gctx, dev):
         err_p.append(abs(est_p - bits) / bits)
     _say(f"held-out rate-estimate error: learned {np.mean(err_l):.4f}, plain {np.mean(err_p):.4f}")
     assert np.mean(err_l) < np.mean(err_p)
+
+
+def test_feature_rows_match_oracle(orc, mlp, gctx, dev):
+    """sgs_rate_mlp_features: the BF16 rows the in-loop forward uses, for chosen
+    Gaussians (out-of-range indices give zero rows).  FP32 evaluation vs the
+    FP64 features rounded once to BF16: equal, except where the FP64 value lies
+    within FP32 rounding of a BF16 rounding boundary (then one BF16 ulp)."""
+    from paper_2607_12656_amd.rd import RDStep
+    _say("[gpu] mlp features")
+    sc = synth.make_tiny(5000, 32, 32, seed=12)
+    q = synth.learnable_qsteps(13)
+    rd = RDStep(gctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height)
+    params, qd = T(sc.params, dev), T(q, dev)
+    gctx.fakequant_prune(params, qd, None, 0, T(sc.given_mask, dev), 0, 0, rd.qparams, rd.hard,
+                         rd.soft, rd.stats)
+    rng = np.random.default_rng(3)
+    idx = rng.integers(0, sc.n, 3001).astype(np.int32)
+    idx[[5, 77, 3000]] = [-1, sc.n, sc.n + 9]
+    X = torch.full((3001, 64), 0x7FFF, dtype=torch.int16, device=dev)
+    gctx.rate_mlp_features(params, qd, rd.stats, T(idx, dev), 3001, X)
+    torch.cuda.synchronize()
+    got = X.cpu().numpy().view(np.uint16)
+    mmin = mlp.channel_min(sc.params, sc.n)
+    ok = (idx >= 0) & (idx < sc.n)
+    assert np.all(got[~ok] == 0), "zero rows for out-of-range indices"
+    ref64 = mlp.features(sc.params, q, mmin, sc.n, mirror=False)[idx[ok]]
+    refb = mlp.features(sc.params, q, mmin, sc.n, mirror=True)[idx[ok]]
+    ref_bits = (refb.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    g = got[ok]
+    diff = g != ref_bits
+    assert diff.mean() < 1e-3, f"{diff.sum()} of {diff.size} features differ"
+    gv = (g.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    rv = refb.astype(np.float64)
+    ulp = np.abs(rv) * 2.0 ** -7
+    assert np.all(np.abs(gv - rv)[diff] <= ulp[diff] * 1.01), "more than one BF16 ulp"
+    mid = (gv + rv) / 2
+    assert np.all(np.abs(ref64[diff] - mid[diff]) <= 1e-5 * np.abs(ref64[diff]) + 1e-30), \
+        "a differing feature is not at a BF16 rounding boundary"
+    assert np.all(g[:, 59:] == 0)
