@@ -22,7 +22,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .optim import adam_params, adam_vector  # noqa: F401
+from .optim import adam_params, adam_vector, compact  # noqa: F401
 
 NCH = 59
 HERE = os.path.dirname(os.path.abspath(__file__))

@@ -60,3 +60,11 @@ def adam_params(x, m, v, g, lr, step, n, beta1=0.9, beta2=0.999, eps=1e-8, sh_re
                              beta1, beta2, eps, skip)
     x[r, :n], m[r, :n], v[r, :n] = xs, ms, vs
     return x, m, v
+
+
+def compact(arrays, mask, n):
+    """Pruning by the learned mask (the supplement's formation schedule prunes
+    with it every 1,000 iterations): the columns i < n with mask[i] != 0 of
+    each array ([rows][npad] or [npad]), in index order."""
+    keep = np.asarray(mask[:n]) != 0
+    return [np.asarray(a)[..., :n][..., keep] for a in arrays]

@@ -87,3 +87,22 @@ def test_sh_rest_and_sparse_switches():
     zero = dead & ~only_sh
     assert np.array_equal(x3[:, :n][:, zero], x[:, :n][:, zero])
     assert np.all(x3[6:51, :n][:, only_sh] != x[6:51, :n][:, only_sh])
+
+
+def test_compact_against_a_plain_loop():
+    """The oracle's compaction equals appending the kept columns one by one."""
+    rng = np.random.default_rng(4)
+    n, npad = 150, 192
+    a = rng.normal(0, 1, (59, npad))
+    b = rng.normal(0, 1, npad)
+    mask = (rng.random(npad) < 0.6).astype(np.uint8) * rng.integers(1, 255, npad).astype(np.uint8)
+    ca, cb = oracle.compact([a, b], mask, n)
+    cols_a, vals_b = [], []
+    for i in range(n):
+        if mask[i]:
+            cols_a.append(a[:, i])
+            vals_b.append(b[i])
+    assert np.array_equal(ca, np.stack(cols_a, axis=1)) and np.array_equal(cb, np.array(vals_b))
+    assert ca.shape == (59, int((mask[:n] != 0).sum()))
+    none = oracle.compact([a], np.zeros(npad, np.uint8), n)[0]
+    assert none.shape == (59, 0)
