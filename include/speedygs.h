@@ -256,6 +256,24 @@ sgs_status sgs_rate_mlp_train_step(sgs_ctx *ctx, float *theta, float *adam_m, fl
                                    int64_t rows, float lr, int64_t step, float *loss,
                                    float *grad_theta, void *scratch);
 
+/* Pruning by the learned mask (the paper's supplement applies the learned
+ * mask to prune every 1,000 iterations of the formation stage): copies the
+ * Gaussians with hard_mask != 0 (hard_mask: device uint8 [n], 16-byte
+ * aligned), in index order, of narrays (1..SGS_COMPACT_MAX_ARRAYS) SoA
+ * float32 arrays of the scene.  src[a], dst[a]: host arrays of device
+ * pointers; src[a] has rows[a] rows of stride npad (the scene's; 16-byte
+ * aligned) of which columns [0, n) are read (a one-row array needs n
+ * floats); dst[a] rows have stride dst_pad and receive columns [0, kept);
+ * rows[a] in 1..59 (59 for the parameters and their moments, 1 for scores).
+ * *kept (host) receives the count: the call synchronizes once to read it and
+ * returns SGS_ECAPACITY if dst_pad < *kept, or SGS_EINVAL if what would be
+ * written overlaps what is read, in both cases having written no dst.  The
+ * caller then calls sgs_set_scene with the new count. */
+#define SGS_COMPACT_MAX_ARRAYS 8
+sgs_status sgs_compact(sgs_ctx *ctx, const uint8_t *hard_mask, int32_t narrays,
+                       const float *const *src /* host */, float *const *dst /* host */,
+                       const int32_t *rows /* host */, int64_t dst_pad, int64_t *kept /* host */);
+
 /* One Adam step (Kingma & Ba 2015) on the formation variables: the
  * parameters y [59][npad] (SoA, 16-byte aligned rows), the step sizes q [59]
  * and the retention scores s [n] of the context's scene, from their

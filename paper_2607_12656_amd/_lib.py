@@ -87,6 +87,8 @@ _SIGS = {
     "sgs_rate_mlp_train_step": [P, P, P, P, P, P, P, I64, F32, I64, P, P, P],
     "sgs_adam_step": [P, P, P, P, P, P, P, P, P, P, P, P, P, P],
     "sgs_rate_mlp_features": [P, P, P, P, P, I64, P],
+    "sgs_compact": [P, P, I32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(I32),
+                    I64, C.POINTER(I64)],
     "sgs_fl_encode": [P, P, P, P, P, P, I64, P],
     "sgs_fl_decode": [P, P, P, I64, I64, I64, P],
 }
@@ -309,6 +311,18 @@ class Context:
     def fl_decode(self, header, payload, payload_words, kept, out_pad, out):
         self._check(self.L.sgs_fl_decode(self.h, _ptr(header), _ptr(payload), payload_words,
                                          kept, out_pad, _ptr(out)), self.h)
+
+    def compact(self, hard_mask, pairs, dst_pad: int) -> int:
+        """Keep the Gaussians with hard_mask != 0 in every (src, dst) pair of
+        device tensors ([rows][npad] -> [rows][dst_pad]); returns the kept count."""
+        k = len(pairs)
+        src = (C.c_void_p * k)(*[_ptr(s) for s, _ in pairs])
+        dst = (C.c_void_p * k)(*[_ptr(d) for _, d in pairs])
+        rows = (C.c_int32 * k)(*[1 if s.dim() == 1 else int(s.shape[0]) for s, _ in pairs])
+        kept = I64()
+        self._check(self.L.sgs_compact(self.h, _ptr(hard_mask), k, src, dst, rows, dst_pad,
+                                       C.byref(kept)), self.h)
+        return int(kept.value)
 
     def rate_mlp_features(self, params, qstep, stats, idx, rows, X):
         self._check(self.L.sgs_rate_mlp_features(self.h, _ptr(params), _ptr(qstep), _ptr(stats),

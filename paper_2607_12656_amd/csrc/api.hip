@@ -123,11 +123,12 @@ sgs_status sgs_create(sgs_ctx **out, int device, void *hip_stream) {
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
   if (hipSetDevice(device) != hipSuccess ||
-      hipHostMalloc((void **)&c->h_pairs_total, sizeof(uint32_t), hipHostMallocDefault) !=
+      hipHostMalloc((void **)&c->h_pairs_total, 2 * sizeof(uint32_t), hipHostMallocDefault) !=
           hipSuccess) {
     delete c;
     return SGS_EHIP;
   }
+  c->h_aux = c->h_pairs_total + 1;
   *out = c;
   return SGS_OK;
 }
@@ -345,6 +346,50 @@ sgs_status sgs_fakequant_prune_bwd(sgs_ctx *c, const float *params, const float 
   SGS_HIP(launch_fakequant_bwd(c, params, qstep, soft_mask, mask_mode, rate_grad, stats,
                                grad_qparams, grad_hard_mask, grad_params, grad_qstep, grad_score),
           "fakequant_prune_bwd");
+  return SGS_OK;
+}
+
+sgs_status sgs_compact(sgs_ctx *c, const uint8_t *hard, int32_t narrays, const float *const *src,
+                       float *const *dst, const int32_t *rows, int64_t dst_pad, int64_t *kept) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "compact: set_scene first");
+  if (!hard || !src || !dst || !rows || !kept) return fail(c, SGS_EINVAL, "compact: null pointer");
+  if (narrays < 1 || narrays > SGS_COMPACT_MAX_ARRAYS || dst_pad < 0)
+    return fail(c, SGS_EINVAL, "compact: need 1 <= narrays <= %d and dst_pad >= 0",
+                SGS_COMPACT_MAX_ARRAYS);
+  if (!aligned(hard, 16)) return fail(c, SGS_EINVAL, "compact: hard_mask must be 16-byte aligned");
+  SgsCompactArrays A;
+  A.narrays = narrays;
+  A.row0[0] = 0;
+  for (int a = 0; a < narrays; ++a) {
+    if (!src[a] || !dst[a] || rows[a] < 1 || rows[a] > SGS_NCH || !aligned(src[a], 16))
+      return fail(c, SGS_EINVAL, "compact: array %d: null or misaligned pointer, or rows "
+                                 "outside 1..59", a);
+    A.src[a] = src[a];
+    A.dst[a] = dst[a];
+    A.row0[a + 1] = A.row0[a] + rows[a];
+  }
+  const int64_t nc = (c->n + 4095) / 4096;
+  uint32_t *d_total = c->fl_tmp + 2 * nc;
+  SGS_HIP(launch_compact_count(c, hard, d_total), "compact count");
+  SGS_HIP(hipMemcpyAsync(c->h_aux, d_total, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream),
+          "compact count");
+  SGS_HIP(hipStreamSynchronize(c->stream), "compact count");
+  *kept = (int64_t)*c->h_aux;
+  if (*kept > dst_pad)
+    return fail(c, SGS_ECAPACITY, "compact: dst_pad %lld < kept %lld", (long long)dst_pad,
+                (long long)*kept);
+  for (int a = 0; a < narrays; ++a) {  // what is written must not overlap what is read
+    const char *d0 = (const char *)dst[a];
+    const char *d1 = d0 + ((size_t)(rows[a] - 1) * dst_pad + *kept) * 4;
+    for (int b = 0; b < narrays; ++b) {
+      const char *s0 = (const char *)src[b];
+      const char *s1 = s0 + ((size_t)(rows[b] - 1) * c->npad + c->n) * 4;
+      if (*kept > 0 && d0 < s1 && s0 < d1)
+        return fail(c, SGS_EINVAL, "compact: dst %d overlaps src %d", a, b);
+    }
+  }
+  if (*kept > 0) SGS_HIP(launch_compact_scatter(c, hard, A, dst_pad), "compact scatter");
   return SGS_OK;
 }
 

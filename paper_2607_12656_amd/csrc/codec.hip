@@ -62,14 +62,6 @@ __device__ __forceinline__ int32_t code_fast(float y, float q, float rq, bool fa
   return code_of(y, q, ok);
 }
 
-// bit i = (byte i of m) != 0: the high bit of each nonzero byte (the carry of
-// its low seven bits plus 0x7F, or its own high bit), gathered by one
-// multiply into bits 28..31 (the other partial products land below bit 24)
-__device__ __forceinline__ uint32_t nonzero_nibble(uint32_t m) {
-  const uint32_t nz = (((m & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | m) & 0x80808080u;
-  return ((nz >> 7) * 0x10204080u) >> 28;
-}
-
 // thread t of a chunk's block: Gaussians i0 .. i0 + 15; mask bytes and the
 // channel-j values (0 past n)
 __device__ __forceinline__ void load_items(int64_t n, const float *__restrict__ row,
@@ -78,8 +70,8 @@ __device__ __forceinline__ void load_items(int64_t n, const float *__restrict__ 
   keep = 0;
   if (i0 + kCItems <= n) {  // rows 64-byte aligned here (npad % 64 == 0, 16-byte aligned rows)
     const uint4 m = *reinterpret_cast<const uint4 *>(hard + i0);
-    keep = nonzero_nibble(m.x) | nonzero_nibble(m.y) << 4 | nonzero_nibble(m.z) << 8 |
-           nonzero_nibble(m.w) << 12;
+    keep = sgs_nonzero_nibble(m.x) | sgs_nonzero_nibble(m.y) << 4 | sgs_nonzero_nibble(m.z) << 8 |
+           sgs_nonzero_nibble(m.w) << 12;
 #pragma unroll
     for (int e = 0; e < kCItems; e += 4) {
       const float4 v4 = *reinterpret_cast<const float4 *>(row + i0 + e);

@@ -81,6 +81,7 @@ struct sgs_ctx {
   bool mlp_saved = false;         // a learned-rate forward ran since set_scene
   uint32_t *d_pairs_total = nullptr;  // [0] pair count, [1] count clamped to capacity, [2] overflow
   uint32_t *h_pairs_total = nullptr;  // pinned host mirror
+  uint32_t *h_aux = nullptr;          // pinned host word (kept count of a compaction)
   bool fixed_cap = false;             // pair capacity fixed by the caller: no host sync per step
   int64_t cap_limit = 0;              // the reserved capacity (buffers may be larger)
   bool capturing = false;             // the stream is being captured into a HIP graph
@@ -168,6 +169,15 @@ int64_t fl_scratch_words(int64_t n);
 hipError_t launch_adam(sgs_ctx *c, const sgs_adam_options *o, float *params, float *pm,
                        float *pv, const float *gp, float *q, float *qm, float *qv,
                        const float *gq, float *s, float *sm, float *sv, const float *gs);
+struct SgsCompactArrays {
+  const float *src[SGS_COMPACT_MAX_ARRAYS];
+  float *dst[SGS_COMPACT_MAX_ARRAYS];
+  int32_t row0[SGS_COMPACT_MAX_ARRAYS + 1];  // first row of each array in the launch
+  int32_t narrays;
+};
+hipError_t launch_compact_count(sgs_ctx *c, const uint8_t *hard, uint32_t *d_total);
+hipError_t launch_compact_scatter(sgs_ctx *c, const uint8_t *hard, const SgsCompactArrays &A,
+                                  int64_t dst_pad);
 hipError_t launch_fl_encode(sgs_ctx *c, const float *params, const float *q, const uint8_t *hard,
                             sgs_fl_channel *hdr, uint32_t *payload, int64_t cap_words,
                             int64_t *out);
@@ -262,6 +272,14 @@ __device__ __forceinline__ int64_t sgs_xcd_block_live(int64_t i, int64_t nb, int
     r += before > share ? before - share : 0;
   }
   return nlive + r;
+}
+
+// Bit i = (byte i of m) != 0: the high bit of each nonzero byte (the carry of
+// its low seven bits plus 0x7F, or its own high bit), gathered by one
+// multiply into bits 28..31 (the other partial products land below bit 24).
+__device__ __forceinline__ uint32_t sgs_nonzero_nibble(uint32_t m) {
+  const uint32_t nz = (((m & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | m) & 0x80808080u;
+  return ((nz >> 7) * 0x10204080u) >> 28;
 }
 
 // Order-preserving map of float bits to uint32 (for min/max keys).
