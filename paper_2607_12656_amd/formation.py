@@ -6,7 +6,10 @@ schedule with separated updates of the higher SH coefficients; read here as
 ``sh_every`` and ``sparse``).
 
 Only library calls are issued; nothing here computes, and an iteration never
-synchronizes with the host.  The learning rates are vanilla 3DGS's defaults
+synchronizes with the host.  ``prune`` applies the learned mask (the
+supplement prunes with it every 1,000 iterations of the formation stage):
+the Gaussians whose current hard mask is 0 leave the scene, with their
+moments, and the step is rebuilt for the survivors (one synchronization).  The learning rates are vanilla 3DGS's defaults
 (Kerbl et al. 2023; the paper builds on vanilla 3DGS, Sec. 4.1): mean 1.6e-4,
 DC colour 2.5e-3, higher SH 2.5e-3 / 20, opacity 2.5e-2, log-scale 5e-3,
 rotation 1e-3; the step sizes and scores take rates the paper does not
@@ -76,3 +79,27 @@ class Formation:
                     lr_score=self.lr_score, sh_rest=(k % self.sh_every == 0),
                     sparse=self.sparse)
         self.k += 1
+
+    def prune(self, pair_capacity: int = 0) -> int:
+        """Keep the Gaussians the mask keeps now (the hard mask of a fresh
+        decision at the current step); returns the new count.  N_hat (the
+        count before formation) is unchanged.  pair_capacity > 0 reserves that
+        pair capacity for the rebuilt scene."""
+        torch = self.rd.torch
+        c, rd = self.ctx, self.rd
+        p, q, s = self.params, self.q, self.score
+        c.fakequant_prune(p, q, s, self.mask_mode, self.given, self.seed, self.k, rd.qparams,
+                          rd.hard, rd.soft, rd.stats)
+        npad = rd.npad
+        new = [torch.empty_like(a) for a in (p, self.pm, self.pv, s, self.sm, self.sv)]
+        old = (p, self.pm, self.pv, s, self.sm, self.sv)
+        kept = c.compact(rd.hard, list(zip(old, new)), npad)
+        (self.params, self.pm, self.pv, self.score, self.sm, self.sv) = new
+        if self.given is not None:   # every survivor was kept by the given mask
+            self.given = torch.ones(npad, dtype=torch.uint8, device=rd.dev)
+        self.rd = RDStep(c, kept, npad, rd.n_hat, rd.cams, rd.W, rd.H, tile=rd.tile,
+                         tau=rd.tau, schedule=rd.schedule)
+        if pair_capacity > 0:
+            c.reserve_pairs(pair_capacity)
+        return kept
+

@@ -28,6 +28,7 @@ class RDStep:
         self.dev = dev
         V = cams.shape[0]
         self.n, self.npad, self.n_hat, self.V, self.W, self.H = n, npad, n_hat, V, width, height
+        self.cams, self.tile, self.tau, self.schedule = cams, tile, tau, schedule
         ctx.set_scene(n, npad, n_hat, cams, width, height, tile=tile, tau=tau,
                       schedule=schedule)
         f32, u8, i32, i64 = torch.float32, torch.uint8, torch.int32, torch.int64
