@@ -5,7 +5,8 @@ TEST INFRASTRUCTURE ONLY: this package is imported by ``tests/``, by
 nothing else.  It never imports the HIP package, and the HIP package never
 imports it.  The arithmetic lives in ``oracle.c`` (plain C, FP64, built with
 gcc, no contraction); this module only marshals numpy arrays.  The optimizer
-step is plain FP64 numpy in ``optim.py``.
+step and pruning are plain FP64 numpy in ``optim.py``, the SSIM term in
+``ssim.py``.
 
 Each function names the paper passage it follows; see ``oracle.c`` for the
 formulas.  Parity-unpinned constants (near plane 0.2, low-pass dilation 0.3,
@@ -23,6 +24,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .optim import adam_params, adam_vector, compact  # noqa: F401
+from . import ssim  # noqa: F401
 
 NCH = 59
 HERE = os.path.dirname(os.path.abspath(__file__))
