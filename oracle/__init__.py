@@ -6,7 +6,7 @@ nothing else.  It never imports the HIP package, and the HIP package never
 imports it.  The arithmetic lives in ``oracle.c`` (plain C, FP64, built with
 gcc, no contraction); this module only marshals numpy arrays.  The optimizer
 step and pruning are plain FP64 numpy in ``optim.py``, the SSIM term in
-``ssim.py``.
+``ssim.py``, the rate-proxy variants in ``rate_variants.py``.
 
 Each function names the paper passage it follows; see ``oracle.c`` for the
 formulas.  Parity-unpinned constants (near plane 0.2, low-pass dilation 0.3,
@@ -24,7 +24,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .optim import adam_params, adam_vector, compact  # noqa: F401
-from . import ssim  # noqa: F401
+from . import rate_variants, ssim  # noqa: F401
 
 NCH = 59
 HERE = os.path.dirname(os.path.abspath(__file__))
