@@ -256,6 +256,49 @@ sgs_status sgs_rate_mlp_train_step(sgs_ctx *ctx, float *theta, float *adam_m, fl
                                    int64_t rows, float lr, int64_t step, float *loss,
                                    float *grad_theta, void *scratch);
 
+/* Rate-proxy variants the paper compares with sgs_rate_proxy's range-based
+ * multiplicative proxy (Sec. 3.3.1 and the supplement's "Comparison with an
+ * Alternative Rate Proxy"; the ablation's additive masking).
+ *  proxy 1, scale-based Laplace: per channel b_j = mean |y_ij - mean_j| over
+ *    the N Gaussians (the maximum-likelihood Laplace scale) and
+ *    L_j = log2(max(1, 2 e b_j / q_j)) (code length of a Laplace source
+ *    quantized with step q_j); needs params, two passes over them.
+ *  masking 1, additive: the loss carries lambda L_quant + alpha L_mask
+ *    instead of lambda L_mask L_quant. */
+typedef struct {
+  int32_t proxy;     /* 0 range-based (Sec. 3.3.1), 1 scale-based Laplace */
+  int32_t masking;   /* 0 multiplicative (Sec. 3.3.1), 1 additive */
+  float alpha;       /* weight of the additive mask term */
+  int32_t reserved;  /* must be zero */
+} sgs_rate_options;
+
+/* out3 (device float[3]) = {the rate's term in the loss (lambda = rate_weight
+ * folded in), L_quant, L_mask}; rate_grad (device, SGS_RATE_GRAD_FLOATS, may
+ * be NULL) receives the compact gradient sgs_fakequant_prune_bwd consumes
+ * (the Laplace proxy has no argmin / argmax terms: its y gradient is dense and
+ * added by sgs_rate_variant_bwd).  stats: from sgs_fakequant_prune on the
+ * same params and steps. */
+sgs_status sgs_rate_variant(sgs_ctx *ctx, const float *params, const float *qstep,
+                            const uint64_t *stats, const sgs_rate_options *opt /* host */,
+                            float rate_weight, float *out3, float *rate_grad);
+/* After sgs_fakequant_prune_bwd: adds the dense y gradient of the last
+ * sgs_rate_variant (Laplace proxy) to grad_params [59][npad]; does nothing
+ * after the range proxy. */
+sgs_status sgs_rate_variant_bwd(sgs_ctx *ctx, const float *params, float *grad_params);
+
+/* SSIM term of the rendering distortion (the supplement's D_render follows
+ * vanilla 3DGS: D = (1 - w) L1 + w (1 - SSIM), w = 0.2 there; call
+ * sgs_l1_loss with scale 1 - w, then this with weight w).  SSIM (Wang et al.
+ * 2004) per view and colour plane with the 11 x 11 Gaussian window of
+ * standard deviation 1.5, zero outside the image, C1 = 0.01^2, C2 = 0.03^2,
+ * averaged over the V * 3 * H * W pixels.  loss[0] (device float) receives
+ * weight * (1 - SSIM); dL_dimage (device [V][3][H][W], may be NULL) has
+ * weight * d(1 - SSIM)/d image ADDED.  weight in [0, 1].  The first call on a
+ * scene allocates the context's SSIM scratch (24 bytes per pixel), so it
+ * must not be the first inside graph capture. */
+sgs_status sgs_ssim_loss(sgs_ctx *ctx, const float *image, const float *target, float weight,
+                         float *loss, float *dL_dimage);
+
 /* Pruning by the learned mask (the paper's supplement applies the learned
  * mask to prune every 1,000 iterations of the formation stage): copies the
  * Gaussians with hard_mask != 0 (hard_mask: device uint8 [n], 16-byte
@@ -365,7 +408,8 @@ enum {
   SGS_PROF_MLP_TRAIN = 16, /* a13 training step */
   SGS_PROF_CODEC = 17,     /* fixed-length encode / decode */
   SGS_PROF_ADAM = 18,      /* optimizer step */
-  SGS_PROF_GROUPS = 19
+  SGS_PROF_SSIM = 19,      /* SSIM term of the distortion */
+  SGS_PROF_GROUPS = 20
 };
 /* enable != 0 starts recording (and clears earlier records); 0 stops. */
 sgs_status sgs_profile_enable(sgs_ctx *ctx, int32_t enable);

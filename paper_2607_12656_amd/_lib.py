@@ -41,6 +41,11 @@ class sgs_options(C.Structure):
                 ("schedule", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
+class sgs_rate_options(C.Structure):
+    _fields_ = [("proxy", C.c_int32), ("masking", C.c_int32), ("alpha", C.c_float),
+                ("reserved", C.c_int32)]
+
+
 class sgs_adam_options(C.Structure):
     _fields_ = [("lr", C.c_float * 59), ("lr_q", C.c_float), ("lr_score", C.c_float),
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
@@ -87,6 +92,9 @@ _SIGS = {
     "sgs_rate_mlp_train_step": [P, P, P, P, P, P, P, I64, F32, I64, P, P, P],
     "sgs_adam_step": [P, P, P, P, P, P, P, P, P, P, P, P, P, P],
     "sgs_rate_mlp_features": [P, P, P, P, P, I64, P],
+    "sgs_ssim_loss": [P, P, P, F32, P, P],
+    "sgs_rate_variant": [P, P, P, P, P, F32, P, P],
+    "sgs_rate_variant_bwd": [P, P, P],
     "sgs_compact": [P, P, I32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(I32),
                     I64, C.POINTER(I64)],
     "sgs_fl_encode": [P, P, P, P, P, P, I64, P],
@@ -95,7 +103,7 @@ _SIGS = {
 PROF_GROUPS = ("fakequant", "rate", "preprocess", "depth_sort", "scan", "duplicate",
                "tile_sort", "ranges", "blend_fwd", "l1", "grad_clear", "blend_bwd",
                "preprocess_bwd", "fakequant_bwd", "mlp_fwd", "mlp_bwd", "mlp_train", "codec",
-               "adam")
+               "adam", "ssim")
 MLP_PARAMS = 24961
 MLP_PACKED_BYTES = 98304
 EXPORTS = tuple(_SIGS)
@@ -311,6 +319,23 @@ class Context:
     def fl_decode(self, header, payload, payload_words, kept, out_pad, out):
         self._check(self.L.sgs_fl_decode(self.h, _ptr(header), _ptr(payload), payload_words,
                                          kept, out_pad, _ptr(out)), self.h)
+
+    def rate_variant(self, params, qstep, stats, rate_weight, out3, rate_grad=None,
+                     proxy="range", masking="mult", alpha=0.0):
+        o = sgs_rate_options()
+        o.proxy = {"range": 0, "laplace": 1}[proxy]
+        o.masking = {"mult": 0, "add": 1}[masking]
+        o.alpha, o.reserved = alpha, 0
+        self._check(self.L.sgs_rate_variant(self.h, _ptr(params), _ptr(qstep), _ptr(stats),
+                                            C.byref(o), rate_weight, _ptr(out3),
+                                            _ptr(rate_grad)), self.h)
+
+    def rate_variant_bwd(self, params, grad_params):
+        self._check(self.L.sgs_rate_variant_bwd(self.h, _ptr(params), _ptr(grad_params)), self.h)
+
+    def ssim_loss(self, image, target, weight, loss, dL_dimage=None):
+        self._check(self.L.sgs_ssim_loss(self.h, _ptr(image), _ptr(target), weight, _ptr(loss),
+                                         _ptr(dL_dimage)), self.h)
 
     def compact(self, hard_mask, pairs, dst_pad: int) -> int:
         """Keep the Gaussians with hard_mask != 0 in every (src, dst) pair of

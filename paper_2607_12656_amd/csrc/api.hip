@@ -62,6 +62,10 @@ void free_scene(sgs_ctx *c) {
   dfree(c->mlp_f);
   dfree(c->fl_tmp);
   c->fl_tmp_words = 0;
+  dfree(c->ssim_tmp);
+  c->ssim_tmp_doubles = 0;
+  dfree(c->lap_coef);
+  c->lap_ready = false;
   dfree(c->mlp_signs);
   c->mlp_saved = false;
   dfree(c->blk_start);
@@ -231,10 +235,13 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   const int64_t red_q = quant_partial_words(n);
   const int64_t red_l1 = (int64_t)views * 3 * width * height / 2048 + 64;
   const int64_t red_mlp = (int64_t)mlp_grid(n) * 64;
+  const int64_t red_lap = lap_partial_doubles(n);
   int64_t red = red_q > red_l1 ? red_q : red_l1;
-  red = (red > red_mlp ? red : red_mlp) + 64;
+  red = red > red_mlp ? red : red_mlp;
+  red = (red > red_lap ? red : red_lap) + 64;
   SGS_ALLOC(c->red_tmp, red);
   c->red_tmp_words = red;
+  SGS_ALLOC(c->lap_coef, 192);
 #undef SGS_ALLOC
   const int64_t hist = radix_hist_words(vn);
   const int64_t scan = (vn + 4095) / 4096 + 1;
@@ -275,6 +282,7 @@ sgs_status sgs_rate_proxy(sgs_ctx *c, const uint64_t *stats, const float *qstep,
   if (!c->scene_set) return fail(c, SGS_ESTATE, "rate_proxy: set_scene first");
   if (!stats || !qstep || !out3) return fail(c, SGS_EINVAL, "rate_proxy: null pointer");
   SGS_HIP(launch_rate_proxy(c, stats, qstep, rate_weight, out3, rate_grad), "rate_proxy");
+  c->lap_ready = false;
   return SGS_OK;
 }
 
@@ -346,6 +354,53 @@ sgs_status sgs_fakequant_prune_bwd(sgs_ctx *c, const float *params, const float 
   SGS_HIP(launch_fakequant_bwd(c, params, qstep, soft_mask, mask_mode, rate_grad, stats,
                                grad_qparams, grad_hard_mask, grad_params, grad_qstep, grad_score),
           "fakequant_prune_bwd");
+  return SGS_OK;
+}
+
+sgs_status sgs_rate_variant(sgs_ctx *c, const float *params, const float *qstep,
+                            const uint64_t *stats, const sgs_rate_options *o, float rate_weight,
+                            float *out3, float *rate_grad) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "rate_variant: set_scene first");
+  if (!o || !qstep || !stats || !out3) return fail(c, SGS_EINVAL, "rate_variant: null pointer");
+  if ((o->proxy != 0 && o->proxy != 1) || (o->masking != 0 && o->masking != 1) ||
+      o->reserved != 0 || !std::isfinite(o->alpha) || !std::isfinite(rate_weight))
+    return fail(c, SGS_EINVAL, "rate_variant: proxy and masking 0/1, reserved 0, finite weights");
+  if (o->proxy == 1 && !params)
+    return fail(c, SGS_EINVAL, "rate_variant: the Laplace proxy reads params");
+  SGS_HIP(launch_rate_variant(c, params, qstep, stats, o, rate_weight, out3, rate_grad),
+          "rate_variant");
+  c->lap_ready = o->proxy == 1;
+  return SGS_OK;
+}
+
+sgs_status sgs_rate_variant_bwd(sgs_ctx *c, const float *params, float *grad_params) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "rate_variant_bwd: set_scene first");
+  if (!c->lap_ready) return SGS_OK;  // the range proxy's y gradient went through rate_grad
+  if (!params || !grad_params) return fail(c, SGS_EINVAL, "rate_variant_bwd: null pointer");
+  SGS_HIP(launch_rate_variant_bwd(c, params, grad_params), "rate_variant_bwd");
+  return SGS_OK;
+}
+
+sgs_status sgs_ssim_loss(sgs_ctx *c, const float *image, const float *target, float weight,
+                         float *loss, float *dL_dimage) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "ssim_loss: set_scene first");
+  if (!image || !target || !loss) return fail(c, SGS_EINVAL, "ssim_loss: null pointer");
+  if (!(weight >= 0.0f && weight <= 1.0f))
+    return fail(c, SGS_EINVAL, "ssim_loss: weight must lie in [0, 1]");
+  const int64_t need = ssim_scratch_doubles(c->V, c->W, c->H);
+  if (c->ssim_tmp_doubles < need) {
+    if (c->capturing)
+      return fail(c, SGS_ESTATE, "ssim_loss: first call (it allocates) during graph capture");
+    dfree(c->ssim_tmp);
+    c->ssim_tmp_doubles = 0;
+    hipError_t e = dalloc(&c->ssim_tmp, need);
+    if (e != hipSuccess) return hip_fail(c, e, "ssim_loss scratch");
+    c->ssim_tmp_doubles = need;
+  }
+  SGS_HIP(launch_ssim(c, image, target, weight, loss, dL_dimage), "ssim_loss");
   return SGS_OK;
 }
 

@@ -76,6 +76,10 @@ struct sgs_ctx {
   double *red_tmp = nullptr;      int64_t red_tmp_words = 0;
   uint32_t *fl_tmp = nullptr;     // fixed-length encoder scratch
   int64_t fl_tmp_words = 0;
+  double *lap_coef = nullptr;     // Laplace proxy: per-channel mean, mean sign, coefficient
+  bool lap_ready = false;         // lap_coef holds the last Laplace forward's values
+  double *ssim_tmp = nullptr;     // SSIM gradient maps + block sums (allocated on first use)
+  int64_t ssim_tmp_doubles = 0;
   float *mlp_f = nullptr;         // [n] f of the last learned-rate forward
   uint4 *mlp_signs = nullptr;     // [2n] its hidden activation signs (two lanes per row)
   bool mlp_saved = false;         // a learned-rate forward ran since set_scene
@@ -178,6 +182,17 @@ struct SgsCompactArrays {
 hipError_t launch_compact_count(sgs_ctx *c, const uint8_t *hard, uint32_t *d_total);
 hipError_t launch_compact_scatter(sgs_ctx *c, const uint8_t *hard, const SgsCompactArrays &A,
                                   int64_t dst_pad);
+hipError_t launch_rate_proxy_mode(sgs_ctx *c, const uint64_t *stats, const float *q,
+                                  float weight, int additive, float alpha, float *out3,
+                                  float *rate_grad);
+int64_t lap_partial_doubles(int64_t n);
+hipError_t launch_rate_variant(sgs_ctx *c, const float *params, const float *q,
+                               const uint64_t *stats, const sgs_rate_options *o, float weight,
+                               float *out3, float *rate_grad);
+hipError_t launch_rate_variant_bwd(sgs_ctx *c, const float *params, float *grad);
+int64_t ssim_scratch_doubles(int64_t V, int64_t W, int64_t H);
+hipError_t launch_ssim(sgs_ctx *c, const float *image, const float *target, float weight,
+                       float *loss, float *dimg);
 hipError_t launch_fl_encode(sgs_ctx *c, const float *params, const float *q, const uint8_t *hard,
                             sgs_fl_channel *hdr, uint32_t *payload, int64_t cap_words,
                             int64_t *out);

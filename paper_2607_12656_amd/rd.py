@@ -7,8 +7,10 @@ memory) and issues the C-ABI calls in order:
     -> render_bwd -> fakequant_prune_bwd
 
 Every arithmetic step runs in libspeedygs's HIP kernels; nothing here
-computes.  The loss is D_render + lam * R_proxy (paper Sec. 3.3.2, total loss,
-with the L1 part of D_render).
+computes.  The loss is D_render + lam * R_proxy (paper Sec. 3.3.2, total loss).
+D_render is the L1 distortion, or with ``ssim_weight`` = w > 0 vanilla
+3DGS's (1 - w) L1 + w (1 - SSIM), which the supplement's training objective
+follows (w = 0.2 there).
 """
 from __future__ import annotations
 
@@ -44,6 +46,7 @@ class RDStep:
         self.last = e(V, height, width, dt=i32)
         self.evals = torch.zeros(1, dtype=i64, device=dev)
         self.loss = e(1)
+        self.loss_ssim = torch.zeros(1, dtype=f32, device=dev)
         self.dimage = e(V, 3, height, width)
         self.grad_qparams = e(NCH, npad)
         self.grad_mask = e(n)
@@ -52,14 +55,16 @@ class RDStep:
 
     def forward(self, params, qstep, score, target, lam: float, mask_mode: int = 0,
                 given_mask=None, seed: int = 0, step: int = 0, count_evals: bool = True,
-                loss_scale: float = 1.0):
+                loss_scale: float = 1.0, ssim_weight: float = 0.0):
         c = self.ctx
         c.fakequant_prune(params, qstep, score, mask_mode, given_mask, seed, step, self.qparams,
                           self.hard, self.soft, self.stats)
         c.rate_proxy(self.stats, qstep, lam, self.rate3, self.rate_grad)
         c.render_fwd(self.qparams, self.hard, self.image, self.final_T, self.last,
                      self.evals if count_evals else None)
-        c.l1_loss(self.image, target, self.loss, self.dimage, loss_scale)
+        c.l1_loss(self.image, target, self.loss, self.dimage, loss_scale * (1.0 - ssim_weight))
+        if ssim_weight > 0.0:
+            c.ssim_loss(self.image, target, loss_scale * ssim_weight, self.loss_ssim, self.dimage)
 
     def backward(self, params, qstep, mask_mode: int = 0, grad_params=None, dimage=None):
         """Gradients of loss = D + lam R.  grad_params defaults to an in-place
