@@ -22,8 +22,9 @@ the set the backward re-walks), the roofline of the dominant kernel group
 the timed region), the same step replayed from a HIP graph, the learned-rate
 step (MLP in the loop, forward + recompute backward) timed beside it, the
 MLP's training / inference throughput, the fixed-length encode / decode of
-the kept Gaussians (Sec. 3.4.1), and the FP64 oracle timed on the host as a
-CPU baseline.
+the kept Gaussians (Sec. 3.4.1), the SSIM term of the distortion, the
+Laplace rate proxy beside the range proxy, and the FP64 oracle timed on the
+host as a CPU baseline.
 """
 from __future__ import annotations
 
@@ -218,7 +219,7 @@ def main():
                     help="blend launch schedule when --tile names a shape (default: stride "
                          "on the 1M workload, where the autotuner picks it, else tile)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip graph / learned / MLP / codec legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip graph / learned / MLP / codec / SSIM / rate-variant legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (scale for HBM counters)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -469,6 +470,36 @@ def main():
             "encode_hbm_frac": round(enc_bytes / (ems * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "decode_hbm_frac": round(dec_bytes / (dms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         del payload, out
+
+        # SSIM term of the distortion (forward + gradient) on the step's image
+        lss = torch.empty(1, dtype=torch.float32, device=dev)
+        for _ in range(3):
+            ctx.ssim_loss(rd.image, target, 0.2, lss, rd.dimage)
+        ev[0].record(stream)
+        for _ in range(args.steps):
+            ctx.ssim_loss(rd.image, target, 0.2, lss, rd.dimage)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        sms = ev[0].elapsed_time(ev[1]) / args.steps
+        npx = sc.views * 3 * sc.width * sc.height
+        line["ssim"] = {"ms": round(sms, 4), "pixels": npx,
+                        "gpix_per_s": round(npx / (sms * 1e-3) / 1e9, 2)}
+
+        # rate-proxy variants: the range proxy from the quantizer's statistics
+        # against the scale-based Laplace proxy (two passes + dense backward)
+        def time_rate(proxy):
+            for _ in range(3):
+                ctx.rate_variant(params, q, rd.stats, lam, rd.rate3, rd.rate_grad, proxy)
+                ctx.rate_variant_bwd(params, rd.grad_qparams)
+            ev[0].record(stream)
+            for _ in range(args.steps):
+                ctx.rate_variant(params, q, rd.stats, lam, rd.rate3, rd.rate_grad, proxy)
+                ctx.rate_variant_bwd(params, rd.grad_qparams)
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            return ev[0].elapsed_time(ev[1]) / args.steps
+        line["rate_variants"] = {"range_ms": round(time_rate("range"), 4),
+                                 "laplace_fwd_bwd_ms": round(time_rate("laplace"), 4)}
 
     if not args.no_cpu_baseline and args.workload == "c2":
         line["cpu_baseline"] = cpu_baseline(sc, lam)

@@ -183,9 +183,12 @@ k_stats_finish(int nblocks, const uint64_t *__restrict__ part, const float *__re
   }
 }
 
-// Rate proxy from the statistics: one wave, lane j = channel j.
+// Rate proxy from the statistics: one wave, lane j = channel j.  additive:
+// the loss carries weight L_quant + alpha L_mask instead of weight L_mask
+// L_quant; loss_form: out3[0] is that loss term instead of R = L_mask L_quant.
 __global__ void k_rate_proxy(const uint64_t *__restrict__ stats, const float *__restrict__ q,
-                             int64_t n_hat, float weight, float *__restrict__ out3,
+                             int64_t n_hat, float weight, int additive, float alpha,
+                             int loss_form, float *__restrict__ out3,
                              float *__restrict__ rate_grad) {
   const int j = threadIdx.x;
   float L = 0.0f, c = 1.0f, R = 0.0f, qj = 1.0f;
@@ -201,23 +204,26 @@ __global__ void k_rate_proxy(const uint64_t *__restrict__ stats, const float *__
   const double kept = (double)stats[118];
   const float Lm = (float)(kept / (double)n_hat);
   if (j == 0) {
-    out3[0] = Lm * Lq;
+    out3[0] = !loss_form ? Lm * Lq : (additive ? weight * Lq + alpha * Lm : weight * Lm * Lq);
     out3[1] = Lq;
     out3[2] = Lm;
   }
   if (rate_grad) {
     const float ln2 = 0.69314718055994531f;
+    const float f = additive ? 1.0f : Lm;  // factor on the L_quant gradients
     if (j < SGS_NCH) {
       float gR = 0.0f, gq = 0.0f;
       if (R > 0.0f) {
-        gR = weight * Lm / (c * qj * ln2);
-        gq = -weight * Lm * R / (c * qj * qj * ln2);
+        gR = weight * f / (c * qj * ln2);
+        gq = -weight * f * R / (c * qj * qj * ln2);
       }
       rate_grad[j] = gR;
       rate_grad[64 + j] = -gR;
       rate_grad[128 + j] = gq;
     }
-    if (j == 0) rate_grad[192] = (float)((double)weight * (double)Lq / (double)n_hat);
+    if (j == 0)
+      rate_grad[192] = additive ? (float)((double)alpha / (double)n_hat)
+                                : (float)((double)weight * (double)Lq / (double)n_hat);
   }
 }
 
@@ -344,7 +350,15 @@ hipError_t launch_fakequant_prune(sgs_ctx *c, const float *params, const float *
 hipError_t launch_rate_proxy(sgs_ctx *c, const uint64_t *stats, const float *q, float weight,
                              float *out3, float *rate_grad) {
   SgsProfScope ps(c, SGS_PROF_RATE);
-  k_rate_proxy<<<1, 64, 0, c->stream>>>(stats, q, c->n_hat, weight, out3, rate_grad);
+  k_rate_proxy<<<1, 64, 0, c->stream>>>(stats, q, c->n_hat, weight, 0, 0.0f, 0, out3, rate_grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_rate_proxy_mode(sgs_ctx *c, const uint64_t *stats, const float *q,
+                                  float weight, int additive, float alpha, float *out3,
+                                  float *rate_grad) {
+  k_rate_proxy<<<1, 64, 0, c->stream>>>(stats, q, c->n_hat, weight, additive, alpha, 1, out3,
+                                        rate_grad);
   return hipGetLastError();
 }
 

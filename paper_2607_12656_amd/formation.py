@@ -1,6 +1,7 @@
 """The structural-formation iteration on the GPU (paper Sec. 3.3): one RD
 step on the Gumbel-sigmoid (or given) mask, the plain rate proxy or the
-learned estimator in the loop, then one Adam step on the parameters, the
+learned estimator in the loop, L1 or (with ``ssim_weight``) vanilla 3DGS's
+L1 + SSIM distortion, then one Adam step on the parameters, the
 step sizes and the retention scores (Sec. 4.1 adopts an economical Adam
 schedule with separated updates of the higher SH coefficients; read here as
 ``sh_every`` and ``sparse``).
@@ -31,19 +32,24 @@ class Formation:
     every ``iterate``; target is the image stack the L1 distortion compares
     with.  ``mlp = (packed, theta)`` puts the learned estimator in the loop
     (its forward and recompute backward); otherwise the plain proxy supplies
-    the rate gradient."""
+    the rate gradient: the paper's range-based multiplicative proxy, or with
+    ``proxy="laplace"`` / ``masking="add"`` (weight ``alpha``) the variants its
+    ablations compare."""
 
     def __init__(self, rd: RDStep, params, qstep, score, target, lam: float,
                  mask_mode: int = 1, given_mask=None, seed: int = 0, mlp=None,
                  lr=LR_3DGS, lr_q: float = 1e-4, lr_score: float = 1e-2,
-                 sh_every: int = 16, sparse: bool = True):
+                 sh_every: int = 16, sparse: bool = True, ssim_weight: float = 0.0,
+                 proxy: str = "range", masking: str = "mult", alpha: float = 0.0):
         torch = rd.torch
         self.rd, self.ctx = rd, rd.ctx
         self.params, self.q, self.score, self.target = params, qstep, score, target
         self.lam, self.mask_mode, self.given, self.seed = lam, mask_mode, given_mask, seed
         self.mlp = mlp
         self.lr, self.lr_q, self.lr_score = list(lr), lr_q, lr_score
-        self.sh_every, self.sparse = sh_every, sparse
+        self.sh_every, self.sparse, self.ssim_weight = sh_every, sparse, ssim_weight
+        self.proxy, self.masking, self.alpha = proxy, masking, alpha
+        self.variant = (proxy, masking) != ("range", "mult")
         z = lambda a: torch.zeros_like(a)
         self.pm, self.pv = z(params), z(params)
         self.qm, self.qv = z(qstep), z(qstep)
@@ -61,11 +67,17 @@ class Formation:
             packed, theta = self.mlp
             c.rate_proxy(rd.stats, q, 0.0, rd.rate3, None)      # evaluated, not followed
             c.rate_mlp_fwd(packed, theta, p, q, rd.stats, rd.hard, self.R_learned, None)
+        elif self.variant:      # the Laplace proxy or additive masking
+            c.rate_variant(p, q, rd.stats, self.lam, rd.rate3, rd.rate_grad, self.proxy,
+                           self.masking, self.alpha)
         else:
             c.rate_proxy(rd.stats, q, self.lam, rd.rate3, rd.rate_grad)
         c.render_fwd(rd.qparams, rd.hard, rd.image, rd.final_T, rd.last,
                      rd.evals if count_evals else None)
-        c.l1_loss(rd.image, self.target, rd.loss, rd.dimage)
+        w = self.ssim_weight
+        c.l1_loss(rd.image, self.target, rd.loss, rd.dimage, 1.0 - w)
+        if w > 0.0:
+            c.ssim_loss(rd.image, self.target, w, rd.loss_ssim, rd.dimage)
         c.render_bwd(rd.qparams, rd.hard, rd.final_T, rd.last, rd.dimage, rd.grad_qparams,
                      rd.grad_mask)
         c.fakequant_prune_bwd(p, q, rd.soft, mm, None if learned else rd.rate_grad,
@@ -74,6 +86,8 @@ class Formation:
         if learned:
             c.rate_mlp_bwd(packed, theta, p, q, rd.stats, rd.hard, rd.soft, mm, self.lam,
                            rd.grad_qparams, rd.grad_q, rd.grad_score, None)
+        elif self.variant:
+            c.rate_variant_bwd(p, rd.grad_qparams)
         c.adam_step(self.lr, k + 1, p, self.pm, self.pv, rd.grad_qparams, q, self.qm, self.qv,
                     rd.grad_q, s, self.sm, self.sv, rd.grad_score, lr_q=self.lr_q,
                     lr_score=self.lr_score, sh_rest=(k % self.sh_every == 0),
