@@ -62,7 +62,7 @@ __device__ __forceinline__ uint64_t uniform_mask(uint64_t m) {
 }
 
 // One tile of the forward; evals accumulates the thread's in-span pairs.
-template <int TW, int TH>
+template <int TW, int TH, bool COUNT>
 __device__ __forceinline__ void blend_fwd_tile(int tile, int n, int W, int H, int GW,
                                                int tiles_per_view,
                                                const uint2 *__restrict__ ranges,
@@ -137,10 +137,10 @@ __device__ __forceinline__ void blend_fwd_tile(int tile, int n, int W, int H, in
       uint64_t m = uniform_mask(s_meet[wave][word]);
       if (m == 0ull) continue;
       // composite entry k; false once every pixel of the wave has stopped
-      auto step = [&](const SplatLds &cur, int k) -> bool {
+      auto step = [&](const SplatLds &cur, int k) {
         const SplatEval e = eval_splat(cur, px, py, fx, fy);
         const bool act = !done;
-        evals += (act && e.in_span) ? 1u : 0u;
+        if (COUNT) evals += (act && e.in_span) ? 1u : 0u;
         const bool okc = act && e.ok;
         const float at = cur.c.w * e.alpha;
         const float Tn = T * (1.0f - at);
@@ -153,7 +153,6 @@ __device__ __forceinline__ void blend_fwd_tile(int tile, int n, int W, int H, in
         T = contrib ? Tn : T;
         stop = term ? b - rg.x + (uint32_t)k : stop;
         done = done || term;
-        return __ballot(!done) != 0ull;
       };
       // two register sets in turn: the next record loads while one is used
       int ka = word * 64 + __builtin_ctzll(m), kb = ka;
@@ -166,7 +165,7 @@ __device__ __forceinline__ void blend_fwd_tile(int tile, int n, int W, int H, in
           m &= m - 1;
           rb_ = sh[kb];
         }
-        if (!step(ra_, ka)) { wave_done = true; break; }
+        step(ra_, ka);
         if (!more) break;
         more = m != 0ull;
         if (more) {
@@ -174,9 +173,13 @@ __device__ __forceinline__ void blend_fwd_tile(int tile, int n, int W, int H, in
           m &= m - 1;
           ra_ = sh[ka];
         }
-        if (!step(rb_, kb)) { wave_done = true; break; }
+        step(rb_, kb);
+        // whether any pixel of the wave still runs, every second entry (an
+        // entry composited after the last pixel stopped changes nothing)
+        if (__ballot(!done) == 0ull) { wave_done = true; break; }
         if (!more) break;
       }
+      if (!wave_done && __ballot(!done) == 0ull) wave_done = true;
     }
   }
   if (inside) {
@@ -222,7 +225,7 @@ __device__ __forceinline__ int later_tile(int q, uint32_t *head, int total) {
   return q < total ? q : -1;
 }
 
-template <int TW, int TH, int SCHED>
+template <int TW, int TH, int SCHED, bool COUNT>
 __global__ void __launch_bounds__(TW * TH)
 k_blend_fwd(int total_tiles, const uint32_t *__restrict__ order, uint32_t *__restrict__ head,
             int n, int W, int H, int GW, int tiles_per_view, const uint2 *__restrict__ ranges,
@@ -234,9 +237,9 @@ k_blend_fwd(int total_tiles, const uint32_t *__restrict__ order, uint32_t *__res
   uint32_t evals = 0;
   for (int q = first_tile<SCHED>(head, total_tiles); q >= 0;
        q = later_tile<SCHED>(q, head, total_tiles))
-    blend_fwd_tile<TW, TH>(SCHED == kPerTile ? q : (int)order[q], n, W, H, GW, tiles_per_view,
-                           ranges, vals, rec, image, final_T, last, evals);
-  if (eval_count) {
+    blend_fwd_tile<TW, TH, COUNT>(SCHED == kPerTile ? q : (int)order[q], n, W, H, GW,
+                                  tiles_per_view, ranges, vals, rec, image, final_T, last, evals);
+  if (COUNT) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     unsigned long long ev = evals;
 #pragma unroll
@@ -570,17 +573,25 @@ int persistent_grid(K kernel, int block, int tiles) {
   return (int)(g < tiles ? g : tiles);
 }
 
-template <int TW, int TH, int SCHED>
-hipError_t fwd_t(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint64_t *ec) {
+template <int TW, int TH, int SCHED, bool COUNT>
+hipError_t fwd_tc(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint64_t *ec) {
   const uint32_t *vals = c->pair_val[c->pair_sorted_buf];
   const int tiles = (int)c->total_tiles;
-  const int grid = SCHED == kPerTile ? tiles
-                                     : persistent_grid(k_blend_fwd<TW, TH, SCHED>, TW * TH, tiles);
-  k_blend_fwd<TW, TH, SCHED><<<grid, TW * TH, 0, c->stream>>>(
+  const int grid = SCHED == kPerTile
+                       ? tiles
+                       : persistent_grid(k_blend_fwd<TW, TH, SCHED, COUNT>, TW * TH, tiles);
+  k_blend_fwd<TW, TH, SCHED, COUNT><<<grid, TW * TH, 0, c->stream>>>(
       tiles, c->tile_order, c->tile_bins + 66, (int)c->n, c->W, c->H, c->GW,
       (int)c->tiles_per_view, c->ranges, vals, c->rec, image, final_T, last,
       (unsigned long long *)ec);
   return hipGetLastError();
+}
+
+// the evaluation count is compiled in only when it is asked for
+template <int TW, int TH, int SCHED>
+hipError_t fwd_t(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint64_t *ec) {
+  return ec ? fwd_tc<TW, TH, SCHED, true>(c, image, final_T, last, ec)
+            : fwd_tc<TW, TH, SCHED, false>(c, image, final_T, last, ec);
 }
 
 template <int TW, int TH, int SCHED>
