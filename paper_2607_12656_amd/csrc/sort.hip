@@ -122,13 +122,15 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
 // lanes each, rows padded to 257 words so that equal digits of different
 // sub-histograms sit in different banks): the pass over the high digit sees
 // long runs of equal digits, and same-address LDS atomics serialize.
+template <int IT>
 __global__ void __launch_bounds__(kThreads)
 k_radix_hist(const uint32_t *__restrict__ keys, int64_t count_static,
              const uint32_t *__restrict__ dcount, int shift, uint32_t *__restrict__ hist) {
+  constexpr int TILE = kThreads * IT;
   __shared__ uint32_t s_sub[kThreads / 8][257];
   const int64_t count = dcount ? (int64_t)*dcount : count_static;
-  const int64_t blk = sgs_xcd_block_live(blockIdx.x, gridDim.x, (count + kTile - 1) / kTile);
-  const int64_t base = blk * kTile;
+  const int64_t blk = sgs_xcd_block_live(blockIdx.x, gridDim.x, (count + TILE - 1) / TILE);
+  const int64_t base = blk * TILE;
   if (base >= count) {  // grid sized for a capacity, not the live count
     hist[blk * 256 + threadIdx.x] = 0;
     return;
@@ -136,16 +138,16 @@ k_radix_hist(const uint32_t *__restrict__ keys, int64_t count_static,
 #pragma unroll
   for (int w = 0; w < kThreads / 8; ++w) s_sub[w][threadIdx.x] = 0;
   // all loads of the block in flight at once
-  uint32_t kr[kItems];
+  uint32_t kr[IT];
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
+  for (int r = 0; r < IT; ++r) {
     const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
     kr[r] = i < count ? keys[i] : 0u;
   }
   __syncthreads();
   uint32_t *mine = s_sub[threadIdx.x >> 3];
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
+  for (int r = 0; r < IT; ++r) {
     const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
     if (i < count) atomicAdd(&mine[(kr[r] >> shift) & 0xFFu], 1u);
   }
@@ -220,8 +222,9 @@ constexpr int kTilePad = kTile + kTile / 16;
 // consecutive threads on consecutive addresses (coalesced).
 // h_raw / h_scan: this thread's digit (= tid) entries of the block's raw and
 // scanned histogram rows, loaded by the caller ahead of its other work.
-__device__ __forceinline__ void scatter_block(const uint32_t (&kr)[kItems],
-                                              const uint32_t (&vr)[kItems], int64_t base,
+template <int IT>
+__device__ __forceinline__ void scatter_block(const uint32_t (&kr)[IT],
+                                              const uint32_t (&vr)[IT], int64_t base,
                                               int64_t count, int shift, uint32_t h_raw,
                                               uint32_t h_scan, uint32_t *__restrict__ kout,
                                               uint32_t *__restrict__ vout, uint32_t *s_key,
@@ -240,7 +243,7 @@ __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[kItems],
   s_run[threadIdx.x] = 0;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
+  for (int r = 0; r < IT; ++r) {
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) s_wc[w][threadIdx.x] = 0;
     __syncthreads();
@@ -265,13 +268,13 @@ __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[kItems],
     }
     __syncthreads();
     if (valid) {
-      const uint32_t lp = s_loff[d] + s_wc[wave][d] + rank;  // < kTile
+      const uint32_t lp = s_loff[d] + s_wc[wave][d] + rank;  // < kThreads * IT
       s_key[lp] = k;
       s_val[lp] = v;
     }
     __syncthreads();
   }
-  const int nloc = (int)min((int64_t)kTile, count - base);
+  const int nloc = (int)min((int64_t)(kThreads * IT), count - base);
 #pragma unroll 4
   for (int p = threadIdx.x; p < nloc; p += kThreads) {
     const uint32_t k = s_key[p];
@@ -282,28 +285,30 @@ __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[kItems],
   }
 }
 
+template <int IT>
 __global__ void __launch_bounds__(kThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                 uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                 int64_t count_static, const uint32_t *__restrict__ dcount, int shift,
                 const uint32_t *__restrict__ hist_raw, const uint32_t *__restrict__ hist_scanned) {
-  __shared__ uint32_t s_key[kTile];
-  __shared__ uint32_t s_val[kTile];
+  constexpr int TILE = kThreads * IT;
+  __shared__ uint32_t s_key[TILE];
+  __shared__ uint32_t s_val[TILE];
   const int64_t count = dcount ? (int64_t)*dcount : count_static;
-  const int64_t blk = sgs_xcd_block_live(blockIdx.x, gridDim.x, (count + kTile - 1) / kTile);
-  const int64_t base = blk * kTile;
+  const int64_t blk = sgs_xcd_block_live(blockIdx.x, gridDim.x, (count + TILE - 1) / TILE);
+  const int64_t base = blk * TILE;
   if (base >= count) return;
   // all loads of the block in flight at once
   const uint32_t h_raw = hist_raw[blk * 256 + threadIdx.x];
   const uint32_t h_scan = hist_scanned[blk * 256 + threadIdx.x];
-  uint32_t kr[kItems], vr[kItems];
+  uint32_t kr[IT], vr[IT];
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
+  for (int r = 0; r < IT; ++r) {
     const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
     kr[r] = i < count ? kin[i] : 0u;
     vr[r] = i < count ? vin[i] : 0u;
   }
-  scatter_block(kr, vr, base, count, shift, h_raw, h_scan, kout, vout, s_key, s_val);
+  scatter_block<IT>(kr, vr, base, count, shift, h_raw, h_scan, kout, vout, s_key, s_val);
 }
 
 // ---------------------------------------------------------------------------
@@ -488,7 +493,7 @@ k_gen_scatter(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ br
     vr[r] = s_val[li];
   }
   __syncthreads();
-  scatter_block(kr, vr, base, count, 0, h_raw, h_scan, kout, vout, s_key, s_val);
+  scatter_block<kItems>(kr, vr, base, count, 0, h_raw, h_scan, kout, vout, s_key, s_val);
 }
 
 __global__ void k_zero_ranges(uint2 *__restrict__ ranges, int64_t tiles) {
@@ -567,8 +572,18 @@ hipError_t ensure_tmp(sgs_ctx *c, int64_t scan_words, int64_t hist_words) {
 
 int64_t radix_blocks(int64_t count) { return (count + kTile - 1) / kTile; }
 
+// A plain radix pass over at most kSmallSort elements takes kSmallItems per
+// thread: with 4096 per block a 1M-element sort would launch fewer blocks
+// than there are compute units.
+constexpr int64_t kSmallSort = (int64_t)1 << 22;
+constexpr int kSmallItems = 4;
+int64_t radix_tile(int64_t count) {
+  return count <= kSmallSort ? (int64_t)kThreads * kSmallItems : (int64_t)kTile;
+}
+
 int64_t radix_hist_words(int64_t count) {
-  const int64_t nb = (count + kTile - 1) / kTile;
+  const int64_t tile = radix_tile(count);
+  const int64_t nb = (count + tile - 1) / tile;
   const int64_t ng = (nb + kChunk - 1) / kChunk;
   return 2 * nb * 256 + ng * 256 + 256 + 1;
 }
@@ -595,8 +610,8 @@ struct SortBufs {
   uint32_t *hraw, *hscan, *chunk, *total;
 };
 
-bool sort_bufs(sgs_ctx *c, int64_t count, SortBufs &b) {
-  b.nb = (count + kTile - 1) / kTile;
+bool sort_bufs(sgs_ctx *c, int64_t count, SortBufs &b, int64_t tile = kTile) {
+  b.nb = (count + tile - 1) / tile;
   b.ng = (b.nb + kChunk - 1) / kChunk;
   if (radix_hist_words(count) > c->sort_hist_words) return false;
   b.hraw = c->sort_hist;
@@ -625,15 +640,25 @@ hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2], i
   int cur = cur0;
   *which = cur0;
   if (count <= 1 || shift0 >= bits) return hipSuccess;
+  const bool small = count <= kSmallSort;
   SortBufs b;
-  if (!sort_bufs(c, count, b)) return hipErrorInvalidValue;
+  if (!sort_bufs(c, count, b, radix_tile(count))) return hipErrorInvalidValue;
   for (int shift = shift0; shift < bits; shift += 8) {
-    k_radix_hist<<<(unsigned)b.nb, kThreads, 0, c->stream>>>(keys[cur], count, dcount, shift,
-                                                             b.hraw);
+    if (small)
+      k_radix_hist<kSmallItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
+          keys[cur], count, dcount, shift, b.hraw);
+    else
+      k_radix_hist<kItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(keys[cur], count, dcount,
+                                                                      shift, b.hraw);
     launch_digit_offsets(c, b);
-    k_radix_scatter<<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
-        keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, b.hraw,
-        b.hscan);
+    if (small)
+      k_radix_scatter<kSmallItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
+          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, b.hraw,
+          b.hscan);
+    else
+      k_radix_scatter<kItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
+          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, b.hraw,
+          b.hscan);
     cur ^= 1;
   }
   *which = cur;
