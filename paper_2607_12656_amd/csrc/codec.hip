@@ -37,30 +37,6 @@ constexpr int kPlanThreads = 1024;
 constexpr int kOffW = 0, kWidW = 2 * SGS_NCH, kCntW = 3 * SGS_NCH;
 __host__ __device__ constexpr int64_t range_word(int64_t nc) { return (kCntW + 2 * nc + 1) & ~1LL; }
 
-__device__ __forceinline__ int32_t code_of(float y, float q, bool &ok) {
-  const float k = rintf(__fdiv_rn(y, q));
-  ok = k >= -2147483648.0f && k < 2147483648.0f;
-  return ok ? (int32_t)k : 0;
-}
-
-// The same decision from y * rq, rq = 1 / q correctly rounded and a normal
-// float (fast_ok): then |y rq - y/q| <= (2^-23 + 2^-48) |y/q| (plus 2^-150
-// where y rq is subnormal) and the rounded quotient lies within 2^-24 |y/q|
-// of y/q, so the two are within about 3 * 2^-24 |y rq| of each other and round
-// to the same integer whenever y rq lies farther than 2^-21 |y rq| from every
-// half-integer: |y rq - k| < 1/2 - 2^-21 |y rq| with k = rint(y rq) (t - k is
-// exact; the bound, rounded once, keeps a margin of more than 2 over the
-// error; it is negative from |y rq| = 2^20 on, so k stays far inside int32).
-// Otherwise (near a tie, large, not finite) the division decides.
-__device__ __forceinline__ int32_t code_fast(float y, float q, float rq, bool fast_ok, bool &ok) {
-  const float t = y * rq;
-  const float k = rintf(t);
-  if (fast_ok && fabsf(t - k) < __fmaf_rn(-fabsf(t), 4.76837158203125e-7f, 0.5f)) {
-    ok = true;
-    return (int32_t)k;
-  }
-  return code_of(y, q, ok);
-}
 
 // thread t of a chunk's block: Gaussians i0 .. i0 + 15; mask bytes and the
 // channel-j values (0 past n)
@@ -222,8 +198,8 @@ k_fl_plan(int nc, const float *__restrict__ q, uint32_t *__restrict__ scr,
       bool ok_lo = false, ok_hi = false;
       if (lo <= hi) {
         const float qt = q[t];
-        const int32_t a = code_of(lo, qt, ok_lo);
-        const int32_t z = code_of(hi, qt, ok_hi);
+        const int32_t a = sgs_code_of(lo, qt, ok_lo);
+        const int32_t z = sgs_code_of(hi, qt, ok_hi);
         kmin = min(a, z);  // q < 0 reverses the order
         const uint64_t K = (uint64_t)((int64_t)max(a, z) - (int64_t)kmin) + 1;
         w = K <= 1 ? 0 : 64 - __clzll((long long)(K - 1));
@@ -308,7 +284,7 @@ k_fl_pack(int64_t n, int64_t npad, const float *__restrict__ y, const uint8_t *_
 #pragma unroll
   for (int e = 0; e < kCItems; ++e) {  // every slot is coded; dropped ones land in a discard
     bool ok;
-    const int32_t k = code_fast(yv[e], qj, rq, fast_ok, ok);
+    const int32_t k = sgs_code_fast(yv[e], qj, rq, fast_ok, ok);
     const bool kept = (keep >> e) & 1u;
     bad |= kept && !ok;
     s_vals[kept ? before + __popc(keep & ((1u << e) - 1u)) : kCChunk + lane] =

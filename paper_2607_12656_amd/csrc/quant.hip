@@ -243,6 +243,8 @@ k_fakequant_bwd(int64_t n, int64_t npad, const float *__restrict__ params,
   const int64_t c0 = chunk * kRPer;
   const bool copy = gparams != gq_in;
   const float qj = q[j];
+  const float rq = __fdiv_rn(1.0f, qj);
+  const bool fast_ok = sgs_rq_ok(rq);
   const float *yrow = params + j * npad;
   const float *grow = gq_in + j * npad;
   float *orow = gparams + j * npad;
@@ -257,7 +259,7 @@ k_fakequant_bwd(int64_t n, int64_t npad, const float *__restrict__ params,
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         if (i + e < n) {
-          const float k = rintf(__fdiv_rn(yv[e], qj));
+          const float k = sgs_rint_div(yv[e], qj, rq, fast_ok);  // = rint(fl32(y / q))
           acc = fma((double)gv[e], (double)fmaf(k, qj, -yv[e]), acc);
         }
       }

@@ -289,6 +289,46 @@ __device__ __forceinline__ int64_t sgs_xcd_block_live(int64_t i, int64_t nb, int
   return nlive + r;
 }
 
+// The quantizer's code k = rint(y / q) (FP32 division, ties to even), and
+// whether it lies in int32.
+__device__ __forceinline__ int32_t sgs_code_of(float y, float q, bool &ok) {
+  const float k = rintf(__fdiv_rn(y, q));
+  ok = k >= -2147483648.0f && k < 2147483648.0f;
+  return ok ? (int32_t)k : 0;
+}
+
+// The same decision from y * rq, rq = 1 / q correctly rounded and a normal
+// float (fast_ok): then |y rq - y/q| <= (2^-23 + 2^-48) |y/q| (plus 2^-150
+// where y rq is subnormal) and the rounded quotient lies within 2^-24 |y/q|
+// of y/q, so the two are within about 3 * 2^-24 |y rq| of each other and round
+// to the same integer whenever y rq lies farther than 2^-21 |y rq| from every
+// half-integer: |y rq - k| < 1/2 - 2^-21 |y rq| with k = rint(y rq) (t - k is
+// exact; the bound, rounded once, keeps a margin of more than 2 over the
+// error; it is negative from |y rq| = 2^20 on, so k stays far inside int32).
+// Otherwise (near a tie, large, not finite) the division decides.  This one
+// returns rint(fl32(y / q)) as a float; sgs_code_fast below, the int32 code.
+__device__ __forceinline__ float sgs_rint_div(float y, float q, float rq, bool fast_ok) {
+  const float t = y * rq;
+  const float k = rintf(t);
+  if (fast_ok && fabsf(t - k) < __fmaf_rn(-fabsf(t), 4.76837158203125e-7f, 0.5f)) return k;
+  return rintf(__fdiv_rn(y, q));
+}
+// Whether rq = 1 / q (correctly rounded) is a normal float, so that the
+// product rule above holds.
+__device__ __forceinline__ bool sgs_rq_ok(float rq) {
+  return fabsf(rq) >= 1.17549435e-38f && fabsf(rq) <= 3.40282347e+38f;
+}
+
+__device__ __forceinline__ int32_t sgs_code_fast(float y, float q, float rq, bool fast_ok, bool &ok) {
+  const float t = y * rq;
+  const float k = rintf(t);
+  if (fast_ok && fabsf(t - k) < __fmaf_rn(-fabsf(t), 4.76837158203125e-7f, 0.5f)) {
+    ok = true;
+    return (int32_t)k;
+  }
+  return sgs_code_of(y, q, ok);
+}
+
 // Bit i = (byte i of m) != 0: the high bit of each nonzero byte (the carry of
 // its low seven bits plus 0x7F, or its own high bit), gathered by one
 // multiply into bits 28..31 (the other partial products land below bit 24).
