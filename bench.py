@@ -43,7 +43,7 @@ HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
-# Algorithmic work per unit ("Kernels and their rooflines").
+# Algorithmic work per unit of each kernel group.
 NCH = 59
 FLOP_PER_EVAL_FWD = 24     # offsets 2, quadratic form 9, exp 2, alpha/T 5, colour 6
 FLOP_PER_EVAL_BWD = 60     # alpha recompute 15, T and dalpha 12, 10 gradients 23, back colour 10
@@ -228,8 +228,8 @@ def main():
                          "is unchanged since the counters were taken)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "the step runs on one GPU; --gpus must be 1 (sharding "
+                                   "over GPUs is not implemented)"}))
         sys.exit(2)
 
     import numpy as np

@@ -286,7 +286,7 @@ sgs_status sgs_rate_variant(sgs_ctx *ctx, const float *params, const float *qste
  * after the range proxy. */
 sgs_status sgs_rate_variant_bwd(sgs_ctx *ctx, const float *params, float *grad_params);
 
-/* SSIM term of the rendering distortion (the supplement's D_render follows
+/* SSIM term of the rendering distortion (the supplement takes D_render from
  * vanilla 3DGS: D = (1 - w) L1 + w (1 - SSIM), w = 0.2 there; call
  * sgs_l1_loss with scale 1 - w, then this with weight w).  SSIM (Wang et al.
  * 2004) per view and colour plane with the 11 x 11 Gaussian window of

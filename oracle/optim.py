@@ -6,8 +6,8 @@ package).  Plain numpy in FP64.
 Adam as Kingma & Ba (2015) define it (Algorithm 1, bias-corrected moments):
     m <- b1 m + (1 - b1) g;  v <- b2 v + (1 - b2) g^2
     x <- x - lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
-and the two switches this build reads from the economical optimizer schedule
-the paper adopts (Sec. 4.1): the 45 higher-order SH rows (channels 6-50) can
+and the two switches read here from the economical optimizer schedule the
+paper adopts (Sec. 4.1): the 45 higher-order SH rows (channels 6-50) can
 be left out of a step, and with ``sparse`` a Gaussian whose gradients in the
 rows of the step are all exactly zero keeps its values and moments.
 """

@@ -1,4 +1,4 @@
-// SSIM part of the rendering distortion (the supplement's D_render follows
+// SSIM part of the rendering distortion (the supplement takes D_render from
 // vanilla 3DGS: D = (1 - w) L1 + w (1 - SSIM)).  SSIM per image plane with
 // the 11 x 11 Gaussian window of standard deviation 1.5, zero outside the
 // image, C1 = 0.01^2, C2 = 0.03^2, averaged over all pixels.
