@@ -53,8 +53,11 @@ MLP_FLOP_PER_ROW = 2 * (64 * 128 + 128 * 128 + 128)
 def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int):
     """(bound, algorithmic amount per launch, unit) of one kernel group."""
     pix = V * W * H
+    # the step runs the fused entry points: the quantizer pass reads the rows
+    # for the rate statistics only, the projections quantize in registers,
+    # and the projection backward applies the quantizer's backward
     if g == "fakequant":
-        return "hbm", n * (NCH * 4 * 2 + 1 + 1 + 4), "B"
+        return "hbm", n * (NCH * 4 + 1 + 1 + 4), "B"
     if g == "preprocess":
         return "hbm", n * (NCH * 4 + 1) + V * n * (48 + 12), "B"
     if g in ("depth_sort", "scan"):
@@ -74,9 +77,9 @@ def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int):
     if g == "blend_bwd":
         return "alu", E * FLOP_PER_EVAL_BWD, "FLOP"
     if g == "preprocess_bwd":
-        return "hbm", n * (NCH * 4 * 2 + 4) + V * n * 48, "B"
-    if g == "fakequant_bwd":
-        return "hbm", n * (NCH * 4 * 3 + 4 * 3), "B"
+        return "hbm", n * (NCH * 4 * 2 + 4 + 4) + V * n * 48, "B"
+    if g == "fakequant_bwd":     # the step-size partials of the projection backward
+        return "hbm", NCH * 8 * -(-n // 128), "B"
     return "hbm", 0, "B"
 
 
@@ -258,8 +261,9 @@ def main():
         del src, dst
 
     def plain_step(rd, count=False):
-        # the straight-through gradient is written in place over the render
-        # gradient buffer (the C ABI allows grad_params == grad_qparams)
+        # the fused entry points (quant_render_fwd / quant_render_bwd): the
+        # quantized rows and their gradient never cross HBM
+        rd.fused = True
         rd.forward(params, q, score, target, lam, 0, mask, 0, 0, count_evals=count)
         rd.backward(params, q, 0)
 
@@ -365,16 +369,13 @@ def main():
 
         def learned_step():
             c = ctx
-            c.fakequant_prune(params, q, score, 0, mask, 0, 0, rd.qparams, rd.hard, rd.soft,
-                              rd.stats)
+            c.quant_render_fwd(params, q, score, 0, mask, 0, 0, rd.hard, rd.soft, rd.stats,
+                               rd.image, rd.final_T, rd.last)
             c.rate_proxy(rd.stats, q, 0.0, rd.rate3, None)
             c.rate_mlp_fwd(packed, theta, params, q, rd.stats, rd.hard, Rl, None)
-            c.render_fwd(rd.qparams, rd.hard, rd.image, rd.final_T, rd.last, None)
             c.l1_loss(rd.image, target, rd.loss, rd.dimage)
-            c.render_bwd(rd.qparams, rd.hard, rd.final_T, rd.last, rd.dimage, rd.grad_qparams,
-                         rd.grad_mask)
-            c.fakequant_prune_bwd(params, q, rd.soft, 0, None, None, rd.grad_qparams,
-                                  rd.grad_mask, rd.grad_qparams, rd.grad_q, rd.grad_score)
+            c.quant_render_bwd(params, q, rd.soft, 0, None, None, rd.final_T, rd.last, rd.dimage,
+                               rd.grad_qparams, rd.grad_q, rd.grad_score, rd.grad_mask)
             c.rate_mlp_bwd(packed, theta, params, q, rd.stats, rd.hard, rd.soft, 0, lam,
                            rd.grad_qparams, rd.grad_q, rd.grad_score, None)
 

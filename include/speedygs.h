@@ -7,14 +7,17 @@
  * G = the 59 channels of every Gaussian (`params`), Q = the 59 channel step
  * sizes (`qstep`), M = the per-Gaussian retention scores (`score`).  A step is
  *     sgs_fakequant_prune -> sgs_rate_proxy -> sgs_render_fwd -> sgs_l1_loss
- *     -> sgs_render_bwd -> sgs_fakequant_prune_bwd.
+ *     -> sgs_render_bwd -> sgs_fakequant_prune_bwd,
+ * or, with the same results and two fewer passes over the parameters each way,
+ *     sgs_quant_render_fwd -> sgs_rate_proxy -> sgs_l1_loss -> sgs_quant_render_bwd.
  *
  * Conventions common to every call
  *  - Device pointers are HIP device memory owned by the caller; the library
  *    never frees or keeps them beyond the call.  Host pointers are marked.
  *  - Every call only enqueues work on the stream given to sgs_create (HIP
- *    stream order gives the dependencies).  The exception is sgs_render_fwd,
- *    which reads the pair count back to the host once (it sizes the sort).
+ *    stream order gives the dependencies).  The exceptions are sgs_render_fwd
+ *    and sgs_quant_render_fwd, which read the pair count back to the host
+ *    once (it sizes the sort) unless the pair capacity is fixed.
  *  - Gaussian parameters are SoA float32 [59][npad], npad a multiple of 64,
  *    256-byte aligned rows.  Channels: 0-2 mean, 3-5 SH DC (r,g,b), 6-50 SH
  *    k=1..15 coefficient-major (6 + 3(k-1) + c), 51 opacity logit,
@@ -157,6 +160,37 @@ sgs_status sgs_fakequant_prune_bwd(sgs_ctx *ctx, const float *params, const floa
                                    const float *rate_grad, const uint64_t *stats,
                                    const float *grad_qparams, const float *grad_hard_mask,
                                    float *grad_params, float *grad_qstep, float *grad_score);
+
+/* a1-a8 in one call (Sec. 3.3.1 quantizer and mask, Sec. 3.1 render): the
+ * results of sgs_fakequant_prune followed by sgs_render_fwd (hard_mask,
+ * soft_mask, stats, image, final_T, last, eval_count bit for bit), without
+ * the quantized parameters: the projection quantizes the raw rows itself, so
+ * qparams is neither written nor read (two fewer passes over [59][npad]).
+ * Arguments as in those two calls; params rows 16-byte aligned.
+ * Synchronizes the stream once, as sgs_render_fwd does. */
+sgs_status sgs_quant_render_fwd(sgs_ctx *ctx, const float *params, const float *qstep,
+                                const float *score, int32_t mask_mode,
+                                const uint8_t *given_mask, uint64_t seed, uint64_t step,
+                                uint8_t *hard_mask, float *soft_mask, uint64_t *stats,
+                                float *image, float *final_T, uint32_t *last,
+                                uint64_t *eval_count);
+
+/* a10-a12 in one call: the results of sgs_render_bwd followed by
+ * sgs_fakequant_prune_bwd with grad_params aliasing grad_qparams (grad_params,
+ * grad_score and grad_hard_mask bit for bit; grad_qstep the same FP64 sum in
+ * another order, then rounded to float).  The projection backward re-quantizes
+ * the raw rows and applies the straight-through quantizer backward itself,
+ * so no gradient of the quantized parameters crosses HBM.  Must follow
+ * sgs_quant_render_fwd (or sgs_render_fwd of the quantized params) of the
+ * same params / qstep on this context; rate_grad/stats (both or neither) add
+ * the rate-proxy gradient.  All outputs are overwritten; grad_params [59][npad]
+ * must not alias params. */
+sgs_status sgs_quant_render_bwd(sgs_ctx *ctx, const float *params, const float *qstep,
+                                const float *soft_mask, int32_t mask_mode,
+                                const float *rate_grad, const uint64_t *stats,
+                                const float *final_T, const uint32_t *last,
+                                const float *dL_dimage, float *grad_params,
+                                float *grad_qstep, float *grad_score, float *grad_hard_mask);
 
 /* Host-side query (synchronizes the stream): pairs of the last render and the
  * device flags word of `stats` (may be NULL).  Returns SGS_EINVAL when the

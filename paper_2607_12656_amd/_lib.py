@@ -74,6 +74,8 @@ _SIGS = {
     "sgs_l1_loss": [P, P, P, F32, P, P],
     "sgs_render_bwd": [P, P, P, P, P, P, P, P],
     "sgs_fakequant_prune_bwd": [P, P, P, P, I32, P, P, P, P, P, P, P],
+    "sgs_quant_render_fwd": [P, P, P, P, I32, P, U64, U64, P, P, P, P, P, P, P],
+    "sgs_quant_render_bwd": [P, P, P, P, I32, P, P, P, P, P, P, P, P, P],
     "sgs_query": [P, P, C.POINTER(I64), C.POINTER(U64)],
     "sgs_copy_structure": [P, P, P, I64, P, P, P, P],
     "sgs_copy_splat_grads": [P, P],
@@ -245,6 +247,22 @@ class Context:
             self.h, _ptr(params), _ptr(qstep), _ptr(soft_mask), mask_mode, _ptr(rate_grad),
             _ptr(stats), _ptr(grad_qparams), _ptr(grad_hard_mask), _ptr(grad_params),
             _ptr(grad_qstep), _ptr(grad_score)), self.h)
+
+    def quant_render_fwd(self, params, qstep, score, mask_mode, given_mask, seed, step,
+                         hard_mask, soft_mask, stats, image, final_T, last, eval_count=None):
+        """fakequant_prune + render_fwd without materializing the quantized rows."""
+        self._check(self.L.sgs_quant_render_fwd(
+            self.h, _ptr(params), _ptr(qstep), _ptr(score), mask_mode, _ptr(given_mask), seed,
+            step, _ptr(hard_mask), _ptr(soft_mask), _ptr(stats), _ptr(image), _ptr(final_T),
+            _ptr(last), _ptr(eval_count)), self.h)
+
+    def quant_render_bwd(self, params, qstep, soft_mask, mask_mode, rate_grad, stats, final_T,
+                         last, dL_dimage, grad_params, grad_qstep, grad_score, grad_hard_mask):
+        """render_bwd + fakequant_prune_bwd over the raw rows."""
+        self._check(self.L.sgs_quant_render_bwd(
+            self.h, _ptr(params), _ptr(qstep), _ptr(soft_mask), mask_mode, _ptr(rate_grad),
+            _ptr(stats), _ptr(final_T), _ptr(last), _ptr(dL_dimage), _ptr(grad_params),
+            _ptr(grad_qstep), _ptr(grad_score), _ptr(grad_hard_mask)), self.h)
 
     def query(self, stats=None):
         pairs = I64()

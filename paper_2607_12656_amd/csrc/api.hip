@@ -236,8 +236,10 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   const int64_t red_l1 = (int64_t)views * 3 * width * height / 2048 + 64;
   const int64_t red_mlp = (int64_t)mlp_grid(n) * 64;
   const int64_t red_lap = lap_partial_doubles(n);
+  const int64_t red_proj = proj_partial_doubles(n);
   int64_t red = red_q > red_l1 ? red_q : red_l1;
   red = red > red_mlp ? red : red_mlp;
+  red = red > red_proj ? red : red_proj;
   red = (red > red_lap ? red : red_lap) + 64;
   SGS_ALLOC(c->red_tmp, red);
   c->red_tmp_words = red;
@@ -286,13 +288,11 @@ sgs_status sgs_rate_proxy(sgs_ctx *c, const uint64_t *stats, const float *qstep,
   return SGS_OK;
 }
 
-sgs_status sgs_render_fwd(sgs_ctx *c, const float *qparams, const uint8_t *hard_mask,
-                          float *image, float *final_T, uint32_t *last, uint64_t *eval_count) {
-  if (!c) return SGS_EINVAL;
-  if (!c->scene_set) return fail(c, SGS_ESTATE, "render_fwd: set_scene first");
-  if (!qparams || !hard_mask || !image || !final_T || !last)
-    return fail(c, SGS_EINVAL, "render_fwd: null pointer");
-  SGS_HIP(launch_preprocess(c, qparams, hard_mask), "render_fwd preprocess");
+// Everything of the forward render after the projection: depth order, pair
+// count (a host synchronization unless the pair capacity is fixed), binning
+// and the blend.
+static sgs_status render_after_projection(sgs_ctx *c, float *image, float *final_T,
+                                          uint32_t *last, uint64_t *eval_count) {
   SGS_HIP(launch_depth_order(c), "render_fwd depth order");
   if (!c->fixed_cap) {
     SGS_HIP(hipMemcpyAsync(c->h_pairs_total, c->d_pairs_total, sizeof(uint32_t),
@@ -309,6 +309,38 @@ sgs_status sgs_render_fwd(sgs_ctx *c, const float *qparams, const uint8_t *hard_
   SGS_HIP(launch_blend_fwd(c, image, final_T, last, eval_count), "render_fwd blend");
   c->rendered = true;
   return SGS_OK;
+}
+
+sgs_status sgs_render_fwd(sgs_ctx *c, const float *qparams, const uint8_t *hard_mask,
+                          float *image, float *final_T, uint32_t *last, uint64_t *eval_count) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "render_fwd: set_scene first");
+  if (!qparams || !hard_mask || !image || !final_T || !last)
+    return fail(c, SGS_EINVAL, "render_fwd: null pointer");
+  SGS_HIP(launch_preprocess(c, qparams, hard_mask), "render_fwd preprocess");
+  return render_after_projection(c, image, final_T, last, eval_count);
+}
+
+sgs_status sgs_quant_render_fwd(sgs_ctx *c, const float *params, const float *qstep,
+                                const float *score, int32_t mask_mode,
+                                const uint8_t *given_mask, uint64_t seed, uint64_t step,
+                                uint8_t *hard_mask, float *soft_mask, uint64_t *stats,
+                                float *image, float *final_T, uint32_t *last,
+                                uint64_t *eval_count) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "quant_render_fwd: set_scene first");
+  if (!params || !qstep || !hard_mask || !stats || !image || !final_T || !last)
+    return fail(c, SGS_EINVAL, "quant_render_fwd: null pointer");
+  if (!aligned(params, 16))
+    return fail(c, SGS_EINVAL, "quant_render_fwd: parameter rows must be 16-byte aligned");
+  if (mask_mode < 0 || mask_mode > 2) return fail(c, SGS_EINVAL, "quant_render_fwd: mask_mode");
+  if (mask_mode == 0 && !given_mask) return fail(c, SGS_EINVAL, "quant_render_fwd: given_mask");
+  if (mask_mode == 1 && !score) return fail(c, SGS_EINVAL, "quant_render_fwd: score");
+  SGS_HIP(launch_fakequant_prune(c, params, qstep, score, mask_mode, given_mask, seed, step,
+                                 nullptr, hard_mask, soft_mask, stats),
+          "quant_render_fwd statistics");
+  SGS_HIP(launch_preprocess(c, params, hard_mask, qstep), "quant_render_fwd preprocess");
+  return render_after_projection(c, image, final_T, last, eval_count);
 }
 
 sgs_status sgs_l1_loss(sgs_ctx *c, const float *image, const float *target, float scale,
@@ -354,6 +386,36 @@ sgs_status sgs_fakequant_prune_bwd(sgs_ctx *c, const float *params, const float 
   SGS_HIP(launch_fakequant_bwd(c, params, qstep, soft_mask, mask_mode, rate_grad, stats,
                                grad_qparams, grad_hard_mask, grad_params, grad_qstep, grad_score),
           "fakequant_prune_bwd");
+  return SGS_OK;
+}
+
+sgs_status sgs_quant_render_bwd(sgs_ctx *c, const float *params, const float *qstep,
+                                const float *soft_mask, int32_t mask_mode,
+                                const float *rate_grad, const uint64_t *stats,
+                                const float *final_T, const uint32_t *last,
+                                const float *dL_dimage, float *grad_params, float *grad_qstep,
+                                float *grad_score, float *grad_hard_mask) {
+  if (!c) return SGS_EINVAL;
+  if (!c->rendered) return fail(c, SGS_ESTATE, "quant_render_bwd: render forward first");
+  if (!params || !qstep || !final_T || !last || !dL_dimage || !grad_params || !grad_qstep ||
+      !grad_score || !grad_hard_mask)
+    return fail(c, SGS_EINVAL, "quant_render_bwd: null pointer");
+  if ((rate_grad == nullptr) != (stats == nullptr))
+    return fail(c, SGS_EINVAL, "quant_render_bwd: rate_grad and stats go together");
+  if (mask_mode < 0 || mask_mode > 2) return fail(c, SGS_EINVAL, "quant_render_bwd: mask_mode");
+  if (mask_mode == 1 && !soft_mask)
+    return fail(c, SGS_EINVAL, "quant_render_bwd: soft_mask needed in mask mode 1");
+  if (params == grad_params)
+    return fail(c, SGS_EINVAL, "quant_render_bwd: grad_params must not alias params");
+  double *partial = c->red_tmp;
+  int64_t nb = 0;
+  SGS_HIP(launch_blend_bwd(c, final_T, last, dL_dimage), "quant_render_bwd blend");
+  SGS_HIP(launch_preprocess_bwd_fused(c, params, qstep, mask_mode, soft_mask, rate_grad,
+                                      grad_params, grad_hard_mask, grad_score, partial, &nb),
+          "quant_render_bwd project");
+  SGS_HIP(launch_quant_bwd_finish(c, nb, partial, nb, 1, qstep, rate_grad, stats, grad_params,
+                                  grad_qstep),
+          "quant_render_bwd step sizes");
   return SGS_OK;
 }
 

@@ -7,6 +7,77 @@
 namespace {
 
 constexpr int kPThreads = 128;
+constexpr int kPWaves = kPThreads / 64;
+
+// The step sizes of the fused paths, once per block: q_j and rq_j = 1 / q_j
+// (correctly rounded), rq_j NaN where it is not a normal float, so that the
+// product test of sgs_rint_div fails there and the division decides.
+__device__ __forceinline__ void load_quant_table(const float *__restrict__ q, float *s_q,
+                                                 float *s_rq) {
+  if (threadIdx.x < SGS_NCH) {
+    const float qj = q[threadIdx.x];
+    const float rq = __fdiv_rn(1.0f, qj);
+    s_q[threadIdx.x] = qj;
+    s_rq[threadIdx.x] = sgs_rq_ok(rq) ? rq : __int_as_float(0x7FC00000);
+  }
+  __syncthreads();
+}
+
+// Codes k_j = rint(fl32(v_j / q_j)) of one Gaussian's 59 raw values, decided
+// from the products v_j rq_j (sgs_rint_div's rule; rq_j NaN sends channel j to
+// the division), with the divisions, needed only near a tie, in one branch
+// after all 59 products, so that the row's loads stay batched ahead of it.
+__device__ __forceinline__ void quantize_row(const float (&v)[SGS_NCH], const float *s_q,
+                                             const float *s_rq, float (&k)[SGS_NCH]) {
+  bool slow = false;
+#pragma unroll
+  for (int j = 0; j < SGS_NCH; ++j) {
+    const float t = v[j] * s_rq[j];
+    k[j] = rintf(t);
+    slow |= !sgs_product_decides(t, k[j]);
+  }
+  if (slow) {
+#pragma unroll
+    for (int j = 0; j < SGS_NCH; ++j)
+      if (!sgs_product_decides(v[j] * s_rq[j], k[j])) k[j] = rintf(__fdiv_rn(v[j], s_q[j]));
+  }
+}
+
+// Wave sums of 16 slots held by every lane, returned in lane L for slot
+// L & 15: four exchange steps, each lane keeping the half of its slots that
+// its lane bit selects and adding its partner's copy of that half (a
+// transposing butterfly: 15 exchanges instead of 16 x 6), then two steps
+// across the four 16-lane quarters.  The order of the additions is fixed.
+// The slots are vector values, not an array: selecting between two array
+// elements by a lane bit would be turned into a per-lane array index (a
+// compare-and-select over every element).
+typedef double sgs_d16 __attribute__((ext_vector_type(16)));
+typedef double sgs_d8 __attribute__((ext_vector_type(8)));
+typedef double sgs_d4 __attribute__((ext_vector_type(4)));
+typedef double sgs_d2 __attribute__((ext_vector_type(2)));
+
+template <typename H, int N>
+__device__ __forceinline__ H exchange_half(H lo, H hi, int m) {
+  const bool up = (threadIdx.x & m) != 0;
+  const H send = up ? lo : hi;
+  const H keep = up ? hi : lo;
+  H r;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r[k] = __shfl_xor(send[k], m, 64);
+  return keep + r;
+}
+
+__device__ __forceinline__ double wave_transpose_sum16(sgs_d16 a) {
+  const sgs_d8 b = exchange_half<sgs_d8, 8>(a.lo, a.hi, 8);
+  const sgs_d4 c = exchange_half<sgs_d4, 4>(b.lo, b.hi, 4);
+  const sgs_d2 d = exchange_half<sgs_d2, 2>(c.lo, c.hi, 2);
+  const bool up = (threadIdx.x & 1) != 0;
+  const double send = up ? d.x : d.y;
+  const double keep = up ? d.y : d.x;
+  const double e = keep + __shfl_xor(send, 1, 64);
+  const double h = e + __shfl_xor(e, 16, 64);
+  return h + __shfl_xor(h, 32, 64);
+}
 
 __device__ __forceinline__ void load_cam(const sgs_camera *cams, int v, SgsCam &cam) {
   const float *src = (const float *)(cams + v);
@@ -40,18 +111,30 @@ __device__ __forceinline__ void colour(const float *y, const SgsCam &cam, float 
   }
 }
 
+// QUANT: qp holds the raw rows and the kernel applies the quantizer itself
+// (y_hat = rint(fl32(y / q)) q in FP32, the value the quantizer pass writes),
+// so the quantized rows never cross HBM.
+template <bool QUANT>
 __global__ void __launch_bounds__(kPThreads)
 k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
              const sgs_camera *__restrict__ cams, const float *__restrict__ qp,
-             const uint8_t *__restrict__ hard, float4 *__restrict__ rec,
-             uint32_t *__restrict__ depth_key, uint32_t *__restrict__ depth_val,
-             uint32_t *__restrict__ touched, uint4 *__restrict__ bins, int GW,
-             int64_t tiles_per_view) {
+             const float *__restrict__ q, const uint8_t *__restrict__ hard,
+             float4 *__restrict__ rec, uint32_t *__restrict__ depth_key,
+             uint32_t *__restrict__ depth_val, uint32_t *__restrict__ touched,
+             uint4 *__restrict__ bins, int GW, int64_t tiles_per_view) {
+  __shared__ float s_q[QUANT ? 64 : 1], s_rq[QUANT ? 64 : 1];
+  if (QUANT) load_quant_table(q, s_q, s_rq);
   const int64_t i = (int64_t)blockIdx.x * kPThreads + threadIdx.x;
   if (i >= n) return;
   float y[SGS_NCH];
 #pragma unroll
   for (int j = 0; j < SGS_NCH; ++j) y[j] = qp[j * npad + i];
+  if (QUANT) {
+    float k[SGS_NCH];
+    quantize_row(y, s_q, s_rq, k);
+#pragma unroll
+    for (int j = 0; j < SGS_NCH; ++j) y[j] = k[j] * s_q[j];
+  }
   const float m = hard[i] ? 1.0f : 0.0f;
   const float opa = 1.0f / (1.0f + __expf(-y[SGS_CH_OPA]));
   for (int v = 0; v < V; ++v) {
@@ -90,22 +173,53 @@ k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
 
 // Chain rule from the per-view splat gradients (px, py, A, B, C, opacity,
 // r, g, b, mask) to the 59 channels, summed over views.
+//
+// FUSED: qp holds the raw rows; the kernel quantizes them as k_preprocess<true>
+// does and also takes the quantizer's backward (Sec. 3.3.1, straight-through):
+// the channel gradient it writes is the parameter gradient, and each block
+// writes, per channel j, the FP64 sum over its Gaussians of g_ij (k_ij q_j -
+// y_ij) (the learned-step gradient before the division by q_j; the residual
+// is one fused multiply-add, exact, and its product with g exact in FP64) to
+// partial[j * gridDim.x + block]; with gscore it also writes the score
+// gradient (mask mode 1: (g_mask + rate term) s (1 - s) / tau, else 0).
+template <bool FUSED>
 __global__ void __launch_bounds__(kPThreads)
 k_preprocess_bwd(int64_t n, int64_t npad, int V, int W, int H,
                  const sgs_camera *__restrict__ cams, const float *__restrict__ qp,
-                 const uint32_t *__restrict__ touched, const double *__restrict__ sgrad,
-                 float *__restrict__ gout, float *__restrict__ gmask) {
+                 const float *__restrict__ q, const uint32_t *__restrict__ touched,
+                 const double *__restrict__ sgrad, float *__restrict__ gout,
+                 float *__restrict__ gmask, double *__restrict__ partial, int mode, float tau,
+                 const float *__restrict__ soft, const float *__restrict__ rate_grad,
+                 float *__restrict__ gscore) {
+  __shared__ float s_q[FUSED ? 64 : 1], s_rq[FUSED ? 64 : 1];
+  // residuals k q - y of the block's Gaussians, kept for the end
+  __shared__ float s_r[FUSED ? SGS_NCH : 1][kPThreads];
+  __shared__ double s_part[FUSED ? kPWaves : 1][64];
+  if (FUSED) load_quant_table(q, s_q, s_rq);
   const int64_t i = (int64_t)blockIdx.x * kPThreads + threadIdx.x;
-  if (i >= n) return;
+  const bool live = i < n;
+  if (!FUSED && !live) return;
   float y[SGS_NCH], g[SGS_NCH];
+  const int64_t il = live ? i : 0;  // lanes past n load row entry 0, then drop it
 #pragma unroll
   for (int j = 0; j < SGS_NCH; ++j) {
-    y[j] = qp[j * npad + i];
+    const float v = qp[j * npad + il];
+    y[j] = live ? v : 0.0f;
     g[j] = 0.0f;
+  }
+  if (FUSED) {
+    float k[SGS_NCH];
+    quantize_row(y, s_q, s_rq, k);
+#pragma unroll
+    for (int j = 0; j < SGS_NCH; ++j) {
+      s_r[j][threadIdx.x] = fmaf(k[j], s_q[j], -y[j]);
+      y[j] = k[j] * s_q[j];
+    }
   }
   float gm = 0.0f;
   const float opa = 1.0f / (1.0f + __expf(-y[SGS_CH_OPA]));
-  for (int v = 0; v < V; ++v) {
+  const int nv = live ? V : 0;
+  for (int v = 0; v < nv; ++v) {
     const int64_t s = (int64_t)v * n + i;
     if (touched[s] == 0) continue;
     const double2 *gs = (const double2 *)(sgrad + s * SGS_SGRAD);
@@ -248,26 +362,84 @@ k_preprocess_bwd(int64_t n, int64_t npad, int V, int W, int H,
 #pragma unroll
     for (int k = 0; k < 3; ++k) g[k] += cam.R[k] * gtx + cam.R[3 + k] * gty + cam.R[6 + k] * gtz;
   }
+  if (live) {
 #pragma unroll
-  for (int j = 0; j < SGS_NCH; ++j) gout[j * npad + i] = g[j];
-  gmask[i] = gm;
+    for (int j = 0; j < SGS_NCH; ++j) gout[j * npad + i] = g[j];
+    gmask[i] = gm;
+    if (FUSED && gscore) {
+      float gs = 0.0f;
+      if (mode == 1) {
+        const float gg = gm + (rate_grad ? rate_grad[192] : 0.0f);
+        const float sm = soft[i];
+        gs = gg * sm * (1.0f - sm) / tau;
+      }
+      gscore[i] = gs;
+    }
+  }
+  if (FUSED) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // four groups of 16 channels (16 double slots each keep the registers
+    // within budget)
+#pragma unroll
+    for (int grp = 0; grp < 4; ++grp) {
+      sgs_d16 a;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int j = 16 * grp + k;
+        a[k] = j < SGS_NCH ? (double)g[j] * (double)s_r[j][threadIdx.x] : 0.0;
+      }
+      const double t = wave_transpose_sum16(a);
+      if (lane < 16) s_part[wave][16 * grp + lane] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < SGS_NCH) {
+      double t = s_part[0][threadIdx.x];
+#pragma unroll
+      for (int w = 1; w < kPWaves; ++w) t += s_part[w][threadIdx.x];
+      partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+    }
+  }
 }
 
 }  // namespace
 
-hipError_t launch_preprocess(sgs_ctx *c, const float *qparams, const uint8_t *hard) {
+int64_t proj_partial_doubles(int64_t n) { return (int64_t)SGS_NCH * sgs_blocks(n, kPThreads); }
+
+hipError_t launch_preprocess(sgs_ctx *c, const float *qparams, const uint8_t *hard,
+                             const float *q) {
   SgsProfScope ps(c, SGS_PROF_PREPROCESS);
-  k_preprocess<<<sgs_blocks(c->n, kPThreads), kPThreads, 0, c->stream>>>(
-      c->n, c->npad, c->V, c->W, c->H, c->TW, c->TH, c->d_cams, qparams, hard, c->rec,
-      c->depth_key[0], c->depth_val[0], c->touched, c->bin_splat, c->GW, c->tiles_per_view);
+  const int64_t nb = sgs_blocks(c->n, kPThreads);
+  if (q)
+    k_preprocess<true><<<nb, kPThreads, 0, c->stream>>>(
+        c->n, c->npad, c->V, c->W, c->H, c->TW, c->TH, c->d_cams, qparams, q, hard, c->rec,
+        c->depth_key[0], c->depth_val[0], c->touched, c->bin_splat, c->GW, c->tiles_per_view);
+  else
+    k_preprocess<false><<<nb, kPThreads, 0, c->stream>>>(
+        c->n, c->npad, c->V, c->W, c->H, c->TW, c->TH, c->d_cams, qparams, nullptr, hard,
+        c->rec, c->depth_key[0], c->depth_val[0], c->touched, c->bin_splat, c->GW,
+        c->tiles_per_view);
   return hipGetLastError();
 }
 
 hipError_t launch_preprocess_bwd(sgs_ctx *c, const float *qparams, float *grad_qparams,
                                  float *grad_mask) {
   SgsProfScope ps(c, SGS_PROF_PREPROCESS_BWD);
-  k_preprocess_bwd<<<sgs_blocks(c->n, kPThreads), kPThreads, 0, c->stream>>>(
-      c->n, c->npad, c->V, c->W, c->H, c->d_cams, qparams, c->touched, c->splat_grad,
-      grad_qparams, grad_mask);
+  k_preprocess_bwd<false><<<sgs_blocks(c->n, kPThreads), kPThreads, 0, c->stream>>>(
+      c->n, c->npad, c->V, c->W, c->H, c->d_cams, qparams, nullptr, c->touched, c->splat_grad,
+      grad_qparams, grad_mask, nullptr, 0, 1.0f, nullptr, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_bwd_fused(sgs_ctx *c, const float *params, const float *q,
+                                       int mode, const float *soft, const float *rate_grad,
+                                       float *grad_params, float *grad_mask, float *grad_score,
+                                       double *partial, int64_t *nblocks) {
+  SgsProfScope ps(c, SGS_PROF_PREPROCESS_BWD);
+  const int64_t nb = sgs_blocks(c->n, kPThreads);
+  if (proj_partial_doubles(c->n) > c->red_tmp_words) return hipErrorInvalidValue;
+  *nblocks = nb;
+  k_preprocess_bwd<true><<<nb, kPThreads, 0, c->stream>>>(
+      c->n, c->npad, c->V, c->W, c->H, c->d_cams, params, q, c->touched, c->splat_grad,
+      grad_params, grad_mask, partial, mode, c->tau, soft, rate_grad, grad_score);
   return hipGetLastError();
 }

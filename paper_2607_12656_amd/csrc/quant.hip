@@ -35,8 +35,11 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
   return v;
 }
 
-// Pass 1, block (chunk, j) for j < 59: qparams of row j and the row's range
-// keys over the chunk; block (chunk, 59): hard/soft mask and kept count.
+// Pass 1, block (chunk, j) for j < 59: qparams of row j (WRITE) and the row's
+// range keys over the chunk; block (chunk, 59): hard/soft mask and kept count.
+// Without WRITE the pass reads the rows for their statistics only (the fused
+// path quantizes inside the projection).
+template <bool WRITE>
 __global__ void __launch_bounds__(kQThreads)
 k_fakequant_prune(int64_t n, int64_t npad, const float *__restrict__ params,
                   const float *__restrict__ q, const float *__restrict__ score, int mode,
@@ -52,7 +55,7 @@ k_fakequant_prune(int64_t n, int64_t npad, const float *__restrict__ params,
   if (j < SGS_NCH) {
     const float qj = q[j];
     const float *row = params + j * npad;
-    float *orow = qparams + j * npad;
+    float *orow = WRITE ? qparams + j * npad : nullptr;
     uint64_t kmin = ~0ull, kmax = 0ull;
 #pragma unroll
     for (int r = 0; r < kRVec; ++r) {
@@ -64,7 +67,7 @@ k_fakequant_prune(int64_t n, int64_t npad, const float *__restrict__ params,
         float o[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          o[e] = rintf(__fdiv_rn(yv[e], qj)) * qj;
+          if (WRITE) o[e] = rintf(__fdiv_rn(yv[e], qj)) * qj;
           if (i + e < n) {
             const uint64_t ok = (uint64_t)sgs_ord(yv[e]) << 32;
             const uint64_t a = ok | (uint64_t)(uint32_t)(i + e);
@@ -73,12 +76,14 @@ k_fakequant_prune(int64_t n, int64_t npad, const float *__restrict__ params,
             kmax = b > kmax ? b : kmax;
           }
         }
-        if (i + 3 < n) {
-          *reinterpret_cast<float4 *>(orow + i) = make_float4(o[0], o[1], o[2], o[3]);
-        } else {
+        if (WRITE) {
+          if (i + 3 < n) {
+            *reinterpret_cast<float4 *>(orow + i) = make_float4(o[0], o[1], o[2], o[3]);
+          } else {
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (i + e < n) orow[i + e] = o[e];
+            for (int e = 0; e < 4; ++e)
+              if (i + e < n) orow[i + e] = o[e];
+          }
         }
       }
     }
@@ -285,18 +290,19 @@ k_fakequant_bwd(int64_t n, int64_t npad, const float *__restrict__ params,
   }
 }
 
-// Backward pass 2: block j sums channel j's partials (fixed order per
-// thread, then a tree), divides by q_j, adds the rate proxy's step gradient
-// and scatters its parameter gradient at argmax_j / argmin_j.
+// Backward pass 2: block j sums channel j's partials (partial[j * jstride +
+// b * bstride], fixed order per thread, then a tree), divides by q_j, adds the
+// rate proxy's step gradient and scatters its parameter gradient at
+// argmax_j / argmin_j.
 __global__ void __launch_bounds__(kQThreads)
-k_fakequant_bwd_finish(int nblocks, const double *__restrict__ partial,
-                       const float *__restrict__ q, const float *__restrict__ rate_grad,
-                       const uint64_t *__restrict__ stats, int64_t npad,
-                       float *__restrict__ gparams, float *__restrict__ gqstep) {
+k_fakequant_bwd_finish(int64_t nblocks, const double *__restrict__ partial, int64_t jstride,
+                       int64_t bstride, const float *__restrict__ q,
+                       const float *__restrict__ rate_grad, const uint64_t *__restrict__ stats,
+                       int64_t npad, float *__restrict__ gparams, float *__restrict__ gqstep) {
   __shared__ double s_w[kQWaves];
   const int j = blockIdx.x;
   double t = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += kQThreads) t += partial[(int64_t)b * SGS_NCH + j];
+  for (int64_t b = threadIdx.x; b < nblocks; b += kQThreads) t += partial[j * jstride + b * bstride];
   t = sgs_wave_sum_d(t);
   if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = t;
   __syncthreads();
@@ -343,8 +349,14 @@ hipError_t launch_fakequant_prune(sgs_ctx *c, const float *params, const float *
   const int nb = (int)((c->n + kRPer - 1) / kRPer);
   if ((int64_t)nb * kPartWords > c->red_tmp_words) return hipErrorInvalidValue;
   uint64_t *part = (uint64_t *)c->red_tmp;
-  k_fakequant_prune<<<dim3(nb, SGS_NCH + 1), kQThreads, 0, c->stream>>>(
-      c->n, c->npad, params, q, score, mode, given, seed, step, c->tau, qparams, hard, soft, part);
+  if (qparams)
+    k_fakequant_prune<true><<<dim3(nb, SGS_NCH + 1), kQThreads, 0, c->stream>>>(
+        c->n, c->npad, params, q, score, mode, given, seed, step, c->tau, qparams, hard, soft,
+        part);
+  else
+    k_fakequant_prune<false><<<dim3(nb, SGS_NCH + 1), kQThreads, 0, c->stream>>>(
+        c->n, c->npad, params, q, score, mode, given, seed, step, c->tau, nullptr, hard, soft,
+        part);
   k_stats_finish<<<SGS_NCH, kQThreads, 0, c->stream>>>(nb, part, q, stats);
   return hipGetLastError();
 }
@@ -374,9 +386,19 @@ hipError_t launch_fakequant_bwd(sgs_ctx *c, const float *params, const float *q,
   SgsProfScope ps(c, SGS_PROF_FAKEQUANT_BWD);
   k_fakequant_bwd<<<dim3(nb, SGS_NCH), kQThreads, 0, c->stream>>>(c->n, c->npad, params, q,
                                                                   gq_in, gparams, c->red_tmp);
-  k_fakequant_bwd_finish<<<SGS_NCH, kQThreads, 0, c->stream>>>(nb, c->red_tmp, q, rate_grad,
-                                                               stats, c->npad, gparams, gqstep);
+  k_fakequant_bwd_finish<<<SGS_NCH, kQThreads, 0, c->stream>>>(
+      nb, c->red_tmp, 1, SGS_NCH, q, rate_grad, stats, c->npad, gparams, gqstep);
   k_score_bwd<<<sgs_blocks(c->n, 256), 256, 0, c->stream>>>(c->n, mode, c->tau, soft, gmask_in,
                                                             rate_grad, gscore);
+  return hipGetLastError();
+}
+
+hipError_t launch_quant_bwd_finish(sgs_ctx *c, int64_t nblocks, const double *partial,
+                                   int64_t jstride, int64_t bstride, const float *q,
+                                   const float *rate_grad, const uint64_t *stats,
+                                   float *gparams, float *gqstep) {
+  SgsProfScope ps(c, SGS_PROF_FAKEQUANT_BWD);
+  k_fakequant_bwd_finish<<<SGS_NCH, kQThreads, 0, c->stream>>>(
+      nblocks, partial, jstride, bstride, q, rate_grad, stats, c->npad, gparams, gqstep);
   return hipGetLastError();
 }

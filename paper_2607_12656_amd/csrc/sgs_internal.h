@@ -145,10 +145,26 @@ hipError_t launch_fakequant_bwd(sgs_ctx *c, const float *params, const float *q,
                                 const uint64_t *stats, const float *gq_in,
                                 const float *gmask_in, float *gparams, float *gqstep,
                                 float *gscore);
+// Finish of the step-size gradient over block partials partial[j * jstride +
+// b * bstride], b < nblocks, with the rate proxy's gradients (rate_grad and
+// stats both given, or both null).
+hipError_t launch_quant_bwd_finish(sgs_ctx *c, int64_t nblocks, const double *partial,
+                                   int64_t jstride, int64_t bstride, const float *q,
+                                   const float *rate_grad, const uint64_t *stats,
+                                   float *gparams, float *gqstep);
 // project.hip
-hipError_t launch_preprocess(sgs_ctx *c, const float *qparams, const uint8_t *hard);
+// q non-null: qparams holds the raw rows, quantized inside the projection.
+hipError_t launch_preprocess(sgs_ctx *c, const float *qparams, const uint8_t *hard,
+                             const float *q = nullptr);
 hipError_t launch_preprocess_bwd(sgs_ctx *c, const float *qparams, float *grad_qparams,
                                  float *grad_mask);
+// Projection backward fused with the quantizer/mask backward over the raw
+// rows; the step-size partials go to partial[j * (*nblocks) + b].
+hipError_t launch_preprocess_bwd_fused(sgs_ctx *c, const float *params, const float *q,
+                                       int mode, const float *soft, const float *rate_grad,
+                                       float *grad_params, float *grad_mask, float *grad_score,
+                                       double *partial, int64_t *nblocks);
+int64_t proj_partial_doubles(int64_t n);  // FP64 scratch words of the fused backward
 // sort.hip
 hipError_t ensure_tmp(sgs_ctx *c, int64_t scan_words, int64_t hist_words);
 // Pair total reported when the true total does not fit in 32 bits (the
@@ -307,10 +323,14 @@ __device__ __forceinline__ int32_t sgs_code_of(float y, float q, bool &ok) {
 // error; it is negative from |y rq| = 2^20 on, so k stays far inside int32).
 // Otherwise (near a tie, large, not finite) the division decides.  This one
 // returns rint(fl32(y / q)) as a float; sgs_code_fast below, the int32 code.
+// sgs_product_decides(t, k): whether k = rint(t), t = y rq, is that integer.
+__device__ __forceinline__ bool sgs_product_decides(float t, float k) {
+  return fabsf(t - k) < __fmaf_rn(-fabsf(t), 4.76837158203125e-7f, 0.5f);
+}
 __device__ __forceinline__ float sgs_rint_div(float y, float q, float rq, bool fast_ok) {
   const float t = y * rq;
   const float k = rintf(t);
-  if (fast_ok && fabsf(t - k) < __fmaf_rn(-fabsf(t), 4.76837158203125e-7f, 0.5f)) return k;
+  if (fast_ok && sgs_product_decides(t, k)) return k;
   return rintf(__fdiv_rn(y, q));
 }
 // Whether rq = 1 / q (correctly rounded) is a normal float, so that the
@@ -322,7 +342,7 @@ __device__ __forceinline__ bool sgs_rq_ok(float rq) {
 __device__ __forceinline__ int32_t sgs_code_fast(float y, float q, float rq, bool fast_ok, bool &ok) {
   const float t = y * rq;
   const float k = rintf(t);
-  if (fast_ok && fabsf(t - k) < __fmaf_rn(-fabsf(t), 4.76837158203125e-7f, 0.5f)) {
+  if (fast_ok && sgs_product_decides(t, k)) {
     ok = true;
     return (int32_t)k;
   }

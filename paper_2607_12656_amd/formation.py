@@ -61,8 +61,10 @@ class Formation:
         c, rd, k, mm = self.ctx, self.rd, self.k, self.mask_mode
         p, q, s = self.params, self.q, self.score
         learned = self.mlp is not None
-        c.fakequant_prune(p, q, s, mm, self.given, self.seed, k, rd.qparams, rd.hard, rd.soft,
-                          rd.stats)
+        # quantizer, mask and render in one call (the quantized rows stay in
+        # registers); the rate terms read the statistics it leaves
+        c.quant_render_fwd(p, q, s, mm, self.given, self.seed, k, rd.hard, rd.soft, rd.stats,
+                           rd.image, rd.final_T, rd.last, rd.evals if count_evals else None)
         if learned:
             packed, theta = self.mlp
             c.rate_proxy(rd.stats, q, 0.0, rd.rate3, None)      # evaluated, not followed
@@ -72,17 +74,13 @@ class Formation:
                            self.masking, self.alpha)
         else:
             c.rate_proxy(rd.stats, q, self.lam, rd.rate3, rd.rate_grad)
-        c.render_fwd(rd.qparams, rd.hard, rd.image, rd.final_T, rd.last,
-                     rd.evals if count_evals else None)
         w = self.ssim_weight
         c.l1_loss(rd.image, self.target, rd.loss, rd.dimage, 1.0 - w)
         if w > 0.0:
             c.ssim_loss(rd.image, self.target, w, rd.loss_ssim, rd.dimage)
-        c.render_bwd(rd.qparams, rd.hard, rd.final_T, rd.last, rd.dimage, rd.grad_qparams,
-                     rd.grad_mask)
-        c.fakequant_prune_bwd(p, q, rd.soft, mm, None if learned else rd.rate_grad,
-                              None if learned else rd.stats, rd.grad_qparams, rd.grad_mask,
-                              rd.grad_qparams, rd.grad_q, rd.grad_score)
+        c.quant_render_bwd(p, q, rd.soft, mm, None if learned else rd.rate_grad,
+                           None if learned else rd.stats, rd.final_T, rd.last, rd.dimage,
+                           rd.grad_qparams, rd.grad_q, rd.grad_score, rd.grad_mask)
         if learned:
             c.rate_mlp_bwd(packed, theta, p, q, rd.stats, rd.hard, rd.soft, mm, self.lam,
                            rd.grad_qparams, rd.grad_q, rd.grad_score, None)

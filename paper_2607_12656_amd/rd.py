@@ -6,6 +6,11 @@ memory) and issues the C-ABI calls in order:
     fakequant_prune -> rate_proxy -> render_fwd -> l1_loss
     -> render_bwd -> fakequant_prune_bwd
 
+or, with ``fused=True`` (the same results; the quantized rows are neither
+written nor read back):
+
+    quant_render_fwd -> rate_proxy -> l1_loss -> quant_render_bwd
+
 Every arithmetic step runs in libspeedygs's HIP kernels; nothing here
 computes.  The loss is D_render + lam * R_proxy (paper Sec. 3.3.2, total loss).
 D_render is the L1 distortion, or with ``ssim_weight`` = w > 0 vanilla
@@ -22,10 +27,11 @@ from ._lib import NCH, RATE_GRAD_FLOATS, STATS_WORDS, Context
 class RDStep:
     def __init__(self, ctx: Context, n: int, npad: int, n_hat: int, cams: np.ndarray,
                  width: int, height: int, tile=(16, 16), tau: float = 1.0,
-                 schedule: str = "tile"):
+                 schedule: str = "tile", fused: bool = False):
         import torch
         self.torch = torch
         self.ctx = ctx
+        self.fused = fused
         dev = torch.device("cuda", ctx.device)
         self.dev = dev
         V = cams.shape[0]
@@ -57,11 +63,17 @@ class RDStep:
                 given_mask=None, seed: int = 0, step: int = 0, count_evals: bool = True,
                 loss_scale: float = 1.0, ssim_weight: float = 0.0):
         c = self.ctx
-        c.fakequant_prune(params, qstep, score, mask_mode, given_mask, seed, step, self.qparams,
-                          self.hard, self.soft, self.stats)
-        c.rate_proxy(self.stats, qstep, lam, self.rate3, self.rate_grad)
-        c.render_fwd(self.qparams, self.hard, self.image, self.final_T, self.last,
-                     self.evals if count_evals else None)
+        ev = self.evals if count_evals else None
+        if self.fused:
+            c.quant_render_fwd(params, qstep, score, mask_mode, given_mask, seed, step,
+                               self.hard, self.soft, self.stats, self.image, self.final_T,
+                               self.last, ev)
+            c.rate_proxy(self.stats, qstep, lam, self.rate3, self.rate_grad)
+        else:
+            c.fakequant_prune(params, qstep, score, mask_mode, given_mask, seed, step,
+                              self.qparams, self.hard, self.soft, self.stats)
+            c.rate_proxy(self.stats, qstep, lam, self.rate3, self.rate_grad)
+            c.render_fwd(self.qparams, self.hard, self.image, self.final_T, self.last, ev)
         c.l1_loss(self.image, target, self.loss, self.dimage, loss_scale * (1.0 - ssim_weight))
         if ssim_weight > 0.0:
             c.ssim_loss(self.image, target, loss_scale * ssim_weight, self.loss_ssim, self.dimage)
@@ -71,6 +83,12 @@ class RDStep:
         reuse of the render gradient buffer (straight-through aliasing)."""
         c = self.ctx
         gp = self.grad_qparams if grad_params is None else grad_params
+        if self.fused:
+            c.quant_render_bwd(params, qstep, self.soft, mask_mode, self.rate_grad, self.stats,
+                               self.final_T, self.last,
+                               self.dimage if dimage is None else dimage, gp, self.grad_q,
+                               self.grad_score, self.grad_mask)
+            return gp
         c.render_bwd(self.qparams, self.hard, self.final_T, self.last,
                      self.dimage if dimage is None else dimage, self.grad_qparams,
                      self.grad_mask)

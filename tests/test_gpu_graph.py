@@ -90,12 +90,14 @@ def test_capacity_overflow_is_reported(dev):
     assert np.array_equal(got["image"], ref["image"])
 
 
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
-def test_graph_replays_match_eager(dev, tile):
+def test_graph_replays_match_eager(dev, tile, fused):
     sc = synth.make_scene("c1")
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         ctx, rd, ins = _setup(dev, sc, stream, tile=tile)
+        rd.fused = fused
         gp = torch.empty_like(ins["params"])
         _step(rd, ins, gp=gp)
         P, _ = ctx.query()

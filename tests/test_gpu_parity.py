@@ -62,15 +62,18 @@ def grad_close(g, ref, tol=1e-3, name=""):
 
 
 def run_pair(orc, gctx, dev, sc, tile=(16, 16), lam=0.5, mode=0, seed=0, step=0,
-             schedule="tile"):
+             schedule="tile", fused=False):
     """GPU step and oracle step on the same inputs.  Both backward passes get
     the same dL/dimage: the GPU's L1 gradient with the oracle's margin pixels
     zeroed, so no gradient depends on a decision FP32 and FP64 may take
-    differently at a kink (alpha clamp, alpha cut-off, termination)."""
+    differently at a kink (alpha clamp, alpha cut-off, termination).
+    fused: the GPU step runs quant_render_fwd / quant_render_bwd (the quantized
+    rows and their gradient are then not materialized)."""
     from paper_2607_12656_amd.rd import RDStep
-    _say(f"[gpu] {sc.name} tile={tile} schedule={schedule} mode={mode} n={sc.n} V={sc.views}")
+    _say(f"[gpu] {sc.name} tile={tile} schedule={schedule} mode={mode} n={sc.n} V={sc.views}"
+         f" fused={fused}")
     rd = RDStep(gctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height, tile=tile,
-                schedule=schedule)
+                schedule=schedule, fused=fused)
     params, q, score = T(sc.params, dev), T(sc.qstep, dev), T(sc.score, dev)
     mask, target = T(sc.given_mask, dev), T(sc.target, dev)
     rd.forward(params, q, score, target, lam, mode, mask, seed, step)
@@ -105,11 +108,12 @@ def gpu_backward(gctx, dev, sc, rd, params, q, mode, tile, dimage):
     gctx.copy_splat_grads(sgrad)
     torch.cuda.synchronize()
     c = lambda x: x.cpu().numpy()
-    out.update(qparams=c(rd.qparams), hard=c(rd.hard), soft=c(rd.soft),
+    out.update(qparams=None if rd.fused else c(rd.qparams), hard=c(rd.hard), soft=c(rd.soft),
                stats=c(rd.stats).view(np.uint64), rate3=c(rd.rate3), rate_grad=c(rd.rate_grad),
                image=c(rd.image), T=c(rd.final_T), last=c(rd.last).view(np.uint32),
                evals=int(c(rd.evals)[0]), loss=float(c(rd.loss)[0]), dimage=c(rd.dimage),
-               gq_render=c(rd.grad_qparams), gmask=c(rd.grad_mask), gparams=c(gp),
+               gq_render=None if rd.fused else c(rd.grad_qparams), gmask=c(rd.grad_mask),
+               gparams=c(gp),
                gq=c(rd.grad_q), gscore=c(rd.grad_score),
                tile_ids=c(tile_ids)[:P].view(np.uint32), vals=c(vals)[:P].view(np.uint32),
                ranges=c(ranges).view(np.uint32), spans=c(spans), depth=c(depth),
@@ -119,7 +123,8 @@ def gpu_backward(gctx, dev, sc, rd, params, q, mode, tile, dimage):
 
 def check_structure(g, r, sc):
     n = sc.n
-    assert np.array_equal(g["qparams"][:, :n], r["yhat"][:, :n]), "quantized parameters"
+    if g["qparams"] is not None:
+        assert np.array_equal(g["qparams"][:, :n], r["yhat"][:, :n]), "quantized parameters"
     assert np.array_equal(g["hard"], r["mhat"]), "hard mask"
     st = r["st"]
     valid = st.valid > 0
@@ -246,6 +251,51 @@ def test_gumbel_mask_mode(orc, gctx, dev):
     assert g["hard"].all()
 
 
+FUSED_CASES = [
+    dict(kind="tiny", cfg=0),
+    dict(kind="tiny", cfg=1),
+    dict(kind="tiny", cfg=2, tile=(8, 8)),
+    dict(kind="c1", lam=1.0),
+    dict(kind="gumbel", mode=1, step=7),
+    dict(kind="gumbel", mode=2),
+    dict(kind="two_views", schedule="stride", tile=(32, 8)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(FUSED_CASES)))
+def test_fused_step_matches_oracle(orc, gctx, dev, case):
+    """quant_render_fwd / quant_render_bwd (quantizer inside the projection and
+    its backward) against the oracle: structure, statistics, image and every
+    gradient, mask modes 0-2, several tile shapes and schedules."""
+    c = FUSED_CASES[case]
+    kind = c["kind"]
+    if kind == "tiny":
+        t = TINY[c["cfg"]]
+        sc = synth.make_tiny(t["n"], t["W"], t["H"], views=t["V"], seed=t["seed"],
+                             logscale_mu=t.get("logscale", -2.0))
+    elif kind == "c1":
+        sc = synth.make_scene("c1")
+    elif kind == "gumbel":
+        sc = synth.make_tiny(300, 64, 48, seed=9)
+    else:
+        sc = synth.make_tiny(400, 150, 90, views=2, seed=11)
+    mode = c.get("mode", 0)
+    g, r = run_pair(orc, gctx, dev, sc, tile=c.get("tile", (16, 16)), lam=c.get("lam", 0.5),
+                    mode=mode, seed=1234 if mode == 1 else 0, step=c.get("step", 0),
+                    schedule=c.get("schedule", "tile"), fused=True)
+    check_structure(g, r, sc)
+    check_stats(g, r, sc)
+    check_image(g, r)
+    if mode == 1:
+        assert np.allclose(g["soft"], r["msoft"], atol=2e-6)
+        grad_close(g["gscore"], r["gs"], name="grad score")
+    elif mode == 2:
+        assert g["hard"].all()
+    grad_close(g["gparams"][:, :sc.n], r["gy"][:, :sc.n], name="grad params")
+    grad_close(g["gq"], r["gq"], name="grad qstep")
+    grad_close(g["gmask"], r["gmhat"], name="grad mask")
+
+
 def test_fakequant_bwd_isolated(orc, gctx, dev):
     """Same upstream gradient on both sides: STE copy, LSQ step gradient,
     rate-gradient scatter."""
@@ -299,6 +349,21 @@ def test_full_size_1m_workload(orc, gctx, dev):
     err, frac = check_image(g, r)
     _say(f"c2: pixel err {err:.2e}, margin {frac:.2e}, P={g['P']}, E={g['evals']}")
     grad_close(g["gq_render"][:, :sc.n], r["gyhat"][:, :sc.n], name="grad qparams")
+    grad_close(g["gmask"], r["gmhat"], name="grad mask")
+    grad_close(g["gq"], r["gq"], name="grad qstep")
+
+
+def test_full_size_1m_workload_fused(orc, gctx, dev):
+    """The benchmark's step (fused entry points, stride schedule, 16x16 tiles)
+    at 1M Gaussians, 1297x840: every pair, pixel and gradient against the
+    oracle."""
+    sc = synth.make_scene("c2")
+    g, r = run_pair(orc, gctx, dev, sc, lam=2.5e-5, schedule="stride", fused=True)
+    check_structure(g, r, sc)
+    check_stats(g, r, sc)
+    err, frac = check_image(g, r)
+    _say(f"c2 fused: pixel err {err:.2e}, margin {frac:.2e}, P={g['P']}, E={g['evals']}")
+    grad_close(g["gparams"][:, :sc.n], r["gy"][:, :sc.n], name="grad params")
     grad_close(g["gmask"], r["gmhat"], name="grad mask")
     grad_close(g["gq"], r["gq"], name="grad qstep")
 
