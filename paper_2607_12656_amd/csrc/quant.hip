@@ -54,20 +54,29 @@ k_fakequant_prune(int64_t n, int64_t npad, const float *__restrict__ params,
   uint64_t *dst = part + chunk * kPartWords;
   if (j < SGS_NCH) {
     const float qj = q[j];
+    const float rq = __fdiv_rn(1.0f, qj);
+    const bool fast_ok = sgs_rq_ok(rq);
     const float *row = params + j * npad;
     float *orow = WRITE ? qparams + j * npad : nullptr;
     uint64_t kmin = ~0ull, kmax = 0ull;
+    // all loads first (i + 3 < npad for i < n, npad % 64 == 0: a 16-byte load
+    // stays in the row; lanes past n load the row's first entries and drop them)
+    float4 y4[kRVec];
+#pragma unroll
+    for (int r = 0; r < kRVec; ++r) {
+      const int64_t i = c0 + ((int64_t)r * kQThreads + threadIdx.x) * 4;
+      y4[r] = *reinterpret_cast<const float4 *>(row + (i < n ? i : 0));
+    }
 #pragma unroll
     for (int r = 0; r < kRVec; ++r) {
       const int64_t i = c0 + ((int64_t)r * kQThreads + threadIdx.x) * 4;
       if (i < n) {
-        // i + 3 < npad (npad % 64 == 0): the 16-byte load stays in the row
-        const float4 y = *reinterpret_cast<const float4 *>(row + i);
+        const float4 y = y4[r];
         const float yv[4] = {y.x, y.y, y.z, y.w};
         float o[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          if (WRITE) o[e] = rintf(__fdiv_rn(yv[e], qj)) * qj;
+          if (WRITE) o[e] = sgs_rint_div(yv[e], qj, rq, fast_ok) * qj;  // rint(fl32(y / q)) q
           if (i + e < n) {
             const uint64_t ok = (uint64_t)sgs_ord(yv[e]) << 32;
             const uint64_t a = ok | (uint64_t)(uint32_t)(i + e);
@@ -106,29 +115,47 @@ k_fakequant_prune(int64_t n, int64_t npad, const float *__restrict__ params,
     }
     return;
   }
-  uint32_t kept = 0;
-  for (int r = 0; r < kRVec * 4; ++r) {
-    const int64_t i = c0 + (int64_t)r * kQThreads + threadIdx.x;
-    if (i >= n) break;
-    uint8_t m;
-    float sm;
-    if (mode == 0) {
-      m = given[i] ? 1 : 0;
-      sm = (float)m;
-    } else if (mode == 2) {
-      m = 1;
-      sm = 1.0f;
-    } else {
-      const float u = sgs_uniform(seed, step, (uint64_t)i);
-      const float sc = score[i];
-      const float e = sgs_exp_repro(sc);
-      m = (u * (1.0f + e)) > 1.0f ? 1 : 0;
-      const float l = logf(u) - logf(1.0f - u);
-      sm = 1.0f / (1.0f + __expf(-(sc + l) / tau));
+  // the mode is uniform: one branch, then all loads of the given mask or the
+  // scores issued together (lanes past n load entry n - 1 and store nothing)
+  constexpr int kM = kRVec * 4;
+  uint8_t mv[kM];
+  float sv[kM];
+  if (mode == 0) {
+#pragma unroll
+    for (int r = 0; r < kM; ++r) {
+      const int64_t i = c0 + (int64_t)r * kQThreads + threadIdx.x;
+      mv[r] = given[i < n ? i : n - 1] ? 1 : 0;
     }
-    hard[i] = m;
-    if (soft) soft[i] = sm;
-    kept += m;
+#pragma unroll
+    for (int r = 0; r < kM; ++r) sv[r] = (float)mv[r];
+  } else if (mode == 2) {
+#pragma unroll
+    for (int r = 0; r < kM; ++r) {
+      mv[r] = 1;
+      sv[r] = 1.0f;
+    }
+  } else {
+    float sc[kM];
+#pragma unroll
+    for (int r = 0; r < kM; ++r) {
+      const int64_t i = c0 + (int64_t)r * kQThreads + threadIdx.x;
+      sc[r] = score[i < n ? i : n - 1];
+    }
+#pragma unroll
+    for (int r = 0; r < kM; ++r) {
+      const int64_t i = c0 + (int64_t)r * kQThreads + threadIdx.x;
+      mv[r] = sgs_gumbel_decide(sc[r], sgs_uniform(seed, step, (uint64_t)i), tau, sv[r]);
+    }
+  }
+  uint32_t kept = 0;
+#pragma unroll
+  for (int r = 0; r < kM; ++r) {
+    const int64_t i = c0 + (int64_t)r * kQThreads + threadIdx.x;
+    if (i < n) {
+      hard[i] = mv[r];
+      if (soft) soft[i] = sv[r];
+      kept += mv[r];
+    }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) kept += __shfl_xor(kept, off, 64);

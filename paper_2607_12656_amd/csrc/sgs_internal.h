@@ -276,6 +276,37 @@ __device__ __forceinline__ float sgs_exp_repro(float x) {
   return ldexpf(p, (int)n);
 }
 
+// Gumbel-sigmoid retention of a Gaussian with score sc and uniform draw u:
+// hard = [u (1 + e^sc) > 1] (= [sc + logit u > 0]), sm = sigmoid((sc + logit
+// u) / tau).
+__device__ __forceinline__ uint8_t sgs_gumbel_decide(float sc, float u, float tau, float &sm) {
+  const float e = sgs_exp_repro(sc);
+  const uint8_t m = (u * (1.0f + e)) > 1.0f ? 1 : 0;
+  const float l = logf(u) - logf(1.0f - u);
+  sm = 1.0f / (1.0f + __expf(-(sc + l) / tau));
+  return m;
+}
+
+// Retention decision of Gaussian i (Sec. 3.3.1): mode 0 the given mask, 1 the
+// Gumbel-sigmoid draw (hard = [u (1 + e^s) > 1], soft = sigmoid((s + logit
+// u) / tau)), 2 keep every Gaussian.  Returns the hard mask; sm receives the
+// relaxed one (the hard one in modes 0 and 2).
+__device__ __forceinline__ uint8_t sgs_mask_decide(int mode, const uint8_t *__restrict__ given,
+                                                   const float *__restrict__ score, uint64_t seed,
+                                                   uint64_t step, float tau, int64_t i,
+                                                   float &sm) {
+  if (mode == 0) {
+    const uint8_t m = given[i] ? 1 : 0;
+    sm = (float)m;
+    return m;
+  }
+  if (mode == 2) {
+    sm = 1.0f;
+    return 1;
+  }
+  return sgs_gumbel_decide(score[i], sgs_uniform(seed, step, (uint64_t)i), tau, sm);
+}
+
 // Workgroups are dispatched to the eight XCDs round-robin (hardware id i runs
 // on XCD i % 8, each XCD with its own L2).  Logical id of hardware id i in a
 // grid of nb blocks such that every XCD takes one contiguous range of logical
