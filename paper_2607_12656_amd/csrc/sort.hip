@@ -210,6 +210,50 @@ k_hist_chunk_down(const uint32_t *__restrict__ H, int64_t nb, const uint32_t *__
   }
 }
 
+// Digit offsets for at most kColRows blocks in one launch: block d scans
+// column d of H[b][d] over b (each thread a run of consecutive rows), writing
+// O[b][d] = sum_{b' < b} H[b'][d] and total[d].  The scatter adds the
+// digit's base (the exclusive scan of the totals) itself.  Beyond kColRows
+// the column reads (one word per 1 KB row) would not stay in L2, and the
+// chunked kernels above take over.
+constexpr int64_t kColRows = 2048;
+__global__ void __launch_bounds__(kThreads)
+k_digit_cols(const uint32_t *__restrict__ H, int64_t nb, uint32_t *__restrict__ O,
+             uint32_t *__restrict__ total) {
+  __shared__ uint32_t s_wave[kWaves];
+  const int d = blockIdx.x;
+  const int64_t per = (nb + kThreads - 1) / kThreads;
+  const int64_t b0 = min(nb, (int64_t)threadIdx.x * per), b1 = min(nb, b0 + per);
+  uint32_t s = 0;
+#pragma unroll 8
+  for (int64_t b = b0; b < b1; ++b) s += H[b * 256 + d];
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan(s, s_wave, tot);
+#pragma unroll 8
+  for (int64_t b = b0; b < b1; ++b) {
+    const uint32_t v = H[b * 256 + d];
+    O[b * 256 + d] = run;
+    run += v;
+  }
+  if (threadIdx.x == 0) total[d] = tot;
+}
+
+// The scanned histogram entry of this thread's digit: with digit_tot (the
+// column path) the digit's base, the exclusive scan of the digit totals, is
+// added here; the chunked path has it included already.  Every thread of the
+// block calls this (it synchronizes).
+__device__ __forceinline__ uint32_t scanned_offset(const uint32_t *__restrict__ hist_scanned,
+                                                   const uint32_t *__restrict__ digit_tot,
+                                                   int64_t blk) {
+  __shared__ uint32_t s_wave[kWaves];
+  uint32_t h = hist_scanned[blk * 256 + threadIdx.x];
+  if (digit_tot) {
+    uint32_t tot;
+    h += block_exclusive_scan(digit_tot[threadIdx.x], s_wave, tot);
+  }
+  return h;
+}
+
 // LDS index with one pad word per 16: a thread's run of kItems consecutive
 // elements and a round of consecutive threads both spread over the banks.
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
@@ -290,7 +334,8 @@ __global__ void __launch_bounds__(kThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                 uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                 int64_t count_static, const uint32_t *__restrict__ dcount, int shift,
-                const uint32_t *__restrict__ hist_raw, const uint32_t *__restrict__ hist_scanned) {
+                const uint32_t *__restrict__ hist_raw, const uint32_t *__restrict__ hist_scanned,
+                const uint32_t *__restrict__ digit_tot) {
   constexpr int TILE = kThreads * IT;
   __shared__ uint32_t s_key[TILE];
   __shared__ uint32_t s_val[TILE];
@@ -300,7 +345,6 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
   if (base >= count) return;
   // all loads of the block in flight at once
   const uint32_t h_raw = hist_raw[blk * 256 + threadIdx.x];
-  const uint32_t h_scan = hist_scanned[blk * 256 + threadIdx.x];
   uint32_t kr[IT], vr[IT];
 #pragma unroll
   for (int r = 0; r < IT; ++r) {
@@ -308,6 +352,7 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
     kr[r] = i < count ? kin[i] : 0u;
     vr[r] = i < count ? vin[i] : 0u;
   }
+  const uint32_t h_scan = scanned_offset(hist_scanned, digit_tot, blk);
   scatter_block<IT>(kr, vr, base, count, shift, h_raw, h_scan, kout, vout, s_key, s_val);
 }
 
@@ -463,7 +508,8 @@ k_gen_scatter(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ br
               const uint32_t *__restrict__ bstart, int64_t vn, int64_t count_static,
               const uint32_t *__restrict__ dcount, int GW,
               const uint32_t *__restrict__ hist_raw, const uint32_t *__restrict__ hist_scanned,
-              uint32_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+              const uint32_t *__restrict__ digit_tot, uint32_t *__restrict__ kout,
+              uint32_t *__restrict__ vout) {
   // s_key doubles as the generator's LDS window
   __shared__ __align__(16) uint32_t s_key[kTilePad];
   __shared__ uint32_t s_val[kTilePad];
@@ -473,7 +519,7 @@ k_gen_scatter(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ br
   const int64_t base = blk * kTile;
   if (base >= count) return;
   const uint32_t h_raw = hist_raw[blk * 256 + threadIdx.x];
-  const uint32_t h_scan = hist_scanned[blk * 256 + threadIdx.x];
+  const uint32_t h_scan = scanned_offset(hist_scanned, digit_tot, blk);
   {
     uint32_t key[kItems], val[kItems];
     gen_block(offsets, brec, bstart, blk, base, count, vn, GW, s_key, key, val);
@@ -622,12 +668,18 @@ bool sort_bufs(sgs_ctx *c, int64_t count, SortBufs &b, int64_t tile = kTile) {
 }
 
 // Digit offsets of every block from the raw block histograms (raw counts kept
-// for the block-local placement).
-void launch_digit_offsets(sgs_ctx *c, const SortBufs &b) {
+// for the block-local placement).  Returns the digit totals the scatter must
+// add the digit bases of (column path), or null (chunked path: included).
+const uint32_t *launch_digit_offsets(sgs_ctx *c, const SortBufs &b) {
+  if (b.nb <= kColRows) {
+    k_digit_cols<<<256, kThreads, 0, c->stream>>>(b.hraw, b.nb, b.hscan, b.total);
+    return b.total;
+  }
   k_hist_chunk_sums<<<(unsigned)b.ng, kThreads, 0, c->stream>>>(b.hraw, b.nb, b.chunk);
   k_hist_chunk_scan<<<256, kThreads, 0, c->stream>>>(b.chunk, b.ng, b.total);
   k_hist_chunk_down<<<(unsigned)b.ng, kThreads, 0, c->stream>>>(b.hraw, b.nb, b.chunk, b.total,
                                                                 b.hscan);
+  return nullptr;
 }
 
 }  // namespace
@@ -650,15 +702,15 @@ hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2], i
     else
       k_radix_hist<kItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(keys[cur], count, dcount,
                                                                       shift, b.hraw);
-    launch_digit_offsets(c, b);
+    const uint32_t *dtot = launch_digit_offsets(c, b);
     if (small)
       k_radix_scatter<kSmallItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
           keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, b.hraw,
-          b.hscan);
+          b.hscan, dtot);
     else
       k_radix_scatter<kItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
           keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, b.hraw,
-          b.hscan);
+          b.hscan, dtot);
     cur ^= 1;
   }
   *which = cur;
@@ -702,9 +754,9 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
                                                                     c->blk_start);
       k_gen_hist<<<(unsigned)b.nb, kThreads, 0, c->stream>>>(c->offsets, c->bin_rec, c->blk_start,
                                                              c->vn, P, dcount, c->GW, b.hraw);
-      launch_digit_offsets(c, b);
+      const uint32_t *dtot = launch_digit_offsets(c, b);
       k_gen_scatter<<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
-          c->offsets, c->bin_rec, c->blk_start, c->vn, P, dcount, c->GW, b.hraw, b.hscan,
+          c->offsets, c->bin_rec, c->blk_start, c->vn, P, dcount, c->GW, b.hraw, b.hscan, dtot,
           c->tile_key[1], c->pair_val[1]);
     }
   }
