@@ -254,10 +254,12 @@ __device__ __forceinline__ uint32_t scanned_offset(const uint32_t *__restrict__ 
   return h;
 }
 
-// LDS index with one pad word per 16: a thread's run of kItems consecutive
-// elements and a round of consecutive threads both spread over the banks.
-__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
-constexpr int kTilePad = kTile + kTile / 16;
+// LDS index of element i of a block's tile with the low four bits XORed by
+// the next four: a thread's run of kItems (16) consecutive elements and a
+// round of consecutive threads both spread over the banks, with no pad words
+// (the pair scatter then fits four workgroups in a compute unit's LDS).
+__device__ __forceinline__ int lds_pad(int i) { return i ^ ((i >> 4) & 15); }
+constexpr int kTilePad = kTile;
 
 // Scatter of one pass for the block's elements, held in rounds (element
 // base + r*256 + tid in kr[r], vr[r]).  Ranks follow (round, wave, lane) =
@@ -397,8 +399,9 @@ __global__ void k_block_starts(const uint32_t *__restrict__ offsets, int64_t vn,
 // so no thread searches.  When the block spans at most kWin splats their
 // offsets and records are staged in LDS (`win`, 16-byte aligned, kWinWords
 // words, free again on return) and the walk reads nothing else; otherwise
-// it reads them from global memory.  Splats without pairs own no pair and
-// are passed over.
+// it reads them from global memory.  s_k (kThreads words of LDS, disjoint
+// from win, free again on return) holds each thread's first splat.  Splats
+// without pairs own no pair and are passed over.
 constexpr int kWin = 512;
 constexpr int kWinWords = 4 * kWin + kWin + 1;
 
@@ -406,9 +409,8 @@ __device__ __forceinline__ void gen_block(const uint32_t *__restrict__ offsets,
                                           const uint4 *__restrict__ brec,
                                           const uint32_t *__restrict__ bstart, int64_t blk,
                                           int64_t base, int64_t count, int64_t vn, int GW,
-                                          uint32_t *win, uint32_t (&key)[kItems],
+                                          uint32_t *win, uint32_t *s_k, uint32_t (&key)[kItems],
                                           uint32_t (&val)[kItems]) {
-  __shared__ uint32_t s_k[kThreads];
   const int64_t nb_live = (count + kTile - 1) / kTile;
   const int64_t klo = bstart[blk];
   const int64_t khi = blk + 1 < nb_live ? (int64_t)bstart[blk + 1] : vn - 1;
@@ -475,7 +477,7 @@ k_gen_hist(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ brec,
            const uint32_t *__restrict__ dcount, int GW, uint32_t *__restrict__ hist) {
   // the sub-histograms double as the generator's LDS window
   __shared__ __align__(16) uint32_t s_sub[kThreads / 8][257];
-  static_assert((kThreads / 8) * 257 >= kWinWords, "window does not fit");
+  static_assert((kThreads / 8) * 257 >= kWinWords + 3 + kThreads, "window does not fit");
   const int64_t count = dcount ? (int64_t)*dcount : count_static;
   const int64_t blk = sgs_xcd_block_live(blockIdx.x, gridDim.x, (count + kTile - 1) / kTile);
   const int64_t base = blk * kTile;
@@ -485,7 +487,8 @@ k_gen_hist(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ brec,
   }
   const int64_t p = base + (int64_t)threadIdx.x * kItems;
   uint32_t key[kItems], val[kItems];
-  gen_block(offsets, brec, bstart, blk, base, count, vn, GW, &s_sub[0][0], key, val);
+  gen_block(offsets, brec, bstart, blk, base, count, vn, GW, &s_sub[0][0],
+            &s_sub[0][0] + kWinWords + 3, key, val);
 #pragma unroll
   for (int w = 0; w < kThreads / 8; ++w) s_sub[w][threadIdx.x] = 0;
   __syncthreads();
@@ -522,7 +525,7 @@ k_gen_scatter(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ br
   const uint32_t h_scan = scanned_offset(hist_scanned, digit_tot, blk);
   {
     uint32_t key[kItems], val[kItems];
-    gen_block(offsets, brec, bstart, blk, base, count, vn, GW, s_key, key, val);
+    gen_block(offsets, brec, bstart, blk, base, count, vn, GW, s_key, s_val, key, val);
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       const int li = lds_pad(threadIdx.x * kItems + j);
