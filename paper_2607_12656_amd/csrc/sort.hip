@@ -261,11 +261,25 @@ __device__ __forceinline__ uint32_t scanned_offset(const uint32_t *__restrict__ 
 __device__ __forceinline__ int lds_pad(int i) { return i ^ ((i >> 4) & 15); }
 constexpr int kTilePad = kTile;
 
-// Scatter of one pass for the block's elements, held in rounds (element
-// base + r*256 + tid in kr[r], vr[r]).  Ranks follow (round, wave, lane) =
-// input order; the block first places its elements in LDS in digit order
-// (stable), then writes each digit's run to its global position with
-// consecutive threads on consecutive addresses (coalesced).
+// Ordering of the LDS accesses of one wave among themselves (lanes of a wave
+// read what other lanes of the same wave wrote; no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Scatter of one pass for the block's elements in the wave-segment layout:
+// wave w holds elements w * IT * 64 + r * 64 + lane of the block in kr[r],
+// vr[r], so the input order is (wave, round, lane).  Each wave ranks its own
+// elements digit by digit with ballots and wave-private running counts in
+// LDS (no workgroup barrier inside the rounds); one barrier later the
+// per-wave counts become prefixes, and every element lands at
+//   block offset of its digit + elements of that digit in earlier waves
+//   + its rank within its wave,
+// i.e. the block's elements in LDS in stable digit order; each digit's run is
+// then written to its global position with consecutive threads on
+// consecutive addresses (coalesced).
 // h_raw / h_scan: this thread's digit (= tid) entries of the block's raw and
 // scanned histogram rows, loaded by the caller ahead of its other work.
 template <int IT>
@@ -277,8 +291,7 @@ __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[IT],
                                               uint32_t *s_val) {
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_loff[256];
-  __shared__ uint32_t s_run[256];
-  __shared__ uint32_t s_wc[kWaves][256];
+  __shared__ uint32_t s_cnt[kWaves][256];
   __shared__ uint32_t s_wave[kWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   s_base[threadIdx.x] = h_scan;
@@ -286,40 +299,45 @@ __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[IT],
     uint32_t tot;
     s_loff[threadIdx.x] = block_exclusive_scan(h_raw, s_wave, tot);
   }
-  s_run[threadIdx.x] = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) s_cnt[w][threadIdx.x] = 0;
+  __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t wbase = base + (int64_t)wave * IT * 64;
+  uint32_t rank[IT];
 #pragma unroll
   for (int r = 0; r < IT; ++r) {
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) s_wc[w][threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
-    const bool valid = i < count;
-    const uint32_t k = kr[r], v = vr[r];
-    const uint32_t d = (k >> shift) & 0xFFu;
+    const bool valid = wbase + (int64_t)r * 64 + lane < count;
+    const uint32_t d = (kr[r] >> shift) & 0xFFu;
     const uint64_t m = match_digit(d, valid);
-    const uint32_t rank = (uint32_t)__popcll(m & lt);
-    if (valid && (__ffsll((long long)m) - 1) == lane) s_wc[wave][d] = (uint32_t)__popcll(m);
-    __syncthreads();
-    {
-      const int t = threadIdx.x;
-      uint32_t run = s_run[t];
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) {
-        const uint32_t c = s_wc[w][t];
-        s_wc[w][t] = run;
-        run += c;
-      }
-      s_run[t] = run;
-    }
-    __syncthreads();
-    if (valid) {
-      const uint32_t lp = s_loff[d] + s_wc[wave][d] + rank;  // < kThreads * IT
-      s_key[lp] = k;
-      s_val[lp] = v;
-    }
-    __syncthreads();
+    const uint32_t before = valid ? s_cnt[wave][d] : 0u;
+    rank[r] = before + (uint32_t)__popcll(m & lt);
+    wave_lds_sync();  // every lane has read before the leader writes
+    if (valid && (__ffsll((long long)m) - 1) == lane) s_cnt[wave][d] = before + (uint32_t)__popcll(m);
+    wave_lds_sync();
   }
+  __syncthreads();
+  {
+    const int t = threadIdx.x;
+    uint32_t run = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t c = s_cnt[w][t];
+      s_cnt[w][t] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < IT; ++r) {
+    if (wbase + (int64_t)r * 64 + lane < count) {
+      const uint32_t d = (kr[r] >> shift) & 0xFFu;
+      const uint32_t lp = s_loff[d] + s_cnt[wave][d] + rank[r];  // < kThreads * IT
+      s_key[lp] = kr[r];
+      s_val[lp] = vr[r];
+    }
+  }
+  __syncthreads();
   const int nloc = (int)min((int64_t)(kThreads * IT), count - base);
 #pragma unroll 4
   for (int p = threadIdx.x; p < nloc; p += kThreads) {
@@ -345,12 +363,13 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
   const int64_t blk = sgs_xcd_block_live(blockIdx.x, gridDim.x, (count + TILE - 1) / TILE);
   const int64_t base = blk * TILE;
   if (base >= count) return;
-  // all loads of the block in flight at once
+  // all loads of the block in flight at once, in the wave-segment layout
   const uint32_t h_raw = hist_raw[blk * 256 + threadIdx.x];
+  const int64_t wbase = base + (int64_t)(threadIdx.x >> 6) * IT * 64 + (threadIdx.x & 63);
   uint32_t kr[IT], vr[IT];
 #pragma unroll
   for (int r = 0; r < IT; ++r) {
-    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+    const int64_t i = wbase + (int64_t)r * 64;
     kr[r] = i < count ? kin[i] : 0u;
     vr[r] = i < count ? vin[i] : 0u;
   }
@@ -504,8 +523,9 @@ k_gen_hist(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ brec,
 }
 
 // Generated pairs of each block scattered by their low digit.  Threads
-// generate runs of kItems consecutive pairs; LDS transposes them into the
-// round layout of scatter_block.
+// generate runs of kItems consecutive pairs; each wave transposes its own
+// 64 kItems pairs through LDS into the wave-segment layout of scatter_block
+// (a wave's runs are its segment: kItems * 64 pairs).
 __global__ void __launch_bounds__(kThreads)
 k_gen_scatter(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ brec,
               const uint32_t *__restrict__ bstart, int64_t vn, int64_t count_static,
@@ -523,25 +543,27 @@ k_gen_scatter(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ br
   if (base >= count) return;
   const uint32_t h_raw = hist_raw[blk * 256 + threadIdx.x];
   const uint32_t h_scan = scanned_offset(hist_scanned, digit_tot, blk);
+  const int lane = threadIdx.x & 63;
+  uint32_t *wk = s_key + (threadIdx.x >> 6) * kItems * 64;
+  uint32_t *wv = s_val + (threadIdx.x >> 6) * kItems * 64;
   {
     uint32_t key[kItems], val[kItems];
     gen_block(offsets, brec, bstart, blk, base, count, vn, GW, s_key, s_val, key, val);
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
-      const int li = lds_pad(threadIdx.x * kItems + j);
-      s_key[li] = key[j];
-      s_val[li] = val[j];
+      const int li = lds_pad(lane * kItems + j);
+      wk[li] = key[j];
+      wv[li] = val[j];
     }
   }
-  __syncthreads();
+  wave_lds_sync();
   uint32_t kr[kItems], vr[kItems];
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    const int li = lds_pad(r * kThreads + threadIdx.x);
-    kr[r] = s_key[li];
-    vr[r] = s_val[li];
+    const int li = lds_pad(r * 64 + lane);
+    kr[r] = wk[li];
+    vr[r] = wv[li];
   }
-  __syncthreads();
   scatter_block<kItems>(kr, vr, base, count, 0, h_raw, h_scan, kout, vout, s_key, s_val);
 }
 
