@@ -280,13 +280,14 @@ __device__ __forceinline__ void wave_lds_sync() {
 // i.e. the block's elements in LDS in stable digit order; each digit's run is
 // then written to its global position with consecutive threads on
 // consecutive addresses (coalesced).
-// h_raw / h_scan: this thread's digit (= tid) entries of the block's raw and
-// scanned histogram rows, loaded by the caller ahead of its other work.
+// The block's count of each digit (the offsets inside the block) comes from
+// the ranking itself.  h_scan: this thread's digit (= tid) entry of the
+// block's scanned histogram row, loaded by the caller ahead of its other work.
 template <int IT>
 __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[IT],
                                               const uint32_t (&vr)[IT], int64_t base,
-                                              int64_t count, int shift, uint32_t h_raw,
-                                              uint32_t h_scan, uint32_t *__restrict__ kout,
+                                              int64_t count, int shift, uint32_t h_scan,
+                                              uint32_t *__restrict__ kout,
                                               uint32_t *__restrict__ vout, uint32_t *s_key,
                                               uint32_t *s_val) {
   __shared__ uint32_t s_base[256];
@@ -295,10 +296,6 @@ __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[IT],
   __shared__ uint32_t s_wave[kWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   s_base[threadIdx.x] = h_scan;
-  {
-    uint32_t tot;
-    s_loff[threadIdx.x] = block_exclusive_scan(h_raw, s_wave, tot);
-  }
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) s_cnt[w][threadIdx.x] = 0;
   __syncthreads();
@@ -326,6 +323,8 @@ __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[IT],
       s_cnt[w][t] = run;
       run += c;
     }
+    uint32_t tot;
+    s_loff[t] = block_exclusive_scan(run, s_wave, tot);  // run: the block's count of digit t
   }
   __syncthreads();
 #pragma unroll
@@ -354,7 +353,7 @@ __global__ void __launch_bounds__(kThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                 uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                 int64_t count_static, const uint32_t *__restrict__ dcount, int shift,
-                const uint32_t *__restrict__ hist_raw, const uint32_t *__restrict__ hist_scanned,
+                const uint32_t *__restrict__ hist_scanned,
                 const uint32_t *__restrict__ digit_tot) {
   constexpr int TILE = kThreads * IT;
   __shared__ uint32_t s_key[TILE];
@@ -364,7 +363,6 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
   const int64_t base = blk * TILE;
   if (base >= count) return;
   // all loads of the block in flight at once, in the wave-segment layout
-  const uint32_t h_raw = hist_raw[blk * 256 + threadIdx.x];
   const int64_t wbase = base + (int64_t)(threadIdx.x >> 6) * IT * 64 + (threadIdx.x & 63);
   uint32_t kr[IT], vr[IT];
 #pragma unroll
@@ -374,7 +372,7 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
     vr[r] = i < count ? vin[i] : 0u;
   }
   const uint32_t h_scan = scanned_offset(hist_scanned, digit_tot, blk);
-  scatter_block<IT>(kr, vr, base, count, shift, h_raw, h_scan, kout, vout, s_key, s_val);
+  scatter_block<IT>(kr, vr, base, count, shift, h_scan, kout, vout, s_key, s_val);
 }
 
 // ---------------------------------------------------------------------------
@@ -530,7 +528,7 @@ __global__ void __launch_bounds__(kThreads)
 k_gen_scatter(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ brec,
               const uint32_t *__restrict__ bstart, int64_t vn, int64_t count_static,
               const uint32_t *__restrict__ dcount, int GW,
-              const uint32_t *__restrict__ hist_raw, const uint32_t *__restrict__ hist_scanned,
+              const uint32_t *__restrict__ hist_scanned,
               const uint32_t *__restrict__ digit_tot, uint32_t *__restrict__ kout,
               uint32_t *__restrict__ vout) {
   // s_key doubles as the generator's LDS window
@@ -541,7 +539,6 @@ k_gen_scatter(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ br
   const int64_t blk = sgs_xcd_block_live(blockIdx.x, gridDim.x, (count + kTile - 1) / kTile);
   const int64_t base = blk * kTile;
   if (base >= count) return;
-  const uint32_t h_raw = hist_raw[blk * 256 + threadIdx.x];
   const uint32_t h_scan = scanned_offset(hist_scanned, digit_tot, blk);
   const int lane = threadIdx.x & 63;
   uint32_t *wk = s_key + (threadIdx.x >> 6) * kItems * 64;
@@ -564,7 +561,7 @@ k_gen_scatter(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ br
     kr[r] = wk[li];
     vr[r] = wv[li];
   }
-  scatter_block<kItems>(kr, vr, base, count, 0, h_raw, h_scan, kout, vout, s_key, s_val);
+  scatter_block<kItems>(kr, vr, base, count, 0, h_scan, kout, vout, s_key, s_val);
 }
 
 __global__ void k_zero_ranges(uint2 *__restrict__ ranges, int64_t tiles) {
@@ -730,12 +727,12 @@ hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2], i
     const uint32_t *dtot = launch_digit_offsets(c, b);
     if (small)
       k_radix_scatter<kSmallItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
-          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, b.hraw,
-          b.hscan, dtot);
+          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, b.hscan,
+          dtot);
     else
       k_radix_scatter<kItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
-          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, b.hraw,
-          b.hscan, dtot);
+          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, b.hscan,
+          dtot);
     cur ^= 1;
   }
   *which = cur;
@@ -781,7 +778,7 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
                                                              c->vn, P, dcount, c->GW, b.hraw);
       const uint32_t *dtot = launch_digit_offsets(c, b);
       k_gen_scatter<<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
-          c->offsets, c->bin_rec, c->blk_start, c->vn, P, dcount, c->GW, b.hraw, b.hscan, dtot,
+          c->offsets, c->bin_rec, c->blk_start, c->vn, P, dcount, c->GW, b.hscan, dtot,
           c->tile_key[1], c->pair_val[1]);
     }
   }
