@@ -49,7 +49,7 @@ __device__ __forceinline__ SplatEval eval_splat(const SplatLds &s, int px, int p
   r.G = __expf(power);
   const float raw = s.b.y * r.G;
   r.clamped = raw > SGS_ALPHA_MAX;
-  r.alpha = r.clamped ? SGS_ALPHA_MAX : raw;
+  r.alpha = fminf(raw, SGS_ALPHA_MAX);  // raw is finite: the same value as the clamp
   r.ok = r.in_span && !(power > 0.0f) && r.alpha >= SGS_ALPHA_MIN;
   return r;
 }
@@ -146,10 +146,11 @@ __device__ __forceinline__ void blend_fwd_tile(int tile, int n, int W, int H, in
         const float Tn = T * (1.0f - at);
         const bool term = okc && Tn < SGS_T_MIN;
         const bool contrib = okc && !term;
-        const float w = at * T;
-        C0 = contrib ? fmaf(cur.c.x, w, C0) : C0;
-        C1 = contrib ? fmaf(cur.c.y, w, C1) : C1;
-        C2 = contrib ? fmaf(cur.c.z, w, C2) : C2;
+        // a zero weight leaves C unchanged bit for bit (colours are finite)
+        const float w = contrib ? at * T : 0.0f;
+        C0 = fmaf(cur.c.x, w, C0);
+        C1 = fmaf(cur.c.y, w, C1);
+        C2 = fmaf(cur.c.z, w, C2);
         T = contrib ? Tn : T;
         stop = term ? b - rg.x + (uint32_t)k : stop;
         done = done || term;
@@ -426,7 +427,9 @@ __device__ __forceinline__ void blend_bwd_tile(int tile, int n, int W, int H, in
           const float mk = cur.c.w;
           const float at = mk * e.alpha;
           const float om = 1.0f - at;
-          const float Tb = (at == 0.0f) ? T : T / om;  // T in front of this splat
+          // T in front of this splat (hardware reciprocal, 1 ulp: the
+          // recovered T drifts by about one ulp per blended splat)
+          const float Tb = (at == 0.0f) ? T : T * __builtin_amdgcn_rcpf(om);
           const float dat =
               Tb * fmaf(g0, cur.c.x - B0, fmaf(g1, cur.c.y - B1, g2 * (cur.c.z - B2)));
           const float wcol = at * Tb;
