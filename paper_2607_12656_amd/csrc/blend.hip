@@ -11,10 +11,10 @@
 // fall below 1e-4; the workgroup stops when every pixel has stopped.
 //
 // The backward walks the same list from each pixel's stop position towards
-// the front, recovers T by division with the same (1 - alpha~) the forward
-// multiplied by, and reduces the ten per-splat gradients of a wave with a
-// transposing butterfly (17 shuffles for all ten values); ten lanes then
-// issue one atomic each.
+// the front, recovers T by multiplying with the reciprocal of the same
+// (1 - alpha~) the forward multiplied by, and reduces the ten per-splat
+// gradients of a wave with a transposing butterfly (17 shuffles for all ten
+// values); ten lanes then issue one atomic each.
 #include "sgs_internal.h"
 
 namespace {
