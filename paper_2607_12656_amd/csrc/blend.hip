@@ -13,8 +13,8 @@
 // The backward walks the same list from each pixel's stop position towards
 // the front, recovers T by multiplying with the reciprocal of the same
 // (1 - alpha~) the forward multiplied by, and reduces the ten per-splat
-// gradients of a wave with a transposing butterfly (17 shuffles for all ten
-// values); ten lanes then issue one atomic each.
+// gradients of a wave with a transposing butterfly (eight lane swaps and
+// five DPP exchanges for all ten values); ten lanes then issue one atomic each.
 #include "sgs_internal.h"
 
 namespace {
@@ -255,11 +255,14 @@ k_blend_fwd(int total_tiles, const uint32_t *__restrict__ order, uint32_t *__res
   }
 }
 
-// Sum each of v[0..15] over the 64 lanes of the wave with a transposing
+// Sum each of v[0..9] over the 64 lanes of the wave with a transposing
 // butterfly: every exchange halves the number of values a lane carries, so
-// the sixteen sums cost 8 + 4 cross-half swaps (v_permlane32/16_swap), two
-// DPP exchanges inside a row and two quad reductions.  After the call lane L
-// holds the total of value 4*(L>>4) + 2*((L>>3)&1) + ((L>>2)&1).
+// the ten sums cost five cross-half swaps (v_permlane32_swap), three row
+// swaps (v_permlane16_swap; the fifth value is summed over the row pair
+// without halving), two DPP exchanges across eights, one across fours and
+// two quad reductions.  After the call lane L, with h = L >> 5,
+// r = (L >> 4) & 1, b3 = (L >> 3) & 1 and b2 = (L >> 2) & 1, holds the total
+// of value sum10_index(L) = 5 h + (b2 ? 2 : b3 ? (r ? 4 : 1) : (r ? 3 : 0)).
 template <int kCtrl>
 __device__ __forceinline__ float dpp(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, 0xF, 0xF, false));
@@ -269,35 +272,38 @@ constexpr int kDppRowHalfMirror = 0x141; // lane i <- lane 7 - i within each eig
 constexpr int kDppQuad2301 = 0x4E;       // lane i <- lane i ^ 2 within a quad
 constexpr int kDppQuad1032 = 0xB1;       // lane i <- lane i ^ 1 within a quad
 
-__device__ __forceinline__ float wave_transpose_sum16(const float v[16], int lane) {
-  float r8[8], r4[4], r2[2];
+__device__ __forceinline__ int sum10_index(int lane) {
+  const int b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1, r = (lane >> 4) & 1;
+  return 5 * (lane >> 5) + (b2 ? 2 : (b3 ? (r ? 4 : 1) : (r ? 3 : 0)));
+}
+
+__device__ __forceinline__ float wave_transpose_sum10(const float v[10], int lane) {
+  float r5[5], t[3];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    // lanes 0-31 end with value i, lanes 32-63 with value 8 + i
+  for (int i = 0; i < 5; ++i) {
+    // lanes 0-31 end with value i, lanes 32-63 with value 5 + i
     const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]),
-                                                     __float_as_uint(v[8 + i]), false, false);
-    r8[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+                                                     __float_as_uint(v[5 + i]), false, false);
+    r5[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    // row q (lanes 16q .. 16q + 15) ends with value 4q + i
-    const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(r8[i]),
-                                                     __float_as_uint(r8[4 + i]), false, false);
-    r4[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+  for (int i = 0; i < 2; ++i) {
+    // even rows end with slot i, odd rows with slot 3 + i
+    const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(r5[i]),
+                                                     __float_as_uint(r5[3 + i]), false, false);
+    t[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
   }
   {
-    const bool hi = lane & 8;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const float mine = hi ? r4[2 + i] : r4[i];
-      const float send = hi ? r4[i] : r4[2 + i];
-      r2[i] = mine + dpp<kDppRowRor8>(send);
-    }
+    // slot 2 in every row, summed over the row pair
+    const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(r5[2]),
+                                                     __float_as_uint(r5[2]), false, false);
+    t[2] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
   }
-  const bool hi = lane & 4;
-  const float mine = hi ? r2[1] : r2[0];
-  const float send = hi ? r2[0] : r2[1];
-  float x = mine + dpp<kDppRowHalfMirror>(send);
+  const bool b3 = lane & 8;
+  const float u0 = (b3 ? t[1] : t[0]) + dpp<kDppRowRor8>(b3 ? t[0] : t[1]);
+  const float u1 = t[2] + dpp<kDppRowRor8>(t[2]);
+  const bool b2 = lane & 4;
+  float x = (b2 ? u1 : u0) + dpp<kDppRowHalfMirror>(b2 ? u0 : u1);
   x += dpp<kDppQuad2301>(x);
   x += dpp<kDppQuad1032>(x);
   return x;
@@ -359,10 +365,12 @@ __device__ __forceinline__ void blend_bwd_tile(int tile, int n, int W, int H, in
   if (reach == 0) return;
   float B0 = 0.f, B1 = 0.f, B2 = 0.f;  // colour seen behind the current splat
   const int nbatch = (int)((reach + BS - 1) / BS);
-  const int vidx = 4 * (lane >> 4) + 2 * ((lane >> 3) & 1) + ((lane >> 2) & 1);
-  // the lane that adds value vidx to the splat's gradient, and the factor on
+  const int vidx = sum10_index(lane);
+  // the lane that adds value vidx to the splat's gradient (one per value: the
+  // first of its quad, and for value 5 h + 2, which 16 lanes hold, the one
+  // with r = b3 = 0), and the factor on
   // its own wave sum for the values the conic does not enter
-  const bool lead = (lane & 3) == 0 && vidx < 10;
+  const bool lead = (lane & 3) == 0 && (((lane >> 2) & 1) == 0 || ((lane >> 3) & 3) == 0);
   const float k_self = (vidx == 2 || vidx == 4) ? -0.5f : (vidx == 3 ? -1.0f : 1.0f);
   // per-splat sums in FP64: a splat's terms come from many tiles and
   // cancel, and FP32 sums in arbitrary order lose the small result
@@ -420,9 +428,9 @@ __device__ __forceinline__ void blend_bwd_tile(int tile, int n, int W, int H, in
         const SplatEval e = eval_splat(cur, px, py, fx, fy);
         const bool ok = inside && pos < my_last && e.ok;
         if (__ballot(ok) == 0ull) return;
-        float d[16];
+        float d[10];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) d[q] = 0.0f;
+        for (int q = 0; q < 10; ++q) d[q] = 0.0f;
         if (ok) {
           const float mk = cur.c.w;
           const float at = mk * e.alpha;
@@ -455,9 +463,9 @@ __device__ __forceinline__ void blend_bwd_tile(int tile, int n, int W, int H, in
           B2 = fmaf(cur.c.z, at, om * B2);
           T = Tb;
         }
-        const float tot = wave_transpose_sum16(d, lane);
-        // lanes 0-3 hold Sx and lanes 4-7 hold Sy: each reads the other
-        const float other = dpp<kDppRowHalfMirror>(tot);
+        const float tot = wave_transpose_sum10(d, lane);
+        // lanes 0-3 hold Sx and lanes 8-11 hold Sy: each reads the other
+        const float other = dpp<kDppRowRor8>(tot);
         const float cs = vidx == 0 ? cur.a.z : (vidx == 1 ? cur.b.x : k_self);
         const float co = vidx < 2 ? cur.a.w : 0.0f;
         const float gv = fmaf(cs, tot, co * other);
