@@ -372,6 +372,10 @@ __device__ __forceinline__ void blend_bwd_tile(int tile, int n, int W, int H, in
   // its own wave sum for the values the conic does not enter
   const bool lead = (lane & 3) == 0 && (((lane >> 2) & 1) == 0 || ((lane >> 3) & 3) == 0);
   const float k_self = (vidx == 2 || vidx == 4) ? -0.5f : (vidx == 3 ? -1.0f : 1.0f);
+  // per-lane 0/1 selectors of the conic entries (multiplying by 1 or 0 and
+  // adding 0 is exact)
+  const float sel_a = vidx == 0 ? 1.0f : 0.0f, sel_c = vidx == 1 ? 1.0f : 0.0f;
+  const float sel_b = vidx < 2 ? 1.0f : 0.0f, k_rest = vidx < 2 ? 0.0f : k_self;
   // per-splat sums in FP64: a splat's terms come from many tiles and
   // cancel, and FP32 sums in arbitrary order lose the small result
   double *const gbase = sgrad + base * SGS_SGRAD;
@@ -428,46 +432,45 @@ __device__ __forceinline__ void blend_bwd_tile(int tile, int n, int W, int H, in
         const SplatEval e = eval_splat(cur, px, py, fx, fy);
         const bool ok = inside && pos < my_last && e.ok;
         if (__ballot(ok) == 0ull) return;
+        // branch-free: lanes without the pair take alpha~ = 0 and dL/dalpha~ = 0,
+        // so every value below is 0 there and B, T stay as they are (bit for
+        // bit: colours and B are finite and non-negative, 1 - 0 = 1 and its
+        // reciprocal is exact)
+        const float mk = cur.c.w;
+        const float at = ok ? mk * e.alpha : 0.0f;
+        const float om = 1.0f - at;
+        // T in front of this splat (hardware reciprocal, 1 ulp: the
+        // recovered T drifts by about one ulp per blended splat)
+        const float Tb = (at == 0.0f) ? T : T * __builtin_amdgcn_rcpf(om);
+        const float dsum = fmaf(g0, cur.c.x - B0, fmaf(g1, cur.c.y - B1, g2 * (cur.c.z - B2)));
+        const float dat = ok ? Tb * dsum : 0.0f;
+        const float wcol = at * Tb;
         float d[10];
-#pragma unroll
-        for (int q = 0; q < 10; ++q) d[q] = 0.0f;
-        if (ok) {
-          const float mk = cur.c.w;
-          const float at = mk * e.alpha;
-          const float om = 1.0f - at;
-          // T in front of this splat (hardware reciprocal, 1 ulp: the
-          // recovered T drifts by about one ulp per blended splat)
-          const float Tb = (at == 0.0f) ? T : T * __builtin_amdgcn_rcpf(om);
-          const float dat =
-              Tb * fmaf(g0, cur.c.x - B0, fmaf(g1, cur.c.y - B1, g2 * (cur.c.z - B2)));
-          const float wcol = at * Tb;
-          d[6] = g0 * wcol;
-          d[7] = g1 * wcol;
-          d[8] = g2 * wcol;
-          d[9] = dat * e.alpha;
-          if (!e.clamped) {
-            // moments of dL/dpower over the pixels; the conic enters after
-            // the wave sum: dL/dpx = A Sx + B Sy, dL/dpy = B Sx + C Sy,
-            // dL/dA = -Sxx / 2, dL/dB = -Sxy, dL/dC = -Syy / 2
-            const float dal = mk * dat;
-            d[5] = dal * e.G;
-            const float dp = dal * e.alpha;
-            d[0] = dp * e.dx;
-            d[1] = dp * e.dy;
-            d[2] = d[0] * e.dx;
-            d[3] = d[0] * e.dy;
-            d[4] = d[1] * e.dy;
-          }
-          B0 = fmaf(cur.c.x, at, om * B0);
-          B1 = fmaf(cur.c.y, at, om * B1);
-          B2 = fmaf(cur.c.z, at, om * B2);
-          T = Tb;
-        }
+        d[6] = g0 * wcol;
+        d[7] = g1 * wcol;
+        d[8] = g2 * wcol;
+        d[9] = dat * e.alpha;
+        // moments of dL/dpower over the pixels (zero through the alpha clamp);
+        // the conic enters after the wave sum: dL/dpx = A Sx + B Sy,
+        // dL/dpy = B Sx + C Sy, dL/dA = -Sxx / 2, dL/dB = -Sxy, dL/dC = -Syy / 2
+        const float dal = e.clamped ? 0.0f : mk * dat;
+        d[5] = dal * e.G;
+        const float dp = dal * e.alpha;
+        d[0] = dp * e.dx;
+        d[1] = dp * e.dy;
+        d[2] = d[0] * e.dx;
+        d[3] = d[0] * e.dy;
+        d[4] = d[1] * e.dy;
+        B0 = fmaf(cur.c.x, at, om * B0);
+        B1 = fmaf(cur.c.y, at, om * B1);
+        B2 = fmaf(cur.c.z, at, om * B2);
+        T = Tb;
         const float tot = wave_transpose_sum10(d, lane);
         // lanes 0-3 hold Sx and lanes 8-11 hold Sy: each reads the other
         const float other = dpp<kDppRowRor8>(tot);
-        const float cs = vidx == 0 ? cur.a.z : (vidx == 1 ? cur.b.x : k_self);
-        const float co = vidx < 2 ? cur.a.w : 0.0f;
+        // cs = A (value 0), C (value 1) or k_self; co = B for values 0 and 1
+        const float cs = fmaf(sel_a, cur.a.z, fmaf(sel_c, cur.b.x, k_rest));
+        const float co = sel_b * cur.a.w;
         const float gv = fmaf(cs, tot, co * other);
         if (lead && gv != 0.0f)
           unsafeAtomicAdd(gbase + (size_t)gid * SGS_SGRAD + vidx, (double)gv);
