@@ -329,8 +329,11 @@ def main():
         tr = json.load(open(args.traffic))
         ent = tr.get(f"{args.workload}:{dom}")
         if ent:
-            src = os.path.join(ROOT, ent["kernel_file"])
-            cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+            # the counters hold while the kernel's sources are unchanged
+            h = hashlib.sha256()
+            for f in ent.get("kernel_files", [ent.get("kernel_file")]):
+                h.update(open(os.path.join(ROOT, f), "rb").read())
+            cur = h.hexdigest()[:16]
             if cur == ent["kernel_sha256_16"]:
                 roof["traffic"] = ent["bytes_per_launch"]
                 roof["traffic_source"] = ent["source"] + " (profiles/hbm_traffic_*.md)"

@@ -861,16 +861,19 @@ extern "C" sgs_status sgs_copy_structure(sgs_ctx *c, uint32_t *tile_ids, uint32_
 }
 
 namespace {
+// FP64 records of SGS_SGRAD values -> float rows of 12 (the last ones 0)
 __global__ void k_export_grads(int64_t count, const double *__restrict__ in,
                                float *__restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) out[i] = (float)in[i];
+  if (i >= count) return;
+  const int64_t s = i / 12, k = i - s * 12;
+  out[i] = k < SGS_SGRAD ? (float)in[s * SGS_SGRAD + k] : 0.0f;
 }
 }  // namespace
 
 extern "C" sgs_status sgs_copy_splat_grads(sgs_ctx *c, float *out) {
   if (!c || !out) return SGS_EINVAL;
-  const int64_t count = SGS_SGRAD * c->vn;
+  const int64_t count = 12 * c->vn;
   k_export_grads<<<sgs_blocks(count, 256), 256, 0, c->stream>>>(count, c->splat_grad, out);
   SGS_HIP(hipGetLastError(), "copy splat grads");
   return SGS_OK;

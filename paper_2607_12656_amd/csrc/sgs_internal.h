@@ -20,7 +20,7 @@
 
 // Splat-gradient record stride (floats): px, py, A, B, C, opacity, r, g, b,
 // mask, pad, pad.
-#define SGS_SGRAD 12
+#define SGS_SGRAD 10  // px, py, A, B, C, opacity, r, g, b, mask (five 16-byte pairs)
 
 // Blend conventions (the paper does not state them).
 #define SGS_NEAR 0.2f
