@@ -814,8 +814,9 @@ __global__ void k_export(int64_t vn, const float4 *__restrict__ rec,
   if (depth) depth[s] = 0.0f;
   if (splats) {
     float *o = splats + 12 * s;
-    o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
-    o[4] = b.x; o[5] = b.y; o[6] = cc.x; o[7] = cc.y; o[8] = cc.z; o[9] = cc.w;
+    // the records hold the conic scaled for the blend: undo it
+    o[0] = a.x; o[1] = a.y; o[2] = a.z / SGS_CONIC_KAC; o[3] = a.w / SGS_CONIC_KB;
+    o[4] = b.x / SGS_CONIC_KAC; o[5] = b.y; o[6] = cc.x; o[7] = cc.y; o[8] = cc.z; o[9] = cc.w;
     o[10] = 0.0f; o[11] = 0.0f;
   }
 }

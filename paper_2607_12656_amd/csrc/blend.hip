@@ -20,8 +20,8 @@
 namespace {
 
 struct SplatLds {
-  float4 a;  // px, py, A, B
-  float4 b;  // C, opacity, spanx (x0 | x1 << 16), spany
+  float4 a;  // px, py, A', B' (the conic scaled by SGS_CONIC_KAC / KB)
+  float4 b;  // C', opacity, spanx (x0 | x1 << 16), spany
   float4 c;  // r, g, b, mask
 };
 
@@ -42,15 +42,13 @@ __device__ __forceinline__ SplatEval eval_splat(const SplatLds &s, int px, int p
               (py >= (int)(sy & 0xFFFF)) && (py <= (int)(sy >> 16));
   r.dx = fx - s.a.x;
   r.dy = fy - s.a.y;
-  const float q1 = s.a.z * r.dx * r.dx;
-  const float q2 = s.b.x * r.dy * r.dy;
-  const float q3 = s.a.w * r.dx * r.dy;
-  const float power = -0.5f * (q1 + q2) - q3;
-  r.G = __expf(power);
+  // log2(e) power = A' dx^2 + C' dy^2 + B' dx dy (the record's scaled conic)
+  const float p2 = fmaf(s.a.z * r.dx, r.dx, fmaf(s.b.x * r.dy, r.dy, s.a.w * r.dx * r.dy));
+  r.G = __builtin_amdgcn_exp2f(p2);
   const float raw = s.b.y * r.G;
   r.clamped = raw > SGS_ALPHA_MAX;
   r.alpha = fminf(raw, SGS_ALPHA_MAX);  // raw is finite: the same value as the clamp
-  r.ok = r.in_span && !(power > 0.0f) && r.alpha >= SGS_ALPHA_MIN;
+  r.ok = r.in_span && !(p2 > 0.0f) && r.alpha >= SGS_ALPHA_MIN;
   return r;
 }
 
@@ -372,10 +370,12 @@ __device__ __forceinline__ void blend_bwd_tile(int tile, int n, int W, int H, in
   // its own wave sum for the values the conic does not enter
   const bool lead = (lane & 3) == 0 && (((lane >> 2) & 1) == 0 || ((lane >> 3) & 3) == 0);
   const float k_self = (vidx == 2 || vidx == 4) ? -0.5f : (vidx == 3 ? -1.0f : 1.0f);
-  // per-lane 0/1 selectors of the conic entries (multiplying by 1 or 0 and
-  // adding 0 is exact)
-  const float sel_a = vidx == 0 ? 1.0f : 0.0f, sel_c = vidx == 1 ? 1.0f : 0.0f;
-  const float sel_b = vidx < 2 ? 1.0f : 0.0f, k_rest = vidx < 2 ? 0.0f : k_self;
+  // per-lane selectors of the conic entries, which also undo the records'
+  // scaling (A = A' / SGS_CONIC_KAC, B = B' / SGS_CONIC_KB, C = C' / KAC;
+  // multiplying by 0 and adding 0 is exact)
+  const float sel_a = vidx == 0 ? SGS_CONIC_INV_KAC : 0.0f;
+  const float sel_c = vidx == 1 ? SGS_CONIC_INV_KAC : 0.0f;
+  const float sel_b = vidx < 2 ? SGS_CONIC_INV_KB : 0.0f, k_rest = vidx < 2 ? 0.0f : k_self;
   // per-splat sums in FP64: a splat's terms come from many tiles and
   // cancel, and FP32 sums in arbitrary order lose the small result
   double *const gbase = sgrad + base * SGS_SGRAD;

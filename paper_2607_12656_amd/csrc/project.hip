@@ -165,8 +165,9 @@ k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
     colour(y, cam, col, cl);
     const uint32_t sx = (uint32_t)p.x0 | ((uint32_t)p.x1 << 16);
     const uint32_t sy = (uint32_t)p.y0 | ((uint32_t)p.y1 << 16);
-    rec[3 * s] = make_float4(p.px, p.py, A, B);
-    rec[3 * s + 1] = make_float4(C, opa, __uint_as_float(sx), __uint_as_float(sy));
+    // the conic scaled into the blend's exponent of 2 (SGS_CONIC_KAC / KB)
+    rec[3 * s] = make_float4(p.px, p.py, A * SGS_CONIC_KAC, B * SGS_CONIC_KB);
+    rec[3 * s + 1] = make_float4(C * SGS_CONIC_KAC, opa, __uint_as_float(sx), __uint_as_float(sy));
     rec[3 * s + 2] = make_float4(col[0], col[1], col[2], m);
   }
 }

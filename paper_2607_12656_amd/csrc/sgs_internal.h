@@ -28,6 +28,13 @@
 #define SGS_ALPHA_MAX 0.99f
 #define SGS_ALPHA_MIN (1.0f / 255.0f)
 #define SGS_T_MIN 1e-4f
+// The splat records hold the conic scaled into the blend's exponent of 2:
+// A' = -log2(e)/2 A, B' = -log2(e) B, C' = -log2(e)/2 C, so that
+// log2(e) power = A' dx^2 + C' dy^2 + B' dx dy and e^power = 2^(that).
+#define SGS_CONIC_KAC (-0.72134752044448170368f)   // -log2(e) / 2
+#define SGS_CONIC_KB (-1.44269504088896340736f)    // -log2(e)
+#define SGS_CONIC_INV_KAC (-1.38629436111989061883f)  // -2 ln 2 = 1 / SGS_CONIC_KAC
+#define SGS_CONIC_INV_KB (-0.69314718055994530942f)   // -ln 2 = 1 / SGS_CONIC_KB
 #define SGS_FOV_CLAMP 1.3f
 
 struct sgs_ctx {
