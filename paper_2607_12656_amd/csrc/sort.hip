@@ -564,6 +564,10 @@ k_gen_scatter(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ br
   scatter_block<kItems>(kr, vr, base, count, 0, h_scan, kout, vout, s_key, s_val);
 }
 
+// Pair counts (the pair capacity in the fixed-capacity mode) from which the
+// ranges come from binary searches rather than from a pass over every id.
+constexpr int64_t kRangeSearchMin = (int64_t)1 << 20;
+
 __global__ void k_zero_ranges(uint2 *__restrict__ ranges, int64_t tiles) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < tiles) ranges[t] = make_uint2(0, 0);
@@ -606,6 +610,35 @@ __global__ void k_ranges(const uint32_t *__restrict__ tile_key, int64_t P_static
     const uint32_t last = tile_key[P - 1];
     if (last < tiles) ranges[last].y = (uint32_t)P;
   }
+}
+
+// Tile ranges by binary search in the sorted tile ids: thread t finds the
+// first position of tile t and of tile t + 1 (lower bounds over [0, P), the
+// two searches in lock step, ceil(log2(P + 1)) probes each); an empty tile
+// gets (0, 0).  About 2 log2(P) words read per tile instead of every id: for
+// large P the pass that reads them all is HBM-bound, the searches are not.
+__global__ void __launch_bounds__(256)
+k_ranges_search(const uint32_t *__restrict__ tile_key, int64_t P_static,
+                const uint32_t *__restrict__ dcount, uint32_t tiles,
+                uint2 *__restrict__ ranges) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tiles) return;
+  const int64_t P = dcount ? (int64_t)*dcount : P_static;
+  const uint32_t k0 = (uint32_t)t, k1 = (uint32_t)t + 1u;
+  int64_t lo0 = 0, hi0 = P, lo1 = 0, hi1 = P;
+  while (lo0 < hi0 || lo1 < hi1) {
+    const int64_t m0 = (lo0 + hi0) >> 1, m1 = (lo1 + hi1) >> 1;
+    // both probes stay below hi <= P; a finished search probes nothing
+    const uint32_t v0 = lo0 < hi0 ? tile_key[m0] : 0u;
+    const uint32_t v1 = lo1 < hi1 ? tile_key[m1] : 0u;
+    if (lo0 < hi0) {
+      if (v0 < k0) lo0 = m0 + 1; else hi0 = m0;
+    }
+    if (lo1 < hi1) {
+      if (v1 < k1) lo1 = m1 + 1; else hi1 = m1;
+    }
+  }
+  ranges[t] = lo0 < lo1 ? make_uint2((uint32_t)lo0, (uint32_t)lo1) : make_uint2(0u, 0u);
 }
 
 // counts[0] = total pairs (from the scan); counts[1] = min(total, cap);
@@ -792,10 +825,15 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
   }
   c->pair_sorted_buf = which;
   SgsProfScope ps(c, SGS_PROF_RANGES);
-  k_zero_ranges<<<sgs_blocks(c->total_tiles, 256), 256, 0, c->stream>>>(c->ranges,
-                                                                       c->total_tiles);
-  if (P > 0)
-    k_ranges<<<sgs_blocks((P + 3) / 4, 256), 256, 0, c->stream>>>(c->tile_key[which], P, dcount,
-                                                        (uint32_t)c->total_tiles, c->ranges);
+  if (P >= kRangeSearchMin) {
+    k_ranges_search<<<sgs_blocks(c->total_tiles, 256), 256, 0, c->stream>>>(
+        c->tile_key[which], P, dcount, (uint32_t)c->total_tiles, c->ranges);
+  } else {
+    k_zero_ranges<<<sgs_blocks(c->total_tiles, 256), 256, 0, c->stream>>>(c->ranges,
+                                                                         c->total_tiles);
+    if (P > 0)
+      k_ranges<<<sgs_blocks((P + 3) / 4, 256), 256, 0, c->stream>>>(
+          c->tile_key[which], P, dcount, (uint32_t)c->total_tiles, c->ranges);
+  }
   return launch_tile_order(c);
 }
