@@ -486,15 +486,17 @@ __device__ __forceinline__ void gen_block(const uint32_t *__restrict__ offsets,
   __syncthreads();  // win and s_k free again
 }
 
-// Low-digit histogram of the generated pairs of each block (sub-histograms
-// as in k_radix_hist).
+// Low-digit histogram of the generated pairs of each block, in 16
+// sub-histograms of 16 lanes (a thread's pairs are runs of neighbouring tiles,
+// so lanes rarely meet on one digit; the smaller LDS footprint lets eight
+// workgroups share a compute unit, which hides the window loads).
 __global__ void __launch_bounds__(kThreads)
 k_gen_hist(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ brec,
            const uint32_t *__restrict__ bstart, int64_t vn, int64_t count_static,
            const uint32_t *__restrict__ dcount, int GW, uint32_t *__restrict__ hist) {
   // the sub-histograms double as the generator's LDS window
-  __shared__ __align__(16) uint32_t s_sub[kThreads / 8][257];
-  static_assert((kThreads / 8) * 257 >= kWinWords + 3 + kThreads, "window does not fit");
+  __shared__ __align__(16) uint32_t s_sub[kThreads / 16][257];
+  static_assert((kThreads / 16) * 257 >= kWinWords + 3 + kThreads, "window does not fit");
   const int64_t count = dcount ? (int64_t)*dcount : count_static;
   const int64_t blk = sgs_xcd_block_live(blockIdx.x, gridDim.x, (count + kTile - 1) / kTile);
   const int64_t base = blk * kTile;
@@ -507,16 +509,16 @@ k_gen_hist(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ brec,
   gen_block(offsets, brec, bstart, blk, base, count, vn, GW, &s_sub[0][0],
             &s_sub[0][0] + kWinWords + 3, key, val);
 #pragma unroll
-  for (int w = 0; w < kThreads / 8; ++w) s_sub[w][threadIdx.x] = 0;
+  for (int w = 0; w < kThreads / 16; ++w) s_sub[w][threadIdx.x] = 0;
   __syncthreads();
-  uint32_t *mine = s_sub[threadIdx.x >> 3];
+  uint32_t *mine = s_sub[threadIdx.x >> 4];
 #pragma unroll
   for (int j = 0; j < kItems; ++j)
     if (p + j < count) atomicAdd(&mine[key[j] & 0xFFu], 1u);
   __syncthreads();
   uint32_t tot = 0;
 #pragma unroll
-  for (int w = 0; w < kThreads / 8; ++w) tot += s_sub[w][threadIdx.x];
+  for (int w = 0; w < kThreads / 16; ++w) tot += s_sub[w][threadIdx.x];
   hist[blk * 256 + threadIdx.x] = tot;
 }
 
