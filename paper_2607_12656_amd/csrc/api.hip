@@ -198,6 +198,7 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   c->TH = th;
   c->tau = tau;
   c->schedule = schedule;
+  c->blend_occ[0] = c->blend_occ[1] = c->blend_occ[2] = 0;
   c->GW = (width + tw - 1) / tw;
   c->GH = (height + th - 1) / th;
   c->tiles_per_view = (int64_t)c->GW * c->GH;

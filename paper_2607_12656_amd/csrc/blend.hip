@@ -1,16 +1,17 @@
 // Front-to-back alpha compositing over the per-tile depth-ordered lists
 // (paper Sec. 3.1, compositing equation) and its reverse-order backward.
 //
-// One workgroup per tile.  Each wave64 owns an 8x8 pixel sub-tile (a
-// 16x16 tile is four of them), one pixel per lane.  The workgroup stages a
-// batch of 48-byte splat records in LDS (one gather per thread, one cache
-// line per record); a wave skips every staged splat whose pixel span misses
-// its sub-tile (a wave-uniform branch) and stops walking once all its pixels
-// have terminated.  All lanes read the same LDS record at the same time
-// (broadcast, no bank conflicts).  A pixel stops when T (1 - alpha~) would
-// fall below 1e-4; the workgroup stops when every pixel has stopped.
+// The lists are binned per tile (16x16 by default); the work item of a launch
+// is one 8x8 sub-tile of a tile, done by one wave64 as its own workgroup, one
+// pixel per lane.  The wave stages 64 list entries at a time in its LDS (one
+// 48-byte record per lane, one cache line each), marks with one ballot those
+// whose pixel span meets its sub-tile and walks only those; all lanes read the
+// same LDS record at the same time (broadcast, no bank conflicts).  A pixel
+// stops when T (1 - alpha~) would fall below 1e-4; the wave stops when all its
+// pixels have stopped.  Sub-tiles of one tile finish independently and a
+// finished wave's slot takes the next work item at once.
 //
-// The backward walks the same list from each pixel's stop position towards
+// The backward walks the same list from the wave's furthest stop towards
 // the front, recovers T by multiplying with the reciprocal of the same
 // (1 - alpha~) the forward multiplied by, and reduces the ten per-splat
 // gradients of a wave with a transposing butterfly (eight lane swaps and
@@ -59,27 +60,30 @@ __device__ __forceinline__ uint64_t uniform_mask(uint64_t m) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// One tile of the forward; evals accumulates the thread's in-span pairs.
+// One 8x8 sub-tile of a tile's forward, by one wave (the workgroup): the
+// wave stages 64 list entries at a time in its LDS (one 48-byte record per
+// lane), marks with a ballot those whose pixel span meets its sub-tile, and
+// composites them in list order, two register sets in turn so that the next
+// record loads while one is used; the next 64 records are fetched from global
+// memory during the walk.  It stops once all its pixels have stopped.  evals
+// accumulates the lane's in-span pairs.
 template <int TW, int TH, bool COUNT>
-__device__ __forceinline__ void blend_fwd_tile(int tile, int n, int W, int H, int GW,
-                                               int tiles_per_view,
-                                               const uint2 *__restrict__ ranges,
-                                               const uint32_t *__restrict__ vals,
-                                               const float4 *__restrict__ rec,
-                                               float *__restrict__ image,
-                                               float *__restrict__ final_T,
-                                               uint32_t *__restrict__ last, uint32_t &evals) {
-  constexpr int BS = TW * TH;
-  constexpr int NW = BS / 64;  // waves = 8x8 sub-tiles
+__device__ __forceinline__ void blend_fwd_sub(int tile, int sub, int n, int W, int H, int GW,
+                                              int tiles_per_view,
+                                              const uint2 *__restrict__ ranges,
+                                              const uint32_t *__restrict__ vals,
+                                              const float4 *__restrict__ rec,
+                                              float *__restrict__ image,
+                                              float *__restrict__ final_T,
+                                              uint32_t *__restrict__ last, uint32_t &evals) {
   constexpr int SUBW = TW / 8;
-  __shared__ SplatLds sh[BS];
-  __shared__ uint64_t s_meet[NW][NW];  // [sub-tile][64-entry word]: entries meeting the sub-tile
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ SplatLds sh[64];
+  const int lane = threadIdx.x & 63;
   const int v = tile / tiles_per_view;
   const int t = tile - v * tiles_per_view;
   const int tx = t % GW, ty = t / GW;
-  const int sx0 = tx * TW + (wave % SUBW) * 8;
-  const int sy0 = ty * TH + (wave / SUBW) * 8;
+  const int sx0 = tx * TW + (sub % SUBW) * 8;
+  const int sy0 = ty * TH + (sub / SUBW) * 8;
   const int px = sx0 + (lane & 7);
   const int py = sy0 + (lane >> 3);
   const bool inside = px < W && py < H;
@@ -92,7 +96,7 @@ __device__ __forceinline__ void blend_fwd_tile(int tile, int n, int W, int H, in
   // the next batch's records, fetched while the current one is walked
   float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra;
   auto fetch = [&](uint32_t b) {
-    const uint32_t e = b + threadIdx.x;
+    const uint32_t e = b + (uint32_t)lane;
     if (e < rg.y) {
       const float4 *r = rec + 3 * (base + vals[e]);
       ra = r[0];
@@ -101,84 +105,69 @@ __device__ __forceinline__ void blend_fwd_tile(int tile, int n, int W, int H, in
     }
   };
   if (rg.x < rg.y) fetch(rg.x);
-  for (uint32_t b = rg.x; b < rg.y; b += BS) {
-    if (__syncthreads_count(done ? 1 : 0) == BS) break;
-    const int cnt = (int)min((uint32_t)BS, rg.y - b);
-    if ((int)threadIdx.x < cnt) {
-      sh[threadIdx.x].a = ra;
-      sh[threadIdx.x].b = rb;
-      sh[threadIdx.x].c = rc;
-    }
-    // which sub-tiles this thread's entry meets, one ballot per sub-tile
+  for (uint32_t b = rg.x; b < rg.y; b += 64) {
+    if (__ballot(!done) == 0ull) break;
+    const uint32_t cnt = min(64u, rg.y - b);
+    wave_lds_sync();  // the previous batch's records have been read
+    uint64_t m;
     {
+      const bool valid = (uint32_t)lane < cnt;
+      if (valid) {
+        sh[lane].a = ra;
+        sh[lane].b = rb;
+        sh[lane].c = rc;
+      }
+      // entries whose pixel span meets this sub-tile
       const uint32_t sx = __float_as_uint(rb.z), sy = __float_as_uint(rb.w);
-      const bool valid = (int)threadIdx.x < cnt;
-      const int ex0 = (int)(sx & 0xFFFF), ex1 = (int)(sx >> 16);
-      const int ey0 = (int)(sy & 0xFFFF), ey1 = (int)(sy >> 16);
-      const int bx = tx * TW, by = ty * TH;
-#pragma unroll
-      for (int j = 0; j < NW; ++j) {
-        const int qx = bx + (j % SUBW) * 8, qy = by + (j / SUBW) * 8;
-        const bool m = valid && ex0 <= qx + 7 && ex1 >= qx && ey0 <= qy + 7 && ey1 >= qy;
-        const uint64_t bal = __ballot(m);
-        if (lane == 0) s_meet[j][wave] = bal;
-      }
+      m = __ballot(valid && (int)(sx & 0xFFFF) <= sx0 + 7 && (int)(sx >> 16) >= sx0 &&
+                   (int)(sy & 0xFFFF) <= sy0 + 7 && (int)(sy >> 16) >= sy0);
     }
-    __syncthreads();
-    if (b + BS < rg.y) fetch(b + BS);
-    if (__ballot(!done) == 0ull) continue;
-    // entries meeting this wave's sub-tile, in list order; the next entry's
-    // record is read from LDS while the current one is composited
-    bool wave_done = false;
-#pragma unroll 1
-    for (int word = 0; word < NW && !wave_done; ++word) {
-      uint64_t m = uniform_mask(s_meet[wave][word]);
-      if (m == 0ull) continue;
-      // composite entry k; false once every pixel of the wave has stopped
-      auto step = [&](const SplatLds &cur, int k) {
-        const SplatEval e = eval_splat(cur, px, py, fx, fy);
-        const bool act = !done;
-        if (COUNT) evals += (act && e.in_span) ? 1u : 0u;
-        const bool okc = act && e.ok;
-        const float at = cur.c.w * e.alpha;
-        const float Tn = T * (1.0f - at);
-        const bool term = okc && Tn < SGS_T_MIN;
-        const bool contrib = okc && !term;
-        // a zero weight leaves C unchanged bit for bit (colours are finite)
-        const float w = contrib ? at * T : 0.0f;
-        C0 = fmaf(cur.c.x, w, C0);
-        C1 = fmaf(cur.c.y, w, C1);
-        C2 = fmaf(cur.c.z, w, C2);
-        T = contrib ? Tn : T;
-        stop = term ? b - rg.x + (uint32_t)k : stop;
-        done = done || term;
-      };
-      // two register sets in turn: the next record loads while one is used
-      int ka = word * 64 + __builtin_ctzll(m), kb = ka;
-      m &= m - 1;
-      SplatLds ra_ = sh[ka], rb_;
-      for (;;) {
-        bool more = m != 0ull;
-        if (more) {
-          kb = word * 64 + __builtin_ctzll(m);
-          m &= m - 1;
-          rb_ = sh[kb];
-        }
-        step(ra_, ka);
-        if (!more) break;
-        more = m != 0ull;
-        if (more) {
-          ka = word * 64 + __builtin_ctzll(m);
-          m &= m - 1;
-          ra_ = sh[ka];
-        }
-        step(rb_, kb);
-        // whether any pixel of the wave still runs, every second entry (an
-        // entry composited after the last pixel stopped changes nothing)
-        if (__ballot(!done) == 0ull) { wave_done = true; break; }
-        if (!more) break;
+    wave_lds_sync();
+    if (b + 64 < rg.y) fetch(b + 64);
+    if (m == 0ull) continue;
+    // composite entry k
+    auto step = [&](const SplatLds &cur, int k) {
+      const SplatEval e = eval_splat(cur, px, py, fx, fy);
+      const bool act = !done;
+      if (COUNT) evals += (act && e.in_span) ? 1u : 0u;
+      const bool okc = act && e.ok;
+      const float at = cur.c.w * e.alpha;
+      const float Tn = T * (1.0f - at);
+      const bool term = okc && Tn < SGS_T_MIN;
+      const bool contrib = okc && !term;
+      // a zero weight leaves C unchanged bit for bit (colours are finite)
+      const float w = contrib ? at * T : 0.0f;
+      C0 = fmaf(cur.c.x, w, C0);
+      C1 = fmaf(cur.c.y, w, C1);
+      C2 = fmaf(cur.c.z, w, C2);
+      T = contrib ? Tn : T;
+      stop = term ? b - rg.x + (uint32_t)k : stop;
+      done = done || term;
+    };
+    // two register sets in turn: the next record loads while one is used
+    int ka = __builtin_ctzll(m), kb = ka;
+    m &= m - 1;
+    SplatLds ra_ = sh[ka], rb_;
+    for (;;) {
+      bool more = m != 0ull;
+      if (more) {
+        kb = __builtin_ctzll(m);
+        m &= m - 1;
+        rb_ = sh[kb];
       }
-      if (!wave_done && __ballot(!done) == 0ull) wave_done = true;
+      step(ra_, ka);
+      if (!more) break;
+      more = m != 0ull;
+      if (more) {
+        ka = __builtin_ctzll(m);
+        m &= m - 1;
+        ra_ = sh[ka];
+      }
+      step(rb_, kb);
+      // whether any pixel of the wave still runs, every second entry (an
+      // entry composited after the last pixel stopped changes nothing)
+      if (__ballot(!done) == 0ull) break;
+      if (!more) break;
     }
   }
   if (inside) {
@@ -224,32 +213,29 @@ __device__ __forceinline__ int later_tile(int q, uint32_t *head, int total) {
   return q < total ? q : -1;
 }
 
+// Work item q of a launch: sub-tile q % NW of tile q / NW (in the order of
+// `order` for the persistent schedules).
 template <int TW, int TH, int SCHED, bool COUNT>
-__global__ void __launch_bounds__(TW * TH)
-k_blend_fwd(int total_tiles, const uint32_t *__restrict__ order, uint32_t *__restrict__ head,
+__global__ void __launch_bounds__(64)
+k_blend_fwd(int total_items, const uint32_t *__restrict__ order, uint32_t *__restrict__ head,
             int n, int W, int H, int GW, int tiles_per_view, const uint2 *__restrict__ ranges,
             const uint32_t *__restrict__ vals, const float4 *__restrict__ rec,
             float *__restrict__ image, float *__restrict__ final_T, uint32_t *__restrict__ last,
             unsigned long long *__restrict__ eval_count) {
   constexpr int NW = TW * TH / 64;
-  __shared__ unsigned long long s_ev[NW];
   uint32_t evals = 0;
-  for (int q = first_tile<SCHED>(head, total_tiles); q >= 0;
-       q = later_tile<SCHED>(q, head, total_tiles))
-    blend_fwd_tile<TW, TH, COUNT>(SCHED == kPerTile ? q : (int)order[q], n, W, H, GW,
-                                  tiles_per_view, ranges, vals, rec, image, final_T, last, evals);
+  for (int q = first_tile<SCHED>(head, total_items); q >= 0;
+       q = later_tile<SCHED>(q, head, total_items)) {
+    const int ti = q / NW;
+    blend_fwd_sub<TW, TH, COUNT>(SCHED == kPerTile ? ti : (int)order[ti], q - ti * NW, n, W, H,
+                                 GW, tiles_per_view, ranges, vals, rec, image, final_T, last,
+                                 evals);
+  }
   if (COUNT) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     unsigned long long ev = evals;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) ev += __shfl_xor(ev, o, 64);
-    if (lane == 0) s_ev[wave] = ev;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      unsigned long long tot = 0;
-      for (int w = 0; w < NW; ++w) tot += s_ev[w];
-      if (tot) atomicAdd(eval_count, tot);
-    }
+    if (threadIdx.x == 0 && ev) atomicAdd(eval_count, ev);
   }
 }
 
@@ -307,29 +293,28 @@ __device__ __forceinline__ float wave_transpose_sum10(const float v[10], int lan
   return x;
 }
 
+// One 8x8 sub-tile of a tile's backward, by one wave: the list from the
+// wave's furthest stop towards the front, 64 entries at a time staged in LDS
+// with their Gaussian ids, walked back to front.
 template <int TW, int TH>
-__device__ __forceinline__ void blend_bwd_tile(int tile, int n, int W, int H, int GW,
-                                               int tiles_per_view,
-                                               const uint2 *__restrict__ ranges,
-                                               const uint32_t *__restrict__ vals,
-                                               const float4 *__restrict__ rec,
-                                               const float *__restrict__ final_T,
-                                               const uint32_t *__restrict__ last,
-                                               const float *__restrict__ dimg,
-                                               double *__restrict__ sgrad) {
-  constexpr int BS = TW * TH;
-  constexpr int NW = BS / 64;
+__device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, int H, int GW,
+                                              int tiles_per_view,
+                                              const uint2 *__restrict__ ranges,
+                                              const uint32_t *__restrict__ vals,
+                                              const float4 *__restrict__ rec,
+                                              const float *__restrict__ final_T,
+                                              const uint32_t *__restrict__ last,
+                                              const float *__restrict__ dimg,
+                                              double *__restrict__ sgrad) {
   constexpr int SUBW = TW / 8;
-  __shared__ SplatLds sh[BS];
-  __shared__ uint32_t s_gid[BS];
-  __shared__ uint32_t s_max[NW];
-  __shared__ uint64_t s_meet[NW][NW];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ SplatLds sh[64];
+  __shared__ uint32_t s_gid[64];
+  const int lane = threadIdx.x & 63;
   const int v = tile / tiles_per_view;
   const int t = tile - v * tiles_per_view;
   const int tx = t % GW, ty = t / GW;
-  const int sx0 = tx * TW + (wave % SUBW) * 8;
-  const int sy0 = ty * TH + (wave / SUBW) * 8;
+  const int sx0 = tx * TW + (sub % SUBW) * 8;
+  const int sy0 = ty * TH + (sub / SUBW) * 8;
   const int px = sx0 + (lane & 7);
   const int py = sy0 + (lane >> 3);
   const bool inside = px < W && py < H;
@@ -347,27 +332,18 @@ __device__ __forceinline__ void blend_bwd_tile(int tile, int n, int W, int H, in
     g1 = dimg[((int64_t)v * 3 + 1) * plane + pix];
     g2 = dimg[((int64_t)v * 3 + 2) * plane + pix];
   }
-  // furthest list position reached by any pixel of the wave / workgroup
-  uint32_t wave_reach = my_last;
+  // furthest list position reached by any pixel of the wave
+  uint32_t reach = my_last;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) wave_reach = max(wave_reach, (uint32_t)__shfl_xor(wave_reach, o, 64));
-  if (lane == 0) s_max[wave] = wave_reach;
-  __syncthreads();
-  uint32_t reach = 0;
-  uint32_t sub_reach[NW];
-#pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    sub_reach[w] = s_max[w];
-    reach = max(reach, s_max[w]);
-  }
+  for (int o = 32; o > 0; o >>= 1) reach = max(reach, (uint32_t)__shfl_xor(reach, o, 64));
   if (reach == 0) return;
   float B0 = 0.f, B1 = 0.f, B2 = 0.f;  // colour seen behind the current splat
-  const int nbatch = (int)((reach + BS - 1) / BS);
+  const int nbatch = (int)((reach + 63) / 64);
   const int vidx = sum10_index(lane);
   // the lane that adds value vidx to the splat's gradient (one per value: the
   // first of its quad, and for value 5 h + 2, which 16 lanes hold, the one
-  // with r = b3 = 0), and the factor on
-  // its own wave sum for the values the conic does not enter
+  // with r = b3 = 0), and the factor on its own wave sum for the values the
+  // conic does not enter
   const bool lead = (lane & 3) == 0 && (((lane >> 2) & 1) == 0 || ((lane >> 3) & 3) == 0);
   const float k_self = (vidx == 2 || vidx == 4) ? -0.5f : (vidx == 3 ? -1.0f : 1.0f);
   // per-lane selectors of the conic entries, which also undo the records'
@@ -382,7 +358,7 @@ __device__ __forceinline__ void blend_bwd_tile(int tile, int n, int W, int H, in
   float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra;
   uint32_t rgid = 0;
   auto fetch = [&](int bi) {
-    const uint32_t p = (uint32_t)bi * BS + threadIdx.x;
+    const uint32_t p = (uint32_t)bi * 64 + (uint32_t)lane;
     if (p < reach) {
       rgid = vals[rg.x + p];
       const float4 *r = rec + 3 * (base + rgid);
@@ -393,131 +369,120 @@ __device__ __forceinline__ void blend_bwd_tile(int tile, int n, int W, int H, in
   };
   fetch(nbatch - 1);
   for (int bi = nbatch - 1; bi >= 0; --bi) {
-    const uint32_t p0 = (uint32_t)bi * BS;
-    __syncthreads();
-    const uint32_t p = p0 + threadIdx.x;
-    const bool valid = p < reach;
-    if (valid) {
-      s_gid[threadIdx.x] = rgid;
-      sh[threadIdx.x].a = ra;
-      sh[threadIdx.x].b = rb;
-      sh[threadIdx.x].c = rc;
-    }
-    // entries meeting each sub-tile before that sub-tile's furthest stop
+    const uint32_t p0 = (uint32_t)bi * 64;
+    wave_lds_sync();  // the previous batch's records have been read
+    uint64_t m;
     {
+      const bool valid = p0 + (uint32_t)lane < reach;
+      if (valid) {
+        s_gid[lane] = rgid;
+        sh[lane].a = ra;
+        sh[lane].b = rb;
+        sh[lane].c = rc;
+      }
+      // entries before the wave's furthest stop whose span meets the sub-tile
       const uint32_t sx = __float_as_uint(rb.z), sy = __float_as_uint(rb.w);
-      const int ex0 = (int)(sx & 0xFFFF), ex1 = (int)(sx >> 16);
-      const int ey0 = (int)(sy & 0xFFFF), ey1 = (int)(sy >> 16);
-      const int bx = tx * TW, by = ty * TH;
-#pragma unroll
-      for (int j = 0; j < NW; ++j) {
-        const int qx = bx + (j % SUBW) * 8, qy = by + (j / SUBW) * 8;
-        const bool m = valid && p < sub_reach[j] && ex0 <= qx + 7 && ex1 >= qx &&
-                       ey0 <= qy + 7 && ey1 >= qy;
-        const uint64_t bal = __ballot(m);
-        if (lane == 0) s_meet[j][wave] = bal;
-      }
+      m = __ballot(valid && (int)(sx & 0xFFFF) <= sx0 + 7 && (int)(sx >> 16) >= sx0 &&
+                   (int)(sy & 0xFFFF) <= sy0 + 7 && (int)(sy >> 16) >= sy0);
     }
-    __syncthreads();
+    wave_lds_sync();
     if (bi > 0) fetch(bi - 1);
-    // entries meeting this wave's sub-tile before its furthest stop, back to
-    // front; the next entry's record is read while the current one is done
-#pragma unroll 1
-    for (int word = NW - 1; word >= 0; --word) {
-      uint64_t m = uniform_mask(s_meet[wave][word]);
-      if (m == 0ull) continue;
-      // gradient of entry k (record cur, Gaussian gid)
-      auto step = [&](const SplatLds &cur, int k, uint32_t gid) {
-        const uint32_t pos = p0 + (uint32_t)k;
-        const SplatEval e = eval_splat(cur, px, py, fx, fy);
-        const bool ok = inside && pos < my_last && e.ok;
-        if (__ballot(ok) == 0ull) return;
-        // branch-free: lanes without the pair take alpha~ = 0 and dL/dalpha~ = 0,
-        // so every value below is 0 there and B, T stay as they are (bit for
-        // bit: colours and B are finite and non-negative, 1 - 0 = 1 and its
-        // reciprocal is exact)
-        const float mk = cur.c.w;
-        const float at = ok ? mk * e.alpha : 0.0f;
-        const float om = 1.0f - at;
-        // T in front of this splat (hardware reciprocal, 1 ulp: the
-        // recovered T drifts by about one ulp per blended splat)
-        const float Tb = (at == 0.0f) ? T : T * __builtin_amdgcn_rcpf(om);
-        const float dsum = fmaf(g0, cur.c.x - B0, fmaf(g1, cur.c.y - B1, g2 * (cur.c.z - B2)));
-        const float dat = ok ? Tb * dsum : 0.0f;
-        const float wcol = at * Tb;
-        float d[10];
-        d[6] = g0 * wcol;
-        d[7] = g1 * wcol;
-        d[8] = g2 * wcol;
-        d[9] = dat * e.alpha;
-        // moments of dL/dpower over the pixels (zero through the alpha clamp);
-        // the conic enters after the wave sum: dL/dpx = A Sx + B Sy,
-        // dL/dpy = B Sx + C Sy, dL/dA = -Sxx / 2, dL/dB = -Sxy, dL/dC = -Syy / 2
-        const float dal = e.clamped ? 0.0f : mk * dat;
-        d[5] = dal * e.G;
-        const float dp = dal * e.alpha;
-        d[0] = dp * e.dx;
-        d[1] = dp * e.dy;
-        d[2] = d[0] * e.dx;
-        d[3] = d[0] * e.dy;
-        d[4] = d[1] * e.dy;
-        B0 = fmaf(cur.c.x, at, om * B0);
-        B1 = fmaf(cur.c.y, at, om * B1);
-        B2 = fmaf(cur.c.z, at, om * B2);
-        T = Tb;
-        const float tot = wave_transpose_sum10(d, lane);
-        // lanes 0-3 hold Sx and lanes 8-11 hold Sy: each reads the other
-        const float other = dpp<kDppRowRor8>(tot);
-        // cs = A (value 0), C (value 1) or k_self; co = B for values 0 and 1
-        const float cs = fmaf(sel_a, cur.a.z, fmaf(sel_c, cur.b.x, k_rest));
-        const float co = sel_b * cur.a.w;
-        const float gv = fmaf(cs, tot, co * other);
-        if (lead && gv != 0.0f)
-          unsafeAtomicAdd(gbase + (size_t)gid * SGS_SGRAD + vidx, (double)gv);
-      };
-      // two register sets in turn: the next record loads while one is used
-      int hb = 63 - __builtin_clzll(m);
-      m &= ~(1ull << hb);
-      int ka = word * 64 + hb, kb = ka;
-      SplatLds ra_ = sh[ka], rb_;
-      uint32_t ga = s_gid[ka], gb = ga;
-      for (;;) {
-        bool more = m != 0ull;
-        if (more) {
-          hb = 63 - __builtin_clzll(m);
-          m &= ~(1ull << hb);
-          kb = word * 64 + hb;
-          rb_ = sh[kb];
-          gb = s_gid[kb];
-        }
-        step(ra_, ka, ga);
-        if (!more) break;
-        more = m != 0ull;
-        if (more) {
-          hb = 63 - __builtin_clzll(m);
-          m &= ~(1ull << hb);
-          ka = word * 64 + hb;
-          ra_ = sh[ka];
-          ga = s_gid[ka];
-        }
-        step(rb_, kb, gb);
-        if (!more) break;
+    if (m == 0ull) continue;
+    // gradient of entry k (record cur, Gaussian gid)
+    auto step = [&](const SplatLds &cur, int k, uint32_t gid) {
+      const uint32_t pos = p0 + (uint32_t)k;
+      const SplatEval e = eval_splat(cur, px, py, fx, fy);
+      const bool ok = inside && pos < my_last && e.ok;
+      if (__ballot(ok) == 0ull) return;
+      // branch-free: lanes without the pair take alpha~ = 0 and dL/dalpha~ = 0,
+      // so every value below is 0 there and B, T stay as they are (bit for
+      // bit: colours and B are finite and non-negative, 1 - 0 = 1 and its
+      // reciprocal is exact)
+      const float mk = cur.c.w;
+      const float at = ok ? mk * e.alpha : 0.0f;
+      const float om = 1.0f - at;
+      // T in front of this splat (hardware reciprocal, 1 ulp: the
+      // recovered T drifts by about one ulp per blended splat)
+      const float Tb = (at == 0.0f) ? T : T * __builtin_amdgcn_rcpf(om);
+      const float dsum = fmaf(g0, cur.c.x - B0, fmaf(g1, cur.c.y - B1, g2 * (cur.c.z - B2)));
+      const float dat = ok ? Tb * dsum : 0.0f;
+      const float wcol = at * Tb;
+      float d[10];
+      d[6] = g0 * wcol;
+      d[7] = g1 * wcol;
+      d[8] = g2 * wcol;
+      d[9] = dat * e.alpha;
+      // moments of dL/dpower over the pixels (zero through the alpha clamp);
+      // the conic enters after the wave sum: dL/dpx = A Sx + B Sy,
+      // dL/dpy = B Sx + C Sy, dL/dA = -Sxx / 2, dL/dB = -Sxy, dL/dC = -Syy / 2
+      const float dal = e.clamped ? 0.0f : mk * dat;
+      d[5] = dal * e.G;
+      const float dp = dal * e.alpha;
+      d[0] = dp * e.dx;
+      d[1] = dp * e.dy;
+      d[2] = d[0] * e.dx;
+      d[3] = d[0] * e.dy;
+      d[4] = d[1] * e.dy;
+      B0 = fmaf(cur.c.x, at, om * B0);
+      B1 = fmaf(cur.c.y, at, om * B1);
+      B2 = fmaf(cur.c.z, at, om * B2);
+      T = Tb;
+      const float tot = wave_transpose_sum10(d, lane);
+      // lanes 0-3 hold Sx and lanes 8-11 hold Sy: each reads the other
+      const float other = dpp<kDppRowRor8>(tot);
+      // cs = A (value 0), C (value 1) or k_self; co = B for values 0 and 1
+      const float cs = fmaf(sel_a, cur.a.z, fmaf(sel_c, cur.b.x, k_rest));
+      const float co = sel_b * cur.a.w;
+      const float gv = fmaf(cs, tot, co * other);
+      if (lead && gv != 0.0f)
+        unsafeAtomicAdd(gbase + (size_t)gid * SGS_SGRAD + vidx, (double)gv);
+    };
+    // back to front, two register sets in turn: the next record loads while
+    // one is used
+    int hb = 63 - __builtin_clzll(m);
+    m &= ~(1ull << hb);
+    int ka = hb, kb = ka;
+    SplatLds ra_ = sh[ka], rb_;
+    uint32_t ga = s_gid[ka], gb = ga;
+    for (;;) {
+      bool more = m != 0ull;
+      if (more) {
+        hb = 63 - __builtin_clzll(m);
+        m &= ~(1ull << hb);
+        kb = hb;
+        rb_ = sh[kb];
+        gb = s_gid[kb];
       }
+      step(ra_, ka, ga);
+      if (!more) break;
+      more = m != 0ull;
+      if (more) {
+        hb = 63 - __builtin_clzll(m);
+        m &= ~(1ull << hb);
+        ka = hb;
+        ra_ = sh[ka];
+        ga = s_gid[ka];
+      }
+      step(rb_, kb, gb);
+      if (!more) break;
     }
   }
 }
 
 template <int TW, int TH, int SCHED>
-__global__ void __launch_bounds__(TW * TH)
-k_blend_bwd(int total_tiles, const uint32_t *__restrict__ order, uint32_t *__restrict__ head,
+__global__ void __launch_bounds__(64)
+k_blend_bwd(int total_items, const uint32_t *__restrict__ order, uint32_t *__restrict__ head,
             int n, int W, int H, int GW, int tiles_per_view, const uint2 *__restrict__ ranges,
             const uint32_t *__restrict__ vals, const float4 *__restrict__ rec,
             const float *__restrict__ final_T, const uint32_t *__restrict__ last,
             const float *__restrict__ dimg, double *__restrict__ sgrad) {
-  for (int q = first_tile<SCHED>(head, total_tiles); q >= 0;
-       q = later_tile<SCHED>(q, head, total_tiles))
-    blend_bwd_tile<TW, TH>(SCHED == kPerTile ? q : (int)order[q], n, W, H, GW, tiles_per_view,
-                           ranges, vals, rec, final_T, last, dimg, sgrad);
+  constexpr int NW = TW * TH / 64;
+  for (int q = first_tile<SCHED>(head, total_items); q >= 0;
+       q = later_tile<SCHED>(q, head, total_items)) {
+    const int ti = q / NW;
+    blend_bwd_sub<TW, TH>(SCHED == kPerTile ? ti : (int)order[ti], q - ti * NW, n, W, H, GW,
+                          tiles_per_view, ranges, vals, rec, final_T, last, dimg, sgrad);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -569,33 +534,33 @@ k_tile_order_scatter(const uint2 *__restrict__ ranges, int tiles, uint32_t *__re
   if (t < tiles) order[s_at[b] + rank] = (uint32_t)t;
 }
 
-// Workgroups resident on the device for a persistent blend kernel.
+// Workgroups (of 64 threads) resident on the device for a persistent blend
+// kernel, measured once per context and kernel variant (slot).
 template <typename K>
-int persistent_grid(K kernel, int block, int tiles) {
-  static int per_cu = 0, cus = 0;
-  if (per_cu == 0) {
+int persistent_grid(sgs_ctx *c, int slot, K kernel, int items) {
+  if (c->blend_occ[slot] == 0) {
     int dev = 0, occ = 0, n = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, block, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, 64, 0) != hipSuccess ||
         occ < 1 || n < 1)
-      return tiles;  // one workgroup per tile still drains the queue
-    per_cu = occ;
-    cus = n;
+      return items;  // one workgroup per item still drains the queue
+    c->blend_occ[slot] = occ * n;
   }
-  const int64_t g = (int64_t)per_cu * cus;
-  return (int)(g < tiles ? g : tiles);
+  const int g = c->blend_occ[slot];
+  return g < items ? g : items;
 }
 
 template <int TW, int TH, int SCHED, bool COUNT>
 hipError_t fwd_tc(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint64_t *ec) {
   const uint32_t *vals = c->pair_val[c->pair_sorted_buf];
-  const int tiles = (int)c->total_tiles;
+  const int items = (int)c->total_tiles * (TW * TH / 64);
   const int grid = SCHED == kPerTile
-                       ? tiles
-                       : persistent_grid(k_blend_fwd<TW, TH, SCHED, COUNT>, TW * TH, tiles);
-  k_blend_fwd<TW, TH, SCHED, COUNT><<<grid, TW * TH, 0, c->stream>>>(
-      tiles, c->tile_order, c->tile_bins + 66, (int)c->n, c->W, c->H, c->GW,
+                       ? items
+                       : persistent_grid(c, COUNT ? 1 : 0, k_blend_fwd<TW, TH, SCHED, COUNT>,
+                                         items);
+  k_blend_fwd<TW, TH, SCHED, COUNT><<<grid, 64, 0, c->stream>>>(
+      items, c->tile_order, c->tile_bins + 66, (int)c->n, c->W, c->H, c->GW,
       (int)c->tiles_per_view, c->ranges, vals, c->rec, image, final_T, last,
       (unsigned long long *)ec);
   return hipGetLastError();
@@ -611,11 +576,11 @@ hipError_t fwd_t(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint6
 template <int TW, int TH, int SCHED>
 hipError_t bwd_t(sgs_ctx *c, const float *final_T, const uint32_t *last, const float *dimg) {
   const uint32_t *vals = c->pair_val[c->pair_sorted_buf];
-  const int tiles = (int)c->total_tiles;
-  const int grid = SCHED == kPerTile ? tiles
-                                     : persistent_grid(k_blend_bwd<TW, TH, SCHED>, TW * TH, tiles);
-  k_blend_bwd<TW, TH, SCHED><<<grid, TW * TH, 0, c->stream>>>(
-      tiles, c->tile_order, c->tile_bins + 67, (int)c->n, c->W, c->H, c->GW,
+  const int items = (int)c->total_tiles * (TW * TH / 64);
+  const int grid =
+      SCHED == kPerTile ? items : persistent_grid(c, 2, k_blend_bwd<TW, TH, SCHED>, items);
+  k_blend_bwd<TW, TH, SCHED><<<grid, 64, 0, c->stream>>>(
+      items, c->tile_order, c->tile_bins + 67, (int)c->n, c->W, c->H, c->GW,
       (int)c->tiles_per_view, c->ranges, vals, c->rec, final_T, last, dimg, c->splat_grad);
   return hipGetLastError();
 }

@@ -49,6 +49,7 @@ struct sgs_ctx {
   int64_t tiles_per_view = 0, total_tiles = 0;
   float tau = 1.0f;
   int schedule = 0;               // blend launch schedule (sgs_options.schedule)
+  int blend_occ[3] = {0, 0, 0};   // resident blend workgroups (fwd, fwd counting, bwd); 0 unknown
   bool scene_set = false;
   bool rendered = false;
   sgs_camera *d_cams = nullptr;
@@ -361,6 +362,14 @@ __device__ __forceinline__ int32_t sgs_code_of(float y, float q, bool &ok) {
 // error; it is negative from |y rq| = 2^20 on, so k stays far inside int32).
 // Otherwise (near a tie, large, not finite) the division decides.  This one
 // returns rint(fl32(y / q)) as a float; sgs_code_fast below, the int32 code.
+// Ordering of the LDS accesses of one wave among themselves (lanes of a wave
+// read what other lanes of the same wave wrote; no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // sgs_product_decides(t, k): whether k = rint(t), t = y rq, is that integer.
 __device__ __forceinline__ bool sgs_product_decides(float t, float k) {
   return fabsf(t - k) < __fmaf_rn(-fabsf(t), 4.76837158203125e-7f, 0.5f);

@@ -261,14 +261,6 @@ __device__ __forceinline__ uint32_t scanned_offset(const uint32_t *__restrict__ 
 __device__ __forceinline__ int lds_pad(int i) { return i ^ ((i >> 4) & 15); }
 constexpr int kTilePad = kTile;
 
-// Ordering of the LDS accesses of one wave among themselves (lanes of a wave
-// read what other lanes of the same wave wrote; no workgroup barrier).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Scatter of one pass for the block's elements in the wave-segment layout:
 // wave w holds elements w * IT * 64 + r * 64 + lane of the block in kr[r],
 // vr[r], so the input order is (wave, round, lane).  Each wave ranks its own
