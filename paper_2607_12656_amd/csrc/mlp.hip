@@ -234,14 +234,25 @@ __device__ __forceinline__ float tile_fwd_masks(const MlpLds &L, const bf16x4 xb
 __device__ __forceinline__ void features(const float *__restrict__ y, int64_t npad, int64_t r,
                                          bool valid, const float *s_rq, const float *s_min,
                                          int lane, bf16x4 xb[8]) {
+  // all 32 loads first, branch-free (rows past n and padding channels read
+  // entry 0 of channel 0 and are dropped), then the arithmetic
+  const int64_t rr = valid ? r : 0;
+  float yv[8][4];
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int j = 8 * s + 4 * (lane >> 5) + jj;
+      yv[s][jj] = y[(j < SGS_NCH ? j : 0) * npad + rr];
+    }
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     float v[4];
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
       const int j = 8 * s + 4 * (lane >> 5) + jj;
-      float uu = 0.0f;
-      if (valid && j < SGS_NCH) uu = (y[j * npad + r] - s_min[j]) * s_rq[j];
+      const int jc = j < SGS_NCH ? j : 0;
+      const float uu = (valid && j < SGS_NCH) ? (yv[s][jj] - s_min[jc]) * s_rq[jc] : 0.0f;
       v[jj] = __log2f(1.0f + uu);
     }
     xb[s] = pack4(v[0], v[1], v[2], v[3]);
