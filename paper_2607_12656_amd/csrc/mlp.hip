@@ -343,7 +343,9 @@ __global__ void k_mlp_rate_finish(int nb, const double *__restrict__ partial, in
 // signs the forward kept (no forward recompute, so only the backward
 // weights sit in LDS).  Adds into grad_params, per-block step partials,
 // grad_score (mask mode 1) / grad_hard_mask.
-__global__ void __launch_bounds__(kThreads, 2)
+// One wave per SIMD: its 344 registers (VGPRs and AGPRs) fit without
+// spilling; at two waves it spilled 160 bytes per lane and took 1.3x longer.
+__global__ void __launch_bounds__(kThreads, 1)
 k_mlp_rate_bwd(int64_t n, int64_t npad, int64_t n_hat, float weight, float tau, int mode,
                const bf16x4 *__restrict__ packed, const float *__restrict__ th,
                const float *__restrict__ y, const float *__restrict__ q,
