@@ -74,6 +74,7 @@ void free_scene(sgs_ctx *c) {
   dfree(c->ranges);
   dfree(c->tile_order);
   dfree(c->tile_bins);
+  dfree(c->eval_slots);
   dfree(c->scan_tmp);
   dfree(c->sort_hist);
   dfree(c->red_tmp);
@@ -229,8 +230,10 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   SGS_ALLOC(c->ranges, c->total_tiles);
   SGS_ALLOC(c->tile_order, c->total_tiles);
   SGS_ALLOC(c->tile_bins, SGS_TILE_BINS);
+  SGS_ALLOC(c->eval_slots, SGS_EVAL_SLOTS);
   SGS_ALLOC(c->d_pairs_total, 4);
   e = hipMemset(c->d_pairs_total, 0, 4 * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemset(c->eval_slots, 0, SGS_EVAL_SLOTS * sizeof(uint64_t));
   if (e != hipSuccess) { free_scene(c); return hip_fail(c, e, "set_scene clear"); }
   c->fixed_cap = false;
   const int64_t red_q = quant_partial_words(n);

@@ -235,8 +235,21 @@ k_blend_fwd(int total_items, const uint32_t *__restrict__ order, uint32_t *__res
     unsigned long long ev = evals;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) ev += __shfl_xor(ev, o, 64);
-    if (threadIdx.x == 0 && ev) atomicAdd(eval_count, ev);
+    // one of SGS_EVAL_SLOTS counters per workgroup (a single counter for
+    // 2e5 workgroups serializes); k_eval_finish adds them up
+    if (threadIdx.x == 0 && ev) atomicAdd(eval_count + (blockIdx.x & (SGS_EVAL_SLOTS - 1)), ev);
   }
+}
+
+// Adds the slot counters of the blend into the caller's count and clears them
+// for the next blend (one wave).
+__global__ void k_eval_finish(unsigned long long *__restrict__ slots,
+                              unsigned long long *__restrict__ eval_count) {
+  unsigned long long v = slots[threadIdx.x];
+  slots[threadIdx.x] = 0ull;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (threadIdx.x == 0 && v) atomicAdd(eval_count, v);
 }
 
 // Sum each of v[0..9] over the 64 lanes of the wave with a transposing
@@ -562,7 +575,10 @@ hipError_t fwd_tc(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint
   k_blend_fwd<TW, TH, SCHED, COUNT><<<grid, 64, 0, c->stream>>>(
       items, c->tile_order, c->tile_bins + 66, (int)c->n, c->W, c->H, c->GW,
       (int)c->tiles_per_view, c->ranges, vals, c->rec, image, final_T, last,
-      (unsigned long long *)ec);
+      (unsigned long long *)c->eval_slots);
+  if (COUNT)
+    k_eval_finish<<<1, SGS_EVAL_SLOTS, 0, c->stream>>>((unsigned long long *)c->eval_slots,
+                                                        (unsigned long long *)ec);
   return hipGetLastError();
 }
 

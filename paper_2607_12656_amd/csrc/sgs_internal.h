@@ -77,6 +77,7 @@ struct sgs_ctx {
   uint2 *ranges = nullptr;        // [total_tiles]
   uint32_t *tile_order = nullptr; // [total_tiles] blend order, longest lists first
   uint32_t *tile_bins = nullptr;  // [SGS_TILE_BINS] order counters and blend queue heads
+  uint64_t *eval_slots = nullptr; // [SGS_EVAL_SLOTS] evaluation counts of one blend, zero between
 
   // reusable temporaries
   uint32_t *scan_tmp = nullptr;   int64_t scan_tmp_words = 0;
@@ -192,6 +193,7 @@ hipError_t launch_bin_pairs(sgs_ctx *c);   // depth order -> pairs -> tile sort 
 hipError_t launch_depth_order(sgs_ctx *c); // depth sort + scan (writes d_pairs_total)
 // blend.hip
 #define SGS_TILE_BINS 68
+#define SGS_EVAL_SLOTS 64
 // codec.hip
 int64_t fl_scratch_words(int64_t n);
 hipError_t launch_adam(sgs_ctx *c, const sgs_adam_options *o, float *params, float *pm,
