@@ -854,8 +854,12 @@ hipError_t launch_mlp_infer(sgs_ctx *c, const void *packed, const float *theta,
   return hipGetLastError();
 }
 
+// Batch rows per workgroup of the weight-gradient GEMMs: 256 gives a 65,536-row
+// batch 256 workgroups (with 2048, 32 of them left most compute units idle).
+constexpr int64_t kWgradChunk = 256;
+
 int64_t mlp_train_scratch_bytes(int64_t B) {
-  const int64_t chunks = (B + 2047) / 2048;
+  const int64_t chunks = (B + kWgradChunk - 1) / kWgradChunk;
   return B * (64 + 3 * 128) * 2 + B * 128 * 4 + B * 4 + chunks * 24 * 1024 * 4 + 4096 * 8 + 256;
 }
 
@@ -875,7 +879,7 @@ hipError_t launch_mlp_train_step(sgs_ctx *c, float *theta, float *m, float *v, v
   uint16_t *DZ1T = (uint16_t *)take(B * 128 * 2);
   float *H2T = (float *)take(B * 128 * 4);
   float *df = (float *)take(B * 4);
-  const int64_t chunk = 2048;
+  const int64_t chunk = kWgradChunk;
   const int nchunks = (int)((B + chunk - 1) / chunk);
   float *part = (float *)take((int64_t)nchunks * 24 * 1024 * 4);
   const int nb = mlp_grid(B);
