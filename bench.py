@@ -219,9 +219,9 @@ def main():
                          "formation iteration at 3M x 8 views (learned rate in the loop, "
                          "Gumbel-sigmoid mask, Adam), learned vs plain rate")
     ap.add_argument("--tile", default=None, help="16x16 | 8x8 | 32x8 | auto")
-    ap.add_argument("--schedule", default=None, choices=("tile", "stride", "queue"),
-                    help="blend launch schedule when --tile names a shape (default: stride "
-                         "on the 1M workload, where the autotuner picks it, else tile)")
+    ap.add_argument("--schedule", default=None, choices=("tile", "stride", "queue", "block"),
+                    help="blend launch schedule when --tile names a shape (default: block "
+                         "on the 1M workload, the fastest there, else tile)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip graph / learned / MLP / codec / SSIM / rate-variant legs")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -276,7 +276,7 @@ def main():
         tile, schedule = tune["tile"], tune["schedule"]
     else:
         tile = tuple(int(v) for v in tile_choice.split("x"))
-        schedule = args.schedule or ("stride" if args.workload == "c2" else "tile")
+        schedule = args.schedule or ("block" if args.workload == "c2" else "tile")
     rd = RDStep(ctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height, tile=tile,
                 schedule=schedule)
     if args.workload == "c5":

@@ -71,10 +71,13 @@ typedef struct {
 typedef struct {
   int32_t tile_w, tile_h; /* blend tile: 8x8, 16x16 (default) or 32x8 */
   float tau;              /* Gumbel-sigmoid temperature (default 1) */
-  int32_t schedule;       /* blend launch: 0 one workgroup per tile (default),
-                             1 resident workgroups striding over the tiles
-                             ordered by list length, 2 the same tiles taken
-                             from an atomic queue; results do not depend on it */
+  int32_t schedule;       /* blend launch (one wave per 8x8 sub-tile): 0 one
+                             workgroup per sub-tile (default), 1 resident
+                             workgroups striding over the sub-tiles of the
+                             tiles ordered by list length, 2 the same taken
+                             from an atomic queue, 3 resident workgroups of one
+                             whole tile each (a wave per sub-tile) striding
+                             over that order; results do not depend on it */
   int32_t reserved[4];    /* must be zero */
 } sgs_options;
 

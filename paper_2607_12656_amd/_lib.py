@@ -53,7 +53,7 @@ class sgs_adam_options(C.Structure):
                 ("step", C.c_int64)]
 
 
-SCHEDULES = {"tile": 0, "stride": 1, "queue": 2}
+SCHEDULES = {"tile": 0, "stride": 1, "queue": 2, "block": 3}
 
 
 P = C.c_void_p
@@ -206,8 +206,10 @@ class Context:
     # ---- the C ABI, one method per entry point -----------------------------
     def set_scene(self, n, npad, n_hat, cams, width, height, tile=(16, 16), tau=1.0,
                   schedule="tile"):
-        """schedule: blend launch, "tile" (one workgroup per tile), "stride" or
-        "queue" (resident workgroups over the tiles ordered by list length)."""
+        """schedule: blend launch, one wave per 8x8 sub-tile: "tile" (one
+        workgroup per sub-tile), "stride" or "queue" (resident workgroups over
+        the sub-tiles of the tiles ordered by list length), "block" (resident
+        workgroups of one whole tile each, striding over that order)."""
         cams = np.ascontiguousarray(cams, np.float32)
         arr = cameras(cams)
         opt = sgs_options(tile[0], tile[1], tau, SCHEDULES[schedule], (C.c_int32 * 4)())

@@ -1,10 +1,11 @@
 """Autotuner for the RD step: tile shape, then blend schedule.
 
 The support rule is pixel-exact, so every candidate tile shape renders the
-same image and gradients, and the blend schedule (one workgroup per tile,
-or resident workgroups over the tiles ordered by list length, striding or
-taking them from an atomic queue) only changes which workgroup blends which
-tile: the tuner may pick on speed alone.  The tile shapes are timed with the
+same image and gradients, and the blend schedule (one workgroup per 8x8
+sub-tile, or resident workgroups over the sub-tiles of the tiles ordered by
+list length, striding or taking them from an atomic queue, or resident
+workgroups of one whole tile each striding over that order) only changes
+which wave blends which sub-tile: the tuner may pick on speed alone.  The tile shapes are timed with the
 per-tile schedule, then the schedules with the best shape.  Each candidate is
 timed over whole forward + backward steps with HIP events on the step's
 stream; results are cached per (device, N, views, width, height) in a JSON
@@ -16,7 +17,7 @@ import json
 import os
 
 CANDIDATES = ((16, 16), (8, 8), (32, 8))
-SCHEDULES = ("tile", "stride", "queue")
+SCHEDULES = ("tile", "stride", "queue", "block")
 
 
 def _key(dev_name, n, V, W, H):

@@ -182,7 +182,7 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
     for (int k = 0; k < 4; ++k)
       if (opt->reserved[k] != 0) return fail(c, SGS_EINVAL, "set_scene: reserved options must be 0");
   }
-  if (schedule < 0 || schedule > 2) return fail(c, SGS_EINVAL, "set_scene: schedule must be 0, 1 or 2");
+  if (schedule < 0 || schedule > 3) return fail(c, SGS_EINVAL, "set_scene: schedule must be 0 to 3");
   if (!((tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 32 && th == 8)))
     return fail(c, SGS_EINVAL, "set_scene: tile shape must be 8x8, 16x16 or 32x8");
   if (!(tau > 0.0f)) return fail(c, SGS_EINVAL, "set_scene: tau must be > 0");

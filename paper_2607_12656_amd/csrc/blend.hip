@@ -67,7 +67,7 @@ __device__ __forceinline__ uint64_t uniform_mask(uint64_t m) {
 // record loads while one is used; the next 64 records are fetched from global
 // memory during the walk.  It stops once all its pixels have stopped.  evals
 // accumulates the lane's in-span pairs.
-template <int TW, int TH, bool COUNT>
+template <int TW, int TH, bool COUNT, int WPB>
 __device__ __forceinline__ void blend_fwd_sub(int tile, int sub, int n, int W, int H, int GW,
                                               int tiles_per_view,
                                               const uint2 *__restrict__ ranges,
@@ -77,7 +77,8 @@ __device__ __forceinline__ void blend_fwd_sub(int tile, int sub, int n, int W, i
                                               float *__restrict__ final_T,
                                               uint32_t *__restrict__ last, uint32_t &evals) {
   constexpr int SUBW = TW / 8;
-  __shared__ SplatLds sh[64];
+  __shared__ SplatLds sh_all[WPB][64];  // one region per wave of the workgroup
+  SplatLds *sh = sh_all[WPB > 1 ? (threadIdx.x >> 6) : 0];
   const int lane = threadIdx.x & 63;
   const int v = tile / tiles_per_view;
   const int t = tile - v * tiles_per_view;
@@ -198,7 +199,7 @@ __device__ __forceinline__ int next_tile(uint32_t *head, int total) {
 // the length-ordered tile list.  kQueue: a resident grid taking positions of
 // that list from an atomic queue head.  Every workgroup of a persistent grid
 // leaves its loop once the positions run out.
-enum BlendSchedule { kPerTile = 0, kStride = 1, kQueue = 2 };
+enum BlendSchedule { kPerTile = 0, kStride = 1, kQueue = 2, kTileBlock = 3 };
 
 template <int SCHED>
 __device__ __forceinline__ int first_tile(uint32_t *head, int total) {
@@ -214,22 +215,30 @@ __device__ __forceinline__ int later_tile(int q, uint32_t *head, int total) {
 }
 
 // Work item q of a launch: sub-tile q % NW of tile q / NW (in the order of
-// `order` for the persistent schedules).
+// `order` for the persistent schedules), one wave per workgroup; with
+// kTileBlock a workgroup of NW waves takes whole tiles of that order (striding),
+// wave w sub-tile w, the waves walking independently.
 template <int TW, int TH, int SCHED, bool COUNT>
-__global__ void __launch_bounds__(64)
-k_blend_fwd(int total_items, const uint32_t *__restrict__ order, uint32_t *__restrict__ head,
+__global__ void __launch_bounds__(SCHED == kTileBlock ? TW * TH : 64)
+k_blend_fwd(int total, const uint32_t *__restrict__ order, uint32_t *__restrict__ head,
             int n, int W, int H, int GW, int tiles_per_view, const uint2 *__restrict__ ranges,
             const uint32_t *__restrict__ vals, const float4 *__restrict__ rec,
             float *__restrict__ image, float *__restrict__ final_T, uint32_t *__restrict__ last,
             unsigned long long *__restrict__ eval_count) {
   constexpr int NW = TW * TH / 64;
   uint32_t evals = 0;
-  for (int q = first_tile<SCHED>(head, total_items); q >= 0;
-       q = later_tile<SCHED>(q, head, total_items)) {
-    const int ti = q / NW;
-    blend_fwd_sub<TW, TH, COUNT>(SCHED == kPerTile ? ti : (int)order[ti], q - ti * NW, n, W, H,
-                                 GW, tiles_per_view, ranges, vals, rec, image, final_T, last,
-                                 evals);
+  if (SCHED == kTileBlock) {
+    for (int q = (int)blockIdx.x; q < total; q += (int)gridDim.x)
+      blend_fwd_sub<TW, TH, COUNT, NW>((int)order[q], (int)(threadIdx.x >> 6), n, W, H, GW,
+                                       tiles_per_view, ranges, vals, rec, image, final_T, last,
+                                       evals);
+  } else {
+    for (int q = first_tile<SCHED>(head, total); q >= 0; q = later_tile<SCHED>(q, head, total)) {
+      const int ti = q / NW;
+      blend_fwd_sub<TW, TH, COUNT, 1>(SCHED == kPerTile ? ti : (int)order[ti], q - ti * NW, n,
+                                      W, H, GW, tiles_per_view, ranges, vals, rec, image,
+                                      final_T, last, evals);
+    }
   }
   if (COUNT) {
     unsigned long long ev = evals;
@@ -237,7 +246,8 @@ k_blend_fwd(int total_items, const uint32_t *__restrict__ order, uint32_t *__res
     for (int o = 32; o > 0; o >>= 1) ev += __shfl_xor(ev, o, 64);
     // one of SGS_EVAL_SLOTS counters per workgroup (a single counter for
     // 2e5 workgroups serializes); k_eval_finish adds them up
-    if (threadIdx.x == 0 && ev) atomicAdd(eval_count + (blockIdx.x & (SGS_EVAL_SLOTS - 1)), ev);
+    if ((threadIdx.x & 63) == 0 && ev)
+      atomicAdd(eval_count + (blockIdx.x & (SGS_EVAL_SLOTS - 1)), ev);
   }
 }
 
@@ -309,7 +319,7 @@ __device__ __forceinline__ float wave_transpose_sum10(const float v[10], int lan
 // One 8x8 sub-tile of a tile's backward, by one wave: the list from the
 // wave's furthest stop towards the front, 64 entries at a time staged in LDS
 // with their Gaussian ids, walked back to front.
-template <int TW, int TH>
+template <int TW, int TH, int WPB>
 __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, int H, int GW,
                                               int tiles_per_view,
                                               const uint2 *__restrict__ ranges,
@@ -320,8 +330,10 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
                                               const float *__restrict__ dimg,
                                               double *__restrict__ sgrad) {
   constexpr int SUBW = TW / 8;
-  __shared__ SplatLds sh[64];
-  __shared__ uint32_t s_gid[64];
+  __shared__ SplatLds sh_all[WPB][64];  // one region per wave of the workgroup
+  __shared__ uint32_t s_gid_all[WPB][64];
+  SplatLds *sh = sh_all[WPB > 1 ? (threadIdx.x >> 6) : 0];
+  uint32_t *s_gid = s_gid_all[WPB > 1 ? (threadIdx.x >> 6) : 0];
   const int lane = threadIdx.x & 63;
   const int v = tile / tiles_per_view;
   const int t = tile - v * tiles_per_view;
@@ -483,18 +495,23 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
 }
 
 template <int TW, int TH, int SCHED>
-__global__ void __launch_bounds__(64)
-k_blend_bwd(int total_items, const uint32_t *__restrict__ order, uint32_t *__restrict__ head,
+__global__ void __launch_bounds__(SCHED == kTileBlock ? TW * TH : 64)
+k_blend_bwd(int total, const uint32_t *__restrict__ order, uint32_t *__restrict__ head,
             int n, int W, int H, int GW, int tiles_per_view, const uint2 *__restrict__ ranges,
             const uint32_t *__restrict__ vals, const float4 *__restrict__ rec,
             const float *__restrict__ final_T, const uint32_t *__restrict__ last,
             const float *__restrict__ dimg, double *__restrict__ sgrad) {
   constexpr int NW = TW * TH / 64;
-  for (int q = first_tile<SCHED>(head, total_items); q >= 0;
-       q = later_tile<SCHED>(q, head, total_items)) {
-    const int ti = q / NW;
-    blend_bwd_sub<TW, TH>(SCHED == kPerTile ? ti : (int)order[ti], q - ti * NW, n, W, H, GW,
-                          tiles_per_view, ranges, vals, rec, final_T, last, dimg, sgrad);
+  if (SCHED == kTileBlock) {
+    for (int q = (int)blockIdx.x; q < total; q += (int)gridDim.x)
+      blend_bwd_sub<TW, TH, NW>((int)order[q], (int)(threadIdx.x >> 6), n, W, H, GW,
+                                tiles_per_view, ranges, vals, rec, final_T, last, dimg, sgrad);
+  } else {
+    for (int q = first_tile<SCHED>(head, total); q >= 0; q = later_tile<SCHED>(q, head, total)) {
+      const int ti = q / NW;
+      blend_bwd_sub<TW, TH, 1>(SCHED == kPerTile ? ti : (int)order[ti], q - ti * NW, n, W, H, GW,
+                               tiles_per_view, ranges, vals, rec, final_T, last, dimg, sgrad);
+    }
   }
 }
 
@@ -547,15 +564,15 @@ k_tile_order_scatter(const uint2 *__restrict__ ranges, int tiles, uint32_t *__re
   if (t < tiles) order[s_at[b] + rank] = (uint32_t)t;
 }
 
-// Workgroups (of 64 threads) resident on the device for a persistent blend
-// kernel, measured once per context and kernel variant (slot).
+// Workgroups (of `block` threads) resident on the device for a persistent
+// blend kernel, measured once per context and kernel variant (slot).
 template <typename K>
-int persistent_grid(sgs_ctx *c, int slot, K kernel, int items) {
+int persistent_grid(sgs_ctx *c, int slot, K kernel, int items, int block) {
   if (c->blend_occ[slot] == 0) {
     int dev = 0, occ = 0, n = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, 64, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, block, 0) != hipSuccess ||
         occ < 1 || n < 1)
       return items;  // one workgroup per item still drains the queue
     c->blend_occ[slot] = occ * n;
@@ -567,12 +584,13 @@ int persistent_grid(sgs_ctx *c, int slot, K kernel, int items) {
 template <int TW, int TH, int SCHED, bool COUNT>
 hipError_t fwd_tc(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint64_t *ec) {
   const uint32_t *vals = c->pair_val[c->pair_sorted_buf];
-  const int items = (int)c->total_tiles * (TW * TH / 64);
+  const int block = SCHED == kTileBlock ? TW * TH : 64;
+  const int items = (int)c->total_tiles * (SCHED == kTileBlock ? 1 : TW * TH / 64);
   const int grid = SCHED == kPerTile
                        ? items
                        : persistent_grid(c, COUNT ? 1 : 0, k_blend_fwd<TW, TH, SCHED, COUNT>,
-                                         items);
-  k_blend_fwd<TW, TH, SCHED, COUNT><<<grid, 64, 0, c->stream>>>(
+                                         items, block);
+  k_blend_fwd<TW, TH, SCHED, COUNT><<<grid, block, 0, c->stream>>>(
       items, c->tile_order, c->tile_bins + 66, (int)c->n, c->W, c->H, c->GW,
       (int)c->tiles_per_view, c->ranges, vals, c->rec, image, final_T, last,
       (unsigned long long *)c->eval_slots);
@@ -592,10 +610,12 @@ hipError_t fwd_t(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint6
 template <int TW, int TH, int SCHED>
 hipError_t bwd_t(sgs_ctx *c, const float *final_T, const uint32_t *last, const float *dimg) {
   const uint32_t *vals = c->pair_val[c->pair_sorted_buf];
-  const int items = (int)c->total_tiles * (TW * TH / 64);
-  const int grid =
-      SCHED == kPerTile ? items : persistent_grid(c, 2, k_blend_bwd<TW, TH, SCHED>, items);
-  k_blend_bwd<TW, TH, SCHED><<<grid, 64, 0, c->stream>>>(
+  const int block = SCHED == kTileBlock ? TW * TH : 64;
+  const int items = (int)c->total_tiles * (SCHED == kTileBlock ? 1 : TW * TH / 64);
+  const int grid = SCHED == kPerTile
+                       ? items
+                       : persistent_grid(c, 2, k_blend_bwd<TW, TH, SCHED>, items, block);
+  k_blend_bwd<TW, TH, SCHED><<<grid, block, 0, c->stream>>>(
       items, c->tile_order, c->tile_bins + 67, (int)c->n, c->W, c->H, c->GW,
       (int)c->tiles_per_view, c->ranges, vals, c->rec, final_T, last, dimg, c->splat_grad);
   return hipGetLastError();
@@ -605,6 +625,7 @@ template <int TW, int TH>
 hipError_t fwd_s(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint64_t *ec) {
   SgsProfScope ps(c, SGS_PROF_BLEND_FWD);
   if (c->schedule == kStride) return fwd_t<TW, TH, kStride>(c, image, final_T, last, ec);
+  if (c->schedule == kTileBlock) return fwd_t<TW, TH, kTileBlock>(c, image, final_T, last, ec);
   if (c->schedule == kQueue) return fwd_t<TW, TH, kQueue>(c, image, final_T, last, ec);
   return fwd_t<TW, TH, kPerTile>(c, image, final_T, last, ec);
 }
@@ -613,6 +634,7 @@ template <int TW, int TH>
 hipError_t bwd_s(sgs_ctx *c, const float *final_T, const uint32_t *last, const float *dimg) {
   SgsProfScope ps(c, SGS_PROF_BLEND_BWD);
   if (c->schedule == kStride) return bwd_t<TW, TH, kStride>(c, final_T, last, dimg);
+  if (c->schedule == kTileBlock) return bwd_t<TW, TH, kTileBlock>(c, final_T, last, dimg);
   if (c->schedule == kQueue) return bwd_t<TW, TH, kQueue>(c, final_T, last, dimg);
   return bwd_t<TW, TH, kPerTile>(c, final_T, last, dimg);
 }

@@ -58,6 +58,7 @@ CASES = [
     dict(scene="gumbel", lam=0.5, mode=1, step=3),
     dict(scene="gumbel", lam=0.5, mode=2),
     dict(scene="c2", lam=2.5e-5, schedule="stride"),
+    dict(scene="c2", lam=2.5e-5, schedule="block"),
 ]
 
 

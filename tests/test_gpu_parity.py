@@ -224,7 +224,7 @@ def test_c1_full_step(orc, gctx, dev):
         grad_close(g["gmask"], r["gmhat"], name="grad mask")
 
 
-@pytest.mark.parametrize("schedule", ["stride", "queue"])
+@pytest.mark.parametrize("schedule", ["stride", "queue", "block"])
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
 def test_persistent_schedules(orc, gctx, dev, tile, schedule):
     """Resident-workgroup blend schedules (tiles ordered by list length) give
@@ -259,6 +259,7 @@ FUSED_CASES = [
     dict(kind="gumbel", mode=1, step=7),
     dict(kind="gumbel", mode=2),
     dict(kind="two_views", schedule="stride", tile=(32, 8)),
+    dict(kind="two_views", schedule="block", tile=(16, 16)),
 ]
 
 
@@ -354,11 +355,11 @@ def test_full_size_1m_workload(orc, gctx, dev):
 
 
 def test_full_size_1m_workload_fused(orc, gctx, dev):
-    """The benchmark's step (fused entry points, stride schedule, 16x16 tiles)
-    at 1M Gaussians, 1297x840: every pair, pixel and gradient against the
-    oracle."""
+    """The benchmark's step (fused entry points, whole-tile blend schedule,
+    16x16 tiles) at 1M Gaussians, 1297x840: every pair, pixel and gradient
+    against the oracle."""
     sc = synth.make_scene("c2")
-    g, r = run_pair(orc, gctx, dev, sc, lam=2.5e-5, schedule="stride", fused=True)
+    g, r = run_pair(orc, gctx, dev, sc, lam=2.5e-5, schedule="block", fused=True)
     check_structure(g, r, sc)
     check_stats(g, r, sc)
     err, frac = check_image(g, r)
