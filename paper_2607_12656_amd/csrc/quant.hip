@@ -328,8 +328,15 @@ k_fakequant_bwd_finish(int64_t nblocks, const double *__restrict__ partial, int6
                        int64_t npad, float *__restrict__ gparams, float *__restrict__ gqstep) {
   __shared__ double s_w[kQWaves];
   const int j = blockIdx.x;
-  double t = 0.0;
-  for (int64_t b = threadIdx.x; b < nblocks; b += kQThreads) t += partial[j * jstride + b * bstride];
+  // eight loads in flight per thread (a loop-carried sum would wait on each)
+  double t8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t b = threadIdx.x;
+  for (; b + 7 * kQThreads < nblocks; b += 8 * kQThreads) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t8[u] += partial[j * jstride + (b + u * kQThreads) * bstride];
+  }
+  for (; b < nblocks; b += kQThreads) t8[0] += partial[j * jstride + b * bstride];
+  double t = ((t8[0] + t8[1]) + (t8[2] + t8[3])) + ((t8[4] + t8[5]) + (t8[6] + t8[7]));
   t = sgs_wave_sum_d(t);
   if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = t;
   __syncthreads();

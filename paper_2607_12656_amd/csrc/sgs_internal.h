@@ -181,8 +181,11 @@ hipError_t ensure_tmp(sgs_ctx *c, int64_t scan_words, int64_t hist_words);
 constexpr uint32_t kPairsSaturated = 0xFFFFFFFFu;
 int64_t radix_blocks(int64_t count);       // blocks of a radix pass over count elements
 int64_t radix_hist_words(int64_t count);   // sort_hist words a radix sort of count needs
+// Exclusive scan of count words into out[0..count] (out[count] = total); the
+// total also to *total_out; with cap >= 0 total_out[1] = min(total, cap) and
+// total_out[2] |= 1 on overflow (the pair count of the fixed-capacity mode).
 hipError_t launch_exclusive_scan(sgs_ctx *c, const uint32_t *in, uint32_t *out,
-                                 int64_t count, uint32_t *total_out);
+                                 int64_t count, uint32_t *total_out, int64_t cap = -1);
 // Stable LSD radix sort of 32-bit keys with 32-bit values over bits
 // [shift0, bits) starting in buffer cur0; ping-pongs between buffer 0 and 1;
 // returns the buffer index that holds the result in *which.

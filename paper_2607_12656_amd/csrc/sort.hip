@@ -59,9 +59,11 @@ k_scan_reduce(const uint32_t *__restrict__ in, int64_t count, uint32_t *__restri
 }
 
 // single block: exclusive scan of the block sums in place; total to *total_out
+// (with cap >= 0 also total_out[1] = min(total, cap), 0 for a saturated total,
+// and bit 0 of total_out[2] set when the total exceeds cap)
 __global__ void __launch_bounds__(kThreads)
 k_scan_sums(uint32_t *__restrict__ sums, int64_t nb, uint32_t *__restrict__ total_out,
-            uint32_t *__restrict__ tail) {
+            uint32_t *__restrict__ tail, int64_t cap) {
   __shared__ uint32_t s_wave[kWaves];
   uint64_t carry = 0;  // a block sum fits in 32 bits, the total may not
   for (int64_t base = 0; base < nb; base += kThreads) {
@@ -76,6 +78,11 @@ k_scan_sums(uint32_t *__restrict__ sums, int64_t nb, uint32_t *__restrict__ tota
     const uint32_t t = carry >= kPairsSaturated ? kPairsSaturated : (uint32_t)carry;
     if (total_out) *total_out = t;
     if (tail) *tail = t;
+    if (total_out && cap >= 0) {
+      // a saturated total leaves the offsets wrapped: emit nothing
+      total_out[1] = t == kPairsSaturated ? 0u : (uint32_t)((int64_t)t < cap ? (int64_t)t : cap);
+      if ((int64_t)t > cap) total_out[2] |= 1u;
+    }
   }
 }
 
@@ -635,16 +642,6 @@ k_ranges_search(const uint32_t *__restrict__ tile_key, int64_t P_static,
   ranges[t] = lo0 < lo1 ? make_uint2((uint32_t)lo0, (uint32_t)lo1) : make_uint2(0u, 0u);
 }
 
-// counts[0] = total pairs (from the scan); counts[1] = min(total, cap);
-// counts[2] |= 1 when the total exceeded the capacity.
-__global__ void k_clamp_count(uint32_t *__restrict__ counts, int64_t cap) {
-  if (threadIdx.x != 0) return;
-  const int64_t total = counts[0];
-  // a saturated total leaves the offsets wrapped: emit nothing
-  counts[1] = total == kPairsSaturated ? 0u : (uint32_t)(total < cap ? total : cap);
-  if (total > cap) counts[2] |= 1u;
-}
-
 }  // namespace
 
 hipError_t ensure_tmp(sgs_ctx *c, int64_t scan_words, int64_t hist_words) {
@@ -685,15 +682,15 @@ int64_t radix_hist_words(int64_t count) {
 
 // scan_tmp must hold ceil(count / kTile) words
 hipError_t launch_exclusive_scan(sgs_ctx *c, const uint32_t *in, uint32_t *out, int64_t count,
-                                 uint32_t *total_out) {
+                                 uint32_t *total_out, int64_t cap) {
   const int64_t nb = (count + kTile - 1) / kTile;
   if (nb == 0) {
-    k_scan_sums<<<1, kThreads, 0, c->stream>>>(c->scan_tmp, 0, total_out, out);
+    k_scan_sums<<<1, kThreads, 0, c->stream>>>(c->scan_tmp, 0, total_out, out, cap);
     return hipGetLastError();
   }
   if (nb > c->scan_tmp_words) return hipErrorInvalidValue;
   k_scan_reduce<<<(unsigned)nb, kThreads, 0, c->stream>>>(in, count, c->scan_tmp);
-  k_scan_sums<<<1, kThreads, 0, c->stream>>>(c->scan_tmp, nb, total_out, out + count);
+  k_scan_sums<<<1, kThreads, 0, c->stream>>>(c->scan_tmp, nb, total_out, out + count, cap);
   k_scan_down<<<(unsigned)nb, kThreads, 0, c->stream>>>(in, count, c->scan_tmp, out);
   return hipGetLastError();
 }
@@ -781,7 +778,9 @@ hipError_t launch_depth_order(sgs_ctx *c) {
   uint32_t *tmp = c->depth_key[which ^ 1];
   k_gather_bins<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(c->depth_val[which], c->bin_splat,
                                                                c->vn, tmp, c->bin_rec);
-  return launch_exclusive_scan(c, tmp, c->offsets, c->vn, c->d_pairs_total);
+  // with a fixed pair capacity the scan also clamps the count to it
+  return launch_exclusive_scan(c, tmp, c->offsets, c->vn, c->d_pairs_total,
+                               c->fixed_cap ? c->cap_limit : -1);
 }
 
 // Pairs -> stable tile sort -> ranges.  With a fixed pair capacity the pair
@@ -795,7 +794,6 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
   {
     // pair emission fused with the pass over the low digit: buffer 1
     SgsProfScope ps(c, SGS_PROF_DUPLICATE);
-    if (dev) k_clamp_count<<<1, 64, 0, c->stream>>>(c->d_pairs_total, cap);
     if (P > 0) {
       SortBufs b;
       if (!sort_bufs(c, P, b) || b.nb + 1 > c->blk_start_words) return hipErrorInvalidValue;
