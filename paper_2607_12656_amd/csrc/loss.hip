@@ -13,12 +13,22 @@ k_l1(const float *__restrict__ img, const float *__restrict__ tgt, int64_t count
      float *__restrict__ dimg, double *__restrict__ partial) {
   __shared__ double s_w[kThreads / 64];
   const int64_t base = (int64_t)blockIdx.x * kThreads * kItems;
+  // all loads first (entries past count read entry 0 and are dropped), then
+  // the arithmetic and the stores
+  float a[kItems], t[kItems];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
+    const int64_t ic = i < count ? i : 0;
+    a[k] = img[ic];
+    t[k] = tgt[ic];
+  }
   double acc = 0.0;
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
     const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
     if (i < count) {
-      const float d = img[i] - tgt[i];
+      const float d = a[k] - t[k];
       acc += (double)fabsf(d);
       dimg[i] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
     }

@@ -281,12 +281,22 @@ k_fakequant_bwd(int64_t n, int64_t npad, const float *__restrict__ params,
   const float *grow = gq_in + j * npad;
   float *orow = gparams + j * npad;
   double acc = 0.0;
+  // all loads first (i + 3 < npad for i < n; lanes past n read the row's first
+  // entries and drop them)
+  float4 y4[kRVec], g4[kRVec];
+#pragma unroll
+  for (int r = 0; r < kRVec; ++r) {
+    const int64_t i = c0 + ((int64_t)r * kQThreads + threadIdx.x) * 4;
+    const int64_t ic = i < n ? i : 0;
+    y4[r] = *reinterpret_cast<const float4 *>(yrow + ic);
+    g4[r] = *reinterpret_cast<const float4 *>(grow + ic);
+  }
 #pragma unroll
   for (int r = 0; r < kRVec; ++r) {
     const int64_t i = c0 + ((int64_t)r * kQThreads + threadIdx.x) * 4;
     if (i < n) {
-      const float4 y = *reinterpret_cast<const float4 *>(yrow + i);
-      const float4 g = *reinterpret_cast<const float4 *>(grow + i);
+      const float4 y = y4[r];
+      const float4 g = g4[r];
       const float yv[4] = {y.x, y.y, y.z, y.w}, gv[4] = {g.x, g.y, g.z, g.w};
 #pragma unroll
       for (int e = 0; e < 4; ++e) {

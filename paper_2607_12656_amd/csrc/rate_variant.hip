@@ -38,11 +38,18 @@ k_lap_sum(int64_t n, int64_t npad, const float *__restrict__ y, int nc,
   const int j = blockIdx.y;
   const int64_t chunk = blockIdx.x;
   const float *row = y + j * npad;
+  // all loads first (entries past n read entry 0 and are dropped)
+  float v[kVItems];
+#pragma unroll
+  for (int e = 0; e < kVItems; ++e) {
+    const int64_t i = chunk * kVChunk + (int64_t)e * kVThreads + threadIdx.x;
+    v[e] = row[i < n ? i : 0];
+  }
   double acc = 0.0;
 #pragma unroll
   for (int e = 0; e < kVItems; ++e) {
     const int64_t i = chunk * kVChunk + (int64_t)e * kVThreads + threadIdx.x;
-    if (i < n) acc += (double)row[i];
+    if (i < n) acc += (double)v[e];
   }
   const double t = block_sum_d(acc, s_w);
   if (threadIdx.x == 0) part[(int64_t)j * nc + chunk] = t;
@@ -68,12 +75,18 @@ k_lap_abs(int64_t n, int64_t npad, const float *__restrict__ y, int nc,
   const int64_t chunk = blockIdx.x;
   const float *row = y + j * npad;
   const double mu = coef[j];
+  float v[kVItems];
+#pragma unroll
+  for (int e = 0; e < kVItems; ++e) {
+    const int64_t i = chunk * kVChunk + (int64_t)e * kVThreads + threadIdx.x;
+    v[e] = row[i < n ? i : 0];
+  }
   double sa = 0.0, ss = 0.0;
 #pragma unroll
   for (int e = 0; e < kVItems; ++e) {
     const int64_t i = chunk * kVChunk + (int64_t)e * kVThreads + threadIdx.x;
     if (i < n) {
-      const double d = (double)row[i] - mu;
+      const double d = (double)v[e] - mu;
       sa += fabs(d);
       ss += d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
     }
@@ -139,14 +152,22 @@ k_lap_bwd(int64_t n, int64_t npad, const float *__restrict__ y, const double *__
   const double mu = coef[j], sbar = coef[64 + j], cj = coef[128 + j];
   if (cj == 0.0) return;
   const int64_t base = (int64_t)blockIdx.x * kVChunk;
+  // all loads first (entries past n read entry 0 and are dropped)
+  float yv[kVItems], gv[kVItems];
+#pragma unroll
+  for (int e = 0; e < kVItems; ++e) {
+    const int64_t i = base + (int64_t)e * kVThreads + threadIdx.x;
+    const int64_t ic = i < n ? i : 0;
+    yv[e] = y[j * npad + ic];
+    gv[e] = grad[j * npad + ic];
+  }
 #pragma unroll
   for (int e = 0; e < kVItems; ++e) {
     const int64_t i = base + (int64_t)e * kVThreads + threadIdx.x;
     if (i < n) {
-      const double d = (double)y[j * npad + i] - mu;
+      const double d = (double)yv[e] - mu;
       const double s = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
-      float &g = grad[j * npad + i];
-      g = (float)((double)g + cj * (s - sbar));
+      grad[j * npad + i] = (float)((double)gv[e] + cj * (s - sbar));
     }
   }
 }
