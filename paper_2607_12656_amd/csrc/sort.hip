@@ -115,14 +115,19 @@ k_scan_down(const uint32_t *__restrict__ in, int64_t count, const uint32_t *__re
 // ranks follow (round, wave, lane) = input order.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
-  uint64_t m = __ballot(valid);
+  const uint64_t v = __ballot(valid);
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t bal = __ballot(bit);
-    m &= bit ? bal : ~bal;
+    // s: all ones where the lane's bit b is set; a lane keeps the lanes whose
+    // bit b equals its own, i.e. those where the ballot agrees with s (kept
+    // as 32-bit halves so that each half is one three-input bitwise op)
+    const uint32_t s = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+    const uint64_t bal = __ballot(s != 0u);
+    lo &= ~((uint32_t)bal ^ s);
+    hi &= ~((uint32_t)(bal >> 32) ^ s);
   }
-  return m;
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // Block histogram of one digit.  Lanes count into 32 sub-histograms (eight
@@ -307,9 +312,11 @@ __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[IT],
     const uint32_t d = (kr[r] >> shift) & 0xFFu;
     const uint64_t m = match_digit(d, valid);
     const uint32_t before = valid ? s_cnt[wave][d] : 0u;
-    rank[r] = before + (uint32_t)__popcll(m & lt);
+    const uint32_t below = (uint32_t)__popcll(m & lt);  // same-digit lanes before this one
+    rank[r] = before + below;
     wave_lds_sync();  // every lane has read before the leader writes
-    if (valid && (__ffsll((long long)m) - 1) == lane) s_cnt[wave][d] = before + (uint32_t)__popcll(m);
+    // the leader (lowest lane of the digit) has none before it
+    if (valid && below == 0u) s_cnt[wave][d] = before + (uint32_t)__popcll(m);
     wave_lds_sync();
   }
   __syncthreads();
