@@ -126,9 +126,8 @@ __device__ __forceinline__ void blend_fwd_sub(int tile, int sub, int n, int W, i
     wave_lds_sync();
     if (b + 64 < rg.y) fetch(b + 64);
     if (m == 0ull) continue;
-    // composite entry k
-    auto step = [&](const SplatLds &cur, int k) {
-      const SplatEval e = eval_splat(cur, px, py, fx, fy);
+    // composite entry k, evaluated as e
+    auto step = [&](const SplatLds &cur, const SplatEval &e, int k) {
       const bool act = !done;
       if (COUNT) evals += (act && e.in_span) ? 1u : 0u;
       const bool okc = act && e.ok;
@@ -145,30 +144,22 @@ __device__ __forceinline__ void blend_fwd_sub(int tile, int sub, int n, int W, i
       stop = term ? b - rg.x + (uint32_t)k : stop;
       done = done || term;
     };
-    // two register sets in turn: the next record loads while one is used
-    int ka = __builtin_ctzll(m), kb = ka;
-    m &= m - 1;
-    SplatLds ra_ = sh[ka], rb_;
-    for (;;) {
-      bool more = m != 0ull;
-      if (more) {
-        kb = __builtin_ctzll(m);
-        m &= m - 1;
-        rb_ = sh[kb];
-      }
-      step(ra_, ka);
-      if (!more) break;
-      more = m != 0ull;
-      if (more) {
-        ka = __builtin_ctzll(m);
-        m &= m - 1;
-        ra_ = sh[ka];
-      }
-      step(rb_, kb);
+    // entries in pairs: both records are read and evaluated before either is
+    // composited, so two evaluation chains are in flight at once
+    while (m != 0ull) {
+      const int ka = __builtin_ctzll(m);
+      m &= m - 1;
+      const bool two = m != 0ull;
+      const int kb = two ? __builtin_ctzll(m) : ka;
+      if (two) m &= m - 1;
+      const SplatLds ra_ = sh[ka], rb_ = sh[kb];
+      const SplatEval ea = eval_splat(ra_, px, py, fx, fy);
+      const SplatEval eb = eval_splat(rb_, px, py, fx, fy);
+      step(ra_, ea, ka);
+      if (two) step(rb_, eb, kb);
       // whether any pixel of the wave still runs, every second entry (an
       // entry composited after the last pixel stopped changes nothing)
       if (__ballot(!done) == 0ull) break;
-      if (!more) break;
     }
   }
   if (inside) {
@@ -414,9 +405,8 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
     if (bi > 0) fetch(bi - 1);
     if (m == 0ull) continue;
     // gradient of entry k (record cur, Gaussian gid)
-    auto step = [&](const SplatLds &cur, int k, uint32_t gid) {
+    auto step = [&](const SplatLds &cur, const SplatEval &e, int k, uint32_t gid) {
       const uint32_t pos = p0 + (uint32_t)k;
-      const SplatEval e = eval_splat(cur, px, py, fx, fy);
       const bool ok = inside && pos < my_last && e.ok;
       if (__ballot(ok) == 0ull) return;
       // branch-free: lanes without the pair take alpha~ = 0 and dL/dalpha~ = 0,
@@ -462,34 +452,20 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
       if (lead && gv != 0.0f)
         unsafeAtomicAdd(gbase + (size_t)gid * SGS_SGRAD + vidx, (double)gv);
     };
-    // back to front, two register sets in turn: the next record loads while
-    // one is used
-    int hb = 63 - __builtin_clzll(m);
-    m &= ~(1ull << hb);
-    int ka = hb, kb = ka;
-    SplatLds ra_ = sh[ka], rb_;
-    uint32_t ga = s_gid[ka], gb = ga;
-    for (;;) {
-      bool more = m != 0ull;
-      if (more) {
-        hb = 63 - __builtin_clzll(m);
-        m &= ~(1ull << hb);
-        kb = hb;
-        rb_ = sh[kb];
-        gb = s_gid[kb];
-      }
-      step(ra_, ka, ga);
-      if (!more) break;
-      more = m != 0ull;
-      if (more) {
-        hb = 63 - __builtin_clzll(m);
-        m &= ~(1ull << hb);
-        ka = hb;
-        ra_ = sh[ka];
-        ga = s_gid[ka];
-      }
-      step(rb_, kb, gb);
-      if (!more) break;
+    // back to front, entries in pairs: both records are read and evaluated
+    // before either gradient is taken
+    while (m != 0ull) {
+      const int ka = 63 - __builtin_clzll(m);
+      m &= ~(1ull << ka);
+      const bool two = m != 0ull;
+      const int kb = two ? 63 - __builtin_clzll(m) : ka;
+      if (two) m &= ~(1ull << kb);
+      const SplatLds ra_ = sh[ka], rb_ = sh[kb];
+      const uint32_t ga = s_gid[ka], gb = s_gid[kb];
+      const SplatEval ea = eval_splat(ra_, px, py, fx, fy);
+      const SplatEval eb = eval_splat(rb_, px, py, fx, fy);
+      step(ra_, ea, ka, ga);
+      if (two) step(rb_, eb, kb, gb);
     }
   }
 }
