@@ -53,6 +53,31 @@ __device__ __forceinline__ SplatEval eval_splat(const SplatLds &s, int px, int p
   return r;
 }
 
+// Whether a splat can pass the alpha cut-off at any pixel centre of the 8x8
+// sub-tile at (sx0, sy0); a test per list entry, made once per batch.  The
+// log2 Gaussian of the record is a concave quadratic of the offset, so its
+// largest value over the rectangle of the sub-tile's pixel centres is 0
+// when the centre lies inside, else it lies on an edge, where the
+// quadratic's best point is clamped to the edge.  A pixel passes only if
+// opacity 2^p2 >= 1/255; the test keeps the entry when the best value is
+// within 0.05 of log2(1 / (255 opacity)), far above the rounding of either
+// side, so no entry a pixel would take is dropped.  A record whose
+// quadratic is not strictly concave along both axes, or any NaN, keeps it.
+__device__ __forceinline__ bool may_reach(const float4 &a, const float4 &b, int sx0, int sy0) {
+  const float Ap = a.z, Bp = a.w, Cp = b.x;
+  if (!(Ap < 0.0f && Cp < 0.0f)) return true;
+  const float x0 = (float)sx0 - a.x, x1 = x0 + 7.0f;
+  const float y0 = (float)sy0 - a.y, y1 = y0 + 7.0f;
+  if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return true;
+  auto p2 = [&](float dx, float dy) { return Ap * dx * dx + Cp * dy * dy + Bp * dx * dy; };
+  const float kx = -0.5f * Bp / Cp, ky = -0.5f * Bp / Ap;
+  auto on_x = [&](float dx) { return p2(dx, fminf(fmaxf(kx * dx, y0), y1)); };
+  auto on_y = [&](float dy) { return p2(fminf(fmaxf(ky * dy, x0), x1), dy); };
+  const float best = fmaxf(fmaxf(on_x(x0), on_x(x1)), fmaxf(on_y(y0), on_y(y1)));
+  const float need = -__log2f(255.0f * b.y);
+  return !(best + 0.05f < need);
+}
+
 // A 64-bit mask read from LDS, made wave-uniform (held in scalar registers).
 __device__ __forceinline__ uint64_t uniform_mask(uint64_t m) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)m);
@@ -120,8 +145,11 @@ __device__ __forceinline__ void blend_fwd_sub(int tile, int sub, int n, int W, i
       }
       // entries whose pixel span meets this sub-tile
       const uint32_t sx = __float_as_uint(rb.z), sy = __float_as_uint(rb.w);
+      // (the counting pass keeps every entry whose span meets the sub-tile:
+      // it counts in-span pairs)
       m = __ballot(valid && (int)(sx & 0xFFFF) <= sx0 + 7 && (int)(sx >> 16) >= sx0 &&
-                   (int)(sy & 0xFFFF) <= sy0 + 7 && (int)(sy >> 16) >= sy0);
+                   (int)(sy & 0xFFFF) <= sy0 + 7 && (int)(sy >> 16) >= sy0 &&
+                   (COUNT || may_reach(ra, rb, sx0, sy0)));
     }
     wave_lds_sync();
     if (b + 64 < rg.y) fetch(b + 64);
@@ -399,7 +427,8 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
       // entries before the wave's furthest stop whose span meets the sub-tile
       const uint32_t sx = __float_as_uint(rb.z), sy = __float_as_uint(rb.w);
       m = __ballot(valid && (int)(sx & 0xFFFF) <= sx0 + 7 && (int)(sx >> 16) >= sx0 &&
-                   (int)(sy & 0xFFFF) <= sy0 + 7 && (int)(sy >> 16) >= sy0);
+                   (int)(sy & 0xFFFF) <= sy0 + 7 && (int)(sy >> 16) >= sy0 &&
+                   may_reach(ra, rb, sx0, sy0));
     }
     wave_lds_sync();
     if (bi > 0) fetch(bi - 1);
