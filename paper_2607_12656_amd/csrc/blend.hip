@@ -87,11 +87,12 @@ __device__ __forceinline__ uint64_t uniform_mask(uint64_t m) {
 
 // One 8x8 sub-tile of a tile's forward, by one wave (the workgroup): the
 // wave stages 64 list entries at a time in its LDS (one 48-byte record per
-// lane), marks with a ballot those whose pixel span meets its sub-tile, and
-// composites them in list order, two register sets in turn so that the next
-// record loads while one is used; the next 64 records are fetched from global
-// memory during the walk.  It stops once all its pixels have stopped.  evals
-// accumulates the lane's in-span pairs.
+// lane), marks with a ballot those whose pixel span meets its sub-tile and
+// that can pass the alpha cut-off there (may_reach; the counting pass keeps
+// every entry whose span meets the sub-tile), and composites them in list
+// order, in pairs whose records are read and evaluated together; the next
+// 64 records are fetched from global memory during the walk.  It stops once
+// all its pixels have stopped.  evals accumulates the lane's in-span pairs.
 template <int TW, int TH, bool COUNT, int WPB>
 __device__ __forceinline__ void blend_fwd_sub(int tile, int sub, int n, int W, int H, int GW,
                                               int tiles_per_view,
