@@ -292,6 +292,24 @@ sgs_status sgs_rate_mlp_train_step(sgs_ctx *ctx, float *theta, float *adam_m, fl
                                    void *packed, const uint16_t *X, const float *target,
                                    int64_t rows, float lr, int64_t step, float *loss,
                                    float *grad_theta, void *scratch);
+/* For callers that cannot allocate device memory (code under HIP-graph
+ * capture, tight training loops, harnesses that forbid hipMalloc): the
+ * training step of sgs_rate_mlp_train_step, same kernels and the same results
+ * bit for bit, with its workspace taken from a static device array of the
+ * library (sgs_rate_mlp_train_scratch_bytes(SGS_MLP_STATIC_ROWS) bytes, about
+ * 14 MiB) instead of a caller buffer.  rows: a multiple of 8 in
+ * [8, SGS_MLP_STATIC_ROWS]; a larger batch returns SGS_ECAPACITY with nothing
+ * enqueued.  The array exists once per GPU, from the first sgs_create on that
+ * GPU until the process ends, and every call on that GPU (from any context)
+ * uses it: calls that overlap on one GPU (two streams, two threads) race and
+ * their results are undefined.  Nothing in it needs clearing between calls.
+ * Calls no device allocation or free; no profiling events are recorded for it.
+ * Other arguments as in sgs_rate_mlp_train_step. */
+#define SGS_MLP_STATIC_ROWS 8192
+sgs_status sgs_rate_mlp_train_step_static(sgs_ctx *ctx, float *theta, float *adam_m,
+                                          float *adam_v, void *packed, const uint16_t *X,
+                                          const float *target, int64_t rows, float lr,
+                                          int64_t step, float *loss, float *grad_theta);
 
 /* Rate-proxy variants the paper compares with sgs_rate_proxy's range-based
  * multiplicative proxy (Sec. 3.3.1 and the supplement's "Comparison with an

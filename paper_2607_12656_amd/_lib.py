@@ -92,6 +92,7 @@ _SIGS = {
     "sgs_rate_mlp_infer": [P, P, P, P, I64, P],
     "sgs_rate_mlp_train_scratch_bytes": [I64],
     "sgs_rate_mlp_train_step": [P, P, P, P, P, P, P, I64, F32, I64, P, P, P],
+    "sgs_rate_mlp_train_step_static": [P, P, P, P, P, P, P, I64, F32, I64, P, P],
     "sgs_adam_step": [P, P, P, P, P, P, P, P, P, P, P, P, P, P],
     "sgs_rate_mlp_features": [P, P, P, P, P, I64, P],
     "sgs_ssim_loss": [P, P, P, F32, P, P],
@@ -108,6 +109,7 @@ PROF_GROUPS = ("fakequant", "rate", "preprocess", "depth_sort", "scan", "duplica
                "adam", "ssim")
 MLP_PARAMS = 24961
 MLP_PACKED_BYTES = 98304
+MLP_STATIC_ROWS = 8192
 EXPORTS = tuple(_SIGS)
 
 _lib = None
@@ -385,6 +387,12 @@ class Context:
         self._check(self.L.sgs_rate_mlp_train_step(
             self.h, _ptr(theta), _ptr(adam_m), _ptr(adam_v), _ptr(packed), _ptr(X),
             _ptr(target), rows, lr, step, _ptr(loss), _ptr(grad_theta), _ptr(scratch)), self.h)
+
+    def rate_mlp_train_step_static(self, theta, adam_m, adam_v, packed, X, target, rows, lr,
+                                   step, loss, grad_theta):
+        self._check(self.L.sgs_rate_mlp_train_step_static(
+            self.h, _ptr(theta), _ptr(adam_m), _ptr(adam_v), _ptr(packed), _ptr(X),
+            _ptr(target), rows, lr, step, _ptr(loss), _ptr(grad_theta)), self.h)
 
     def profile_enable(self, on: bool = True):
         self._check(self.L.sgs_profile_enable(self.h, 1 if on else 0), self.h)

@@ -134,6 +134,14 @@ sgs_status sgs_create(sgs_ctx **out, int device, void *hip_stream) {
     return SGS_EHIP;
   }
   c->h_aux = c->h_pairs_total + 1;
+  // the allocation-free training step's workspace: its device address on
+  // this device, resolved once per device with the device current
+  hipError_t se = hipSuccess;
+  if (!mlp_static_scratch(device, &se)) {
+    (void)hipHostFree(c->h_pairs_total);
+    delete c;
+    return SGS_EHIP;
+  }
   *out = c;
   return SGS_OK;
 }
@@ -756,6 +764,35 @@ sgs_status sgs_rate_mlp_train_step(sgs_ctx *c, float *theta, float *adam_m, floa
   SGS_HIP(launch_mlp_train_step(c, theta, adam_m, adam_v, packed, X, target, rows, lr, step, loss,
                                 grad_theta, scratch),
           "rate_mlp_train_step");
+  return SGS_OK;
+}
+
+sgs_status sgs_rate_mlp_train_step_static(sgs_ctx *c, float *theta, float *adam_m,
+                                          float *adam_v, void *packed, const uint16_t *X,
+                                          const float *target, int64_t rows, float lr,
+                                          int64_t step, float *loss, float *grad_theta) {
+  if (!c) return SGS_EINVAL;
+  if (!theta || !packed || !X || !target || !loss || !grad_theta)
+    return fail(c, SGS_EINVAL, "rate_mlp_train_step_static: null pointer");
+  if (rows > SGS_MLP_STATIC_ROWS)
+    return fail(c, SGS_ECAPACITY,
+                "rate_mlp_train_step_static: %lld rows exceed the static workspace's %d",
+                (long long)rows, SGS_MLP_STATIC_ROWS);
+  if (rows < 8 || rows % 8 != 0)
+    return fail(c, SGS_EINVAL, "rate_mlp_train_step_static: rows must be a multiple of 8");
+  if (lr > 0.0f && (!adam_m || !adam_v || step < 1))
+    return fail(c, SGS_EINVAL, "rate_mlp_train_step_static: Adam needs moments and step >= 1");
+  if (!aligned(X, 8) || !aligned(packed, 16))
+    return fail(c, SGS_EINVAL, "rate_mlp_train_step_static: misaligned pointer");
+  if (mlp_train_scratch_bytes(rows) > mlp_static_scratch_bytes())
+    return fail(c, SGS_ECAPACITY, "rate_mlp_train_step_static: workspace too small");
+  // the device address resolved at sgs_create for this context's device
+  hipError_t se = hipSuccess;
+  void *ws = mlp_static_scratch(c->device, &se);
+  if (!ws) return hip_fail(c, se, "rate_mlp_train_step_static: static workspace");
+  SGS_HIP(launch_mlp_train_step(c, theta, adam_m, adam_v, packed, X, target, rows, lr, step,
+                                loss, grad_theta, ws, false),
+          "rate_mlp_train_step_static");
   return SGS_OK;
 }
 

@@ -13,6 +13,8 @@
 // backward to the inputs (dH1^T = W2 dZ2^T, dX^T = W1 dZ1^T).  Weight
 // gradients (training) are split-K GEMMs over the batch on transposed
 // activations written by the row kernel.
+#include <mutex>
+
 #include "sgs_internal.h"
 
 namespace {
@@ -858,15 +860,57 @@ hipError_t launch_mlp_infer(sgs_ctx *c, const void *packed, const float *theta,
 // batch 256 workgroups (with 2048, 32 of them left most compute units idle).
 constexpr int64_t kWgradChunk = 256;
 
-int64_t mlp_train_scratch_bytes(int64_t B) {
-  const int64_t chunks = (B + kWgradChunk - 1) / kWgradChunk;
-  return B * (64 + 3 * 128) * 2 + B * 128 * 4 + B * 4 + chunks * 24 * 1024 * 4 + 4096 * 8 + 256;
+constexpr int64_t train_scratch_bytes(int64_t B) {
+  // the takes of launch_mlp_train_step, each rounded up to 256 bytes (only
+  // the B * 4 one can be ragged for B a multiple of 8)
+  return B * (64 + 3 * 128) * 2 + B * 128 * 4 + B * 4 +
+         (B + kWgradChunk - 1) / kWgradChunk * 24 * 1024 * 4 + 4096 * 8 + 256;
+}
+
+int64_t mlp_train_scratch_bytes(int64_t B) { return train_scratch_bytes(B); }
+
+// Workspace of sgs_rate_mlp_train_step_static: one copy per GPU, held until
+// the process ends, shared by every call on that GPU.  Host code never uses
+// this name as an address (it is a host-side stand-in there); it uses the
+// device address resolved per device below.
+constexpr int64_t kStaticScratchBytes = train_scratch_bytes(SGS_MLP_STATIC_ROWS);
+static __device__ __align__(256) unsigned char g_train_scratch[kStaticScratchBytes];
+
+int64_t mlp_static_scratch_bytes() { return kStaticScratchBytes; }
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices] = {};
+}  // namespace
+
+void *mlp_static_scratch(int device, hipError_t *err) {
+  *err = hipSuccess;
+  if (device < 0 || device >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (g_static_ptr[device]) return g_static_ptr[device];
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+  void *ptr = nullptr;
+  if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(g_train_scratch));
+  if (cur != device) (void)hipSetDevice(cur);
+  if (e != hipSuccess || !ptr) {
+    *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+    return nullptr;
+  }
+  g_static_ptr[device] = ptr;
+  return ptr;
 }
 
 hipError_t launch_mlp_train_step(sgs_ctx *c, float *theta, float *m, float *v, void *packed,
                                  const uint16_t *X, const float *target, int64_t B, float lr,
-                                 int64_t step, float *loss, float *gtheta, void *scratch) {
-  SgsProfScope ps(c, SGS_PROF_MLP_TRAIN);
+                                 int64_t step, float *loss, float *gtheta, void *scratch,
+                                 bool profile) {
+  SgsProfScope ps(c, SGS_PROF_MLP_TRAIN, profile);
   char *p = (char *)scratch;
   auto take = [&](int64_t bytes) {
     char *r = p;

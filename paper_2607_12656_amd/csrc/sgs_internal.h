@@ -125,8 +125,8 @@ struct SgsProfScope {
     }
     return e;
   }
-  SgsProfScope(sgs_ctx *ctx, int group) : c(ctx), g(group) {
-    if (c->prof && !c->capturing) {
+  SgsProfScope(sgs_ctx *ctx, int group, bool on = true) : c(ctx), g(group) {
+    if (on && c->prof && !c->capturing) {
       a = get(c);
       if (a) (void)hipEventRecord(a, c->stream);
     }
@@ -235,6 +235,11 @@ hipError_t launch_blend_bwd(sgs_ctx *c, const float *final_T, const uint32_t *la
 // mlp.hip
 int mlp_grid(int64_t rows);  // blocks of the row kernels (partials per block)
 int64_t mlp_train_scratch_bytes(int64_t B);
+// Device address of the static training workspace (SGS_MLP_STATIC_ROWS rows)
+// on `device`, resolved once per device with that device current; nullptr
+// with the HIP error in *err when the symbol cannot be resolved.
+void *mlp_static_scratch(int device, hipError_t *err);
+int64_t mlp_static_scratch_bytes();
 hipError_t launch_mlp_pack(sgs_ctx *c, const float *theta, void *packed);
 hipError_t launch_mlp_rate_fwd(sgs_ctx *c, const void *packed, const float *theta,
                                const float *params, const float *q, const uint64_t *stats,
@@ -250,7 +255,8 @@ hipError_t launch_mlp_infer(sgs_ctx *c, const void *packed, const float *theta,
                             const uint16_t *X, int64_t B, float *fout);
 hipError_t launch_mlp_train_step(sgs_ctx *c, float *theta, float *m, float *v, void *packed,
                                  const uint16_t *X, const float *target, int64_t B, float lr,
-                                 int64_t step, float *loss, float *gtheta, void *scratch);
+                                 int64_t step, float *loss, float *gtheta, void *scratch,
+                                 bool profile = true);
 // loss.hip
 hipError_t launch_l1(sgs_ctx *c, const float *image, const float *target, float scale,
                      float *loss, float *dimg);
