@@ -1121,11 +1121,10 @@ double orc_l1(int64_t cnt, const double *img, const float *target, double *dimg)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Channel-wise fixed-length code length [Sec. 3.4.1]: each channel's        */
-/* quantized values are stored with one bit width fixed by the channel's     */
-/* code range; per-channel metadata is (q_j f32, kmin_j i32, width_j u8).    */
-/* Over kept Gaussians: K_j = kmax_j - kmin_j + 1, w_j = ceil(log2 K_j)      */
-/* (0 when K_j = 1); bits = N_kept sum_j w_j + 59 * 72.                      */
+/* Channel-wise fixed-length code length [Sec. 3.4.1].  Per channel j over  */
+/* the kept Gaussians: K_j = kmax_j - kmin_j + 1, w_j = ceil(log2 K_j)       */
+/* bits per code (0 when K_j = 1); header per channel (q_j f32, kmin_j i32,  */
+/* w_j u8); bits = N_kept sum_j w_j + 59 * 72.                               */
 /* kmin/kmax/width may be NULL.  Returns total bits.                         */
 /* ------------------------------------------------------------------------ */
 int64_t orc_fixed_length_bits(int64_t n, int64_t npad, const int32_t *k,

@@ -158,3 +158,102 @@ def test_coder_targets_and_learned_rate_gradient(orc, mlp):
         assert fd == pytest.approx(r["gy"][j, i], rel=1e-4, abs=1e-10)
     # mask gradient is f / N_hat
     assert np.allclose(r["gm"], r["f"] / sc.n_hat)
+
+
+def _torch_mlp(w, bf16_points=False):
+    """The estimator as a torch FP64 nn.Sequential (Linear stores W as
+    (out, in): the transposes of the (in, out) weight layout).  With
+    bf16_points the values the matrix cores take in BF16 (inputs, W1, W2, w3
+    and the first hidden activation) are rounded by torch's own bfloat16
+    conversion (round to nearest even) in between."""
+    torch = pytest.importorskip("torch")
+    r = (lambda t: t.to(torch.bfloat16).to(torch.float64)) if bf16_points else (lambda t: t)
+    l1 = torch.nn.Linear(64, 128, dtype=torch.float64)
+    l2 = torch.nn.Linear(128, 128, dtype=torch.float64)
+    l3 = torch.nn.Linear(128, 1, dtype=torch.float64)
+    with torch.no_grad():
+        l1.weight.copy_(r(torch.from_numpy(w["W1"].astype(np.float64)).T))
+        l1.bias.copy_(torch.from_numpy(w["b1"].astype(np.float64)))
+        l2.weight.copy_(r(torch.from_numpy(w["W2"].astype(np.float64)).T))
+        l2.bias.copy_(torch.from_numpy(w["b2"].astype(np.float64)))
+        l3.weight.copy_(r(torch.from_numpy(w["w3"].astype(np.float64))[None, :]))
+        l3.bias.copy_(torch.from_numpy(w["b3"].astype(np.float64)))
+
+    class Rb(torch.nn.Module):
+        def forward(self, t):
+            return r(t)
+    return torch.nn.Sequential(Rb(), l1, torch.nn.ReLU(), Rb(), l2, torch.nn.ReLU(), l3)
+
+
+def test_mlp_forward_and_backward_match_torch_fp64(mlp):
+    """The oracle MLP (mirror off) against torch's FP64 Linear / ReLU layers:
+    forward, weight gradients and input gradient of sum_i c_i f(x_i)."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(31)
+    w = mlp.init_weights(8)
+    for k in ("b1", "b2", "b3"):
+        w[k] = rng.normal(0, 0.2, size=w[k].shape).astype(np.float32)
+    X = _toy(32, B=48)
+    c = rng.normal(size=48)
+    f = mlp.forward(X, w, mirror=False)
+    net = _torch_mlp(w)
+    Xt = torch.from_numpy(X).requires_grad_(True)
+    ft = net(Xt)[:, 0]
+    assert np.allclose(f, ft.detach().numpy(), rtol=1e-13, atol=1e-13)
+    (ft * torch.from_numpy(c)).sum().backward()
+    g, dX = mlp.backward(X, w, c, mirror=False, want_dx=True)
+    l1, l2, l3 = net[1], net[4], net[6]
+    pairs = (("W1", l1.weight.grad.T), ("b1", l1.bias.grad), ("W2", l2.weight.grad.T),
+             ("b2", l2.bias.grad), ("w3", l3.weight.grad[0]), ("b3", l3.bias.grad))
+    for name, ref in pairs:
+        ref = ref.numpy().reshape(g[name].shape)
+        assert np.allclose(g[name], ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max()), name
+    assert np.allclose(dX, Xt.grad.numpy(), rtol=1e-12, atol=1e-13)
+
+
+def test_mlp_bf16_mirror_points_match_torch(mlp):
+    """With mirroring on, the oracle forward on BF16 features equals the FP64
+    network whose W1, W2, w3 and first hidden activation are rounded to BF16
+    (the values the matrix cores read), and nothing else."""
+    torch = pytest.importorskip("torch")
+    w = mlp.init_weights(9)
+    # the features arrive in BF16 (the feature pass rounds them)
+    X = torch.from_numpy(_toy(33, B=40)).to(torch.bfloat16).to(torch.float64).numpy()
+    f = mlp.forward(X, w, mirror=True)
+    ft = _torch_mlp(w, bf16_points=True)(torch.from_numpy(X))[:, 0].detach().numpy()
+    assert np.allclose(f, ft, rtol=1e-13, atol=1e-13)
+    # and it is not the unrounded network
+    assert not np.allclose(f, mlp.forward(X, w, mirror=False), rtol=1e-6)
+
+
+def test_mlp_bf16_mirror_backward_points_match_torch(mlp):
+    """With mirroring on, the oracle backward of sum_i c_i f(x_i) equals torch
+    autograd through the BF16-rounded network with the gradients at the two
+    backward matrix-core inputs rounded to BF16: dz2 = c w3 [z2 > 0] (the
+    row weight c enters before the rounding) and dz1 = (W2 dz2) [z1 > 0]."""
+    torch = pytest.importorskip("torch")
+    rb = lambda t: t.to(torch.bfloat16).to(torch.float64)
+    rng = np.random.default_rng(41)
+    w = mlp.init_weights(10)
+    for k in ("b1", "b2"):
+        w[k] = rng.normal(0, 0.1, size=w[k].shape).astype(np.float32)
+    X = torch.from_numpy(_toy(34, B=24)).to(torch.bfloat16).to(torch.float64)
+    c = rng.normal(size=24)
+    leaf = lambda a: rb(torch.from_numpy(a.astype(np.float64))).requires_grad_(True)
+    W1, W2, w3 = leaf(w["W1"]), leaf(w["W2"]), leaf(w["w3"])
+    b1 = torch.from_numpy(w["b1"].astype(np.float64)).requires_grad_(True)
+    b2 = torch.from_numpy(w["b2"].astype(np.float64)).requires_grad_(True)
+    b3 = torch.from_numpy(w["b3"].astype(np.float64)).requires_grad_(True)
+    Xl = X.clone().requires_grad_(True)
+    z1 = Xl @ W1 + b1
+    h1 = rb(torch.relu(z1))             # its gradient passes through the cast: rounded
+    z2 = h1 @ W2 + b2
+    z2.register_hook(lambda g: rb(g))   # dz2 rounded before the second GEMM
+    f = torch.relu(z2) @ w3 + b3
+    (f * torch.from_numpy(c)).sum().backward()
+    g, dX = mlp.backward(X.numpy(), w, c, mirror=True, want_dx=True)
+    for name, ref in (("W1", W1.grad), ("b1", b1.grad), ("W2", W2.grad), ("b2", b2.grad),
+                      ("w3", w3.grad), ("b3", b3.grad)):
+        ref = ref.numpy().reshape(g[name].shape)
+        assert np.allclose(g[name], ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max()), name
+    assert np.allclose(dX, Xl.grad.numpy(), rtol=1e-12, atol=1e-13)

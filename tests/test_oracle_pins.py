@@ -570,3 +570,201 @@ def test_sampled_oracle_helpers_agree_with_full_binning(orc):
     for k, (v, u, y) in enumerate(pix):
         assert np.array_equal(out[k, :3], full["image"][v, :, y, u])
         assert out[k, 3] == full["T"][v, y, u]
+
+
+# ---------------------------------------------------------------------------
+# Early termination (reading of Sec. 3.1's compositing with early stopping):
+# a pixel stops BEFORE blending the candidate whose T (1 - alpha~) would fall
+# below 1e-4; `last` is the list position of that candidate.
+# ---------------------------------------------------------------------------
+
+def _stack_scene(logits, masked, W=64, H=64):
+    """Splats stacked on the optical axis (front to back in list order), each
+    centred exactly on pixel (W/2, H/2), where its Gaussian factor is
+    exactly 1 and alpha = sigmoid(logit); white colour (DC = sqrt(pi))."""
+    n = len(logits)
+    cam = synth.camera_axis(W, H, 3.0)[None]
+    p = _empty_params(n)
+    p[2, :n] = 0.05 * np.arange(n)                   # strictly increasing depth
+    p[CH_SCALE:CH_ROT, :n] = math.log(0.03)
+    p[CH_OPA, :n] = logits
+    p[CH_DC:CH_DC + 3, :n] = math.sqrt(math.pi)
+    m = np.array([0.0 if k in masked else 1.0 for k in range(n)])
+    return p, m, cam, W, H
+
+
+def _stop_closed_form(alpha_seq, mask):
+    """Stop position and T of a pixel whose candidates have the given alpha
+    and mask: for identical unmasked alphas the k-th candidate (0-based
+    count of unmasked ones) is refused when (1 - alpha)^(k + 1) < 1e-4."""
+    T = 1.0
+    for j, (a, mk) in enumerate(zip(alpha_seq, mask)):
+        if mk == 0.0:
+            continue
+        if T * (1.0 - a) < 1e-4:
+            return j, T
+        T *= 1.0 - a
+    return len(alpha_seq), T
+
+
+@pytest.mark.parametrize("logit,masked", [(1.375, ()), (0.5, ()), (1.375, (1, 4, 6))])
+def test_termination_stack_closed_form(orc, logit, masked):
+    n = 14
+    p, m, cam, W, H = _stack_scene(np.full(n, logit, np.float32), masked)
+    st = orc.decide(p, n, cam, W, H)
+    assert (st.valid[0, :n] == 1).all()
+    fw = orc.forward(p.astype(np.float64), m, n, cam, W, H, st)
+    alpha = 1.0 / (1.0 + math.exp(-float(np.float32(logit))))
+    # closed form: k unmasked splats are blended, k = floor(ln 1e-4 / ln(1 - alpha))
+    k = math.floor(math.log(1e-4) / math.log(1.0 - alpha))
+    assert k < n - len(masked)
+    unmasked = [j for j in range(n) if j not in masked]
+    stop_pos = unmasked[k]                           # the refused candidate's list position
+    T_ref = (1.0 - alpha) ** k
+    colour = float(np.float32(math.sqrt(math.pi))) / (2 * math.sqrt(math.pi)) + 0.5
+    u = v = W // 2
+    assert fw["last"][0, v, u] == stop_pos
+    assert fw["T"][0, v, u] == pytest.approx(T_ref, rel=1e-12)
+    for ch in range(3):
+        assert fw["image"][0, ch, v, u] == pytest.approx(colour * (1 - T_ref), rel=1e-12)
+    assert fw["margin"][0, v, u] == 0
+    # the same stop from the step-by-step reading, as a cross-check of k
+    pos, T2 = _stop_closed_form([alpha] * n, m)
+    assert pos == stop_pos and T2 == pytest.approx(T_ref, rel=1e-12)
+
+
+def test_termination_uses_candidate_alpha(orc):
+    """Two alphas: eleven splats of alpha sigmoid(0) = 1/2 leave T = 2^-11;
+    the twelfth (alpha 1/2) would give 2^-12 = 2.4e-4 >= 1e-4, so it is
+    blended; the thirteenth is a high-opacity splat (logit 2.5, alpha 0.924)
+    that would give 1.9e-5 < 1e-4: refused at position 12 with T = 2^-12,
+    even though the splat after it (alpha 1/2) would pass on its own."""
+    logits = np.array([0.0] * 12 + [2.5, 0.0], np.float32)
+    p, m, cam, W, H = _stack_scene(logits, ())
+    n = len(logits)
+    st = orc.decide(p, n, cam, W, H)
+    fw = orc.forward(p.astype(np.float64), m, n, cam, W, H, st)
+    u = v = W // 2
+    assert fw["last"][0, v, u] == 12
+    assert fw["T"][0, v, u] == pytest.approx(2.0 ** -12, rel=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Projection and SH view direction under a rotated camera (Sec. 3.1): moving
+# the scene and the camera by the same rigid rotation changes no pixel.
+# ---------------------------------------------------------------------------
+
+def _quat_matrix(q):
+    """Textbook rotation matrix of the unit quaternion (w, x, y, z)."""
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def _hamilton(a, b):
+    aw, ax, ay, az = a
+    bw, bx, by, bz = b
+    return np.array([aw * bw - ax * bx - ay * by - az * bz,
+                     aw * bx + ax * bw + ay * bz - az * by,
+                     aw * by - ax * bz + ay * bw + az * bx,
+                     aw * bz + ax * by - ay * bx + az * bw])
+
+
+def _rotate_scene(orc, p64, n, cam, qw):
+    """The scene and camera moved by the rotation Rw of unit quaternion qw:
+    means Rw mu, orientations qw * q, SH coefficients re-fitted so that the
+    colour seen along Rw d equals the old colour along d (degree <= 3 is a
+    rotation-invariant space, so the least-squares fit is exact), camera
+    R Rw^T with the same translation and centre Rw c."""
+    Rw = _quat_matrix(qw)
+    pr = p64.copy()
+    pr[0:3, :n] = Rw @ p64[0:3, :n]
+    for i in range(n):
+        pr[CH_ROT:NCH, i] = _hamilton(qw, p64[CH_ROT:NCH, i])
+    rng = np.random.default_rng(0)
+    d = rng.normal(size=(400, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    Y, Yr = orc.sh_basis(d), orc.sh_basis(d @ Rw.T)
+    for ch in range(3):
+        rows = [CH_DC + ch] + [CH_REST + 3 * (k - 1) + ch for k in range(1, 16)]
+        f = p64[rows, :n]
+        fr, *_ = np.linalg.lstsq(Yr, Y @ f, rcond=None)
+        pr[rows, :n] = fr
+    cr = cam.astype(np.float64).copy()
+    R = cam[0:9].astype(np.float64).reshape(3, 3)
+    cr[0:9] = (R @ Rw.T).reshape(-1)
+    cr[16:19] = Rw @ cam[16:19].astype(np.float64)
+    return pr, cr, Rw
+
+
+def test_rotated_scene_and_camera_render_identically(orc):
+    """A ring camera (R != I) and a random 3D rotation of scene + camera: the
+    FP64 projection records (mean, conic, opacity, colour with SH up to
+    degree 3), the image, T and stop positions, and the gradients are
+    invariant (mean gradients rotate with the scene).  A transposed
+    world-to-camera rotation, a covariance conjugated the wrong way or an SH
+    direction taken in camera coordinates breaks this."""
+    sc = synth.make_tiny(50, 64, 48, views=2, seed=21, logscale_mu=-2.2)
+    n, W, H = sc.n, sc.width, sc.height
+    p64 = sc.params.astype(np.float64)
+    p64[CH_REST:CH_OPA, :n] *= 0.8                  # keep colours mostly unclamped
+    cam = sc.cams[1]                                # the ring camera at theta = pi
+    assert not np.allclose(cam[0:9].reshape(3, 3), np.eye(3))
+    st = orc.decide(p64.astype(np.float32), n, cam[None], W, H)
+    qw = np.random.default_rng(4).normal(size=4)
+    qw /= np.linalg.norm(qw)
+    pr, cr, Rw = _rotate_scene(orc, p64, n, cam, qw)
+    # the rotated camera record holds float32; rotate in FP64 and round once
+    cr32 = cr.astype(np.float32)[None]
+    a = orc.project64(p64, n, cam[None], W, H, st)[0]
+    b = orc.project64(pr, n, cr32, W, H, st)[0]
+    ok = st.valid[0] == 1
+    assert ok.sum() > 30
+    # camera entries rounded to FP32 move the projection by ~1e-7 relative
+    assert np.allclose(b[ok, 0:2], a[ok, 0:2], rtol=0, atol=1e-4)
+    for k in (2, 3, 4):
+        scale = np.abs(a[ok, 2:5]).max(axis=1)
+        assert (np.abs(b[ok, k] - a[ok, k]) <= 1e-5 * scale).all(), f"conic entry {k}"
+    assert np.allclose(b[ok, 5], a[ok, 5], rtol=1e-15)
+    assert np.allclose(b[ok, 6:9], a[ok, 6:9], rtol=0, atol=1e-6), "view-dependent colour"
+    m = np.ones(n)
+    fa = orc.forward(p64, m, n, cam[None], W, H, st)
+    fb = orc.forward(pr, m, n, cr32, W, H, st)
+    clean = (fa["margin"] == 0) & (fb["margin"] == 0)
+    assert clean.mean() > 0.99
+    assert np.abs(fb["image"] - fa["image"]).max(axis=1)[clean].max() < 1e-5
+    assert np.array_equal(fb["last"][clean], fa["last"][clean])
+    # gradients of the same image loss: mean gradients rotate, the rest match
+    dimg = np.random.default_rng(5).normal(size=fa["image"].shape) * clean[:, None]
+    ga, gma, _ = orc.backward(p64, m, n, cam[None], W, H, st, dimg)
+    gb, gmb, _ = orc.backward(pr, m, n, cr32, W, H, st, dimg)
+    gmax = np.abs(ga[0:3, :n]).max()
+    assert np.abs(gb[0:3, :n] - Rw @ ga[0:3, :n]).max() <= 1e-3 * gmax
+    for rows in ((CH_OPA,), tuple(range(CH_SCALE, CH_ROT))):
+        r = list(rows)
+        assert np.abs(gb[r, :n] - ga[r, :n]).max() <= 1e-3 * np.abs(ga[r, :n]).max()
+    assert np.abs(gmb - gma).max() <= 1e-3 * np.abs(gma).max()
+    # the FP32 decision layer on the rotated scene: the same spans almost everywhere
+    st2 = orc.decide(pr.astype(np.float32), n, cr32, W, H)
+    same = (st2.span[0] == st.span[0]).all(axis=1)
+    assert same[ok].mean() >= 0.95
+    assert np.abs(st2.pxy[0, ok] - st.pxy[0, ok]).max() < 1e-3
+
+
+def test_sh_view_direction_sign(orc):
+    """Only the degree-1 coefficient along z (index 2, Y_10 = sqrt(3/(4 pi)) z)
+    is set: a Gaussian straight ahead of the axis camera is seen along +z
+    (direction from the camera centre to the mean), so its colour is
+    1/2 + f sqrt(3/(4 pi))."""
+    W = H = 32
+    cam = synth.camera_axis(W, H, 3.0)[None]
+    p = _empty_params(1)
+    p[CH_SCALE:CH_ROT, 0] = math.log(0.05)
+    p[CH_OPA, 0] = 0.0
+    f = 0.25
+    p[CH_REST + 3 * (2 - 1) + 0, 0] = f               # red, coefficient k = 2
+    st = orc.decide(p, 1, cam, W, H)
+    pj = orc.project64(p.astype(np.float64), 1, cam, W, H, st)[0]
+    assert pj[0, 6] == pytest.approx(0.5 + f * math.sqrt(3 / (4 * math.pi)), rel=1e-14)
+    assert pj[0, 7] == pytest.approx(0.5, rel=1e-15) and pj[0, 8] == pytest.approx(0.5, rel=1e-15)
