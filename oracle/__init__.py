@@ -87,6 +87,8 @@ def _declare(L):
         "orc_tile_counts": (None, [I64, I32, P, P, I32, I32, I32, I32, P]),
         "orc_tile_list": (I64, [I64, I32, I64, P, P, P, I32, I32, I32, P]),
         "orc_pixels_brute": (I64, [I64, I64, P, P, I32, P, I32, I32, P, P, P, I64, P, P, P]),
+        "orc_splat_grads_sampled": (I64, [I64, I64, P, P, I32, P, I32, I32, P, P, P, I64, P,
+                                          P, P, P, P]),
         "orc_l1": (F64, [I64, P, P, P]),
         "orc_sh_basis": (None, [I64, P, P]),
         "orc_fixed_length_bits": (I64, [I64, I64, P, P, P, P, P]),
@@ -334,6 +336,29 @@ def pixels_brute(p64, mask64, n, cams, W, H, st: Structure, pix: np.ndarray):
                                H, _p(st.valid), _p(st.tz), _p(st.span), pix.shape[0], _p(pix),
                                _p(out), _p(margin))
     return out, margin, int(E)
+
+
+def splat_grads_sampled(p64, mask64, n, cams, W, H, st: Structure, sel, dimage=None):
+    """Gradients of chosen Gaussians by brute force over their span pixels:
+    (gsplat [k][V][10], gparam [k][59], margin [V][H][W] uint8).  Without
+    dimage only the margin flags of the span pixels are produced."""
+    p64 = np.ascontiguousarray(p64, np.float64)
+    mask64 = np.ascontiguousarray(mask64, np.float64)
+    cams = np.ascontiguousarray(cams, np.float32)
+    sel = np.ascontiguousarray(sel, np.int64)
+    if sel.size and not ((sel >= 0).all() and (sel < n).all()):
+        raise ValueError("chosen Gaussian outside the scene")
+    V = cams.shape[0]
+    if dimage is not None:
+        dimage = np.ascontiguousarray(dimage, np.float64)
+        assert dimage.shape == (V, 3, H, W)
+    gs = np.zeros((sel.size, V, 10))
+    gp = np.zeros((sel.size, NCH))
+    margin = np.zeros((V, H, W), np.uint8)
+    lib().orc_splat_grads_sampled(n, p64.shape[1], _p(p64), _p(mask64), V, _p(cams), W, H,
+                                  _p(st.valid), _p(st.tz), _p(st.span), sel.size, _p(sel),
+                                  _p(dimage), _p(gs), _p(gp), _p(margin))
+    return gs, gp, margin
 
 
 def sh_basis(dirs: np.ndarray) -> np.ndarray:

@@ -896,6 +896,44 @@ int64_t orc_forward_brute(int64_t n, int64_t npad, const double *p,
 /* gparams [59][npad] and gmask [n] are overwritten; gsplat [V][n][10] (may */
 /* be NULL) receives the per-view splat gradients.                          */
 /* ------------------------------------------------------------------------ */
+/* Reverse walk over the candidates one pixel blended (recs, nr from
+ * blend_pixel), colour gradient gC of the pixel: adds every blended
+ * candidate's splat-gradient terms into gs [view * n + i][NSPLATGRAD], or,
+ * when only >= 0, only Gaussian `only`'s terms into gs [NSPLATGRAD]. */
+static void pixel_backward(const blend_ctx *bc, int view, int px, int py, const uint32_t *list,
+                           const blend_rec *recs, int64_t nr, const double gC[3],
+                           int64_t only, double *gs) {
+  const int64_t n = bc->n;
+  double Bk[3] = {0.0, 0.0, 0.0};
+  for (int64_t r = nr - 1; r >= 0; --r) {
+    const blend_rec *br = &recs[r];
+    int64_t i = list[br->j];
+    int64_t s = (int64_t)view * n + i;
+    const pj64 *g = &bc->pj[s];
+    if (only < 0 || i == only) {
+      double *gg = only < 0 ? gs + s * NSPLATGRAD : gs;
+      double dat = 0.0;
+      for (int ch = 0; ch < 3; ++ch) {
+        gg[6 + ch] += gC[ch] * br->at * br->T;
+        dat += gC[ch] * br->T * (g->col[ch] - Bk[ch]);
+      }
+      gg[9] += dat * br->alpha;
+      double dalpha = bc->mask[i] * dat;
+      if (!br->clamped) {
+        gg[5] += dalpha * br->G;
+        double dpow = dalpha * br->alpha;
+        double dx = px - g->px, dy = py - g->py;
+        gg[0] += dpow * (g->A * dx + g->B * dy);
+        gg[1] += dpow * (g->B * dx + g->C * dy);
+        gg[2] += dpow * (-0.5 * dx * dx);
+        gg[3] += dpow * (-dx * dy);
+        gg[4] += dpow * (-0.5 * dy * dy);
+      }
+    }
+    for (int ch = 0; ch < 3; ++ch) Bk[ch] = g->col[ch] * br->at + (1.0 - br->at) * Bk[ch];
+  }
+}
+
 void orc_backward(int64_t n, int64_t npad, const double *p, const double *mask,
                   int32_t V, const float *cams, int32_t W, int32_t H,
                   int32_t TW, int32_t TH, const int32_t *valid,
@@ -925,32 +963,7 @@ void orc_backward(int64_t n, int64_t npad, const double *p, const double *mask,
             int64_t pix = (int64_t)py * W + px;
             double gC[3];
             for (int ch = 0; ch < 3; ++ch) gC[ch] = dimage[((int64_t)v * 3 + ch) * H * W + pix];
-            double Bk[3] = {0.0, 0.0, 0.0};
-            for (int64_t r = nr - 1; r >= 0; --r) {
-              const blend_rec *br = &recs[r];
-              int64_t i = list[br->j];
-              int64_t s = (int64_t)v * n + i;
-              const pj64 *g = &pj[s];
-              double *gg = gs + s * NSPLATGRAD;
-              double dat = 0.0;
-              for (int ch = 0; ch < 3; ++ch) {
-                gg[6 + ch] += gC[ch] * br->at * br->T;
-                dat += gC[ch] * br->T * (g->col[ch] - Bk[ch]);
-              }
-              gg[9] += dat * br->alpha;
-              double dalpha = mask[i] * dat;
-              if (!br->clamped) {
-                gg[5] += dalpha * br->G;
-                double dpow = dalpha * br->alpha;
-                double dx = px - g->px, dy = py - g->py;
-                gg[0] += dpow * (g->A * dx + g->B * dy);
-                gg[1] += dpow * (g->B * dx + g->C * dy);
-                gg[2] += dpow * (-0.5 * dx * dx);
-                gg[3] += dpow * (-dx * dy);
-                gg[4] += dpow * (-0.5 * dy * dy);
-              }
-              for (int ch = 0; ch < 3; ++ch) Bk[ch] = g->col[ch] * br->at + (1.0 - br->at) * Bk[ch];
-            }
+            pixel_backward(&bc, v, px, py, list, recs, nr, gC, -1, gs);
           }
       }
   free(recs);
@@ -1090,6 +1103,93 @@ int64_t orc_pixels_brute(int64_t n, int64_t npad, const double *p, const double 
   free(ord);
   free(list);
   return evals;
+}
+
+/* Splat and parameter gradients of chosen Gaussians by brute force over
+ * their pixels [Sec. 3.1 compositing and its reverse pass]: in every view
+ * where Gaussian i is not culled, each pixel of its span composites every
+ * valid splat of that view whose span holds the pixel, in global (depth
+ * bits, index) order, then walks back; only i's terms are summed.
+ *   sel [nsel]: Gaussian indices; dimage [V][3][H][W] (NULL: only the
+ *   margin flags are produced);
+ *   gsplat [nsel][V][10] (px, py, A, B, C, opacity, r, g, b, mask; zero
+ *   where culled); gparam [nsel][59]: the projection backward of those,
+ *   summed over views; margin [V][H][W] (may be NULL) is set to 1 at every
+ *   span pixel of a chosen Gaussian where a per-pair decision lies within
+ *   the margin.  Returns the number of (view, pixel) walks. */
+int64_t orc_splat_grads_sampled(int64_t n, int64_t npad, const double *p, const double *mask,
+                                int32_t V, const float *cams, int32_t W, int32_t H,
+                                const int32_t *valid, const float *tz, const int32_t *span,
+                                int64_t nsel, const int64_t *sel, const double *dimage,
+                                double *gsplat, double *gparam, uint8_t *margin) {
+  int64_t walks = 0;
+  int64_t *ord = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  uint32_t *list = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+  pj64 *pj = (pj64 *)calloc((size_t)n, sizeof(pj64));
+  blend_rec *recs = (blend_rec *)malloc(sizeof(blend_rec) * (size_t)(n > 0 ? n : 1));
+  if (gsplat) memset(gsplat, 0, sizeof(double) * (size_t)(nsel * V * NSPLATGRAD));
+  if (gparam) memset(gparam, 0, sizeof(double) * (size_t)(nsel * NCH));
+  for (int64_t q = 0; q < nsel; ++q) {
+    const int64_t i = sel[q];
+    double p1[NCH], gp1[NCH];
+    for (int k = 0; k < NCH; ++k) {
+      p1[k] = p[(int64_t)k * npad + i];
+      gp1[k] = 0.0;
+    }
+    for (int v = 0; v < V; ++v) {
+      const int64_t si = (int64_t)v * n + i;
+      if (!valid[si]) continue;
+      const orc_cam *c = (const orc_cam *)(cams + 19 * v);
+      const int32_t *spi = span + 4 * si;
+      int x0 = spi[0] < 0 ? 0 : spi[0], x1 = spi[1] >= W ? W - 1 : spi[1];
+      int y0 = spi[2] < 0 ? 0 : spi[2], y1 = spi[3] >= H ? H - 1 : spi[3];
+      if (x0 > x1 || y0 > y1) continue;
+      /* every splat of the view whose span meets i's span, depth order */
+      int64_t cnt = 0;
+      for (int64_t k = 0; k < n; ++k) {
+        const int64_t sk = (int64_t)v * n + k;
+        if (!valid[sk]) continue;
+        const int32_t *sp = span + 4 * sk;
+        if (sp[1] < x0 || sp[0] > x1 || sp[3] < y0 || sp[2] > y1) continue;
+        ord[cnt++] = k;
+        pj64_tmp m;
+        proj64(p, npad, k, c, W, H, &pj[k], &m);
+      }
+      g_sort_tz = tz + (int64_t)v * n;
+      qsort(ord, (size_t)cnt, sizeof(int64_t), idx_cmp);
+      for (int64_t k = 0; k < cnt; ++k) list[k] = (uint32_t)ord[k];
+      blend_ctx bc = {pj, span + (int64_t)v * n * 4, mask, n};
+      double gg[NSPLATGRAD] = {0};
+      for (int py = y0; py <= y1; ++py)
+        for (int px = x0; px <= x1; ++px) {
+          double col[3], T;
+          int64_t ev = 0, nr = 0;
+          int mg = 0;
+          blend_pixel(&bc, 0, px, py, list, cnt, col, &T, &ev, &mg, recs, &nr);
+          ++walks;
+          const int64_t pix = (int64_t)py * W + px;
+          if (margin && mg) margin[(int64_t)v * H * W + pix] = 1;
+          if (!dimage) continue;
+          double gC[3];
+          for (int ch = 0; ch < 3; ++ch) gC[ch] = dimage[((int64_t)v * 3 + ch) * H * W + pix];
+          pixel_backward(&bc, 0, px, py, list, recs, nr, gC, i, gg);
+        }
+      if (!dimage) continue;
+      if (gsplat)
+        for (int k = 0; k < NSPLATGRAD; ++k) gsplat[(q * V + v) * NSPLATGRAD + k] = gg[k];
+      pj64 o;
+      pj64_tmp m;
+      proj64(p1, 1, 0, c, W, H, &o, &m);
+      proj64_bwd(p1, 1, 0, c, &o, &m, gg, gp1);
+    }
+    if (gparam)
+      for (int k = 0; k < NCH; ++k) gparam[q * NCH + k] = gp1[k];
+  }
+  free(recs);
+  free(pj);
+  free(list);
+  free(ord);
+  return walks;
 }
 
 /* Projection only (FP64): fields px, py, A, B, C, opacity, r, g, b per

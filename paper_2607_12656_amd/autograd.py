@@ -7,14 +7,29 @@ upstream gradients of D and R become the scale of dL/dimage and the weight of
 the rate gradient, so ``(D + lam * R).backward()`` gives the gradient of the
 paper's structural-formation loss (Sec. 3.3.2).
 
-``Render``: qparams -> image for callers with their own image loss; the
-gradient w.r.t. the hard mask is left in ``rd.grad_mask``.
+``Render``: (qparams, hard_mask) -> image for callers with their own image
+loss; the gradient w.r.t. the hard mask is left in ``rd.grad_mask``.
+
+Both keep no per-pair state: the backward re-walks the tile lists of the
+forward (alpha and T recomputed from the per-pixel final T and stop
+position).  Those lists, records and per-pixel buffers belong to the
+``RDStep`` (and its context), so a backward must follow its own forward with
+no other forward on that ``RDStep`` in between; otherwise it raises instead of
+differentiating the wrong scene.
 """
 from __future__ import annotations
 
 import torch
 
 from .rd import RDStep
+
+
+def _check_current(ctx, rd: RDStep):
+    if rd.generation != ctx.generation:
+        raise RuntimeError(
+            "backward after another forward on the same RDStep: the tile lists and "
+            "per-pixel state of this forward were overwritten (run backward before the "
+            "next forward, or use one RDStep per pending graph)")
 
 
 class FormationStep(torch.autograd.Function):
@@ -24,6 +39,7 @@ class FormationStep(torch.autograd.Function):
         rd.forward(params, qstep, score, target, 0.0, mask_mode, given_mask, seed, step,
                    count_evals=False)
         ctx.rd, ctx.target, ctx.mask_mode = rd, target, mask_mode
+        ctx.generation = rd.generation
         ctx.save_for_backward(params, qstep)
         image = rd.image.clone()
         ctx.mark_non_differentiable(image)
@@ -33,6 +49,7 @@ class FormationStep(torch.autograd.Function):
     def backward(ctx, gD, gR, _gimg):
         params, qstep = ctx.saved_tensors
         rd: RDStep = ctx.rd
+        _check_current(ctx, rd)
         gd = 0.0 if gD is None else float(gD)
         gr = 0.0 if gR is None else float(gR)
         c = rd.ctx
@@ -48,8 +65,10 @@ class Render(torch.autograd.Function):
     @staticmethod
     def forward(ctx, qparams, hard_mask, rd: RDStep):
         c = rd.ctx
+        rd.generation += 1
         c.render_fwd(qparams, hard_mask, rd.image, rd.final_T, rd.last, None)
         ctx.rd = rd
+        ctx.generation = rd.generation
         ctx.save_for_backward(qparams, hard_mask)
         return rd.image.clone()
 
@@ -57,6 +76,7 @@ class Render(torch.autograd.Function):
     def backward(ctx, gimg):
         qparams, hard_mask = ctx.saved_tensors
         rd: RDStep = ctx.rd
+        _check_current(ctx, rd)
         g = torch.empty_like(qparams)
         rd.ctx.render_bwd(qparams, hard_mask, rd.final_T, rd.last, gimg.contiguous(), g,
                           rd.grad_mask)

@@ -16,6 +16,7 @@
 // (1 - alpha~) the forward multiplied by, and reduces the ten per-splat
 // gradients of a wave with a transposing butterfly (eight lane swaps and
 // five DPP exchanges for all ten values); ten lanes then issue one atomic each.
+#include "blend_reach.h"
 #include "sgs_internal.h"
 
 namespace {
@@ -53,29 +54,11 @@ __device__ __forceinline__ SplatEval eval_splat(const SplatLds &s, int px, int p
   return r;
 }
 
-// Whether a splat can pass the alpha cut-off at any pixel centre of the 8x8
-// sub-tile at (sx0, sy0); a test per list entry, made once per batch.  The
-// log2 Gaussian of the record is a concave quadratic of the offset, so its
-// largest value over the rectangle of the sub-tile's pixel centres is 0
-// when the centre lies inside, else it lies on an edge, where the
-// quadratic's best point is clamped to the edge.  A pixel passes only if
-// opacity 2^p2 >= 1/255; the test keeps the entry when the best value is
-// within 0.05 of log2(1 / (255 opacity)), far above the rounding of either
-// side, so no entry a pixel would take is dropped.  A record whose
-// quadratic is not strictly concave along both axes, or any NaN, keeps it.
+// Whether a splat (record a, b) can pass the alpha cut-off at any pixel
+// centre of the 8x8 sub-tile at (sx0, sy0); a test per list entry, made once
+// per batch (blend_reach.h states the rule and its margin).
 __device__ __forceinline__ bool may_reach(const float4 &a, const float4 &b, int sx0, int sy0) {
-  const float Ap = a.z, Bp = a.w, Cp = b.x;
-  if (!(Ap < 0.0f && Cp < 0.0f)) return true;
-  const float x0 = (float)sx0 - a.x, x1 = x0 + 7.0f;
-  const float y0 = (float)sy0 - a.y, y1 = y0 + 7.0f;
-  if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return true;
-  auto p2 = [&](float dx, float dy) { return Ap * dx * dx + Cp * dy * dy + Bp * dx * dy; };
-  const float kx = -0.5f * Bp / Cp, ky = -0.5f * Bp / Ap;
-  auto on_x = [&](float dx) { return p2(dx, fminf(fmaxf(kx * dx, y0), y1)); };
-  auto on_y = [&](float dy) { return p2(fminf(fmaxf(ky * dy, x0), x1), dy); };
-  const float best = fmaxf(fmaxf(on_x(x0), on_x(x1)), fmaxf(on_y(y0), on_y(y1)));
-  const float need = -__log2f(255.0f * b.y);
-  return !(best + 0.05f < need);
+  return sgs_may_reach(a.x, a.y, a.z, a.w, b.x, -__log2f(255.0f * b.y), sx0, sy0);
 }
 
 // A 64-bit mask read from LDS, made wave-uniform (held in scalar registers).

@@ -58,12 +58,16 @@ class RDStep:
         self.grad_mask = e(n)
         self.grad_q = e(NCH)
         self.grad_score = e(n)
+        # forwards issued on this step's buffers (and context): a backward
+        # must follow the forward it differentiates, with no other in between
+        self.generation = 0
 
     def forward(self, params, qstep, score, target, lam: float, mask_mode: int = 0,
                 given_mask=None, seed: int = 0, step: int = 0, count_evals: bool = True,
                 loss_scale: float = 1.0, ssim_weight: float = 0.0):
         c = self.ctx
         ev = self.evals if count_evals else None
+        self.generation += 1
         if self.fused:
             c.quant_render_fwd(params, qstep, score, mask_mode, given_mask, seed, step,
                                self.hard, self.soft, self.stats, self.image, self.final_T,

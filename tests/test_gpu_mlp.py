@@ -3,9 +3,12 @@ ABI) against the FP64 oracle with BF16 mirroring, and a training run on the
 GPU that shows what the learned estimate gains over the plain range proxy.
 
 Bars (BF16 inputs/weights/activations, FP32 accumulation): outputs and
-gradients within 1e-3 relative in L2; element-wise within 1e-2 relative on
-entries above 1 % of the largest (a BF16 rounding of a hidden activation
-can flip between FP32 and FP64 at a tie boundary, one BF16 ulp is 0.4 %).
+gradients within 1e-3 relative in L2.  Element-wise: the weight gradients of
+a training step within 1e-3 relative on entries above 1 % of the largest
+(each is a sum over the batch, where a single flipped rounding weighs
+little); per-Gaussian outputs f (and the mask gradient f / N_hat) within
+1e-2, because one BF16 rounding of a hidden activation can land on the other
+side of a rounding midpoint in FP32 than in FP64, and one BF16 ulp is 0.4 %.
 """
 import sys
 
@@ -131,7 +134,7 @@ def test_mfma_training_gradient_parity(orc, mlp, gctx, dev):
     gr, _ = mlp.backward(X, w, mlp.mse_grad_weights(f, t), mirror=True)
     gg = unflat(g.cpu().numpy(), mlp)
     for k, _ in mlp.WEIGHT_SHAPES:
-        close(gg[k], gr[k], f"d{k}", tol=2e-3, ew_tol=2e-2)
+        close(gg[k], gr[k], f"d{k}", tol=1e-3, ew_tol=1e-3)
 
 
 def test_learned_rate_in_loop_parity(orc, mlp, gctx, dev):

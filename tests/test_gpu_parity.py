@@ -5,9 +5,20 @@ Bars: structure (codes k, hard mask, culling, spans, depth keys, sorted tile
 lists, ranges, per-pixel stop positions) bit-exact; pixels within 1e-4
 absolute outside margin pixels (where FP32 and FP64 may take a different
 per-pair decision: alpha within 2e-5 relative of 1/255 or 0.99, or T within
-2e-5 relative of 1e-4); gradients within 1e-3 relative (per tensor in L2, and
-element-wise on entries above 1 % of the tensor's largest); rate scalars
-within 1e-6 relative.
+2e-5 relative of 1e-4); margin pixels at most 1e-3 of all pixels, and margin
+pixels whose value or stop position actually differs at most 1e-5 of them;
+the L1 gradient dL/dC element-wise within 1e-6 relative wherever |C - target|
+> 1e-4; gradients within 1e-3 relative (per tensor in L2, and element-wise on
+entries above 1 % of the tensor's largest); rate scalars within 1e-6
+relative.
+
+Every forward is run twice: with the evaluation count (which keeps every
+in-span list entry) and without it (the timed path, which drops the entries
+that cannot reach the alpha cut-off in a sub-tile); the two must give the
+same image, transmittance and stop positions bit for bit, and both are
+compared with the oracle.  Both backward passes take the oracle's own L1
+gradient, zeroed at the oracle's margin pixels (no oracle input comes from
+the GPU).
 """
 import sys
 
@@ -63,12 +74,14 @@ def grad_close(g, ref, tol=1e-3, name=""):
 
 def run_pair(orc, gctx, dev, sc, tile=(16, 16), lam=0.5, mode=0, seed=0, step=0,
              schedule="tile", fused=False):
-    """GPU step and oracle step on the same inputs.  Both backward passes get
-    the same dL/dimage: the GPU's L1 gradient with the oracle's margin pixels
-    zeroed, so no gradient depends on a decision FP32 and FP64 may take
-    differently at a kink (alpha clamp, alpha cut-off, termination).
-    fused: the GPU step runs quant_render_fwd / quant_render_bwd (the quantized
-    rows and their gradient are then not materialized)."""
+    """GPU step and oracle step on the same inputs.  The GPU forward runs with
+    and without the evaluation count (bit-identical results required).  Both
+    backward passes get the same dL/dimage: the oracle's L1 gradient with the
+    oracle's margin pixels zeroed, so no gradient depends on a decision FP32
+    and FP64 may take differently at a kink (alpha clamp, alpha cut-off,
+    termination).  fused: the GPU step runs quant_render_fwd /
+    quant_render_bwd (the quantized rows and their gradient are then not
+    materialized)."""
     from paper_2607_12656_amd.rd import RDStep
     _say(f"[gpu] {sc.name} tile={tile} schedule={schedule} mode={mode} n={sc.n} V={sc.views}"
          f" fused={fused}")
@@ -78,15 +91,35 @@ def run_pair(orc, gctx, dev, sc, tile=(16, 16), lam=0.5, mode=0, seed=0, step=0,
     mask, target = T(sc.given_mask, dev), T(sc.target, dev)
     rd.forward(params, q, score, target, lam, mode, mask, seed, step)
     torch.cuda.synchronize()
+    counted = [x.cpu().numpy().view(np.uint32) for x in (rd.image, rd.final_T, rd.last)]
+    rd.forward(params, q, score, target, lam, mode, mask, seed, step, count_evals=False)
+    torch.cuda.synchronize()
+    timed = [x.cpu().numpy().view(np.uint32) for x in (rd.image, rd.final_T, rd.last)]
+    for name, a, b in zip(("image", "T", "last"), counted, timed):
+        assert np.array_equal(a, b), f"{name}: counting and timed forward differ"
     s = orc.rd_forward(sc.params, sc.qstep, sc.score, sc.given_mask, sc.cams, sc.width,
                        sc.height, sc.target, sc.n, sc.n_hat, lam, mask_mode=mode, seed=seed,
                        step=step, TW=tile[0], TH=tile[1])
-    dimage = rd.dimage.cpu().numpy()
-    dimage = dimage * (s["fw"]["margin"] == 0)[:, None, :, :]
+    l1_oracle = s["dimage"].copy()
+    dimage = (s["dimage"] * (s["fw"]["margin"] == 0)[:, None, :, :]).astype(np.float32)
     g = gpu_backward(gctx, dev, sc, rd, params, q, mode, tile, dimage)
     g["dimage_l1"] = rd.dimage.cpu().numpy()
-    r = orc.rd_backward(s, dimage)
+    r = orc.rd_backward(s, dimage.astype(np.float64))
+    r["l1_grad"] = l1_oracle
     return g, r
+
+
+def check_l1(g, r, sc):
+    """L1 loss within 1e-6 and dL/dC element by element (value and scale),
+    off pixels where |C - target| <= 1e-4 (the sign may flip there) and off
+    margin pixels."""
+    assert abs(g["loss"] - r["D"]) <= 1e-6 * r["D"], f"L1 {g['loss']} vs {r['D']}"
+    ok = (r["fw"]["margin"] == 0)[:, None, :, :]
+    far = (np.abs(r["fw"]["image"] - sc.target) > 1e-4) & ok
+    ref = r["l1_grad"]
+    err = np.abs(g["dimage_l1"].astype(np.float64) - ref)[far]
+    assert far.mean() > 0.99
+    assert (err <= 1e-6 * np.abs(ref[far])).all(), f"dL/dC max error {err.max():.3e}"
 
 
 def gpu_backward(gctx, dev, sc, rd, params, q, mode, tile, dimage):
@@ -155,14 +188,19 @@ def check_stats(g, r, sc):
 def check_image(g, r):
     ok = r["fw"]["margin"] == 0
     frac = 1 - ok.mean()
-    err = np.abs(g["image"] - r["fw"]["image"]).max(axis=1)[ok].max()
-    terr = np.abs(g["T"] - r["fw"]["T"])[ok].max()
-    assert err <= 1e-4, f"pixel error {err:.3e}"
-    assert terr <= 1e-4, f"transmittance error {terr:.3e}"
-    assert np.array_equal(g["last"][ok], r["fw"]["last"][ok].astype(np.uint32)), "stop positions"
+    perr = np.maximum(np.abs(g["image"] - r["fw"]["image"]).max(axis=1),
+                      np.abs(g["T"] - r["fw"]["T"]))
+    err = perr[ok].max()
+    assert err <= 1e-4, f"pixel / transmittance error {err:.3e}"
+    same_last = g["last"] == r["fw"]["last"].astype(np.uint32)
+    assert same_last[ok].all(), "stop positions"
     assert frac <= 1e-3, f"margin pixels {frac:.2e}"
+    # margin pixels that really took another decision
+    moved = ~ok & ((perr > 1e-4) | ~same_last)
+    assert moved.sum() <= 1e-5 * ok.size, f"{moved.sum()} margin pixels differ"
     if not (~ok).any():
         assert g["evals"] == r["fw"]["evals"]
+    g["margin_moved"] = int(moved.sum())
     return err, frac
 
 
@@ -183,15 +221,18 @@ def test_tiny_scenes_full_step(orc, gctx, dev, tile, cfg):
     check_structure(g, r, sc)
     check_stats(g, r, sc)
     check_image(g, r)
-    # L1 forward and its gradient (signs agree wherever |C - target| > 1e-4)
-    assert abs(g["loss"] - r["D"]) <= 1e-6 * r["D"]
-    far = np.abs(r["fw"]["image"] - sc.target) > 1e-4
-    assert np.array_equal(np.sign(g["dimage_l1"])[far], np.sign(r["fw"]["image"] - sc.target)[far])
+    check_l1(g, r, sc)
     # render backward fed the same dL/dimage
     grad_close(g["gq_render"][:, :sc.n], r["gyhat"][:, :sc.n], name="grad qparams")
     grad_close(g["gmask"], r["gmhat"], name="grad mask")
     grad_close(g["gparams"][:, :sc.n], r["gy"][:, :sc.n], name="grad params")
     grad_close(g["gq"], r["gq"], name="grad qstep")
+    # the exported per-(view, Gaussian) splat gradients (the records the
+    # sampled full-size test compares) against the oracle's
+    _, _, gs = orc.backward(r["p64"], r["m64"], sc.n, sc.cams, sc.width, sc.height, r["st"],
+                            r["dimage"], want_splat=True)
+    for k, name in enumerate(("px", "py", "A", "B", "C", "opacity", "r", "g", "b", "mask")):
+        grad_close(g["sgrad"][..., k], gs[..., k], name=f"splat grad {name}")
 
 
 def test_projection_records(orc, gctx, dev):
@@ -218,10 +259,44 @@ def test_c1_full_step(orc, gctx, dev):
         check_structure(g, r, sc)
         check_stats(g, r, sc)
         err, frac = check_image(g, r)
+        check_l1(g, r, sc)
         _say(f"c1 lam={lam}: pixel err {err:.2e}, margin {frac:.2e}, P={g['P']}, E={g['evals']}")
         grad_close(g["gparams"][:, :sc.n], r["gy"][:, :sc.n], name="grad params")
         grad_close(g["gq"], r["gq"], name="grad qstep")
         grad_close(g["gmask"], r["gmhat"], name="grad mask")
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_end_to_end_each_side_own_l1_gradient(orc, gctx, dev, fused):
+    """The whole step with nothing shared but the inputs: each side takes its
+    own L1 gradient into its own backward.  Scenes are drawn (seeds in a
+    fixed order) until one has no margin pixel and no colour within 1e-4 of
+    its target, where the two sides could legitimately differ."""
+    from paper_2607_12656_amd.rd import RDStep
+    lam = 0.5
+    for seed in range(40, 60):
+        sc = synth.make_tiny(120, 56, 40, views=2, seed=seed)
+        s = orc.rd_step(sc.params, sc.qstep, sc.score, sc.given_mask, sc.cams, sc.width,
+                        sc.height, sc.target, sc.n, sc.n_hat, lam)
+        near = np.abs(s["fw"]["image"] - sc.target) <= 1e-4
+        if s["fw"]["margin"].any() or near.any():
+            continue
+        break
+    else:
+        pytest.fail("no seed without margin pixels and near-target colours")
+    _say(f"[gpu] end-to-end seed {seed} fused={fused}")
+    rd = RDStep(gctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height, fused=fused)
+    params, q, score = T(sc.params, dev), T(sc.qstep, dev), T(sc.score, dev)
+    mask, target = T(sc.given_mask, dev), T(sc.target, dev)
+    rd.forward(params, q, score, target, lam, 0, mask, 0, 0, count_evals=False)
+    gp = torch.empty_like(params)
+    rd.backward(params, q, 0, grad_params=gp)
+    torch.cuda.synchronize()
+    assert abs(float(rd.loss.item()) - s["D"]) <= 1e-6 * s["D"]
+    assert np.abs(rd.image.cpu().numpy() - s["fw"]["image"]).max() <= 1e-4
+    grad_close(gp.cpu().numpy()[:, :sc.n], s["gy"][:, :sc.n], name="grad params")
+    grad_close(rd.grad_q.cpu().numpy(), s["gq"], name="grad qstep")
+    grad_close(rd.grad_mask.cpu().numpy(), s["gmhat"], name="grad mask")
 
 
 @pytest.mark.parametrize("schedule", ["stride", "queue", "block"])
@@ -233,6 +308,7 @@ def test_persistent_schedules(orc, gctx, dev, tile, schedule):
     g, r = run_pair(orc, gctx, dev, sc, tile=tile, schedule=schedule)
     check_structure(g, r, sc)
     check_image(g, r)
+    check_l1(g, r, sc)
     grad_close(g["gparams"][:, :sc.n], r["gy"][:, :sc.n], name="grad params")
     grad_close(g["gmask"], r["gmhat"], name="grad mask")
 
@@ -245,6 +321,7 @@ def test_gumbel_mask_mode(orc, gctx, dev):
         assert np.allclose(g["soft"], r["msoft"], atol=2e-6)
         check_structure(g, r, sc)
         check_image(g, r)
+        check_l1(g, r, sc)
         grad_close(g["gscore"], r["gs"], name="grad score")
     # keep-all mode
     g, _ = run_pair(orc, gctx, dev, sc, mode=2)
@@ -287,6 +364,7 @@ def test_fused_step_matches_oracle(orc, gctx, dev, case):
     check_structure(g, r, sc)
     check_stats(g, r, sc)
     check_image(g, r)
+    check_l1(g, r, sc)
     if mode == 1:
         assert np.allclose(g["soft"], r["msoft"], atol=2e-6)
         grad_close(g["gscore"], r["gs"], name="grad score")
@@ -348,6 +426,7 @@ def test_full_size_1m_workload(orc, gctx, dev):
     check_structure(g, r, sc)
     check_stats(g, r, sc)
     err, frac = check_image(g, r)
+    check_l1(g, r, sc)
     _say(f"c2: pixel err {err:.2e}, margin {frac:.2e}, P={g['P']}, E={g['evals']}")
     grad_close(g["gq_render"][:, :sc.n], r["gyhat"][:, :sc.n], name="grad qparams")
     grad_close(g["gmask"], r["gmhat"], name="grad mask")
@@ -363,13 +442,82 @@ def test_full_size_1m_workload_fused(orc, gctx, dev):
     check_structure(g, r, sc)
     check_stats(g, r, sc)
     err, frac = check_image(g, r)
+    check_l1(g, r, sc)
     _say(f"c2 fused: pixel err {err:.2e}, margin {frac:.2e}, P={g['P']}, E={g['evals']}")
     grad_close(g["gparams"][:, :sc.n], r["gy"][:, :sc.n], name="grad params")
     grad_close(g["gmask"], r["gmhat"], name="grad mask")
     grad_close(g["gq"], r["gq"], name="grad qstep")
 
 
-def test_full_size_3m_8views_sampled(orc, gctx, dev):
+@pytest.fixture(scope="module")
+def c3_case(orc):
+    """The 3M x 8-view scene, its quantized parameters and the oracle's
+    decision layer (culling, spans, depths; no pair list)."""
+    sc = synth.make_scene("c3")
+    yh, _ = orc.fakequant(sc.params, sc.qstep, sc.n)
+    lite = orc.decide(yh, sc.n, sc.cams, sc.width, sc.height, 16, 16, bin_pairs=False)
+    return sc, yh, lite
+
+
+def test_full_size_3m_8views_gradients_sampled(orc, gctx, dev, c3_case):
+    """Gradients at 3M Gaussians x 8 views of 1600x1060 (the bench's launch
+    configuration, the timed forward path): 24 Gaussians (20 kept, 4
+    pruned), each with its splat gradients in every view summed by the
+    oracle over every pixel of its span (each pixel composited by brute
+    force over the view's splats in depth order), the projection backward
+    summed over views, and the mask gradient.  The upstream gradient is a
+    seeded +-1/(3VHW) pattern (the L1 gradient's shape), zeroed at the
+    oracle's margin pixels inside those spans on both sides."""
+    from paper_2607_12656_amd.rd import RDStep
+    sc, yh, lite = c3_case
+    n, V, W, H = sc.n, sc.views, sc.width, sc.height
+    _say(f"[gpu] c3 gradients n={n} V={V} {W}x{H}")
+    rng = np.random.default_rng(17)
+    valid = lite.valid > 0
+    nvalid = valid.sum(0)
+    rmax = np.where(valid, lite.radius, 0).max(0)
+    ok = (nvalid >= 4) & (rmax >= 2) & (rmax <= 10)
+    kept = sc.given_mask > 0
+    sel = np.concatenate([rng.choice(np.flatnonzero(ok & kept), 20, replace=False),
+                          rng.choice(np.flatnonzero(ok & ~kept), 4, replace=False)])
+    p64 = yh.astype(np.float64)
+    m64 = sc.given_mask.astype(np.float64)
+    _, _, margin = orc.splat_grads_sampled(p64, m64, n, sc.cams, W, H, lite, sel)
+    drng = np.random.default_rng(23)
+    d = np.where(drng.random((V, 3, H, W), dtype=np.float32) < 0.5, -1.0, 1.0).astype(np.float32)
+    d *= np.float32(1.0 / (3 * V * W * H))
+    d *= (margin == 0)[:, None, :, :]
+    _say(f"c3 gradients: {int(margin.sum())} margin pixels in the chosen spans")
+
+    rd = RDStep(gctx, n, sc.npad, sc.n_hat, sc.cams, W, H, tile=(16, 16))
+    gctx.reserve_pairs(lite.pairs + lite.pairs // 8 + 4096)
+    params, q, score = T(sc.params, dev), T(sc.qstep, dev), T(sc.score, dev)
+    mask, target = T(sc.given_mask, dev), T(sc.target, dev)
+    rd.forward(params, q, score, target, 2.5e-5, 0, mask, 0, 0, count_evals=False)
+    gp = torch.empty_like(params)
+    rd.backward(params, q, 0, grad_params=gp, dimage=T(d, dev))
+    del gp
+    sg = torch.empty(V, n, 12, dtype=torch.float32, device=dev)
+    gctx.copy_splat_grads(sg)
+    sel_t = torch.from_numpy(sel).to(dev)
+    g_splat = sg[:, sel_t, :10].cpu().numpy().transpose(1, 0, 2)     # [k][V][10]
+    del sg
+    g_param = rd.grad_qparams[:, sel_t].cpu().numpy().T              # [k][59]
+    g_mask = rd.grad_mask[sel_t].cpu().numpy()
+    torch.cuda.synchronize()
+    gs, gpar, _ = orc.splat_grads_sampled(p64, m64, n, sc.cams, W, H, lite, sel,
+                                          d.astype(np.float64))
+    culled = ~valid[:, sel].T
+    assert not g_splat[culled].any(), "culled (view, Gaussian) with a gradient"
+    for k, name in enumerate(("px", "py", "A", "B", "C", "opacity", "r", "g", "b", "mask")):
+        grad_close(g_splat[..., k], gs[..., k], name=f"splat grad {name}")
+    grad_close(g_param, gpar, name="grad qparams (render)")
+    grad_close(g_mask, gs[..., 9].sum(1), name="grad mask (render)")
+    _say(f"c3 gradients: {len(sel)} Gaussians over {int(valid[:, sel].sum())} (view, Gaussian) "
+         f"spans agree")
+
+
+def test_full_size_3m_8views_sampled(orc, gctx, dev, c3_case):
     """3M Gaussians x 8 views of 1600x1060 in the bench's launch configuration
     (16x16 tiles, reserved pair capacity, about 5.5e8 pairs).  Full check of
     what the oracle can afford at this size: quantized parameters, hard mask,
@@ -378,12 +526,10 @@ def test_full_size_3m_8views_sampled(orc, gctx, dev):
     of 24 tiles (the heaviest, the ragged bottom row, random ones) and the
     colour and transmittance of 24 pixels per view by brute force."""
     from paper_2607_12656_amd.rd import RDStep
-    sc = synth.make_scene("c3")
+    sc, yh, lite = c3_case
     n, V, W, H = sc.n, sc.views, sc.width, sc.height
     lam = 2.5e-5
     _say(f"[gpu] c3 n={n} V={V} {W}x{H}")
-    yh, _ = orc.fakequant(sc.params, sc.qstep, n)
-    lite = orc.decide(yh, n, sc.cams, W, H, 16, 16, bin_pairs=False)
     cnt = orc.tile_counts(lite, n, V, W, H)
     assert cnt.sum() == lite.pairs
 
@@ -461,8 +607,18 @@ def test_full_size_3m_8views_sampled(orc, gctx, dev):
     img = rd.image.cpu().numpy()
     Tg = rd.final_T.cpu().numpy()
     ok = mg == 0
-    assert ok.mean() >= 0.9, f"too many margin pixels ({(~ok).sum()})"
+    # about 3.5e-4 of the pixels are margin pixels at this size (71 in-span
+    # evaluations per pixel): expect none or one among these 192
+    assert (~ok).sum() <= 2, f"too many margin pixels ({(~ok).sum()})"
     g = np.concatenate([img[px[:, 0], :, px[:, 2], px[:, 1]], Tg[px[:, 0], px[:, 2], px[:, 1]][:, None]], 1)
     err = np.abs(g - out)[ok].max()
     _say(f"c3: {ok.sum()} sampled pixels, max error {err:.2e}")
     assert err <= 1e-4, f"sampled pixel error {err:.3e}"
+    # the L1 gradient at the sampled pixels: sign(C - target) / (3 V H W)
+    # from the brute-force colours, wherever |C - target| > 1e-4
+    dg = rd.dimage.cpu().numpy()[px[:, 0], :, px[:, 2], px[:, 1]].astype(np.float64)
+    tg = sc.target[px[:, 0], :, px[:, 2], px[:, 1]].astype(np.float64)
+    diff = out[:, :3] - tg
+    far = (np.abs(diff) > 1e-4) & ok[:, None]
+    ref = np.sign(diff) / (3.0 * V * W * H)
+    assert (np.abs(dg - ref)[far] <= 1e-6 * np.abs(ref[far])).all(), "L1 gradient"

@@ -570,6 +570,27 @@ def test_sampled_oracle_helpers_agree_with_full_binning(orc):
     for k, (v, u, y) in enumerate(pix):
         assert np.array_equal(out[k, :3], full["image"][v, :, y, u])
         assert out[k, 3] == full["T"][v, y, u]
+    # per-Gaussian gradients by brute force over span pixels = the full backward
+    dimg = rng.normal(size=(2, 3, sc.height, sc.width))
+    gp_full, gm_full, gs_full = orc.backward(p64, m, sc.n, sc.cams, sc.width, sc.height, st,
+                                             dimg, want_splat=True)
+    sel = np.array([0, 3, 17, 40, 41, 79])
+    gs, gpar, margin = orc.splat_grads_sampled(p64, m, sc.n, sc.cams, sc.width, sc.height,
+                                               lite, sel, dimg)
+    fw = orc.forward(p64, m, sc.n, sc.cams, sc.width, sc.height, st)
+    for q, i in enumerate(sel):
+        scale = np.abs(gs_full[:, i]).max() + 1e-30
+        assert np.abs(gs[q] - gs_full[:, i]).max() <= 1e-12 * scale
+        pscale = np.abs(gp_full[:, i]).max() + 1e-30
+        assert np.abs(gpar[q] - gp_full[:, i]).max() <= 1e-12 * pscale
+        assert gs[q, :, 9].sum() == pytest.approx(gm_full[i], rel=1e-12, abs=1e-15)
+        # margin flags: exactly the full forward's margin pixels inside the spans
+        for v in range(2):
+            if lite.valid[v, i]:
+                x0, x1, y0, y1 = lite.span[v, i]
+                x0, y0 = max(x0, 0), max(y0, 0)
+                win = fw["margin"][v, y0:y1 + 1, x0:x1 + 1]
+                assert np.array_equal(margin[v, y0:y1 + 1, x0:x1 + 1] | (win == 0), np.ones_like(win))
 
 
 # ---------------------------------------------------------------------------
