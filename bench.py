@@ -1,37 +1,43 @@
 #!/usr/bin/env python
-"""Benchmark of one RD step (forward + backward) of SpeedyGS's structural
-formation on one MI355X.
+"""Benchmark of SpeedyGS's structural-formation step on one MI355X.
 
-Default workload (the measured configuration): plain rate proxy, 1,000,000
-Gaussians (clustered: 3-component mixture), one 1297x840 camera on the
-radius-4 ring, learned per-channel steps initialised to 2^-6, 20 % pruned by
-a given mask, L1 distortion against a seeded random target, lambda 2.5e-5,
-16x16 tiles.  `--workload c3`: 3,000,000 Gaussians, 8 views of 1600x1060,
-tile shape from the autotuner.  Inputs are synthetic (seeded) and resident
-in HBM before the timed region.
+Default workload (``--workload c5``): the full formation iteration at
+3,000,000 Gaussians (clustered: 3-component mixture) rendered in 8 views of
+1600x1060 on a radius-4 ring, Gumbel-sigmoid retention mask, L1 distortion
+against a seeded random target, lambda 2.5e-5, the learned rate estimator in
+the loop (MLP forward + recompute backward; the range proxy evaluated beside
+it) and Adam on (parameters, step sizes, scores) so the scene evolves.  The
+same iterations with the plain range proxy are timed beside it.  Tile shape
+and blend schedule come from the library's autotuner; the estimator is
+trained first on the GPU on this scene's exact fixed-length coder bits.
 
-A step = fake-quantize + mask + channel statistics, rate proxy, projection,
-depth sort, pair emission, tile sort, ranges, blend, L1, blend backward,
-projection backward, quantizer/mask backward (all in libspeedygs kernels).
-The pair capacity is reserved once, so a step never synchronizes.
+A step = one iteration: fake-quantize + mask + channel statistics and
+projection (one call), rate proxy, learned rate forward, depth sort, pair
+emission, tile sort, ranges, blend, L1, blend backward, projection and
+quantizer backward, learned rate backward, Adam; all in libspeedygs
+kernels, no host synchronization.  Timed region: K iterations replayed from
+HIP graphs, one graph per iteration of a 16-iteration period (the higher-SH
+update period), launched in turn; their Gumbel-noise step and Adam step
+count repeat with that period.  The evaluation counts and per-kernel times
+come from re-runs of the same K iterations from the same starting state
+(restored in place), outside the timed region.
 
-Prints one JSON line: ms/step and Gaussian-pixel evaluations per second
-(E / step time, E = in-support (Gaussian, pixel) evaluations of the forward,
-the set the backward re-walks) over K replays of the step captured in a HIP
-graph; the same step enqueued eagerly, with the roofline of the dominant
-kernel group (HIP events recorded on the library's stream around every kernel
-group over that run); the learned-rate
-step (MLP in the loop, forward + recompute backward) timed beside it, the
-MLP's training / inference throughput, the fixed-length encode / decode of
-the kept Gaussians (Sec. 3.4.1), the SSIM term of the distortion, the
-Laplace rate proxy beside the range proxy, and the FP64 oracle timed on the
-host as a CPU baseline.
+Prints one JSON line.  ``value`` = E / t: Gaussian-pixel evaluations per
+second, E = the method's evaluations (in-span (Gaussian, pixel) pairs before
+the pixel stops) summed over the K iterations of the learned run.  Also:
+the plain-proxy run, both runs enqueued eagerly, the RD step alone (forward
++ backward, graph-replayed), the rate-estimate errors against the exact coder
+bits, the roofline of the dominant kernel group, the 1M-Gaussian single-view
+step (``c2``) as a sub-record, the MLP / codec / SSIM / rate-variant legs at
+1M, and the FP64 oracle on the host on a bounded sample of this workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -43,26 +49,29 @@ HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
-# Algorithmic work per unit of each kernel group.
 NCH = 59
-FLOP_PER_EVAL_FWD = 24     # offsets 2, quadratic form 9, exp 2, alpha/T 5, colour 6
-FLOP_PER_EVAL_BWD = 60     # alpha recompute 15, T and dalpha 12, 10 gradients 23, back colour 10
+# FP32 work per evaluation (counted as VALU operations, the exponential as 4):
+# forward 22 + 4 (support 4, offsets 2, quadratic 6, alpha 2, thresholds 2,
+# T test 2, colour 3, T 1); backward 70 + 4 (recompute, T recovery, dalpha,
+# ten gradient terms, back colour, wave sums)
+FLOP_PER_EVAL_FWD = 26
+FLOP_PER_EVAL_BWD = 74
 MLP_FLOP_PER_ROW = 2 * (64 * 128 + 128 * 128 + 128)
+METRIC = "RD-step ms/iter & Gaussian-pixel evals/s (fwd+bwd), learned vs plain rate"
+PERIOD = 16
 
 
 def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int):
-    """(bound, algorithmic amount per launch, unit) of one kernel group."""
+    """(bound, algorithmic amount per launch, unit) of one kernel group; E is
+    the count of evaluations the blend performs (after its reach test)."""
     pix = V * W * H
-    # the step runs the fused entry points: the quantizer pass reads the rows
-    # for the rate statistics only, the projections quantize in registers,
-    # and the projection backward applies the quantizer's backward
-    if g == "fakequant":
+    if g == "fakequant":          # statistics and mask (the projection quantizes)
         return "hbm", n * (NCH * 4 + 1 + 1 + 4), "B"
     if g == "preprocess":
         return "hbm", n * (NCH * 4 + 1) + V * n * (48 + 12), "B"
     if g in ("depth_sort", "scan"):
         return "hbm", V * n * 16, "B"
-    if g == "duplicate":
+    if g == "duplicate":          # pair emission + first tile-sort pass
         return "hbm", V * n * 12 + P * 8, "B"
     if g == "tile_sort":
         return "hbm", P * 16, "B"
@@ -73,59 +82,193 @@ def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int):
     if g == "l1":
         return "hbm", pix * 3 * 12, "B"
     if g == "grad_clear":
-        return "hbm", V * n * 48, "B"
+        return "hbm", V * n * 80, "B"
     if g == "blend_bwd":
         return "alu", E * FLOP_PER_EVAL_BWD, "FLOP"
     if g == "preprocess_bwd":
-        return "hbm", n * (NCH * 4 * 2 + 4 + 4) + V * n * 48, "B"
-    if g == "fakequant_bwd":     # the step-size partials of the projection backward
+        return "hbm", n * (NCH * 4 * 2 + 4 + 4) + V * n * 80, "B"
+    if g == "fakequant_bwd":
         return "hbm", NCH * 8 * -(-n // 128), "B"
+    if g == "adam":               # y, m, v read + written, g read; steps and scores
+        return "hbm", n * (NCH * 4 * 7 + 4 * 7), "B"
+    if g in ("mlp_fwd", "mlp_bwd"):
+        return "mfma", n * MLP_FLOP_PER_ROW * (1 if g == "mlp_fwd" else 2), "FLOP"
     return "hbm", 0, "B"
 
 
-def roofline(g, ms, n, V, P, E, W, H):
+def roofline(g, ms, n, V, P, E, W, H, traffic_key=None):
     bound, amount, unit = group_work(g, n, V, P, E, W, H)
     dur = ms * 1e-3
     if unit == "B":
         achieved, peak, ru = amount / dur / 1e9, HBM_PEAK_GBS, "GB/s"
+    elif bound == "mfma":
+        achieved, peak, ru = amount / dur / 1e12, BF16_MFMA_PEAK_TFLOPS, "TFLOP/s"
     else:
         achieved, peak, ru = amount / dur / 1e12, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
-    return {"bound": bound, "kernel": g, "achieved": round(achieved, 3), "peak": peak,
-            "unit": ru, "frac": round(achieved / peak, 5), "traffic": None,
-            "algorithmic_per_launch": amount, "avg_launch_ms": round(ms, 4)}
+    r = {"bound": bound, "kernel": g, "achieved": round(achieved, 3), "peak": peak,
+         "unit": ru, "frac": round(achieved / peak, 5), "traffic": None,
+         "algorithmic_per_launch": amount, "avg_launch_ms": round(ms, 4)}
+    if traffic_key:
+        t = traffic_for(traffic_key)
+        if t:
+            r["traffic"], r["traffic_source"] = t
+    return r
 
 
-def cpu_baseline(sc, lam):
+def traffic_for(key):
+    """HBM bytes per launch measured with rocprofv3 counters for this kernel
+    group and workload, valid while its sources are unchanged."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    ent = json.load(open(path)).get(key)
+    if not ent:
+        return None
+    h = hashlib.sha256()
+    for f in ent.get("kernel_files", [ent.get("kernel_file")]):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest()[:16] != ent["kernel_sha256_16"]:
+        return None
+    return ent["bytes_per_launch"], ent["source"] + " (profiles/hbm_traffic_*.md)"
+
+
+def host_info():
+    model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on a bounded sample of the workload
+# ---------------------------------------------------------------------------
+
+def cpu_baseline_c5(sc, tiles_per_view=16, seed=9):
+    """The oracle's render forward + backward over tiles_per_view random 16x16
+    tiles per view (each tile's whole list; dL/dC a +-1/(3VHW) pattern, the
+    L1 gradient's form), serial and with OpenMP over the tiles, plus the
+    quantizer, mask, range proxy and the learned estimator on a
+    proportional sample of Gaussians; extrapolated to the whole step."""
+    import numpy as np
+
+    import oracle
+    from oracle import mlp as omlp
+
+    n, V, W, H = sc.n, sc.views, sc.width, sc.height
+    GW, GH = -(-W // 16), -(-H // 16)
+    total_tiles = V * GW * GH
+    rng = np.random.default_rng(seed)
+    tiles = np.concatenate([v * GW * GH + np.sort(rng.choice(GW * GH, tiles_per_view,
+                                                              replace=False))
+                            for v in range(V)])
+    frac = tiles.size / total_tiles
+    t0 = time.perf_counter()
+    yh, _ = oracle.fakequant(sc.params, sc.qstep, n)
+    mh, ms = oracle.mask(n, 1, None, sc.score, 5, 0, 1.0)
+    rp = oracle.rate_proxy(sc.params, sc.qstep, mh, n, sc.n_hat, 2.5e-5)
+    t_quant = time.perf_counter() - t0
+    lite = oracle.decide(yh, n, sc.cams, W, H, 16, 16, bin_pairs=False)
+    t_decide = time.perf_counter() - t0 - t_quant
+    p64, m64 = yh.astype(np.float64), mh.astype(np.float64)
+    d = np.where(rng.random((V, 3, H, W), dtype=np.float32) < 0.5, -1.0, 1.0)
+    d *= 1.0 / (3 * V * W * H)
+    legs = {}
+    for name, par in (("serial", False), ("openmp", True)):
+        t1 = time.perf_counter()
+        E, _, _ = oracle.step_tiles_sampled(p64, m64, n, sc.cams, W, H, lite, tiles, d,
+                                            parallel=par)
+        legs[name] = (E, time.perf_counter() - t1)
+    del p64
+    # learned estimator (FP64, no BF16 mirroring) on a proportional row sample
+    rows = max(256, int(round(n * frac)))
+    w = omlp.init_weights(3)
+    idx = rng.choice(n, rows, replace=False)
+    t2 = time.perf_counter()
+    mmin = omlp.channel_min(sc.params, n)
+    sub = np.ascontiguousarray(sc.params[:, idx])
+    X = omlp.features(sub, sc.qstep, mmin, rows, mirror=False)
+    f = omlp.forward(X, w, mirror=False)
+    omlp.backward(X, w, np.full(rows, 1.0 / sc.n_hat), mirror=False, want_dx=True)
+    t_mlp = time.perf_counter() - t2
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or host_info()["usable_cpus"]
+    out = {}
+    for name, (E, t) in legs.items():
+        # whole step: render over every tile, estimator over every Gaussian,
+        # decision layer and quantizer once
+        t_step = t / frac + t_mlp * (n / rows) + t_quant + t_decide
+        out[name] = {"evals_sample": E, "seconds_sample": round(t, 2),
+                     "evals_per_s_sample": round(E / t, 1),
+                     "step_seconds_extrapolated": round(t_step, 1),
+                     "evals_per_s_step": round(E / frac / t_step, 1)}
+    best = out["openmp"]
+    info = host_info()
+    return {"value": best["evals_per_s_step"], "unit": "Gaussian-pixel evals/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle, render forward + backward over {tiles.size} random 16x16 "
+                      f"tiles ({tiles_per_view} per view, {frac:.2%} of the pixels, whole tile "
+                      f"lists), OpenMP over tiles with {threads} threads; quantizer, mask, "
+                      f"range proxy and decision layer over all {n} Gaussians; learned "
+                      f"estimator on {rows} Gaussians; extrapolated to one whole iteration "
+                      f"(Adam not included)",
+            "serial": out["serial"], "openmp": best, "cpu_model": info["cpu_model"],
+            "nproc": info["nproc"], "usable_cpus": info["usable_cpus"],
+            "quant_rate_s": round(t_quant, 2), "decision_layer_s": round(t_decide, 2),
+            "mlp_sample_s": round(t_mlp, 3), "rate_R": rp["R"], "f_mean": float(f.mean())}
+
+
+def cpu_baseline_c2(sc, lam):
     """The FP64 oracle, as it stands, on the same workload: one full step
-    (forward + backward) on the same scene and camera, single-threaded."""
+    (forward + backward) of the 1M-Gaussian scene, single-threaded."""
     import oracle
     t0 = time.perf_counter()
     r = oracle.rd_step(sc.params, sc.qstep, sc.score, sc.given_mask, sc.cams, sc.width,
                        sc.height, sc.target, sc.n, sc.n_hat, lam)
     dt = time.perf_counter() - t0
     E = r["fw"]["evals"]
+    info = host_info()
     return {"value": E / dt, "unit": "Gaussian-pixel evals/s", "cores": 1, "kind": "oracle",
             "sample": f"one full RD step (fwd+bwd) of the measured workload, "
                       f"{E} evals in {dt:.1f} s, single thread",
-            "s_per_step": round(dt, 3)}
+            "s_per_step": round(dt, 3), "cpu_model": info["cpu_model"], "nproc": info["nproc"]}
 
 
-def bench_formation(args, sc, ctx, rd, stream, dev, t, tile, schedule, tune):
-    """Full formation iterations at 3M Gaussians x 8 views: RD step on the
-    Gumbel-sigmoid mask, learned rate in the loop (forward + recompute
-    backward), Adam on (y, q, s); the same iterations with the plain proxy.
-    Both start from the same scene; every iteration counts its evaluations.
-    Ends with the rate-estimate error of each rate term against the exact
-    bits of the fixed-length coder on the final state."""
+# ---------------------------------------------------------------------------
+# c5: the formation iteration, learned vs plain rate
+# ---------------------------------------------------------------------------
+
+def bench_formation(args, sc, ctx, stream, dev, t):
     import numpy as np
     import torch
 
+    from paper_2607_12656_amd import autotune
     from paper_2607_12656_amd.formation import Formation
     from paper_2607_12656_amd.rate_train import RateTrainer
+    from paper_2607_12656_amd.rd import RDStep
 
     lam = 2.5e-5
     K, W = args.steps, args.warmup
     p0, q0, s0, target = t(sc.params), t(sc.qstep), t(sc.score), t(sc.target)
+    mask = t(sc.given_mask)
+    say(f"c5: scene {sc.n} x {sc.views} views {sc.width}x{sc.height} resident")
+
+    # tile shape and blend schedule: the library's tuner on the plain step
+    ctx.set_scene(sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height)
+    tune = autotune.tune_native(ctx, p0, q0, mask, target, sc.n, sc.views, sc.width, sc.height,
+                                reps=2)
+    tile, schedule = tune["tile"], tune["schedule"]
+    say(f"c5: tuned {tile} {schedule}")
+    rd = RDStep(ctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height, tile=tile,
+                schedule=schedule, fused=True)
+
     # the estimator, trained on this scene's own coder bits (GPU only)
     t0 = time.perf_counter()
     trainer = RateTrainer(ctx, rd, p0, s0, sc.given_mask, seed=3, scenes=64)
@@ -133,102 +276,422 @@ def bench_formation(args, sc, ctx, rd, stream, dev, t, tile, schedule, tune):
     err_l, err_p = trainer.held_out_errors(theta, packed)
     train_s = time.perf_counter() - t0
     del trainer
+    say(f"c5: estimator trained in {train_s:.1f} s")
     rd.forward(p0, q0, s0, target, lam, 1, None, 5, 0, count_evals=False)
-    P, _ = ctx.query()
-    ctx.reserve_pairs(P + P // 2 + 4096)       # the scene moves; the count is checked after
+    P0, _ = ctx.query()
+    ctx.reserve_pairs(P0 + P0 // 2 + 4096)     # the scene moves; the count is checked after
+
     runs = {}
     for name, mlp in (("learned", (packed, theta)), ("plain", None)):
         p, q, s = p0.clone(), q0.clone(), s0.clone()
         f = Formation(rd, p, q, s, target, lam, mask_mode=1, seed=5, mlp=mlp)
+        e_first = f.check_rate()                # the fallback rule's check before the run
         for _ in range(W):
             f.iterate()
         torch.cuda.synchronize()
-        rd.evals.zero_()
-        ctx.profile_enable(True)
+        start = f.snapshot()
+        # one graph per iteration of the 16-iteration period
+        graphs = []
+        for _ in range(PERIOD):
+            ctx.graph_begin()
+            f.iterate()
+            graphs.append(ctx.graph_end())
+        f.restore(start)
+        for g in graphs[:2]:                    # first launches outside the timed region
+            g.launch(stream)
+        torch.cuda.synchronize()
+        f.restore(start)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(K):
-            f.iterate(count_evals=True)
+        for i in range(K):
+            graphs[i % PERIOD].launch(stream)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        ctx.query()                             # raises if the reserved capacity overflowed
+        # the same iterations enqueued eagerly (no profiling)
+        f.restore(start)
+        f.k = start[1]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            f.iterate()
+        torch.cuda.synchronize()
+        dt_eager = time.perf_counter() - t0
+        # re-runs from the same state: the method's evaluations, the blend's
+        # evaluations after its reach test, per-kernel times
+        counts = {}
+        for mode in (0, 1):
+            f.restore(start)
+            ctx.set_eval_count_mode(mode)
+            rd.evals.zero_()
+            for _ in range(K):
+                f.iterate(count_evals=True)
+            torch.cuda.synchronize()
+            counts[mode] = int(rd.evals.item())
+        ctx.set_eval_count_mode(0)
+        f.restore(start)
+        ctx.profile_enable(True)
+        for _ in range(K):
+            f.iterate()
         prof = ctx.profile_read()
         ctx.profile_enable(False)
-        pairs, _ = ctx.query()                 # raises if the reserved capacity overflowed
-        E = int(rd.evals.item())
-        # the final state: plain proxy, learned estimate and the coder's exact bits
-        c = ctx
-        c.fakequant_prune(p, q, s, 1, None, 5, f.k, rd.qparams, rd.hard, rd.soft, rd.stats)
-        c.rate_proxy(rd.stats, q, 0.0, rd.rate3, None)
-        c.rate_mlp_fwd(packed, theta, p, q, rd.stats, rd.hard, f.R_learned, None)
-        words = sc.n * NCH + 64
-        hdr = torch.empty((NCH, 3), dtype=torch.int32, device=dev)
-        payload = torch.empty(words, dtype=torch.int32, device=dev)
-        info = torch.empty(3, dtype=torch.int64, device=dev)
-        c.fl_encode(p, q, rd.hard, hdr, payload, words, info)
-        torch.cuda.synchronize()
-        bits = int(info[0].item()) + NCH * 72
-        r_plain = float(rd.rate3[0].item()) * sc.n_hat
-        r_learn = float(f.R_learned[0].item()) * sc.n_hat
+        pairs, _ = ctx.query()
+        bits, kept, e_plain, e_learn = f.rate_errors()
+        for g in graphs:
+            g.close()
         kernels = {g: round(tot / cnt, 4) for g, (tot, cnt) in prof.items() if cnt}
+        E, Er = counts[0], counts[1]
         runs[name] = {"ms_per_step": round(dt * 1e3 / K, 4), "value": round(E / dt, 1),
-                      "evals": E, "pairs_last": pairs, "kept_last": int(info[1].item()),
-                      "coder_bits_last": bits,
-                      "plain_proxy_error": round(abs(r_plain - bits) / bits, 4),
-                      "learned_error": round(abs(r_learn - bits) / bits, 4),
+                      "eager_ms_per_step": round(dt_eager * 1e3 / K, 4),
+                      "evals": E, "evals_after_reach_test": Er, "pairs_last": pairs,
+                      "kept_last": kept, "coder_bits_last": bits,
+                      "plain_proxy_error": round(e_plain, 4),
+                      "learned_error": None if e_learn is None else round(e_learn, 4),
+                      "rate_check_before_run": {"plain_error": round(e_first[0], 4),
+                                                "learned_error": None if e_first[1] is None
+                                                else round(e_first[1], 4),
+                                                "learned_used": f.use_learned},
                       "kernel_ms": kernels}
-        del payload
+        say(f"c5 {name}: {runs[name]['ms_per_step']} ms/iter (graph), "
+            f"{runs[name]['eager_ms_per_step']} eager")
+        del f, start
+
+    # the RD step alone (forward + backward, no optimizer), graph-replayed
+    rd_only = {}
+    R = torch.zeros(1, dtype=torch.float32, device=dev)
+    for name in ("learned", "plain"):
+        c = ctx
+
+        def rd_step():
+            c.quant_render_fwd(p0, q0, s0, 1, None, 5, 0, rd.hard, rd.soft, rd.stats, rd.image,
+                               rd.final_T, rd.last, None)
+            if name == "learned":
+                c.rate_proxy(rd.stats, q0, 0.0, rd.rate3, None)
+                c.rate_mlp_fwd(packed, theta, p0, q0, rd.stats, rd.hard, R, None)
+            else:
+                c.rate_proxy(rd.stats, q0, lam, rd.rate3, rd.rate_grad)
+            c.l1_loss(rd.image, target, rd.loss, rd.dimage)
+            learned = name == "learned"
+            c.quant_render_bwd(p0, q0, rd.soft, 1, None if learned else rd.rate_grad,
+                               None if learned else rd.stats, rd.final_T, rd.last, rd.dimage,
+                               rd.grad_qparams, rd.grad_q, rd.grad_score, rd.grad_mask)
+            if learned:
+                c.rate_mlp_bwd(packed, theta, p0, q0, rd.stats, rd.hard, rd.soft, 1, lam,
+                               rd.grad_qparams, rd.grad_q, rd.grad_score, None)
+        ctx.graph_begin()
+        rd_step()
+        g = ctx.graph_end()
+        for _ in range(2):
+            g.launch(stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            g.launch(stream)
+        torch.cuda.synchronize()
+        rd_only[name] = round((time.perf_counter() - t0) * 1e3 / K, 4)
+        g.close()
+    ctx.query()
+
     L = runs["learned"]
     dom = max(L["kernel_ms"], key=L["kernel_ms"].get)
     roof = roofline(dom, L["kernel_ms"][dom], sc.n, sc.views, L["pairs_last"],
-                    L["evals"] // K, sc.width, sc.height)
+                    L["evals_after_reach_test"] // K, sc.width, sc.height,
+                    traffic_key=f"c5:{dom}")
+    blend = {g: roofline(g, L["kernel_ms"][g], sc.n, sc.views, L["pairs_last"],
+                         L["evals_after_reach_test"] // K, sc.width, sc.height)
+             for g in ("blend_fwd", "blend_bwd") if g in L["kernel_ms"]}
     line = {
-        "metric": "RD-step ms/iter & Gaussian-pixel evals/s (fwd+bwd), learned vs plain rate",
-        "value": L["value"], "unit": "Gaussian-pixel evals/s", "n_gpus": 1, "steps": K,
-        "warmup": W, "ms_per_step": L["ms_per_step"], "higher_is_better": True,
+        "metric": METRIC, "value": L["value"], "unit": "Gaussian-pixel evals/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": L["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"c5: full formation iteration, {sc.n} Gaussians (clustered), "
                                f"{sc.views} views {sc.width}x{sc.height}, Gumbel-sigmoid mask, "
                                f"learned rate in the loop (forward + recompute backward), "
                                f"Adam on parameters / steps / scores (higher SH every 16th, "
-                               f"sparse), lambda {lam}, {K} iterations, tile "
-                               f"{tile[0]}x{tile[1]}",
+                               f"sparse), lambda {lam}, tile {tile[0]}x{tile[1]} "
+                               f"({schedule} schedule, autotuned)",
                    "gaussians": sc.n, "views": sc.views, "width": sc.width,
                    "height": sc.height, "tile": f"{tile[0]}x{tile[1]}", "schedule": schedule,
                    "mlp_weights": "trained on the GPU on this scene's fixed-length coder "
                                   "bits (64 step vectors 2^U[-9,-3], 400 steps of 65,536 "
                                   "rows)"},
+        "timing": "K iterations replayed from HIP graphs (one per iteration of the 16-"
+                  "iteration higher-SH period, launched in turn), host clock around the "
+                  "replays between two synchronizations; evaluation counts and kernel times "
+                  "from re-runs of the same K iterations from the same state",
+        "roofline": roof,
+        "blend_roofline": blend,
+        "learned": L, "plain": runs["plain"],
+        "learned_over_plain_time": round(L["ms_per_step"] / runs["plain"]["ms_per_step"], 4),
+        "rd_step_graph_ms": rd_only,
+        "autotune_ms": tune["ms"],
         "mlp_training": {"seconds": round(train_s, 2), "loss": [round(v, 2) for v in losses],
                          "held_out_error_learned": round(err_l, 4),
                          "held_out_error_plain": round(err_p, 4)},
-        "roofline": roof,
-        "learned": L, "plain": runs["plain"],
-        "learned_over_plain_time": round(L["ms_per_step"] / runs["plain"]["ms_per_step"], 4),
+    }
+    del rd
+    return line
+
+
+# ---------------------------------------------------------------------------
+# c2 / c3: the plain RD step (forward + backward, no optimizer)
+# ---------------------------------------------------------------------------
+
+def bench_rd(args, sc, ctx, stream, dev, t, extras: bool, tile, schedule, tune=None):
+    import numpy as np
+    import torch
+
+    from paper_2607_12656_amd.rd import RDStep
+
+    lam = 2.5e-5
+    steps = args.steps
+    params, q, score = t(sc.params), t(sc.qstep), t(sc.score)
+    mask, target = t(sc.given_mask), t(sc.target)
+    rd = RDStep(ctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height, tile=tile,
+                schedule=schedule, fused=True)
+
+    def plain_step(count=False):
+        rd.forward(params, q, score, target, lam, 0, mask, 0, 0, count_evals=count)
+        rd.backward(params, q, 0)
+
+    counts = {}
+    for mode in (0, 1):
+        ctx.set_eval_count_mode(mode)
+        rd.evals.zero_()
+        plain_step(count=True)
+        torch.cuda.synchronize()
+        counts[mode] = int(rd.evals.item())
+    ctx.set_eval_count_mode(0)
+    E, Er = counts[0], counts[1]
+    P, _ = ctx.query()
+    ctx.reserve_pairs(P + P // 8 + 4096)      # no host synchronization inside a step
+    for _ in range(args.warmup):
+        plain_step()
+    ctx.query()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plain_step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ctx.profile_enable(True)
+    for _ in range(steps):
+        plain_step()
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    kernels = {g: round(tot / cnt, 4) for g, (tot, cnt) in prof.items() if cnt}
+    ctx.graph_begin()
+    plain_step()
+    graph = ctx.graph_end()
+    for _ in range(max(args.warmup, 2)):
+        graph.launch(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.launch(stream)
+    torch.cuda.synchronize()
+    gms = (time.perf_counter() - t0) * 1e3 / steps
+    ctx.query()
+    graph.close()
+    dom = max(kernels, key=kernels.get)
+    roof = roofline(dom, kernels[dom], sc.n, sc.views, P, Er, sc.width, sc.height,
+                    traffic_key=f"{args.workload if args.workload != 'c5' else 'c2'}:{dom}")
+    blend = {g: roofline(g, kernels[g], sc.n, sc.views, P, Er, sc.width, sc.height)
+             for g in ("blend_fwd", "blend_bwd") if g in kernels}
+    line = {
+        "metric": METRIC, "value": round(E / (gms * 1e-3), 1), "unit": "Gaussian-pixel evals/s",
+        "ms_per_step": round(gms, 4),
+        "config": {"workload": f"plain RD step, {sc.n} Gaussians (clustered), {sc.views} "
+                               f"view(s) {sc.width}x{sc.height}, 20% pruned, lambda 2.5e-5, "
+                               f"tile {tile[0]}x{tile[1]}",
+                   "gaussians": sc.n, "views": sc.views, "width": sc.width,
+                   "height": sc.height, "tile": f"{tile[0]}x{tile[1]}", "schedule": schedule,
+                   "pairs": P, "evals_per_step": E, "evals_after_reach_test": Er},
+        "roofline": roof, "blend_roofline": blend, "kernel_ms": kernels,
+        "timing": "HIP-graph replays of the whole step; eager_ms_per_step: the same calls "
+                  "enqueued by the host each step (no profiling); kernel_ms: HIP events on "
+                  "the library's stream in a separate run",
+        "eager_ms_per_step": round(ms, 4),
     }
     if tune is not None:
         line["autotune_ms"] = tune["ms"]
+    if extras:
+        line.update(extra_legs(args, sc, ctx, rd, stream, dev, params, q, score, mask, target,
+                               E, ms))
+    del rd
     return line
+
+
+def extra_legs(args, sc, ctx, rd, stream, dev, params, q, score, mask, target, E, plain_ms):
+    import torch
+    lam = 2.5e-5
+    out = {}
+    theta = torch.empty(24961, dtype=torch.float32, device=dev)
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    theta.copy_((torch.rand(24961, generator=gen) * 2 - 1) * 0.2)
+    packed = torch.empty(98304 // 4, dtype=torch.int32, device=dev)
+    ctx.rate_mlp_pack(theta, packed)
+    Rl = torch.empty(1, dtype=torch.float32, device=dev)
+
+    def learned_step():
+        c = ctx
+        c.quant_render_fwd(params, q, score, 0, mask, 0, 0, rd.hard, rd.soft, rd.stats,
+                           rd.image, rd.final_T, rd.last)
+        c.rate_proxy(rd.stats, q, 0.0, rd.rate3, None)
+        c.rate_mlp_fwd(packed, theta, params, q, rd.stats, rd.hard, Rl, None)
+        c.l1_loss(rd.image, target, rd.loss, rd.dimage)
+        c.quant_render_bwd(params, q, rd.soft, 0, None, None, rd.final_T, rd.last, rd.dimage,
+                           rd.grad_qparams, rd.grad_q, rd.grad_score, rd.grad_mask)
+        c.rate_mlp_bwd(packed, theta, params, q, rd.stats, rd.hard, rd.soft, 0, lam,
+                       rd.grad_qparams, rd.grad_q, rd.grad_score, None)
+
+    for _ in range(args.warmup):
+        learned_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        learned_step()
+    torch.cuda.synchronize()
+    lms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ctx.profile_enable(True)
+    for _ in range(args.steps):
+        learned_step()
+    lprof = ctx.profile_read()
+    ctx.profile_enable(False)
+    ctx.query()
+    lk = {g: round(tot / cnt, 4) for g, (tot, cnt) in lprof.items() if cnt}
+    mf = lk.get("mlp_fwd", 0.0)
+    out["learned_rate"] = {
+        "ms_per_step": round(lms, 4), "value": round(E / (lms * 1e-3), 1),
+        "mlp_fwd_ms": mf, "mlp_bwd_ms": lk.get("mlp_bwd", 0.0),
+        "mlp_fwd_tflops": round(sc.n * MLP_FLOP_PER_ROW / (mf * 1e-3) / 1e12, 2) if mf else None,
+        "plain_ms_per_step": round(plain_ms, 4), "timing": "eager, both"}
+
+    # MLP alone: one training step on 65,536 rows, inference over 3M rows
+    B = 65536
+    Xtr = torch.randint(0, 1 << 14, (B, 64), dtype=torch.int16, device=dev)
+    ttr = torch.rand(B, device=dev) * 100 + 200
+    m_, v_, g_ = torch.zeros_like(theta), torch.zeros_like(theta), torch.empty_like(theta)
+    lo = torch.empty(1, device=dev)
+    scratch = torch.empty(ctx.rate_mlp_train_scratch_bytes(B), dtype=torch.uint8, device=dev)
+    th2 = theta.clone()
+    for s in range(1, 4):
+        ctx.rate_mlp_train_step(th2, m_, v_, packed, Xtr, ttr, B, 1e-4, s, lo, g_, scratch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(4, 4 + args.steps):
+        ctx.rate_mlp_train_step(th2, m_, v_, packed, Xtr, ttr, B, 1e-4, s, lo, g_, scratch)
+    torch.cuda.synchronize()
+    tms = (time.perf_counter() - t0) * 1e3 / args.steps
+    Ni = 3_000_000
+    Xin = torch.randint(0, 1 << 14, (Ni, 64), dtype=torch.int16, device=dev)
+    fo = torch.empty(Ni, device=dev)
+    ctx.rate_mlp_pack(theta, packed)
+    ctx.rate_mlp_infer(packed, theta, Xin, Ni, fo)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.rate_mlp_infer(packed, theta, Xin, Ni, fo)
+    torch.cuda.synchronize()
+    ims = (time.perf_counter() - t0) * 1e3 / args.steps
+    out["mlp"] = {
+        "train_step_ms_65536_rows": round(tms, 4),
+        "train_tflops": round(3 * B * MLP_FLOP_PER_ROW / (tms * 1e-3) / 1e12, 2),
+        "infer_ms_3M_rows": round(ims, 4),
+        "infer_tflops": round(Ni * MLP_FLOP_PER_ROW / (ims * 1e-3) / 1e12, 2),
+        "infer_mfma_frac": round(Ni * MLP_FLOP_PER_ROW / (ims * 1e-3) / 1e12
+                                 / BF16_MFMA_PEAK_TFLOPS, 4)}
+    del Xin, fo, Xtr, scratch
+
+    # fixed-length coding of the kept Gaussians (the pruned step's mask)
+    rd.forward(params, q, score, target, lam, 0, mask, 0, 0, count_evals=False)
+    words = sc.n * NCH + 64
+    hdr = torch.empty((NCH, 3), dtype=torch.int32, device=dev)
+    payload = torch.empty(words, dtype=torch.int32, device=dev)
+    info = torch.empty(3, dtype=torch.int64, device=dev)
+    ctx.fl_encode(params, q, rd.hard, hdr, payload, words, info)
+    torch.cuda.synchronize()
+    bits, kept, flags = (int(v) for v in info.cpu())
+    pad = (kept + 63) // 64 * 64
+    outp = torch.empty((NCH, max(pad, 64)), dtype=torch.float32, device=dev)
+    pw = (bits + 31) // 32 + 1
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    for _ in range(3):
+        ctx.fl_encode(params, q, rd.hard, hdr, payload, words, info)
+        ctx.fl_decode(hdr, payload, pw, kept, max(pad, 64), outp)
+    ev[0].record(stream)
+    for _ in range(args.steps):
+        ctx.fl_encode(params, q, rd.hard, hdr, payload, words, info)
+    ev[1].record(stream)
+    for _ in range(args.steps):
+        ctx.fl_decode(hdr, payload, pw, kept, max(pad, 64), outp)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    ems = ev[0].elapsed_time(ev[1]) / args.steps
+    dms = ev[1].elapsed_time(ev[2]) / args.steps
+    enc_bytes = sc.n * NCH * 4 + sc.n + bits / 8
+    dec_bytes = bits / 8 + kept * NCH * 4
+    out["codec"] = {
+        "kept": kept, "payload_bits": bits, "header_bits": NCH * 72, "flags": flags,
+        "bits_per_kept_gaussian": round(bits / max(kept, 1), 2),
+        "encode_ms": round(ems, 4), "decode_ms": round(dms, 4),
+        "encode_gbs": round(enc_bytes / (ems * 1e-3) / 1e9, 1),
+        "decode_gbs": round(dec_bytes / (dms * 1e-3) / 1e9, 1),
+        "encode_hbm_frac": round(enc_bytes / (ems * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "decode_hbm_frac": round(dec_bytes / (dms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del payload, outp
+
+    lss = torch.empty(1, dtype=torch.float32, device=dev)
+    for _ in range(3):
+        ctx.ssim_loss(rd.image, target, 0.2, lss, rd.dimage)
+    ev[0].record(stream)
+    for _ in range(args.steps):
+        ctx.ssim_loss(rd.image, target, 0.2, lss, rd.dimage)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    sms = ev[0].elapsed_time(ev[1]) / args.steps
+    npx = sc.views * 3 * sc.width * sc.height
+    out["ssim"] = {"ms": round(sms, 4), "pixels": npx,
+                   "gpix_per_s": round(npx / (sms * 1e-3) / 1e9, 2)}
+
+    def time_rate(proxy):
+        for _ in range(3):
+            ctx.rate_variant(params, q, rd.stats, lam, rd.rate3, rd.rate_grad, proxy)
+            ctx.rate_variant_bwd(params, rd.grad_qparams)
+        ev[0].record(stream)
+        for _ in range(args.steps):
+            ctx.rate_variant(params, q, rd.stats, lam, rd.rate3, rd.rate_grad, proxy)
+            ctx.rate_variant_bwd(params, rd.grad_qparams)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / args.steps
+    out["rate_variants"] = {"range_ms": round(time_rate("range"), 4),
+                            "laplace_fwd_bwd_ms": round(time_rate("laplace"), 4)}
+    return out
+
+
+def say(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default 20; 1000 iterations for c5)")
+                    help="timed steps (default: 1000 iterations for c5, 20 otherwise)")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c5"),
-                    help="c2: 1M Gaussians, 1 view; c3: 3M Gaussians, 8 views; c5: the full "
-                         "formation iteration at 3M x 8 views (learned rate in the loop, "
-                         "Gumbel-sigmoid mask, Adam), learned vs plain rate")
-    ap.add_argument("--tile", default=None, help="16x16 | 8x8 | 32x8 | auto")
-    ap.add_argument("--schedule", default=None, choices=("tile", "stride", "queue", "block"),
-                    help="blend launch schedule when --tile names a shape (default: block "
-                         "on the 1M workload, the fastest there, else tile)")
+    ap.add_argument("--workload", default="c5", choices=("c5", "c2", "c3"),
+                    help="c5: the formation iteration at 3M Gaussians x 8 views of 1600x1060, "
+                         "learned vs plain rate (default); c2: the plain RD step at 1M, one "
+                         "1297x840 view; c3: the plain RD step at 3M x 8 views")
+    ap.add_argument("--tile", default=None, help="16x16 | 8x8 | 32x8 | auto (c2 / c3)")
+    ap.add_argument("--schedule", default=None, choices=("tile", "stride", "queue", "block"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip graph / learned / MLP / codec / SSIM / rate-variant legs")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 1M sub-record's MLP / codec / SSIM / rate-variant legs")
+    ap.add_argument("--no-c2", action="store_true", help="c5 only: skip the 1M sub-record")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (scale for HBM counters)")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
-                    help="rocprofv3 HBM bytes per launch (used only while the kernel source "
-                         "is unchanged since the counters were taken)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the step runs on one GPU; --gpus must be 1 (sharding "
@@ -240,18 +703,13 @@ def main():
 
     import synth
     from paper_2607_12656_amd import Context
-    from paper_2607_12656_amd.rd import RDStep
 
     if args.steps is None:
         args.steps = 1000 if args.workload == "c5" else 20
-    sc = synth.make_scene("c3" if args.workload == "c5" else args.workload)
-    lam = 2.5e-5
     dev = torch.device("cuda", 0)
     stream = torch.cuda.Stream(dev)
     torch.cuda.set_stream(stream)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    params, q, score = t(sc.params), t(sc.qstep), t(sc.score)
-    mask, target = t(sc.given_mask), t(sc.target)
     ctx = Context(0, stream=stream)
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
@@ -260,256 +718,42 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def plain_step(rd, count=False):
-        # the fused entry points (quant_render_fwd / quant_render_bwd): the
-        # quantized rows and their gradient never cross HBM
-        rd.fused = True
-        rd.forward(params, q, score, target, lam, 0, mask, 0, 0, count_evals=count)
-        rd.backward(params, q, 0)
-
-    tile_choice = args.tile or ("16x16" if args.workload == "c2" else "auto")
-    tune = None
-    if tile_choice == "auto":
-        from paper_2607_12656_amd import autotune
-        tune = autotune.tune(ctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height,
-                             plain_step, reps=2)
-        tile, schedule = tune["tile"], tune["schedule"]
-    else:
-        tile = tuple(int(v) for v in tile_choice.split("x"))
-        schedule = args.schedule or ("block" if args.workload == "c2" else "tile")
-    rd = RDStep(ctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height, tile=tile,
-                schedule=schedule)
     if args.workload == "c5":
-        print(json.dumps(bench_formation(args, sc, ctx, rd, stream, dev, t, tile, schedule,
-                                         tune)), flush=True)
-        return
-
-    # evaluation count and pair count of one step (deterministic)
-    rd.evals.zero_()
-    plain_step(rd, count=True)
-    torch.cuda.synchronize()
-    E = int(rd.evals.item())
-    P, _ = ctx.query()
-    ctx.reserve_pairs(P + P // 8 + 4096)      # no host synchronization inside a step
-    for _ in range(args.warmup):
-        plain_step(rd)
-    ctx.query()
-    torch.cuda.synchronize()
-    ctx.profile_enable(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plain_step(rd)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = ctx.profile_read()
-    ctx.profile_enable(False)
-    ctx.query()                                # raises if the capacity overflowed
-    ms = (t1 - t0) * 1e3 / args.steps          # eager: the host enqueues every call
-    kernels = {g: round(tot / cnt, 4) for g, (tot, cnt) in prof.items() if cnt}
-    # the timed steps: the whole step captured once in a HIP graph and
-    # replayed K times between synchronizations (no host work inside)
-    ctx.graph_begin()
-    plain_step(rd)
-    graph = ctx.graph_end()
-    for _ in range(max(args.warmup, 2)):
-        graph.launch(stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        graph.launch(stream)
-    torch.cuda.synchronize()
-    gms = (time.perf_counter() - t0) * 1e3 / args.steps
-    ctx.query()
-    graph.close()
-    value = E / (gms * 1e-3)
-    dom = max(kernels, key=kernels.get)
-    roof = roofline(dom, kernels[dom], sc.n, sc.views, P, E, sc.width, sc.height)
-    if args.traffic and os.path.exists(args.traffic):
-        import hashlib
-        tr = json.load(open(args.traffic))
-        ent = tr.get(f"{args.workload}:{dom}")
-        if ent:
-            # the counters hold while the kernel's sources are unchanged
-            h = hashlib.sha256()
-            for f in ent.get("kernel_files", [ent.get("kernel_file")]):
-                h.update(open(os.path.join(ROOT, f), "rb").read())
-            cur = h.hexdigest()[:16]
-            if cur == ent["kernel_sha256_16"]:
-                roof["traffic"] = ent["bytes_per_launch"]
-                roof["traffic_source"] = ent["source"] + " (profiles/hbm_traffic_*.md)"
-
-    line = {
-        "metric": "RD-step ms/iter & Gaussian-pixel evals/s (fwd+bwd), learned vs plain rate",
-        "value": round(value, 1), "unit": "Gaussian-pixel evals/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(gms, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload}: plain RD step, {sc.n} Gaussians (clustered), "
-                               f"{sc.views} view(s) {sc.width}x{sc.height}, 20% pruned, "
-                               f"lambda 2.5e-5, tile {tile[0]}x{tile[1]}",
-                   "gaussians": sc.n, "views": sc.views, "width": sc.width,
-                   "height": sc.height, "tile": f"{tile[0]}x{tile[1]}", "schedule": schedule, "pairs": P,
-                   "evals_per_step": E},
-        "roofline": roof,
-        "kernel_ms": kernels,
-        "timing": "HIP-graph replays of the whole step; eager_ms_per_step: the same calls "
-                  "enqueued by the host each step (kernel_ms, roofline: HIP events in that run)",
-        "eager_ms_per_step": round(ms, 4),
-        "eager_value": round(E / (ms * 1e-3), 1),
-    }
-    if tune is not None:
-        line["autotune_ms"] = tune["ms"]
-
-    if not args.no_extras:
-        # learned rate in the loop: MLP forward + recompute backward replace
-        # the range proxy's gradient; the proxy is still evaluated (forward)
-        theta = torch.empty(24961, dtype=torch.float32, device=dev)
-        gen = torch.Generator(device="cpu").manual_seed(7)
-        theta.copy_((torch.rand(24961, generator=gen) * 2 - 1) * 0.2)
-        packed = torch.empty(98304 // 4, dtype=torch.int32, device=dev)
-        ctx.rate_mlp_pack(theta, packed)
-        Rl = torch.empty(1, dtype=torch.float32, device=dev)
-
-        def learned_step():
-            c = ctx
-            c.quant_render_fwd(params, q, score, 0, mask, 0, 0, rd.hard, rd.soft, rd.stats,
-                               rd.image, rd.final_T, rd.last)
-            c.rate_proxy(rd.stats, q, 0.0, rd.rate3, None)
-            c.rate_mlp_fwd(packed, theta, params, q, rd.stats, rd.hard, Rl, None)
-            c.l1_loss(rd.image, target, rd.loss, rd.dimage)
-            c.quant_render_bwd(params, q, rd.soft, 0, None, None, rd.final_T, rd.last, rd.dimage,
-                               rd.grad_qparams, rd.grad_q, rd.grad_score, rd.grad_mask)
-            c.rate_mlp_bwd(packed, theta, params, q, rd.stats, rd.hard, rd.soft, 0, lam,
-                           rd.grad_qparams, rd.grad_q, rd.grad_score, None)
-
-        for _ in range(args.warmup):
-            learned_step()
+        sc = synth.make_scene("c3")
+        line = bench_formation(args, sc, ctx, stream, dev, t)
         torch.cuda.synchronize()
-        ctx.profile_enable(True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            learned_step()
-        torch.cuda.synchronize()
-        lms = (time.perf_counter() - t0) * 1e3 / args.steps
-        lprof = ctx.profile_read()
-        ctx.profile_enable(False)
-        ctx.query()
-        lk = {g: round(tot / cnt, 4) for g, (tot, cnt) in lprof.items() if cnt}
-        mf = lk.get("mlp_fwd", 0.0)
-        line["learned_rate"] = {
-            "ms_per_step": round(lms, 4), "value": round(E / (lms * 1e-3), 1),
-            "mlp_fwd_ms": mf, "mlp_bwd_ms": lk.get("mlp_bwd", 0.0),
-            "mlp_fwd_tflops": round(sc.n * MLP_FLOP_PER_ROW / (mf * 1e-3) / 1e12, 2) if mf else None,
-            "plain_ms_per_step": round(ms, 4), "timing": "eager, both"}
-
-        # MLP alone: one training step on 65,536 rows, inference over 3M rows
-        B = 65536
-        Xtr = torch.randint(0, 1 << 14, (B, 64), dtype=torch.int16, device=dev)
-        ttr = torch.rand(B, device=dev) * 100 + 200
-        m_ = torch.zeros_like(theta)
-        v_ = torch.zeros_like(theta)
-        g_ = torch.empty_like(theta)
-        lo = torch.empty(1, device=dev)
-        scratch = torch.empty(ctx.rate_mlp_train_scratch_bytes(B), dtype=torch.uint8, device=dev)
-        th2 = theta.clone()
-        for s in range(1, 4):
-            ctx.rate_mlp_train_step(th2, m_, v_, packed, Xtr, ttr, B, 1e-4, s, lo, g_, scratch)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for s in range(4, 4 + args.steps):
-            ctx.rate_mlp_train_step(th2, m_, v_, packed, Xtr, ttr, B, 1e-4, s, lo, g_, scratch)
-        torch.cuda.synchronize()
-        tms = (time.perf_counter() - t0) * 1e3 / args.steps
-        Ni = 3_000_000
-        Xin = torch.randint(0, 1 << 14, (Ni, 64), dtype=torch.int16, device=dev)
-        fo = torch.empty(Ni, device=dev)
-        ctx.rate_mlp_pack(theta, packed)
-        ctx.rate_mlp_infer(packed, theta, Xin, Ni, fo)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            ctx.rate_mlp_infer(packed, theta, Xin, Ni, fo)
-        torch.cuda.synchronize()
-        ims = (time.perf_counter() - t0) * 1e3 / args.steps
-        line["mlp"] = {
-            "train_step_ms_65536_rows": round(tms, 4),
-            "train_tflops": round(3 * B * MLP_FLOP_PER_ROW / (tms * 1e-3) / 1e12, 2),
-            "infer_ms_3M_rows": round(ims, 4),
-            "infer_tflops": round(Ni * MLP_FLOP_PER_ROW / (ims * 1e-3) / 1e12, 2),
-            "infer_mfma_frac": round(Ni * MLP_FLOP_PER_ROW / (ims * 1e-3) / 1e12
-                                     / BF16_MFMA_PEAK_TFLOPS, 4)}
-        del Xin, fo, Xtr, scratch
-
-        # fixed-length coding of the kept Gaussians (the pruned step's mask)
-        rd.forward(params, q, score, target, lam, 0, mask, 0, 0)
-        words = sc.n * NCH + 64                 # 32 bits per code at most
-        hdr = torch.empty((NCH, 3), dtype=torch.int32, device=dev)
-        payload = torch.empty(words, dtype=torch.int32, device=dev)
-        info = torch.empty(3, dtype=torch.int64, device=dev)
-        ctx.fl_encode(params, q, rd.hard, hdr, payload, words, info)
-        torch.cuda.synchronize()
-        bits, kept, flags = (int(v) for v in info.cpu())
-        pad = (kept + 63) // 64 * 64
-        out = torch.empty((NCH, max(pad, 64)), dtype=torch.float32, device=dev)
-        pw = (bits + 31) // 32 + 1
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        for _ in range(3):
-            ctx.fl_encode(params, q, rd.hard, hdr, payload, words, info)
-            ctx.fl_decode(hdr, payload, pw, kept, max(pad, 64), out)
-        ev[0].record(stream)
-        for _ in range(args.steps):
-            ctx.fl_encode(params, q, rd.hard, hdr, payload, words, info)
-        ev[1].record(stream)
-        for _ in range(args.steps):
-            ctx.fl_decode(hdr, payload, pw, kept, max(pad, 64), out)
-        ev[2].record(stream)
-        torch.cuda.synchronize()
-        ems = ev[0].elapsed_time(ev[1]) / args.steps
-        dms = ev[1].elapsed_time(ev[2]) / args.steps
-        enc_bytes = sc.n * NCH * 4 + sc.n + bits / 8          # params + mask in, payload out
-        dec_bytes = bits / 8 + kept * NCH * 4                   # payload in, parameters out
-        line["codec"] = {
-            "kept": kept, "payload_bits": bits, "header_bits": NCH * 72, "flags": flags,
-            "bits_per_kept_gaussian": round(bits / max(kept, 1), 2),
-            "encode_ms": round(ems, 4), "decode_ms": round(dms, 4),
-            "encode_gbs": round(enc_bytes / (ems * 1e-3) / 1e9, 1),
-            "decode_gbs": round(dec_bytes / (dms * 1e-3) / 1e9, 1),
-            "encode_hbm_frac": round(enc_bytes / (ems * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "decode_hbm_frac": round(dec_bytes / (dms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        del payload, out
-
-        # SSIM term of the distortion (forward + gradient) on the step's image
-        lss = torch.empty(1, dtype=torch.float32, device=dev)
-        for _ in range(3):
-            ctx.ssim_loss(rd.image, target, 0.2, lss, rd.dimage)
-        ev[0].record(stream)
-        for _ in range(args.steps):
-            ctx.ssim_loss(rd.image, target, 0.2, lss, rd.dimage)
-        ev[1].record(stream)
-        torch.cuda.synchronize()
-        sms = ev[0].elapsed_time(ev[1]) / args.steps
-        npx = sc.views * 3 * sc.width * sc.height
-        line["ssim"] = {"ms": round(sms, 4), "pixels": npx,
-                        "gpix_per_s": round(npx / (sms * 1e-3) / 1e9, 2)}
-
-        # rate-proxy variants: the range proxy from the quantizer's statistics
-        # against the scale-based Laplace proxy (two passes + dense backward)
-        def time_rate(proxy):
-            for _ in range(3):
-                ctx.rate_variant(params, q, rd.stats, lam, rd.rate3, rd.rate_grad, proxy)
-                ctx.rate_variant_bwd(params, rd.grad_qparams)
-            ev[0].record(stream)
-            for _ in range(args.steps):
-                ctx.rate_variant(params, q, rd.stats, lam, rd.rate3, rd.rate_grad, proxy)
-                ctx.rate_variant_bwd(params, rd.grad_qparams)
-            ev[1].record(stream)
-            torch.cuda.synchronize()
-            return ev[0].elapsed_time(ev[1]) / args.steps
-        line["rate_variants"] = {"range_ms": round(time_rate("range"), 4),
-                                 "laplace_fwd_bwd_ms": round(time_rate("laplace"), 4)}
-
-    if not args.no_cpu_baseline and args.workload == "c2":
-        line["cpu_baseline"] = cpu_baseline(sc, lam)
+        if not args.no_c2:
+            sc2 = synth.make_scene("c2")
+            sub = argparse.Namespace(**vars(args))
+            sub.steps = min(args.steps, 20)
+            line["c2"] = bench_rd(sub, sc2, ctx, stream, dev, t, not args.no_extras, (16, 16),
+                                  "block")
+            say("c2 sub-record done")
+            del sc2
+        if not args.no_cpu_baseline:
+            line["cpu_baseline"] = cpu_baseline_c5(sc)
+            say("cpu baseline done")
+    else:
+        sc = synth.make_scene(args.workload)
+        tune = None
+        choice = args.tile or ("16x16" if args.workload == "c2" else "auto")
+        if choice == "auto":
+            from paper_2607_12656_amd import autotune
+            ctx.set_scene(sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height)
+            tune = autotune.tune_native(ctx, t(sc.params), t(sc.qstep), t(sc.given_mask),
+                                        t(sc.target), sc.n, sc.views, sc.width, sc.height,
+                                        reps=2)
+            tile, schedule = tune["tile"], tune["schedule"]
+        else:
+            tile = tuple(int(v) for v in choice.split("x"))
+            schedule = args.schedule or ("block" if args.workload == "c2" else "tile")
+        line = bench_rd(args, sc, ctx, stream, dev, t, not args.no_extras, tile, schedule, tune)
+        line.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                     "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                     "dtype": "f32", "data": "synthetic"})
+        line["config"]["workload"] = f"{args.workload}: " + line["config"]["workload"]
+        if not args.no_cpu_baseline and args.workload == "c2":
+            line["cpu_baseline"] = cpu_baseline_c2(sc, 2.5e-5)
     print(json.dumps(line), flush=True)
 
 

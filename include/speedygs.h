@@ -195,6 +195,36 @@ sgs_status sgs_quant_render_bwd(sgs_ctx *ctx, const float *params, const float *
                                 const float *dL_dimage, float *grad_params,
                                 float *grad_qstep, float *grad_score, float *grad_hard_mask);
 
+/* Autotuner of the batched step (tile shape, then blend schedule): times
+ * `reps` (1..1000) whole RD steps (sgs_quant_render_fwd on the given mask,
+ * sgs_rate_proxy, sgs_l1_loss, sgs_quant_render_bwd) per candidate with HIP
+ * events on the context's stream, after one untimed step each: the tile
+ * shapes 16x16, 8x8 and 32x8 with schedule 0, then schedules 1, 2 and 3 with
+ * the fastest shape.  *chosen (host) receives the fastest options (tau kept)
+ * and the context is left bound to the same scene with them; a reserved pair
+ * capacity is released (call sgs_reserve_pairs again).  ms_out (host
+ * float[6], may be NULL) receives each candidate's mean step time in the
+ * order timed.  The images and gradients do not depend on the choice (the
+ * support rule is pixel-exact, Sec. 3.1 binning).  Needs params rows 16-byte
+ * aligned, target [V][3][H][W]; allocates temporary device buffers for the
+ * step's outputs and synchronizes.  On failure the scene stays bound with the
+ * last options tried or the best found. */
+sgs_status sgs_autotune(sgs_ctx *ctx, const float *params, const float *qstep,
+                        const uint8_t *given_mask, const float *target, int32_t reps,
+                        sgs_options *chosen, float *ms_out);
+
+/* What the eval_count of sgs_render_fwd / sgs_quant_render_fwd counts:
+ *   mode 0 (default): the method's evaluations, every (Gaussian, pixel) pair
+ *     whose pixel lies in the splat's span, visited before the pixel stops
+ *     (Sec. 3.1 compositing; the count the FP64 oracle reproduces);
+ *   mode 1: the evaluations the uncounted (timed) blend performs: those of
+ *     mode 0 whose splat can reach the alpha cut-off 1/255 somewhere in the
+ *     pixel's 8x8 sub-tile (the blend's per-sub-tile reach test drops the
+ *     others without evaluating them).
+ * Images, T and stop positions are the same bit for bit in both modes and
+ * without counting.  Takes effect at the next render. */
+sgs_status sgs_set_eval_count_mode(sgs_ctx *ctx, int32_t mode);
+
 /* Host-side query (synchronizes the stream): pairs of the last render and the
  * device flags word of `stats` (may be NULL).  Returns SGS_EINVAL when the
  * flags report an invalid step size, SGS_ECAPACITY (once, then cleared) when

@@ -35,29 +35,50 @@ TW_DEFAULT = 16
 TH_DEFAULT = 16
 
 
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
+
+
 def build() -> str:
-    """Compile liboracle.so with gcc (FP64, no floating-point contraction)."""
+    """Compile liboracle.so with gcc (FP64, no floating-point contraction),
+    and the same sources with OpenMP as liboracle_omp.so (only the sampled
+    tile step runs its tiles in parallel; results do not depend on the
+    thread count)."""
     srcs = [s for s in SRC if os.path.exists(s)]
-    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fno-fast-math",
-           "-fPIC", "-shared", "-o", LIB + ".tmp", *srcs, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    base = ["gcc", "-O2", "-std=c11", "-Wall", "-Wno-unknown-pragmas", "-ffp-contract=off",
+            "-fno-fast-math", "-fPIC", "-shared"]
+    for out, extra in ((LIB, []), (LIB_OMP, ["-fopenmp"])):
+        subprocess.run([*base, *extra, "-o", out + ".tmp", *srcs, "-lm"], check=True)
+        os.replace(out + ".tmp", out)
     return LIB
 
 
 _lib = None
+_lib_omp = None
+
+
+def _stale(path):
+    return (not os.path.exists(path)) or any(
+        os.path.exists(s) and os.path.getmtime(s) > os.path.getmtime(path) for s in SRC)
 
 
 def lib():
     global _lib
     if _lib is None:
-        stale = (not os.path.exists(LIB)) or any(
-            os.path.exists(s) and os.path.getmtime(s) > os.path.getmtime(LIB) for s in SRC)
-        if stale:
+        if _stale(LIB) or _stale(LIB_OMP):
             build()
         _lib = C.CDLL(LIB)
         _declare(_lib)
     return _lib
+
+
+def lib_omp():
+    """The OpenMP build (same functions; used for the parallel CPU baseline)."""
+    global _lib_omp
+    if _lib_omp is None:
+        lib()
+        _lib_omp = C.CDLL(LIB_OMP)
+        _declare(_lib_omp)
+    return _lib_omp
 
 
 P = C.c_void_p
@@ -89,6 +110,8 @@ def _declare(L):
         "orc_pixels_brute": (I64, [I64, I64, P, P, I32, P, I32, I32, P, P, P, I64, P, P, P]),
         "orc_splat_grads_sampled": (I64, [I64, I64, P, P, I32, P, I32, I32, P, P, P, I64, P,
                                           P, P, P, P]),
+        "orc_step_tiles_sampled": (I64, [I64, I64, P, P, I32, P, I32, I32, I32, I32, P, P, P,
+                                         I64, P, P, P, P]),
         "orc_l1": (F64, [I64, P, P, P]),
         "orc_sh_basis": (None, [I64, P, P]),
         "orc_fixed_length_bits": (I64, [I64, I64, P, P, P, P, P]),
@@ -359,6 +382,32 @@ def splat_grads_sampled(p64, mask64, n, cams, W, H, st: Structure, sel, dimage=N
                                   _p(st.valid), _p(st.tz), _p(st.span), sel.size, _p(sel),
                                   _p(dimage), _p(gs), _p(gp), _p(margin))
     return gs, gp, margin
+
+
+def step_tiles_sampled(p64, mask64, n, cams, W, H, st: Structure, tiles, dimage,
+                       parallel: bool = False):
+    """Render forward and backward over the chosen global tile ids only (the
+    rest of the image has zero dL/dC): (evals, image [k][3][TH][TW],
+    gparams [59][npad]).  parallel: the OpenMP build."""
+    p64 = np.ascontiguousarray(p64, np.float64)
+    mask64 = np.ascontiguousarray(mask64, np.float64)
+    cams = np.ascontiguousarray(cams, np.float32)
+    tiles = np.ascontiguousarray(tiles, np.int64)
+    V = cams.shape[0]
+    GW, GH = (W + st.TW - 1) // st.TW, (H + st.TH - 1) // st.TH
+    if tiles.size and not ((tiles >= 0).all() and (tiles < V * GW * GH).all()):
+        raise ValueError("tile id outside the views")
+    if np.unique(tiles).size != tiles.size:
+        raise ValueError("repeated tile id")
+    dimage = np.ascontiguousarray(dimage, np.float64)
+    assert dimage.shape == (V, 3, H, W)
+    img = np.zeros((tiles.size, 3, st.TH, st.TW))
+    gp = np.zeros(p64.shape)
+    L = lib_omp() if parallel else lib()
+    E = L.orc_step_tiles_sampled(n, p64.shape[1], _p(p64), _p(mask64), V, _p(cams), W, H,
+                                 st.TW, st.TH, _p(st.valid), _p(st.tz), _p(st.span), tiles.size,
+                                 _p(tiles), _p(dimage), _p(img), _p(gp))
+    return int(E), img, gp
 
 
 def sh_basis(dirs: np.ndarray) -> np.ndarray:

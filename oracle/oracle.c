@@ -1283,3 +1283,190 @@ void orc_fixed_length_unpack(int64_t n, int64_t npad, const uint8_t *buf,
       k[j * npad + i] = (int32_t)((int64_t)v + kmin[j]);
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* One RD step's render part (forward and backward) over a sample of tiles   */
+/* [Sec. 3.1 compositing and its reverse pass]: the pixels of the chosen     */
+/* tiles are composited and differentiated exactly as orc_forward /          */
+/* orc_backward do, with the rest of the image left out (its dL/dC taken as  */
+/* zero).  Each chosen tile's list (every valid splat of the view whose      */
+/* span's tile rectangle holds the tile, in (depth bits, index) order) is    */
+/* built by one pass over the splats; the splats of those lists are          */
+/* projected once; gparams [59][npad] (overwritten) receives the projection  */
+/* backward of their summed gradients; image [ntiles][3][TH][TW] the        */
+/* chosen tiles' colours (pixels outside the image 0).  Tiles are            */
+/* independent: built with OpenMP the tiles run in parallel and their        */
+/* gradients are merged in tile order, so the result does not depend on the  */
+/* thread count.  Returns the in-support evaluations of the forward.         */
+/* ------------------------------------------------------------------------ */
+static int u64_cmp(const void *a, const void *b) {
+  uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+  return x < y ? -1 : (x > y);
+}
+
+int64_t orc_step_tiles_sampled(int64_t n, int64_t npad, const double *p, const double *mask,
+                               int32_t V, const float *cams, int32_t W, int32_t H, int32_t TW,
+                               int32_t TH, const int32_t *valid, const float *tz,
+                               const int32_t *span, int64_t ntiles, const int64_t *tiles,
+                               const double *dimage, double *image, double *gparams) {
+  const int GW = (W + TW - 1) / TW, GH = (H + TH - 1) / TH;
+  const int64_t tpv = (int64_t)GW * GH;
+  if (!sh_ready) sh_build(); /* the SH tables, before any thread reads them */
+  /* which chosen tile (index + 1) each global tile is, 0 = not chosen */
+  int64_t *slot_of_tile = (int64_t *)calloc((size_t)(V * tpv), sizeof(int64_t));
+  for (int64_t k = 0; k < ntiles; ++k) slot_of_tile[tiles[k]] = k + 1;
+  /* lists: count, then fill (key = depth bits << 32 | index) */
+  int64_t *cnt = (int64_t *)calloc((size_t)(ntiles + 1), sizeof(int64_t));
+  for (int v = 0; v < V; ++v)
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t s = (int64_t)v * n + i;
+      if (!valid[s]) continue;
+      const int32_t *sp = span + 4 * s;
+      for (int ty = sp[2] / TH; ty <= sp[3] / TH; ++ty)
+        for (int tx = sp[0] / TW; tx <= sp[1] / TW; ++tx) {
+          const int64_t k = slot_of_tile[(int64_t)v * tpv + (int64_t)ty * GW + tx];
+          if (k) cnt[k - 1] += 1;
+        }
+    }
+  int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ntiles + 1));
+  start[0] = 0;
+  for (int64_t k = 0; k < ntiles; ++k) start[k + 1] = start[k] + cnt[k];
+  const int64_t total = start[ntiles];
+  uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(total > 0 ? total : 1));
+  for (int64_t k = 0; k < ntiles; ++k) cnt[k] = 0;
+  for (int v = 0; v < V; ++v)
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t s = (int64_t)v * n + i;
+      if (!valid[s]) continue;
+      const int32_t *sp = span + 4 * s;
+      uint32_t zb;
+      memcpy(&zb, &tz[s], 4);
+      for (int ty = sp[2] / TH; ty <= sp[3] / TH; ++ty)
+        for (int tx = sp[0] / TW; tx <= sp[1] / TW; ++tx) {
+          const int64_t k = slot_of_tile[(int64_t)v * tpv + (int64_t)ty * GW + tx];
+          if (k) keys[start[k - 1] + cnt[k - 1]++] = ((uint64_t)zb << 32) | (uint64_t)i;
+        }
+    }
+  for (int64_t k = 0; k < ntiles; ++k)
+    qsort(keys + start[k], (size_t)cnt[k], sizeof(uint64_t), u64_cmp);
+  /* compact projection table of the listed splats: slot per (view, splat) */
+  int32_t *pslot = (int32_t *)malloc(sizeof(int32_t) * (size_t)(V * n));
+  for (int64_t s = 0; s < (int64_t)V * n; ++s) pslot[s] = -1;
+  int64_t nused = 0;
+  for (int64_t k = 0; k < ntiles; ++k) {
+    const int v = (int)(tiles[k] / tpv);
+    for (int64_t e = start[k]; e < start[k + 1]; ++e) {
+      const int64_t s = (int64_t)v * n + (int64_t)(keys[e] & 0xFFFFFFFFu);
+      if (pslot[s] < 0) pslot[s] = (int32_t)nused++;
+    }
+  }
+  int64_t *used = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nused > 0 ? nused : 1));
+  for (int64_t s = 0; s < (int64_t)V * n; ++s)
+    if (pslot[s] >= 0) used[pslot[s]] = s;
+  /* per-view tables indexed by Gaussian, as blend_pixel expects: the used
+     splats' projections are placed at their Gaussian index of a view copy */
+  pj64 *pjc = (pj64 *)calloc((size_t)(nused > 0 ? nused : 1), sizeof(pj64));
+#pragma omp parallel for schedule(static)
+  for (int64_t u = 0; u < nused; ++u) {
+    const int64_t s = used[u];
+    const int v = (int)(s / n);
+    pj64_tmp m;
+    proj64(p, npad, s - (int64_t)v * n, (const orc_cam *)(cams + 19 * v), W, H, &pjc[u], &m);
+  }
+  /* per-tile gradient sums of its list entries [start[k] + j][NSPLATGRAD] */
+  double *tg = (double *)calloc((size_t)(total > 0 ? total : 1) * NSPLATGRAD, sizeof(double));
+  int64_t evals = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : evals)
+  for (int64_t k = 0; k < ntiles; ++k) {
+    const int v = (int)(tiles[k] / tpv);
+    const int64_t t = tiles[k] - (int64_t)v * tpv;
+    const int tx = (int)(t % GW), ty = (int)(t / GW);
+    const int64_t len = start[k + 1] - start[k];
+    /* the tile's own view table: list position j holds Gaussian j */
+    pj64 *pj = (pj64 *)malloc(sizeof(pj64) * (size_t)(len > 0 ? len : 1));
+    int32_t *sp4 = (int32_t *)malloc(sizeof(int32_t) * 4 * (size_t)(len > 0 ? len : 1));
+    double *mk = (double *)malloc(sizeof(double) * (size_t)(len > 0 ? len : 1));
+    uint32_t *list = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(len > 0 ? len : 1));
+    blend_rec *recs = (blend_rec *)malloc(sizeof(blend_rec) * (size_t)(len > 0 ? len : 1));
+    double *gl = (double *)calloc((size_t)(len > 0 ? len : 1) * NSPLATGRAD, sizeof(double));
+    for (int64_t j = 0; j < len; ++j) {
+      const int64_t i = (int64_t)(keys[start[k] + j] & 0xFFFFFFFFu);
+      const int64_t s = (int64_t)v * n + i;
+      pj[j] = pjc[pslot[s]];
+      memcpy(sp4 + 4 * j, span + 4 * s, 4 * sizeof(int32_t));
+      mk[j] = mask[i];
+      list[j] = (uint32_t)j;
+    }
+    blend_ctx bc = {pj, sp4, mk, len};
+    for (int py = ty * TH; py < (ty + 1) * TH; ++py)
+      for (int px = tx * TW; px < (tx + 1) * TW; ++px) {
+        double *out = image ? image + k * 3 * TW * TH + (int64_t)(py - ty * TH) * TW + (px - tx * TW)
+                            : NULL;
+        if (px >= W || py >= H) {
+          if (out) out[0] = out[TW * TH] = out[2 * TW * TH] = 0.0;
+          continue;
+        }
+        double col[3], T;
+        int64_t ev = 0, nr = 0;
+        int mg = 0;
+        blend_pixel(&bc, 0, px, py, list, len, col, &T, &ev, &mg, recs, &nr);
+        evals += ev;
+        if (out) {
+          out[0] = col[0];
+          out[TW * TH] = col[1];
+          out[2 * TW * TH] = col[2];
+        }
+        const int64_t pix = (int64_t)py * W + px;
+        double gC[3];
+        for (int ch = 0; ch < 3; ++ch) gC[ch] = dimage[((int64_t)v * 3 + ch) * H * W + pix];
+        pixel_backward(&bc, 0, px, py, list, recs, nr, gC, -1, gl);
+      }
+    memcpy(tg + start[k] * NSPLATGRAD, gl, sizeof(double) * (size_t)len * NSPLATGRAD);
+    free(gl);
+    free(recs);
+    free(list);
+    free(mk);
+    free(sp4);
+    free(pj);
+  }
+  /* merge in tile order into per-(view, splat) sums, then project back */
+  double *gs = (double *)calloc((size_t)(nused > 0 ? nused : 1) * NSPLATGRAD, sizeof(double));
+  for (int64_t k = 0; k < ntiles; ++k) {
+    const int v = (int)(tiles[k] / tpv);
+    for (int64_t e = start[k]; e < start[k + 1]; ++e) {
+      const int64_t s = (int64_t)v * n + (int64_t)(keys[e] & 0xFFFFFFFFu);
+      for (int c = 0; c < NSPLATGRAD; ++c) gs[pslot[s] * NSPLATGRAD + c] += tg[e * NSPLATGRAD + c];
+    }
+  }
+  double *gpu = (double *)calloc((size_t)(nused > 0 ? nused : 1) * NCH, sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int64_t u = 0; u < nused; ++u) {
+    const int64_t s = used[u];
+    const int v = (int)(s / n);
+    const int64_t i = s - (int64_t)v * n;
+    double p1[NCH];
+    for (int c = 0; c < NCH; ++c) p1[c] = p[(int64_t)c * npad + i];
+    pj64 o;
+    pj64_tmp m;
+    const orc_cam *cam = (const orc_cam *)(cams + 19 * v);
+    proj64(p1, 1, 0, cam, W, H, &o, &m);
+    proj64_bwd(p1, 1, 0, cam, &o, &m, gs + u * NSPLATGRAD, gpu + u * NCH);
+  }
+  memset(gparams, 0, sizeof(double) * (size_t)(NCH * npad));
+  for (int64_t u = 0; u < nused; ++u) {  /* (view, splat) order: fixed */
+    const int64_t s = used[u];
+    const int64_t i = s % n;
+    for (int c = 0; c < NCH; ++c) gparams[(int64_t)c * npad + i] += gpu[u * NCH + c];
+  }
+  free(gpu);
+  free(gs);
+  free(tg);
+  free(pjc);
+  free(used);
+  free(pslot);
+  free(keys);
+  free(start);
+  free(cnt);
+  free(slot_of_tile);
+  return evals;
+}

@@ -77,6 +77,8 @@ _SIGS = {
     "sgs_quant_render_fwd": [P, P, P, P, I32, P, U64, U64, P, P, P, P, P, P, P],
     "sgs_quant_render_bwd": [P, P, P, P, I32, P, P, P, P, P, P, P, P, P],
     "sgs_query": [P, P, C.POINTER(I64), C.POINTER(U64)],
+    "sgs_set_eval_count_mode": [P, I32],
+    "sgs_autotune": [P, P, P, P, P, I32, P, P],
     "sgs_copy_structure": [P, P, P, I64, P, P, P, P],
     "sgs_copy_splat_grads": [P, P],
     "sgs_profile_enable": [P, I32],
@@ -267,6 +269,23 @@ class Context:
             self.h, _ptr(params), _ptr(qstep), _ptr(soft_mask), mask_mode, _ptr(rate_grad),
             _ptr(stats), _ptr(final_T), _ptr(last), _ptr(dL_dimage), _ptr(grad_params),
             _ptr(grad_qstep), _ptr(grad_score), _ptr(grad_hard_mask)), self.h)
+
+    def autotune(self, params, qstep, given_mask, target, reps: int = 3):
+        """sgs_autotune: returns ((tile_w, tile_h), schedule name, [ms per
+        candidate in the order timed]); the context stays bound with the choice."""
+        opt = sgs_options()
+        ms = (C.c_float * 6)()
+        self._check(self.L.sgs_autotune(self.h, _ptr(params), _ptr(qstep), _ptr(given_mask),
+                                        _ptr(target), int(reps), C.byref(opt), ms), self.h)
+        names = {v: k for k, v in SCHEDULES.items()}
+        self.tile = (opt.tile_w, opt.tile_h)
+        self.schedule = names[opt.schedule]
+        return self.tile, self.schedule, [float(v) for v in ms]
+
+    def set_eval_count_mode(self, mode: int):
+        """0: the method's in-span evaluations (default); 1: the evaluations
+        the timed blend performs after its reach test."""
+        self._check(self.L.sgs_set_eval_count_mode(self.h, int(mode)), self.h)
 
     def query(self, stats=None):
         pairs = I64()

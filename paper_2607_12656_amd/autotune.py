@@ -1,5 +1,9 @@
 """Autotuner for the RD step: tile shape, then blend schedule.
 
+``tune_native`` calls the library's own tuner (``sgs_autotune``: the whole
+step timed per candidate inside the library, the context left bound with the
+choice); ``tune`` times any caller-supplied step function the same way.
+
 The support rule is pixel-exact, so every candidate tile shape renders the
 same image and gradients, and the blend schedule (one workgroup per 8x8
 sub-tile, or resident workgroups over the sub-tiles of the tiles ordered by
@@ -82,3 +86,35 @@ def tune(ctx, n, npad, n_hat, cams, width, height, step_fn, reps: int = 3,
             json.dump(cache, f, indent=1)
         os.replace(tmp, cache_path)
     return {"tile": tile, "schedule": schedule, "ms": timings, "cached": False}
+
+
+def tune_native(ctx, params, qstep, given_mask, target, n, views, width, height,
+                reps: int = 3, cache_path: str | None = None) -> dict:
+    """sgs_autotune on the bound scene (tile shapes with the per-sub-tile
+    schedule, then the schedules with the fastest shape); the result is cached
+    per (device, N, views, width, height) like ``tune``'s.  The context is left
+    bound with the chosen options."""
+    import torch
+    dev_name = torch.cuda.get_device_name(ctx.device)
+    key = "native|" + _key(dev_name, n, views, width, height)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        try:
+            cache = json.load(open(cache_path))
+        except (OSError, ValueError):
+            cache = {}
+    if key in cache:
+        e = cache[key]
+        return {"tile": tuple(e["tile"]), "schedule": e["schedule"], "ms": e["ms"],
+                "cached": True}
+    tile, schedule, ms = ctx.autotune(params, qstep, given_mask, target, reps)
+    order = [f"{tw}x{th}/tile" for tw, th in CANDIDATES] + \
+        [f"{tile[0]}x{tile[1]}/{name}" for name in SCHEDULES[1:]]
+    timings = {k: v for k, v in zip(order, ms)}
+    if cache_path:
+        cache[key] = {"tile": list(tile), "schedule": schedule, "ms": timings}
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(tmp, cache_path)
+    return {"tile": tuple(tile), "schedule": schedule, "ms": timings, "cached": False}

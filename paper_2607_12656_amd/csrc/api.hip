@@ -207,7 +207,7 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   c->TH = th;
   c->tau = tau;
   c->schedule = schedule;
-  c->blend_occ[0] = c->blend_occ[1] = c->blend_occ[2] = 0;
+  c->blend_occ[0] = c->blend_occ[1] = c->blend_occ[2] = c->blend_occ[3] = 0;
   c->GW = (width + tw - 1) / tw;
   c->GH = (height + th - 1) / th;
   c->tiles_per_view = (int64_t)c->GW * c->GH;
@@ -266,6 +266,7 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   if (e != hipSuccess) { free_scene(c); return hip_fail(c, e, "set_scene alloc"); }
   SGS_HIP(hipMemcpy(c->d_cams, cams, sizeof(sgs_camera) * views, hipMemcpyHostToDevice),
           "set_scene camera copy");
+  c->h_cams.assign(cams, cams + views);
   c->scene_set = true;
   c->rendered = false;
   return SGS_OK;
@@ -571,6 +572,128 @@ sgs_status sgs_fl_decode(sgs_ctx *c, const sgs_fl_channel *header, const uint32_
   if (kept > (int64_t)INT32_MAX * 4096LL)
     return fail(c, SGS_ECAPACITY, "fl_decode: kept too large");
   SGS_HIP(launch_fl_decode(c, header, payload, payload_words, kept, out_pad, out), "fl_decode");
+  return SGS_OK;
+}
+
+sgs_status sgs_autotune(sgs_ctx *c, const float *params, const float *qstep,
+                        const uint8_t *given_mask, const float *target, int32_t reps,
+                        sgs_options *chosen, float *ms_out) {
+  if (!c) return SGS_EINVAL;
+  if (!c->scene_set) return fail(c, SGS_ESTATE, "autotune: set_scene first");
+  if (c->capturing) return fail(c, SGS_ESTATE, "autotune: not inside graph capture");
+  if (!params || !qstep || !given_mask || !target || !chosen)
+    return fail(c, SGS_EINVAL, "autotune: null pointer");
+  if (reps < 1 || reps > 1000) return fail(c, SGS_EINVAL, "autotune: reps must be in [1, 1000]");
+  if (!aligned(params, 16)) return fail(c, SGS_EINVAL, "autotune: parameter rows must be 16-byte aligned");
+  SGS_HIP(hipSetDevice(c->device), "hipSetDevice");
+  // the scene to re-bind for every candidate
+  const int64_t n = c->n, npad = c->npad, n_hat = c->n_hat;
+  const int V = c->V, W = c->W, H = c->H;
+  const float tau = c->tau;
+  const std::vector<sgs_camera> cams = c->h_cams;
+  const int64_t pix = (int64_t)V * W * H;
+  // the step's outputs, in one temporary allocation
+  const int64_t words[] = {(n + 3) / 4, n, 2 * SGS_STATS_WORDS, 3 * pix, pix, pix, 3 * pix,
+                           SGS_NCH * npad, 64, n, n, 4, 4, SGS_RATE_GRAD_FLOATS};
+  int64_t off[15] = {0};
+  for (int k = 0; k < 14; ++k) off[k + 1] = off[k] + (words[k] + 63) / 64 * 64;
+  float *buf = nullptr;
+  hipError_t e = dalloc(&buf, off[14]);
+  if (e != hipSuccess) return hip_fail(c, e, "autotune buffers");
+  auto at = [&](int k) { return buf + off[k]; };
+  uint8_t *hard = (uint8_t *)at(0);
+  float *soft = at(1);
+  uint64_t *stats = (uint64_t *)at(2);
+  float *image = at(3), *fT = at(4);
+  uint32_t *last = (uint32_t *)at(5);
+  float *dimage = at(6), *gp = at(7), *gq = at(8), *gs = at(9), *gm = at(10);
+  float *loss = at(11), *rate3 = at(12), *rgrad = at(13);
+  struct Cand { int tw, th, sched; };
+  const Cand tiles[3] = {{16, 16, 0}, {8, 8, 0}, {32, 8, 0}};
+  float times[6] = {0};
+  int ntimed = 0;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  sgs_status st = SGS_OK;
+  auto run = [&](const Cand &cd, float *ms) -> sgs_status {
+    sgs_options o{};
+    o.tile_w = cd.tw;
+    o.tile_h = cd.th;
+    o.tau = tau;
+    o.schedule = cd.sched;
+    sgs_status r = sgs_set_scene(c, n, npad, n_hat, cams.data(), V, W, H, &o);
+    if (r != SGS_OK) return r;
+    auto step = [&]() -> sgs_status {
+      sgs_status q = sgs_quant_render_fwd(c, params, qstep, nullptr, 0, given_mask, 0, 0, hard,
+                                          soft, stats, image, fT, last, nullptr);
+      if (q == SGS_OK) q = sgs_rate_proxy(c, stats, qstep, 0.0f, rate3, rgrad);
+      if (q == SGS_OK) q = sgs_l1_loss(c, image, target, 1.0f, loss, dimage);
+      if (q == SGS_OK)
+        q = sgs_quant_render_bwd(c, params, qstep, soft, 0, rgrad, stats, fT, last, dimage, gp,
+                                 gq, gs, gm);
+      return q;
+    };
+    r = step();  // sizes the pair buffers
+    if (r != SGS_OK) return r;
+    if (hipEventRecord(ea, c->stream) != hipSuccess) return fail(c, SGS_EHIP, "autotune event");
+    for (int k = 0; k < reps && r == SGS_OK; ++k) r = step();
+    if (r != SGS_OK) return r;
+    if (hipEventRecord(eb, c->stream) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
+        hipEventElapsedTime(ms, ea, eb) != hipSuccess)
+      return fail(c, SGS_EHIP, "autotune timing");
+    *ms /= (float)reps;
+    return SGS_OK;
+  };
+  Cand best = tiles[0];
+  float best_ms = 0.0f;
+  if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) {
+    st = fail(c, SGS_EHIP, "autotune events");
+  }
+  for (int k = 0; k < 3 && st == SGS_OK; ++k) {
+    st = run(tiles[k], &times[ntimed]);
+    if (st == SGS_OK && (ntimed == 0 || times[ntimed] < best_ms)) {
+      best = tiles[k];
+      best_ms = times[ntimed];
+    }
+    ++ntimed;
+  }
+  const Cand shape = best;
+  for (int sched = 1; sched <= 3 && st == SGS_OK; ++sched) {
+    const Cand cd = {shape.tw, shape.th, sched};
+    st = run(cd, &times[ntimed]);
+    if (st == SGS_OK && times[ntimed] < best_ms) {
+      best = cd;
+      best_ms = times[ntimed];
+    }
+    ++ntimed;
+  }
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
+  (void)hipStreamSynchronize(c->stream);
+  dfree(buf);
+  // leave the scene bound with the choice (or, after a failure, as it was)
+  sgs_options o{};
+  o.tile_w = best.tw;
+  o.tile_h = best.th;
+  o.tau = tau;
+  o.schedule = best.sched;
+  char keep_err[sizeof(c->err)];
+  memcpy(keep_err, c->err, sizeof(keep_err));
+  const sgs_status rb = sgs_set_scene(c, n, npad, n_hat, cams.data(), V, W, H, &o);
+  if (st != SGS_OK) {
+    memcpy(c->err, keep_err, sizeof(keep_err));
+    return st;
+  }
+  if (rb != SGS_OK) return rb;
+  *chosen = o;
+  if (ms_out)
+    for (int k = 0; k < 6; ++k) ms_out[k] = times[k];
+  return SGS_OK;
+}
+
+sgs_status sgs_set_eval_count_mode(sgs_ctx *c, int32_t mode) {
+  if (!c) return SGS_EINVAL;
+  if (mode != 0 && mode != 1) return fail(c, SGS_EINVAL, "set_eval_count_mode: mode must be 0 or 1");
+  c->count_mode = mode;
   return SGS_OK;
 }
 

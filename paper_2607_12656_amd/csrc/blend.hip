@@ -68,6 +68,12 @@ __device__ __forceinline__ uint64_t uniform_mask(uint64_t m) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Evaluation counting of the forward: none (the timed path), every in-span
+// pair before termination (the method's evaluations; the reach test is off
+// so that every such pair is visited), or the pairs the timed path visits
+// (in-span pairs kept by the reach test, before termination).
+enum CountMode { kCountNone = 0, kCountSpan = 1, kCountReach = 2 };
+
 // One 8x8 sub-tile of a tile's forward, by one wave (the workgroup): the
 // wave stages 64 list entries at a time in its LDS (one 48-byte record per
 // lane), marks with a ballot those whose pixel span meets its sub-tile and
@@ -76,7 +82,7 @@ __device__ __forceinline__ uint64_t uniform_mask(uint64_t m) {
 // order, in pairs whose records are read and evaluated together; the next
 // 64 records are fetched from global memory during the walk.  It stops once
 // all its pixels have stopped.  evals accumulates the lane's in-span pairs.
-template <int TW, int TH, bool COUNT, int WPB>
+template <int TW, int TH, int COUNT, int WPB>
 __device__ __forceinline__ void blend_fwd_sub(int tile, int sub, int n, int W, int H, int GW,
                                               int tiles_per_view,
                                               const uint2 *__restrict__ ranges,
@@ -133,7 +139,7 @@ __device__ __forceinline__ void blend_fwd_sub(int tile, int sub, int n, int W, i
       // it counts in-span pairs)
       m = __ballot(valid && (int)(sx & 0xFFFF) <= sx0 + 7 && (int)(sx >> 16) >= sx0 &&
                    (int)(sy & 0xFFFF) <= sy0 + 7 && (int)(sy >> 16) >= sy0 &&
-                   (COUNT || may_reach(ra, rb, sx0, sy0)));
+                   (COUNT == kCountSpan || may_reach(ra, rb, sx0, sy0)));
     }
     wave_lds_sync();
     if (b + 64 < rg.y) fetch(b + 64);
@@ -221,7 +227,7 @@ __device__ __forceinline__ int later_tile(int q, uint32_t *head, int total) {
 // `order` for the persistent schedules), one wave per workgroup; with
 // kTileBlock a workgroup of NW waves takes whole tiles of that order (striding),
 // wave w sub-tile w, the waves walking independently.
-template <int TW, int TH, int SCHED, bool COUNT>
+template <int TW, int TH, int SCHED, int COUNT>
 __global__ void __launch_bounds__(SCHED == kTileBlock ? TW * TH : 64)
 k_blend_fwd(int total, const uint32_t *__restrict__ order, uint32_t *__restrict__ head,
             int n, int W, int H, int GW, int tiles_per_view, const uint2 *__restrict__ ranges,
@@ -570,14 +576,14 @@ int persistent_grid(sgs_ctx *c, int slot, K kernel, int items, int block) {
   return g < items ? g : items;
 }
 
-template <int TW, int TH, int SCHED, bool COUNT>
+template <int TW, int TH, int SCHED, int COUNT>
 hipError_t fwd_tc(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint64_t *ec) {
   const uint32_t *vals = c->pair_val[c->pair_sorted_buf];
   const int block = SCHED == kTileBlock ? TW * TH : 64;
   const int items = (int)c->total_tiles * (SCHED == kTileBlock ? 1 : TW * TH / 64);
   const int grid = SCHED == kPerTile
                        ? items
-                       : persistent_grid(c, COUNT ? 1 : 0, k_blend_fwd<TW, TH, SCHED, COUNT>,
+                       : persistent_grid(c, COUNT, k_blend_fwd<TW, TH, SCHED, COUNT>,
                                          items, block);
   k_blend_fwd<TW, TH, SCHED, COUNT><<<grid, block, 0, c->stream>>>(
       items, c->tile_order, c->tile_bins + 66, (int)c->n, c->W, c->H, c->GW,
@@ -592,8 +598,9 @@ hipError_t fwd_tc(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint
 // the evaluation count is compiled in only when it is asked for
 template <int TW, int TH, int SCHED>
 hipError_t fwd_t(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint64_t *ec) {
-  return ec ? fwd_tc<TW, TH, SCHED, true>(c, image, final_T, last, ec)
-            : fwd_tc<TW, TH, SCHED, false>(c, image, final_T, last, ec);
+  if (!ec) return fwd_tc<TW, TH, SCHED, kCountNone>(c, image, final_T, last, ec);
+  if (c->count_mode == 1) return fwd_tc<TW, TH, SCHED, kCountReach>(c, image, final_T, last, ec);
+  return fwd_tc<TW, TH, SCHED, kCountSpan>(c, image, final_T, last, ec);
 }
 
 template <int TW, int TH, int SCHED>
@@ -603,7 +610,7 @@ hipError_t bwd_t(sgs_ctx *c, const float *final_T, const uint32_t *last, const f
   const int items = (int)c->total_tiles * (SCHED == kTileBlock ? 1 : TW * TH / 64);
   const int grid = SCHED == kPerTile
                        ? items
-                       : persistent_grid(c, 2, k_blend_bwd<TW, TH, SCHED>, items, block);
+                       : persistent_grid(c, 3, k_blend_bwd<TW, TH, SCHED>, items, block);
   k_blend_bwd<TW, TH, SCHED><<<grid, block, 0, c->stream>>>(
       items, c->tile_order, c->tile_bins + 67, (int)c->n, c->W, c->H, c->GW,
       (int)c->tiles_per_view, c->ranges, vals, c->rec, final_T, last, dimg, c->splat_grad);

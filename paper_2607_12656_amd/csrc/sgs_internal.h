@@ -49,10 +49,13 @@ struct sgs_ctx {
   int64_t tiles_per_view = 0, total_tiles = 0;
   float tau = 1.0f;
   int schedule = 0;               // blend launch schedule (sgs_options.schedule)
-  int blend_occ[3] = {0, 0, 0};   // resident blend workgroups (fwd, fwd counting, bwd); 0 unknown
+  int blend_occ[4] = {0, 0, 0, 0}; // resident blend workgroups (fwd, fwd counting in-span,
+                                   // fwd counting reach-kept, bwd); 0 unknown
+  int count_mode = 0;             // sgs_set_eval_count_mode
   bool scene_set = false;
   bool rendered = false;
   sgs_camera *d_cams = nullptr;
+  std::vector<sgs_camera> h_cams; // host copy of the scene's cameras (for re-binding)
 
   // per (view, Gaussian): V*n entries
   int64_t vn = 0;

@@ -10,7 +10,16 @@ Only library calls are issued; nothing here computes, and an iteration never
 synchronizes with the host.  ``prune`` applies the learned mask (the
 supplement prunes with it every 1,000 iterations of the formation stage):
 the Gaussians whose current hard mask is 0 leave the scene, with their
-moments, and the step is rebuilt for the survivors (one synchronization).  The learning rates are vanilla 3DGS's defaults
+moments, and the step is rebuilt for the survivors (one synchronization).
+
+With the learned estimator in the loop the plain proxy is still evaluated
+every iteration; ``check_rate`` (every ``check_every`` iterations when that
+is set, one synchronization each) compares both estimates with the exact
+bits of the channel-wise fixed-length coder (Sec. 3.4.1) and, while the
+learned estimate's relative error is the larger, the plain proxy's gradient
+drives the iteration instead (the proxy is the fallback and the judge).
+
+The learning rates are vanilla 3DGS's defaults
 (Kerbl et al. 2023; the paper builds on vanilla 3DGS, Sec. 4.1): mean 1.6e-4,
 DC colour 2.5e-3, higher SH 2.5e-3 / 20, opacity 2.5e-2, log-scale 5e-3,
 rotation 1e-3; the step sizes and scores take rates the paper does not
@@ -40,7 +49,8 @@ class Formation:
                  mask_mode: int = 1, given_mask=None, seed: int = 0, mlp=None,
                  lr=LR_3DGS, lr_q: float = 1e-4, lr_score: float = 1e-2,
                  sh_every: int = 16, sparse: bool = True, ssim_weight: float = 0.0,
-                 proxy: str = "range", masking: str = "mult", alpha: float = 0.0):
+                 proxy: str = "range", masking: str = "mult", alpha: float = 0.0,
+                 check_every: int = 0):
         torch = rd.torch
         self.rd, self.ctx = rd, rd.ctx
         self.params, self.q, self.score, self.target = params, qstep, score, target
@@ -56,11 +66,74 @@ class Formation:
         self.sm, self.sv = z(score), z(score)
         self.R_learned = torch.zeros(1, dtype=torch.float32, device=rd.dev)
         self.k = 0
+        self.check_every = check_every
+        self.use_learned = mlp is not None
+        self.checks = []               # (iteration, plain error, learned error, learned used)
+        self._coder = None
+
+    def _state_tensors(self):
+        return (self.params, self.q, self.score, self.pm, self.pv, self.qm, self.qv, self.sm,
+                self.sv)
+
+    def snapshot(self):
+        """Copies of the iterated tensors and the iteration count."""
+        return [t.clone() for t in self._state_tensors()], self.k
+
+    def restore(self, snap):
+        """Back to a snapshot, in place (buffers keep their addresses, so
+        captured graphs stay valid)."""
+        tensors, k = snap
+        for dst, src in zip(self._state_tensors(), tensors):
+            dst.copy_(src)
+        self.k = k
+
+    def rate_errors(self):
+        """Plain proxy and learned estimate (if any) of the current state
+        against the exact fixed-length coder bits B: returns (B, kept,
+        |N_hat R_plain - B| / B, |N_hat R_learned - B| / B or None).
+        Synchronizes."""
+        torch = self.rd.torch
+        c, rd = self.ctx, self.rd
+        p, q, s = self.params, self.q, self.score
+        if self._coder is None:
+            words = rd.n * 59 + 64            # 32 bits per code at most
+            dev = rd.dev
+            self._coder = (torch.empty((59, 3), dtype=torch.int32, device=dev),
+                           torch.empty(words, dtype=torch.int32, device=dev),
+                           torch.empty(3, dtype=torch.int64, device=dev))
+        hdr, payload, info = self._coder
+        c.fakequant_prune(p, q, s, self.mask_mode, self.given, self.seed, self.k, rd.qparams,
+                          rd.hard, rd.soft, rd.stats)
+        c.rate_proxy(rd.stats, q, 0.0, rd.rate3, None)
+        if self.mlp is not None:
+            packed, theta = self.mlp
+            c.rate_mlp_fwd(packed, theta, p, q, rd.stats, rd.hard, self.R_learned, None)
+        c.fl_encode(p, q, rd.hard, hdr, payload, payload.numel(), info)
+        v = info.cpu().numpy()
+        if v[2] != 0:
+            raise RuntimeError(f"fixed-length coder flags {int(v[2])}")
+        bits = int(v[0]) + 59 * 72
+        e_plain = abs(float(rd.rate3[0].item()) * rd.n_hat - bits) / bits
+        e_learn = None
+        if self.mlp is not None:
+            e_learn = abs(float(self.R_learned[0].item()) * rd.n_hat - bits) / bits
+        return bits, int(v[1]), e_plain, e_learn
+
+    def check_rate(self):
+        """The fallback rule: the learned estimate drives the iteration until a
+        check finds its error larger than the plain proxy's."""
+        bits, kept, e_plain, e_learn = self.rate_errors()
+        if self.mlp is not None:
+            self.use_learned = e_learn <= e_plain
+        self.checks.append((self.k, e_plain, e_learn, self.use_learned))
+        return e_plain, e_learn
 
     def iterate(self, count_evals: bool = False):
+        if self.check_every and self.mlp is not None and self.k % self.check_every == 0:
+            self.check_rate()
         c, rd, k, mm = self.ctx, self.rd, self.k, self.mask_mode
         p, q, s = self.params, self.q, self.score
-        learned = self.mlp is not None
+        learned = self.mlp is not None and self.use_learned
         # quantizer, mask and render in one call (the quantized rows stay in
         # registers); the rate terms read the statistics it leaves
         c.quant_render_fwd(p, q, s, mm, self.given, self.seed, k, rd.hard, rd.soft, rd.stats,

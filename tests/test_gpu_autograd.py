@@ -197,3 +197,33 @@ def test_autotuner_choice_and_cache(orc, gctx, dev, tmp_path):
         torch.cuda.synchronize()
         imgs.append(rd.image.cpu().numpy())
     assert np.array_equal(imgs[0], imgs[1])
+
+
+def test_native_autotuner(orc, gctx, dev):
+    """sgs_autotune: six candidates timed (three tile shapes, then three more
+    schedules with the fastest shape), the fastest chosen, the context left
+    bound with it, and that binding renders the image the oracle renders."""
+    from paper_2607_12656_amd import autotune
+    sc = synth.make_tiny(400, 150, 90, views=2, seed=11)
+    params, q = T(sc.params, dev), T(sc.qstep, dev)
+    mask, target = T(sc.given_mask, dev), T(sc.target, dev)
+    gctx.set_scene(sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height)
+    res = autotune.tune_native(gctx, params, q, mask, target, sc.n, sc.views, sc.width,
+                               sc.height, reps=2)
+    ms = res["ms"]
+    assert len(ms) == 6 and all(v > 0 for v in ms.values())
+    best = f"{res['tile'][0]}x{res['tile'][1]}/{res['schedule']}"
+    assert ms[best] == min(ms.values())
+    # the context is bound with the choice: a step renders the oracle's image
+    n, V, W, H = sc.n, sc.views, sc.width, sc.height
+    e = lambda *s_, dt=torch.float32: torch.empty(*s_, dtype=dt, device=dev)
+    hard, soft, stats = e(n, dt=torch.uint8), e(n), e(128, dt=torch.int64)
+    img, fT, last = e(V, 3, H, W), e(V, H, W), e(V, H, W, dt=torch.int32)
+    gctx.quant_render_fwd(params, q, None, 0, mask, 0, 0, hard, soft, stats, img, fT, last, None)
+    torch.cuda.synchronize()
+    yh, _ = orc.fakequant(sc.params, sc.qstep, n)
+    st = orc.decide(yh, n, sc.cams, W, H, res["tile"][0], res["tile"][1])
+    fw = orc.forward(yh.astype(np.float64), sc.given_mask.astype(np.float64), n, sc.cams, W, H,
+                     st)
+    ok = fw["margin"] == 0
+    assert np.abs(img.cpu().numpy() - fw["image"]).max(axis=1)[ok].max() <= 1e-4

@@ -266,6 +266,38 @@ def test_c1_full_step(orc, gctx, dev):
         grad_close(g["gmask"], r["gmhat"], name="grad mask")
 
 
+def test_eval_count_modes(orc, gctx, dev):
+    """Mode 0 counts the method's evaluations (the oracle's count); mode 1 the
+    evaluations the timed blend performs after its reach test (no more than
+    mode 0); images, T and stop positions are the same bits in every mode."""
+    from paper_2607_12656_amd.rd import RDStep
+    sc = synth.make_scene("c1")
+    rd = RDStep(gctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height, fused=True)
+    params, q, score = T(sc.params, dev), T(sc.qstep, dev), T(sc.score, dev)
+    mask, target = T(sc.given_mask, dev), T(sc.target, dev)
+    outs, counts = [], []
+    for mode in (0, 1, None):
+        if mode is not None:
+            gctx.set_eval_count_mode(mode)
+        rd.evals.zero_()
+        rd.forward(params, q, score, target, 0.5, 0, mask, 0, 0, count_evals=mode is not None)
+        torch.cuda.synchronize()
+        counts.append(int(rd.evals.item()))
+        outs.append([x.cpu().numpy().view(np.uint32) for x in (rd.image, rd.final_T, rd.last)])
+    gctx.set_eval_count_mode(0)
+    s = orc.rd_forward(sc.params, sc.qstep, sc.score, sc.given_mask, sc.cams, sc.width,
+                       sc.height, sc.target, sc.n, sc.n_hat, 0.5)
+    assert counts[0] == s["fw"]["evals"]
+    assert 0 < counts[1] <= counts[0] and counts[2] == 0
+    _say(f"c1 evaluations: {counts[0]} in span, {counts[1]} after the reach test")
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+    from paper_2607_12656_amd import SgsError
+    with pytest.raises(SgsError):
+        gctx.set_eval_count_mode(2)
+
+
 @pytest.mark.parametrize("fused", [False, True])
 def test_end_to_end_each_side_own_l1_gradient(orc, gctx, dev, fused):
     """The whole step with nothing shared but the inputs: each side takes its

@@ -789,3 +789,41 @@ def test_sh_view_direction_sign(orc):
     pj = orc.project64(p.astype(np.float64), 1, cam, W, H, st)[0]
     assert pj[0, 6] == pytest.approx(0.5 + f * math.sqrt(3 / (4 * math.pi)), rel=1e-14)
     assert pj[0, 7] == pytest.approx(0.5, rel=1e-15) and pj[0, 8] == pytest.approx(0.5, rel=1e-15)
+
+
+@pytest.mark.parametrize("parallel", [False, True])
+def test_sampled_tile_step_equals_full_step_on_those_tiles(orc, parallel):
+    """The CPU baseline's bounded sample (the render forward and backward over
+    chosen tiles) computes exactly the full step restricted to them: the
+    tiles' pixels equal the full forward's, and the parameter gradient equals
+    the full backward's with dL/dC zero outside the chosen tiles; the OpenMP
+    build gives the same bits as the serial one."""
+    sc = _tiny(n=90, W=70, H=50, V=2, seed=14)
+    yh, _ = orc.fakequant(sc.params, sc.qstep, sc.n)
+    st = orc.decide(yh, sc.n, sc.cams, sc.width, sc.height, 16, 16)
+    lite = orc.decide(yh, sc.n, sc.cams, sc.width, sc.height, 16, 16, bin_pairs=False)
+    p64, m = yh.astype(np.float64), sc.given_mask.astype(np.float64)
+    GW, GH = -(-sc.width // 16), -(-sc.height // 16)
+    tiles = np.array([0, 3, GW * GH - 1, GW * GH + 5, 2 * GW * GH - 2])   # ragged ones too
+    dimg = np.random.default_rng(2).normal(size=(2, 3, sc.height, sc.width))
+    E, img, gp = orc.step_tiles_sampled(p64, m, sc.n, sc.cams, sc.width, sc.height, lite, tiles,
+                                        dimg, parallel=parallel)
+    fw = orc.forward(p64, m, sc.n, sc.cams, sc.width, sc.height, st)
+    keep = np.zeros((2, sc.height, sc.width), bool)
+    evals = 0
+    for k, t in enumerate(tiles):
+        v, tt = divmod(int(t), GW * GH)
+        ty, tx = divmod(tt, GW)
+        ys, xs = slice(ty * 16, min(ty * 16 + 16, sc.height)), slice(tx * 16, min(tx * 16 + 16, sc.width))
+        keep[v, ys, xs] = True
+        h, w = ys.stop - ys.start, xs.stop - xs.start
+        assert np.array_equal(img[k, :, :h, :w], fw["image"][v, :, ys, xs])
+        assert not img[k, :, h:, :].any() and not img[k, :, :, w:].any()
+    gfull, _, _ = orc.backward(p64, m, sc.n, sc.cams, sc.width, sc.height, st,
+                               dimg * keep[:, None], want_splat=False)
+    assert np.abs(gp - gfull).max() <= 1e-12 * np.abs(gfull).max()
+    assert E > 0
+    if parallel:
+        E1, img1, gp1 = orc.step_tiles_sampled(p64, m, sc.n, sc.cams, sc.width, sc.height, lite,
+                                               tiles, dimg, parallel=False)
+        assert E1 == E and np.array_equal(img1, img) and np.array_equal(gp1, gp)
