@@ -101,3 +101,48 @@ def test_learned_rate_iterations_run(gctx, dev):
     torch.cuda.synchronize()
     assert np.isfinite(float(f.R_learned.item())) and float(f.R_learned.item()) > 0
     assert np.all(np.isfinite(f.params.cpu().numpy()[:, :sc.n]))
+
+
+def test_learned_rate_fallback_rule(orc, gctx, dev):
+    """The learned estimate drives the iteration while its error against the
+    exact coder bits is not larger than the plain proxy's, and the plain
+    proxy's gradient drives it after a check that finds it larger.  Two
+    estimators with zero weights and a constant output: f = B / kept (exact:
+    N_hat R_learned = B) and f = 3 B / kept (error 2)."""
+    from oracle import mlp as omlp
+    from paper_2607_12656_amd._lib import MLP_PACKED_BYTES, MLP_PARAMS
+    from paper_2607_12656_amd.formation import Formation
+    from paper_2607_12656_amd.rd import RDStep
+    sc = synth.make_tiny(3000, 48, 40, seed=52)
+    bits, per = omlp.coder_targets(sc.params, sc.qstep, sc.given_mask, sc.n)
+    lam = 0.5
+    grads = {}
+    for name, b3 in (("exact", per), ("bad", 3.0 * per), ("plain", None)):
+        rd = RDStep(gctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height)
+        mlp = None
+        if b3 is not None:
+            theta = torch.zeros(MLP_PARAMS, dtype=torch.float32, device=dev)
+            theta[-1] = b3
+            packed = torch.empty(MLP_PACKED_BYTES // 4, dtype=torch.int32, device=dev)
+            gctx.rate_mlp_pack(theta, packed)
+            mlp = (packed, theta)
+        f = Formation(rd, T(sc.params, dev), T(sc.qstep, dev), T(sc.score, dev),
+                      T(sc.target, dev), lam, mask_mode=0, given_mask=T(sc.given_mask, dev),
+                      mlp=mlp, check_every=4)
+        B, kept, e_plain, e_learn = f.rate_errors()
+        assert B == bits and kept == int(sc.given_mask.sum())
+        f.iterate()                     # k = 0: the check runs first
+        torch.cuda.synchronize()
+        grads[name] = rd.grad_q.cpu().numpy().copy()
+        if name == "exact":
+            assert e_learn <= 1e-6 and f.use_learned
+        elif name == "bad":
+            assert abs(e_learn - 2.0) <= 1e-6 and not f.use_learned
+            assert f.checks[-1][3] is False
+        _say(f"{name}: plain error {e_plain:.4f}, learned {e_learn}")
+    # fallen back: the step-size gradient is the plain iteration's (up to the
+    # order of the render gradient's atomic sums); with the exact estimator
+    # (zero weights: no rate gradient to q) it is not
+    scale = np.abs(grads["plain"]).max()
+    assert np.abs(grads["bad"] - grads["plain"]).max() <= 1e-5 * scale
+    assert np.abs(grads["exact"] - grads["plain"]).max() > 1e-2 * scale
