@@ -78,7 +78,17 @@ typedef struct {
                              from an atomic queue, 3 resident workgroups of one
                              whole tile each (a wave per sub-tile) striding
                              over that order; results do not depend on it */
-  int32_t reserved[4];    /* must be zero */
+  int32_t deterministic;  /* 0 (default): the blend backward adds each splat's
+                             per-wave gradient sums with FP64 atomics (their
+                             order, hence the last bits, varies from run to
+                             run); 1: it adds them as 96-bit fixed-point
+                             integers (units of 2^-64, terms below 2^31 in
+                             magnitude) whose sums do not depend on order, so
+                             every gradient is the same bits on every run and
+                             schedule (3x the accumulator memory: 240 bytes per
+                             view and Gaussian); a term out of that range is
+                             left out and reported by sgs_query */
+  int32_t reserved[3];    /* must be zero */
 } sgs_options;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
@@ -228,8 +238,9 @@ sgs_status sgs_set_eval_count_mode(sgs_ctx *ctx, int32_t mode);
 /* Host-side query (synchronizes the stream): pairs of the last render and the
  * device flags word of `stats` (may be NULL).  Returns SGS_EINVAL when the
  * flags report an invalid step size, SGS_ECAPACITY (once, then cleared) when
- * a render since the last query exceeded a reserved pair capacity; the
- * caller reserves more and reruns the step. */
+ * a render since the last query exceeded a reserved pair capacity (the
+ * caller reserves more and reruns the step) or, in deterministic mode, a
+ * per-wave gradient term fell outside the fixed-point range. */
 sgs_status sgs_query(sgs_ctx *ctx, const uint64_t *stats, int64_t *pairs_last,
                      uint64_t *flags);
 

@@ -38,7 +38,8 @@ class sgs_camera(C.Structure):
 
 class sgs_options(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("tau", C.c_float),
-                ("schedule", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("schedule", C.c_int32), ("deterministic", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class sgs_rate_options(C.Structure):
@@ -209,14 +210,15 @@ class Context:
 
     # ---- the C ABI, one method per entry point -----------------------------
     def set_scene(self, n, npad, n_hat, cams, width, height, tile=(16, 16), tau=1.0,
-                  schedule="tile"):
+                  schedule="tile", deterministic=False):
         """schedule: blend launch, one wave per 8x8 sub-tile: "tile" (one
         workgroup per sub-tile), "stride" or "queue" (resident workgroups over
         the sub-tiles of the tiles ordered by list length), "block" (resident
         workgroups of one whole tile each, striding over that order)."""
         cams = np.ascontiguousarray(cams, np.float32)
         arr = cameras(cams)
-        opt = sgs_options(tile[0], tile[1], tau, SCHEDULES[schedule], (C.c_int32 * 4)())
+        opt = sgs_options(tile[0], tile[1], tau, SCHEDULES[schedule], int(bool(deterministic)),
+                          (C.c_int32 * 3)())
         self.V, self.W, self.H, self.n, self.npad = cams.shape[0], width, height, n, npad
         self.tile = tile
         self.schedule = schedule

@@ -71,6 +71,7 @@ void free_scene(sgs_ctx *c) {
   dfree(c->blk_start);
   c->blk_start_words = 0;
   dfree(c->splat_grad);
+  dfree(c->det_acc);
   dfree(c->ranges);
   dfree(c->tile_order);
   dfree(c->tile_bins);
@@ -178,7 +179,7 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
     return fail(c, SGS_EINVAL, "set_scene: bad cameras or image size");
   if ((int64_t)views * n >= (int64_t)1 << 31)
     return fail(c, SGS_ECAPACITY, "set_scene: views * n must stay below 2^31");
-  int tw = 16, th = 16, schedule = 0;
+  int tw = 16, th = 16, schedule = 0, det = 0;
   float tau = 1.0f;
   if (opt) {
     if (opt->tile_w || opt->tile_h) {
@@ -187,9 +188,11 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
     }
     if (opt->tau != 0.0f) tau = opt->tau;
     schedule = opt->schedule;
-    for (int k = 0; k < 4; ++k)
+    det = opt->deterministic;
+    for (int k = 0; k < 3; ++k)
       if (opt->reserved[k] != 0) return fail(c, SGS_EINVAL, "set_scene: reserved options must be 0");
   }
+  if (det != 0 && det != 1) return fail(c, SGS_EINVAL, "set_scene: deterministic must be 0 or 1");
   if (schedule < 0 || schedule > 3) return fail(c, SGS_EINVAL, "set_scene: schedule must be 0 to 3");
   if (!((tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 32 && th == 8)))
     return fail(c, SGS_EINVAL, "set_scene: tile shape must be 8x8, 16x16 or 32x8");
@@ -207,7 +210,8 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   c->TH = th;
   c->tau = tau;
   c->schedule = schedule;
-  c->blend_occ[0] = c->blend_occ[1] = c->blend_occ[2] = c->blend_occ[3] = 0;
+  c->deterministic = det != 0;
+  for (int &o : c->blend_occ) o = 0;
   c->GW = (width + tw - 1) / tw;
   c->GH = (height + th - 1) / th;
   c->tiles_per_view = (int64_t)c->GW * c->GH;
@@ -235,6 +239,7 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   c->fl_tmp_words = fl_scratch_words(n);
   SGS_ALLOC(c->mlp_signs, 2 * n);
   SGS_ALLOC(c->splat_grad, vn * SGS_SGRAD);
+  if (c->deterministic) SGS_ALLOC(c->det_acc, vn * SGS_SGRAD * 3);
   SGS_ALLOC(c->ranges, c->total_tiles);
   SGS_ALLOC(c->tile_order, c->total_tiles);
   SGS_ALLOC(c->tile_bins, SGS_TILE_BINS);
@@ -590,6 +595,7 @@ sgs_status sgs_autotune(sgs_ctx *c, const float *params, const float *qstep,
   const int64_t n = c->n, npad = c->npad, n_hat = c->n_hat;
   const int V = c->V, W = c->W, H = c->H;
   const float tau = c->tau;
+  const int det = c->deterministic ? 1 : 0;
   const std::vector<sgs_camera> cams = c->h_cams;
   const int64_t pix = (int64_t)V * W * H;
   // the step's outputs, in one temporary allocation
@@ -620,6 +626,7 @@ sgs_status sgs_autotune(sgs_ctx *c, const float *params, const float *qstep,
     o.tile_h = cd.th;
     o.tau = tau;
     o.schedule = cd.sched;
+    o.deterministic = det;
     sgs_status r = sgs_set_scene(c, n, npad, n_hat, cams.data(), V, W, H, &o);
     if (r != SGS_OK) return r;
     auto step = [&]() -> sgs_status {
@@ -676,6 +683,7 @@ sgs_status sgs_autotune(sgs_ctx *c, const float *params, const float *qstep,
   o.tile_h = best.th;
   o.tau = tau;
   o.schedule = best.sched;
+  o.deterministic = det;
   char keep_err[sizeof(c->err)];
   memcpy(keep_err, c->err, sizeof(keep_err));
   const sgs_status rb = sgs_set_scene(c, n, npad, n_hat, cams.data(), V, W, H, &o);
@@ -721,6 +729,19 @@ sgs_status sgs_query(sgs_ctx *c, const uint64_t *stats, int64_t *pairs_last, uin
     *flags = 0;
     if (stats)
       SGS_HIP(hipMemcpy(flags, stats + 119, sizeof(uint64_t), hipMemcpyDeviceToHost), "query flags");
+  }
+  if (c->deterministic && c->d_pairs_total) {
+    uint32_t dflag = 0;
+    SGS_HIP(hipMemcpy(&dflag, c->d_pairs_total + 3, sizeof(dflag), hipMemcpyDeviceToHost),
+            "query deterministic flag");
+    if (dflag) {
+      const uint32_t zero = 0;
+      SGS_HIP(hipMemcpy(c->d_pairs_total + 3, &zero, sizeof(zero), hipMemcpyHostToDevice),
+              "query clear");
+      return fail(c, SGS_ECAPACITY,
+                  "deterministic gradient sums: a per-wave term of magnitude >= 2^31 or not "
+                  "finite was left out (scale the loss down or use the atomic mode)");
+    }
   }
   if (flags && (*flags & 1ull)) return fail(c, SGS_EINVAL, "a step size q_j was <= 0 or not finite");
   if (overflow)

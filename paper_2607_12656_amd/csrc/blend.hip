@@ -325,10 +325,52 @@ __device__ __forceinline__ float wave_transpose_sum10(const float v[10], int lan
   return x;
 }
 
+// Deterministic mode: a wave's sum v (FP32) is added as the integer
+// X = trunc(v 2^64) (a 96-bit two's-complement number: 2^-64 resolution,
+// |v| < 2^31) split into three 32-bit limbs, each added to its own 64-bit
+// accumulator (the low two as unsigned, the top one signed).  Integer sums
+// do not depend on the order of the additions, so the per-splat totals, and
+// every gradient computed from them, are the same bits from run to run and
+// from schedule to schedule.  Returns false (nothing added) for |v| >= 2^31
+// or a value that is not finite.
+__device__ __forceinline__ bool det_add(unsigned long long *acc, float v) {
+  const uint32_t b = __float_as_uint(v);
+  const int e = (int)((b >> 23) & 0xFFu);
+  if (e == 0) return true;                 // zero or below 2^-126
+  if (e >= 158) return false;              // |v| >= 2^31, infinite or NaN
+  const uint64_t m = (b & 0x7FFFFFu) | 0x800000u;
+  const int sh = e - 86;                   // X = m 2^sh
+  if (sh <= -24) return true;              // below 2^-64
+  uint64_t lo, hi;
+  if (sh < 0) {
+    lo = m >> -sh;
+    hi = 0;
+  } else if (sh < 40) {
+    lo = m << sh;
+    hi = 0;
+  } else if (sh < 64) {
+    lo = m << sh;
+    hi = m >> (64 - sh);
+  } else {
+    lo = 0;
+    hi = m << (sh - 64);
+  }
+  if (b >> 31) {                           // two's complement of hi:lo
+    hi = ~hi + (lo == 0 ? 1u : 0u);
+    lo = ~lo + 1u;
+  }
+  const uint32_t l0 = (uint32_t)lo, l1 = (uint32_t)(lo >> 32);
+  const int32_t l2 = (int32_t)(uint32_t)hi;
+  if (l0) atomicAdd(acc + 0, (unsigned long long)l0);
+  if (l1) atomicAdd(acc + 1, (unsigned long long)l1);
+  if (l2) atomicAdd(acc + 2, (unsigned long long)(int64_t)l2);
+  return true;
+}
+
 // One 8x8 sub-tile of a tile's backward, by one wave: the list from the
 // wave's furthest stop towards the front, 64 entries at a time staged in LDS
 // with their Gaussian ids, walked back to front.
-template <int TW, int TH, int WPB>
+template <int TW, int TH, int WPB, bool DET>
 __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, int H, int GW,
                                               int tiles_per_view,
                                               const uint2 *__restrict__ ranges,
@@ -337,7 +379,9 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
                                               const float *__restrict__ final_T,
                                               const uint32_t *__restrict__ last,
                                               const float *__restrict__ dimg,
-                                              double *__restrict__ sgrad) {
+                                              double *__restrict__ sgrad,
+                                              unsigned long long *__restrict__ dacc,
+                                              uint32_t *__restrict__ dflag) {
   constexpr int SUBW = TW / 8;
   __shared__ SplatLds sh_all[WPB][64];  // one region per wave of the workgroup
   __shared__ uint32_t s_gid_all[WPB][64];
@@ -468,8 +512,14 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
       const float cs = fmaf(sel_a, cur.a.z, fmaf(sel_c, cur.b.x, k_rest));
       const float co = sel_b * cur.a.w;
       const float gv = fmaf(cs, tot, co * other);
-      if (lead && gv != 0.0f)
-        unsafeAtomicAdd(gbase + (size_t)gid * SGS_SGRAD + vidx, (double)gv);
+      if (lead && gv != 0.0f) {
+        if (DET) {
+          const size_t slot = ((size_t)(base + gid) * SGS_SGRAD + vidx) * 3;
+          if (!det_add(dacc + slot, gv)) atomicOr(dflag, 1u);
+        } else {
+          unsafeAtomicAdd(gbase + (size_t)gid * SGS_SGRAD + vidx, (double)gv);
+        }
+      }
     };
     // back to front, entries in pairs: both records are read and evaluated
     // before either gradient is taken
@@ -489,23 +539,26 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
   }
 }
 
-template <int TW, int TH, int SCHED>
+template <int TW, int TH, int SCHED, bool DET>
 __global__ void __launch_bounds__(SCHED == kTileBlock ? TW * TH : 64)
 k_blend_bwd(int total, const uint32_t *__restrict__ order, uint32_t *__restrict__ head,
             int n, int W, int H, int GW, int tiles_per_view, const uint2 *__restrict__ ranges,
             const uint32_t *__restrict__ vals, const float4 *__restrict__ rec,
             const float *__restrict__ final_T, const uint32_t *__restrict__ last,
-            const float *__restrict__ dimg, double *__restrict__ sgrad) {
+            const float *__restrict__ dimg, double *__restrict__ sgrad,
+            unsigned long long *__restrict__ dacc, uint32_t *__restrict__ dflag) {
   constexpr int NW = TW * TH / 64;
   if (SCHED == kTileBlock) {
     for (int q = (int)blockIdx.x; q < total; q += (int)gridDim.x)
-      blend_bwd_sub<TW, TH, NW>((int)order[q], (int)(threadIdx.x >> 6), n, W, H, GW,
-                                tiles_per_view, ranges, vals, rec, final_T, last, dimg, sgrad);
+      blend_bwd_sub<TW, TH, NW, DET>((int)order[q], (int)(threadIdx.x >> 6), n, W, H, GW,
+                                     tiles_per_view, ranges, vals, rec, final_T, last, dimg,
+                                     sgrad, dacc, dflag);
   } else {
     for (int q = first_tile<SCHED>(head, total); q >= 0; q = later_tile<SCHED>(q, head, total)) {
       const int ti = q / NW;
-      blend_bwd_sub<TW, TH, 1>(SCHED == kPerTile ? ti : (int)order[ti], q - ti * NW, n, W, H, GW,
-                               tiles_per_view, ranges, vals, rec, final_T, last, dimg, sgrad);
+      blend_bwd_sub<TW, TH, 1, DET>(SCHED == kPerTile ? ti : (int)order[ti], q - ti * NW, n, W,
+                                    H, GW, tiles_per_view, ranges, vals, rec, final_T, last, dimg,
+                                    sgrad, dacc, dflag);
     }
   }
 }
@@ -603,18 +656,26 @@ hipError_t fwd_t(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint6
   return fwd_tc<TW, TH, SCHED, kCountSpan>(c, image, final_T, last, ec);
 }
 
-template <int TW, int TH, int SCHED>
-hipError_t bwd_t(sgs_ctx *c, const float *final_T, const uint32_t *last, const float *dimg) {
+template <int TW, int TH, int SCHED, bool DET>
+hipError_t bwd_td(sgs_ctx *c, const float *final_T, const uint32_t *last, const float *dimg) {
   const uint32_t *vals = c->pair_val[c->pair_sorted_buf];
   const int block = SCHED == kTileBlock ? TW * TH : 64;
   const int items = (int)c->total_tiles * (SCHED == kTileBlock ? 1 : TW * TH / 64);
   const int grid = SCHED == kPerTile
                        ? items
-                       : persistent_grid(c, 3, k_blend_bwd<TW, TH, SCHED>, items, block);
-  k_blend_bwd<TW, TH, SCHED><<<grid, block, 0, c->stream>>>(
+                       : persistent_grid(c, DET ? 4 : 3, k_blend_bwd<TW, TH, SCHED, DET>, items,
+                                         block);
+  k_blend_bwd<TW, TH, SCHED, DET><<<grid, block, 0, c->stream>>>(
       items, c->tile_order, c->tile_bins + 67, (int)c->n, c->W, c->H, c->GW,
-      (int)c->tiles_per_view, c->ranges, vals, c->rec, final_T, last, dimg, c->splat_grad);
+      (int)c->tiles_per_view, c->ranges, vals, c->rec, final_T, last, dimg, c->splat_grad,
+      (unsigned long long *)c->det_acc, c->d_pairs_total + 3);
   return hipGetLastError();
+}
+
+template <int TW, int TH, int SCHED>
+hipError_t bwd_t(sgs_ctx *c, const float *final_T, const uint32_t *last, const float *dimg) {
+  return c->deterministic ? bwd_td<TW, TH, SCHED, true>(c, final_T, last, dimg)
+                          : bwd_td<TW, TH, SCHED, false>(c, final_T, last, dimg);
 }
 
 template <int TW, int TH>
@@ -640,6 +701,30 @@ __global__ void k_zero_grad(double *__restrict__ p, int64_t count, uint32_t *__r
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = 0.0;
   if (i == 0 && head) *head = 0u;
+}
+
+// Deterministic mode: clears the fixed-point accumulators (three words per
+// value) and the backward queue head.
+__global__ void k_zero_acc(unsigned long long *__restrict__ p, int64_t count,
+                           uint32_t *__restrict__ head) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0ull;
+  if (i == 0 && head) *head = 0u;
+}
+
+// Deterministic mode: per-splat sums from the accumulators,
+//   total = a2 2^64 + a1 2^32 + a0 (units of 2^-64) = hi + lo 2^-64,
+// rounded once to FP64 in a fixed way.
+__global__ void k_acc_to_grad(const unsigned long long *__restrict__ acc, int64_t count,
+                              double *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint64_t a0 = acc[3 * i], a1 = acc[3 * i + 1];
+  const int64_t a2 = (int64_t)acc[3 * i + 2];
+  const uint64_t lo = a0 + (a1 << 32);
+  const uint64_t carry = (a1 >> 32) + (lo < a0 ? 1u : 0u);
+  const int64_t hi = a2 + (int64_t)carry;
+  out[i] = (double)hi + ldexp((double)lo, -64);
 }
 
 }  // namespace
@@ -668,11 +753,20 @@ hipError_t launch_blend_bwd(sgs_ctx *c, const float *final_T, const uint32_t *la
   const int64_t words = c->vn * SGS_SGRAD;
   {
     SgsProfScope ps(c, SGS_PROF_GRAD_CLEAR);
-    k_zero_grad<<<sgs_blocks(words, 256), 256, 0, c->stream>>>(c->splat_grad, words,
-                                                                c->tile_bins + 67);
+    if (c->deterministic)
+      k_zero_acc<<<sgs_blocks(3 * words, 256), 256, 0, c->stream>>>(
+          (unsigned long long *)c->det_acc, 3 * words, c->tile_bins + 67);
+    else
+      k_zero_grad<<<sgs_blocks(words, 256), 256, 0, c->stream>>>(c->splat_grad, words,
+                                                                  c->tile_bins + 67);
   }
-  if (c->TW == 16 && c->TH == 16) return bwd_s<16, 16>(c, final_T, last, dimg);
-  if (c->TW == 8 && c->TH == 8) return bwd_s<8, 8>(c, final_T, last, dimg);
-  if (c->TW == 32 && c->TH == 8) return bwd_s<32, 8>(c, final_T, last, dimg);
-  return hipErrorInvalidValue;
+  hipError_t e = hipErrorInvalidValue;
+  if (c->TW == 16 && c->TH == 16) e = bwd_s<16, 16>(c, final_T, last, dimg);
+  if (c->TW == 8 && c->TH == 8) e = bwd_s<8, 8>(c, final_T, last, dimg);
+  if (c->TW == 32 && c->TH == 8) e = bwd_s<32, 8>(c, final_T, last, dimg);
+  if (e != hipSuccess || !c->deterministic) return e;
+  SgsProfScope ps(c, SGS_PROF_BLEND_BWD);
+  k_acc_to_grad<<<sgs_blocks(words, 256), 256, 0, c->stream>>>(
+      (const unsigned long long *)c->det_acc, words, c->splat_grad);
+  return hipGetLastError();
 }

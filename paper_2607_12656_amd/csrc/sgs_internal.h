@@ -49,8 +49,10 @@ struct sgs_ctx {
   int64_t tiles_per_view = 0, total_tiles = 0;
   float tau = 1.0f;
   int schedule = 0;               // blend launch schedule (sgs_options.schedule)
-  int blend_occ[4] = {0, 0, 0, 0}; // resident blend workgroups (fwd, fwd counting in-span,
-                                   // fwd counting reach-kept, bwd); 0 unknown
+  int blend_occ[5] = {0, 0, 0, 0, 0}; // resident blend workgroups (fwd, fwd counting in-span,
+                                   // fwd counting reach-kept, bwd, bwd deterministic); 0 unknown
+  bool deterministic = false;     // sgs_options.deterministic: fixed-point gradient sums
+  uint64_t *det_acc = nullptr;    // [vn][SGS_SGRAD][3] fixed-point accumulators (that mode)
   int count_mode = 0;             // sgs_set_eval_count_mode
   bool scene_set = false;
   bool rendered = false;

@@ -183,7 +183,7 @@ class Formation:
         if self.given is not None:   # every survivor was kept by the given mask
             self.given = torch.ones(npad, dtype=torch.uint8, device=rd.dev)
         self.rd = RDStep(c, kept, npad, rd.n_hat, rd.cams, rd.W, rd.H, tile=rd.tile,
-                         tau=rd.tau, schedule=rd.schedule)
+                         tau=rd.tau, schedule=rd.schedule, deterministic=rd.deterministic)
         if pair_capacity > 0:
             c.reserve_pairs(pair_capacity)
         return kept

@@ -27,7 +27,7 @@ from ._lib import NCH, RATE_GRAD_FLOATS, STATS_WORDS, Context
 class RDStep:
     def __init__(self, ctx: Context, n: int, npad: int, n_hat: int, cams: np.ndarray,
                  width: int, height: int, tile=(16, 16), tau: float = 1.0,
-                 schedule: str = "tile", fused: bool = False):
+                 schedule: str = "tile", fused: bool = False, deterministic: bool = False):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -37,8 +37,9 @@ class RDStep:
         V = cams.shape[0]
         self.n, self.npad, self.n_hat, self.V, self.W, self.H = n, npad, n_hat, V, width, height
         self.cams, self.tile, self.tau, self.schedule = cams, tile, tau, schedule
+        self.deterministic = deterministic
         ctx.set_scene(n, npad, n_hat, cams, width, height, tile=tile, tau=tau,
-                      schedule=schedule)
+                      schedule=schedule, deterministic=deterministic)
         f32, u8, i32, i64 = torch.float32, torch.uint8, torch.int32, torch.int64
         e = lambda *s, dt=f32: torch.empty(*s, dtype=dt, device=dev)
         self.qparams = e(NCH, npad)
