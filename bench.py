@@ -61,22 +61,32 @@ METRIC = "RD-step ms/iter & Gaussian-pixel evals/s (fwd+bwd), learned vs plain r
 PERIOD = 16
 
 
-def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int):
+def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int, items: int = 0,
+               tiles: int = 0, st: int = 1):
     """(bound, algorithmic amount per launch, unit) of one kernel group; E is
-    the count of evaluations the blend performs (after its reach test)."""
+    the count of evaluations the blend performs (after its reach test),
+    items the (splat, super-tile) items of the binning's first level, tiles
+    and st the tile and super-tile counts."""
     pix = V * W * H
     if g == "fakequant":          # statistics and mask (the projection quantizes)
         return "hbm", n * (NCH * 4 + 1 + 1 + 4), "B"
     if g == "preprocess":
         return "hbm", n * (NCH * 4 + 1) + V * n * (48 + 12), "B"
-    if g in ("depth_sort", "scan"):
+    if g == "depth_sort":         # one read + one write of key and value
         return "hbm", V * n * 16, "B"
-    if g == "duplicate":          # pair emission + first tile-sort pass
-        return "hbm", V * n * 12 + P * 8, "B"
-    if g == "tile_sort":
-        return "hbm", P * 16, "B"
-    if g == "ranges":
-        return "hbm", P * 4, "B"
+    if g == "scan":               # binning records gathered into depth order (16 + 16),
+        # pair counts and offsets (4 + 4 + 4), super-tile records and counts (16 + 4),
+        # item offsets (4 + 4)
+        return "hbm", V * n * 72, "B"
+    if g == "duplicate":          # every pair written once (4 B); per item its depth
+        # rank (4 B) and binning record (16 B) read
+        return "hbm", P * 4 + items * 20, "B"
+    if g == "tile_sort":          # items generated and sorted by super-tile (8 B written,
+        # 16 B per further 8-bit pass), then read for the tile counts (4 + 16)
+        extra = max(0, (max(st - 1, 1).bit_length() - 1) // 8)
+        return "hbm", items * (8 + 16 * extra + 20), "B"
+    if g == "ranges":             # tile counts read, offsets and ranges written
+        return "hbm", tiles * 16, "B"
     if g == "blend_fwd":
         return "alu", E * FLOP_PER_EVAL_FWD, "FLOP"
     if g == "l1":
@@ -96,8 +106,8 @@ def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int):
     return "hbm", 0, "B"
 
 
-def roofline(g, ms, n, V, P, E, W, H, traffic_key=None):
-    bound, amount, unit = group_work(g, n, V, P, E, W, H)
+def roofline(g, ms, n, V, P, E, W, H, traffic_key=None, items=0, tiles=0, st=1):
+    bound, amount, unit = group_work(g, n, V, P, E, W, H, items, tiles, st)
     dur = ms * 1e-3
     if unit == "B":
         achieved, peak, ru = amount / dur / 1e9, HBM_PEAK_GBS, "GB/s"
@@ -130,6 +140,12 @@ def traffic_for(key):
     if h.hexdigest()[:16] != ent["kernel_sha256_16"]:
         return None
     return ent["bytes_per_launch"], ent["source"] + " (profiles/hbm_traffic_*.md)"
+
+
+def geometry(sc, tile):
+    """Tile and super-tile (8x8 tiles) counts of the scene's views."""
+    gw, gh = -(-sc.width // tile[0]), -(-sc.height // tile[1])
+    return {"tiles": sc.views * gw * gh, "st": sc.views * (-(-gw // 8)) * (-(-gh // 8))}
 
 
 def host_info():
@@ -336,6 +352,7 @@ def bench_formation(args, sc, ctx, stream, dev, t):
         prof = ctx.profile_read()
         ctx.profile_enable(False)
         pairs, _ = ctx.query()
+        items = ctx.query_items()
         bits, kept, e_plain, e_learn = f.rate_errors()
         for g in graphs:
             g.close()
@@ -344,6 +361,7 @@ def bench_formation(args, sc, ctx, stream, dev, t):
         runs[name] = {"ms_per_step": round(dt * 1e3 / K, 4), "value": round(E / dt, 1),
                       "eager_ms_per_step": round(dt_eager * 1e3 / K, 4),
                       "evals": E, "evals_after_reach_test": Er, "pairs_last": pairs,
+                      "items_last": items,
                       "kept_last": kept, "coder_bits_last": bits,
                       "plain_proxy_error": round(e_plain, 4),
                       "learned_error": None if e_learn is None else round(e_learn, 4),
@@ -393,13 +411,15 @@ def bench_formation(args, sc, ctx, stream, dev, t):
     ctx.query()
 
     L = runs["learned"]
+    geo = geometry(sc, tile)
     dom = max(L["kernel_ms"], key=L["kernel_ms"].get)
     roof = roofline(dom, L["kernel_ms"][dom], sc.n, sc.views, L["pairs_last"],
                     L["evals_after_reach_test"] // K, sc.width, sc.height,
-                    traffic_key=f"c5:{dom}")
-    blend = {g: roofline(g, L["kernel_ms"][g], sc.n, sc.views, L["pairs_last"],
-                         L["evals_after_reach_test"] // K, sc.width, sc.height)
-             for g in ("blend_fwd", "blend_bwd") if g in L["kernel_ms"]}
+                    traffic_key=f"c5:{dom}", items=L["items_last"], **geo)
+    groups = {g: roofline(g, ms, sc.n, sc.views, L["pairs_last"],
+                          L["evals_after_reach_test"] // K, sc.width, sc.height,
+                          items=L["items_last"], **geo)
+              for g, ms in L["kernel_ms"].items()}
     line = {
         "metric": METRIC, "value": L["value"], "unit": "Gaussian-pixel evals/s", "n_gpus": 1,
         "steps": K, "warmup": W, "ms_per_step": L["ms_per_step"], "higher_is_better": True,
@@ -420,7 +440,8 @@ def bench_formation(args, sc, ctx, stream, dev, t):
                   "replays between two synchronizations; evaluation counts and kernel times "
                   "from re-runs of the same K iterations from the same state",
         "roofline": roof,
-        "blend_roofline": blend,
+        "group_roofline": {g: {k: r[k] for k in ("bound", "achieved", "unit", "frac")}
+                           for g, r in groups.items()},
         "learned": L, "plain": runs["plain"],
         "learned_over_plain_time": round(L["ms_per_step"] / runs["plain"]["ms_per_step"], 4),
         "rd_step_graph_ms": rd_only,
@@ -493,11 +514,14 @@ def bench_rd(args, sc, ctx, stream, dev, t, extras: bool, tile, schedule, tune=N
     gms = (time.perf_counter() - t0) * 1e3 / steps
     ctx.query()
     graph.close()
+    items = ctx.query_items()
+    geo = geometry(sc, tile)
     dom = max(kernels, key=kernels.get)
     roof = roofline(dom, kernels[dom], sc.n, sc.views, P, Er, sc.width, sc.height,
-                    traffic_key=f"{args.workload if args.workload != 'c5' else 'c2'}:{dom}")
-    blend = {g: roofline(g, kernels[g], sc.n, sc.views, P, Er, sc.width, sc.height)
-             for g in ("blend_fwd", "blend_bwd") if g in kernels}
+                    traffic_key=f"{args.workload if args.workload != 'c5' else 'c2'}:{dom}",
+                    items=items, **geo)
+    groups = {g: roofline(g, ms, sc.n, sc.views, P, Er, sc.width, sc.height, items=items, **geo)
+              for g, ms in kernels.items()}
     line = {
         "metric": METRIC, "value": round(E / (gms * 1e-3), 1), "unit": "Gaussian-pixel evals/s",
         "ms_per_step": round(gms, 4),
@@ -506,8 +530,12 @@ def bench_rd(args, sc, ctx, stream, dev, t, extras: bool, tile, schedule, tune=N
                                f"tile {tile[0]}x{tile[1]}",
                    "gaussians": sc.n, "views": sc.views, "width": sc.width,
                    "height": sc.height, "tile": f"{tile[0]}x{tile[1]}", "schedule": schedule,
-                   "pairs": P, "evals_per_step": E, "evals_after_reach_test": Er},
-        "roofline": roof, "blend_roofline": blend, "kernel_ms": kernels,
+                   "pairs": P, "items": items, "evals_per_step": E,
+                   "evals_after_reach_test": Er},
+        "roofline": roof,
+        "group_roofline": {g: {k: r[k] for k in ("bound", "achieved", "unit", "frac")}
+                           for g, r in groups.items()},
+        "kernel_ms": kernels,
         "timing": "HIP-graph replays of the whole step; eager_ms_per_step: the same calls "
                   "enqueued by the host each step (no profiling); kernel_ms: HIP events on "
                   "the library's stream in a separate run",

@@ -244,6 +244,11 @@ sgs_status sgs_set_eval_count_mode(sgs_ctx *ctx, int32_t mode);
 sgs_status sgs_query(sgs_ctx *ctx, const uint64_t *stats, int64_t *pairs_last,
                      uint64_t *flags);
 
+/* Host-side query (synchronizes the stream): the (splat, super-tile) items
+ * of the last render: a splat yields one item per 8x8-tile super-tile its
+ * tile rectangle meets (the first level of the tile binning). */
+sgs_status sgs_query_items(sgs_ctx *ctx, int64_t *items);
+
 /* Fix the (tile, Gaussian) pair capacity (allocating it now; 0 returns to
  * the default mode).  With a fixed capacity sgs_render_fwd never
  * synchronizes: the pair count stays on the device, grids are sized by the
@@ -489,10 +494,10 @@ enum {
   SGS_PROF_RATE = 1,       /* a3 rate proxy */
   SGS_PROF_PREPROCESS = 2, /* a4 projection */
   SGS_PROF_DEPTH_SORT = 3, /* a6 depth radix sort of the splats */
-  SGS_PROF_SCAN = 4,       /* a5 pair offsets */
-  SGS_PROF_DUPLICATE = 5,  /* a5 pair emission */
-  SGS_PROF_TILE_SORT = 6,  /* a6 stable tile radix sort of the pairs */
-  SGS_PROF_RANGES = 7,     /* a7 tile ranges */
+  SGS_PROF_SCAN = 4,       /* a5 pair and super-tile item offsets */
+  SGS_PROF_DUPLICATE = 5,  /* a5 pair emission: every pair written at its place */
+  SGS_PROF_TILE_SORT = 6,  /* a6 super-tile items sorted, per-tile pair counts */
+  SGS_PROF_RANGES = 7,     /* a7 tile offsets and ranges */
   SGS_PROF_BLEND_FWD = 8,  /* a8 */
   SGS_PROF_L1 = 9,         /* a9 */
   SGS_PROF_GRAD_CLEAR = 10,/* a10 clearing of the splat-gradient accumulators */

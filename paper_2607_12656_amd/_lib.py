@@ -79,6 +79,7 @@ _SIGS = {
     "sgs_quant_render_bwd": [P, P, P, P, I32, P, P, P, P, P, P, P, P, P],
     "sgs_query": [P, P, C.POINTER(I64), C.POINTER(U64)],
     "sgs_set_eval_count_mode": [P, I32],
+    "sgs_query_items": [P, C.POINTER(I64)],
     "sgs_autotune": [P, P, P, P, P, I32, P, P],
     "sgs_copy_structure": [P, P, P, I64, P, P, P, P],
     "sgs_copy_splat_grads": [P, P],
@@ -283,6 +284,12 @@ class Context:
         self.tile = (opt.tile_w, opt.tile_h)
         self.schedule = names[opt.schedule]
         return self.tile, self.schedule, [float(v) for v in ms]
+
+    def query_items(self) -> int:
+        """(splat, super-tile) items of the last render (synchronizes)."""
+        v = C.c_int64(0)
+        self._check(self.L.sgs_query_items(self.h, C.byref(v)), self.h)
+        return int(v.value)
 
     def set_eval_count_mode(self, mode: int):
         """0: the method's in-span evaluations (default); 1: the evaluations

@@ -57,6 +57,14 @@ void free_scene(sgs_ctx *c) {
   }
   dfree(c->touched);
   dfree(c->offsets);
+  dfree(c->ioffsets);
+  dfree(c->st_ranges);
+  dfree(c->chunk_first);
+  dfree(c->l2_cnt);
+  dfree(c->l2_wcnt);
+  c->l2_chunks = 0;
+  dfree(c->tile_cnt);
+  dfree(c->tile_start);
   dfree(c->bin_rec);
   dfree(c->bin_splat);
   dfree(c->mlp_f);
@@ -97,6 +105,9 @@ hipError_t grow_pairs(sgs_ctx *c, int64_t P) {
   }
   dfree(c->blk_start);
   c->blk_start_words = 0;
+  dfree(c->l2_cnt);
+  dfree(c->l2_wcnt);
+  c->l2_chunks = 0;
   c->pair_cap = 0;
   for (int k = 0; k < 2; ++k) {
     hipError_t e = dalloc(&c->tile_key[k], cap);
@@ -108,6 +119,12 @@ hipError_t grow_pairs(sgs_ctx *c, int64_t P) {
   hipError_t eb = dalloc(&c->blk_start, nbs);
   if (eb != hipSuccess) return eb;
   c->blk_start_words = nbs;
+  const int64_t chunks = l2_chunks_for(cap, c->total_st);
+  eb = dalloc(&c->l2_cnt, chunks * 64);
+  if (eb != hipSuccess) return eb;
+  eb = dalloc(&c->l2_wcnt, chunks * 4 * 64);
+  if (eb != hipSuccess) return eb;
+  c->l2_chunks = chunks;
   const int64_t hist = radix_hist_words(cap);
   hipError_t e = ensure_tmp(c, c->scan_tmp_words, hist);
   if (e != hipSuccess) return e;
@@ -129,12 +146,12 @@ sgs_status sgs_create(sgs_ctx **out, int device, void *hip_stream) {
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
   if (hipSetDevice(device) != hipSuccess ||
-      hipHostMalloc((void **)&c->h_pairs_total, 2 * sizeof(uint32_t), hipHostMallocDefault) !=
+      hipHostMalloc((void **)&c->h_pairs_total, 8 * sizeof(uint32_t), hipHostMallocDefault) !=
           hipSuccess) {
     delete c;
     return SGS_EHIP;
   }
-  c->h_aux = c->h_pairs_total + 1;
+  c->h_aux = c->h_pairs_total + 7;
   // the allocation-free training step's workspace: its device address on
   // this device, resolved once per device with the device current
   hipError_t se = hipSuccess;
@@ -216,6 +233,14 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   c->GH = (height + th - 1) / th;
   c->tiles_per_view = (int64_t)c->GW * c->GH;
   c->total_tiles = c->tiles_per_view * views;
+  c->SGW = (c->GW + 7) / 8;
+  c->SGH = (c->GH + 7) / 8;
+  c->st_per_view = (int64_t)c->SGW * c->SGH;
+  c->total_st = c->st_per_view * views;
+  if (c->total_st > 65536)
+    return fail(c, SGS_ECAPACITY,
+                "set_scene: views x super-tiles (8x8 tiles) must not exceed 65536 (%lld)",
+                (long long)c->total_st);
   c->vn = (int64_t)views * n;
   const int64_t vn = c->vn;
   hipError_t e = hipSuccess;
@@ -232,6 +257,11 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   }
   SGS_ALLOC(c->touched, vn);
   SGS_ALLOC(c->offsets, vn + 1);
+  SGS_ALLOC(c->ioffsets, vn + 1);
+  SGS_ALLOC(c->st_ranges, c->total_st);
+  SGS_ALLOC(c->chunk_first, c->total_st + 1);
+  SGS_ALLOC(c->tile_cnt, c->total_tiles);
+  SGS_ALLOC(c->tile_start, c->total_tiles + 1);
   SGS_ALLOC(c->bin_rec, vn);
   SGS_ALLOC(c->bin_splat, vn);
   SGS_ALLOC(c->mlp_f, n);
@@ -244,8 +274,8 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   SGS_ALLOC(c->tile_order, c->total_tiles);
   SGS_ALLOC(c->tile_bins, SGS_TILE_BINS);
   SGS_ALLOC(c->eval_slots, SGS_EVAL_SLOTS);
-  SGS_ALLOC(c->d_pairs_total, 4);
-  e = hipMemset(c->d_pairs_total, 0, 4 * sizeof(uint32_t));
+  SGS_ALLOC(c->d_pairs_total, 8);
+  e = hipMemset(c->d_pairs_total, 0, 8 * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMemset(c->eval_slots, 0, SGS_EVAL_SLOTS * sizeof(uint64_t));
   if (e != hipSuccess) { free_scene(c); return hip_fail(c, e, "set_scene clear"); }
   c->fixed_cap = false;
@@ -263,7 +293,8 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   SGS_ALLOC(c->lap_coef, 192);
 #undef SGS_ALLOC
   const int64_t hist = radix_hist_words(vn);
-  const int64_t scan = (vn + 4095) / 4096 + 1;
+  // block sums of the scans over splats and over tiles
+  const int64_t scan = ((vn > c->total_tiles ? vn : c->total_tiles) + 4095) / 4096 + 1;
   e = ensure_tmp(c, scan, hist);
   if (e != hipSuccess) { free_scene(c); return hip_fail(c, e, "set_scene alloc"); }
   // initial pair capacity: 4 tiles per splat
@@ -313,11 +344,12 @@ static sgs_status render_after_projection(sgs_ctx *c, float *image, float *final
                                           uint32_t *last, uint64_t *eval_count) {
   SGS_HIP(launch_depth_order(c), "render_fwd depth order");
   if (!c->fixed_cap) {
-    SGS_HIP(hipMemcpyAsync(c->h_pairs_total, c->d_pairs_total, sizeof(uint32_t),
+    SGS_HIP(hipMemcpyAsync(c->h_pairs_total, c->d_pairs_total, 5 * sizeof(uint32_t),
                            hipMemcpyDeviceToHost, c->stream),
             "render_fwd pair count");
     SGS_HIP(hipStreamSynchronize(c->stream), "render_fwd pair count");
-    c->pairs = *c->h_pairs_total;
+    c->pairs = c->h_pairs_total[0];
+    c->items = c->h_pairs_total[4];
     if (c->pairs == (int64_t)kPairsSaturated)
       return fail(c, SGS_ECAPACITY, "render_fwd: 2^32 - 1 or more (tile, Gaussian) pairs");
     hipError_t e = grow_pairs(c, c->pairs);
@@ -698,6 +730,20 @@ sgs_status sgs_autotune(sgs_ctx *c, const float *params, const float *qstep,
   return SGS_OK;
 }
 
+sgs_status sgs_query_items(sgs_ctx *c, int64_t *items) {
+  if (!c || !items) return SGS_EINVAL;
+  SGS_HIP(hipSetDevice(c->device), "hipSetDevice");
+  SGS_HIP(hipStreamSynchronize(c->stream), "query sync");
+  if (c->fixed_cap && c->d_pairs_total) {
+    uint32_t v = 0;
+    SGS_HIP(hipMemcpy(&v, c->d_pairs_total + 4, sizeof(v), hipMemcpyDeviceToHost), "query items");
+    *items = v;
+  } else {
+    *items = c->items;
+  }
+  return SGS_OK;
+}
+
 sgs_status sgs_set_eval_count_mode(sgs_ctx *c, int32_t mode) {
   if (!c) return SGS_EINVAL;
   if (mode != 0 && mode != 1) return fail(c, SGS_EINVAL, "set_eval_count_mode: mode must be 0 or 1");
@@ -1006,6 +1052,12 @@ __global__ void k_export(int64_t vn, const float4 *__restrict__ rec,
   }
 }
 
+// out[p] = t for every position p of tile t's range (one workgroup per tile)
+__global__ void k_fill_tile_ids(const uint2 *__restrict__ ranges, uint32_t *__restrict__ out) {
+  const uint2 r = ranges[blockIdx.x];
+  for (uint32_t p = r.x + threadIdx.x; p < r.y; p += blockDim.x) out[p] = blockIdx.x;
+}
+
 // depth keys in splat order: scatter the sorted (key, index) pairs back
 __global__ void k_export_depth(int64_t vn, const uint32_t *__restrict__ skey,
                                const uint32_t *__restrict__ sval, float *__restrict__ depth) {
@@ -1024,9 +1076,11 @@ extern "C" sgs_status sgs_copy_structure(sgs_ctx *c, uint32_t *tile_ids, uint32_
   if (!c->rendered) return fail(c, SGS_ESTATE, "copy_structure: render_fwd first");
   const int64_t P = c->pairs;
   if ((tile_ids || vals) && cap < P) return fail(c, SGS_ECAPACITY, "copy_structure: cap < pairs");
-  if (tile_ids && P)
-    SGS_HIP(hipMemcpyAsync(tile_ids, c->tile_key[c->pair_sorted_buf], 4 * P,
-                           hipMemcpyDeviceToDevice, c->stream), "copy tile ids");
+  if (tile_ids && P) {
+    // the tile id of every sorted pair, from the tile ranges
+    k_fill_tile_ids<<<(unsigned)c->total_tiles, 256, 0, c->stream>>>(c->ranges, tile_ids);
+    SGS_HIP(hipGetLastError(), "copy tile ids");
+  }
   if (vals && P)
     SGS_HIP(hipMemcpyAsync(vals, c->pair_val[c->pair_sorted_buf], 4 * P,
                            hipMemcpyDeviceToDevice, c->stream), "copy vals");

@@ -71,6 +71,19 @@ struct sgs_ctx {
   double *splat_grad = nullptr;   // [vn][SGS_SGRAD] per-splat gradient sums (FP64 atomics)
   int depth_sorted_buf = 0;       // which depth buffer holds the sorted order
 
+  // super-tiles (8x8 tiles): the first level of the tile binning
+  int SGW = 0, SGH = 0;           // super-tiles per view row / column
+  int64_t st_per_view = 0, total_st = 0;
+  int64_t items = 0;              // (splat, super-tile) items of the last render (host copy)
+  uint32_t *ioffsets = nullptr;   // [vn + 1] exclusive scan of the item counts, depth order
+  uint2 *st_ranges = nullptr;     // [total_st] item range of every super-tile
+  uint32_t *chunk_first = nullptr;  // [total_st + 1] first item chunk of every super-tile
+  uint32_t *l2_cnt = nullptr;     // [chunks][64] per-chunk tile counts, then offsets
+  uint16_t *l2_wcnt = nullptr;    // [chunks][4][64] per-wave tile counts of every chunk
+  int64_t l2_chunks = 0;          // chunks l2_cnt holds
+  uint32_t *tile_cnt = nullptr;   // [total_tiles] pairs per tile
+  uint32_t *tile_start = nullptr; // [total_tiles + 1] exclusive scan of tile_cnt
+
   // pairs
   int64_t pair_cap = 0;
   int64_t pairs = 0;
@@ -97,8 +110,10 @@ struct sgs_ctx {
   float *mlp_f = nullptr;         // [n] f of the last learned-rate forward
   uint4 *mlp_signs = nullptr;     // [2n] its hidden activation signs (two lanes per row)
   bool mlp_saved = false;         // a learned-rate forward ran since set_scene
-  uint32_t *d_pairs_total = nullptr;  // [0] pair count, [1] count clamped to capacity, [2] overflow
-  uint32_t *h_pairs_total = nullptr;  // pinned host mirror
+  uint32_t *d_pairs_total = nullptr;  // [0] pair count, [1] count clamped to capacity, [2]
+                                      // overflow, [3] deterministic range flag, [4] item
+                                      // count, [5] item count clamped to capacity, [6] unused
+  uint32_t *h_pairs_total = nullptr;  // pinned host mirror of words [0, 5)
   uint32_t *h_aux = nullptr;          // pinned host word (kept count of a compaction)
   bool fixed_cap = false;             // pair capacity fixed by the caller: no host sync per step
   int64_t cap_limit = 0;              // the reserved capacity (buffers may be larger)
@@ -185,6 +200,7 @@ hipError_t ensure_tmp(sgs_ctx *c, int64_t scan_words, int64_t hist_words);
 // offsets are then meaningless and no pair is emitted).
 constexpr uint32_t kPairsSaturated = 0xFFFFFFFFu;
 int64_t radix_blocks(int64_t count);       // blocks of a radix pass over count elements
+int64_t l2_chunks_for(int64_t cap, int64_t total_st);  // level-2 chunks for a pair capacity
 int64_t radix_hist_words(int64_t count);   // sort_hist words a radix sort of count needs
 // Exclusive scan of count words into out[0..count] (out[count] = total); the
 // total also to *total_out; with cap >= 0 total_out[1] = min(total, cap) and

@@ -1,13 +1,23 @@
 // Tile binning and the (tile, depth) order (paper Sec. 3.1: tile-based
 // rasterization of depth-sorted Gaussians).
 //
-// Instead of one radix sort over 64-bit (tile | depth) keys of every pair,
-// the splats are sorted by depth once (V*N keys, 32 bits), their pairs are
-// emitted in that order, and the pairs are then stably sorted by tile id
-// alone (ceil(log2(V*tiles)) bits, two 8-bit passes at the measured sizes).
-// Stability makes the result identical to the (tile, depth, index) order,
-// and the pair array -- ten times larger than the splat array -- crosses
-// HBM two times per pass for two passes instead of six.
+// The splats are sorted by depth once (V*N keys, 32 bits).  The pairs are
+// then ordered in two levels instead of by a radix sort over every pair:
+//  1. items: each splat, in depth order, yields one item per super-tile
+//     (8x8 tiles) its tile rectangle meets; the items are stably sorted by
+//     super-tile id (generated on the fly in the first radix pass), so each
+//     super-tile's items stay in depth order;
+//  2. each super-tile's items are cut into chunks of 1024; a chunk's
+//     workgroup turns every item into a 64-bit mask of the super-tile's tiles
+//     it covers, counts the pairs per tile (one ballot per tile bit), and,
+//     once the per-tile counts are scanned into tile offsets, writes every
+//     pair's Gaussian index straight to its final position: its tile's
+//     offset, plus the tile's pairs in earlier chunks, earlier waves and
+//     earlier lanes (ranks from the same ballots).
+// The pairs come out in (tile, depth, index) order, exactly the order of a
+// stable sort by tile of the depth-ordered pairs, and the tile ranges come
+// from the tile offsets.  At 3M Gaussians x 8 views the items number about a
+// fourteenth of the pairs, and each pair crosses HBM once (its final write).
 #include "sgs_internal.h"
 
 namespace {
@@ -649,6 +659,325 @@ k_ranges_search(const uint32_t *__restrict__ tile_key, int64_t P_static,
   ranges[t] = lo0 < lo1 ? make_uint2((uint32_t)lo0, (uint32_t)lo1) : make_uint2(0u, 0u);
 }
 
+// ---------------------------------------------------------------------------
+// Level 1: super-tile items
+// ---------------------------------------------------------------------------
+// An item's key: the global super-tile id in bits [0, 16) (at most 65536
+// super-tiles; the sort's 8-bit digits stay inside these bits) and, riding
+// along above bit 20, the covered tile rectangle inside the super-tile:
+// first and last column and row, 3 bits each.
+constexpr int kStBits = 20;
+constexpr uint32_t kStMask = (1u << kStBits) - 1u;
+
+// The tile rectangle of a binning record (first tile id, width in tiles,
+// Gaussian, pairs) as columns [tx0, tx1] and rows [ty0, ty1] of its view.
+struct TileRect {
+  uint32_t v;
+  int tx0, tx1, ty0, ty1;
+};
+__device__ __forceinline__ TileRect tile_rect(const uint4 &b, uint32_t tiles_per_view, int GW) {
+  TileRect r;
+  r.v = b.x / tiles_per_view;
+  const uint32_t t = b.x - r.v * tiles_per_view;
+  r.ty0 = (int)(t / (uint32_t)GW);
+  r.tx0 = (int)(t - (uint32_t)r.ty0 * (uint32_t)GW);
+  r.tx1 = r.tx0 + (int)b.y - 1;
+  r.ty1 = r.ty0 + (int)(b.w / b.y) - 1;
+  return r;
+}
+
+// Items per splat (depth order): the 8x8-tile super-tiles its tile
+// rectangle meets.
+__global__ void k_item_counts(const uint4 *__restrict__ brec, int64_t vn, int GW,
+                              uint32_t tiles_per_view, uint32_t *__restrict__ cnt) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= vn) return;
+  const uint4 b = brec[d];
+  if (b.w == 0) {
+    cnt[d] = 0;
+    return;
+  }
+  const TileRect r = tile_rect(b, tiles_per_view, GW);
+  cnt[d] = (uint32_t)(((r.tx1 >> 3) - (r.tx0 >> 3) + 1) * ((r.ty1 >> 3) - (r.ty0 >> 3) + 1));
+}
+
+// The items of every splat, in depth order, at its item offset: key =
+// super-tile id | covered tile rectangle inside it (see kStBits), value =
+// Gaussian index.  Items at or beyond the live item count (a capacity) are
+// not written.
+__global__ void k_emit_items(const uint4 *__restrict__ brec, const uint32_t *__restrict__ ioff,
+                             int64_t vn, int64_t count_static, const uint32_t *__restrict__ dcount,
+                             int GW, uint32_t tiles_per_view, int SGW, uint32_t st_per_view,
+                             uint32_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= vn) return;
+  const uint4 b = brec[d];
+  if (b.w == 0) return;
+  const int64_t count = dcount ? (int64_t)*dcount : count_static;
+  int64_t o = ioff[d];
+  const TileRect r = tile_rect(b, tiles_per_view, GW);
+  for (int sy = r.ty0 >> 3; sy <= (r.ty1 >> 3); ++sy)
+    for (int sx = r.tx0 >> 3; sx <= (r.tx1 >> 3); ++sx, ++o) {
+      if (o >= count) return;
+      const uint32_t cx0 = (uint32_t)max(r.tx0 - 8 * sx, 0), cx1 = (uint32_t)min(r.tx1 - 8 * sx, 7);
+      const uint32_t cy0 = (uint32_t)max(r.ty0 - 8 * sy, 0), cy1 = (uint32_t)min(r.ty1 - 8 * sy, 7);
+      kout[o] = (r.v * st_per_view + (uint32_t)sy * (uint32_t)SGW + (uint32_t)sx) |
+                (cx0 << kStBits) | (cx1 << (kStBits + 3)) | (cy0 << (kStBits + 6)) |
+                (cy1 << (kStBits + 9));
+      vout[o] = b.z;
+    }
+}
+
+// Item range of every super-tile: binary search of the sorted items on the
+// super-tile bits of their keys (lower bounds of g and g + 1 over [0, I)).
+__global__ void __launch_bounds__(256)
+k_st_ranges(const uint32_t *__restrict__ key, int64_t I_static, const uint32_t *__restrict__ dcount,
+            uint32_t nst, uint2 *__restrict__ ranges) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nst) return;
+  const int64_t I = dcount ? (int64_t)*dcount : I_static;
+  const uint32_t k0 = (uint32_t)g, k1 = (uint32_t)g + 1u;
+  int64_t lo0 = 0, hi0 = I, lo1 = 0, hi1 = I;
+  while (lo0 < hi0 || lo1 < hi1) {
+    const int64_t m0 = (lo0 + hi0) >> 1, m1 = (lo1 + hi1) >> 1;
+    const uint32_t v0 = lo0 < hi0 ? key[m0] & kStMask : 0u;
+    const uint32_t v1 = lo1 < hi1 ? key[m1] & kStMask : 0u;
+    if (lo0 < hi0) {
+      if (v0 < k0) lo0 = m0 + 1; else hi0 = m0;
+    }
+    if (lo1 < hi1) {
+      if (v1 < k1) lo1 = m1 + 1; else hi1 = m1;
+    }
+  }
+  ranges[g] = lo0 < lo1 ? make_uint2((uint32_t)lo0, (uint32_t)lo1) : make_uint2(0u, 0u);
+}
+
+// ---------------------------------------------------------------------------
+// Level 2: tiles inside a super-tile
+// ---------------------------------------------------------------------------
+constexpr int kL2Items = 1024;  // items per chunk: 4 waves x 4 rounds x 64 lanes
+
+// chunk_first[g] = sum over super-tiles g' < g of ceil(items / kL2Items);
+// chunk_first[nst] = the number of chunks (one workgroup).
+__global__ void __launch_bounds__(kThreads)
+k_st_chunks(const uint2 *__restrict__ st_ranges, int64_t nst, uint32_t *__restrict__ first) {
+  __shared__ uint32_t s_wave[kWaves];
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nst; b0 += kThreads) {
+    const int64_t g = b0 + threadIdx.x;
+    uint32_t v = 0;
+    if (g < nst) {
+      const uint2 r = st_ranges[g];
+      v = (r.y - r.x + kL2Items - 1) / kL2Items;
+    }
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan(v, s_wave, total);
+    if (g < nst) first[g] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) first[nst] = carry;
+}
+
+// The super-tile of chunk q: the last g with first[g] <= q (q < first[nst]).
+__device__ __forceinline__ uint32_t chunk_super(const uint32_t *__restrict__ first, uint32_t nst,
+                                                uint32_t q) {
+  uint32_t lo = 0, hi = nst;
+  while (hi - lo > 1) {
+    const uint32_t m = (lo + hi) >> 1;
+    if (first[m] <= q) lo = m; else hi = m;
+  }
+  return lo;
+}
+
+// Bit 8 row + column for every tile of the super-tile that the item with
+// this key covers (its rectangle rides in the key's high bits): the row's
+// bits repeated in every row, cut to the covered rows.
+__device__ __forceinline__ uint64_t item_mask(uint32_t key) {
+  const uint32_t cx0 = (key >> kStBits) & 7u, cx1 = (key >> (kStBits + 3)) & 7u;
+  const uint32_t cy0 = (key >> (kStBits + 6)) & 7u, cy1 = (key >> (kStBits + 9)) & 7u;
+  const uint64_t row = (uint64_t)((0xFFu >> (7u - (cx1 - cx0))) << cx0);
+  const uint64_t rows = (~0ull >> (8u * (7u - cy1))) & (~0ull << (8u * cy0));
+  return (row * 0x0101010101010101ull) & rows;
+}
+
+// 64 x 64 bit transpose over the wave: lane L holds row L (bit t set when
+// item L covers tile t); afterwards lane t holds column t (bit L set when
+// item L covers tile t).  Six butterfly stages: lanes L and L ^ s exchange
+// the blocks of s bits that belong to the other one.
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t r, int lane) {
+  const uint64_t M[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                         0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int s = 32 >> k;
+    const uint64_t m = M[k];
+    const uint32_t olo = (uint32_t)__shfl_xor((int)(uint32_t)r, s, 64);
+    const uint32_t ohi = (uint32_t)__shfl_xor((int)(uint32_t)(r >> 32), s, 64);
+    const uint64_t o = ((uint64_t)ohi << 32) | olo;
+    r = (lane & s) ? ((r & ~m) | ((o & ~m) >> s)) : ((r & m) | ((o & m) << s));
+  }
+  return r;
+}
+
+// The chunk's items: masks and Gaussian indices, four rounds per wave
+// (item first + 256 wave + 64 round + lane, in item order).
+struct Chunk {
+  uint32_t g, first, end;
+  int tx_base, ty_base;
+  uint32_t view;
+};
+
+__device__ __forceinline__ bool chunk_of(uint32_t q, const uint32_t *__restrict__ cfirst,
+                                         uint32_t nst, const uint2 *__restrict__ st_ranges,
+                                         int SGW, uint32_t st_per_view, Chunk &ch) {
+  if (q >= cfirst[nst]) return false;
+  ch.g = chunk_super(cfirst, nst, q);
+  const uint2 r = st_ranges[ch.g];
+  ch.first = r.x + (q - cfirst[ch.g]) * (uint32_t)kL2Items;
+  ch.end = r.y;
+  ch.view = ch.g / st_per_view;
+  const uint32_t gs = ch.g - ch.view * st_per_view;
+  const uint32_t sy = gs / (uint32_t)SGW;
+  ch.ty_base = 8 * (int)sy;
+  ch.tx_base = 8 * (int)(gs - sy * (uint32_t)SGW);
+  return true;
+}
+
+// Per-chunk pair counts of the 64 tiles: cnt[q][t].
+__global__ void __launch_bounds__(kThreads)
+k_l2_count(const uint32_t *__restrict__ cfirst, uint32_t nst, const uint2 *__restrict__ st_ranges,
+           const uint32_t *__restrict__ ikey, int SGW, uint32_t st_per_view,
+           uint32_t *__restrict__ cnt, uint16_t *__restrict__ wcnt) {
+  __shared__ uint32_t s_w[kWaves][64];
+  Chunk ch;
+  if (!chunk_of(blockIdx.x, cfirst, nst, st_ranges, SGW, st_per_view, ch)) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t acc = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t idx = ch.first + (uint32_t)(wave * 256 + r * 64 + lane);
+    const uint64_t m = idx < ch.end ? item_mask(ikey[idx]) : 0ull;
+    // lane t: the round's items covering tile t
+    acc += (uint32_t)__popcll(wave_transpose64(m, lane));
+  }
+  // a wave's count of one tile is at most its 256 items
+  wcnt[((int64_t)blockIdx.x * kWaves + wave) * 64 + lane] = (uint16_t)acc;
+  s_w[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0)
+    cnt[(int64_t)blockIdx.x * 64 + lane] = s_w[0][lane] + s_w[1][lane] + s_w[2][lane] + s_w[3][lane];
+}
+
+// Per super-tile (64 threads, thread t = tile t): the chunk counts become the
+// tile's pairs in earlier chunks (in place), and the tile's total goes to
+// tile_cnt (tiles past the image edge have no pairs and no entry).
+__global__ void __launch_bounds__(64)
+k_l2_scan(const uint32_t *__restrict__ cfirst, uint32_t *__restrict__ cnt, int GW, int GH,
+          int SGW, uint32_t st_per_view, uint32_t tiles_per_view, uint32_t *__restrict__ tile_cnt) {
+  const uint32_t g = blockIdx.x;
+  const int t = threadIdx.x;
+  const uint32_t q0 = cfirst[g], q1 = cfirst[g + 1];
+  uint32_t run = 0;
+  for (uint32_t qb = q0; qb < q1; qb += 32) {
+    uint32_t c[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) c[k] = qb + k < q1 ? cnt[(int64_t)(qb + k) * 64 + t] : 0u;
+#pragma unroll
+    for (int k = 0; k < 32; ++k)
+      if (qb + k < q1) {
+        cnt[(int64_t)(qb + k) * 64 + t] = run;
+        run += c[k];
+      }
+  }
+  const uint32_t v = g / st_per_view, gs = g - v * st_per_view;
+  const uint32_t sy = gs / (uint32_t)SGW, sx = gs - sy * (uint32_t)SGW;
+  const int tx = 8 * (int)sx + (t & 7), ty = 8 * (int)sy + (t >> 3);
+  if (tx < GW && ty < GH) tile_cnt[(int64_t)v * tiles_per_view + (int64_t)ty * GW + tx] = run;
+}
+
+// Tile ranges from the tile offsets, clamped to the pairs the buffer holds
+// (the pair count, or the capacity it was clamped to); empty tiles (0, 0).
+__global__ void k_l2_ranges(const uint32_t *__restrict__ tile_cnt,
+                            const uint32_t *__restrict__ tile_start, int64_t tiles,
+                            int64_t held_static, const uint32_t *__restrict__ dheld,
+                            uint2 *__restrict__ ranges) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tiles) return;
+  const int64_t held = dheld ? (int64_t)*dheld : held_static;
+  const int64_t n = tile_cnt[t];
+  const int64_t a = min((int64_t)tile_start[t], held), e = min((int64_t)tile_start[t] + n, held);
+  ranges[t] = n && a < e ? make_uint2((uint32_t)a, (uint32_t)e) : make_uint2(0u, 0u);
+}
+
+// Every pair of the chunk to its final position:
+//   tile offset + the tile's pairs in earlier chunks + in earlier waves of
+//   this chunk (counted by k_l2_count) + in earlier rounds of this wave + in
+//   earlier lanes.  Lane t of `pos` holds tile t's next position; for every
+//   tile some item of the round covers, one ballot ranks the lanes covering
+//   it and they write consecutive positions (one coalesced store).
+__device__ __forceinline__ uint32_t lane_ge(uint32_t v, int t, uint32_t x) {
+  return (int)(threadIdx.x & 63) == t ? x : v;
+}
+
+// The tiles t0 + bit (bits of the wave-uniform u) that the 32-bit half h of
+// this lane's mask covers, scattered as above.
+__device__ __forceinline__ void scatter_half(uint32_t u, uint32_t h, int t0, uint32_t gid,
+                                             uint32_t held, uint32_t &pos,
+                                             uint32_t *__restrict__ vals) {
+  while (u) {
+    const int b = __builtin_ctz(u);
+    u &= u - 1u;
+    const bool mine = (h >> b) & 1u;
+    const uint64_t bal = __ballot(mine);
+    const int t = t0 + b;
+    const uint32_t bt = (uint32_t)__builtin_amdgcn_readlane((int)pos, t);
+    if (mine) {
+      const uint32_t p = bt + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+      if (p < held) vals[p] = gid;
+    }
+    pos = lane_ge(pos, t, bt + (uint32_t)__popcll(bal));
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_l2_scatter(const uint32_t *__restrict__ cfirst, uint32_t nst,
+             const uint2 *__restrict__ st_ranges, const uint32_t *__restrict__ ikey,
+             const uint32_t *__restrict__ ival, int GW, int GH, uint32_t tiles_per_view, int SGW,
+             uint32_t st_per_view, const uint32_t *__restrict__ rel,
+             const uint16_t *__restrict__ wcnt, const uint32_t *__restrict__ tile_start,
+             int64_t held_static, const uint32_t *__restrict__ dheld,
+             uint32_t *__restrict__ vals) {
+  Chunk ch;
+  if (!chunk_of(blockIdx.x, cfirst, nst, st_ranges, SGW, st_per_view, ch)) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tx = ch.tx_base + (lane & 7), ty = ch.ty_base + (lane >> 3);
+  uint32_t pos = 0;
+  if (tx < GW && ty < GH) {
+    pos = tile_start[(int64_t)ch.view * tiles_per_view + (int64_t)ty * GW + tx] +
+          rel[(int64_t)blockIdx.x * 64 + lane];
+    for (int w = 0; w < wave; ++w) pos += wcnt[((int64_t)blockIdx.x * kWaves + w) * 64 + lane];
+  }
+  const uint32_t held = (uint32_t)(dheld ? (int64_t)*dheld : held_static);
+  uint32_t key[4], gid[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {  // all four rounds' loads in flight at once
+    const uint32_t idx = ch.first + (uint32_t)(wave * 256 + r * 64 + lane);
+    const bool ok = idx < ch.end;
+    key[r] = ok ? ikey[idx] : 0u;
+    gid[r] = ok ? ival[idx] : 0u;
+    if (!ok) key[r] = 0xFFFFFFFFu;  // no item: empty mask below
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint64_t m = key[r] == 0xFFFFFFFFu ? 0ull : item_mask(key[r]);
+    // the tiles any lane covers: the transposed masks' non-empty columns
+    const uint64_t u = __ballot(wave_transpose64(m, lane) != 0ull);
+    scatter_half((uint32_t)u, (uint32_t)m, 0, gid[r], held, pos, vals);
+    scatter_half((uint32_t)(u >> 32), (uint32_t)(m >> 32), 32, gid[r], held, pos, vals);
+  }
+}
+
 }  // namespace
 
 hipError_t ensure_tmp(sgs_ctx *c, int64_t scan_words, int64_t hist_words) {
@@ -670,6 +999,10 @@ hipError_t ensure_tmp(sgs_ctx *c, int64_t scan_words, int64_t hist_words) {
 }
 
 int64_t radix_blocks(int64_t count) { return (count + kTile - 1) / kTile; }
+
+// Chunks of kL2Items items for at most cap items over total_st super-tiles
+// (each super-tile's last chunk may be partial).
+int64_t l2_chunks_for(int64_t cap, int64_t total_st) { return cap / kL2Items + total_st + 1; }
 
 // A plain radix pass over at most kSmallSort elements takes kSmallItems per
 // thread: with 4096 per block a 1M-element sort would launch fewer blocks
@@ -786,53 +1119,68 @@ hipError_t launch_depth_order(sgs_ctx *c) {
   k_gather_bins<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(c->depth_val[which], c->bin_splat,
                                                                c->vn, tmp, c->bin_rec);
   // with a fixed pair capacity the scan also clamps the count to it
-  return launch_exclusive_scan(c, tmp, c->offsets, c->vn, c->d_pairs_total,
+  hipError_t e = launch_exclusive_scan(c, tmp, c->offsets, c->vn, c->d_pairs_total,
+                                       c->fixed_cap ? c->cap_limit : -1);
+  if (e != hipSuccess) return e;
+  // super-tile item counts (over tmp, scanned already), then their offsets
+  k_item_counts<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(c->bin_rec, c->vn, c->GW,
+                                                               (uint32_t)c->tiles_per_view, tmp);
+  return launch_exclusive_scan(c, tmp, c->ioffsets, c->vn, c->d_pairs_total + 4,
                                c->fixed_cap ? c->cap_limit : -1);
 }
 
-// Pairs -> stable tile sort -> ranges.  With a fixed pair capacity the pair
-// count never leaves the device: grids are sized by the capacity and every
-// kernel reads the live count (clamped to the capacity, overflow flagged).
+// Items -> super-tile sort -> per-super-tile tile counts -> tile offsets and
+// ranges -> pairs at their final positions.  With a fixed pair capacity the
+// counts never leave the device: grids are sized by the capacity (items and
+// chunks are bounded by it) and every kernel reads the live counts, clamped
+// to the capacity (overflow flagged by the pair scan).
 hipError_t launch_bin_pairs(sgs_ctx *c) {
   const bool dev = c->fixed_cap;
   const int64_t cap = dev ? c->cap_limit : c->pair_cap;
-  const int64_t P = dev ? cap : c->pairs;
-  const uint32_t *dcount = dev ? c->d_pairs_total + 1 : nullptr;
-  {
-    // pair emission fused with the pass over the low digit: buffer 1
-    SgsProfScope ps(c, SGS_PROF_DUPLICATE);
-    if (P > 0) {
-      SortBufs b;
-      if (!sort_bufs(c, P, b) || b.nb + 1 > c->blk_start_words) return hipErrorInvalidValue;
-      k_block_starts<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(c->offsets, c->vn, P, dcount,
-                                                                    c->blk_start);
-      k_gen_hist<<<(unsigned)b.nb, kThreads, 0, c->stream>>>(c->offsets, c->bin_rec, c->blk_start,
-                                                             c->vn, P, dcount, c->GW, b.hraw);
-      const uint32_t *dtot = launch_digit_offsets(c, b);
-      k_gen_scatter<<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
-          c->offsets, c->bin_rec, c->blk_start, c->vn, P, dcount, c->GW, b.hscan, dtot,
-          c->tile_key[1], c->pair_val[1]);
-    }
-  }
+  const int64_t P = dev ? cap : c->pairs;   // pairs the buffer holds (bound)
+  const int64_t I = dev ? cap : c->items;   // items (bound; an item has at least one pair)
+  const uint32_t *dP = dev ? c->d_pairs_total + 1 : nullptr;
+  const uint32_t *dI = dev ? c->d_pairs_total + 5 : nullptr;
+  const uint32_t tpv = (uint32_t)c->tiles_per_view, spv = (uint32_t)c->st_per_view;
+  const uint32_t nst = (uint32_t)c->total_st;
   int bits = 0;
-  while (((int64_t)1 << bits) < c->total_tiles) ++bits;
+  while (((int64_t)1 << bits) < c->total_st) ++bits;
   int which = 1;
+  const int64_t chunks = min(c->l2_chunks, l2_chunks_for(I, c->total_st));
   {
     SgsProfScope ps(c, SGS_PROF_TILE_SORT);
-    hipError_t e = launch_radix_sort(c, c->tile_key, c->pair_val, P, bits, &which, dcount, 8, 1);
+    // items in depth order (buffer 0), stably sorted by super-tile
+    if (I > 0)
+      k_emit_items<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(
+          c->bin_rec, c->ioffsets, c->vn, I, dI, c->GW, tpv, c->SGW, spv, c->tile_key[0],
+          c->pair_val[0]);
+    hipError_t e = launch_radix_sort(c, c->tile_key, c->pair_val, I, bits, &which, dI, 0, 0);
     if (e != hipSuccess) return e;
+    k_st_ranges<<<sgs_blocks(c->total_st, 256), 256, 0, c->stream>>>(c->tile_key[which], I, dI,
+                                                                     nst, c->st_ranges);
+    k_st_chunks<<<1, kThreads, 0, c->stream>>>(c->st_ranges, c->total_st, c->chunk_first);
+    if (chunks > 0)
+      k_l2_count<<<(unsigned)chunks, kThreads, 0, c->stream>>>(
+          c->chunk_first, nst, c->st_ranges, c->tile_key[which], c->SGW, spv, c->l2_cnt,
+          c->l2_wcnt);
+    k_l2_scan<<<nst, 64, 0, c->stream>>>(c->chunk_first, c->l2_cnt, c->GW, c->GH, c->SGW, spv,
+                                         tpv, c->tile_cnt);
   }
-  c->pair_sorted_buf = which;
-  SgsProfScope ps(c, SGS_PROF_RANGES);
-  if (P >= kRangeSearchMin) {
-    k_ranges_search<<<sgs_blocks(c->total_tiles, 256), 256, 0, c->stream>>>(
-        c->tile_key[which], P, dcount, (uint32_t)c->total_tiles, c->ranges);
-  } else {
-    k_zero_ranges<<<sgs_blocks(c->total_tiles, 256), 256, 0, c->stream>>>(c->ranges,
-                                                                         c->total_tiles);
-    if (P > 0)
-      k_ranges<<<sgs_blocks((P + 3) / 4, 256), 256, 0, c->stream>>>(
-          c->tile_key[which], P, dcount, (uint32_t)c->total_tiles, c->ranges);
+  {
+    SgsProfScope ps(c, SGS_PROF_RANGES);
+    hipError_t e = launch_exclusive_scan(c, c->tile_cnt, c->tile_start, c->total_tiles, nullptr);
+    if (e != hipSuccess) return e;
+    k_l2_ranges<<<sgs_blocks(c->total_tiles, 256), 256, 0, c->stream>>>(
+        c->tile_cnt, c->tile_start, c->total_tiles, P, dP, c->ranges);
   }
+  {
+    SgsProfScope ps(c, SGS_PROF_DUPLICATE);
+    if (chunks > 0)
+      k_l2_scatter<<<(unsigned)chunks, kThreads, 0, c->stream>>>(
+          c->chunk_first, nst, c->st_ranges, c->tile_key[which], c->pair_val[which], c->GW,
+          c->GH, tpv, c->SGW, spv, c->l2_cnt, c->l2_wcnt, c->tile_start, P, dP,
+          c->pair_val[which ^ 1]);
+  }
+  c->pair_sorted_buf = which ^ 1;
   return launch_tile_order(c);
 }
