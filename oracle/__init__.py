@@ -29,7 +29,8 @@ from . import rate_variants, ssim  # noqa: F401
 NCH = 59
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SRC = [os.path.join(HERE, "oracle.c"), os.path.join(HERE, "oracle_mlp.c")]
+SRC = [os.path.join(HERE, "oracle.c"), os.path.join(HERE, "oracle_mlp.c"),
+       os.path.join(HERE, "oracle_coding.c")]
 
 TW_DEFAULT = 16
 TH_DEFAULT = 16
@@ -117,6 +118,14 @@ def _declare(L):
         "orc_fixed_length_bits": (I64, [I64, I64, P, P, P, P, P]),
         "orc_fixed_length_pack": (None, [I64, I64, P, P, P, P, P]),
         "orc_fixed_length_unpack": (None, [I64, I64, P, P, P, P, P]),
+        "orc_morton3": (U64, [C.c_uint32, C.c_uint32, C.c_uint32, I32]),
+        "orc_octree_tokens": (I64, [I64, I64, P, P, P, P, P, P, P, P]),
+        "orc_octree_decode": (I64, [P, I64, I32, P, I64]),
+        "orc_voxel_positions": (I64, [P, P, I64, I32, P, P, P, I64]),
+        "orc_ans_model": (None, [P, I64, I32, I64, P]),
+        "orc_ans_ideal_bits": (F64, [P, I64, I32, I64, P]),
+        "orc_ans_encode": (I64, [P, I64, I32, I64, P, P, P]),
+        "orc_ans_decode": (I64, [P, P, I64, I32, I64, P, P]),
     }
     for name, (res, args) in sig.items():
         if not hasattr(L, name):
@@ -488,3 +497,93 @@ def rd_step(params, qstep, score, given_mask, cams, W, H, target, n, n_hat, lam,
     s = rd_forward(params, qstep, score, given_mask, cams, W, H, target, n, n_hat, lam,
                    mask_mode, seed, step, tau, TW, TH)
     return rd_backward(s, dimage)
+
+
+# --------------------------------------------------------------------------
+# Learned-coding stage, lossless parts [Sec. 3.4.2]: octree tokens of the
+# quantized geometry and the interleaved rANS coder (see oracle_coding.c)
+# --------------------------------------------------------------------------
+
+ANS_M = 4096
+ANS_CTX = 257
+
+
+def morton3(ux: int, uy: int, uz: int, depth: int) -> int:
+    return int(lib().orc_morton3(ux, uy, uz, depth))
+
+
+def octree_tokens(y: np.ndarray, q: np.ndarray, mhat: np.ndarray, n: int):
+    """Sec. 3.4.2 geometry occupancy coding: the kept Gaussians' position
+    codes voxelized, merged and written as 8-bit octree tokens, level by
+    level from the root, Morton order within a level."""
+    y = np.ascontiguousarray(y, np.float32)
+    q = np.ascontiguousarray(q[:3], np.float32)
+    mhat = np.ascontiguousarray(mhat[:n], np.uint8)
+    npad = y.shape[1]
+    kept = max(int(mhat.sum()), 1)
+    hdr = np.zeros(8, np.int64)
+    codes = np.zeros(kept, np.uint64)
+    dup = np.zeros(kept, np.uint32)
+    tokens = np.zeros(21 * kept, np.uint8)
+    level = np.zeros(22, np.int64)
+    nt = lib().orc_octree_tokens(n, npad, _p(y), _p(q), _p(mhat), _p(hdr), _p(codes), _p(dup),
+                                 _p(tokens), _p(level))
+    m = int(hdr[5])
+    return dict(depth=int(hdr[0]), kmin=hdr[1:4].copy(), kept=int(hdr[4]), unique=m,
+                flags=int(hdr[7]), codes=codes[:m].copy(), dup=dup[:m].copy(),
+                tokens=tokens[:nt].copy(), level_size=level[:int(hdr[0])].copy())
+
+
+def octree_decode(tokens: np.ndarray, depth: int, cap: int):
+    """The unique voxel codes a token stream describes (None if malformed)."""
+    tokens = np.ascontiguousarray(tokens, np.uint8)
+    codes = np.zeros(max(cap, 1), np.uint64)
+    m = lib().orc_octree_decode(_p(tokens), tokens.size, depth, _p(codes), cap)
+    return None if m < 0 else codes[:m].copy()
+
+
+def voxel_positions(codes, dup, depth: int, kmin, q):
+    codes = np.ascontiguousarray(codes, np.uint64)
+    dup = np.ascontiguousarray(dup, np.uint32)
+    kmin = np.ascontiguousarray(kmin, np.int64)
+    q = np.ascontiguousarray(q[:3], np.float32)
+    total = int(dup.astype(np.int64).sum()) + codes.size
+    xyz = np.zeros((3, max(total, 1)), np.float32)
+    lib().orc_voxel_positions(_p(codes), _p(dup), codes.size, depth, _p(kmin), _p(q), _p(xyz),
+                              total)
+    return xyz[:, :total].copy()
+
+
+def ans_model(sym: np.ndarray, order: int, lane_len: int):
+    sym = np.ascontiguousarray(sym, np.uint8)
+    freq = np.zeros((ANS_CTX, 256), np.uint16)
+    lib().orc_ans_model(_p(sym), sym.size, order, lane_len, _p(freq))
+    return freq
+
+
+def ans_ideal_bits(sym: np.ndarray, order: int, lane_len: int, freq: np.ndarray) -> float:
+    sym = np.ascontiguousarray(sym, np.uint8)
+    freq = np.ascontiguousarray(freq, np.uint16)
+    return float(lib().orc_ans_ideal_bits(_p(sym), sym.size, order, lane_len, _p(freq)))
+
+
+def ans_encode(sym: np.ndarray, order: int, lane_len: int, freq: np.ndarray):
+    """Returns (words uint16, block offsets int64) or None if a symbol has
+    frequency 0."""
+    sym = np.ascontiguousarray(sym, np.uint8)
+    freq = np.ascontiguousarray(freq, np.uint16)
+    nb = (sym.size + 64 * lane_len - 1) // (64 * lane_len)
+    words = np.zeros(128 * nb + sym.size + 1, np.uint16)
+    off = np.zeros(nb + 1, np.int64)
+    r = lib().orc_ans_encode(_p(sym), sym.size, order, lane_len, _p(freq), _p(words), _p(off))
+    return None if r < 0 else (words[:r].copy(), off)
+
+
+def ans_decode(words, block_off, n: int, order: int, lane_len: int, freq):
+    """Returns the n symbols, or None if the stream is malformed."""
+    words = np.ascontiguousarray(words, np.uint16)
+    block_off = np.ascontiguousarray(block_off, np.int64)
+    freq = np.ascontiguousarray(freq, np.uint16)
+    sym = np.zeros(max(n, 1), np.uint8)
+    r = lib().orc_ans_decode(_p(words), _p(block_off), n, order, lane_len, _p(freq), _p(sym))
+    return None if r < 0 else sym[:n].copy()
