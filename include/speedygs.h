@@ -487,6 +487,100 @@ sgs_status sgs_fl_encode(sgs_ctx *ctx, const float *params, const float *qstep,
 sgs_status sgs_fl_decode(sgs_ctx *ctx, const sgs_fl_channel *header, const uint32_t *payload,
                          int64_t payload_words, int64_t kept, int64_t out_pad, float *out);
 
+/* ---- Learned-coding stage, lossless parts (Sec. 3.4.2) -------------------
+ *
+ * Geometry occupancy tokens (Sec. 3.4.2, geometry occupancy coding: the
+ * point cloud voxelized into a multiscale structure, each downsampling step
+ * giving 8-bit occupancy tokens).  The kept Gaussians' position codes
+ * k_c = rint(fl32(y_c / q_c)) (c = x, y, z: channels 0-2; the quantizer's
+ * decision) become voxels u_c = k_c - kmin_c, kmin_c the smallest kept code,
+ * in a cube of side 2^D, D >= 1 the least depth that holds every axis's
+ * range.  Gaussians in one voxel merge: one voxel is coded and its extra
+ * copies are listed as metadata (the paper keeps duplicate counts aside).
+ * Tokens are written level by level from the root (level 0: one token;
+ * level d: one token per occupied node of depth d, in the Morton order of
+ * the nodes); bit (xb << 2 | yb << 1 | zb) of a node's token is set when its
+ * child whose next coordinate bits are xb, yb, zb is occupied.  The Morton
+ * code of a voxel has x bit b at bit 3b + 2, y bit b at 3b + 1, z bit b at
+ * 3b.  Header (all int64): */
+typedef struct {
+  int64_t depth;          /* D, 1..21 */
+  int64_t kmin[3];        /* smallest kept position code per axis (0 if none) */
+  int64_t kept;           /* kept Gaussians */
+  int64_t unique;         /* distinct voxels (nodes of depth D) */
+  int64_t tokens;         /* tokens in all: the sum of level_size */
+  int64_t dups;           /* entries of the duplicate list */
+  int64_t flags;          /* bit 0: a code outside int32 or a range of 2^21 or more
+                             (not decodable); bit 1: token_cap too small (tokens cut);
+                             bit 2: dup_cap too small (list cut) */
+  int64_t level_size[21]; /* tokens of level d (0 from level D on) */
+} sgs_octree_header;
+
+/* Encode the kept Gaussians' positions: params SoA [59][npad] (rows 0-2 are
+ * read), qstep [>= 3], hard_mask [n] (nonzero = kept), all device; n <= npad,
+ * n < 2^31.  Outputs (device, sync-free; read the header afterwards):
+ * tokens [token_cap] (4-byte aligned, token_cap a multiple of 4; 21 n always
+ * suffices); codes [n]: the distinct voxels' Morton codes, ascending (the
+ * first `unique`); dup_index / dup_count [dup_cap]: the voxels holding more
+ * than one kept Gaussian, ascending, with their copies beyond the first;
+ * header: sgs_octree_header. */
+sgs_status sgs_octree_encode(sgs_ctx *ctx, const float *params, int64_t npad, int64_t n,
+                             const float *qstep, const uint8_t *hard_mask, uint8_t *tokens,
+                             int64_t token_cap, uint64_t *codes, uint32_t *dup_index,
+                             uint32_t *dup_count, int64_t dup_cap, sgs_octree_header *header);
+/* Decode: header (HOST copy of the encoder's), tokens, dup_index /
+ * dup_count and qstep (device) give codes [unique] (the distinct voxels'
+ * codes, ascending) and xyz [3][out_pad] (out_pad >= kept): the decoded
+ * positions fl32((u_c + kmin_c) q_c), voxels in code order, each followed by
+ * its copies.  info: device int64[1], bit 0 set when the stream is
+ * inconsistent (children that do not match the level sizes, an empty token,
+ * duplicate entries out of order or not adding up to kept); outputs are then
+ * unspecified but every write stays inside the buffers.  The header itself is
+ * checked on the host (SGS_EINVAL). */
+sgs_status sgs_octree_decode(sgs_ctx *ctx, const sgs_octree_header *header,
+                             const uint8_t *tokens, const uint32_t *dup_index,
+                             const uint32_t *dup_count, const float *qstep, uint64_t *codes,
+                             float *xyz, int64_t out_pad, int64_t *info);
+
+/* Entropy coder for byte streams (the paper codes the octree tokens with
+ * p(t_i | t_{i-1}) and arithmetic coding; here the conditional model is a
+ * count table carried with the stream, order 1: context = the previous
+ * symbol of the same lane, 256 at a lane's start; or order 0: one context).
+ * Model: for each context with counts c_s (K symbols present, N in all),
+ * f_s = 1 + floor(c_s (4096 - K) / N) for present symbols, 0 otherwise, and
+ * the most frequent symbol (the lowest on ties) takes 4096 - sum f.
+ * freq: device uint16 [257][256] (rows of unused contexts 0).
+ * Coder: range ANS with a 32-bit state in [2^16, 2^32), 16-bit words and
+ * 12-bit frequencies (C(s, x) = floor(x / f_s) 4096 + cum_s + x mod f_s),
+ * interleaved over 64 lanes: symbols [64 S b, 64 S (b + 1)) form block b,
+ * lane l of it owns the run [64 S b + S l, 64 S b + S (l + 1)) (S =
+ * lane_len); the decoder advances the 64 lanes together, one symbol each per
+ * step, and after a step the lanes whose state is below 2^16 take the
+ * block's next word, in lane order.  Block b's words start with the 64
+ * lanes' final states (high half, low half), then its renormalization words
+ * in that decoding order; block_off [blocks + 1] (int64, device) are the
+ * blocks' word offsets.  n < 2^31; 1 <= lane_len <= 65536; order 0 or 1. */
+int64_t sgs_ans_max_words(int64_t n, int32_t lane_len);  /* word capacity that always suffices */
+/* Model of sym [n] (device) into freq; ideal_bits (device double, or null):
+ * -sum_i log2(f / 4096) of the stream under the model (Eq. loss_geo's rate
+ * with the count model's probabilities). */
+sgs_status sgs_ans_model(sgs_ctx *ctx, const uint8_t *sym, int64_t n, int32_t order,
+                         int32_t lane_len, uint16_t *freq, double *ideal_bits);
+/* Encode: words [word_cap] (uint16, device), block_off [blocks + 1]; info:
+ * device int64[2] = {words written in all, flags}: flags bit 0 a symbol of
+ * frequency 0 in its context, bit 1 word_cap too small (cut), bit 2 a used
+ * model row that does not sum to 4096. */
+sgs_status sgs_ans_encode(sgs_ctx *ctx, const uint8_t *sym, int64_t n, int32_t order,
+                          int32_t lane_len, const uint16_t *freq, uint16_t *words,
+                          int64_t word_cap, int64_t *block_off, int64_t *info);
+/* Decode n symbols into sym (device) from words [n_words] and block_off;
+ * info: device int64[1], bit 0 a malformed stream (a block's words out of
+ * range, run out or left over, a slot no symbol owns, a lane not back at
+ * the initial state), bit 2 a bad model row. */
+sgs_status sgs_ans_decode(sgs_ctx *ctx, const uint16_t *words, int64_t n_words,
+                          const int64_t *block_off, int64_t n, int32_t order, int32_t lane_len,
+                          const uint16_t *freq, uint8_t *sym, int64_t *info);
+
 /* Kernel-group timing with HIP events recorded on the context's stream around
  * each group's launches (no extra synchronization inside a step).  Groups: */
 enum {
@@ -510,7 +604,9 @@ enum {
   SGS_PROF_CODEC = 17,     /* fixed-length encode / decode */
   SGS_PROF_ADAM = 18,      /* optimizer step */
   SGS_PROF_SSIM = 19,      /* SSIM term of the distortion */
-  SGS_PROF_GROUPS = 20
+  SGS_PROF_OCTREE = 20,    /* octree tokens: encode / decode */
+  SGS_PROF_ANS = 21,       /* entropy coder: model, encode, decode */
+  SGS_PROF_GROUPS = 22
 };
 /* enable != 0 starts recording (and clears earlier records); 0 stops. */
 sgs_status sgs_profile_enable(sgs_ctx *ctx, int32_t enable);

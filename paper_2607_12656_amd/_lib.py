@@ -54,6 +54,15 @@ class sgs_adam_options(C.Structure):
                 ("step", C.c_int64)]
 
 
+class sgs_octree_header(C.Structure):
+    _fields_ = [("depth", C.c_int64), ("kmin", C.c_int64 * 3), ("kept", C.c_int64),
+                ("unique", C.c_int64), ("tokens", C.c_int64), ("dups", C.c_int64),
+                ("flags", C.c_int64), ("level_size", C.c_int64 * 21)]
+
+
+OCTREE_HEADER_WORDS = C.sizeof(sgs_octree_header) // 8
+assert OCTREE_HEADER_WORDS == 30
+
 SCHEDULES = {"tile": 0, "stride": 1, "queue": 2, "block": 3}
 
 
@@ -106,11 +115,17 @@ _SIGS = {
                     I64, C.POINTER(I64)],
     "sgs_fl_encode": [P, P, P, P, P, P, I64, P],
     "sgs_fl_decode": [P, P, P, I64, I64, I64, P],
+    "sgs_octree_encode": [P, P, I64, I64, P, P, P, I64, P, P, P, I64, P],
+    "sgs_octree_decode": [P, P, P, P, P, P, P, P, I64, P],
+    "sgs_ans_max_words": [I64, I32],
+    "sgs_ans_model": [P, P, I64, I32, I32, P, P],
+    "sgs_ans_encode": [P, P, I64, I32, I32, P, P, I64, P, P],
+    "sgs_ans_decode": [P, P, I64, P, I64, I32, I32, P, P, P],
 }
 PROF_GROUPS = ("fakequant", "rate", "preprocess", "depth_sort", "scan", "duplicate",
                "tile_sort", "ranges", "blend_fwd", "l1", "grad_clear", "blend_bwd",
                "preprocess_bwd", "fakequant_bwd", "mlp_fwd", "mlp_bwd", "mlp_train", "codec",
-               "adam", "ssim")
+               "adam", "ssim", "octree", "ans")
 MLP_PARAMS = 24961
 MLP_PACKED_BYTES = 98304
 MLP_STATIC_ROWS = 8192
@@ -132,7 +147,8 @@ def lib(path: str | None = None):
         f = getattr(L, name)
         f.argtypes = args
         f.restype = {"sgs_last_error": C.c_char_p, "sgs_destroy": None, "sgs_graph_destroy": None,
-                     "sgs_rate_mlp_train_scratch_bytes": C.c_int64}.get(name, C.c_int)
+                     "sgs_rate_mlp_train_scratch_bytes": C.c_int64,
+                     "sgs_ans_max_words": C.c_int64}.get(name, C.c_int)
     if path is None:
         _lib = L
     return L
@@ -369,6 +385,47 @@ class Context:
     def fl_decode(self, header, payload, payload_words, kept, out_pad, out):
         self._check(self.L.sgs_fl_decode(self.h, _ptr(header), _ptr(payload), payload_words,
                                          kept, out_pad, _ptr(out)), self.h)
+
+    # ---- learned-coding stage (octree tokens, entropy coder) ----
+    def octree_encode(self, params, npad, n, qstep, hard_mask, tokens, codes, dup_index,
+                      dup_count, header):
+        """Octree tokens of the kept positions; header: int64 [30] device
+        tensor (the sgs_octree_header layout)."""
+        self._check(self.L.sgs_octree_encode(
+            self.h, _ptr(params), npad, n, _ptr(qstep), _ptr(hard_mask), _ptr(tokens),
+            tokens.numel(), _ptr(codes), _ptr(dup_index), _ptr(dup_count),
+            0 if dup_index is None else dup_index.numel(), _ptr(header)), self.h)
+
+    @staticmethod
+    def octree_header(values) -> sgs_octree_header:
+        """Host header from the 30 int64 words the encoder wrote."""
+        v = np.asarray(values, np.int64).reshape(-1)
+        h = sgs_octree_header()
+        C.memmove(C.addressof(h), v.ctypes.data, C.sizeof(h))
+        return h
+
+    def octree_decode(self, header: sgs_octree_header, tokens, dup_index, dup_count, qstep,
+                      codes, xyz, out_pad, info):
+        self._check(self.L.sgs_octree_decode(
+            self.h, C.byref(header), _ptr(tokens), _ptr(dup_index), _ptr(dup_count),
+            _ptr(qstep), _ptr(codes), _ptr(xyz), out_pad, _ptr(info)), self.h)
+
+    def ans_max_words(self, n: int, lane_len: int) -> int:
+        return int(self.L.sgs_ans_max_words(n, lane_len))
+
+    def ans_model(self, sym, n, order, lane_len, freq, ideal_bits=None):
+        self._check(self.L.sgs_ans_model(self.h, _ptr(sym), n, order, lane_len, _ptr(freq),
+                                         _ptr(ideal_bits)), self.h)
+
+    def ans_encode(self, sym, n, order, lane_len, freq, words, block_off, info):
+        self._check(self.L.sgs_ans_encode(self.h, _ptr(sym), n, order, lane_len, _ptr(freq),
+                                          _ptr(words), words.numel(), _ptr(block_off),
+                                          _ptr(info)), self.h)
+
+    def ans_decode(self, words, n_words, block_off, n, order, lane_len, freq, sym, info):
+        self._check(self.L.sgs_ans_decode(self.h, _ptr(words), n_words, _ptr(block_off), n,
+                                          order, lane_len, _ptr(freq), _ptr(sym), _ptr(info)),
+                    self.h)
 
     def rate_variant(self, params, qstep, stats, rate_weight, out3, rate_grad=None,
                      proxy="range", masking="mult", alpha=0.0):

@@ -169,6 +169,7 @@ void sgs_destroy(sgs_ctx *c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
   free_scene(c);
+  coding_free(c);
   for (auto &r : c->prof_recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -609,6 +610,115 @@ sgs_status sgs_fl_decode(sgs_ctx *c, const sgs_fl_channel *header, const uint32_
   if (kept > (int64_t)INT32_MAX * 4096LL)
     return fail(c, SGS_ECAPACITY, "fl_decode: kept too large");
   SGS_HIP(launch_fl_decode(c, header, payload, payload_words, kept, out_pad, out), "fl_decode");
+  return SGS_OK;
+}
+
+// ---- learned-coding stage --------------------------------------------------
+sgs_status sgs_octree_encode(sgs_ctx *c, const float *params, int64_t npad, int64_t n,
+                             const float *qstep, const uint8_t *hard_mask, uint8_t *tokens,
+                             int64_t token_cap, uint64_t *codes, uint32_t *dup_index,
+                             uint32_t *dup_count, int64_t dup_cap, sgs_octree_header *header) {
+  if (!c) return SGS_EINVAL;
+  if (c->capturing) return fail(c, SGS_ESTATE, "octree_encode: not inside graph capture");
+  if (!params || !qstep || !hard_mask || !tokens || !codes || !header ||
+      (dup_cap > 0 && (!dup_index || !dup_count)))
+    return fail(c, SGS_EINVAL, "octree_encode: null pointer");
+  if (n < 1 || npad < n || n > (int64_t)INT32_MAX)
+    return fail(c, SGS_EINVAL, "octree_encode: need 1 <= n <= npad, n < 2^31");
+  if (token_cap < 0 || token_cap % 4 != 0 || !aligned(tokens, 4) || dup_cap < 0)
+    return fail(c, SGS_EINVAL,
+                "octree_encode: token_cap must be a multiple of 4, tokens 4-byte aligned, "
+                "dup_cap >= 0");
+  SgsProfScope ps(c, SGS_PROF_OCTREE);
+  SGS_HIP(launch_octree_encode(c, params, npad, n, qstep, hard_mask, tokens, token_cap, codes,
+                               dup_index, dup_count, dup_cap, header),
+          "octree_encode");
+  return SGS_OK;
+}
+
+sgs_status sgs_octree_decode(sgs_ctx *c, const sgs_octree_header *h, const uint8_t *tokens,
+                             const uint32_t *dup_index, const uint32_t *dup_count,
+                             const float *qstep, uint64_t *codes, float *xyz, int64_t out_pad,
+                             int64_t *info) {
+  if (!c) return SGS_EINVAL;
+  if (c->capturing) return fail(c, SGS_ESTATE, "octree_decode: not inside graph capture");
+  if (!h || !qstep || !info || (h->tokens > 0 && (!tokens || !codes || !xyz)) ||
+      (h->dups > 0 && (!dup_index || !dup_count)))
+    return fail(c, SGS_EINVAL, "octree_decode: null pointer");
+  if (h->depth < 1 || h->depth > 21 || h->flags != 0 || h->kept < 0 || h->unique < 0 ||
+      h->dups < 0 || h->tokens < 0 || h->kept > (int64_t)INT32_MAX ||
+      h->tokens > (int64_t)INT32_MAX)
+    return fail(c, SGS_EINVAL, "octree_decode: bad header");
+  int64_t sum = 0;
+  for (int d = 0; d < 21; ++d) {
+    const int64_t v = h->level_size[d];
+    if (v < 0 || (d >= h->depth && v != 0)) return fail(c, SGS_EINVAL, "octree_decode: bad level sizes");
+    if (d > 0 && d < h->depth && v > 8 * h->level_size[d - 1])
+      return fail(c, SGS_EINVAL, "octree_decode: bad level sizes");
+    sum += v;
+  }
+  const bool empty = h->kept == 0;
+  if (sum != h->tokens || (empty ? (h->tokens != 0 || h->unique != 0 || h->dups != 0)
+                                 : (h->level_size[0] != 1 ||
+                                    h->unique > 8 * h->level_size[h->depth - 1] ||
+                                    h->unique > h->kept || h->dups > h->unique)))
+    return fail(c, SGS_EINVAL, "octree_decode: inconsistent header");
+  if (out_pad < h->kept) return fail(c, SGS_EINVAL, "octree_decode: out_pad < kept");
+  SgsProfScope ps(c, SGS_PROF_OCTREE);
+  SGS_HIP(launch_octree_decode(c, h, tokens, dup_index, dup_count, qstep, codes, xyz, out_pad,
+                               info),
+          "octree_decode");
+  return SGS_OK;
+}
+
+static sgs_status ans_args(sgs_ctx *c, const char *who, int64_t n, int32_t order,
+                           int32_t lane_len) {
+  if (c->capturing) return fail(c, SGS_ESTATE, "%s: not inside graph capture", who);
+  if (n < 0 || n > (int64_t)INT32_MAX) return fail(c, SGS_EINVAL, "%s: need 0 <= n < 2^31", who);
+  if (order != 0 && order != 1) return fail(c, SGS_EINVAL, "%s: order must be 0 or 1", who);
+  if (lane_len < 1 || lane_len > 65536)
+    return fail(c, SGS_EINVAL, "%s: lane_len must be in [1, 65536]", who);
+  return SGS_OK;
+}
+
+sgs_status sgs_ans_model(sgs_ctx *c, const uint8_t *sym, int64_t n, int32_t order,
+                         int32_t lane_len, uint16_t *freq, double *ideal_bits) {
+  if (!c) return SGS_EINVAL;
+  sgs_status r = ans_args(c, "ans_model", n, order, lane_len);
+  if (r != SGS_OK) return r;
+  if (!freq || (n > 0 && !sym)) return fail(c, SGS_EINVAL, "ans_model: null pointer");
+  SgsProfScope ps(c, SGS_PROF_ANS);
+  SGS_HIP(launch_ans_model(c, sym, n, order, lane_len, freq, ideal_bits), "ans_model");
+  return SGS_OK;
+}
+
+sgs_status sgs_ans_encode(sgs_ctx *c, const uint8_t *sym, int64_t n, int32_t order,
+                          int32_t lane_len, const uint16_t *freq, uint16_t *words,
+                          int64_t word_cap, int64_t *block_off, int64_t *info) {
+  if (!c) return SGS_EINVAL;
+  sgs_status r = ans_args(c, "ans_encode", n, order, lane_len);
+  if (r != SGS_OK) return r;
+  if (!freq || !block_off || !info || (n > 0 && (!sym || !words)))
+    return fail(c, SGS_EINVAL, "ans_encode: null pointer");
+  if (word_cap < 0) return fail(c, SGS_EINVAL, "ans_encode: word_cap < 0");
+  SgsProfScope ps(c, SGS_PROF_ANS);
+  SGS_HIP(launch_ans_encode(c, sym, n, order, lane_len, freq, words, word_cap, block_off, info),
+          "ans_encode");
+  return SGS_OK;
+}
+
+sgs_status sgs_ans_decode(sgs_ctx *c, const uint16_t *words, int64_t n_words,
+                          const int64_t *block_off, int64_t n, int32_t order, int32_t lane_len,
+                          const uint16_t *freq, uint8_t *sym, int64_t *info) {
+  if (!c) return SGS_EINVAL;
+  sgs_status r = ans_args(c, "ans_decode", n, order, lane_len);
+  if (r != SGS_OK) return r;
+  if (!freq || !block_off || !info || (n > 0 && (!sym || !words)))
+    return fail(c, SGS_EINVAL, "ans_decode: null pointer");
+  if (n_words < 0) return fail(c, SGS_EINVAL, "ans_decode: n_words < 0");
+  SgsProfScope ps(c, SGS_PROF_ANS);
+  SGS_HIP(launch_ans_decode(c, words, n_words, block_off, n, order, lane_len, freq, sym, info),
+          "ans_decode");
   return SGS_OK;
 }
 

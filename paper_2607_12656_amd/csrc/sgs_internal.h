@@ -118,6 +118,7 @@ struct sgs_ctx {
   bool fixed_cap = false;             // pair capacity fixed by the caller: no host sync per step
   int64_t cap_limit = 0;              // the reserved capacity (buffers may be larger)
   bool capturing = false;             // the stream is being captured into a HIP graph
+  struct SgsCoding *coding = nullptr; // octree and entropy-coder scratch (first use)
 
   // kernel-group timing
   struct ProfRec {
@@ -279,6 +280,25 @@ hipError_t launch_mlp_train_step(sgs_ctx *c, float *theta, float *m, float *v, v
                                  int64_t step, float *loss, float *gtheta, void *scratch,
                                  bool profile = true);
 // loss.hip
+// Learned-coding stage (octree tokens, entropy coder)
+void coding_free(sgs_ctx *c);
+hipError_t launch_octree_encode(sgs_ctx *c, const float *params, int64_t npad, int64_t n,
+                                const float *q, const uint8_t *hard, uint8_t *tokens,
+                                int64_t token_cap, uint64_t *codes, uint32_t *dup_index,
+                                uint32_t *dup_count, int64_t dup_cap, sgs_octree_header *h);
+hipError_t launch_octree_decode(sgs_ctx *c, const sgs_octree_header *h, const uint8_t *tokens,
+                                const uint32_t *dup_index, const uint32_t *dup_count,
+                                const float *q, uint64_t *codes, float *xyz, int64_t out_pad,
+                                int64_t *info);
+hipError_t launch_ans_model(sgs_ctx *c, const uint8_t *sym, int64_t n, int order, int64_t S,
+                            uint16_t *freq, double *bits);
+hipError_t launch_ans_encode(sgs_ctx *c, const uint8_t *sym, int64_t n, int order, int64_t S,
+                             const uint16_t *freq, uint16_t *words, int64_t word_cap,
+                             int64_t *block_off, int64_t *info);
+hipError_t launch_ans_decode(sgs_ctx *c, const uint16_t *words, int64_t n_words,
+                             const int64_t *block_off, int64_t n, int order, int64_t S,
+                             const uint16_t *freq, uint8_t *sym, int64_t *info);
+
 hipError_t launch_l1(sgs_ctx *c, const float *image, const float *target, float scale,
                      float *loss, float *dimg);
 

@@ -1,0 +1,347 @@
+"""GPU learned-coding stage, lossless parts (paper Sec. 3.4.2), against the
+oracle on the same seeded inputs, bit for bit: octree tokens, level sizes,
+distinct voxel codes and duplicate lists of the quantized positions; the
+decoded codes and positions; the entropy coder's model tables, its words and
+block offsets, and its decoding of the oracle's streams.  Edge cases: one
+kept Gaussian, none kept, heavy duplication, the deepest tree, a range that
+does not fit, capacities too small, truncated or corrupted streams, empty
+and ragged symbol streams, every lane length from 1 up."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def gctx(dev):
+    from paper_2607_12656_amd import Context
+    return Context(0)
+
+
+def T(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def clustered(seed, n, spread=0.2, k=8):
+    rng = np.random.default_rng(seed)
+    npad = synth.pad64(n)
+    y = np.zeros((59, npad), np.float32)
+    centres = rng.normal(0, 1, (k, 3))
+    y[:3, :n] = (centres[rng.integers(0, k, n)] + rng.normal(0, spread, (n, 3))).T
+    return y
+
+
+# ---------------------------------------------------------------------------
+# octree
+# ---------------------------------------------------------------------------
+def gpu_octree(gctx, dev, y, q, mask, n, token_cap=None, dup_cap=None):
+    npad = y.shape[1]
+    token_cap = 21 * n + 4 - (21 * n) % 4 if token_cap is None else token_cap
+    dup_cap = n if dup_cap is None else dup_cap
+    tokens = torch.full((token_cap,), 0xA5, dtype=torch.uint8, device=dev)
+    codes = torch.zeros(n, dtype=torch.int64, device=dev)
+    di = torch.zeros(max(dup_cap, 1), dtype=torch.int32, device=dev)[:dup_cap]
+    dc = torch.zeros(max(dup_cap, 1), dtype=torch.int32, device=dev)[:dup_cap]
+    hdr = torch.zeros(30, dtype=torch.int64, device=dev)
+    gctx.octree_encode(T(y, dev), npad, n, T(q, dev), T(mask, dev), tokens, codes,
+                       di if dup_cap else None, dc if dup_cap else None, hdr)
+    torch.cuda.synchronize()
+    h = hdr.cpu().numpy()
+    return dict(hdr=h, depth=int(h[0]), kmin=h[1:4], kept=int(h[4]), unique=int(h[5]),
+                tokens_n=int(h[6]), dups=int(h[7]), flags=int(h[8]), level_size=h[9:30],
+                tokens=tokens.cpu().numpy(), codes=codes.cpu().numpy().view(np.uint64),
+                dup_index=di.cpu().numpy().view(np.uint32),
+                dup_count=dc.cpu().numpy().view(np.uint32), raw=(tokens, di, dc))
+
+
+def gpu_decode(gctx, dev, g, q, out_pad=None, tokens=None):
+    header = gctx.octree_header(g["hdr"])
+    tok, di, dc = g["raw"]
+    if tokens is not None:
+        tok = T(tokens, dev)
+    m, kept = g["unique"], g["kept"]
+    out_pad = max(kept, 1) if out_pad is None else out_pad
+    codes = torch.zeros(max(m, 1), dtype=torch.int64, device=dev)
+    xyz = torch.full((3, out_pad), float("nan"), dtype=torch.float32, device=dev)
+    info = torch.zeros(1, dtype=torch.int64, device=dev)
+    gctx.octree_decode(header, tok, di if g["dups"] else None, dc if g["dups"] else None,
+                       T(q, dev), codes, xyz, out_pad, info)
+    torch.cuda.synchronize()
+    return (codes.cpu().numpy().view(np.uint64)[:m], xyz.cpu().numpy()[:, :kept],
+            int(info.cpu().numpy()[0]))
+
+
+def check_octree(orc, gctx, dev, y, q, mask, n, name):
+    _say(f"[gpu] octree {name} n={n}")
+    r = orc.octree_tokens(y, q, mask, n)
+    g = gpu_octree(gctx, dev, y, q, mask, n)
+    assert g["flags"] == r["flags"]
+    assert g["depth"] == r["depth"] and list(g["kmin"]) == list(r["kmin"])
+    assert g["kept"] == r["kept"] and g["unique"] == r["unique"]
+    nt = r["tokens"].size
+    assert g["tokens_n"] == nt
+    assert np.array_equal(g["level_size"][:r["depth"]], r["level_size"])
+    assert np.all(g["level_size"][r["depth"]:] == 0)
+    assert np.array_equal(g["tokens"][:nt], r["tokens"])
+    assert np.array_equal(g["codes"][:r["unique"]], r["codes"])
+    nz = np.nonzero(r["dup"])[0]
+    assert g["dups"] == nz.size
+    assert np.array_equal(g["dup_index"][:nz.size], nz)
+    assert np.array_equal(g["dup_count"][:nz.size], r["dup"][nz])
+    if r["flags"]:
+        return g
+    codes, xyz, info = gpu_decode(gctx, dev, g, q)
+    assert info == 0
+    assert np.array_equal(codes, r["codes"])
+    want = orc.voxel_positions(r["codes"], r["dup"], r["depth"], r["kmin"], q)
+    assert np.array_equal(xyz, want)
+    return g
+
+
+@pytest.mark.parametrize("seed,n,qv,frac", [(0, 300, 0.01, 0.8), (1, 5000, 0.05, 1.0),
+                                             (2, 20011, 0.002, 0.5), (3, 70000, 1e-4, 0.9)])
+def test_octree_matches_oracle(orc, gctx, dev, seed, n, qv, frac):
+    y = clustered(seed, n)
+    q = np.full(59, qv, np.float32)
+    m = (np.random.default_rng(seed + 100).random(n) < frac).astype(np.uint8)
+    check_octree(orc, gctx, dev, y, q, m, n, f"seed{seed}")
+
+
+def test_octree_edge_cases(orc, gctx, dev):
+    # one kept Gaussian, at a negative position
+    y = clustered(5, 130)
+    q = np.full(59, 0.01, np.float32)
+    m = np.zeros(130, np.uint8)
+    m[77] = 1
+    check_octree(orc, gctx, dev, y, q, m, 130, "one kept")
+    # none kept
+    g = check_octree(orc, gctx, dev, y, q, np.zeros(130, np.uint8), 130, "none kept")
+    assert g["tokens_n"] == 0 and g["unique"] == 0
+    # everything in one voxel
+    y2 = np.zeros_like(y)
+    y2[:3, :130] = 0.5
+    check_octree(orc, gctx, dev, y2, q, np.ones(130, np.uint8), 130, "one voxel")
+    # heavy duplication: a coarse step
+    check_octree(orc, gctx, dev, clustered(6, 9000), np.full(59, 0.5, np.float32),
+                 np.ones(9000, np.uint8), 9000, "coarse")
+    # the deepest tree: range 2^21 - 1 on one axis
+    y3 = clustered(7, 640)
+    y3[:3, :640] = np.abs(y3[:3, :640])
+    y3[0, 0], y3[0, 1] = 0.0, float((1 << 21) - 1)
+    y3[1:3, :2] = 0.0
+    check_octree(orc, gctx, dev, y3, np.full(59, 1.0, np.float32), np.ones(640, np.uint8),
+                 640, "depth 21")
+
+
+def test_octree_flags(orc, gctx, dev):
+    # range 2^21: not codable, flagged on both sides
+    y = clustered(8, 256)
+    y[0, 0], y[0, 1] = 0.0, float(1 << 21)
+    g = check_octree(orc, gctx, dev, y, np.full(59, 1.0, np.float32), np.ones(256, np.uint8),
+                     256, "range 2^21")
+    assert g["flags"] & 1
+    # a code outside int32
+    y[0, 5] = 3e10
+    g = gpu_octree(gctx, dev, y, np.full(59, 1.0, np.float32), np.ones(256, np.uint8), 256)
+    assert g["flags"] & 1
+    # token and duplicate capacities too small: flagged, writes stay inside
+    y = clustered(9, 4000)
+    q = np.full(59, 0.2, np.float32)
+    m = np.ones(4000, np.uint8)
+    r = orc.octree_tokens(y, q, m, 4000)
+    cap = (r["tokens"].size // 2) // 4 * 4
+    assert np.count_nonzero(r["dup"]) > 3
+    g = gpu_octree(gctx, dev, y, q, m, 4000, token_cap=cap, dup_cap=3)
+    assert g["flags"] & 2 and g["flags"] & 4
+    assert g["tokens"].size == cap
+    assert np.array_equal(g["tokens"][:cap], r["tokens"][:cap])
+
+
+def test_octree_decode_rejects_corruption(orc, gctx, dev):
+    y = clustered(10, 3000)
+    q = np.full(59, 0.02, np.float32)
+    m = np.ones(3000, np.uint8)
+    g = gpu_octree(gctx, dev, y, q, m, 3000)
+    nt = g["tokens_n"]
+    bad = g["tokens"].copy()
+    # one more child in the last level's first token: the children no longer
+    # match the level sizes
+    lvl0 = int(np.sum(g["level_size"][:g["depth"] - 1]))
+    t = int(bad[lvl0])
+    free = [b for b in range(8) if not (t >> b) & 1]
+    bad[lvl0] = t | (1 << free[0]) if free else t & 0x7F
+    _, _, info = gpu_decode(gctx, dev, g, q, tokens=bad)
+    assert info & 1
+    # an empty token
+    bad = g["tokens"].copy()
+    bad[nt - 1] = 0
+    _, _, info = gpu_decode(gctx, dev, g, q, tokens=bad)
+    assert info & 1
+    # a header that does not add up is refused on the host
+    from paper_2607_12656_amd import SgsError
+    h = g["hdr"].copy()
+    h[6] += 1
+    with pytest.raises(SgsError):
+        gctx.octree_decode(gctx.octree_header(h), g["raw"][0], None, None,
+                           T(q, dev), torch.zeros(8, dtype=torch.int64, device=dev),
+                           torch.zeros(3, 3000, device=dev), 3000,
+                           torch.zeros(1, dtype=torch.int64, device=dev))
+
+
+def test_octree_full_size_scene(orc, gctx, dev):
+    """The 3M-Gaussian scene of the formation benchmark at three steps."""
+    sc = synth.make_scene("c3")
+    for qv in (2.0 ** -6, 2.0 ** -10, 2.0 ** -14):
+        q = np.full(59, qv, np.float32)
+        check_octree(orc, gctx, dev, sc.params, q, sc.given_mask, sc.n, f"c3 q={qv}")
+
+
+# ---------------------------------------------------------------------------
+# entropy coder
+# ---------------------------------------------------------------------------
+def markov(seed, n, alphabet=37):
+    rng = np.random.default_rng(seed)
+    g = rng.geometric(0.4, n)
+    sym = np.zeros(n, np.uint8)
+    for i in range(1, n):
+        sym[i] = (sym[i - 1] * 5 + g[i]) % alphabet
+    return sym
+
+
+def gpu_model(gctx, dev, sym, order, S):
+    n = sym.size
+    freq = torch.zeros(257 * 256, dtype=torch.int16, device=dev)
+    bits = torch.zeros(1, dtype=torch.float64, device=dev)
+    s = T(sym, dev) if n else torch.zeros(1, dtype=torch.uint8, device=dev)
+    gctx.ans_model(s, n, order, S, freq, bits)
+    torch.cuda.synchronize()
+    return freq.cpu().numpy().view(np.uint16).reshape(257, 256), float(bits.item())
+
+
+def gpu_encode(gctx, dev, sym, order, S, freq, word_cap=None):
+    n = sym.size
+    cap = gctx.ans_max_words(n, S) if word_cap is None else word_cap
+    nb = (n + 64 * S - 1) // (64 * S)
+    words = torch.full((max(cap, 1),), 0x5A5A, dtype=torch.int16, device=dev)[:cap]
+    off = torch.zeros(nb + 1, dtype=torch.int64, device=dev)
+    info = torch.zeros(2, dtype=torch.int64, device=dev)
+    s = T(sym, dev) if n else torch.zeros(1, dtype=torch.uint8, device=dev)
+    gctx.ans_encode(s, n, order, S, T(freq.view(np.int16), dev), words, off, info)
+    torch.cuda.synchronize()
+    inf = info.cpu().numpy()
+    return (words.cpu().numpy().view(np.uint16)[:int(inf[0])], off.cpu().numpy(), int(inf[0]),
+            int(inf[1]))
+
+
+def gpu_decode_ans(gctx, dev, words, off, n, order, S, freq):
+    out = torch.full((max(n, 1),), 0xEE, dtype=torch.uint8, device=dev)
+    info = torch.zeros(1, dtype=torch.int64, device=dev)
+    w = T(words.view(np.int16), dev) if words.size else torch.zeros(1, dtype=torch.int16,
+                                                                     device=dev)
+    gctx.ans_decode(w, words.size, T(off, dev), n, order, S, T(freq.view(np.int16), dev), out,
+                    info)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()[:n], int(info.cpu().numpy()[0])
+
+
+def check_ans(orc, gctx, dev, sym, order, S, name):
+    _say(f"[gpu] ans {name} n={sym.size} order={order} lane_len={S}")
+    f = orc.ans_model(sym, order, S)
+    gf, gbits = gpu_model(gctx, dev, sym, order, S)
+    assert np.array_equal(gf, f)
+    ideal = orc.ans_ideal_bits(sym, order, S, f)
+    assert gbits == pytest.approx(ideal, rel=1e-9, abs=1e-9)   # FP64 sums, other order
+    w, off = orc.ans_encode(sym, order, S, f)
+    gw, goff, total, flags = gpu_encode(gctx, dev, sym, order, S, f)
+    assert flags == 0
+    assert total == w.size
+    assert np.array_equal(goff, off)
+    assert np.array_equal(gw, w)
+    out, info = gpu_decode_ans(gctx, dev, w, off, sym.size, order, S, f)
+    assert info == 0
+    assert np.array_equal(out, sym)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("S", [1, 4, 64, 256, 1000])
+@pytest.mark.parametrize("n", [1, 63, 4097, 100003])
+def test_ans_matches_oracle(orc, gctx, dev, order, S, n):
+    check_ans(orc, gctx, dev, markov(n + S + order, n), order, S, "markov")
+
+
+def test_ans_edge_cases(orc, gctx, dev):
+    # empty stream
+    check_ans(orc, gctx, dev, np.zeros(0, np.uint8), 1, 64, "empty")
+    # one symbol value only: no words beyond the states
+    check_ans(orc, gctx, dev, np.full(70000, 200, np.uint8), 1, 256, "constant")
+    # all 256 values, uniform and heavily skewed
+    rng = np.random.default_rng(12)
+    check_ans(orc, gctx, dev, rng.integers(0, 256, 300000).astype(np.uint8), 0, 256, "uniform")
+    sk = np.minimum(rng.geometric(0.05, 300000) - 1, 255).astype(np.uint8)
+    check_ans(orc, gctx, dev, sk, 1, 512, "skewed")
+    # the longest lanes
+    check_ans(orc, gctx, dev, markov(13, 200000), 1, 65536, "lane 65536")
+
+
+def test_ans_octree_tokens(orc, gctx, dev):
+    """The coder on the geometry tokens of the 3M-Gaussian scene (Eq. loss_geo's
+    rate under the count model)."""
+    sc = synth.make_scene("c3")
+    r = orc.octree_tokens(sc.params, np.full(59, 2.0 ** -12, np.float32), sc.given_mask, sc.n)
+    check_ans(orc, gctx, dev, r["tokens"], 1, 256, "c3 tokens")
+
+
+def test_ans_flags_and_damage(orc, gctx, dev):
+    sym = markov(14, 50000)
+    f = orc.ans_model(sym, 1, 64)
+    # a symbol with frequency 0 in its context
+    g = f.copy()
+    row = int(sym[1])
+    pos = np.nonzero(g[row])[0]
+    g[row, pos[0]] += g[row, pos[-1]] if pos.size > 1 else 0
+    if pos.size > 1:
+        g[row, pos[-1]] = 0
+        _, _, _, flags = gpu_encode(gctx, dev, sym, 1, 64, g)
+        assert flags & 1
+    # a model row that does not sum to 4096
+    g = f.copy()
+    g[256, int(np.nonzero(g[256])[0][0])] += 1
+    _, _, _, flags = gpu_encode(gctx, dev, sym, 1, 64, g)
+    assert flags & 4
+    # too small a word buffer: flagged, nothing written past it
+    w, off = orc.ans_encode(sym, 1, 64, f)
+    gw, goff, total, flags = gpu_encode(gctx, dev, sym, 1, 64, f, word_cap=w.size // 2)
+    assert flags & 2 and total == w.size
+    # decoding: truncated, shifted and corrupted streams are flagged
+    _, info = gpu_decode_ans(gctx, dev, w[:-1], off, sym.size, 1, 64, f)
+    assert info & 1
+    off2 = off.copy()
+    off2[1] += 1
+    _, info = gpu_decode_ans(gctx, dev, w, off2, sym.size, 1, 64, f)
+    assert info & 1
+    bad = w.copy()
+    bad[200] ^= 0x0100
+    out, info = gpu_decode_ans(gctx, dev, bad, off, sym.size, 1, 64, f)
+    assert info & 1 or not np.array_equal(out, sym)
+    ref = orc.ans_decode(bad, off, sym.size, 1, 64, f)
+    assert (ref is None) == bool(info & 1)
+    if ref is not None:
+        assert np.array_equal(out, ref)
