@@ -29,7 +29,9 @@ the plain-proxy run, both runs enqueued eagerly, the RD step alone (forward
 + backward, graph-replayed), the rate-estimate errors against the exact coder
 bits, the roofline of the dominant kernel group, the 1M-Gaussian single-view
 step (``c2``) as a sub-record, the MLP / codec / SSIM / rate-variant legs at
-1M, and the FP64 oracle on the host on a bounded sample of this workload.
+1M, the coding stage (octree tokens and rANS, encode and decode) on the
+formation's final state, and the FP64 oracle on the host on a bounded sample
+of this workload.
 """
 from __future__ import annotations
 
@@ -333,6 +335,8 @@ def bench_formation(args, sc, ctx, stream, dev, t):
             f.iterate()
         torch.cuda.synchronize()
         dt_eager = time.perf_counter() - t0
+        if name == "learned":     # the state the coding stage takes over
+            coding_in = (f.params.clone(), f.q.clone(), rd.hard.clone())
         # re-runs from the same state: the method's evaluations, the blend's
         # evaluations after its reach test, per-kernel times
         counts = {}
@@ -410,6 +414,11 @@ def bench_formation(args, sc, ctx, stream, dev, t):
         g.close()
     ctx.query()
 
+    coding = None
+    if not args.no_coding:
+        coding = bench_coding(ctx, dev, *coding_in, sc.n, sc.npad)
+    del coding_in
+
     L = runs["learned"]
     geo = geometry(sc, tile)
     dom = max(L["kernel_ms"], key=L["kernel_ms"].get)
@@ -446,6 +455,7 @@ def bench_formation(args, sc, ctx, stream, dev, t):
         "learned_over_plain_time": round(L["ms_per_step"] / runs["plain"]["ms_per_step"], 4),
         "rd_step_graph_ms": rd_only,
         "autotune_ms": tune["ms"],
+        "coding": coding,
         "mlp_training": {"seconds": round(train_s, 2), "loss": [round(v, 2) for v in losses],
                          "held_out_error_learned": round(err_l, 4),
                          "held_out_error_plain": round(err_p, 4)},
@@ -702,6 +712,95 @@ def say(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def bench_coding(ctx, dev, params, q, hard, n, npad, reps=10, lane_len=256):
+    """Learned-coding stage, lossless parts, on the formation's final state:
+    octree tokens of the kept positions, their order-1 count model and rANS
+    stream (encode), then the decode back to tokens, voxels and positions.
+    Two position steps: the formation's own, and 2^-12 (a deep tree).  Timed
+    eagerly (host clock around reps calls between synchronizations; the
+    coder allocates its scratch on first use, outside the timed calls);
+    per-group times from the library's event profile."""
+    import numpy as np
+    import torch
+
+    S = lane_len
+    res = {}
+    cap = (21 * n + 3) // 4 * 4
+    tokens = torch.empty(cap, dtype=torch.uint8, device=dev)
+    codes = torch.empty(n, dtype=torch.int64, device=dev)
+    di = torch.empty(n, dtype=torch.int32, device=dev)
+    dc = torch.empty(n, dtype=torch.int32, device=dev)
+    hdr = torch.empty(30, dtype=torch.int64, device=dev)
+    freq = torch.empty(257 * 256, dtype=torch.int16, device=dev)
+    bits = torch.empty(1, dtype=torch.float64, device=dev)
+    info = torch.empty(2, dtype=torch.int64, device=dev)
+    dinfo = torch.empty(1, dtype=torch.int64, device=dev)
+    oinfo = torch.empty(1, dtype=torch.int64, device=dev)
+    for label, qpos in (("formation_steps", None), ("position_step_2^-12", 2.0 ** -12)):
+        qq = q.clone()
+        if qpos is not None:
+            qq[:3] = qpos
+        ctx.octree_encode(params, npad, n, qq, hard, tokens, codes, di, dc, hdr)
+        h = hdr.cpu().numpy()
+        T, m, kept = int(h[6]), int(h[5]), int(h[4])
+        assert h[8] == 0, f"octree flags {h[8]}"
+        tok = tokens[:T]
+        nb = (T + 64 * S - 1) // (64 * S)
+        wcap = ctx.ans_max_words(T, S)
+        words = torch.empty(wcap, dtype=torch.int16, device=dev)
+        off = torch.empty(nb + 1, dtype=torch.int64, device=dev)
+
+        def encode():
+            ctx.octree_encode(params, npad, n, qq, hard, tokens, codes, di, dc, hdr)
+            ctx.ans_model(tok, T, 1, S, freq, bits)
+            ctx.ans_encode(tok, T, 1, S, freq, words, off, info)
+
+        encode()
+        torch.cuda.synchronize()
+        W = int(info[0].item())
+        assert int(info[1].item()) == 0
+        header = ctx.octree_header(h)
+        out_tok = torch.empty(T, dtype=torch.uint8, device=dev)
+        codes2 = torch.empty(max(m, 1), dtype=torch.int64, device=dev)
+        xyz = torch.empty((3, max(kept, 1)), dtype=torch.float32, device=dev)
+
+        def decode():
+            ctx.ans_decode(words, W, off, T, 1, S, freq, out_tok, dinfo)
+            ctx.octree_decode(header, out_tok, di, dc, qq, codes2, xyz, max(kept, 1), oinfo)
+
+        decode()
+        torch.cuda.synchronize()
+        assert int(dinfo.item()) == 0 and int(oinfo.item()) == 0
+        assert torch.equal(out_tok, tok) and torch.equal(codes2[:m], codes[:m])
+        timed = {}
+        for name, fn in (("encode", encode), ("decode", decode)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            timed[name] = (time.perf_counter() - t0) * 1e3 / reps
+            ctx.profile_enable(True)
+            for _ in range(reps):
+                fn()
+            prof = ctx.profile_read()
+            ctx.profile_enable(False)
+            timed[name + "_groups"] = {g: round(prof[g][0] / reps, 4) for g in ("octree", "ans")}
+        nz = int(torch.count_nonzero(freq).item())
+        res[label] = {
+            "kept": kept, "voxels": m, "depth": int(h[0]), "tokens": T, "dups": int(h[7]),
+            "lane_len": S, "blocks": nb, "words": W,
+            "bits_per_kept_gaussian": round(16.0 * W / max(kept, 1), 4),
+            "ideal_bits_R_geo": round(float(bits.item()), 1),
+            "model_entries": nz,
+            "encode_ms": round(timed["encode"], 4), "decode_ms": round(timed["decode"], 4),
+            "encode_group_ms": timed["encode_groups"], "decode_group_ms": timed["decode_groups"],
+            "decode_tokens_per_s": round(T / (timed["decode"] * 1e-3), 1),
+        }
+        say(f"coding {label}: {T} tokens, {W} words, decode {timed['decode']:.3f} ms")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -718,6 +817,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 1M sub-record's MLP / codec / SSIM / rate-variant legs")
     ap.add_argument("--no-c2", action="store_true", help="c5 only: skip the 1M sub-record")
+    ap.add_argument("--no-coding", action="store_true",
+                    help="c5 only: skip the coding-stage leg (octree tokens, rANS)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (scale for HBM counters)")
     args = ap.parse_args()

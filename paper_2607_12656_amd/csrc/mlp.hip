@@ -4,11 +4,14 @@
 // channel-wise fixed-length coder (Sec. 3.4.1).
 //
 // Formulation.  Every layer is computed transposed, H_out^T = W^T H_in^T,
-// with v_mfma_f32_32x32x8bf16_1k: A = 32 rows of W^T (a pre-swizzled BF16
-// fragment per lane, staged in LDS), B = 8 x 32 slice of H_in^T, D = 32 x 32
-// tile of H_out^T.  In the accumulator layout lane l holds batch column l%32
-// and output rows 8(i/4) + 4(l/32) + i%4 (i = 0..15), which is exactly the B
-// operand layout of the next layer's k-steps (rows 8s + 4(l/32) + 0..3), so
+// with v_mfma_f32_32x32x16_bf16 (CDNA4): A = 32 rows of W^T (a pre-swizzled
+// BF16 fragment per lane, staged in LDS), B = 16 x 32 slice of H_in^T, D =
+// 32 x 32 tile of H_out^T.  In the accumulator layout lane l holds batch
+// column l%32 and output rows 8(i/4) + 4(l/32) + i%4 (i = 0..15).  A k-step
+// of 16 takes, in lane half h = l/32, the rows 16p + 4h + 0..3 and
+// 16p + 8 + 4h + 0..3, i.e. accumulator elements 8p .. 8p + 7 of the lane:
+// the contraction only needs A and B to agree on which row each of the 16
+// k slots holds, and the weight fragments are packed in the same order, so
 // activations never leave registers between layers.  The same holds for the
 // backward to the inputs (dH1^T = W2 dZ2^T, dX^T = W1 dZ1^T).  Weight
 // gradients (training) are split-K GEMMs over the batch on transposed
@@ -20,38 +23,46 @@
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16v8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int MI = 64, MH = 128;
 constexpr int kOffW1 = 0, kOffB1 = MI * MH, kOffW2 = kOffB1 + MH, kOffB2 = kOffW2 + MH * MH,
               kOffW3 = kOffB2 + MH, kOffB3 = kOffW3 + MH, kParams = kOffB3 + 1;
 static_assert(kParams == SGS_MLP_PARAMS, "parameter count");
-// packed fragment arrays (bf16x4 per lane)
-constexpr int kF1 = 4 * 8 * 64;    // W1^T tiles  [t out 4][s in 8][lane]
-constexpr int kF2 = 4 * 16 * 64;   // W2^T tiles  [t out 4][s in 16][lane]
-constexpr int kF2B = 4 * 16 * 64;  // W2 tiles    [t in 4][s out 16][lane]
-constexpr int kF1B = 2 * 16 * 64;  // W1 tiles    [t in 2][s out 16][lane]
+// packed fragment arrays, counted in bf16x4 (two per lane and k-step of 16:
+// [t][p][lane][half], half = the two groups of four rows of k-step p)
+constexpr int kF1 = 4 * 8 * 64;    // W1^T tiles  [t out 4][p in 4][lane][2]
+constexpr int kF2 = 4 * 16 * 64;   // W2^T tiles  [t out 4][p in 8][lane][2]
+constexpr int kF2B = 4 * 16 * 64;  // W2 tiles    [t in 4][p out 8][lane][2]
+constexpr int kF1B = 2 * 16 * 64;  // W1 tiles    [t in 2][p out 8][lane][2]
 constexpr int kPacked = kF1 + kF2 + kF2B + kF1B;
 static_assert(kPacked * 8 == SGS_MLP_PACKED_BYTES, "packed size");
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// FP32 -> BF16, round to nearest even (the hardware conversion)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ float rbf(float f) { return bf2f(f2bf(f)); }
+typedef __bf16 bf16v4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
-  bf16x4 r;
-  r[0] = (short)f2bf(a);
-  r[1] = (short)f2bf(b);
-  r[2] = (short)f2bf(c);
-  r[3] = (short)f2bf(d);
-  return r;
+  const f32x4 v = {a, b, c, d};
+  return __builtin_bit_cast(bf16x4, __builtin_convertvector(v, bf16v4));
 }
-__device__ __forceinline__ f32x16 mfma(bf16x4 a, bf16x4 b, f32x16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+// One k-step of 16: A fragment a, B fragments b0 (rows 16p + 4h + 0..3) and
+// b1 (rows 16p + 8 + 4h + 0..3).
+__device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x4 b0, bf16x4 b1, f32x16 c) {
+  const bf16x8 b = __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, a),
+                                                 __builtin_bit_cast(bf16v8, b), c, 0, 0, 0);
 }
+__device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, a),
+                                                 __builtin_bit_cast(bf16v8, b), c, 0, 0, 0);
+}
+// 32-row tile t of a bias vector in the accumulator layout of lane l
+__device__ __forceinline__ f32x16 bias16(const float *b, int t, int lane);
 __device__ __forceinline__ f32x16 zero16() {
   f32x16 z;
 #pragma unroll
@@ -60,58 +71,65 @@ __device__ __forceinline__ f32x16 zero16() {
 }
 // output row of accumulator element i for lane l, within a 32-row tile
 __device__ __forceinline__ int drow(int i, int lane) { return 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3); }
+__device__ __forceinline__ f32x16 bias16(const float *b, int t, int lane) {
+  f32x16 z;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) z[i] = b[32 * t + drow(i, lane)];
+  return z;
+}
 
 // fp32 master weights -> BF16 fragments
 __global__ void k_mlp_pack(const float *__restrict__ th, bf16x4 *__restrict__ out) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= kPacked) return;
   const float *W1 = th + kOffW1, *W2 = th + kOffW2;
+  // e = ((t * P + p) * 64 + lane) * 2 + half, k-step of 8 s = 2p + half
   int r = e, lane, s, t;
   float v[4];
   if (r < kF1) {
-    lane = r & 63; s = (r >> 6) & 7; t = r >> 9;
+    lane = (r >> 1) & 63; s = 2 * ((r >> 7) & 3) + (r & 1); t = r >> 9;
     for (int j = 0; j < 4; ++j) v[j] = W1[(8 * s + 4 * (lane >> 5) + j) * MH + 32 * t + (lane & 31)];
   } else if ((r -= kF1) < kF2) {
-    lane = r & 63; s = (r >> 6) & 15; t = r >> 10;
+    lane = (r >> 1) & 63; s = 2 * ((r >> 7) & 7) + (r & 1); t = r >> 10;
     for (int j = 0; j < 4; ++j) v[j] = W2[(8 * s + 4 * (lane >> 5) + j) * MH + 32 * t + (lane & 31)];
   } else if ((r -= kF2) < kF2B) {
-    lane = r & 63; s = (r >> 6) & 15; t = r >> 10;
+    lane = (r >> 1) & 63; s = 2 * ((r >> 7) & 7) + (r & 1); t = r >> 10;
     for (int j = 0; j < 4; ++j) v[j] = W2[(32 * t + (lane & 31)) * MH + 8 * s + 4 * (lane >> 5) + j];
   } else {
     r -= kF2B;
-    lane = r & 63; s = (r >> 6) & 15; t = r >> 10;
+    lane = (r >> 1) & 63; s = 2 * ((r >> 7) & 7) + (r & 1); t = r >> 10;
     for (int j = 0; j < 4; ++j) v[j] = W1[(32 * t + (lane & 31)) * MH + 8 * s + 4 * (lane >> 5) + j];
   }
   out[e] = pack4(v[0], v[1], v[2], v[3]);
 }
 
 struct MlpLds {
-  bf16x4 F1[4][8][64];
-  bf16x4 F2[4][16][64];
+  bf16x8 F1[4][4][64];
+  bf16x8 F2[4][8][64];
   float b1[MH], b2[MH], w3[MH];
   float b3;
 };
 struct MlpLdsBwd {
   MlpLds f;
-  bf16x4 F2B[4][16][64];
-  bf16x4 F1B[2][16][64];
+  bf16x8 F2B[4][8][64];
+  bf16x8 F1B[2][8][64];
 };
 
 // Backward-only weights: W2 and W1 fragments and w3 (48.5 KB).
 struct MlpLdsB {
-  bf16x4 F2B[4][16][64];
-  bf16x4 F1B[2][16][64];
+  bf16x8 F2B[4][8][64];
+  bf16x8 F1B[2][8][64];
   float w3[MH];
 };
 __device__ void load_lds_b(MlpLdsB &L, const bf16x4 *__restrict__ packed,
                            const float *__restrict__ th) {
-  bf16x4 *d = &L.F2B[0][0][0];
+  bf16x4 *d = (bf16x4 *)&L.F2B[0][0][0];
   for (int e = threadIdx.x; e < kF2B + kF1B; e += blockDim.x) d[e] = packed[kF1 + kF2 + e];
   for (int k = threadIdx.x; k < MH; k += blockDim.x) L.w3[k] = rbf(th[kOffW3 + k]);
 }
 
 __device__ void load_lds(MlpLds &L, const bf16x4 *__restrict__ packed, const float *__restrict__ th) {
-  bf16x4 *d1 = &L.F1[0][0][0];
+  bf16x4 *d1 = (bf16x4 *)&L.F1[0][0][0];
   for (int e = threadIdx.x; e < kF1 + kF2; e += blockDim.x) d1[e] = packed[e];  // F1 then F2
   for (int k = threadIdx.x; k < MH; k += blockDim.x) {
     L.b1[k] = th[kOffB1 + k];
@@ -123,7 +141,7 @@ __device__ void load_lds(MlpLds &L, const bf16x4 *__restrict__ packed, const flo
 __device__ void load_lds_bwd(MlpLdsBwd &L, const bf16x4 *__restrict__ packed,
                              const float *__restrict__ th) {
   load_lds(L.f, packed, th);
-  bf16x4 *d = &L.F2B[0][0][0];
+  bf16x4 *d = (bf16x4 *)&L.F2B[0][0][0];
   for (int e = threadIdx.x; e < kF2B + kF1B; e += blockDim.x) d[e] = packed[kF1 + kF2 + e];
 }
 
@@ -132,11 +150,11 @@ __device__ void load_lds_bwd(MlpLdsBwd &L, const bf16x4 *__restrict__ packed,
 __device__ __forceinline__ float tile_fwd(const MlpLds &L, const bf16x4 xb[8], int lane,
                                           f32x16 z1[4], f32x16 z2[4], bf16x4 hb[16]) {
 #pragma unroll
-  for (int t = 0; t < 4; ++t) z1[t] = zero16();
+  for (int t = 0; t < 4; ++t) z1[t] = bias16(L.b1, t, lane);  // the sums start at the bias
 #pragma unroll
-  for (int s = 0; s < 8; ++s)
+  for (int p = 0; p < 4; ++p)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) z1[t] = mfma(L.F1[t][s][lane], xb[s], z1[t]);
+    for (int t = 0; t < 4; ++t) z1[t] = mfma(L.F1[t][p][lane], xb[2 * p], xb[2 * p + 1], z1[t]);
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -144,28 +162,23 @@ __device__ __forceinline__ float tile_fwd(const MlpLds &L, const bf16x4 xb[8], i
       float h[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int i = 4 * g + j;
-        const float z = z1[t][i] + L.b1[32 * t + drow(i, lane)];
-        z1[t][i] = z;
-        h[j] = fmaxf(z, 0.0f);
+        h[j] = fmaxf(z1[t][4 * g + j], 0.0f);
       }
       hb[4 * t + g] = pack4(h[0], h[1], h[2], h[3]);
     }
 #pragma unroll
-  for (int t = 0; t < 4; ++t) z2[t] = zero16();
+  for (int t = 0; t < 4; ++t) z2[t] = bias16(L.b2, t, lane);
 #pragma unroll
-  for (int s = 0; s < 16; ++s)
+  for (int p = 0; p < 8; ++p)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) z2[t] = mfma(L.F2[t][s][lane], hb[s], z2[t]);
+    for (int t = 0; t < 4; ++t) z2[t] = mfma(L.F2[t][p][lane], hb[2 * p], hb[2 * p + 1], z2[t]);
   float p = 0.0f;
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int o = 32 * t + drow(i, lane);
-      const float z = z2[t][i] + L.b2[o];
-      z2[t][i] = z;
-      p = fmaf(fmaxf(z, 0.0f), L.w3[o], p);
+      p = fmaf(fmaxf(z2[t][i], 0.0f), L.w3[o], p);
     }
   p += __shfl_xor(p, 32, 64);
   return p + L.b3;
@@ -180,13 +193,13 @@ __device__ __forceinline__ float tile_fwd_masks(const MlpLds &L, const bf16x4 xb
   f32x16 z[4];
   bf16x4 hb[16];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) z[t] = zero16();
+  for (int t = 0; t < 4; ++t) z[t] = bias16(L.b1, t, lane);  // the sums start at the bias
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
+  for (int p = 0; p < 4; ++p) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) z[t] = mfma(L.F1[t][s][lane], xb[s], z[t]);
+    for (int t = 0; t < 4; ++t) z[t] = mfma(L.F1[t][p][lane], xb[2 * p], xb[2 * p + 1], z[t]);
     // bound the fragments the compiler reads ahead (registers)
-    if ((s & 3) == 3) __asm__ volatile("" ::: "memory");
+    if ((p & 1) == 1) __asm__ volatile("" ::: "memory");
   }
   uint32_t mw[2] = {0u, 0u};  // the two 32-bit halves of m1
 #pragma unroll
@@ -197,7 +210,7 @@ __device__ __forceinline__ float tile_fwd_masks(const MlpLds &L, const bf16x4 xb
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int i = 4 * g + j;
-        const float zz = z[t][i] + L.b1[32 * t + drow(i, lane)];
+        const float zz = z[t][i];
         mw[t >> 1] |= zz > 0.0f ? 1u << (16 * (t & 1) + i) : 0u;
         h[j] = fmaxf(zz, 0.0f);
       }
@@ -205,13 +218,13 @@ __device__ __forceinline__ float tile_fwd_masks(const MlpLds &L, const bf16x4 xb
     }
   m1 = (uint64_t)mw[0] | ((uint64_t)mw[1] << 32);
 #pragma unroll
-  for (int t = 0; t < 4; ++t) z[t] = zero16();
+  for (int t = 0; t < 4; ++t) z[t] = bias16(L.b2, t, lane);
 #pragma unroll
-  for (int s = 0; s < 16; ++s) {
+  for (int p = 0; p < 8; ++p) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) z[t] = mfma(L.F2[t][s][lane], hb[s], z[t]);
+    for (int t = 0; t < 4; ++t) z[t] = mfma(L.F2[t][p][lane], hb[2 * p], hb[2 * p + 1], z[t]);
     // bound the fragments the compiler reads ahead (registers)
-    if ((s & 3) == 3) __asm__ volatile("" ::: "memory");
+    if ((p & 1) == 1) __asm__ volatile("" ::: "memory");
   }
   float p = 0.0f;
   uint32_t nw[2] = {0u, 0u};  // the two 32-bit halves of m2
@@ -220,7 +233,7 @@ __device__ __forceinline__ float tile_fwd_masks(const MlpLds &L, const bf16x4 xb
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int o = 32 * t + drow(i, lane);
-      const float zz = z[t][i] + L.b2[o];
+      const float zz = z[t][i];
       nw[t >> 1] |= zz > 0.0f ? 1u << (16 * (t & 1) + i) : 0u;
       p = fmaf(fmaxf(zz, 0.0f), L.w3[o], p);
     }
@@ -419,11 +432,11 @@ k_mlp_rate_bwd(int64_t n, int64_t npad, int64_t n_hat, float weight, float tau, 
       dh[0] = zero16();
       dh[1] = zero16();
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
+      for (int p = 0; p < 8; ++p) {
 #pragma unroll
         for (int tt = 0; tt < 2; ++tt)
-          dh[tt] = mfma(L.F2B[2 * half + tt][s][lane], dzb[s], dh[tt]);
-        if ((s & 3) == 3) __asm__ volatile("" ::: "memory");
+          dh[tt] = mfma(L.F2B[2 * half + tt][p][lane], dzb[2 * p], dzb[2 * p + 1], dh[tt]);
+        if ((p & 1) == 1) __asm__ volatile("" ::: "memory");
       }
       bf16x4 d1b[8];
 #pragma unroll
@@ -440,9 +453,9 @@ k_mlp_rate_bwd(int64_t n, int64_t npad, int64_t n_hat, float weight, float tau, 
           d1b[4 * tt + g] = pack4(v[0], v[1], v[2], v[3]);
         }
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        dx[0] = mfma(L.F1B[0][8 * half + s][lane], d1b[s], dx[0]);
-        dx[1] = mfma(L.F1B[1][8 * half + s][lane], d1b[s], dx[1]);
+      for (int p = 0; p < 4; ++p) {
+        dx[0] = mfma(L.F1B[0][4 * half + p][lane], d1b[2 * p], d1b[2 * p + 1], dx[0]);
+        dx[1] = mfma(L.F1B[1][4 * half + p][lane], d1b[2 * p], d1b[2 * p + 1], dx[1]);
       }
     }
     // chain to y and q: x = log2(1 + u), u = (y - m) / q.  Accumulator
@@ -495,17 +508,23 @@ k_mlp_rate_bwd(int64_t n, int64_t npad, int64_t n_hat, float weight, float tau, 
   }
 }
 
-__global__ void k_mlp_q_finish(int nb, const double *__restrict__ qpartial,
-                               float *__restrict__ gqstep) {
-  const int j = threadIdx.x;
-  if (j >= SGS_NCH) return;
+// Block j: channel j's step gradient, the per-block partials summed by
+// strided threads, then wave and block sums (fixed order).
+__global__ void __launch_bounds__(256)
+k_mlp_q_finish(int nb, const double *__restrict__ qpartial, float *__restrict__ gqstep) {
+  __shared__ double s_w[4];
+  const int j = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += qpartial[(int64_t)b * 64 + j];
-  gqstep[j] += (float)s;
+  for (int b = threadIdx.x; b < nb; b += 256) s += qpartial[(int64_t)b * 64 + j];
+  s = sgs_wave_sum_d(s);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) gqstep[j] += (float)(((s_w[0] + s_w[1]) + s_w[2]) + s_w[3]);
 }
 
-// Inference over given feature rows X [B][64] (BF16) -> f [B].
-__global__ void __launch_bounds__(kThreads, 2)
+// Inference over given feature rows X [B][64] (BF16) -> f [B].  Three
+// workgroups per compute unit (50 KB of LDS and at most 168 registers each).
+__global__ void __launch_bounds__(kThreads, 3)
 k_mlp_infer(int64_t B, const bf16x4 *__restrict__ packed, const float *__restrict__ th,
             const uint16_t *__restrict__ X, float *__restrict__ fout) {
   __shared__ MlpLds L;
@@ -608,9 +627,9 @@ k_mlp_train_rows(int64_t B, float scale, const bf16x4 *__restrict__ packed,
 #pragma unroll
     for (int t = 0; t < 4; ++t) dh[t] = zero16();
 #pragma unroll
-    for (int s = 0; s < 16; ++s)
+    for (int p = 0; p < 8; ++p)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) dh[t] = mfma(L.F2B[t][s][lane], dzb[s], dh[t]);
+      for (int t = 0; t < 4; ++t) dh[t] = mfma(L.F2B[t][p][lane], dzb[2 * p], dzb[2 * p + 1], dh[t]);
     if (valid) {
 #pragma unroll
       for (int t = 0; t < 4; ++t)
@@ -647,20 +666,21 @@ k_mlp_wgrad(int64_t B, int64_t chunk, const uint16_t *__restrict__ XT,
   const int64_t k0 = (int64_t)blockIdx.x * chunk;
   const int64_t k1 = min(B, k0 + chunk);
   const int row = 32 * wave + (lane & 31);
-  for (int64_t kb = k0; kb < k1; kb += 8) {
-    const int64_t k = kb + 4 * (lane >> 5);
-    bf16x4 a2, a1, bh[4], bx[2];
-    if (k + 3 < k1) {
-      a2 = *(const bf16x4 *)(DZ2T + (int64_t)row * B + k);
-      a1 = *(const bf16x4 *)(DZ1T + (int64_t)row * B + k);
+  for (int64_t kb = k0; kb < k1; kb += 16) {
+    // lane half h takes batch rows kb + 8h .. kb + 8h + 7 of both operands
+    const int64_t k = kb + 8 * (lane >> 5);
+    bf16x8 a2, a1, bh[4], bx[2];
+    if (k + 7 < k1) {
+      a2 = *(const bf16x8 *)(DZ2T + (int64_t)row * B + k);
+      a1 = *(const bf16x8 *)(DZ1T + (int64_t)row * B + k);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) bh[u] = *(const bf16x4 *)(H1T + (int64_t)(32 * u + (lane & 31)) * B + k);
+      for (int u = 0; u < 4; ++u) bh[u] = *(const bf16x8 *)(H1T + (int64_t)(32 * u + (lane & 31)) * B + k);
 #pragma unroll
-      for (int u = 0; u < 2; ++u) bx[u] = *(const bf16x4 *)(XT + (int64_t)(32 * u + (lane & 31)) * B + k);
+      for (int u = 0; u < 2; ++u) bx[u] = *(const bf16x8 *)(XT + (int64_t)(32 * u + (lane & 31)) * B + k);
     } else {
       // ragged tail: element-wise with zero fill
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < 8; ++j) {
         const bool ok = k + j < k1;
         a2[j] = ok ? (short)DZ2T[(int64_t)row * B + k + j] : (short)0;
         a1[j] = ok ? (short)DZ1T[(int64_t)row * B + k + j] : (short)0;
@@ -685,38 +705,76 @@ k_mlp_wgrad(int64_t B, int64_t chunk, const uint16_t *__restrict__ XT,
 }
 
 // Training, pass 3: fixed-order sums -> gradient of the flat parameter vector.
-//   blocks [0, 24): one weight tile each (sum over the GEMM partials);
-//   blocks [24, 24 + 385): bias / w3 entries as sums over the batch.
+//   blocks [0, 768): one row of 32 entries of one of the 24 weight tiles;
+//     thread (g, j) sums column j over the chunks of group g (eight groups
+//     of consecutive chunks), then the eight group sums are added in order;
+//   blocks [768, 768 + 385 kSeg): bias / w3 entries as sums over kSeg
+//     segments of the batch (per-segment sums, added by k_mlp_bias_finish).
+constexpr int kWRows = 24 * 32;
+constexpr int kSeg = 8;
+constexpr int64_t kLossParts = 1024;       // loss partials (one per row-kernel block)
+constexpr int64_t kSegParts = 385 * kSeg;  // bias / w3 segment sums
 __global__ void __launch_bounds__(kThreads)
 k_mlp_grad_finish(int64_t B, int nchunks, const float *__restrict__ partial,
-                  const uint16_t *__restrict__ H1T, const uint16_t *__restrict__ DZ2T,
-                  const uint16_t *__restrict__ DZ1T, const float *__restrict__ H2T,
-                  const float *__restrict__ df, float *__restrict__ g) {
+                  const uint16_t *__restrict__ DZ2T, const uint16_t *__restrict__ DZ1T,
+                  const float *__restrict__ H2T, const float *__restrict__ df,
+                  float *__restrict__ g, double *__restrict__ seg_part) {
   const int b = blockIdx.x;
-  if (b < 24) {
-    for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
-      double s = 0.0;
-      for (int c = 0; c < nchunks; ++c) s += partial[((int64_t)c * 24 + b) * 1024 + e];
-      const int i = e >> 5, j = e & 31;  // tile row (out), column (in)
-      if (b < 16) {
-        const int out = 32 * (b >> 2) + i, in = 32 * (b & 3) + j;
-        g[kOffW2 + in * MH + out] = (float)s;
+  if (b < kWRows) {
+    __shared__ double s_g[8][32];
+    const int tile = b >> 5, i = b & 31;  // tile row i (out)
+    const int j = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int per = (nchunks + 7) / 8;
+    const int c0 = min(nchunks, grp * per), c1 = min(nchunks, c0 + per);
+    const float *src = partial + (int64_t)tile * 1024 + i * 32 + j;
+    double s = 0.0;
+    // eight loads in flight per round, added in chunk order
+    for (int c = c0; c < c1; c += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = c + u < c1 ? src[(int64_t)(c + u) * 24 * 1024] : 0.0f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += (double)v[u];
+    }
+    s_g[grp][j] = s;
+    __syncthreads();
+    if (grp == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) t += s_g[k][j];
+      if (tile < 16) {
+        const int out = 32 * (tile >> 2) + i, in = 32 * (tile & 3) + j;
+        g[kOffW2 + in * MH + out] = (float)t;
       } else {
-        const int t = b - 16;
-        const int out = 32 * (t >> 1) + i, in = 32 * (t & 1) + j;
-        g[kOffW1 + in * MH + out] = (float)s;
+        const int t2 = tile - 16;
+        const int out = 32 * (t2 >> 1) + i, in = 32 * (t2 & 1) + j;
+        g[kOffW1 + in * MH + out] = (float)t;
       }
     }
     return;
   }
   __shared__ double s_w[kThreads / 64];
-  const int k = b - 24;  // 0..127 db1, 128..255 db2, 256..383 dw3, 384 db3
+  // bias / w3 entry k, segment seg of the batch rows
+  const int k = (b - kWRows) / kSeg, seg = (b - kWRows) % kSeg;
+  const int64_t per = (B + kSeg - 1) / kSeg;
+  const int64_t ra = min(B, seg * per), rb = min(B, ra + per);
+  // each thread adds rows ra + threadIdx.x + 256 m in ascending m, eight
+  // loads in flight per round
+  constexpr int U = 8;
   double s = 0.0;
-  for (int64_t r = threadIdx.x; r < B; r += blockDim.x) {
-    if (k < 128) s += (double)bf2f(DZ1T[(int64_t)k * B + r]);
-    else if (k < 256) s += (double)bf2f(DZ2T[(int64_t)(k - 128) * B + r]);
-    else if (k < 384) s += (double)df[r] * (double)H2T[(int64_t)(k - 256) * B + r];
-    else s += (double)df[r];
+  for (int64_t r0 = ra + threadIdx.x; r0 < rb; r0 += (int64_t)U * kThreads) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = r0 + (int64_t)u * kThreads;
+      const bool ok = r < rb;
+      if (k < 128) v[u] = ok ? (double)bf2f(DZ1T[(int64_t)k * B + r]) : 0.0;
+      else if (k < 256) v[u] = ok ? (double)bf2f(DZ2T[(int64_t)(k - 128) * B + r]) : 0.0;
+      else if (k < 384) v[u] = ok ? (double)df[r] * (double)H2T[(int64_t)(k - 256) * B + r] : 0.0;
+      else v[u] = ok ? (double)df[r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += v[u];
   }
   s = sgs_wave_sum_d(s);
   if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = s;
@@ -724,20 +782,38 @@ k_mlp_grad_finish(int64_t B, int nchunks, const float *__restrict__ partial,
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int w = 0; w < kThreads / 64; ++w) t += s_w[w];
-    if (k < 128) g[kOffB1 + k] = (float)t;
-    else if (k < 256) g[kOffB2 + (k - 128)] = (float)t;
-    else if (k < 384) g[kOffW3 + (k - 256)] = (float)t;
-    else g[kOffB3] = (float)t;
+    seg_part[k * kSeg + seg] = t;
   }
-  (void)H1T;
 }
 
-__global__ void k_mlp_loss_finish(int nb, const double *__restrict__ partial, int64_t B,
-                                  float *__restrict__ loss) {
-  if (threadIdx.x != 0) return;
+// Bias / w3 entries: the kSeg segment sums in order.
+__global__ void k_mlp_bias_finish(const double *__restrict__ seg_part, float *__restrict__ g) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 385) return;
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < kSeg; ++q) t += seg_part[k * kSeg + q];
+  if (k < 128) g[kOffB1 + k] = (float)t;
+  else if (k < 256) g[kOffB2 + (k - 128)] = (float)t;
+  else if (k < 384) g[kOffW3 + (k - 256)] = (float)t;
+  else g[kOffB3] = (float)t;
+}
+
+// Mean squared error from the per-block partials: a strided sum per thread,
+// then wave and block sums, all in a fixed order.
+__global__ void __launch_bounds__(kThreads)
+k_mlp_loss_finish(int nb, const double *__restrict__ partial, int64_t B, float *__restrict__ loss) {
+  __shared__ double s_w[kThreads / 64];
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += partial[b];
-  loss[0] = (float)(s / (double)B);
+  for (int b = threadIdx.x; b < nb; b += kThreads) s += partial[b];
+  s = sgs_wave_sum_d(s);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) t += s_w[w];
+    loss[0] = (float)(t / (double)B);
+  }
 }
 
 // Adam on the FP32 master parameters.
@@ -845,14 +921,15 @@ hipError_t launch_mlp_rate_bwd(sgs_ctx *c, const void *packed, const float *thet
                                                  (const bf16x4 *)packed, theta, params, q, stats,
                                                  hard, soft, c->mlp_f, c->mlp_signs, gparams,
                                                  gscore, gmask, c->red_tmp);
-  k_mlp_q_finish<<<1, 64, 0, c->stream>>>(nb, c->red_tmp, gqstep);
+  k_mlp_q_finish<<<SGS_NCH, 256, 0, c->stream>>>(nb, c->red_tmp, gqstep);
   return hipGetLastError();
 }
 
 hipError_t launch_mlp_infer(sgs_ctx *c, const void *packed, const float *theta,
                             const uint16_t *X, int64_t B, float *fout) {
   SgsProfScope ps(c, SGS_PROF_MLP_FWD);
-  k_mlp_infer<<<mlp_grid(B), kThreads, 0, c->stream>>>(B, (const bf16x4 *)packed, theta, X, fout);
+  k_mlp_infer<<<resident_grid(k_mlp_infer, B), kThreads, 0, c->stream>>>(B, (const bf16x4 *)packed,
+                                                                         theta, X, fout);
   return hipGetLastError();
 }
 
@@ -864,7 +941,7 @@ constexpr int64_t train_scratch_bytes(int64_t B) {
   // the takes of launch_mlp_train_step, each rounded up to 256 bytes (only
   // the B * 4 one can be ragged for B a multiple of 8)
   return B * (64 + 3 * 128) * 2 + B * 128 * 4 + B * 4 +
-         (B + kWgradChunk - 1) / kWgradChunk * 24 * 1024 * 4 + 4096 * 8 + 256;
+         (B + kWgradChunk - 1) / kWgradChunk * 24 * 1024 * 4 + (kLossParts + kSegParts) * 8 + 256;
 }
 
 int64_t mlp_train_scratch_bytes(int64_t B) { return train_scratch_bytes(B); }
@@ -927,15 +1004,16 @@ hipError_t launch_mlp_train_step(sgs_ctx *c, float *theta, float *m, float *v, v
   const int nchunks = (int)((B + chunk - 1) / chunk);
   float *part = (float *)take((int64_t)nchunks * 24 * 1024 * 4);
   const int nb = mlp_grid(B);
-  double *lpart = (double *)take(4096 * 8);
-  if (nb > 4096) return hipErrorInvalidValue;
+  double *lpart = (double *)take((kLossParts + kSegParts) * 8);
+  if (nb > kLossParts) return hipErrorInvalidValue;
   k_mlp_train_rows<<<nb, kThreads, 0, c->stream>>>(B, 2.0f / (float)B, (const bf16x4 *)packed,
                                                    theta, X, target, XT, H1T, DZ2T, DZ1T, H2T,
                                                    df, lpart);
-  k_mlp_loss_finish<<<1, 64, 0, c->stream>>>(nb, lpart, B, loss);
+  k_mlp_loss_finish<<<1, kThreads, 0, c->stream>>>(nb, lpart, B, loss);
   k_mlp_wgrad<<<nchunks, kThreads, 0, c->stream>>>(B, chunk, XT, H1T, DZ2T, DZ1T, part);
-  k_mlp_grad_finish<<<24 + 385, kThreads, 0, c->stream>>>(B, nchunks, part, H1T, DZ2T, DZ1T, H2T,
-                                                          df, gtheta);
+  k_mlp_grad_finish<<<kWRows + 385 * kSeg, kThreads, 0, c->stream>>>(
+      B, nchunks, part, DZ2T, DZ1T, H2T, df, gtheta, lpart + kLossParts);
+  k_mlp_bias_finish<<<2, 256, 0, c->stream>>>(lpart + kLossParts, gtheta);
   if (lr != 0.0f) {
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     const float c1 = (float)(1.0 - pow(0.9, (double)step));
