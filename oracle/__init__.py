@@ -126,6 +126,9 @@ def _declare(L):
         "orc_ans_ideal_bits": (F64, [P, I64, I32, I64, P]),
         "orc_ans_encode": (I64, [P, I64, I32, I64, P, P, P]),
         "orc_ans_decode": (I64, [P, P, I64, I32, I64, P, P]),
+        "orc_morton_order": (I64, [I64, I64, P, P, P, I32, P, P]),
+        "orc_attr_planes": (None, [I64, P, P, P, I64, I32, I64, P]),
+        "orc_attr_reconstruct": (None, [I64, P, I32, I64, I64, F32, P]),
     }
     for name, (res, args) in sig.items():
         if not hasattr(L, name):
@@ -587,3 +590,63 @@ def ans_decode(words, block_off, n: int, order: int, lane_len: int, freq):
     sym = np.zeros(max(n, 1), np.uint8)
     r = lib().orc_ans_decode(_p(words), _p(block_off), n, order, lane_len, _p(freq), _p(sym))
     return None if r < 0 else sym[:n].copy()
+
+
+# attributes [Sec. 3.4.2, autoregressive attribute coding]
+ATTR_CHANNELS = tuple(range(3, NCH))   # colour (DC and higher SH), opacity, scale, rotation
+
+
+def morton_order(y, q, mhat, n, depth, kmin):
+    """Indices of the kept Gaussians in the Morton order of their voxels
+    (ties by index)."""
+    y = np.ascontiguousarray(y, np.float32)
+    q = np.ascontiguousarray(q[:3], np.float32)
+    mhat = np.ascontiguousarray(mhat[:n], np.uint8)
+    kmin = np.ascontiguousarray(kmin, np.int64)
+    perm = np.zeros(max(n, 1), np.int64)
+    kept = lib().orc_morton_order(n, y.shape[1], _p(y), _p(q), _p(mhat), depth, _p(kmin),
+                                  _p(perm))
+    return perm[:kept].copy()
+
+
+def attr_plane_count(width: int) -> int:
+    """Byte planes of a channel whose values take `width` bits: the residual
+    of two such values zigzag-mapped takes width + 1 bits (none for width 0)."""
+    return 0 if width == 0 else (width + 1 + 7) // 8
+
+
+def attr_planes(y_row, q_c, perm, kmin: int, width: int, S: int):
+    """Zigzag DPCM byte planes [planes][kept] of one channel along perm."""
+    y_row = np.ascontiguousarray(y_row, np.float32)
+    perm = np.ascontiguousarray(perm, np.int64)
+    P = attr_plane_count(width)
+    out = np.zeros((max(P, 1), perm.size), np.uint8)
+    qc = np.array([q_c], np.float32)
+    lib().orc_attr_planes(perm.size, _p(y_row), _p(qc), _p(perm), int(kmin), P, S, _p(out))
+    return out[:P].copy()
+
+
+def attr_reconstruct(planes, kmin: int, q_c: float, S: int, kept: int):
+    planes = np.ascontiguousarray(planes, np.uint8)
+    P = planes.shape[0] if planes.ndim == 2 else 0
+    out = np.zeros(max(kept, 1), np.float32)
+    if P == 0:
+        out[:] = np.float32(np.float32(kmin) * np.float32(q_c))
+        return out[:kept]
+    lib().orc_attr_reconstruct(kept, _p(planes), P, S, int(kmin), np.float32(q_c), _p(out))
+    return out[:kept].copy()
+
+
+def fourier_features(mu, L: int = 12):
+    """phi(mu) = [mu; sin(2 pi F mu); cos(2 pi F mu)], F = (2^0 .. 2^(L-1)),
+    per Gaussian: [n][3 + 6L] in FP64 (sin block: band-major, axis-minor)."""
+    mu = np.asarray(mu, np.float64).reshape(-1, 3)
+    F = 2.0 ** np.arange(L)
+    ang = 2.0 * np.pi * mu[:, None, :] * F[None, :, None]          # [n][L][3]
+    return np.concatenate([mu, np.sin(ang).reshape(len(mu), -1),
+                           np.cos(ang).reshape(len(mu), -1)], axis=1)
+
+
+def positional_embedding(mu, W, b, L: int = 12):
+    """PE(mu) = W phi(mu) + b (W [d][3 + 6L], b [d]) in FP64."""
+    return fourier_features(mu, L) @ np.asarray(W, np.float64).T + np.asarray(b, np.float64)

@@ -330,3 +330,74 @@ int64_t orc_voxel_positions(const uint64_t *codes, const uint32_t *dup, int64_t 
   }
   return o;
 }
+
+/* ---- attributes [Sec. 3.4.2, autoregressive attribute coding] ------------ */
+typedef struct {
+  uint64_t code;
+  int64_t idx;
+} code_idx;
+
+static int code_idx_less(const void *a, const void *b) {
+  const code_idx *x = (const code_idx *)a, *y = (const code_idx *)b;
+  if (x->code != y->code) return x->code < y->code ? -1 : 1;
+  return x->idx < y->idx ? -1 : (x->idx > y->idx);
+}
+
+/* Morton order of the kept Gaussians: perm [kept] lists their indices by
+ * voxel code (the octree's, with kmin and depth as orc_octree_tokens finds
+ * them), Gaussians of one voxel by index.  Returns the kept count. */
+int64_t orc_morton_order(int64_t n, int64_t npad, const float *y, const float *q,
+                         const uint8_t *mhat, int32_t depth, const int64_t *kmin, int64_t *perm) {
+  code_idx *a = (code_idx *)malloc(sizeof(code_idx) * (size_t)(n > 0 ? n : 1));
+  int64_t kept = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!mhat[i]) continue;
+    uint32_t u[3];
+    for (int c = 0; c < 3; ++c) {
+      float r = rintf(y[c * npad + i] / q[c]);
+      if (!(r >= -2147483648.0f && r < 2147483648.0f)) r = 0.0f;
+      u[c] = (uint32_t)((int64_t)r - kmin[c]);
+    }
+    a[kept].code = orc_morton3(u[0], u[1], u[2], depth);
+    a[kept].idx = i;
+    ++kept;
+  }
+  qsort(a, (size_t)kept, sizeof(code_idx), code_idx_less);
+  for (int64_t j = 0; j < kept; ++j) perm[j] = a[j].idx;
+  free(a);
+  return kept;
+}
+
+/* Byte planes of one attribute channel in serialized order: v_j = k - kmin
+ * (the fixed-length coder's value, k = rint(fl32(y / q))), predicted by the
+ * previous Gaussian of the same group of S (0 for a group's first), the
+ * residual zigzag-mapped (d >= 0 -> 2d, d < 0 -> -2d - 1) and cut into
+ * `planes` bytes, most significant first: out [planes][kept]. */
+void orc_attr_planes(int64_t kept, const float *yc, const float *qc, const int64_t *perm,
+                     int64_t kmin, int32_t planes, int64_t S, uint8_t *out) {
+  int64_t prev = 0;
+  for (int64_t j = 0; j < kept; ++j) {
+    const float r = rintf(yc[perm[j]] / qc[0]);
+    const int64_t v = (int64_t)r - kmin;
+    const int64_t pred = j % S == 0 ? 0 : prev;
+    const int64_t d = v - pred;
+    const uint64_t z = d >= 0 ? (uint64_t)(2 * d) : (uint64_t)(-2 * d - 1);
+    for (int t = 0; t < planes; ++t)
+      out[(int64_t)t * kept + j] = (uint8_t)(z >> (8 * (planes - 1 - t)));
+    prev = v;
+  }
+}
+
+/* Inverse: the dequantized values fl32((kmin + v) q) in serialized order. */
+void orc_attr_reconstruct(int64_t kept, const uint8_t *pl, int32_t planes, int64_t S, int64_t kmin,
+                          float q, float *out) {
+  int64_t prev = 0;
+  for (int64_t j = 0; j < kept; ++j) {
+    uint64_t z = 0;
+    for (int t = 0; t < planes; ++t) z = (z << 8) | pl[(int64_t)t * kept + j];
+    const int64_t d = (z & 1u) ? -(int64_t)((z + 1) / 2) : (int64_t)(z / 2);
+    const int64_t v = (j % S == 0 ? 0 : prev) + d;
+    out[j] = (float)(kmin + v) * q;
+    prev = v;
+  }
+}

@@ -276,3 +276,95 @@ def test_decode_rejects_damage(orc):
     g = np.zeros_like(f)
     g[:, 200] = 4096
     assert orc.ans_decode(w, off, sym.size, 1, 64, g) is None
+
+
+# ---------------------------------------------------------------------------
+# attributes: Morton order, DPCM byte planes, Fourier positional embedding
+# ---------------------------------------------------------------------------
+def test_morton_order_hand_example(orc):
+    y, q, m, n = one_point_cloud([(3, 3, 3), (0, 0, 0), (1, 0, 0), (0, 0, 0), (2, 2, 2)])
+    m[4] = 0                                   # not kept
+    r = orc.octree_tokens(y, q, m, n)
+    perm = orc.morton_order(y, q, m, n, r["depth"], r["kmin"])
+    # codes 63, 0, 4, 0: by code, then index
+    assert list(perm) == [1, 3, 2, 0]
+
+
+def test_morton_order_matches_octree(orc):
+    rng = np.random.default_rng(21)
+    n = 6000
+    y = np.zeros((59, synth.pad64(n)), np.float32)
+    y[:3, :n] = rng.normal(0, 0.3, (3, n))
+    q = np.full(59, 0.05, np.float32)
+    m = (rng.random(n) < 0.7).astype(np.uint8)
+    r = orc.octree_tokens(y, q, m, n)
+    perm = orc.morton_order(y, q, m, n, r["depth"], r["kmin"])
+    assert sorted(perm) == list(np.nonzero(m)[0])
+    # voxels along the order: the octree's distinct codes with their copies
+    yhat, k = orc.fakequant(y, q, n)
+    got = np.unique(k[:3, perm].T, axis=0, return_index=True)[1]
+    assert len(got) == r["unique"]
+    xyz = orc.voxel_positions(r["codes"], r["dup"], r["depth"], r["kmin"], q)
+    assert np.array_equal(xyz, yhat[:3, perm])
+    # ties (copies of one voxel) by index
+    kk = [tuple(k[:3, i]) for i in perm]
+    for a in range(1, len(perm)):
+        if kk[a] == kk[a - 1]:
+            assert perm[a] > perm[a - 1]
+
+
+def test_attr_planes_hand_example(orc):
+    # values v = k - kmin = [5, 7, 6, 6 | 2], groups of 4: residuals 5, 2, -1,
+    # 0 | 2 -> zigzag 10, 4, 1, 0 | 4; width 3 -> one plane
+    y = np.array([5, 7, 6, 6, 2], np.float32)
+    perm = np.arange(5)
+    pl = orc.attr_planes(y, 1.0, perm, 0, 3, 4)
+    assert pl.shape == (1, 5) and list(pl[0]) == [10, 4, 1, 0, 4]
+    # width 8 -> two planes, most significant first; kmin shifts the values
+    y = np.array([300, 40, 299], np.float32)
+    pl = orc.attr_planes(y, 1.0, np.arange(3), 40, 8, 64)
+    z = [2 * 260, 2 * 260 - 1, 2 * 259]          # 260, then -260, then +259
+    assert list(pl[0]) == [v >> 8 for v in z] and list(pl[1]) == [v & 255 for v in z]
+    assert orc.attr_plane_count(0) == 0 and orc.attr_plane_count(7) == 1
+    assert orc.attr_plane_count(8) == 2 and orc.attr_plane_count(32) == 5
+
+
+@pytest.mark.parametrize("S", [1, 7, 256])
+def test_attr_round_trip_equals_quantizer(orc, S):
+    sc = synth.make_tiny(3000, 32, 32, seed=4)
+    q = synth.learnable_qsteps(5)
+    m = sc.given_mask
+    n = sc.n
+    yhat, k = orc.fakequant(sc.params, q, n)
+    bits, kmin, kmax, width = orc.fixed_length_bits(k, m, n)
+    r = orc.octree_tokens(sc.params, q, m, n)
+    perm = orc.morton_order(sc.params, q, m, n, r["depth"], r["kmin"])
+    for c in orc.ATTR_CHANNELS:
+        pl = orc.attr_planes(sc.params[c], q[c], perm, kmin[c], width[c], S)
+        assert pl.shape[0] == orc.attr_plane_count(int(width[c]))
+        back = orc.attr_reconstruct(pl, kmin[c], q[c], S, perm.size)
+        assert np.array_equal(back, yhat[c, perm]), c
+
+
+def test_fourier_features_closed_form(orc):
+    L = 12
+    phi = orc.fourier_features(np.array([[0.0, 0.25, -0.5]]), L)
+    assert phi.shape == (1, 3 + 6 * L)
+    s = phi[0, 3:3 + 3 * L].reshape(L, 3)
+    c = phi[0, 3 + 3 * L:].reshape(L, 3)
+    # x = 0: sin 0, cos 1 in every band
+    assert np.allclose(s[:, 0], 0, atol=1e-15) and np.allclose(c[:, 0], 1, atol=1e-15)
+    # y = 1/4: band 0 at pi/2, band 1 at pi, then whole turns
+    assert np.isclose(s[0, 1], 1) and np.isclose(c[1, 1], -1)
+    assert np.allclose(s[1:, 1], 0, atol=1e-12) and np.allclose(c[2:, 1], 1, atol=1e-12)
+    # z = -1/2: band 0 at -pi
+    assert np.isclose(c[0, 2], -1) and np.allclose(c[1:, 2], 1, atol=1e-12)
+    # the linear map picks features: PE = W phi + b
+    W = np.zeros((32, 3 + 6 * L))
+    W[0, 0] = 2.0           # 2 mu_x
+    W[1, 3 + 3 * 0 + 1] = 1.0   # sin band 0 of y
+    W[2, 3 + 3 * L + 3 * 1 + 1] = -1.0  # -cos band 1 of y
+    b = np.arange(32, dtype=np.float64)
+    pe = orc.positional_embedding(np.array([[0.5, 0.25, 0.0]]), W, b, L)
+    assert np.allclose(pe[0, :3], [1.0 + 0, 1.0 + 1, 1.0 + 2])
+    assert np.allclose(pe[0, 3:], b[3:])
