@@ -238,6 +238,10 @@ int64_t orc_ans_encode(const uint8_t *sym, int64_t n, int32_t order, int64_t lan
   const int64_t S = lane_len, B = 64 * lane_len;
   const int64_t nb = (n + B - 1) / B;
   uint16_t *stack = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)(B + 1));
+  /* cumulative frequencies of every context, once */
+  uint32_t *cum = (uint32_t *)malloc(sizeof(uint32_t) * ANS_CTX * 256);
+  for (int x = 0; x < ANS_CTX; ++x)
+    for (int s2 = 0; s2 < 256; ++s2) cum[x * 256 + s2] = cum_at(freq + (size_t)x * 256, s2);
   int64_t out = 0;
   for (int64_t b = 0; b < nb; ++b) {
     uint32_t x[64];
@@ -248,10 +252,11 @@ int64_t orc_ans_encode(const uint8_t *sym, int64_t n, int32_t order, int64_t lan
       for (int l = 63; l >= 0; --l) {
         const int64_t i = b * B + l * S + t;
         if (i >= n) continue;
-        const uint16_t *row = freq + (size_t)ctx_of(sym, i, S, order) * 256;
-        const uint32_t f = row[sym[i]];
+        const int ctx = ctx_of(sym, i, S, order);
+        const uint32_t f = freq[(size_t)ctx * 256 + sym[i]];
         if (!f) {
           free(stack);
+          free(cum);
           return -1;
         }
         const uint64_t xmax = ((uint64_t)(ANS_L >> ANS_PB) << 16) * f;
@@ -259,7 +264,7 @@ int64_t orc_ans_encode(const uint8_t *sym, int64_t n, int32_t order, int64_t lan
           stack[top++] = (uint16_t)(x[l] & 0xFFFFu);
           x[l] >>= 16;
         }
-        x[l] = ((x[l] / f) << ANS_PB) + (x[l] % f) + cum_at(row, sym[i]);
+        x[l] = ((x[l] / f) << ANS_PB) + (x[l] % f) + cum[ctx * 256 + sym[i]];
       }
     block_off[b] = out;
     for (int l = 0; l < 64; ++l) {
@@ -270,6 +275,7 @@ int64_t orc_ans_encode(const uint8_t *sym, int64_t n, int32_t order, int64_t lan
   }
   block_off[nb] = out;
   free(stack);
+  free(cum);
   return out;
 }
 
