@@ -581,6 +581,69 @@ sgs_status sgs_ans_decode(sgs_ctx *ctx, const uint16_t *words, int64_t n_words,
                           const int64_t *block_off, int64_t n, int32_t order, int32_t lane_len,
                           const uint16_t *freq, uint8_t *sym, int64_t *info);
 
+/* Several streams decoded in one launch (one wave per block of every
+ * stream).  Each descriptor names one stream as sgs_ans_decode takes it;
+ * info: device int64[count] of per-stream flags (as sgs_ans_decode's).  The
+ * descriptors are read from host memory before the call returns (it
+ * synchronizes the context's stream). */
+typedef struct {
+  const uint16_t *words;     /* device */
+  int64_t n_words;
+  const int64_t *block_off;  /* device [blocks + 1] */
+  int64_t n;                 /* symbols */
+  const uint16_t *freq;      /* device [257][256] */
+  uint8_t *sym;              /* device [n], output */
+  int32_t order;             /* 0 or 1 */
+  int32_t lane_len;          /* 1 .. 65536 */
+} sgs_ans_stream;
+sgs_status sgs_ans_decode_multi(sgs_ctx *ctx, int32_t count, const sgs_ans_stream *streams,
+                                int64_t *info);
+
+/* Attributes (Sec. 3.4.2, autoregressive attribute coding): the kept
+ * Gaussians are serialized in the Morton order of their voxels, and each
+ * token a_i = [colour, opacity, scale, rotation] (channels 3-58) is coded
+ * from its predecessor within a group of lane_len Gaussians (the groups
+ * decode in parallel).  The paper's conditional model is a causal state
+ * space model fed with the decoded attributes and positional embeddings;
+ * here the prediction is the previous token (per channel: residual of the
+ * fixed-length coder's value v = k - kmin against the group's previous
+ * value, 0 for a group's first; zigzag-mapped, d >= 0 -> 2d, d < 0 -> -2d -
+ * 1) and the residual's bytes are entropy-coded as separate streams
+ * ("planes", most significant first): a channel of width w bits (the fixed-
+ * length coder's, sgs_fl_encode) gives ceil((w + 1) / 8) planes, none for
+ * w = 0.  Plane rows follow the channels in order.
+ *
+ * Morton order: perm [kept] (device int32) receives the kept Gaussians'
+ * indices by voxel code (header: HOST copy of sgs_octree_encode's; codes:
+ * its distinct voxel codes, device), Gaussians of one voxel by index. */
+sgs_status sgs_morton_order(sgs_ctx *ctx, const float *params, int64_t npad, int64_t n,
+                            const float *qstep, const uint8_t *hard_mask,
+                            const sgs_octree_header *header, const uint64_t *codes,
+                            int32_t *perm);
+/* Plane rows of a fixed-length header (HOST sgs_fl_channel[59]). */
+int64_t sgs_attr_plane_rows(const sgs_fl_channel *fl_header);
+/* Planes: planes [rows][kept] (device bytes) for the Gaussians perm [kept]
+ * lists, in that order; fl_header: HOST copy of sgs_fl_encode's for the same
+ * parameters, steps and mask. */
+sgs_status sgs_attr_planes(sgs_ctx *ctx, const float *params, int64_t npad, const int32_t *perm,
+                           int64_t kept, const sgs_fl_channel *fl_header, int32_t lane_len,
+                           uint8_t *planes);
+/* Inverse: out [59][out_pad] (device, out_pad >= kept) rows 3-58 receive the
+ * dequantized attributes fl32((kmin + v) q) in serialized order (rows 0-2,
+ * the positions, are sgs_octree_decode's xyz). */
+sgs_status sgs_attr_reconstruct(sgs_ctx *ctx, const uint8_t *planes, int64_t kept,
+                                const sgs_fl_channel *fl_header, int32_t lane_len, float *out,
+                                int64_t out_pad);
+/* Fourier positional embedding (Sec. 3.4.2): PE(mu) = W phi(mu) + b with
+ * phi(mu) = [mu; sin(2 pi f_l mu); cos(2 pi f_l mu)], f_l = 2^l for l < L
+ * (band-major, axis-minor: feature 3 + 3 l + c is sin of axis c in band l,
+ * 3 + 3 L + 3 l + c its cosine), 3 + 6 L features.  xyz [3][pad] (device),
+ * W [d][3 + 6L] and b [d] (device FP32), out [count][d] (device FP32, 16-byte
+ * aligned).  1 <= L <= 16; d a multiple of 4, at most 64. */
+sgs_status sgs_positional_embedding(sgs_ctx *ctx, const float *xyz, int64_t pad, int64_t count,
+                                    int32_t L, int32_t d, const float *W, const float *b,
+                                    float *out);
+
 /* Kernel-group timing with HIP events recorded on the context's stream around
  * each group's launches (no extra synchronization inside a step).  Groups: */
 enum {

@@ -60,6 +60,16 @@ class sgs_octree_header(C.Structure):
                 ("flags", C.c_int64), ("level_size", C.c_int64 * 21)]
 
 
+class sgs_fl_channel(C.Structure):
+    _fields_ = [("q", C.c_float), ("kmin", C.c_int32), ("width", C.c_int32)]
+
+
+class sgs_ans_stream(C.Structure):
+    _fields_ = [("words", C.c_void_p), ("n_words", C.c_int64), ("block_off", C.c_void_p),
+                ("n", C.c_int64), ("freq", C.c_void_p), ("sym", C.c_void_p),
+                ("order", C.c_int32), ("lane_len", C.c_int32)]
+
+
 OCTREE_HEADER_WORDS = C.sizeof(sgs_octree_header) // 8
 assert OCTREE_HEADER_WORDS == 30
 
@@ -121,6 +131,12 @@ _SIGS = {
     "sgs_ans_model": [P, P, I64, I32, I32, P, P],
     "sgs_ans_encode": [P, P, I64, I32, I32, P, P, I64, P, P],
     "sgs_ans_decode": [P, P, I64, P, I64, I32, I32, P, P, P],
+    "sgs_ans_decode_multi": [P, I32, P, P],
+    "sgs_morton_order": [P, P, I64, I64, P, P, P, P, P],
+    "sgs_attr_plane_rows": [P],
+    "sgs_attr_planes": [P, P, I64, P, I64, P, I32, P],
+    "sgs_attr_reconstruct": [P, P, I64, P, I32, P, I64],
+    "sgs_positional_embedding": [P, P, I64, I64, I32, I32, P, P, P],
 }
 PROF_GROUPS = ("fakequant", "rate", "preprocess", "depth_sort", "scan", "duplicate",
                "tile_sort", "ranges", "blend_fwd", "l1", "grad_clear", "blend_bwd",
@@ -148,7 +164,8 @@ def lib(path: str | None = None):
         f.argtypes = args
         f.restype = {"sgs_last_error": C.c_char_p, "sgs_destroy": None, "sgs_graph_destroy": None,
                      "sgs_rate_mlp_train_scratch_bytes": C.c_int64,
-                     "sgs_ans_max_words": C.c_int64}.get(name, C.c_int)
+                     "sgs_ans_max_words": C.c_int64,
+                     "sgs_attr_plane_rows": C.c_int64}.get(name, C.c_int)
     if path is None:
         _lib = L
     return L
@@ -426,6 +443,47 @@ class Context:
         self._check(self.L.sgs_ans_decode(self.h, _ptr(words), n_words, _ptr(block_off), n,
                                           order, lane_len, _ptr(freq), _ptr(sym), _ptr(info)),
                     self.h)
+
+    def ans_decode_multi(self, streams, info):
+        """streams: dicts with words, n_words, block_off, n, freq, sym, order,
+        lane_len (tensors for the buffers)."""
+        arr = (sgs_ans_stream * max(len(streams), 1))()
+        for i, d in enumerate(streams):
+            arr[i] = sgs_ans_stream(_ptr(d["words"]), d["n_words"], _ptr(d["block_off"]), d["n"],
+                                    _ptr(d["freq"]), _ptr(d["sym"]), d["order"], d["lane_len"])
+        self._check(self.L.sgs_ans_decode_multi(self.h, len(streams), arr, _ptr(info)), self.h)
+
+    def morton_order(self, params, npad, n, qstep, hard_mask, header: sgs_octree_header, codes,
+                     perm):
+        self._check(self.L.sgs_morton_order(self.h, _ptr(params), npad, n, _ptr(qstep),
+                                            _ptr(hard_mask), C.byref(header), _ptr(codes),
+                                            _ptr(perm)), self.h)
+
+    @staticmethod
+    def fl_header_host(hdr) -> "C.Array":
+        """Host sgs_fl_channel[59] from the encoder's int32 [59][3] header."""
+        v = np.ascontiguousarray(np.asarray(hdr).reshape(59, 3), dtype=np.int32)
+        arr = (sgs_fl_channel * 59)()
+        C.memmove(arr, v.ctypes.data, v.nbytes)
+        return arr
+
+    def attr_plane_rows(self, fl) -> int:
+        r = int(self.L.sgs_attr_plane_rows(fl))
+        if r < 0:
+            raise SgsError(-1, "attr_plane_rows: bad header")
+        return r
+
+    def attr_planes(self, params, npad, perm, kept, fl, lane_len, planes):
+        self._check(self.L.sgs_attr_planes(self.h, _ptr(params), npad, _ptr(perm), kept, fl,
+                                           lane_len, _ptr(planes)), self.h)
+
+    def attr_reconstruct(self, planes, kept, fl, lane_len, out, out_pad):
+        self._check(self.L.sgs_attr_reconstruct(self.h, _ptr(planes), kept, fl, lane_len,
+                                                _ptr(out), out_pad), self.h)
+
+    def positional_embedding(self, xyz, pad, count, L, d, W, b, out):
+        self._check(self.L.sgs_positional_embedding(self.h, _ptr(xyz), pad, count, L, d, _ptr(W),
+                                                    _ptr(b), _ptr(out)), self.h)
 
     def rate_variant(self, params, qstep, stats, rate_weight, out3, rate_grad=None,
                      proxy="range", masking="mult", alpha=0.0):

@@ -722,6 +722,98 @@ sgs_status sgs_ans_decode(sgs_ctx *c, const uint16_t *words, int64_t n_words,
   return SGS_OK;
 }
 
+sgs_status sgs_ans_decode_multi(sgs_ctx *c, int32_t count, const sgs_ans_stream *st,
+                                int64_t *info) {
+  if (!c) return SGS_EINVAL;
+  if (count < 0 || count > 65535) return fail(c, SGS_EINVAL, "ans_decode_multi: bad count");
+  if (count > 0 && (!st || !info)) return fail(c, SGS_EINVAL, "ans_decode_multi: null pointer");
+  for (int32_t i = 0; i < count; ++i) {
+    sgs_status r = ans_args(c, "ans_decode_multi", st[i].n, st[i].order, st[i].lane_len);
+    if (r != SGS_OK) return r;
+    if (!st[i].freq || !st[i].block_off || (st[i].n > 0 && (!st[i].sym || !st[i].words)) ||
+        st[i].n_words < 0)
+      return fail(c, SGS_EINVAL, "ans_decode_multi: stream %d: bad descriptor", (int)i);
+  }
+  if (count == 0) return SGS_OK;
+  SgsProfScope ps(c, SGS_PROF_ANS);
+  SGS_HIP(launch_ans_decode_multi(c, count, st, info), "ans_decode_multi");
+  return SGS_OK;
+}
+
+sgs_status sgs_morton_order(sgs_ctx *c, const float *params, int64_t npad, int64_t n,
+                            const float *qstep, const uint8_t *hard_mask,
+                            const sgs_octree_header *h, const uint64_t *codes, int32_t *perm) {
+  if (!c) return SGS_EINVAL;
+  if (c->capturing) return fail(c, SGS_ESTATE, "morton_order: not inside graph capture");
+  if (!params || !qstep || !hard_mask || !h || (h->kept > 0 && (!codes || !perm)))
+    return fail(c, SGS_EINVAL, "morton_order: null pointer");
+  if (n < 1 || npad < n || n > (int64_t)INT32_MAX)
+    return fail(c, SGS_EINVAL, "morton_order: need 1 <= n <= npad, n < 2^31");
+  if (h->depth < 1 || h->depth > 21 || h->flags != 0 || h->kept < 0 || h->kept > n ||
+      h->unique < 0 || h->unique > h->kept)
+    return fail(c, SGS_EINVAL, "morton_order: bad header");
+  SgsProfScope ps(c, SGS_PROF_OCTREE);
+  SGS_HIP(launch_morton_order(c, params, npad, n, qstep, hard_mask, h, codes, perm),
+          "morton_order");
+  return SGS_OK;
+}
+
+static bool fl_header_ok(const sgs_fl_channel *fl) {
+  for (int j = 0; j < 59; ++j)
+    if (fl[j].width < 0 || fl[j].width > 32) return false;
+  return true;
+}
+
+int64_t sgs_attr_plane_rows(const sgs_fl_channel *fl) {
+  if (!fl || !fl_header_ok(fl)) return -1;
+  return attr_plane_rows(fl);
+}
+
+sgs_status sgs_attr_planes(sgs_ctx *c, const float *params, int64_t npad, const int32_t *perm,
+                           int64_t kept, const sgs_fl_channel *fl, int32_t lane_len,
+                           uint8_t *planes) {
+  if (!c) return SGS_EINVAL;
+  if (!params || !fl || (kept > 0 && (!perm || !planes)))
+    return fail(c, SGS_EINVAL, "attr_planes: null pointer");
+  if (kept < 0 || kept > npad || kept > (int64_t)INT32_MAX || lane_len < 1 || lane_len > 65536 ||
+      !fl_header_ok(fl))
+    return fail(c, SGS_EINVAL, "attr_planes: bad sizes or header");
+  SgsProfScope ps(c, SGS_PROF_ANS);
+  SGS_HIP(launch_attr_planes(c, params, npad, perm, kept, fl, lane_len, planes), "attr_planes");
+  return SGS_OK;
+}
+
+sgs_status sgs_attr_reconstruct(sgs_ctx *c, const uint8_t *planes, int64_t kept,
+                                const sgs_fl_channel *fl, int32_t lane_len, float *out,
+                                int64_t out_pad) {
+  if (!c) return SGS_EINVAL;
+  if (!fl || (kept > 0 && !out) || (kept > 0 && attr_plane_rows(fl) > 0 && !planes))
+    return fail(c, SGS_EINVAL, "attr_reconstruct: null pointer");
+  if (kept < 0 || out_pad < kept || kept > (int64_t)INT32_MAX || lane_len < 1 ||
+      lane_len > 65536 || !fl_header_ok(fl))
+    return fail(c, SGS_EINVAL, "attr_reconstruct: bad sizes or header");
+  SgsProfScope ps(c, SGS_PROF_ANS);
+  SGS_HIP(launch_attr_reconstruct(c, planes, kept, fl, lane_len, out, out_pad),
+          "attr_reconstruct");
+  return SGS_OK;
+}
+
+sgs_status sgs_positional_embedding(sgs_ctx *c, const float *xyz, int64_t pad, int64_t count,
+                                    int32_t L, int32_t d, const float *W, const float *b,
+                                    float *out) {
+  if (!c) return SGS_EINVAL;
+  if (count > 0 && (!xyz || !W || !b || !out))
+    return fail(c, SGS_EINVAL, "positional_embedding: null pointer");
+  if (count < 0 || pad < count || L < 1 || L > 16 || d < 4 || d > 64 || d % 4 != 0 ||
+      !aligned(out, 16))
+    return fail(c, SGS_EINVAL,
+                "positional_embedding: need 0 <= count <= pad, 1 <= L <= 16, d in {4, 8, .., 64}, "
+                "out 16-byte aligned");
+  SgsProfScope ps(c, SGS_PROF_ANS);
+  SGS_HIP(launch_pos_embed(c, xyz, pad, count, L, d, W, b, out), "positional_embedding");
+  return SGS_OK;
+}
+
 sgs_status sgs_autotune(sgs_ctx *c, const float *params, const float *qstep,
                         const uint8_t *given_mask, const float *target, int32_t reps,
                         sgs_options *chosen, float *ms_out) {

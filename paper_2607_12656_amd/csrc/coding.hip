@@ -25,6 +25,8 @@
 // the block's next words in lane order (a ballot and a popcount).  The
 // encoder runs the same steps backwards, lanes descending, which is what
 // puts the words in that order.  Blocks decode independently.
+#include <vector>
+
 #include "sgs_internal.h"
 
 namespace {
@@ -568,10 +570,10 @@ k_ans_enc_table(const uint16_t *__restrict__ freq, uint32_t *__restrict__ tab, i
 
 // Decoder table: slot -> sym | (f - 1) << 8 | cum << 20 per context (kNoSym
 // where no symbol owns the slot); flags bit 2 for a row not summing to M.
-__global__ void __launch_bounds__(256)
-k_ans_dec_table(const uint16_t *__restrict__ freq, uint32_t *__restrict__ tab, int64_t *info) {
+__device__ __forceinline__ void dec_table_row(const uint16_t *__restrict__ freq,
+                                              uint32_t *__restrict__ tab, int x, int64_t *info) {
   __shared__ uint32_t s_cum[257];
-  const int x = blockIdx.x, s = threadIdx.x;
+  const int s = threadIdx.x;
   const uint32_t f = freq[x * 256 + s];
   s_cum[s + 1] = f;
   if (s == 0) s_cum[0] = 0;
@@ -595,6 +597,11 @@ k_ans_dec_table(const uint16_t *__restrict__ freq, uint32_t *__restrict__ tab, i
     }
     tab[(int64_t)x * kAnsM + slot] = e;
   }
+}
+
+__global__ void __launch_bounds__(256)
+k_ans_dec_table(const uint16_t *__restrict__ freq, uint32_t *__restrict__ tab, int64_t *info) {
+  dec_table_row(freq, tab, blockIdx.x, info);
 }
 
 // ---------------------------------------------------------------------------
@@ -668,11 +675,10 @@ __global__ void k_ans_offsets(const uint32_t *__restrict__ scan, int64_t nb,
 // ---------------------------------------------------------------------------
 // Entropy coder: decode
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64)
-k_ans_decode(const uint16_t *__restrict__ words, int64_t n_words,
-             const int64_t *__restrict__ block_off, int64_t n, int64_t S, int order,
-             const uint32_t *__restrict__ tab, uint8_t *__restrict__ sym, int64_t *info) {
-  const int64_t b = blockIdx.x;
+__device__ __forceinline__ void decode_block(const uint16_t *__restrict__ words, int64_t n_words,
+                                             const int64_t *__restrict__ block_off, int64_t n,
+                                             int64_t S, int order, const uint32_t *__restrict__ tab,
+                                             uint8_t *__restrict__ sym, int64_t *info, int64_t b) {
   const int lane = threadIdx.x;
   const int64_t a = b * 64 * S + (int64_t)lane * S;
   const int64_t len = max((int64_t)0, min(S, n - a));
@@ -720,6 +726,171 @@ k_ans_decode(const uint16_t *__restrict__ words, int64_t n_words,
   if (__ballot(bad) != 0ull && lane == 0) atomicOr((unsigned long long *)info, 1ull);
 }
 
+__global__ void __launch_bounds__(64)
+k_ans_decode(const uint16_t *__restrict__ words, int64_t n_words,
+             const int64_t *__restrict__ block_off, int64_t n, int64_t S, int order,
+             const uint32_t *__restrict__ tab, uint8_t *__restrict__ sym, int64_t *info) {
+  decode_block(words, n_words, block_off, n, S, order, tab, sym, info, blockIdx.x);
+}
+
+// Several streams in one launch: block (b, s) decodes block b of stream s.
+struct AnsDev {
+  const uint16_t *words;
+  int64_t n_words;
+  const int64_t *block_off;
+  int64_t n;
+  const uint16_t *freq;
+  uint8_t *sym;
+  uint32_t *tab;
+  int64_t S, nb;
+  int32_t order, pad;
+};
+
+__global__ void __launch_bounds__(256)
+k_ans_dec_table_multi(const AnsDev *__restrict__ d, int64_t *info) {
+  const AnsDev &a = d[blockIdx.y];
+  const int x = blockIdx.x;
+  if ((a.order == 0 && x > 0) || a.nb == 0) return;
+  dec_table_row(a.freq, a.tab, x, info + blockIdx.y);
+}
+
+__global__ void __launch_bounds__(64)
+k_ans_decode_multi(const AnsDev *__restrict__ d, int64_t *info) {
+  const AnsDev &a = d[blockIdx.y];
+  if ((int64_t)blockIdx.x >= a.nb) return;
+  decode_block(a.words, a.n_words, a.block_off, a.n, a.S, a.order, a.tab, a.sym,
+               info + blockIdx.y, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Attributes: Morton order, DPCM byte planes, reconstruction, Fourier
+// positional embedding
+// ---------------------------------------------------------------------------
+__global__ void k_flags_u8(const uint8_t *__restrict__ m, int64_t n, uint32_t *__restrict__ f) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) f[i] = m[i] ? 1u : 0u;
+}
+
+// Key of kept Gaussian i: its voxel's rank among the distinct codes (binary
+// search), value: i; at its position in index order.
+__global__ void k_mo_keys(const float *__restrict__ params, int64_t npad, int64_t n,
+                          const float *__restrict__ q, const uint8_t *__restrict__ hard,
+                          const uint32_t *__restrict__ pos, int depth, int64_t kx, int64_t ky,
+                          int64_t kz, const uint64_t *__restrict__ codes, int64_t m,
+                          uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !hard[i]) return;
+  int32_t v[3];
+  bool ok;
+  codes_of(params, npad, q, i, v, ok);
+  const uint64_t c = morton3((uint32_t)((int64_t)v[0] - kx), (uint32_t)((int64_t)v[1] - ky),
+                             (uint32_t)((int64_t)v[2] - kz), depth);
+  int64_t a = 0, b = m;  // first code >= c
+  while (a < b) {
+    const int64_t mid = (a + b) >> 1;
+    if (codes[mid] < c) a = mid + 1; else b = mid;
+  }
+  const uint32_t p = pos[i];
+  key[p] = (uint32_t)a;
+  val[p] = (uint32_t)i;
+}
+
+__global__ void k_copy_u32(const uint32_t *__restrict__ src, int64_t count, int32_t *__restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = (int32_t)src[i];
+}
+
+struct AttrChan {
+  float q;
+  int32_t kmin, planes, row0;
+};
+struct AttrChans {
+  AttrChan ch[SGS_NCH - 3];
+};
+
+// Planes of channel 3 + blockIdx.y at serialized position j: the value's
+// residual against the previous position of its group, zigzag-mapped, cut
+// into bytes (most significant first).
+__global__ void k_attr_planes(const float *__restrict__ params, int64_t npad,
+                              const int32_t *__restrict__ perm, int64_t kept, int64_t S,
+                              AttrChans C, uint8_t *__restrict__ planes) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const AttrChan a = C.ch[blockIdx.y];
+  if (j >= kept || a.planes == 0) return;
+  const float *y = params + (int64_t)(3 + blockIdx.y) * npad;
+  bool ok;
+  const int64_t v = (int64_t)sgs_code_of(y[perm[j]], a.q, ok) - a.kmin;
+  const int64_t pred = j % S == 0 ? 0 : (int64_t)sgs_code_of(y[perm[j - 1]], a.q, ok) - a.kmin;
+  const int64_t d = v - pred;
+  const uint64_t z = d >= 0 ? (uint64_t)(2 * d) : (uint64_t)(-2 * d - 1);
+  for (int t = 0; t < a.planes; ++t)
+    planes[(int64_t)(a.row0 + t) * kept + j] = (uint8_t)(z >> (8 * (a.planes - 1 - t)));
+}
+
+// Group g of channel 3 + blockIdx.y: running sum of the residuals, then the
+// dequantized values fl32((kmin + v) q) into out [59][out_pad].
+__global__ void k_attr_reconstruct(const uint8_t *__restrict__ planes, int64_t kept, int64_t S,
+                                   AttrChans C, float *__restrict__ out, int64_t out_pad) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const AttrChan a = C.ch[blockIdx.y];
+  const int64_t j0 = g * S;
+  if (j0 >= kept) return;
+  const int64_t j1 = min(kept, j0 + S);
+  float *o = out + (int64_t)(3 + blockIdx.y) * out_pad;
+  int64_t v = 0;
+  for (int64_t j = j0; j < j1; ++j) {
+    uint64_t z = 0;
+    for (int t = 0; t < a.planes; ++t) z = (z << 8) | planes[(int64_t)(a.row0 + t) * kept + j];
+    const int64_t d = (z & 1u) ? -(int64_t)((z + 1) >> 1) : (int64_t)(z >> 1);
+    v = (j == j0 ? 0 : v) + d;
+    o[j] = (float)(a.kmin + v) * a.q;
+  }
+}
+
+// PE(mu) = W phi(mu) + b, phi = [mu; sin(2 pi 2^l mu); cos(2 pi 2^l mu)]
+// (band-major, axis-minor): one thread per Gaussian, W and b in LDS, the
+// features in registers (L fixed per instance), four outputs per store.
+constexpr int kPeMaxD = 64;
+template <int L>
+__global__ void __launch_bounds__(256)
+k_pos_embed(const float *__restrict__ xyz, int64_t pad, int64_t count, int d,
+            const float *__restrict__ W, const float *__restrict__ bias, float *__restrict__ out) {
+  constexpr int F = 3 + 6 * L;
+  __shared__ float s_w[kPeMaxD * F];
+  __shared__ float s_b[kPeMaxD];
+  for (int e = threadIdx.x; e < d * F; e += blockDim.x) s_w[e] = W[e];
+  for (int e = threadIdx.x; e < d; e += blockDim.x) s_b[e] = bias[e];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  float phi[F];
+  const float mu[3] = {xyz[i], xyz[pad + i], xyz[2 * pad + i]};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) phi[c] = mu[c];
+#pragma unroll
+  for (int l = 0; l < L; ++l)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      // sin(2 pi 2^l mu) = sinpi(2^(l+1) mu); the product is exact
+      const float x = ldexpf(mu[c], l + 1);
+      phi[3 + 3 * l + c] = sinpif(x);
+      phi[3 + 3 * L + 3 * l + c] = cospif(x);
+    }
+  float4 *o = (float4 *)(out + i * d);
+  for (int k = 0; k < d; k += 4) {
+    float acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float *w = s_w + (k + u) * F;
+      float a = s_b[k + u];
+#pragma unroll
+      for (int f = 0; f < F; ++f) a = fmaf(w[f], phi[f], a);
+      acc[u] = a;
+    }
+    o[k >> 2] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -740,6 +911,10 @@ struct SgsCoding {
   double *ans_bits = nullptr;
   int64_t cap_blocks = 0;
   uint32_t *ans_blk = nullptr, *ans_scan = nullptr;
+  uint32_t *multi_tab = nullptr;   // decode tables of a multi-stream decode
+  int64_t multi_tab_words = 0;
+  unsigned char *multi_desc = nullptr;  // its stream descriptors
+  int32_t multi_cap = 0;
 };
 
 namespace {
@@ -853,6 +1028,8 @@ void coding_free(sgs_ctx *c) {
   cfree(k->ans_bits);
   cfree(k->ans_blk);
   cfree(k->ans_scan);
+  cfree(k->multi_tab);
+  cfree(k->multi_desc);
   delete k;
   c->coding = nullptr;
 }
@@ -994,5 +1171,142 @@ hipError_t launch_ans_decode(sgs_ctx *c, const uint16_t *words, int64_t n_words,
   if (nb > 0)
     k_ans_decode<<<(unsigned)nb, 64, 0, st>>>(words, n_words, block_off, n, S, order, k->ans_dec,
                                                sym, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_ans_decode_multi(sgs_ctx *c, int32_t count, const sgs_ans_stream *st,
+                                   int64_t *info) {
+  hipError_t e = coding_base(c);
+  if (e != hipSuccess) return e;
+  SgsCoding *k = c->coding;
+  // decode tables: 4096 entries per order-0 stream, 257 x 4096 per order-1
+  std::vector<AnsDev> h((size_t)count);
+  int64_t tab_words = 0, most = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const int64_t S = st[i].lane_len;
+    h[i] = AnsDev{st[i].words, st[i].n_words, st[i].block_off, st[i].n, st[i].freq, st[i].sym,
+                  nullptr, S, (st[i].n + 64 * S - 1) / (64 * S), st[i].order, 0};
+    tab_words += (st[i].order ? kCtx : 1) * (int64_t)kAnsM;
+    most = h[i].nb > most ? h[i].nb : most;
+  }
+  if (tab_words > k->multi_tab_words) {
+    k->multi_tab_words = 0;
+    if ((e = calloc_(k->multi_tab, tab_words)) != hipSuccess) return e;
+    k->multi_tab_words = tab_words;
+  }
+  if (count > k->multi_cap) {
+    k->multi_cap = 0;
+    if ((e = calloc_(k->multi_desc, (int64_t)count * (int64_t)sizeof(AnsDev))) != hipSuccess) return e;
+    k->multi_cap = count;
+  }
+  int64_t o = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    h[i].tab = k->multi_tab + o;
+    o += (h[i].order ? kCtx : 1) * (int64_t)kAnsM;
+  }
+  hipStream_t s = c->stream;
+  e = hipMemcpyAsync(k->multi_desc, h.data(), sizeof(AnsDev) * (size_t)count,
+                     hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  const AnsDev *d = (const AnsDev *)k->multi_desc;
+  k_fill_u32<<<grid_for(2 * (int64_t)count, 256, 64), 256, 0, s>>>((uint32_t *)info,
+                                                                  2 * (int64_t)count, 0u);
+  k_ans_dec_table_multi<<<dim3(kCtx, (unsigned)count), 256, 0, s>>>(d, info);
+  if (most > 0)
+    k_ans_decode_multi<<<dim3((unsigned)most, (unsigned)count), 64, 0, s>>>(d, info);
+  // the host copy of the descriptors must outlive the transfer
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_morton_order(sgs_ctx *c, const float *params, int64_t npad, int64_t n,
+                               const float *q, const uint8_t *hard, const sgs_octree_header *h,
+                               const uint64_t *codes, int32_t *perm) {
+  hipError_t e = coding_octree(c, n);
+  if (e != hipSuccess) return e;
+  SgsCoding *k = c->coding;
+  hipStream_t s = c->stream;
+  const int64_t kept = h->kept, m = h->unique;
+  k_flags_u8<<<grid_for(n, 256, 1 << 30), 256, 0, s>>>(hard, n, k->dflag);
+  e = launch_exclusive_scan(c, k->dflag, k->dpos, n, nullptr);
+  if (e != hipSuccess) return e;
+  k_mo_keys<<<grid_for(n, 256, 1 << 30), 256, 0, s>>>(params, npad, n, q, hard, k->dpos,
+                                                      (int)h->depth, h->kmin[0], h->kmin[1],
+                                                      h->kmin[2], codes, m, k->key[0], k->key[2]);
+  int bits = 1;
+  while (bits < 32 && ((int64_t)1 << bits) <= m) ++bits;
+  int w = 0;
+  uint32_t *keys[2] = {k->key[0], k->key[1]}, *vals[2] = {k->key[2], k->key[3]};
+  e = ensure_tmp(c, (n + 4095) / 4096 + 1, radix_hist_words(kept));
+  if (e != hipSuccess) return e;
+  e = launch_radix_sort(c, keys, vals, kept, bits, &w, nullptr);
+  if (e != hipSuccess) return e;
+  if (kept > 0)
+    k_copy_u32<<<grid_for(kept, 256, 1 << 30), 256, 0, s>>>(vals[w], kept, perm);
+  return hipGetLastError();
+}
+
+static AttrChans attr_chans(const sgs_fl_channel *fl, int64_t *rows) {
+  AttrChans C;
+  int32_t r = 0;
+  for (int j = 3; j < SGS_NCH; ++j) {
+    const int w = fl[j].width;
+    const int P = w == 0 ? 0 : (w + 8) / 8;
+    C.ch[j - 3] = AttrChan{fl[j].q, fl[j].kmin, P, r};
+    r += P;
+  }
+  *rows = r;
+  return C;
+}
+
+int64_t attr_plane_rows(const sgs_fl_channel *fl) {
+  int64_t r;
+  (void)attr_chans(fl, &r);
+  return r;
+}
+
+hipError_t launch_attr_planes(sgs_ctx *c, const float *params, int64_t npad, const int32_t *perm,
+                              int64_t kept, const sgs_fl_channel *fl, int32_t S,
+                              uint8_t *planes) {
+  int64_t rows;
+  const AttrChans C = attr_chans(fl, &rows);
+  if (kept > 0 && rows > 0)
+    k_attr_planes<<<dim3(grid_for(kept, 256, 1 << 30), SGS_NCH - 3), 256, 0, c->stream>>>(
+        params, npad, perm, kept, S, C, planes);
+  return hipGetLastError();
+}
+
+hipError_t launch_attr_reconstruct(sgs_ctx *c, const uint8_t *planes, int64_t kept,
+                                   const sgs_fl_channel *fl, int32_t S, float *out,
+                                   int64_t out_pad) {
+  int64_t rows;
+  const AttrChans C = attr_chans(fl, &rows);
+  const int64_t groups = (kept + S - 1) / S;
+  if (kept > 0)
+    k_attr_reconstruct<<<dim3(grid_for(groups, 256, 1 << 30), SGS_NCH - 3), 256, 0, c->stream>>>(
+        planes, kept, S, C, out, out_pad);
+  return hipGetLastError();
+}
+
+template <int L>
+static void pe_launch(sgs_ctx *c, const float *xyz, int64_t pad, int64_t count, int d,
+                      const float *W, const float *b, float *out) {
+  k_pos_embed<L><<<grid_for(count, 256, 1 << 30), 256, 0, c->stream>>>(xyz, pad, count, d, W, b,
+                                                                       out);
+}
+
+hipError_t launch_pos_embed(sgs_ctx *c, const float *xyz, int64_t pad, int64_t count, int L,
+                            int d, const float *W, const float *b, float *out) {
+  if (count == 0) return hipSuccess;
+  switch (L) {
+#define SGS_PE_CASE(v) \
+  case v: pe_launch<v>(c, xyz, pad, count, d, W, b, out); break;
+    SGS_PE_CASE(1) SGS_PE_CASE(2) SGS_PE_CASE(3) SGS_PE_CASE(4) SGS_PE_CASE(5) SGS_PE_CASE(6)
+    SGS_PE_CASE(7) SGS_PE_CASE(8) SGS_PE_CASE(9) SGS_PE_CASE(10) SGS_PE_CASE(11)
+    SGS_PE_CASE(12) SGS_PE_CASE(13) SGS_PE_CASE(14) SGS_PE_CASE(15) SGS_PE_CASE(16)
+#undef SGS_PE_CASE
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }

@@ -345,3 +345,130 @@ def test_ans_flags_and_damage(orc, gctx, dev):
     assert (ref is None) == bool(info & 1)
     if ref is not None:
         assert np.array_equal(out, ref)
+
+
+# ---------------------------------------------------------------------------
+# attributes: Morton order, planes, multi-stream decode, reconstruction, PE
+# ---------------------------------------------------------------------------
+def attr_case(orc, gctx, dev, sc, q, S, name, coded_planes=None):
+    """Whole attribute path on one scene against the oracle; returns the
+    decoded scene rows [59][kept] (serialized order)."""
+    _say(f"[gpu] attributes {name} n={sc.n} lane_len={S}")
+    n, npad = sc.n, sc.npad
+    m = sc.given_mask
+    P, Q, M = T(sc.params, dev), T(q, dev), T(m, dev)
+    # octree and Morton order
+    g = gpu_octree(gctx, dev, sc.params, q, m, n)
+    r = orc.octree_tokens(sc.params, q, m, n)
+    assert g["flags"] == 0
+    hdr = gctx.octree_header(g["hdr"])
+    codes_dev = torch.from_numpy(g["codes"].view(np.int64).copy()).to(dev)
+    perm = torch.zeros(max(g["kept"], 1), dtype=torch.int32, device=dev)
+    gctx.morton_order(P, npad, n, Q, M, hdr, codes_dev, perm)
+    want_perm = orc.morton_order(sc.params, q, m, n, r["depth"], r["kmin"])
+    kept = want_perm.size
+    got_perm = perm.cpu().numpy()[:kept]
+    assert np.array_equal(got_perm, want_perm)
+    # fixed-length header (its widths fix the planes), then the planes
+    gctx.set_scene(n, npad, sc.n_hat, sc.cams, sc.width, sc.height)
+    fh = torch.zeros(59, 3, dtype=torch.int32, device=dev)
+    payload = torch.zeros(59 * n + 64, dtype=torch.int32, device=dev)
+    info = torch.zeros(3, dtype=torch.int64, device=dev)
+    gctx.fl_encode(P, Q, M, fh, payload, payload.numel(), info)
+    fhn = fh.cpu().numpy()
+    fl = gctx.fl_header_host(fhn)
+    yhat, k = orc.fakequant(sc.params, q, n)
+    bits, kmin, kmax, width = orc.fixed_length_bits(k, m, n)
+    assert np.array_equal(fhn[:, 1], kmin) and np.array_equal(fhn[:, 2], width)
+    rows = gctx.attr_plane_rows(fl)
+    want = [orc.attr_planes(sc.params[c], q[c], want_perm, kmin[c], width[c], S)
+            for c in orc.ATTR_CHANNELS]
+    want = np.concatenate([w for w in want if w.size], axis=0) if rows else \
+        np.zeros((0, kept), np.uint8)
+    assert want.shape == (rows, kept)
+    planes = torch.zeros(max(rows * kept, 1), dtype=torch.uint8, device=dev)
+    gctx.attr_planes(P, npad, perm, kept, fl, S, planes)
+    torch.cuda.synchronize()
+    got = planes.cpu().numpy()[:rows * kept].reshape(rows, kept)
+    assert np.array_equal(got, want)
+    # every plane through the coder (oracle streams), decoded in one launch
+    streams = []
+    ncode = rows if coded_planes is None else min(rows, coded_planes)
+    for t in range(ncode):
+        f = orc.ans_model(want[t], 0, S)
+        w, off = orc.ans_encode(want[t], 0, S, f)
+        d = dict(words=T(w.view(np.int16), dev) if w.size else torch.zeros(1, dtype=torch.int16,
+                                                                            device=dev),
+                 n_words=w.size, block_off=T(off, dev), n=kept, freq=T(f.view(np.int16), dev),
+                 sym=torch.full((max(kept, 1),), 0xEE, dtype=torch.uint8, device=dev),
+                 order=0, lane_len=S)
+        streams.append(d)
+    minfo = torch.zeros(max(ncode, 1), dtype=torch.int64, device=dev)
+    gctx.ans_decode_multi(streams, minfo)
+    torch.cuda.synchronize()
+    assert np.all(minfo.cpu().numpy()[:ncode] == 0)
+    if ncode:
+        assert np.array_equal(np.stack([d["sym"].cpu().numpy()[:kept] for d in streams]),
+                              want[:ncode])
+    dec = want
+    # reconstruction: attribute rows, positions from the octree decode
+    out = torch.full((59, max(kept, 1)), float("nan"), dtype=torch.float32, device=dev)
+    dplanes = torch.from_numpy(np.ascontiguousarray(dec).reshape(-1)).to(dev) if rows else planes
+    gctx.attr_reconstruct(dplanes, kept, fl, S, out, max(kept, 1))
+    codes2, xyz, oinfo = gpu_decode(gctx, dev, g, q)
+    assert oinfo == 0
+    out[:3, :kept] = torch.from_numpy(xyz).to(dev)
+    torch.cuda.synchronize()
+    scene = out.cpu().numpy()[:, :kept]
+    for c in orc.ATTR_CHANNELS:
+        pl = orc.attr_planes(sc.params[c], q[c], want_perm, kmin[c], width[c], S)
+        ref = orc.attr_reconstruct(pl, kmin[c], q[c], S, kept)
+        assert np.array_equal(scene[c], ref), c
+    # the decoded scene is the quantized scene in Morton order
+    assert np.array_equal(scene, yhat[:, want_perm])
+    return scene
+
+
+@pytest.mark.parametrize("S", [1, 16, 256])
+def test_attributes_match_oracle(orc, gctx, dev, S):
+    sc = synth.make_tiny(5000, 48, 32, seed=7)
+    attr_case(orc, gctx, dev, sc, synth.learnable_qsteps(8), S, "tiny")
+
+
+def test_attributes_edge_cases(orc, gctx, dev):
+    # constant channels (width 0: no planes) and a single kept Gaussian
+    sc = synth.make_tiny(700, 32, 32, seed=9)
+    sc.params[10:20, :sc.n] = 0.125
+    attr_case(orc, gctx, dev, sc, synth.learnable_qsteps(10), 64, "constant channels")
+    m = np.zeros(sc.n, np.uint8)
+    m[123] = 1
+    sc.given_mask = m
+    attr_case(orc, gctx, dev, sc, synth.learnable_qsteps(10), 64, "one kept")
+
+
+def test_attributes_full_size_scene(orc, gctx, dev):
+    sc = synth.make_scene("c3")
+    q = np.full(59, 2.0 ** -6, np.float32)
+    attr_case(orc, gctx, dev, sc, q, 256, "c3")
+
+
+@pytest.mark.parametrize("L,d", [(12, 32), (3, 8), (16, 64)])
+def test_positional_embedding(orc, gctx, dev, L, d):
+    rng = np.random.default_rng(L * 100 + d)
+    count, pad = 3001, 3072
+    xyz = np.zeros((3, pad), np.float32)
+    xyz[:, :count] = rng.normal(0, 1.5, (3, count))
+    xyz[:, 0] = [0.0, 0.25, -0.5]          # exact sin / cos values
+    F = 3 + 6 * L
+    W = (rng.normal(0, 0.1, (d, F))).astype(np.float32)
+    b = rng.normal(0, 0.1, d).astype(np.float32)
+    out = torch.full((count, d), float("nan"), dtype=torch.float32, device=dev)
+    gctx.positional_embedding(T(xyz, dev), pad, count, L, d, T(W, dev), T(b, dev), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ref = orc.positional_embedding(xyz[:, :count].T.astype(np.float64), W, b, L)
+    # bound: each feature within 2.5e-7 (sinpi / cospi of an exact argument,
+    # a few ulp), the FP32 dot product within F 2^-24 sum |w phi|
+    bound = np.abs(W).sum(axis=1)[None, :] * 2.5e-7 + \
+        F * 6e-8 * (np.abs(orc.fourier_features(xyz[:, :count].T, L)) @ np.abs(W).T + np.abs(b))
+    assert np.all(np.abs(got - ref) <= bound + 1e-7), np.max(np.abs(got - ref) - bound)
