@@ -798,6 +798,111 @@ def bench_coding(ctx, dev, params, q, hard, n, npad, reps=10, lane_len=256):
             "decode_tokens_per_s": round(T / (timed["decode"] * 1e-3), 1),
         }
         say(f"coding {label}: {T} tokens, {W} words, decode {timed['decode']:.3f} ms")
+        if qpos is None:
+            res[label]["attributes"] = bench_attributes(ctx, dev, params, q, hard, n, npad, header,
+                                                        codes, m, kept, xyz, reps, S)
+            res[label]["attributes"]["geometry_and_attributes_decode_ms"] = round(
+                timed["decode"] + res[label]["attributes"]["decode_ms"], 4)
+    return res
+
+
+def bench_attributes(ctx, dev, params, q, hard, n, npad, oheader, codes, m, kept, xyz, reps, S):
+    """Attribute half of the coding stage on the same state: Morton order,
+    DPCM byte planes per channel, an order-0 rANS stream per plane (encode);
+    all planes decoded in one launch, the scene rows rebuilt, and the
+    positional embedding of the decoded positions (L = 12 bands, d = 32, seeded
+    weights; decode).  Also the planes' ideal bits in Gaussian index order,
+    against which the Morton order's gain shows."""
+    import numpy as np
+    import torch
+
+    fh = torch.empty((59, 3), dtype=torch.int32, device=dev)
+    payload = torch.empty(59 * n + 64, dtype=torch.int32, device=dev)
+    finfo = torch.empty(3, dtype=torch.int64, device=dev)
+    ctx.fl_encode(params, q, hard, fh, payload, payload.numel(), finfo)
+    fl = ctx.fl_header_host(fh.cpu().numpy())
+    fl_bits = int(finfo[0].item()) + 59 * 72
+    rows = ctx.attr_plane_rows(fl)
+    perm = torch.empty(max(kept, 1), dtype=torch.int32, device=dev)
+    planes = torch.empty((max(rows, 1), max(kept, 1)), dtype=torch.uint8, device=dev)
+    nb = (kept + 64 * S - 1) // (64 * S)
+    cap = ctx.ans_max_words(kept, S)
+    freqs = torch.empty((max(rows, 1), 257 * 256), dtype=torch.int16, device=dev)
+    words = torch.empty((max(rows, 1), cap), dtype=torch.int16, device=dev)
+    offs = torch.empty((max(rows, 1), nb + 1), dtype=torch.int64, device=dev)
+    infos = torch.empty((max(rows, 1), 2), dtype=torch.int64, device=dev)
+    bits = torch.empty(max(rows, 1), dtype=torch.float64, device=dev)
+
+    def encode(order_perm=None):
+        if order_perm is None:
+            ctx.morton_order(params, npad, n, q, hard, oheader, codes, perm)
+            p = perm
+        else:
+            p = order_perm
+        ctx.attr_planes(params, npad, p, kept, fl, S, planes)
+        for t in range(rows):
+            ctx.ans_model(planes[t], kept, 0, S, freqs[t], bits[t:t + 1])
+            ctx.ans_encode(planes[t], kept, 0, S, freqs[t], words[t], offs[t], infos[t])
+
+    encode()
+    torch.cuda.synchronize()
+    inf = infos.cpu().numpy()[:rows]
+    assert np.all(inf[:, 1] == 0)
+    nwords = inf[:, 0].astype(np.int64)
+    ideal_morton = float(bits[:rows].sum().item())
+    out = torch.empty((59, max(kept, 1)), dtype=torch.float32, device=dev)
+    dplanes = torch.empty_like(planes)
+    dinfo = torch.empty(max(rows, 1), dtype=torch.int64, device=dev)
+    streams = [dict(words=words[t], n_words=int(nwords[t]), block_off=offs[t], n=kept,
+                    freq=freqs[t], sym=dplanes[t], order=0, lane_len=S) for t in range(rows)]
+    g = torch.Generator().manual_seed(12)
+    Wpe = (torch.randn((32, 75), generator=g) * 0.1).to(dev)
+    bpe = (torch.randn(32, generator=g) * 0.1).to(dev)
+    pe = torch.empty((max(kept, 1), 32), dtype=torch.float32, device=dev)
+
+    def decode():
+        ctx.ans_decode_multi(streams, dinfo)
+        ctx.attr_reconstruct(dplanes, kept, fl, S, out, max(kept, 1))
+        ctx.positional_embedding(xyz, max(kept, 1), kept, 12, 32, Wpe, bpe, pe)
+
+    decode()
+    torch.cuda.synchronize()
+    assert int(dinfo[:rows].abs().sum().item()) == 0
+    assert torch.equal(dplanes[:rows], planes[:rows])
+    timed = {}
+    for name, fn in (("encode", encode), ("decode", decode)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        timed[name] = (time.perf_counter() - t0) * 1e3 / reps
+    # decode pieces, from the library's event profile
+    ctx.profile_enable(True)
+    for _ in range(reps):
+        decode()
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    # the same planes in Gaussian index order
+    idx = torch.nonzero(hard[:n]).reshape(-1).to(torch.int32)
+    encode(idx)
+    torch.cuda.synchronize()
+    ideal_index = float(bits[:rows].sum().item())
+    words_total = int(nwords.sum())
+    res = {
+        "channels": 56, "plane_rows": rows, "lane_len_W": S, "groups_G": (kept + S - 1) // S,
+        "words": words_total,
+        "bits_per_kept_gaussian": round(16.0 * words_total / max(kept, 1), 3),
+        "ideal_bits_R_attr_morton_order": round(ideal_morton, 1),
+        "ideal_bits_index_order": round(ideal_index, 1),
+        "morton_over_index_bits": round(ideal_morton / max(ideal_index, 1.0), 4),
+        "fixed_length_coder_bits_all_channels": fl_bits,
+        "encode_ms": round(timed["encode"], 4), "decode_ms": round(timed["decode"], 4),
+        "decode_group_ms": {"ans_planes_and_reconstruction_and_pe":
+                            round(prof["ans"][0] / reps, 4)},
+        "pe": "L = 12 power-of-two bands, d = 32, seeded weights (no trained model here)",
+    }
+    say(f"coding attributes: {rows} planes, {words_total} words, decode {timed['decode']:.3f} ms")
     return res
 
 

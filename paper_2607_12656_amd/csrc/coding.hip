@@ -675,11 +675,19 @@ __global__ void k_ans_offsets(const uint32_t *__restrict__ scan, int64_t nb,
 // ---------------------------------------------------------------------------
 // Entropy coder: decode
 // ---------------------------------------------------------------------------
+// Decode of rANS block b by one wave.  tab: the decode table (LDS for an
+// order-0 stream, else global).  The block's words are read through a
+// window of 256 in four registers per lane (lane i holds word base + 64 r +
+// i of register r): a lane's next word is taken from the window with a
+// cross-lane read, and the window slides by 64 when the first register is
+// used up, its refill loaded two slides before it is read.  Symbols are
+// kept in registers and stored 16 at a time where the lane's run is 16-byte
+// aligned.
 __device__ __forceinline__ void decode_block(const uint16_t *__restrict__ words, int64_t n_words,
                                              const int64_t *__restrict__ block_off, int64_t n,
-                                             int64_t S, int order, const uint32_t *__restrict__ tab,
+                                             int64_t S, int order, const uint32_t *tab,
                                              uint8_t *__restrict__ sym, int64_t *info, int64_t b) {
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int64_t a = b * 64 * S + (int64_t)lane * S;
   const int64_t len = max((int64_t)0, min(S, n - a));
   const int64_t off = block_off[b], end = block_off[b + 1];
@@ -689,48 +697,101 @@ __device__ __forceinline__ void decode_block(const uint16_t *__restrict__ words,
     return;
   }
   uint32_t x = ((uint32_t)words[off + 2 * lane] << 16) | words[off + 2 * lane + 1];
-  int64_t p = off + 128;
+  int64_t p = off + 128, base = p;
+  auto wload = [&](int64_t i) -> uint32_t { return i < end ? (uint32_t)words[i] : 0u; };
+  uint32_t w0 = wload(base + lane), w1 = wload(base + 64 + lane), w2 = wload(base + 128 + lane),
+           w3 = wload(base + 192 + lane);
+  const uint64_t lt = lanemask_lt();
+  const bool vec = ((uintptr_t)(sym + a) & 15u) == 0u;
   int ctx = order ? 256 : 0;
   bool alive = true;
-  for (int64_t t = 0; t < S; ++t) {
-    const bool act = t < len && alive;
-    bool need = false;
-    if (act) {
-      const uint32_t slot = x & (kAnsM - 1u);
-      const uint32_t e = tab[ctx * (int)kAnsM + (int)slot];
-      if (e == kNoSym) {
-        alive = false;
-        bad = true;
-      } else {
-        const uint32_t s = e & 0xFFu, f = ((e >> 8) & 0xFFFu) + 1u, cum = e >> 20;
-        x = f * (x >> kAnsPB) + slot - cum;
-        sym[a + t] = (uint8_t)s;
-        if (order) ctx = (int)s;
-        need = x < kAnsL;
+  for (int64_t t0 = 0; t0 < S; t0 += 16) {
+    uint32_t pk[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int64_t t = t0 + j;
+      const bool act = t < len && alive;
+      bool need = false;
+      if (act) {
+        const uint32_t slot = x & (kAnsM - 1u);
+        const uint32_t e = tab[ctx * (int)kAnsM + (int)slot];
+        if (e == kNoSym) {
+          alive = false;
+          bad = true;
+        } else {
+          const uint32_t sv = e & 0xFFu, f = ((e >> 8) & 0xFFFu) + 1u, cum = e >> 20;
+          x = f * (x >> kAnsPB) + slot - cum;
+          pk[j >> 2] |= sv << (8 * (j & 3));
+          if (order) ctx = (int)sv;
+          need = x < kAnsL;
+        }
+      }
+      const uint64_t m = __ballot(need);
+      if (m) {
+        // the window: offsets < 64 + 63 always lie in its first two registers
+        const int o = (int)(p - base) + __popcll(m & lt);
+        const uint32_t r0 = (uint32_t)__shfl((int)w0, o & 63, 64);
+        const uint32_t r1 = (uint32_t)__shfl((int)w1, o & 63, 64);
+        if (need) {
+          if (p + __popcll(m & lt) < end) {
+            x = (x << 16) | (o < 64 ? r0 : r1);
+          } else {
+            alive = false;
+            bad = true;
+          }
+        }
+        p += __popcll(m);
+        if (p - base >= 64) {
+          w0 = w1;
+          w1 = w2;
+          w2 = w3;
+          w3 = wload(base + 256 + lane);
+          base += 64;
+        }
       }
     }
-    const uint64_t m = __ballot(need);
-    if (need) {
-      const int64_t pos = p + __popcll(m & lanemask_lt());
-      if (pos < end) {
-        x = (x << 16) | words[pos];
-      } else {
-        alive = false;
-        bad = true;
-      }
+    // this lane's symbols of the round
+    const int64_t cnt = min((int64_t)16, len - t0);
+    if (cnt == 16 && vec) {
+      *(uint4 *)(sym + a + t0) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+    } else if (cnt > 0) {
+      for (int k = 0; k < (int)cnt; ++k) sym[a + t0 + k] = (uint8_t)(pk[k >> 2] >> (8 * (k & 3)));
     }
-    p += __popcll(m);
   }
   // every word read, every lane back at the encoder's initial state
   bad = bad || (lane == 0 && p != end) || x != kAnsL;
   if (__ballot(bad) != 0ull && lane == 0) atomicOr((unsigned long long *)info, 1ull);
 }
 
-__global__ void __launch_bounds__(64)
+// Four waves per workgroup, wave w decoding block 4 blockIdx.x + w; an
+// order-0 stream's table (16 KB) is staged in LDS once for the four.
+constexpr int kDecWaves = 4;
+__device__ __forceinline__ void decode_blocks(const uint16_t *__restrict__ words, int64_t n_words,
+                                              const int64_t *__restrict__ block_off, int64_t n,
+                                              int64_t S, int order, int64_t nb,
+                                              const uint32_t *__restrict__ gtab,
+                                              uint8_t *__restrict__ sym, int64_t *info,
+                                              int64_t group) {
+  __shared__ uint32_t s_tab[kAnsM];
+  if (order == 0) {
+    for (int e = threadIdx.x; e < (int)kAnsM; e += blockDim.x) s_tab[e] = gtab[e];
+    __syncthreads();
+  }
+  const int64_t b = group * kDecWaves + (threadIdx.x >> 6);
+  if (b >= nb) return;
+  // two call sites so that each sees one address space (LDS reads for the
+  // staged table)
+  if (order == 0)
+    decode_block(words, n_words, block_off, n, S, 0, s_tab, sym, info, b);
+  else
+    decode_block(words, n_words, block_off, n, S, order, gtab, sym, info, b);
+}
+
+__global__ void __launch_bounds__(64 * kDecWaves)
 k_ans_decode(const uint16_t *__restrict__ words, int64_t n_words,
-             const int64_t *__restrict__ block_off, int64_t n, int64_t S, int order,
+             const int64_t *__restrict__ block_off, int64_t n, int64_t S, int order, int64_t nb,
              const uint32_t *__restrict__ tab, uint8_t *__restrict__ sym, int64_t *info) {
-  decode_block(words, n_words, block_off, n, S, order, tab, sym, info, blockIdx.x);
+  decode_blocks(words, n_words, block_off, n, S, order, nb, tab, sym, info, blockIdx.x);
 }
 
 // Several streams in one launch: block (b, s) decodes block b of stream s.
@@ -754,12 +815,12 @@ k_ans_dec_table_multi(const AnsDev *__restrict__ d, int64_t *info) {
   dec_table_row(a.freq, a.tab, x, info + blockIdx.y);
 }
 
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64 * kDecWaves)
 k_ans_decode_multi(const AnsDev *__restrict__ d, int64_t *info) {
   const AnsDev &a = d[blockIdx.y];
-  if ((int64_t)blockIdx.x >= a.nb) return;
-  decode_block(a.words, a.n_words, a.block_off, a.n, a.S, a.order, a.tab, a.sym,
-               info + blockIdx.y, blockIdx.x);
+  if ((int64_t)blockIdx.x * kDecWaves >= a.nb) return;  // whole workgroup: before the barrier
+  decode_blocks(a.words, a.n_words, a.block_off, a.n, a.S, a.order, a.nb, a.tab, a.sym,
+                info + blockIdx.y, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -827,23 +888,46 @@ __global__ void k_attr_planes(const float *__restrict__ params, int64_t npad,
     planes[(int64_t)(a.row0 + t) * kept + j] = (uint8_t)(z >> (8 * (a.planes - 1 - t)));
 }
 
-// Group g of channel 3 + blockIdx.y: running sum of the residuals, then the
-// dequantized values fl32((kmin + v) q) into out [59][out_pad].
-__global__ void k_attr_reconstruct(const uint8_t *__restrict__ planes, int64_t kept, int64_t S,
-                                   AttrChans C, float *__restrict__ out, int64_t out_pad) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Group g of channel 3 + blockIdx.y, one wave: the running sum of the
+// residuals (a wave scan per round of 256 positions, four per lane, carried
+// from round to round), then the dequantized values fl32((kmin + v) q) into
+// out [59][out_pad].
+__global__ void __launch_bounds__(256)
+k_attr_reconstruct(const uint8_t *__restrict__ planes, int64_t kept, int64_t S, AttrChans C,
+                   float *__restrict__ out, int64_t out_pad) {
   const AttrChan a = C.ch[blockIdx.y];
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t j0 = g * S;
   if (j0 >= kept) return;
   const int64_t j1 = min(kept, j0 + S);
   float *o = out + (int64_t)(3 + blockIdx.y) * out_pad;
-  int64_t v = 0;
-  for (int64_t j = j0; j < j1; ++j) {
-    uint64_t z = 0;
-    for (int t = 0; t < a.planes; ++t) z = (z << 8) | planes[(int64_t)(a.row0 + t) * kept + j];
-    const int64_t d = (z & 1u) ? -(int64_t)((z + 1) >> 1) : (int64_t)(z >> 1);
-    v = (j == j0 ? 0 : v) + d;
-    o[j] = (float)(a.kmin + v) * a.q;
+  int64_t carry = 0;
+  for (int64_t c0 = j0; c0 < j1; c0 += 256) {
+    int64_t d[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t j = c0 + 4 * lane + k;
+      uint64_t z = 0;
+      if (j < j1)
+        for (int t = 0; t < a.planes; ++t) z = (z << 8) | planes[(int64_t)(a.row0 + t) * kept + j];
+      d[k] = (z & 1u) ? -(int64_t)((z + 1) >> 1) : (int64_t)(z >> 1);
+    }
+    const int64_t sum = (d[0] + d[1]) + (d[2] + d[3]);
+    int64_t incl = sum;
+#pragma unroll
+    for (int sh = 1; sh < 64; sh <<= 1) {
+      const int64_t u = __shfl_up(incl, sh, 64);
+      if (lane >= sh) incl += u;
+    }
+    int64_t run = carry + incl - sum;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t j = c0 + 4 * lane + k;
+      run += d[k];
+      if (j < j1) o[j] = (float)(a.kmin + run) * a.q;
+    }
+    carry += __shfl(incl, 63, 64);
   }
 }
 
@@ -1169,7 +1253,8 @@ hipError_t launch_ans_decode(sgs_ctx *c, const uint16_t *words, int64_t n_words,
   k_fill_u32<<<1, 64, 0, st>>>((uint32_t *)info, 2, 0u);
   k_ans_dec_table<<<kCtx, 256, 0, st>>>(freq, k->ans_dec, info);
   if (nb > 0)
-    k_ans_decode<<<(unsigned)nb, 64, 0, st>>>(words, n_words, block_off, n, S, order, k->ans_dec,
+    k_ans_decode<<<(unsigned)((nb + kDecWaves - 1) / kDecWaves), 64 * kDecWaves, 0, st>>>(
+        words, n_words, block_off, n, S, order, nb, k->ans_dec,
                                                sym, info);
   return hipGetLastError();
 }
@@ -1213,7 +1298,8 @@ hipError_t launch_ans_decode_multi(sgs_ctx *c, int32_t count, const sgs_ans_stre
                                                                   2 * (int64_t)count, 0u);
   k_ans_dec_table_multi<<<dim3(kCtx, (unsigned)count), 256, 0, s>>>(d, info);
   if (most > 0)
-    k_ans_decode_multi<<<dim3((unsigned)most, (unsigned)count), 64, 0, s>>>(d, info);
+    k_ans_decode_multi<<<dim3((unsigned)((most + kDecWaves - 1) / kDecWaves), (unsigned)count),
+                         64 * kDecWaves, 0, s>>>(d, info);
   // the host copy of the descriptors must outlive the transfer
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
@@ -1284,7 +1370,7 @@ hipError_t launch_attr_reconstruct(sgs_ctx *c, const uint8_t *planes, int64_t ke
   const AttrChans C = attr_chans(fl, &rows);
   const int64_t groups = (kept + S - 1) / S;
   if (kept > 0)
-    k_attr_reconstruct<<<dim3(grid_for(groups, 256, 1 << 30), SGS_NCH - 3), 256, 0, c->stream>>>(
+    k_attr_reconstruct<<<dim3((unsigned)((groups + 3) / 4), SGS_NCH - 3), 256, 0, c->stream>>>(
         planes, kept, S, C, out, out_pad);
   return hipGetLastError();
 }
