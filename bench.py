@@ -5,8 +5,10 @@ Default workload (``--workload c5``): the full formation iteration at
 3,000,000 Gaussians (clustered: 3-component mixture) rendered in 8 views of
 1600x1060 on a radius-4 ring, Gumbel-sigmoid retention mask, L1 distortion
 against a seeded random target, lambda 2.5e-5, the learned rate estimator in
-the loop (MLP forward + recompute backward; the range proxy evaluated beside
-it) and Adam on (parameters, step sizes, scores) so the scene evolves.  The
+the loop (MLP forward + backward from the saved activation signs; the range proxy evaluated beside
+it; every 100 iterations both checked against the coder's exact bits, the
+plain proxy's gradient taking over while the learned estimate's error is the
+larger) and Adam on (parameters, step sizes, scores) so the scene evolves.  The
 same iterations with the plain range proxy are timed beside it.  Tile shape
 and blend schedule come from the library's autotuner; the estimator is
 trained first on the GPU on this scene's exact fixed-length coder bits.
@@ -61,6 +63,17 @@ FLOP_PER_EVAL_BWD = 74
 MLP_FLOP_PER_ROW = 2 * (64 * 128 + 128 * 128 + 128)
 METRIC = "RD-step ms/iter & Gaussian-pixel evals/s (fwd+bwd), learned vs plain rate"
 PERIOD = 16
+CHECK = 100     # iterations between two checks of the learned rate against the coder
+
+
+def _decided(decisions, use0, i):
+    """Whether iteration i runs on the learned rate gradient."""
+    cur = use0
+    for k in sorted(decisions):
+        if k > i:
+            break
+        cur = decisions[k]
+    return cur
 
 
 def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int, items: int = 0,
@@ -308,31 +321,55 @@ def bench_formation(args, sc, ctx, stream, dev, t):
             f.iterate()
         torch.cuda.synchronize()
         start = f.snapshot()
-        # one graph per iteration of the 16-iteration period
-        graphs = []
-        for _ in range(PERIOD):
-            ctx.graph_begin()
-            f.iterate()
-            graphs.append(ctx.graph_end())
-        f.restore(start)
-        for g in graphs[:2]:                    # first launches outside the timed region
-            g.launch(stream)
+        use0 = f.use_learned
+        # one graph per iteration of the 16-iteration period, for each rate
+        # gradient the fallback rule can select (learned, plain)
+        graphs = {}
+        for v in ((True, False) if mlp is not None else (False,)):
+            f.use_learned = v
+            for j in range(PERIOD):
+                ctx.graph_begin()
+                f.iterate()
+                graphs[(v, j)] = ctx.graph_end()
+            f.restore(start)
+        f.use_learned = use0
+        for j in range(2):                      # first launches outside the timed region
+            graphs[(use0, j)].launch(stream)
         torch.cuda.synchronize()
         f.restore(start)
         torch.cuda.synchronize()
+        # the fallback rule: every CHECK iterations both estimates against the
+        # coder's exact bits (one synchronization each, inside the timed
+        # region); the graphs of the rate gradient it selects run next
+        decisions = {}
         t0 = time.perf_counter()
         for i in range(K):
-            graphs[i % PERIOD].launch(stream)
+            if mlp is not None and (start[1] + i) % CHECK == 0:
+                f.k = start[1] + i % PERIOD     # the noise step of the next graph
+                f.check_rate()
+                decisions[i] = f.use_learned
+            graphs[(f.use_learned, i % PERIOD)].launch(stream)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         ctx.query()                             # raises if the reserved capacity overflowed
+        learned_iters = sum(1 for i in range(K) if _decided(decisions, use0, i))
+
+        def rerun(count_evals=False, check=False):
+            """The same K iterations from the start, eagerly, with the timed
+            run's fallback decisions (checks issued too when check)."""
+            f.restore(start)
+            f.use_learned = use0
+            for i in range(K):
+                if i in decisions:
+                    if check:
+                        f.check_rate()
+                    f.use_learned = decisions[i]
+                f.iterate(count_evals=count_evals)
+
         # the same iterations enqueued eagerly (no profiling)
-        f.restore(start)
-        f.k = start[1]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(K):
-            f.iterate()
+        rerun(check=True)
         torch.cuda.synchronize()
         dt_eager = time.perf_counter() - t0
         if name == "learned":     # the state the coding stage takes over
@@ -341,24 +378,20 @@ def bench_formation(args, sc, ctx, stream, dev, t):
         # evaluations after its reach test, per-kernel times
         counts = {}
         for mode in (0, 1):
-            f.restore(start)
             ctx.set_eval_count_mode(mode)
             rd.evals.zero_()
-            for _ in range(K):
-                f.iterate(count_evals=True)
+            rerun(count_evals=True)
             torch.cuda.synchronize()
             counts[mode] = int(rd.evals.item())
         ctx.set_eval_count_mode(0)
-        f.restore(start)
         ctx.profile_enable(True)
-        for _ in range(K):
-            f.iterate()
+        rerun()
         prof = ctx.profile_read()
         ctx.profile_enable(False)
         pairs, _ = ctx.query()
         items = ctx.query_items()
         bits, kept, e_plain, e_learn = f.rate_errors()
-        for g in graphs:
+        for g in graphs.values():
             g.close()
         kernels = {g: round(tot / cnt, 4) for g, (tot, cnt) in prof.items() if cnt}
         E, Er = counts[0], counts[1]
@@ -372,7 +405,14 @@ def bench_formation(args, sc, ctx, stream, dev, t):
                       "rate_check_before_run": {"plain_error": round(e_first[0], 4),
                                                 "learned_error": None if e_first[1] is None
                                                 else round(e_first[1], 4),
-                                                "learned_used": f.use_learned},
+                                                "learned_used": use0},
+                      "fallback_rule": None if mlp is None else {
+                          "check_every": CHECK, "checks": len(decisions),
+                          "iterations_on_learned_gradient": learned_iters,
+                          "iterations_on_plain_gradient": K - learned_iters,
+                          "checks_detail": [[int(k), round(a, 4), None if b is None
+                                             else round(b, 4), bool(u)]
+                                            for k, a, b, u in f.checks[1:1 + len(decisions)]]},
                       "kernel_ms": kernels}
         say(f"c5 {name}: {runs[name]['ms_per_step']} ms/iter (graph), "
             f"{runs[name]['eager_ms_per_step']} eager")
@@ -435,7 +475,7 @@ def bench_formation(args, sc, ctx, stream, dev, t):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"c5: full formation iteration, {sc.n} Gaussians (clustered), "
                                f"{sc.views} views {sc.width}x{sc.height}, Gumbel-sigmoid mask, "
-                               f"learned rate in the loop (forward + recompute backward), "
+                               f"learned rate in the loop (forward + backward), fallback rule every {CHECK} iterations, "
                                f"Adam on parameters / steps / scores (higher SH every 16th, "
                                f"sparse), lambda {lam}, tile {tile[0]}x{tile[1]} "
                                f"({schedule} schedule, autotuned)",
@@ -446,8 +486,12 @@ def bench_formation(args, sc, ctx, stream, dev, t):
                                   "rows)"},
         "timing": "K iterations replayed from HIP graphs (one per iteration of the 16-"
                   "iteration higher-SH period, launched in turn), host clock around the "
-                  "replays between two synchronizations; evaluation counts and kernel times "
-                  "from re-runs of the same K iterations from the same state",
+                  "replays between two synchronizations; in the learned run the fallback "
+                  "rule checks both rate estimates against the coder's exact bits every "
+                  f"{CHECK} iterations (inside the timed region) and the graphs of the "
+                  "gradient it selects run next; evaluation counts and kernel times from "
+                  "re-runs of the same K iterations from the same state with the same "
+                  "decisions",
         "roofline": roof,
         "group_roofline": {g: {k: r[k] for k in ("bound", "achieved", "unit", "frac")}
                            for g, r in groups.items()},

@@ -40,7 +40,7 @@ class Formation:
     params [59][npad], qstep [59], score [n] (float32, device) are updated by
     every ``iterate``; target is the image stack the L1 distortion compares
     with.  ``mlp = (packed, theta)`` puts the learned estimator in the loop
-    (its forward and recompute backward); otherwise the plain proxy supplies
+    (its forward and its backward from the saved activation signs); otherwise the plain proxy supplies
     the rate gradient: the paper's range-based multiplicative proxy, or with
     ``proxy="laplace"`` / ``masking="add"`` (weight ``alpha``) the variants its
     ablations compare."""
