@@ -98,13 +98,16 @@ __device__ __forceinline__ void codes_of(const float *__restrict__ params, int64
   }
 }
 
-// Range of the kept codes per axis and the kept count.
+// Range of the kept codes per axis and the kept count: per workgroup
+// partials {min x3, max x3, count, bad} (no atomics), reduced by k_oc_depth.
+constexpr int kOcRangeBlocks = 512;
 __global__ void __launch_bounds__(kOcThreads)
 k_oc_range(const float *__restrict__ params, int64_t npad, int64_t n, const float *__restrict__ q,
-           const uint8_t *__restrict__ hard, OcState *s) {
+           const uint8_t *__restrict__ hard, int32_t *__restrict__ part) {
+  __shared__ int32_t s_p[kOcThreads / 64][8];
   int32_t mn[3] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF};
   int32_t mx[3] = {(int32_t)0x80000000, (int32_t)0x80000000, (int32_t)0x80000000};
-  uint32_t cnt = 0;
+  int32_t cnt = 0;
   bool bad = false;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -130,22 +133,54 @@ k_oc_range(const float *__restrict__ params, int64_t npad, int64_t n, const floa
     cnt += __shfl_xor(cnt, o, 64);
   }
   const bool anybad = __ballot(bad) != 0ull;
+  const int wave = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    if (cnt) {
-      atomicAdd(&s->kept, cnt);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        atomicMin(&s->kmin[c], mn[c]);
-        atomicMax(&s->kmax[c], mx[c]);
-      }
+    for (int c = 0; c < 3; ++c) {
+      s_p[wave][c] = mn[c];
+      s_p[wave][3 + c] = mx[c];
     }
-    if (anybad) atomicOr(&s->flags, 1u);
+    s_p[wave][6] = cnt;
+    s_p[wave][7] = anybad ? 1 : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    const int k = threadIdx.x;
+    int32_t r = s_p[0][k];
+    for (int w = 1; w < kOcThreads / 64; ++w) {
+      const int32_t v = s_p[w][k];
+      r = k < 3 ? min(r, v) : k < 6 ? max(r, v) : k == 6 ? r + v : (r | v);
+    }
+    part[blockIdx.x * 8 + k] = r;
   }
 }
 
-// Depth and the header's geometry fields.
-__global__ void k_oc_depth(OcState *s, sgs_octree_header *h) {
+// The partials reduced (one workgroup, fixed order); depth and the header's
+// geometry fields.
+__global__ void __launch_bounds__(256)
+k_oc_depth(const int32_t *__restrict__ part, int nparts, OcState *s, sgs_octree_header *h) {
+  __shared__ int32_t s_r[256][8];
+  int32_t r[8] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, (int32_t)0x80000000, (int32_t)0x80000000,
+                  (int32_t)0x80000000, 0, 0};
+  for (int b = threadIdx.x; b < nparts; b += 256) {
+    for (int k = 0; k < 8; ++k) {
+      const int32_t v = part[b * 8 + k];
+      r[k] = k < 3 ? min(r[k], v) : k < 6 ? max(r[k], v) : k == 6 ? r[k] + v : (r[k] | v);
+    }
+  }
+  for (int k = 0; k < 8; ++k) s_r[threadIdx.x][k] = r[k];
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  for (int t = 1; t < 256; ++t)
+    for (int k = 0; k < 8; ++k) {
+      const int32_t v = s_r[t][k];
+      r[k] = k < 3 ? min(r[k], v) : k < 6 ? max(r[k], v) : k == 6 ? r[k] + v : (r[k] | v);
+    }
+  for (int c = 0; c < 3; ++c) {
+    s->kmin[c] = r[c];
+    s->kmax[c] = r[3 + c];
+  }
+  s->kept = (uint32_t)r[6];
+  if (r[7]) s->flags |= 1u;
   int D = depth_of(s);
   if (D > kMaxDepth) {
     s->flags |= 1u;
@@ -159,21 +194,15 @@ __global__ void k_oc_depth(OcState *s, sgs_octree_header *h) {
   h->kept = s->kept;
 }
 
-// Morton codes of the kept Gaussians (any order: only the sorted multiset
-// matters), split into low and high words for the radix sort.
+// Morton codes of the kept Gaussians at their positions in index order
+// (pos: exclusive scan of the kept flags), split into low and high words
+// for the radix sort.
 __global__ void __launch_bounds__(kOcThreads)
 k_oc_codes(const float *__restrict__ params, int64_t npad, int64_t n, const float *__restrict__ q,
-           const uint8_t *__restrict__ hard, OcState *s, uint32_t *__restrict__ lo,
-           uint32_t *__restrict__ hi) {
+           const uint8_t *__restrict__ hard, const uint32_t *__restrict__ pos, const OcState *s,
+           uint32_t *__restrict__ lo, uint32_t *__restrict__ hi) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool keep = i < n && hard[i];
-  const uint64_t bal = __ballot(keep);
-  if (bal == 0ull) return;
-  uint32_t base = 0;
-  const int leader = __ffsll((long long)bal) - 1;
-  if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(&s->fill, (uint32_t)__popcll(bal));
-  base = __shfl(base, leader, 64);
-  if (!keep) return;
+  if (i >= n || !hard[i]) return;
   int32_t v[3];
   bool ok;
   codes_of(params, npad, q, i, v, ok);
@@ -181,7 +210,7 @@ k_oc_codes(const float *__restrict__ params, int64_t npad, int64_t n, const floa
   const uint64_t c =
       morton3((uint32_t)((int64_t)v[0] - s->kmin[0]), (uint32_t)((int64_t)v[1] - s->kmin[1]),
               (uint32_t)((int64_t)v[2] - s->kmin[2]), D);
-  const uint32_t p = base + (uint32_t)__popcll(bal & lanemask_lt());
+  const uint32_t p = pos[i];
   lo[p] = (uint32_t)c;
   hi[p] = (uint32_t)(c >> 32);
 }
@@ -982,6 +1011,7 @@ k_pos_embed(const float *__restrict__ xyz, int64_t pad, int64_t count, int d,
 // ---------------------------------------------------------------------------
 struct SgsCoding {
   OcState *st = nullptr;
+  int32_t *oc_part = nullptr;  // range partials [kOcRangeBlocks][8]
   int64_t cap_n = 0;        // elements the octree buffers hold
   uint32_t *key[4] = {nullptr, nullptr, nullptr, nullptr};  // lo0, lo1, hi0, hi1
   uint32_t *heads = nullptr, *ustart = nullptr, *dflag = nullptr, *dpos = nullptr;
@@ -1022,6 +1052,7 @@ hipError_t coding_base(sgs_ctx *c) {
   if (!k->st) {
     hipError_t e = calloc_(k->st, 1);
     if (e != hipSuccess) return e;
+    if ((e = calloc_(k->oc_part, kOcRangeBlocks * 8)) != hipSuccess) return e;
     if ((e = calloc_(k->ans_cnt, kCtx * 256)) != hipSuccess) return e;
     if ((e = calloc_(k->ans_enc, kCtx * 256)) != hipSuccess) return e;
     if ((e = calloc_(k->ans_dec, (int64_t)kCtx * kAnsM)) != hipSuccess) return e;
@@ -1095,6 +1126,7 @@ void coding_free(sgs_ctx *c) {
   SgsCoding *k = c->coding;
   if (!k) return;
   cfree(k->st);
+  cfree(k->oc_part);
   for (auto &p : k->key) cfree(p);
   cfree(k->heads);
   cfree(k->ustart);
@@ -1134,11 +1166,14 @@ hipError_t launch_octree_encode(sgs_ctx *c, const float *params, int64_t npad, i
   hipStream_t st = c->stream;
   const int64_t nb = (n + kOcThreads - 1) / kOcThreads;
   k_oc_init<<<1, 64, 0, st>>>(k->st);
-  k_oc_range<<<grid_for(n, kOcThreads, 2048), kOcThreads, 0, st>>>(params, npad, n, q, hard,
-                                                                     k->st);
-  k_oc_depth<<<1, 64, 0, st>>>(k->st, h);
-  k_oc_codes<<<(unsigned)nb, kOcThreads, 0, st>>>(params, npad, n, q, hard, k->st, k->key[0],
-                                                   k->key[2]);
+  const int nparts = (int)grid_for(n, kOcThreads, kOcRangeBlocks);
+  k_oc_range<<<nparts, kOcThreads, 0, st>>>(params, npad, n, q, hard, k->oc_part);
+  k_oc_depth<<<1, 256, 0, st>>>(k->oc_part, nparts, k->st, h);
+  k_flags_u8<<<grid_for(n, 256, 1 << 30), 256, 0, st>>>(hard, n, k->dflag);
+  e = launch_exclusive_scan(c, k->dflag, k->dpos, n, nullptr);
+  if (e != hipSuccess) return e;
+  k_oc_codes<<<(unsigned)nb, kOcThreads, 0, st>>>(params, npad, n, q, hard, k->dpos, k->st,
+                                                   k->key[0], k->key[2]);
   // 64-bit keys: low words (carrying the high ones), then the high words
   // (carrying the low ones); both passes stable
   int w1 = 0, w2 = 0;
