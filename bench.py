@@ -51,6 +51,10 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+# VALU issue ceiling of the per-evaluation operation counts below (one lane
+# operation per op, packed FP32 not used): 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz
+VALU_ISSUE_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 NCH = 59
@@ -133,6 +137,10 @@ def roofline(g, ms, n, V, P, E, W, H, traffic_key=None, items=0, tiles=0, st=1):
     r = {"bound": bound, "kernel": g, "achieved": round(achieved, 3), "peak": peak,
          "unit": ru, "frac": round(achieved / peak, 5), "traffic": None,
          "algorithmic_per_launch": amount, "avg_launch_ms": round(ms, 4)}
+    if bound == "alu":
+        # the same count against the issue rate of single (unpacked) lane ops
+        r["issue_peak_tops"] = round(VALU_ISSUE_PEAK_TOPS, 2)
+        r["issue_frac"] = round(achieved / VALU_ISSUE_PEAK_TOPS, 5)
     if traffic_key:
         t = traffic_for(traffic_key)
         if t:
