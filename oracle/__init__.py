@@ -127,8 +127,8 @@ def _declare(L):
         "orc_ans_encode": (I64, [P, I64, I32, I64, P, P, P]),
         "orc_ans_decode": (I64, [P, P, I64, I32, I64, P, P]),
         "orc_morton_order": (I64, [I64, I64, P, P, P, I32, P, P]),
-        "orc_attr_planes": (None, [I64, P, P, P, I64, I32, I64, P]),
-        "orc_attr_reconstruct": (None, [I64, P, I32, I64, I64, F32, P]),
+        "orc_attr_planes": (None, [I64, P, P, P, I64, I32, I64, I32, P]),
+        "orc_attr_reconstruct": (None, [I64, P, I32, I64, I64, F32, I32, P]),
     }
     for name, (res, args) in sig.items():
         if not hasattr(L, name):
@@ -609,31 +609,37 @@ def morton_order(y, q, mhat, n, depth, kmin):
     return perm[:kept].copy()
 
 
-def attr_plane_count(width: int) -> int:
-    """Byte planes of a channel whose values take `width` bits: the residual
-    of two such values zigzag-mapped takes width + 1 bits (none for width 0)."""
-    return 0 if width == 0 else (width + 1 + 7) // 8
+def attr_plane_count(width: int, predictor: int = 1) -> int:
+    """Byte planes of a channel whose values take `width` bits: the values
+    themselves (predictor 0) take width bits, the residual of two of them
+    zigzag-mapped (predictor 1) width + 1; none for width 0."""
+    if width == 0:
+        return 0
+    return (width + 7) // 8 if predictor == 0 else (width + 1 + 7) // 8
 
 
-def attr_planes(y_row, q_c, perm, kmin: int, width: int, S: int):
-    """Zigzag DPCM byte planes [planes][kept] of one channel along perm."""
+def attr_planes(y_row, q_c, perm, kmin: int, width: int, S: int, predictor: int = 1):
+    """Byte planes [planes][kept] of one channel along perm (predictor 1:
+    zigzag residual against the group's previous value; 0: the value)."""
     y_row = np.ascontiguousarray(y_row, np.float32)
     perm = np.ascontiguousarray(perm, np.int64)
-    P = attr_plane_count(width)
+    P = attr_plane_count(width, predictor)
     out = np.zeros((max(P, 1), perm.size), np.uint8)
     qc = np.array([q_c], np.float32)
-    lib().orc_attr_planes(perm.size, _p(y_row), _p(qc), _p(perm), int(kmin), P, S, _p(out))
+    lib().orc_attr_planes(perm.size, _p(y_row), _p(qc), _p(perm), int(kmin), P, S, predictor,
+                          _p(out))
     return out[:P].copy()
 
 
-def attr_reconstruct(planes, kmin: int, q_c: float, S: int, kept: int):
+def attr_reconstruct(planes, kmin: int, q_c: float, S: int, kept: int, predictor: int = 1):
     planes = np.ascontiguousarray(planes, np.uint8)
     P = planes.shape[0] if planes.ndim == 2 else 0
     out = np.zeros(max(kept, 1), np.float32)
     if P == 0:
         out[:] = np.float32(np.float32(kmin) * np.float32(q_c))
         return out[:kept]
-    lib().orc_attr_reconstruct(kept, _p(planes), P, S, int(kmin), np.float32(q_c), _p(out))
+    lib().orc_attr_reconstruct(kept, _p(planes), P, S, int(kmin), np.float32(q_c), predictor,
+                               _p(out))
     return out[:kept].copy()
 
 

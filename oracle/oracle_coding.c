@@ -375,19 +375,22 @@ int64_t orc_morton_order(int64_t n, int64_t npad, const float *y, const float *q
 }
 
 /* Byte planes of one attribute channel in serialized order: v_j = k - kmin
- * (the fixed-length coder's value, k = rint(fl32(y / q))), predicted by the
- * previous Gaussian of the same group of S (0 for a group's first), the
- * residual zigzag-mapped (d >= 0 -> 2d, d < 0 -> -2d - 1) and cut into
- * `planes` bytes, most significant first: out [planes][kept]. */
+ * (the fixed-length coder's value, k = rint(fl32(y / q))).  Predictor 1:
+ * v_j is predicted by the previous Gaussian of the same group of S (0 for a
+ * group's first) and the residual zigzag-mapped (d >= 0 -> 2d, d < 0 ->
+ * -2d - 1); predictor 0: v_j itself.  Cut into `planes` bytes, most
+ * significant first: out [planes][kept]. */
 void orc_attr_planes(int64_t kept, const float *yc, const float *qc, const int64_t *perm,
-                     int64_t kmin, int32_t planes, int64_t S, uint8_t *out) {
+                     int64_t kmin, int32_t planes, int64_t S, int32_t predictor, uint8_t *out) {
   int64_t prev = 0;
   for (int64_t j = 0; j < kept; ++j) {
     const float r = rintf(yc[perm[j]] / qc[0]);
     const int64_t v = (int64_t)r - kmin;
     const int64_t pred = j % S == 0 ? 0 : prev;
     const int64_t d = v - pred;
-    const uint64_t z = d >= 0 ? (uint64_t)(2 * d) : (uint64_t)(-2 * d - 1);
+    const uint64_t z = predictor == 0 ? (uint64_t)v
+                       : d >= 0     ? (uint64_t)(2 * d)
+                                    : (uint64_t)(-2 * d - 1);
     for (int t = 0; t < planes; ++t)
       out[(int64_t)t * kept + j] = (uint8_t)(z >> (8 * (planes - 1 - t)));
     prev = v;
@@ -396,13 +399,13 @@ void orc_attr_planes(int64_t kept, const float *yc, const float *qc, const int64
 
 /* Inverse: the dequantized values fl32((kmin + v) q) in serialized order. */
 void orc_attr_reconstruct(int64_t kept, const uint8_t *pl, int32_t planes, int64_t S, int64_t kmin,
-                          float q, float *out) {
+                          float q, int32_t predictor, float *out) {
   int64_t prev = 0;
   for (int64_t j = 0; j < kept; ++j) {
     uint64_t z = 0;
     for (int t = 0; t < planes; ++t) z = (z << 8) | pl[(int64_t)t * kept + j];
     const int64_t d = (z & 1u) ? -(int64_t)((z + 1) / 2) : (int64_t)(z / 2);
-    const int64_t v = (j % S == 0 ? 0 : prev) + d;
+    const int64_t v = predictor == 0 ? (int64_t)z : (j % S == 0 ? 0 : prev) + d;
     out[j] = (float)(kmin + v) * q;
     prev = v;
   }

@@ -368,3 +368,23 @@ def test_fourier_features_closed_form(orc):
     pe = orc.positional_embedding(np.array([[0.5, 0.25, 0.0]]), W, b, L)
     assert np.allclose(pe[0, :3], [1.0 + 0, 1.0 + 1, 1.0 + 2])
     assert np.allclose(pe[0, 3:], b[3:])
+
+
+def test_attr_planes_without_prediction(orc):
+    # predictor 0: the values themselves, width bits -> ceil(width / 8) planes
+    y = np.array([5, 7, 6, 6, 2], np.float32)
+    pl = orc.attr_planes(y, 1.0, np.arange(5), 0, 3, 4, predictor=0)
+    assert pl.shape == (1, 5) and list(pl[0]) == [5, 7, 6, 6, 2]
+    y = np.array([300, 40, 299], np.float32)
+    pl = orc.attr_planes(y, 1.0, np.arange(3), 40, 9, 64, predictor=0)
+    assert list(pl[0]) == [1, 0, 1] and list(pl[1]) == [4, 0, 3]
+    assert orc.attr_plane_count(8, 0) == 1 and orc.attr_plane_count(9, 0) == 2
+    sc = synth.make_tiny(2000, 32, 32, seed=6)
+    q = synth.learnable_qsteps(7)
+    yhat, k = orc.fakequant(sc.params, q, sc.n)
+    bits, kmin, kmax, width = orc.fixed_length_bits(k, sc.given_mask, sc.n)
+    perm = np.nonzero(sc.given_mask)[0]
+    for c in orc.ATTR_CHANNELS:
+        pl = orc.attr_planes(sc.params[c], q[c], perm, kmin[c], width[c], 16, predictor=0)
+        back = orc.attr_reconstruct(pl, kmin[c], q[c], 16, perm.size, predictor=0)
+        assert np.array_equal(back, yhat[c, perm]), c
