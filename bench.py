@@ -860,7 +860,8 @@ def bench_coding(ctx, dev, params, q, hard, n, npad, reps=10, lane_len=256):
 
 def bench_attributes(ctx, dev, params, q, hard, n, npad, oheader, codes, m, kept, xyz, reps, S):
     """Attribute half of the coding stage on the same state: Morton order,
-    DPCM byte planes per channel, an order-0 rANS stream per plane (encode);
+    the per-channel predictor choice (previous token or none, by ideal bits),
+    byte planes per channel, an order-0 rANS stream per plane (encode);
     all planes decoded in one launch, the scene rows rebuilt, and the
     positional embedding of the decoded positions (L = 12 bands, d = 32, seeded
     weights; decode).  Also the planes' ideal bits in Gaussian index order,
@@ -868,14 +869,18 @@ def bench_attributes(ctx, dev, params, q, hard, n, npad, oheader, codes, m, kept
     import numpy as np
     import torch
 
+    from paper_2607_12656_amd.coding import choose_predictors
+
     fh = torch.empty((59, 3), dtype=torch.int32, device=dev)
     payload = torch.empty(59 * n + 64, dtype=torch.int32, device=dev)
     finfo = torch.empty(3, dtype=torch.int64, device=dev)
     ctx.fl_encode(params, q, hard, fh, payload, payload.numel(), finfo)
     fl = ctx.fl_header_host(fh.cpu().numpy())
     fl_bits = int(finfo[0].item()) + 59 * 72
-    rows = ctx.attr_plane_rows(fl)
     perm = torch.empty(max(kept, 1), dtype=torch.int32, device=dev)
+    ctx.morton_order(params, npad, n, q, hard, oheader, codes, perm)
+    pred, bits_chosen, bits_all_prev = choose_predictors(ctx, params, npad, perm, kept, fl, S)
+    rows = ctx.attr_plane_rows(fl, pred)
     planes = torch.empty((max(rows, 1), max(kept, 1)), dtype=torch.uint8, device=dev)
     nb = (kept + 64 * S - 1) // (64 * S)
     cap = ctx.ans_max_words(kept, S)
@@ -889,9 +894,10 @@ def bench_attributes(ctx, dev, params, q, hard, n, npad, oheader, codes, m, kept
         if order_perm is None:
             ctx.morton_order(params, npad, n, q, hard, oheader, codes, perm)
             p = perm
+            choose_predictors(ctx, params, npad, p, kept, fl, S)   # (the same choice)
         else:
             p = order_perm
-        ctx.attr_planes(params, npad, p, kept, fl, S, planes)
+        ctx.attr_planes(params, npad, p, kept, fl, S, planes, pred)
         for t in range(rows):
             ctx.ans_model(planes[t], kept, 0, S, freqs[t], bits[t:t + 1])
             ctx.ans_encode(planes[t], kept, 0, S, freqs[t], words[t], offs[t], infos[t])
@@ -914,7 +920,7 @@ def bench_attributes(ctx, dev, params, q, hard, n, npad, oheader, codes, m, kept
 
     def decode():
         ctx.ans_decode_multi(streams, dinfo)
-        ctx.attr_reconstruct(dplanes, kept, fl, S, out, max(kept, 1))
+        ctx.attr_reconstruct(dplanes, kept, fl, S, out, max(kept, 1), pred)
         ctx.positional_embedding(xyz, max(kept, 1), kept, 12, 32, Wpe, bpe, pe)
 
     decode()
@@ -946,6 +952,8 @@ def bench_attributes(ctx, dev, params, q, hard, n, npad, oheader, codes, m, kept
         "words": words_total,
         "bits_per_kept_gaussian": round(16.0 * words_total / max(kept, 1), 3),
         "ideal_bits_R_attr_morton_order": round(ideal_morton, 1),
+        "channels_with_prediction": int(pred[3:].sum()),
+        "ideal_bits_prediction_everywhere": round(bits_all_prev, 1),
         "ideal_bits_index_order": round(ideal_index, 1),
         "morton_over_index_bits": round(ideal_morton / max(ideal_index, 1.0), 4),
         "fixed_length_coder_bits_all_channels": fl_bits,

@@ -605,12 +605,14 @@ sgs_status sgs_ans_decode_multi(sgs_ctx *ctx, int32_t count, const sgs_ans_strea
  * from its predecessor within a group of lane_len Gaussians (the groups
  * decode in parallel).  The paper's conditional model is a causal state
  * space model fed with the decoded attributes and positional embeddings;
- * here the prediction is the previous token (per channel: residual of the
- * fixed-length coder's value v = k - kmin against the group's previous
- * value, 0 for a group's first; zigzag-mapped, d >= 0 -> 2d, d < 0 -> -2d -
- * 1) and the residual's bytes are entropy-coded as separate streams
- * ("planes", most significant first): a channel of width w bits (the fixed-
- * length coder's, sgs_fl_encode) gives ceil((w + 1) / 8) planes, none for
+ * here each channel takes one of two predictors (predictor [59], HOST bytes,
+ * entries 3-58 used; null = 1 for all): 1, the previous token (the residual
+ * of the fixed-length coder's value v = k - kmin against the group's
+ * previous value, 0 for a group's first, zigzag-mapped: d >= 0 -> 2d,
+ * d < 0 -> -2d - 1), or 0, no prediction (v itself).  The result's bytes are
+ * entropy-coded as separate streams ("planes", most significant first): a
+ * channel of width w bits (the fixed-length coder's, sgs_fl_encode) gives
+ * ceil((w + 1) / 8) planes with predictor 1, ceil(w / 8) with 0, none for
  * w = 0.  Plane rows follow the channels in order.
  *
  * Morton order: perm [kept] (device int32) receives the kept Gaussians'
@@ -620,20 +622,21 @@ sgs_status sgs_morton_order(sgs_ctx *ctx, const float *params, int64_t npad, int
                             const float *qstep, const uint8_t *hard_mask,
                             const sgs_octree_header *header, const uint64_t *codes,
                             int32_t *perm);
-/* Plane rows of a fixed-length header (HOST sgs_fl_channel[59]). */
-int64_t sgs_attr_plane_rows(const sgs_fl_channel *fl_header);
+/* Plane rows of a fixed-length header (HOST sgs_fl_channel[59]) with the
+ * given predictors. */
+int64_t sgs_attr_plane_rows(const sgs_fl_channel *fl_header, const uint8_t *predictor);
 /* Planes: planes [rows][kept] (device bytes) for the Gaussians perm [kept]
  * lists, in that order; fl_header: HOST copy of sgs_fl_encode's for the same
  * parameters, steps and mask. */
 sgs_status sgs_attr_planes(sgs_ctx *ctx, const float *params, int64_t npad, const int32_t *perm,
-                           int64_t kept, const sgs_fl_channel *fl_header, int32_t lane_len,
-                           uint8_t *planes);
+                           int64_t kept, const sgs_fl_channel *fl_header,
+                           const uint8_t *predictor, int32_t lane_len, uint8_t *planes);
 /* Inverse: out [59][out_pad] (device, out_pad >= kept) rows 3-58 receive the
  * dequantized attributes fl32((kmin + v) q) in serialized order (rows 0-2,
  * the positions, are sgs_octree_decode's xyz). */
 sgs_status sgs_attr_reconstruct(sgs_ctx *ctx, const uint8_t *planes, int64_t kept,
-                                const sgs_fl_channel *fl_header, int32_t lane_len, float *out,
-                                int64_t out_pad);
+                                const sgs_fl_channel *fl_header, const uint8_t *predictor,
+                                int32_t lane_len, float *out, int64_t out_pad);
 /* Fourier positional embedding (Sec. 3.4.2): PE(mu) = W phi(mu) + b with
  * phi(mu) = [mu; sin(2 pi f_l mu); cos(2 pi f_l mu)], f_l = 2^l for l < L
  * (band-major, axis-minor: feature 3 + 3 l + c is sin of axis c in band l,

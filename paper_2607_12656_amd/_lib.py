@@ -133,9 +133,9 @@ _SIGS = {
     "sgs_ans_decode": [P, P, I64, P, I64, I32, I32, P, P, P],
     "sgs_ans_decode_multi": [P, I32, P, P],
     "sgs_morton_order": [P, P, I64, I64, P, P, P, P, P],
-    "sgs_attr_plane_rows": [P],
-    "sgs_attr_planes": [P, P, I64, P, I64, P, I32, P],
-    "sgs_attr_reconstruct": [P, P, I64, P, I32, P, I64],
+    "sgs_attr_plane_rows": [P, P],
+    "sgs_attr_planes": [P, P, I64, P, I64, P, P, I32, P],
+    "sgs_attr_reconstruct": [P, P, I64, P, P, I32, P, I64],
     "sgs_positional_embedding": [P, P, I64, I64, I32, I32, P, P, P],
 }
 PROF_GROUPS = ("fakequant", "rate", "preprocess", "depth_sort", "scan", "duplicate",
@@ -467,19 +467,28 @@ class Context:
         C.memmove(arr, v.ctypes.data, v.nbytes)
         return arr
 
-    def attr_plane_rows(self, fl) -> int:
-        r = int(self.L.sgs_attr_plane_rows(fl))
+    @staticmethod
+    def _pred(predictor):
+        if predictor is None:
+            return None
+        v = np.ascontiguousarray(np.asarray(predictor).reshape(59), dtype=np.uint8)
+        return (C.c_uint8 * 59).from_buffer_copy(v.tobytes())
+
+    def attr_plane_rows(self, fl, predictor=None) -> int:
+        r = int(self.L.sgs_attr_plane_rows(fl, self._pred(predictor)))
         if r < 0:
             raise SgsError(-1, "attr_plane_rows: bad header")
         return r
 
-    def attr_planes(self, params, npad, perm, kept, fl, lane_len, planes):
+    def attr_planes(self, params, npad, perm, kept, fl, lane_len, planes, predictor=None):
         self._check(self.L.sgs_attr_planes(self.h, _ptr(params), npad, _ptr(perm), kept, fl,
-                                           lane_len, _ptr(planes)), self.h)
+                                           self._pred(predictor), lane_len, _ptr(planes)),
+                    self.h)
 
-    def attr_reconstruct(self, planes, kept, fl, lane_len, out, out_pad):
-        self._check(self.L.sgs_attr_reconstruct(self.h, _ptr(planes), kept, fl, lane_len,
-                                                _ptr(out), out_pad), self.h)
+    def attr_reconstruct(self, planes, kept, fl, lane_len, out, out_pad, predictor=None):
+        self._check(self.L.sgs_attr_reconstruct(self.h, _ptr(planes), kept, fl,
+                                                self._pred(predictor), lane_len, _ptr(out),
+                                                out_pad), self.h)
 
     def positional_embedding(self, xyz, pad, count, L, d, W, b, out):
         self._check(self.L.sgs_positional_embedding(self.h, _ptr(xyz), pad, count, L, d, _ptr(W),

@@ -764,14 +764,14 @@ static bool fl_header_ok(const sgs_fl_channel *fl) {
   return true;
 }
 
-int64_t sgs_attr_plane_rows(const sgs_fl_channel *fl) {
+int64_t sgs_attr_plane_rows(const sgs_fl_channel *fl, const uint8_t *predictor) {
   if (!fl || !fl_header_ok(fl)) return -1;
-  return attr_plane_rows(fl);
+  return attr_plane_rows(fl, predictor);
 }
 
 sgs_status sgs_attr_planes(sgs_ctx *c, const float *params, int64_t npad, const int32_t *perm,
-                           int64_t kept, const sgs_fl_channel *fl, int32_t lane_len,
-                           uint8_t *planes) {
+                           int64_t kept, const sgs_fl_channel *fl, const uint8_t *predictor,
+                           int32_t lane_len, uint8_t *planes) {
   if (!c) return SGS_EINVAL;
   if (!params || !fl || (kept > 0 && (!perm || !planes)))
     return fail(c, SGS_EINVAL, "attr_planes: null pointer");
@@ -779,21 +779,22 @@ sgs_status sgs_attr_planes(sgs_ctx *c, const float *params, int64_t npad, const 
       !fl_header_ok(fl))
     return fail(c, SGS_EINVAL, "attr_planes: bad sizes or header");
   SgsProfScope ps(c, SGS_PROF_ANS);
-  SGS_HIP(launch_attr_planes(c, params, npad, perm, kept, fl, lane_len, planes), "attr_planes");
+  SGS_HIP(launch_attr_planes(c, params, npad, perm, kept, fl, predictor, lane_len, planes),
+          "attr_planes");
   return SGS_OK;
 }
 
 sgs_status sgs_attr_reconstruct(sgs_ctx *c, const uint8_t *planes, int64_t kept,
-                                const sgs_fl_channel *fl, int32_t lane_len, float *out,
-                                int64_t out_pad) {
+                                const sgs_fl_channel *fl, const uint8_t *predictor,
+                                int32_t lane_len, float *out, int64_t out_pad) {
   if (!c) return SGS_EINVAL;
-  if (!fl || (kept > 0 && !out) || (kept > 0 && attr_plane_rows(fl) > 0 && !planes))
+  if (!fl || (kept > 0 && !out) || (kept > 0 && attr_plane_rows(fl, predictor) > 0 && !planes))
     return fail(c, SGS_EINVAL, "attr_reconstruct: null pointer");
   if (kept < 0 || out_pad < kept || kept > (int64_t)INT32_MAX || lane_len < 1 ||
       lane_len > 65536 || !fl_header_ok(fl))
     return fail(c, SGS_EINVAL, "attr_reconstruct: bad sizes or header");
   SgsProfScope ps(c, SGS_PROF_ANS);
-  SGS_HIP(launch_attr_reconstruct(c, planes, kept, fl, lane_len, out, out_pad),
+  SGS_HIP(launch_attr_reconstruct(c, planes, kept, fl, predictor, lane_len, out, out_pad),
           "attr_reconstruct");
   return SGS_OK;
 }

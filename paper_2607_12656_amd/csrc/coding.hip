@@ -892,7 +892,7 @@ __global__ void k_copy_u32(const uint32_t *__restrict__ src, int64_t count, int3
 
 struct AttrChan {
   float q;
-  int32_t kmin, planes, row0;
+  int32_t kmin, planes, row0, pred;
 };
 struct AttrChans {
   AttrChan ch[SGS_NCH - 3];
@@ -910,9 +910,12 @@ __global__ void k_attr_planes(const float *__restrict__ params, int64_t npad,
   const float *y = params + (int64_t)(3 + blockIdx.y) * npad;
   bool ok;
   const int64_t v = (int64_t)sgs_code_of(y[perm[j]], a.q, ok) - a.kmin;
-  const int64_t pred = j % S == 0 ? 0 : (int64_t)sgs_code_of(y[perm[j - 1]], a.q, ok) - a.kmin;
-  const int64_t d = v - pred;
-  const uint64_t z = d >= 0 ? (uint64_t)(2 * d) : (uint64_t)(-2 * d - 1);
+  uint64_t z = (uint64_t)v;  // predictor 0: the value itself
+  if (a.pred) {
+    const int64_t pv = j % S == 0 ? 0 : (int64_t)sgs_code_of(y[perm[j - 1]], a.q, ok) - a.kmin;
+    const int64_t d = v - pv;
+    z = d >= 0 ? (uint64_t)(2 * d) : (uint64_t)(-2 * d - 1);
+  }
   for (int t = 0; t < a.planes; ++t)
     planes[(int64_t)(a.row0 + t) * kept + j] = (uint8_t)(z >> (8 * (a.planes - 1 - t)));
 }
@@ -941,7 +944,11 @@ k_attr_reconstruct(const uint8_t *__restrict__ planes, int64_t kept, int64_t S, 
       if (j < j1)
         for (int t = 0; t < a.planes; ++t) z = (z << 8) | planes[(int64_t)(a.row0 + t) * kept + j];
       d[k] = (z & 1u) ? -(int64_t)((z + 1) >> 1) : (int64_t)(z >> 1);
+      if (!a.pred) {  // predictor 0: the value itself
+        if (j < j1) o[j] = (float)(a.kmin + (int64_t)z) * a.q;
+      }
     }
+    if (!a.pred) continue;
     const int64_t sum = (d[0] + d[1]) + (d[2] + d[3]);
     int64_t incl = sum;
 #pragma unroll
@@ -1368,30 +1375,31 @@ hipError_t launch_morton_order(sgs_ctx *c, const float *params, int64_t npad, in
   return hipGetLastError();
 }
 
-static AttrChans attr_chans(const sgs_fl_channel *fl, int64_t *rows) {
+static AttrChans attr_chans(const sgs_fl_channel *fl, const uint8_t *pred, int64_t *rows) {
   AttrChans C;
   int32_t r = 0;
   for (int j = 3; j < SGS_NCH; ++j) {
     const int w = fl[j].width;
-    const int P = w == 0 ? 0 : (w + 8) / 8;
-    C.ch[j - 3] = AttrChan{fl[j].q, fl[j].kmin, P, r};
+    const int pj = pred ? (pred[j] ? 1 : 0) : 1;
+    const int P = w == 0 ? 0 : pj ? (w + 8) / 8 : (w + 7) / 8;
+    C.ch[j - 3] = AttrChan{fl[j].q, fl[j].kmin, P, r, pj};
     r += P;
   }
   *rows = r;
   return C;
 }
 
-int64_t attr_plane_rows(const sgs_fl_channel *fl) {
+int64_t attr_plane_rows(const sgs_fl_channel *fl, const uint8_t *pred) {
   int64_t r;
-  (void)attr_chans(fl, &r);
+  (void)attr_chans(fl, pred, &r);
   return r;
 }
 
 hipError_t launch_attr_planes(sgs_ctx *c, const float *params, int64_t npad, const int32_t *perm,
-                              int64_t kept, const sgs_fl_channel *fl, int32_t S,
-                              uint8_t *planes) {
+                              int64_t kept, const sgs_fl_channel *fl, const uint8_t *pred,
+                              int32_t S, uint8_t *planes) {
   int64_t rows;
-  const AttrChans C = attr_chans(fl, &rows);
+  const AttrChans C = attr_chans(fl, pred, &rows);
   if (kept > 0 && rows > 0)
     k_attr_planes<<<dim3(grid_for(kept, 256, 1 << 30), SGS_NCH - 3), 256, 0, c->stream>>>(
         params, npad, perm, kept, S, C, planes);
@@ -1399,10 +1407,10 @@ hipError_t launch_attr_planes(sgs_ctx *c, const float *params, int64_t npad, con
 }
 
 hipError_t launch_attr_reconstruct(sgs_ctx *c, const uint8_t *planes, int64_t kept,
-                                   const sgs_fl_channel *fl, int32_t S, float *out,
-                                   int64_t out_pad) {
+                                   const sgs_fl_channel *fl, const uint8_t *pred, int32_t S,
+                                   float *out, int64_t out_pad) {
   int64_t rows;
-  const AttrChans C = attr_chans(fl, &rows);
+  const AttrChans C = attr_chans(fl, pred, &rows);
   const int64_t groups = (kept + S - 1) / S;
   if (kept > 0)
     k_attr_reconstruct<<<dim3((unsigned)((groups + 3) / 4), SGS_NCH - 3), 256, 0, c->stream>>>(

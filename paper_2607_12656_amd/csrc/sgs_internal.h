@@ -303,13 +303,13 @@ hipError_t launch_ans_decode_multi(sgs_ctx *c, int32_t count, const sgs_ans_stre
 hipError_t launch_morton_order(sgs_ctx *c, const float *params, int64_t npad, int64_t n,
                                const float *q, const uint8_t *hard, const sgs_octree_header *h,
                                const uint64_t *codes, int32_t *perm);
-int64_t attr_plane_rows(const sgs_fl_channel *fl);
+int64_t attr_plane_rows(const sgs_fl_channel *fl, const uint8_t *pred);
 hipError_t launch_attr_planes(sgs_ctx *c, const float *params, int64_t npad, const int32_t *perm,
-                              int64_t kept, const sgs_fl_channel *fl, int32_t S,
-                              uint8_t *planes);
+                              int64_t kept, const sgs_fl_channel *fl, const uint8_t *pred,
+                              int32_t S, uint8_t *planes);
 hipError_t launch_attr_reconstruct(sgs_ctx *c, const uint8_t *planes, int64_t kept,
-                                   const sgs_fl_channel *fl, int32_t S, float *out,
-                                   int64_t out_pad);
+                                   const sgs_fl_channel *fl, const uint8_t *pred, int32_t S,
+                                   float *out, int64_t out_pad);
 hipError_t launch_pos_embed(sgs_ctx *c, const float *xyz, int64_t pad, int64_t count, int L,
                             int d, const float *W, const float *b, float *out);
 

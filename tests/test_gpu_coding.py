@@ -350,7 +350,7 @@ def test_ans_flags_and_damage(orc, gctx, dev):
 # ---------------------------------------------------------------------------
 # attributes: Morton order, planes, multi-stream decode, reconstruction, PE
 # ---------------------------------------------------------------------------
-def attr_case(orc, gctx, dev, sc, q, S, name, coded_planes=None):
+def attr_case(orc, gctx, dev, sc, q, S, name, coded_planes=None, predictor=None):
     """Whole attribute path on one scene against the oracle; returns the
     decoded scene rows [59][kept] (serialized order)."""
     _say(f"[gpu] attributes {name} n={sc.n} lane_len={S}")
@@ -380,14 +380,15 @@ def attr_case(orc, gctx, dev, sc, q, S, name, coded_planes=None):
     yhat, k = orc.fakequant(sc.params, q, n)
     bits, kmin, kmax, width = orc.fixed_length_bits(k, m, n)
     assert np.array_equal(fhn[:, 1], kmin) and np.array_equal(fhn[:, 2], width)
-    rows = gctx.attr_plane_rows(fl)
-    want = [orc.attr_planes(sc.params[c], q[c], want_perm, kmin[c], width[c], S)
+    pred = np.ones(59, np.uint8) if predictor is None else predictor
+    rows = gctx.attr_plane_rows(fl, pred)
+    want = [orc.attr_planes(sc.params[c], q[c], want_perm, kmin[c], width[c], S, int(pred[c]))
             for c in orc.ATTR_CHANNELS]
     want = np.concatenate([w for w in want if w.size], axis=0) if rows else \
         np.zeros((0, kept), np.uint8)
     assert want.shape == (rows, kept)
     planes = torch.zeros(max(rows * kept, 1), dtype=torch.uint8, device=dev)
-    gctx.attr_planes(P, npad, perm, kept, fl, S, planes)
+    gctx.attr_planes(P, npad, perm, kept, fl, S, planes, pred)
     torch.cuda.synchronize()
     got = planes.cpu().numpy()[:rows * kept].reshape(rows, kept)
     assert np.array_equal(got, want)
@@ -414,15 +415,15 @@ def attr_case(orc, gctx, dev, sc, q, S, name, coded_planes=None):
     # reconstruction: attribute rows, positions from the octree decode
     out = torch.full((59, max(kept, 1)), float("nan"), dtype=torch.float32, device=dev)
     dplanes = torch.from_numpy(np.ascontiguousarray(dec).reshape(-1)).to(dev) if rows else planes
-    gctx.attr_reconstruct(dplanes, kept, fl, S, out, max(kept, 1))
+    gctx.attr_reconstruct(dplanes, kept, fl, S, out, max(kept, 1), pred)
     codes2, xyz, oinfo = gpu_decode(gctx, dev, g, q)
     assert oinfo == 0
     out[:3, :kept] = torch.from_numpy(xyz).to(dev)
     torch.cuda.synchronize()
     scene = out.cpu().numpy()[:, :kept]
     for c in orc.ATTR_CHANNELS:
-        pl = orc.attr_planes(sc.params[c], q[c], want_perm, kmin[c], width[c], S)
-        ref = orc.attr_reconstruct(pl, kmin[c], q[c], S, kept)
+        pl = orc.attr_planes(sc.params[c], q[c], want_perm, kmin[c], width[c], S, int(pred[c]))
+        ref = orc.attr_reconstruct(pl, kmin[c], q[c], S, kept, int(pred[c]))
         assert np.array_equal(scene[c], ref), c
     # the decoded scene is the quantized scene in Morton order
     assert np.array_equal(scene, yhat[:, want_perm])
@@ -433,6 +434,47 @@ def attr_case(orc, gctx, dev, sc, q, S, name, coded_planes=None):
 def test_attributes_match_oracle(orc, gctx, dev, S):
     sc = synth.make_tiny(5000, 48, 32, seed=7)
     attr_case(orc, gctx, dev, sc, synth.learnable_qsteps(8), S, "tiny")
+    # mixed predictors (seeded): both kinds of channel in one set of planes
+    pred = (np.random.default_rng(S).random(59) < 0.5).astype(np.uint8)
+    attr_case(orc, gctx, dev, sc, synth.learnable_qsteps(8), S, "tiny mixed", predictor=pred)
+
+
+def test_predictor_choice(orc, gctx, dev):
+    """The library-side choice equals the one made from the oracle's planes
+    and ideal code lengths: a smooth channel (neighbours in Morton order
+    alike) takes prediction, an independent one does not."""
+    from paper_2607_12656_amd.coding import choose_predictors
+    sc = synth.make_tiny(6000, 32, 32, seed=11)
+    n, npad = sc.n, sc.npad
+    q = synth.learnable_qsteps(12)
+    q[:3] = 2.0 ** -7
+    sc.params[20, :n] = np.float32(8.0) * sc.params[0, :n] + sc.params[1, :n]   # smooth in space
+    m = sc.given_mask
+    r = orc.octree_tokens(sc.params, q, m, n)
+    perm = orc.morton_order(sc.params, q, m, n, r["depth"], r["kmin"])
+    yhat, k = orc.fakequant(sc.params, q, n)
+    bits, kmin, kmax, width = orc.fixed_length_bits(k, m, n)
+    S = 64
+    want = np.ones(59, np.uint8)
+    for c in orc.ATTR_CHANNELS:
+        b = []
+        for p in (0, 1):
+            pl = orc.attr_planes(sc.params[c], q[c], perm, kmin[c], width[c], S, p)
+            b.append(sum(orc.ans_ideal_bits(pl[t], 0, S, orc.ans_model(pl[t], 0, S))
+                         for t in range(pl.shape[0])))
+        want[c] = 1 if b[1] < b[0] else 0
+    assert want[20] == 1
+    gctx.set_scene(n, npad, sc.n_hat, sc.cams, sc.width, sc.height)
+    P, Q = T(sc.params, dev), T(q, dev)
+    fh = torch.zeros(59, 3, dtype=torch.int32, device=dev)
+    payload = torch.zeros(59 * n + 64, dtype=torch.int32, device=dev)
+    info = torch.zeros(3, dtype=torch.int64, device=dev)
+    gctx.fl_encode(P, Q, T(m, dev), fh, payload, payload.numel(), info)
+    fl = gctx.fl_header_host(fh.cpu().numpy())
+    pd = T(perm.astype(np.int32), dev)
+    pred, chosen, all_prev = choose_predictors(gctx, P, npad, pd, perm.size, fl, S)
+    assert np.array_equal(pred[3:], want[3:])
+    assert chosen <= all_prev
 
 
 def test_attributes_edge_cases(orc, gctx, dev):
