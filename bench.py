@@ -300,10 +300,17 @@ def bench_formation(args, sc, ctx, stream, dev, t):
     say(f"c5: scene {sc.n} x {sc.views} views {sc.width}x{sc.height} resident")
 
     # tile shape and blend schedule: the library's tuner on the plain step
+    # (or fixed by --tile / --schedule, e.g. for counter runs, whose overhead
+    # would steer the tuner)
     ctx.set_scene(sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height)
-    tune = autotune.tune_native(ctx, p0, q0, mask, target, sc.n, sc.views, sc.width, sc.height,
-                                reps=2)
-    tile, schedule = tune["tile"], tune["schedule"]
+    if args.tile and args.tile != "auto":
+        tile = tuple(int(v) for v in args.tile.split("x"))
+        schedule = args.schedule or "tile"
+        tune = {"tile": tile, "schedule": schedule, "ms": None}
+    else:
+        tune = autotune.tune_native(ctx, p0, q0, mask, target, sc.n, sc.views, sc.width,
+                                    sc.height, reps=2)
+        tile, schedule = tune["tile"], tune["schedule"]
     say(f"c5: tuned {tile} {schedule}")
     rd = RDStep(ctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height, tile=tile,
                 schedule=schedule, fused=True)
@@ -486,7 +493,7 @@ def bench_formation(args, sc, ctx, stream, dev, t):
                                f"learned rate in the loop (forward + backward), fallback rule every {CHECK} iterations, "
                                f"Adam on parameters / steps / scores (higher SH every 16th, "
                                f"sparse), lambda {lam}, tile {tile[0]}x{tile[1]} "
-                               f"({schedule} schedule, autotuned)",
+                               f"({schedule} schedule, " + ("autotuned)" if tune["ms"] else "fixed)"),
                    "gaussians": sc.n, "views": sc.views, "width": sc.width,
                    "height": sc.height, "tile": f"{tile[0]}x{tile[1]}", "schedule": schedule,
                    "mlp_weights": "trained on the GPU on this scene's fixed-length coder "
@@ -976,7 +983,8 @@ def main():
                     help="c5: the formation iteration at 3M Gaussians x 8 views of 1600x1060, "
                          "learned vs plain rate (default); c2: the plain RD step at 1M, one "
                          "1297x840 view; c3: the plain RD step at 3M x 8 views")
-    ap.add_argument("--tile", default=None, help="16x16 | 8x8 | 32x8 | auto (c2 / c3)")
+    ap.add_argument("--tile", default=None,
+                    help="16x16 | 8x8 | 32x8 | auto (default: auto for c3 / c5, 16x16 for c2)")
     ap.add_argument("--schedule", default=None, choices=("tile", "stride", "queue", "block"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
