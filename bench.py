@@ -89,17 +89,18 @@ def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int, items: in
     pix = V * W * H
     if g == "fakequant":          # statistics and mask (the projection quantizes)
         return "hbm", n * (NCH * 4 + 1 + 1 + 4), "B"
-    if g == "preprocess":
-        return "hbm", n * (NCH * 4 + 1) + V * n * (48 + 12), "B"
+    if g == "preprocess":         # splat record 48 B, depth key / value / count 12 B,
+        # binning record 16 B per splat
+        return "hbm", n * (NCH * 4 + 1) + V * n * (48 + 12 + 16), "B"
     if g == "depth_sort":         # one read + one write of key and value
         return "hbm", V * n * 16, "B"
     if g == "scan":               # binning records gathered into depth order (16 + 16),
         # pair counts and offsets (4 + 4 + 4), super-tile records and counts (16 + 4),
         # item offsets (4 + 4)
         return "hbm", V * n * 72, "B"
-    if g == "duplicate":          # every pair written once (4 B); per item its depth
-        # rank (4 B) and binning record (16 B) read
-        return "hbm", P * 4 + items * 20, "B"
+    if g == "duplicate":          # every pair written once (4 B); per item its key and
+        # Gaussian index read (8 B)
+        return "hbm", P * 4 + items * 8, "B"
     if g == "tile_sort":          # items generated and sorted by super-tile (8 B written,
         # 16 B per further 8-bit pass), then read for the tile counts (4 + 16)
         extra = max(0, (max(st - 1, 1).bit_length() - 1) // 8)
