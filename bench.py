@@ -863,7 +863,43 @@ def bench_coding(ctx, dev, params, q, hard, n, npad, reps=10, lane_len=256):
                                                         codes, m, kept, xyz, reps, S)
             res[label]["attributes"]["geometry_and_attributes_decode_ms"] = round(
                 timed["decode"] + res[label]["attributes"]["decode_ms"], 4)
+            res[label]["container"] = bench_container(ctx, dev, params, q, hard, n, npad, kept,
+                                                      S)
     return res
+
+
+def bench_container(ctx, dev, params, q, hard, n, npad, kept, S):
+    """The whole coding-stage stream as bytes (headers, model tables, rANS
+    words): its size against the fixed-length coder's, and the wall time of
+    encoding into a host byte string and decoding from one (host-device
+    transfers included, unlike the device-resident decode times above)."""
+    import numpy as np
+    import torch
+
+    from paper_2607_12656_amd.coding import decode_scene, encode_scene
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    data, sizes = encode_scene(ctx, params, npad, n, q, hard, S)
+    t_enc = time.perf_counter() - t0
+    decode_scene(ctx, data, dev)           # first call allocates the decoder's scratch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    scene = decode_scene(ctx, data, dev)
+    torch.cuda.synchronize()
+    t_dec = time.perf_counter() - t0
+    fh = torch.empty((59, 3), dtype=torch.int32, device=dev)
+    payload = torch.empty(59 * n + 64, dtype=torch.int32, device=dev)
+    info = torch.empty(3, dtype=torch.int64, device=dev)
+    ctx.fl_encode(params, q, hard, fh, payload, payload.numel(), info)
+    fl_bits = int(info[0].item()) + 59 * 72
+    assert scene.shape[1] == kept
+    say(f"coding container: {len(data)} bytes, decode from host {t_dec * 1e3:.2f} ms")
+    return {"bytes": len(data), "parts": sizes,
+            "bits_per_kept_gaussian": round(8.0 * len(data) / max(kept, 1), 3),
+            "fixed_length_coder_bits": fl_bits,
+            "size_vs_fixed_length": round(8.0 * len(data) / fl_bits, 4),
+            "encode_to_host_s": round(t_enc, 3), "decode_from_host_ms": round(t_dec * 1e3, 3)}
 
 
 def bench_attributes(ctx, dev, params, q, hard, n, npad, oheader, codes, m, kept, xyz, reps, S):

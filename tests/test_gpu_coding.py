@@ -514,3 +514,42 @@ def test_positional_embedding(orc, gctx, dev, L, d):
     bound = np.abs(W).sum(axis=1)[None, :] * 2.5e-7 + \
         F * 6e-8 * (np.abs(orc.fourier_features(xyz[:, :count].T, L)) @ np.abs(W).T + np.abs(b))
     assert np.all(np.abs(got - ref) <= bound + 1e-7), np.max(np.abs(got - ref) - bound)
+
+
+# ---------------------------------------------------------------------------
+# the whole stream as bytes
+# ---------------------------------------------------------------------------
+def scene_round_trip(orc, gctx, dev, sc, q, S, name):
+    from paper_2607_12656_amd import coding
+    _say(f"[gpu] container {name} n={sc.n}")
+    n, npad = sc.n, sc.npad
+    gctx.set_scene(n, npad, sc.n_hat, sc.cams, sc.width, sc.height)
+    P, Q, M = T(sc.params, dev), T(q, dev), T(sc.given_mask, dev)
+    data, sizes = coding.encode_scene(gctx, P, npad, n, Q, M, S)
+    assert sizes["total"] == len(data)
+    scene = coding.decode_scene(gctx, data, dev)
+    torch.cuda.synchronize()
+    r = orc.octree_tokens(sc.params, q, sc.given_mask, n)
+    perm = orc.morton_order(sc.params, q, sc.given_mask, n, r["depth"], r["kmin"])
+    yhat, _ = orc.fakequant(sc.params, q, n)
+    assert np.array_equal(scene.cpu().numpy(), yhat[:, perm])
+    return data
+
+
+def test_container_round_trip(orc, gctx, dev):
+    sc = synth.make_tiny(4000, 32, 32, seed=13)
+    data = scene_round_trip(orc, gctx, dev, sc, synth.learnable_qsteps(14), 64, "tiny")
+    from paper_2607_12656_amd import coding
+    # a damaged stream is refused
+    bad = bytearray(data)
+    bad[len(bad) // 2] ^= 0x40
+    with pytest.raises((RuntimeError, ValueError)):
+        coding.decode_scene(gctx, bytes(bad), dev)
+    with pytest.raises(ValueError):
+        coding.decode_scene(gctx, bytes(data) + b"x", dev)
+
+
+def test_container_full_size_scene(orc, gctx, dev):
+    sc = synth.make_scene("c3")
+    q = np.full(59, 2.0 ** -8, np.float32)
+    scene_round_trip(orc, gctx, dev, sc, q, 256, "c3")

@@ -388,3 +388,26 @@ def test_attr_planes_without_prediction(orc):
         pl = orc.attr_planes(sc.params[c], q[c], perm, kmin[c], width[c], 16, predictor=0)
         back = orc.attr_reconstruct(pl, kmin[c], q[c], 16, perm.size, predictor=0)
         assert np.array_equal(back, yhat[c, perm]), c
+
+
+# ---------------------------------------------------------------------------
+# stream container marshalling (host code, no GPU)
+# ---------------------------------------------------------------------------
+def test_container_model_and_stream_round_trip(orc):
+    from paper_2607_12656_amd import coding
+    rng = np.random.default_rng(9)
+    sym = rng.integers(0, 40, 20000).astype(np.uint8)
+    for order in (0, 1):
+        f = orc.ans_model(sym, order, 64)
+        b = coding.pack_model(f, order)
+        g, o, pos = coding.unpack_model(b, 0)
+        assert o == order and pos == len(b) and np.array_equal(f, g)
+        used = (f.sum(axis=1) > 0).sum()
+        nz = int((f > 0).sum())
+        assert len(b) == 1 + (33 if order else 0) + 2 * used + 3 * nz
+        w, off = orc.ans_encode(sym, order, 64, f)
+        s = coding.pack_stream(w, off)
+        w2, off2, pos = coding.unpack_stream(s, 0)
+        assert pos == len(s) and np.array_equal(w, w2) and np.array_equal(off, off2)
+        # the unpacked pieces decode
+        assert np.array_equal(orc.ans_decode(w2, off2, sym.size, order, 64, g), sym)
