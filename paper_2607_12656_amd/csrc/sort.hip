@@ -4,9 +4,9 @@
 // The splats are sorted by depth once (V*N keys, 32 bits).  The pairs are
 // then ordered in two levels instead of by a radix sort over every pair:
 //  1. items: each splat, in depth order, yields one item per super-tile
-//     (8x8 tiles) its tile rectangle meets; the items are stably sorted by
-//     super-tile id (generated on the fly in the first radix pass), so each
-//     super-tile's items stay in depth order;
+//     (8x8 tiles) its tile rectangle meets, written at its item offset; the
+//     items are stably sorted by super-tile id, so each super-tile's items
+//     stay in depth order;
 //  2. each super-tile's items are cut into chunks of 1024; a chunk's
 //     workgroup turns every item into a 64-bit mask of the super-tile's tiles
 //     it covers, counts the pairs per tile (one ballot per tile bit), and,
@@ -96,39 +96,60 @@ k_scan_sums(uint32_t *__restrict__ sums, int64_t nb, uint32_t *__restrict__ tota
   }
 }
 
+// Each wave scans 16 x 64 consecutive elements of the block's 4096 as 64
+// consecutive elements at a time (so every load and store is one coalesced
+// access), carrying the running sum from group to group; the waves' totals
+// are then scanned across the block.
 __global__ void __launch_bounds__(kThreads)
 k_scan_down(const uint32_t *__restrict__ in, int64_t count, const uint32_t *__restrict__ sums,
             uint32_t *__restrict__ out) {
   __shared__ uint32_t s_wave[kWaves];
-  // each thread scans kItems consecutive elements
-  const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)wave * (kItems * 64) + lane;
   uint32_t v[kItems];
-  uint32_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) v[k] = (base + k * 64 < count) ? in[base + k * 64] : 0u;
+  // inclusive scans of the 16 groups (independent, interleaved), then carries
+  uint32_t x[kItems];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) x[k] = v[k];
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const uint32_t t = __shfl_up(x[k], o, 64);
+      if (lane >= o) x[k] += t;
+    }
+  }
+  uint32_t carry = 0;
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
-    v[k] = (base + k < count) ? in[base + k] : 0;
-    acc += v[k];
+    const uint32_t tot = (uint32_t)__shfl(x[k], 63, 64);
+    x[k] += carry - v[k];  // exclusive within the wave's segment
+    carry += tot;
   }
-  uint32_t total;
-  uint32_t run = block_exclusive_scan(acc, s_wave, total) + sums[blockIdx.x];
+  if (lane == 0) s_wave[wave] = carry;
+  __syncthreads();
+  uint32_t off = sums[blockIdx.x];
+  for (int w = 0; w < wave; ++w) off += s_wave[w];
 #pragma unroll
-  for (int k = 0; k < kItems; ++k) {
-    if (base + k < count) out[base + k] = run;
-    run += v[k];
-  }
+  for (int k = 0; k < kItems; ++k)
+    if (base + k * 64 < count) out[base + k * 64] = off + x[k];
 }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort, 8-bit digits, reduce-then-scan.  Elements of a
-// block are taken in rounds of 256 (position base + r*256 + tid); within a
-// round each wave finds the lanes sharing its digit with eight ballots, so
-// ranks follow (round, wave, lane) = input order.
+// Stable LSD radix sort, 8-bit digits (the last pass of a key narrower than
+// a multiple of 8 bits takes only the bits left: nb < 8), reduce-then-scan.
+// Elements of a block are taken in rounds of 256 (position base + r*256 +
+// tid); within a round each wave finds the lanes sharing its digit with nb
+// ballots, so ranks follow (round, wave, lane) = input order.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int nb) {
   const uint64_t v = __ballot(valid);
   uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
+    if (b >= nb) break;  // the pass's digit has nb bits (wave-uniform)
     // s: all ones where the lane's bit b is set; a lane keeps the lanes whose
     // bit b equals its own, i.e. those where the ballot agrees with s (kept
     // as 32-bit halves so that each half is one three-input bitwise op)
@@ -147,7 +168,7 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
 template <int IT>
 __global__ void __launch_bounds__(kThreads)
 k_radix_hist(const uint32_t *__restrict__ keys, int64_t count_static,
-             const uint32_t *__restrict__ dcount, int shift, uint32_t *__restrict__ hist) {
+             const uint32_t *__restrict__ dcount, int shift, int nb, uint32_t *__restrict__ hist) {
   constexpr int TILE = kThreads * IT;
   __shared__ uint32_t s_sub[kThreads / 8][257];
   const int64_t count = dcount ? (int64_t)*dcount : count_static;
@@ -157,6 +178,7 @@ k_radix_hist(const uint32_t *__restrict__ keys, int64_t count_static,
     hist[blk * 256 + threadIdx.x] = 0;
     return;
   }
+  const uint32_t dmask = (1u << nb) - 1u;
 #pragma unroll
   for (int w = 0; w < kThreads / 8; ++w) s_sub[w][threadIdx.x] = 0;
   // all loads of the block in flight at once
@@ -167,11 +189,29 @@ k_radix_hist(const uint32_t *__restrict__ keys, int64_t count_static,
     kr[r] = i < count ? keys[i] : 0u;
   }
   __syncthreads();
-  uint32_t *mine = s_sub[threadIdx.x >> 3];
+  if (nb <= 3) {
+    // at most 8 digits: the keys share few addresses, which LDS atomics would
+    // serialize on; a ballot per digit value and round counts them instead,
+    // and lane v of each wave adds the wave's count of digit v once
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t own = 0;
 #pragma unroll
-  for (int r = 0; r < IT; ++r) {
-    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
-    if (i < count) atomicAdd(&mine[(kr[r] >> shift) & 0xFFu], 1u);
+    for (int r = 0; r < IT; ++r) {
+      const bool ok = base + (int64_t)r * kThreads + threadIdx.x < count;
+      const uint32_t d = (kr[r] >> shift) & dmask;
+      for (uint32_t v = 0; v <= dmask; ++v) {
+        const uint32_t n = (uint32_t)__popcll(__ballot(ok && d == v));
+        if (lane == v) own += n;
+      }
+    }
+    if (lane <= dmask) atomicAdd(&s_sub[0][lane], own);
+  } else {
+    uint32_t *mine = s_sub[threadIdx.x >> 3];
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+      const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+      if (i < count) atomicAdd(&mine[(kr[r] >> shift) & dmask], 1u);
+    }
   }
   __syncthreads();
   uint32_t tot = 0;
@@ -300,7 +340,7 @@ constexpr int kTilePad = kTile;
 template <int IT>
 __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[IT],
                                               const uint32_t (&vr)[IT], int64_t base,
-                                              int64_t count, int shift, uint32_t h_scan,
+                                              int64_t count, int shift, int nb, uint32_t h_scan,
                                               uint32_t *__restrict__ kout,
                                               uint32_t *__restrict__ vout, uint32_t *s_key,
                                               uint32_t *s_val) {
@@ -309,6 +349,7 @@ __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[IT],
   __shared__ uint32_t s_cnt[kWaves][256];
   __shared__ uint32_t s_wave[kWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t dmask = (1u << nb) - 1u;
   s_base[threadIdx.x] = h_scan;
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) s_cnt[w][threadIdx.x] = 0;
@@ -319,8 +360,8 @@ __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[IT],
 #pragma unroll
   for (int r = 0; r < IT; ++r) {
     const bool valid = wbase + (int64_t)r * 64 + lane < count;
-    const uint32_t d = (kr[r] >> shift) & 0xFFu;
-    const uint64_t m = match_digit(d, valid);
+    const uint32_t d = (kr[r] >> shift) & dmask;
+    const uint64_t m = match_digit(d, valid, nb);
     const uint32_t before = valid ? s_cnt[wave][d] : 0u;
     const uint32_t below = (uint32_t)__popcll(m & lt);  // same-digit lanes before this one
     rank[r] = before + below;
@@ -346,7 +387,7 @@ __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[IT],
 #pragma unroll
   for (int r = 0; r < IT; ++r) {
     if (wbase + (int64_t)r * 64 + lane < count) {
-      const uint32_t d = (kr[r] >> shift) & 0xFFu;
+      const uint32_t d = (kr[r] >> shift) & dmask;
       const uint32_t lp = s_loff[d] + s_cnt[wave][d] + rank[r];  // < kThreads * IT
       s_key[lp] = kr[r];
       s_val[lp] = vr[r];
@@ -357,7 +398,7 @@ __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[IT],
 #pragma unroll 4
   for (int p = threadIdx.x; p < nloc; p += kThreads) {
     const uint32_t k = s_key[p];
-    const uint32_t d = (k >> shift) & 0xFFu;
+    const uint32_t d = (k >> shift) & dmask;
     const uint32_t pos = s_base[d] + ((uint32_t)p - s_loff[d]);
     kout[pos] = k;
     vout[pos] = s_val[p];
@@ -368,7 +409,7 @@ template <int IT>
 __global__ void __launch_bounds__(kThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                 uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
-                int64_t count_static, const uint32_t *__restrict__ dcount, int shift,
+                int64_t count_static, const uint32_t *__restrict__ dcount, int shift, int nb,
                 const uint32_t *__restrict__ hist_scanned,
                 const uint32_t *__restrict__ digit_tot) {
   constexpr int TILE = kThreads * IT;
@@ -388,287 +429,12 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
     vr[r] = i < count ? vin[i] : 0u;
   }
   const uint32_t h_scan = scanned_offset(hist_scanned, digit_tot, blk);
-  scatter_block<IT>(kr, vr, base, count, shift, h_scan, kout, vout, s_key, s_val);
+  scatter_block<IT>(kr, vr, base, count, shift, nb, h_scan, kout, vout, s_key, s_val);
 }
 
 // ---------------------------------------------------------------------------
-// Binning: pair emission fused with the first digit pass
+// Binning input in depth order
 // ---------------------------------------------------------------------------
-// The pairs of the splats in depth order (key: global tile id, value:
-// Gaussian index) are never written in emission order: the kernels below
-// generate them on the fly from one 16-byte record per splat, once to count
-// the low digit per block and once to scatter them by that digit.
-
-// Binning records in depth order (the only gather of splat data in that
-// order) and the pair counts, input of the offsets scan.
-__global__ void k_gather_bins(const uint32_t *__restrict__ order,
-                              const uint4 *__restrict__ bin_splat, int64_t count,
-                              uint32_t *__restrict__ cnt_out, uint4 *__restrict__ brec) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= count) return;
-  const uint4 b = bin_splat[order[k]];
-  cnt_out[k] = b.w;
-  brec[k] = b;
-}
-
-// First splat (in depth order) of every block of kTile pairs: the block
-// starting inside splat k's pair range records k.
-__global__ void k_block_starts(const uint32_t *__restrict__ offsets, int64_t vn,
-                               int64_t count_static, const uint32_t *__restrict__ dcount,
-                               uint32_t *__restrict__ bstart) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= vn) return;
-  const int64_t count = dcount ? (int64_t)*dcount : count_static;
-  const int64_t a = offsets[k];
-  const int64_t e = min((int64_t)offsets[k + 1], count);
-  for (int64_t b = (a + kTile - 1) / kTile; b * kTile < e; ++b) bstart[b] = (uint32_t)k;
-}
-
-// Pairs base + tid*kItems + j, j < kItems (those below count) of the
-// depth-ordered emission: key = first tile + row * GW + column inside the
-// splat's tile rectangle (row-major), value = Gaussian index.  The block's
-// splats are [klo, khi] (khi = the splat of the next block's first pair, or
-// the last splat); each of them marks the threads whose first pair it owns,
-// so no thread searches.  When the block spans at most kWin splats their
-// offsets and records are staged in LDS (`win`, 16-byte aligned, kWinWords
-// words, free again on return) and the walk reads nothing else; otherwise
-// it reads them from global memory.  s_k (kThreads words of LDS, disjoint
-// from win, free again on return) holds each thread's first splat.  Splats
-// without pairs own no pair and are passed over.
-constexpr int kWin = 512;
-constexpr int kWinWords = 4 * kWin + kWin + 1;
-
-__device__ __forceinline__ void gen_block(const uint32_t *__restrict__ offsets,
-                                          const uint4 *__restrict__ brec,
-                                          const uint32_t *__restrict__ bstart, int64_t blk,
-                                          int64_t base, int64_t count, int64_t vn, int GW,
-                                          uint32_t *win, uint32_t *s_k, uint32_t (&key)[kItems],
-                                          uint32_t (&val)[kItems]) {
-  const int64_t nb_live = (count + kTile - 1) / kTile;
-  const int64_t klo = bstart[blk];
-  const int64_t khi = blk + 1 < nb_live ? (int64_t)bstart[blk + 1] : vn - 1;
-  const int64_t m = khi - klo + 1;
-  const bool staged = m <= kWin;  // uniform over the block
-  uint4 *w_rec = reinterpret_cast<uint4 *>(win);
-  uint32_t *w_off = win + 4 * kWin;
-  if (staged) {
-    for (int i = threadIdx.x; i <= m; i += kThreads) w_off[i] = offsets[klo + i];
-    for (int i = threadIdx.x; i < m; i += kThreads) w_rec[i] = brec[klo + i];
-    __syncthreads();
-  }
-  for (int64_t i = threadIdx.x; i < m; i += kThreads) {
-    const int64_t a = staged ? w_off[i] : offsets[klo + i];
-    const int64_t e = staged ? w_off[i + 1] : offsets[klo + i + 1];
-    // threads tt whose first pair base + tt*kItems lies in [a, e)
-    int64_t t0 = a <= base ? 0 : (a - base + kItems - 1) / kItems;
-    const int64_t t1 = min((int64_t)kThreads, e <= base ? 0 : (e - base + kItems - 1) / kItems);
-    for (; t0 < t1; ++t0) s_k[t0] = (uint32_t)i;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    key[j] = 0u;
-    val[j] = 0u;
-  }
-  const int64_t p = base + (int64_t)threadIdx.x * kItems;
-  if (p < count) {
-    // pair indices fit in 32 bits (the pair capacity is below 2^32)
-    const uint32_t p32 = (uint32_t)p, n32 = (uint32_t)min(count - p, (int64_t)kItems);
-    int i = (int)s_k[threadIdx.x];  // splat index relative to klo
-    uint4 b = staged ? w_rec[i] : brec[klo + i];
-    uint32_t next = staged ? w_off[i + 1] : offsets[klo + i + 1];
-    const uint32_t e = p32 - (staged ? w_off[i] : offsets[klo + i]);
-    uint32_t row = e / b.y, col = e - row * b.y;
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const uint32_t q = p32 + (uint32_t)j;
-      if ((uint32_t)j < n32) {
-        while (q >= next) {  // ends: q < count <= offsets[vn], and i stays below m
-          ++i;
-          b = staged ? w_rec[i] : brec[klo + i];
-          next = staged ? w_off[i + 1] : offsets[klo + i + 1];
-          row = 0;
-          col = 0;
-        }
-        key[j] = b.x + row * (uint32_t)GW + col;
-        val[j] = b.z;
-        if (++col == b.y) {
-          col = 0;
-          ++row;
-        }
-      }
-    }
-  }
-  __syncthreads();  // win and s_k free again
-}
-
-// Low-digit histogram of the generated pairs of each block, in 16
-// sub-histograms of 16 lanes (a thread's pairs are runs of neighbouring tiles,
-// so lanes rarely meet on one digit; the smaller LDS footprint lets eight
-// workgroups share a compute unit, which hides the window loads).
-__global__ void __launch_bounds__(kThreads)
-k_gen_hist(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ brec,
-           const uint32_t *__restrict__ bstart, int64_t vn, int64_t count_static,
-           const uint32_t *__restrict__ dcount, int GW, uint32_t *__restrict__ hist) {
-  // the sub-histograms double as the generator's LDS window
-  __shared__ __align__(16) uint32_t s_sub[kThreads / 16][257];
-  static_assert((kThreads / 16) * 257 >= kWinWords + 3 + kThreads, "window does not fit");
-  const int64_t count = dcount ? (int64_t)*dcount : count_static;
-  const int64_t blk = sgs_xcd_block_live(blockIdx.x, gridDim.x, (count + kTile - 1) / kTile);
-  const int64_t base = blk * kTile;
-  if (base >= count) {
-    hist[blk * 256 + threadIdx.x] = 0;
-    return;
-  }
-  const int64_t p = base + (int64_t)threadIdx.x * kItems;
-  uint32_t key[kItems], val[kItems];
-  gen_block(offsets, brec, bstart, blk, base, count, vn, GW, &s_sub[0][0],
-            &s_sub[0][0] + kWinWords + 3, key, val);
-#pragma unroll
-  for (int w = 0; w < kThreads / 16; ++w) s_sub[w][threadIdx.x] = 0;
-  __syncthreads();
-  uint32_t *mine = s_sub[threadIdx.x >> 4];
-#pragma unroll
-  for (int j = 0; j < kItems; ++j)
-    if (p + j < count) atomicAdd(&mine[key[j] & 0xFFu], 1u);
-  __syncthreads();
-  uint32_t tot = 0;
-#pragma unroll
-  for (int w = 0; w < kThreads / 16; ++w) tot += s_sub[w][threadIdx.x];
-  hist[blk * 256 + threadIdx.x] = tot;
-}
-
-// Generated pairs of each block scattered by their low digit.  Threads
-// generate runs of kItems consecutive pairs; each wave transposes its own
-// 64 kItems pairs through LDS into the wave-segment layout of scatter_block
-// (a wave's runs are its segment: kItems * 64 pairs).
-__global__ void __launch_bounds__(kThreads)
-k_gen_scatter(const uint32_t *__restrict__ offsets, const uint4 *__restrict__ brec,
-              const uint32_t *__restrict__ bstart, int64_t vn, int64_t count_static,
-              const uint32_t *__restrict__ dcount, int GW,
-              const uint32_t *__restrict__ hist_scanned,
-              const uint32_t *__restrict__ digit_tot, uint32_t *__restrict__ kout,
-              uint32_t *__restrict__ vout) {
-  // s_key doubles as the generator's LDS window
-  __shared__ __align__(16) uint32_t s_key[kTilePad];
-  __shared__ uint32_t s_val[kTilePad];
-  static_assert(kTilePad >= kWinWords, "window does not fit");
-  const int64_t count = dcount ? (int64_t)*dcount : count_static;
-  const int64_t blk = sgs_xcd_block_live(blockIdx.x, gridDim.x, (count + kTile - 1) / kTile);
-  const int64_t base = blk * kTile;
-  if (base >= count) return;
-  const uint32_t h_scan = scanned_offset(hist_scanned, digit_tot, blk);
-  const int lane = threadIdx.x & 63;
-  uint32_t *wk = s_key + (threadIdx.x >> 6) * kItems * 64;
-  uint32_t *wv = s_val + (threadIdx.x >> 6) * kItems * 64;
-  {
-    uint32_t key[kItems], val[kItems];
-    gen_block(offsets, brec, bstart, blk, base, count, vn, GW, s_key, s_val, key, val);
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const int li = lds_pad(lane * kItems + j);
-      wk[li] = key[j];
-      wv[li] = val[j];
-    }
-  }
-  wave_lds_sync();
-  uint32_t kr[kItems], vr[kItems];
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const int li = lds_pad(r * 64 + lane);
-    kr[r] = wk[li];
-    vr[r] = wv[li];
-  }
-  scatter_block<kItems>(kr, vr, base, count, 0, h_scan, kout, vout, s_key, s_val);
-}
-
-// Pair counts (the pair capacity in the fixed-capacity mode) from which the
-// ranges come from binary searches rather than from a pass over every id.
-constexpr int64_t kRangeSearchMin = (int64_t)1 << 20;
-
-__global__ void k_zero_ranges(uint2 *__restrict__ ranges, int64_t tiles) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < tiles) ranges[t] = make_uint2(0, 0);
-}
-
-// Tile ranges from the sorted tile ids.  A thread owns 4 consecutive ids
-// (one 16-byte load) plus the id before them; a run boundary between
-// positions e-1 and e sets the end of the earlier tile and the start of the
-// later one.
-__device__ __forceinline__ void range_edge(uint2 *__restrict__ ranges, uint32_t tiles,
-                                           uint32_t prev, uint32_t cur, int64_t e) {
-  if (prev == cur) return;
-  if (prev < tiles) ranges[prev].y = (uint32_t)e;
-  if (cur < tiles) ranges[cur].x = (uint32_t)e;
-}
-
-__global__ void k_ranges(const uint32_t *__restrict__ tile_key, int64_t P_static,
-                         const uint32_t *__restrict__ dcount, uint32_t tiles,
-                         uint2 *__restrict__ ranges) {
-  const int64_t P = dcount ? (int64_t)*dcount : P_static;
-  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-  if (e0 >= P) return;
-  uint32_t v[4];
-  if (e0 + 3 < P) {
-    const uint4 q = *(const uint4 *)(tile_key + e0);
-    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-  } else {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = e0 + j < P ? tile_key[e0 + j] : 0xFFFFFFFFu;
-  }
-  // sentinel 0xFFFFFFFF (>= tiles) stands for "before the first / after the last"
-  uint32_t prev = e0 == 0 ? 0xFFFFFFFFu : tile_key[e0 - 1];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    if (e0 + j >= P) break;
-    range_edge(ranges, tiles, prev, v[j], e0 + j);
-    prev = v[j];
-  }
-  if (e0 + 3 >= P - 1) {  // this thread holds the last id
-    const uint32_t last = tile_key[P - 1];
-    if (last < tiles) ranges[last].y = (uint32_t)P;
-  }
-}
-
-// Tile ranges by binary search in the sorted tile ids: thread t finds the
-// first position of tile t and of tile t + 1 (lower bounds over [0, P), the
-// two searches in lock step, ceil(log2(P + 1)) probes each); an empty tile
-// gets (0, 0).  About 2 log2(P) words read per tile instead of every id: for
-// large P the pass that reads them all is HBM-bound, the searches are not.
-__global__ void __launch_bounds__(256)
-k_ranges_search(const uint32_t *__restrict__ tile_key, int64_t P_static,
-                const uint32_t *__restrict__ dcount, uint32_t tiles,
-                uint2 *__restrict__ ranges) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= tiles) return;
-  const int64_t P = dcount ? (int64_t)*dcount : P_static;
-  const uint32_t k0 = (uint32_t)t, k1 = (uint32_t)t + 1u;
-  int64_t lo0 = 0, hi0 = P, lo1 = 0, hi1 = P;
-  while (lo0 < hi0 || lo1 < hi1) {
-    const int64_t m0 = (lo0 + hi0) >> 1, m1 = (lo1 + hi1) >> 1;
-    // both probes stay below hi <= P; a finished search probes nothing
-    const uint32_t v0 = lo0 < hi0 ? tile_key[m0] : 0u;
-    const uint32_t v1 = lo1 < hi1 ? tile_key[m1] : 0u;
-    if (lo0 < hi0) {
-      if (v0 < k0) lo0 = m0 + 1; else hi0 = m0;
-    }
-    if (lo1 < hi1) {
-      if (v1 < k1) lo1 = m1 + 1; else hi1 = m1;
-    }
-  }
-  ranges[t] = lo0 < lo1 ? make_uint2((uint32_t)lo0, (uint32_t)lo1) : make_uint2(0u, 0u);
-}
-
-// ---------------------------------------------------------------------------
-// Level 1: super-tile items
-// ---------------------------------------------------------------------------
-// An item's key: the global super-tile id in bits [0, 16) (at most 65536
-// super-tiles; the sort's 8-bit digits stay inside these bits) and, riding
-// along above bit 20, the covered tile rectangle inside the super-tile:
-// first and last column and row, 3 bits each.
-constexpr int kStBits = 20;
-constexpr uint32_t kStMask = (1u << kStBits) - 1u;
-
 // The tile rectangle of a binning record (first tile id, width in tiles,
 // Gaussian, pairs) as columns [tx0, tx1] and rows [ty0, ty1] of its view.
 struct TileRect {
@@ -686,20 +452,60 @@ __device__ __forceinline__ TileRect tile_rect(const uint4 &b, uint32_t tiles_per
   return r;
 }
 
-// Items per splat (depth order): the 8x8-tile super-tiles its tile
-// rectangle meets.
-__global__ void k_item_counts(const uint4 *__restrict__ brec, int64_t vn, int GW,
-                              uint32_t tiles_per_view, uint32_t *__restrict__ cnt) {
-  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (d >= vn) return;
-  const uint4 b = brec[d];
-  if (b.w == 0) {
-    cnt[d] = 0;
-    return;
-  }
+// Items per splat: the 8x8-tile super-tiles its tile rectangle meets.
+__device__ __forceinline__ uint32_t super_tiles_met(const uint4 &b, uint32_t tiles_per_view,
+                                                    int GW) {
   const TileRect r = tile_rect(b, tiles_per_view, GW);
-  cnt[d] = (uint32_t)(((r.tx1 >> 3) - (r.tx0 >> 3) + 1) * ((r.ty1 >> 3) - (r.ty0 >> 3) + 1));
+  return (uint32_t)(((r.tx1 >> 3) - (r.tx0 >> 3) + 1) * ((r.ty1 >> 3) - (r.ty0 >> 3) + 1));
 }
+
+// Binning records in depth order (the only gather of splat data in that
+// order; a splat whose sorted depth key is the invalid marker has no record
+// to read and gets an empty one), the item count of every splat (input of
+// the item offsets scan), and the pair count of every block of kTile splats
+// (their sum is the pair total; no per-splat pair offset is needed).
+__global__ void __launch_bounds__(kThreads)
+k_gather_bins(const uint32_t *__restrict__ order, const uint32_t *__restrict__ dkey,
+              const uint4 *__restrict__ bin_splat, int64_t count, int GW,
+              uint32_t tiles_per_view, uint32_t *__restrict__ icnt, uint4 *__restrict__ brec,
+              uint32_t *__restrict__ psums) {
+  __shared__ uint64_t s_sum[kWaves];
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  uint64_t acc = 0;
+#pragma unroll 4
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
+    if (i < count) {
+      // the record of an invalid splat, as the projection writes it
+      uint4 b = make_uint4(0u, 1u, 0u, 0u);
+      if (dkey[i] != 0xFFFFFFFFu) b = bin_splat[order[i]];
+      brec[i] = b;
+      acc += b.w;
+      icnt[i] = b.w ? super_tiles_met(b, tiles_per_view, GW) : 0u;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) t += s_sum[w];
+    // a saturated block sum saturates the total (k_scan_sums)
+    psums[blockIdx.x] = t >= kPairsSaturated ? kPairsSaturated : (uint32_t)t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Level 1: super-tile items
+// ---------------------------------------------------------------------------
+// An item's key: the global super-tile id in bits [0, 16) (at most 65536
+// super-tiles; the sort's 8-bit digits stay inside these bits) and, riding
+// along above bit 20, the covered tile rectangle inside the super-tile:
+// first and last column and row, 3 bits each.
+constexpr int kStBits = 20;
+constexpr uint32_t kStMask = (1u << kStBits) - 1u;
 
 // The items of every splat, in depth order, at its item offset: key =
 // super-tile id | covered tile rectangle inside it (see kStBits), value =
@@ -912,9 +718,11 @@ __global__ void k_l2_ranges(const uint32_t *__restrict__ tile_cnt,
 // Every pair of the chunk to its final position:
 //   tile offset + the tile's pairs in earlier chunks + in earlier waves of
 //   this chunk (counted by k_l2_count) + in earlier rounds of this wave + in
-//   earlier lanes.  Lane t of `pos` holds tile t's next position; for every
-//   tile some item of the round covers, one ballot ranks the lanes covering
-//   it and they write consecutive positions (one coalesced store).
+//   earlier lanes.  Lane t of `pos` holds tile t's next position.  Ballot
+//   form (below): for every tile some item of the round covers, one ballot
+//   ranks the lanes covering it and they write consecutive positions (one
+//   coalesced store per tile).  Staged form (after it): the round's pairs are
+//   placed in LDS tile after tile, then copied out with consecutive lanes.
 __device__ __forceinline__ uint32_t lane_ge(uint32_t v, int t, uint32_t x) {
   return (int)(threadIdx.x & 63) == t ? x : v;
 }
@@ -940,6 +748,46 @@ __device__ __forceinline__ void scatter_half(uint32_t u, uint32_t h, int t0, uin
   }
 }
 
+// Pairs staged per wave and round (8 B each: destination, Gaussian index).
+// A round whose pairs exceed it (about 1 % of the rounds at 3M Gaussians x 8
+// views, items of large splats) takes the ballot loop above instead.
+constexpr int kL2Stage = 1024;
+
+// Lane t holds col, the round's items covering tile t (bit L = lane L's
+// item).  The tile's k-th covering item goes to pos + k; the round's pairs
+// are laid out tile after tile in the wave's LDS stage (tile t from its
+// exclusive prefix o) as (destination, item lane), and the copy-out writes
+// each tile's run with consecutive lanes, reading the Gaussian index from the
+// item's lane (every lane active there: the cross-lane read needs its source
+// lane active).
+__device__ __forceinline__ void scatter_staged(uint64_t col, uint32_t o, uint32_t total,
+                                               uint32_t gid, uint32_t held, uint32_t pos,
+                                               uint2 *__restrict__ stage,
+                                               uint32_t *__restrict__ vals) {
+  const uint32_t lane = threadIdx.x & 63u;
+  uint32_t slot = o, p = pos;
+  while (col) {
+    stage[slot] = make_uint2(p, (uint32_t)__builtin_ctzll(col));
+    col &= col - 1ull;
+    ++slot;
+    ++p;
+  }
+  __builtin_amdgcn_wave_barrier();
+  for (uint32_t e0 = 0; e0 < total; e0 += 128u) {  // wave-uniform trip count
+    const uint32_t e1 = e0 + lane, e2 = e1 + 64u;
+    const bool v1 = e1 < total, v2 = e2 < total;
+    // both reads unconditional (in the stage; stale entries past the total
+    // are read and dropped), so that they are in flight together
+    const uint2 d1 = stage[e1 & (uint32_t)(kL2Stage - 1)];
+    const uint2 d2 = stage[e2 & (uint32_t)(kL2Stage - 1)];
+    const uint32_t g1 = (uint32_t)__shfl((int)gid, (int)d1.y, 64);
+    const uint32_t g2 = (uint32_t)__shfl((int)gid, (int)d2.y, 64);
+    if (v1 && d1.x < held) vals[d1.x] = g1;
+    if (v2 && d2.x < held) vals[d2.x] = g2;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
 __global__ void __launch_bounds__(kThreads)
 k_l2_scatter(const uint32_t *__restrict__ cfirst, uint32_t nst,
              const uint2 *__restrict__ st_ranges, const uint32_t *__restrict__ ikey,
@@ -948,6 +796,7 @@ k_l2_scatter(const uint32_t *__restrict__ cfirst, uint32_t nst,
              const uint16_t *__restrict__ wcnt, const uint32_t *__restrict__ tile_start,
              int64_t held_static, const uint32_t *__restrict__ dheld,
              uint32_t *__restrict__ vals) {
+  __shared__ uint2 s_stage[kWaves][kL2Stage];
   Chunk ch;
   if (!chunk_of(blockIdx.x, cfirst, nst, st_ranges, SGW, st_per_view, ch)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -971,10 +820,25 @@ k_l2_scatter(const uint32_t *__restrict__ cfirst, uint32_t nst,
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const uint64_t m = key[r] == 0xFFFFFFFFu ? 0ull : item_mask(key[r]);
-    // the tiles any lane covers: the transposed masks' non-empty columns
-    const uint64_t u = __ballot(wave_transpose64(m, lane) != 0ull);
-    scatter_half((uint32_t)u, (uint32_t)m, 0, gid[r], held, pos, vals);
-    scatter_half((uint32_t)(u >> 32), (uint32_t)(m >> 32), 32, gid[r], held, pos, vals);
+    // lane t: the round's items covering tile t
+    const uint64_t col = wave_transpose64(m, lane);
+    const uint32_t c = (uint32_t)__popcll(col);
+    uint32_t incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t v = (uint32_t)__shfl_up((int)incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    if (total <= (uint32_t)kL2Stage) {
+      scatter_staged(col, incl - c, total, gid[r], held, pos, s_stage[wave], vals);
+      pos += c;
+    } else {
+      // the tiles any lane covers: the transposed masks' non-empty columns
+      const uint64_t u = __ballot(col != 0ull);
+      scatter_half((uint32_t)u, (uint32_t)m, 0, gid[r], held, pos, vals);
+      scatter_half((uint32_t)(u >> 32), (uint32_t)(m >> 32), 32, gid[r], held, pos, vals);
+    }
   }
 }
 
@@ -1082,21 +946,22 @@ hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2], i
   SortBufs b;
   if (!sort_bufs(c, count, b, radix_tile(count))) return hipErrorInvalidValue;
   for (int shift = shift0; shift < bits; shift += 8) {
+    const int nb = min(8, bits - shift);  // digit bits of this pass
     if (small)
       k_radix_hist<kSmallItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
-          keys[cur], count, dcount, shift, b.hraw);
+          keys[cur], count, dcount, shift, nb, b.hraw);
     else
       k_radix_hist<kItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(keys[cur], count, dcount,
-                                                                      shift, b.hraw);
+                                                                      shift, nb, b.hraw);
     const uint32_t *dtot = launch_digit_offsets(c, b);
     if (small)
       k_radix_scatter<kSmallItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
-          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, b.hscan,
-          dtot);
+          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, nb,
+          b.hscan, dtot);
     else
       k_radix_scatter<kItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
-          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, b.hscan,
-          dtot);
+          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, nb,
+          b.hscan, dtot);
     cur ^= 1;
   }
   *which = cur;
@@ -1114,17 +979,19 @@ hipError_t launch_depth_order(sgs_ctx *c) {
   }
   c->depth_sorted_buf = which;
   SgsProfScope ps(c, SGS_PROF_SCAN);
-  // pair counts in depth order -> scratch (the other key buffer is free now)
+  // records and item counts in depth order (item counts -> scratch: the other
+  // key buffer is free now), pair counts summed per block of kTile splats
   uint32_t *tmp = c->depth_key[which ^ 1];
-  k_gather_bins<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(c->depth_val[which], c->bin_splat,
-                                                               c->vn, tmp, c->bin_rec);
-  // with a fixed pair capacity the scan also clamps the count to it
-  hipError_t e = launch_exclusive_scan(c, tmp, c->offsets, c->vn, c->d_pairs_total,
-                                       c->fixed_cap ? c->cap_limit : -1);
-  if (e != hipSuccess) return e;
-  // super-tile item counts (over tmp, scanned already), then their offsets
-  k_item_counts<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(c->bin_rec, c->vn, c->GW,
-                                                               (uint32_t)c->tiles_per_view, tmp);
+  const int64_t nb = (c->vn + kTile - 1) / kTile;
+  if (nb > c->scan_tmp_words) return hipErrorInvalidValue;
+  if (nb > 0)
+    k_gather_bins<<<(unsigned)nb, kThreads, 0, c->stream>>>(
+        c->depth_val[which], c->depth_key[which], c->bin_splat, c->vn, c->GW,
+        (uint32_t)c->tiles_per_view, tmp, c->bin_rec, c->scan_tmp);
+  // the pair total (with a fixed pair capacity also clamped to it)
+  k_scan_sums<<<1, kThreads, 0, c->stream>>>(c->scan_tmp, nb, c->d_pairs_total, nullptr,
+                                             c->fixed_cap ? c->cap_limit : -1);
+  // the item offsets
   return launch_exclusive_scan(c, tmp, c->ioffsets, c->vn, c->d_pairs_total + 4,
                                c->fixed_cap ? c->cap_limit : -1);
 }
