@@ -384,27 +384,59 @@ k_mlp_rate_bwd(int64_t n, int64_t npad, int64_t n_hat, float weight, float tau, 
 #pragma unroll
   for (int k = 0; k < 32; ++k) gq[k] = 0.0f;
   const int64_t ntiles = (n + 31) / 32;
-  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < ntiles;
-       tile += (int64_t)gridDim.x * kWaves) {
+  const int64_t stride = (int64_t)gridDim.x * kWaves;
+  // a tile's per-row inputs, loaded one tile ahead (software pipelining: the
+  // wave is alone on its SIMD, so nothing else hides their latency)
+  struct RowIn {
+    uint4 sg;
+    float fs, gm, sm, gs;
+    bool m;
+  };
+  auto row_in = [&](int64_t t) {
+    RowIn o;
+    const int64_t rr = t * 32 + (lane & 31);
+    const bool ok = t < ntiles && rr < n;
+    o.m = ok && hard[rr];
+    o.sg = ok ? signs[2 * rr + (lane >> 5)] : make_uint4(0u, 0u, 0u, 0u);
+    const bool own = ok && lane < 32;  // one lane per row writes its mask gradient
+    o.fs = own ? fsave[rr] : 0.0f;
+    o.gm = own && gmask ? gmask[rr] : 0.0f;
+    o.sm = own && mode == 1 && gscore ? soft[rr] : 0.0f;
+    o.gs = own && mode == 1 && gscore ? gscore[rr] : 0.0f;
+    return o;
+  };
+  RowIn nxt = row_in((int64_t)blockIdx.x * kWaves + wave);
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < ntiles; tile += stride) {
     // keep the weight fragments in LDS: without this the loop-invariant
     // fragment reads are hoisted into registers and the kernel spills
     __asm__ volatile("" ::: "memory");
     const int64_t r = tile * 32 + (lane & 31);
     const bool valid = r < n;
-    const bool m = valid && hard[r];
-    uint4 sg = make_uint4(0u, 0u, 0u, 0u);
-    if (valid) sg = signs[2 * r + (lane >> 5)];
-    const uint64_t m1 = (uint64_t)sg.x | ((uint64_t)sg.y << 32);
-    const uint64_t m2 = (uint64_t)sg.z | ((uint64_t)sg.w << 32);
+    const RowIn in = nxt;
+    const bool m = in.m;
+    const uint4 sg = in.sg;
     // mask gradient
     if (valid && lane < 32) {
-      const float gmv = cscale * fsave[r];
-      if (gmask) gmask[r] += gmv;
-      if (mode == 1 && gscore) {
-        const float sm = soft[r];
-        gscore[r] += gmv * sm * (1.0f - sm) / tau;
-      }
+      const float gmv = cscale * in.fs;
+      if (gmask) gmask[r] = in.gm + gmv;
+      if (mode == 1 && gscore) gscore[r] = in.gs + gmv * in.sm * (1.0f - in.sm) / tau;
     }
+    const uint64_t m1 = (uint64_t)sg.x | ((uint64_t)sg.y << 32);
+    const uint64_t m2 = (uint64_t)sg.z | ((uint64_t)sg.w << 32);
+    // this tile's parameter rows and gradient rows for the chain to y and q
+    // below, loaded ahead of the MFMA section so that their latency overlaps
+    // it (accumulator element (t, i) is channel 32t + drow(i, lane))
+    float yv[2][16], old[2][16];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int j = 32 * t + drow(i, lane);
+        const bool ok = valid && j < SGS_NCH;
+        yv[t][i] = ok ? y[j * npad + r] : 0.0f;
+        old[t][i] = ok ? gparams[j * npad + r] : 0.0f;
+      }
+    nxt = row_in(tile + stride);
     if (__ballot(m) == 0ull) continue;
     const float c = m ? cscale : 0.0f;
     // dz2 = c w3 [z2 > 0]  (BF16, B operand layout)
@@ -458,32 +490,20 @@ k_mlp_rate_bwd(int64_t n, int64_t npad, int64_t n_hat, float weight, float tau, 
         dx[1] = mfma(L.F1B[1][4 * half + p][lane], d1b[2 * p], d1b[2 * p + 1], dx[1]);
       }
     }
-    // chain to y and q: x = log2(1 + u), u = (y - m) / q.  Accumulator
-    // element (t, i) is channel 32t + drow(i, lane); per half of the
-    // channels all loads (y and the read-modify-write of grad_params) first.
-    __builtin_amdgcn_sched_barrier(0);  // keep these loads out of the MFMA section
+    // chain to y and q: x = log2(1 + u), u = (y - m) / q
     if (valid) {
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        float yv[16], old[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int j = 32 * t + drow(i, lane);
-          const bool ok = j < SGS_NCH;
-          yv[i] = ok ? y[j * npad + r] : 0.0f;
-          old[i] = ok ? gparams[j * npad + r] : 0.0f;
-        }
+      for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int j = 32 * t + drow(i, lane);
           if (t == 0 || j < SGS_NCH) {
-            const float uu = (yv[i] - s_min[j]) * s_rq[j];
+            const float uu = (yv[t][i] - s_min[j]) * s_rq[j];
             const float gp = dx[t][i] * __builtin_amdgcn_rcpf(1.0f + uu) * inv_ln2 * s_rq[j];
-            gparams[j * npad + r] = old[i] + gp;
+            gparams[j * npad + r] = old[t][i] + gp;
             gq[16 * t + i] -= gp * uu;
           }
         }
-      }
     }
   }
   // reduce the step gradient: lanes sharing lane>>5 hold the same channels
