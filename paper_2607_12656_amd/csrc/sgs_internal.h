@@ -382,21 +382,31 @@ __device__ __forceinline__ uint8_t sgs_mask_decide(int mode, const uint8_t *__re
 }
 
 // Workgroups are dispatched to the eight XCDs round-robin (hardware id i runs
-// on XCD i % 8, each XCD with its own L2).  Logical id of hardware id i in a
-// grid of nb blocks such that every XCD takes one contiguous range of logical
-// blocks: neighbouring blocks, which touch neighbouring memory (the two
-// halves of a cache line at a write boundary), then share an L2.
-__device__ __forceinline__ int64_t sgs_xcd_block(int64_t i, int64_t nb) {
-  const int64_t x = i & 7, k = i >> 3, per = nb >> 3, rem = nb & 7;
-  return x * per + (x < rem ? x : rem) + k;
+// on XCD i % 8, each XCD with its own L2).  A grid of g workgroups that loops
+// over nlive logical blocks (a resident grid whose work count is on the
+// device) walks them so that every XCD takes one contiguous share:
+// neighbouring blocks, which touch neighbouring memory (the two halves of a
+// cache line at a write boundary), then share an L2.  Hardware block i takes
+// first, first + step, ... < end; with fewer than eight workgroups some XCD
+// has none, and the walk is a plain stride.
+struct SgsXcdWalk {
+  int64_t first, step, end;
+};
+__device__ __forceinline__ SgsXcdWalk sgs_xcd_walk(int64_t i, int64_t g, int64_t nlive) {
+  if (g < 8) return {i, g, nlive};
+  const int64_t x = i & 7, k = i >> 3;
+  const int64_t gx = (g >> 3) + (x < (g & 7) ? 1 : 0);  // workgroups on XCD x
+  const int64_t per = nlive >> 3, rem = nlive & 7;
+  const int64_t start = x * per + (x < rem ? x : rem);
+  return {start + k, gx, start + per + (x < rem ? 1 : 0)};
 }
 
-// The same for a grid of nb blocks of which only the first nlive logical
-// blocks hold work (grids sized for a capacity): the live range is split
-// over the eight XCDs as above, so each does an equal share whatever the
-// grid size, and the other hardware blocks take the logical blocks nlive,
-// nlive + 1, ... in dispatch order (their rank among them: for each XCD, its
-// blocks dispatched earlier beyond its live share).  A bijection of [0, nb).
+// One workgroup per logical block in a grid of nb sized for a capacity, of
+// which only the first nlive hold work: the live range is split over the
+// eight XCDs as above, so each does an equal share whatever the grid size,
+// and the other hardware blocks take the logical blocks nlive, nlive + 1,
+// ... in dispatch order (their rank among them: for each XCD, its blocks
+// dispatched earlier beyond its live share).  A bijection of [0, nb).
 __device__ __forceinline__ int64_t sgs_xcd_block_live(int64_t i, int64_t nb, int64_t nlive) {
   nlive = nlive < nb ? nlive : nb;
   const int64_t x = i & 7, k = i >> 3, per = nlive >> 3, rem = nlive & 7;

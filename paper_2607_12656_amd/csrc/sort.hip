@@ -26,7 +26,7 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kItems = 16;
 constexpr int kTile = kThreads * kItems;  // elements per block
-constexpr int kChunk = 64;                 // histogram rows per chunk of the digit scan
+constexpr int kChunk = 16;                 // histogram rows per chunk of the digit scan
 
 // ---------------------------------------------------------------------------
 // Exclusive scan of uint32 (reduce -> scan of block sums -> downsweep).
@@ -161,10 +161,22 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int nb) 
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Blocks of `tile` elements that hold live elements: the sort kernels of a
+// grid sized for a capacity loop over these only (the count is on the
+// device), and the digit-offset kernels scan only their histogram rows.
+__device__ __forceinline__ int64_t live_blocks(int64_t count_static,
+                                               const uint32_t *__restrict__ dcount,
+                                               int64_t tile) {
+  const int64_t count = dcount ? (int64_t)*dcount : count_static;
+  return (count + tile - 1) / tile;
+}
+
 // Block histogram of one digit.  Lanes count into 32 sub-histograms (eight
 // lanes each, rows padded to 257 words so that equal digits of different
 // sub-histograms sit in different banks): the pass over the high digit sees
-// long runs of equal digits, and same-address LDS atomics serialize.
+// long runs of equal digits, and same-address LDS atomics serialize.  A grid
+// of resident size loops over the live blocks (rows of other blocks are
+// neither written nor read).
 template <int IT>
 __global__ void __launch_bounds__(kThreads)
 k_radix_hist(const uint32_t *__restrict__ keys, int64_t count_static,
@@ -172,52 +184,52 @@ k_radix_hist(const uint32_t *__restrict__ keys, int64_t count_static,
   constexpr int TILE = kThreads * IT;
   __shared__ uint32_t s_sub[kThreads / 8][257];
   const int64_t count = dcount ? (int64_t)*dcount : count_static;
-  const int64_t blk = sgs_xcd_block_live(blockIdx.x, gridDim.x, (count + TILE - 1) / TILE);
-  const int64_t base = blk * TILE;
-  if (base >= count) {  // grid sized for a capacity, not the live count
-    hist[blk * 256 + threadIdx.x] = 0;
-    return;
-  }
+  const int64_t live = (count + TILE - 1) / TILE;
   const uint32_t dmask = (1u << nb) - 1u;
+  const SgsXcdWalk wk = sgs_xcd_walk(blockIdx.x, gridDim.x, live);
+  for (int64_t blk = wk.first; blk < wk.end; blk += wk.step) {
+    const int64_t base = blk * TILE;
 #pragma unroll
-  for (int w = 0; w < kThreads / 8; ++w) s_sub[w][threadIdx.x] = 0;
-  // all loads of the block in flight at once
-  uint32_t kr[IT];
-#pragma unroll
-  for (int r = 0; r < IT; ++r) {
-    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
-    kr[r] = i < count ? keys[i] : 0u;
-  }
-  __syncthreads();
-  if (nb <= 3) {
-    // at most 8 digits: the keys share few addresses, which LDS atomics would
-    // serialize on; a ballot per digit value and round counts them instead,
-    // and lane v of each wave adds the wave's count of digit v once
-    const uint32_t lane = threadIdx.x & 63u;
-    uint32_t own = 0;
-#pragma unroll
-    for (int r = 0; r < IT; ++r) {
-      const bool ok = base + (int64_t)r * kThreads + threadIdx.x < count;
-      const uint32_t d = (kr[r] >> shift) & dmask;
-      for (uint32_t v = 0; v <= dmask; ++v) {
-        const uint32_t n = (uint32_t)__popcll(__ballot(ok && d == v));
-        if (lane == v) own += n;
-      }
-    }
-    if (lane <= dmask) atomicAdd(&s_sub[0][lane], own);
-  } else {
-    uint32_t *mine = s_sub[threadIdx.x >> 3];
+    for (int w = 0; w < kThreads / 8; ++w) s_sub[w][threadIdx.x] = 0;
+    // all loads of the block in flight at once
+    uint32_t kr[IT];
 #pragma unroll
     for (int r = 0; r < IT; ++r) {
       const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
-      if (i < count) atomicAdd(&mine[(kr[r] >> shift) & dmask], 1u);
+      kr[r] = i < count ? keys[i] : 0u;
     }
-  }
-  __syncthreads();
-  uint32_t tot = 0;
+    __syncthreads();
+    if (nb <= 3) {
+      // at most 8 digits: the keys share few addresses, which LDS atomics
+      // would serialize on; a ballot per digit value and round counts them
+      // instead, and lane v of each wave adds the wave's count of digit v once
+      const uint32_t lane = threadIdx.x & 63u;
+      uint32_t own = 0;
 #pragma unroll
-  for (int w = 0; w < kThreads / 8; ++w) tot += s_sub[w][threadIdx.x];
-  hist[blk * 256 + threadIdx.x] = tot;
+      for (int r = 0; r < IT; ++r) {
+        const bool ok = base + (int64_t)r * kThreads + threadIdx.x < count;
+        const uint32_t d = (kr[r] >> shift) & dmask;
+        for (uint32_t v = 0; v <= dmask; ++v) {
+          const uint32_t n = (uint32_t)__popcll(__ballot(ok && d == v));
+          if (lane == v) own += n;
+        }
+      }
+      if (lane <= dmask) atomicAdd(&s_sub[0][lane], own);
+    } else {
+      uint32_t *mine = s_sub[threadIdx.x >> 3];
+#pragma unroll
+      for (int r = 0; r < IT; ++r) {
+        const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+        if (i < count) atomicAdd(&mine[(kr[r] >> shift) & dmask], 1u);
+      }
+    }
+    __syncthreads();
+    uint32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 8; ++w) tot += s_sub[w][threadIdx.x];
+    hist[blk * 256 + threadIdx.x] = tot;
+    __syncthreads();  // the sums are read before the next block clears them
+  }
 }
 
 // Digit offsets from the block-major histogram rows H[b][d]: the position of
@@ -227,9 +239,12 @@ k_radix_hist(const uint32_t *__restrict__ keys, int64_t count_static,
 // whole 1 KB rows (coalesced), unlike a scan over a digit-major table, whose
 // per-block stores and loads are 4 bytes each, a row apart.
 __global__ void __launch_bounds__(kThreads)
-k_hist_chunk_sums(const uint32_t *__restrict__ H, int64_t nb, uint32_t *__restrict__ CS) {
+k_hist_chunk_sums(const uint32_t *__restrict__ H, int64_t count_static,
+                  const uint32_t *__restrict__ dcount, int64_t tile, uint32_t *__restrict__ CS) {
+  const int64_t nb = live_blocks(count_static, dcount, tile);
   const int64_t g = blockIdx.x;
   const int64_t b0 = g * kChunk, b1 = min(nb, b0 + kChunk);
+  if (b0 >= nb) return;
   uint32_t s = 0;
 #pragma unroll 8
   for (int64_t b = b0; b < b1; ++b) s += H[b * 256 + threadIdx.x];
@@ -239,8 +254,10 @@ k_hist_chunk_sums(const uint32_t *__restrict__ H, int64_t nb, uint32_t *__restri
 // One block per digit: exclusive scan of the chunk sums over chunks (in
 // place) and the digit total.
 __global__ void __launch_bounds__(kThreads)
-k_hist_chunk_scan(uint32_t *__restrict__ CS, int64_t ng, uint32_t *__restrict__ total) {
+k_hist_chunk_scan(uint32_t *__restrict__ CS, int64_t count_static,
+                  const uint32_t *__restrict__ dcount, int64_t tile, uint32_t *__restrict__ total) {
   __shared__ uint32_t s_wave[kWaves];
+  const int64_t ng = (live_blocks(count_static, dcount, tile) + kChunk - 1) / kChunk;
   const int d = blockIdx.x;
   const int64_t per = (ng + kThreads - 1) / kThreads;
   const int64_t g0 = min(ng, (int64_t)threadIdx.x * per), g1 = min(ng, g0 + per);
@@ -257,10 +274,14 @@ k_hist_chunk_scan(uint32_t *__restrict__ CS, int64_t ng, uint32_t *__restrict__ 
 }
 
 __global__ void __launch_bounds__(kThreads)
-k_hist_chunk_down(const uint32_t *__restrict__ H, int64_t nb, const uint32_t *__restrict__ CB,
-                  const uint32_t *__restrict__ total, uint32_t *__restrict__ O) {
+k_hist_chunk_down(const uint32_t *__restrict__ H, int64_t count_static,
+                  const uint32_t *__restrict__ dcount, int64_t tile,
+                  const uint32_t *__restrict__ CB, const uint32_t *__restrict__ total,
+                  uint32_t *__restrict__ O) {
   __shared__ uint32_t s_wave[kWaves];
+  const int64_t nb = live_blocks(count_static, dcount, tile);
   const int64_t g = blockIdx.x;
+  if (g * kChunk >= nb) return;
   uint32_t tot;
   uint32_t run = block_exclusive_scan(total[threadIdx.x], s_wave, tot) + CB[g * 256 + threadIdx.x];
   const int64_t b0 = g * kChunk, b1 = min(nb, b0 + kChunk);
@@ -280,9 +301,11 @@ k_hist_chunk_down(const uint32_t *__restrict__ H, int64_t nb, const uint32_t *__
 // chunked kernels above take over.
 constexpr int64_t kColRows = 2048;
 __global__ void __launch_bounds__(kThreads)
-k_digit_cols(const uint32_t *__restrict__ H, int64_t nb, uint32_t *__restrict__ O,
+k_digit_cols(const uint32_t *__restrict__ H, int64_t count_static,
+             const uint32_t *__restrict__ dcount, int64_t tile, uint32_t *__restrict__ O,
              uint32_t *__restrict__ total) {
   __shared__ uint32_t s_wave[kWaves];
+  const int64_t nb = live_blocks(count_static, dcount, tile);
   const int d = blockIdx.x;
   const int64_t per = (nb + kThreads - 1) / kThreads;
   const int64_t b0 = min(nb, (int64_t)threadIdx.x * per), b1 = min(nb, b0 + per);
@@ -315,13 +338,6 @@ __device__ __forceinline__ uint32_t scanned_offset(const uint32_t *__restrict__ 
   }
   return h;
 }
-
-// LDS index of element i of a block's tile with the low four bits XORed by
-// the next four: a thread's run of kItems (16) consecutive elements and a
-// round of consecutive threads both spread over the banks, with no pad words
-// (the pair scatter then fits four workgroups in a compute unit's LDS).
-__device__ __forceinline__ int lds_pad(int i) { return i ^ ((i >> 4) & 15); }
-constexpr int kTilePad = kTile;
 
 // Scatter of one pass for the block's elements in the wave-segment layout:
 // wave w holds elements w * IT * 64 + r * 64 + lane of the block in kr[r],
@@ -405,6 +421,9 @@ __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[IT],
   }
 }
 
+// One workgroup per block of the capacity-sized grid (a loop over the live
+// blocks would need more registers than four workgroups per compute unit
+// leave); blocks past the live count return at once.
 template <int IT>
 __global__ void __launch_bounds__(kThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
@@ -649,29 +668,34 @@ __device__ __forceinline__ bool chunk_of(uint32_t q, const uint32_t *__restrict_
   return true;
 }
 
-// Per-chunk pair counts of the 64 tiles: cnt[q][t].
+// Per-chunk pair counts of the 64 tiles: cnt[q][t].  A grid of resident
+// size loops over the chunks (their number is on the device).
 __global__ void __launch_bounds__(kThreads)
 k_l2_count(const uint32_t *__restrict__ cfirst, uint32_t nst, const uint2 *__restrict__ st_ranges,
            const uint32_t *__restrict__ ikey, int SGW, uint32_t st_per_view,
            uint32_t *__restrict__ cnt, uint16_t *__restrict__ wcnt) {
   __shared__ uint32_t s_w[kWaves][64];
-  Chunk ch;
-  if (!chunk_of(blockIdx.x, cfirst, nst, st_ranges, SGW, st_per_view, ch)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t acc = 0;
+  const SgsXcdWalk wk = sgs_xcd_walk(blockIdx.x, gridDim.x, cfirst[nst]);
+  Chunk ch;
+  for (int64_t q = wk.first; q < wk.end; q += wk.step) {
+    chunk_of((uint32_t)q, cfirst, nst, st_ranges, SGW, st_per_view, ch);
+    uint32_t acc = 0;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const uint32_t idx = ch.first + (uint32_t)(wave * 256 + r * 64 + lane);
-    const uint64_t m = idx < ch.end ? item_mask(ikey[idx]) : 0ull;
-    // lane t: the round's items covering tile t
-    acc += (uint32_t)__popcll(wave_transpose64(m, lane));
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t idx = ch.first + (uint32_t)(wave * 256 + r * 64 + lane);
+      const uint64_t m = idx < ch.end ? item_mask(ikey[idx]) : 0ull;
+      // lane t: the round's items covering tile t
+      acc += (uint32_t)__popcll(wave_transpose64(m, lane));
+    }
+    // a wave's count of one tile is at most its 256 items
+    wcnt[(q * kWaves + wave) * 64 + lane] = (uint16_t)acc;
+    s_w[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0)
+      cnt[q * 64 + lane] = s_w[0][lane] + s_w[1][lane] + s_w[2][lane] + s_w[3][lane];
+    __syncthreads();  // read before the next chunk writes
   }
-  // a wave's count of one tile is at most its 256 items
-  wcnt[((int64_t)blockIdx.x * kWaves + wave) * 64 + lane] = (uint16_t)acc;
-  s_w[wave][lane] = acc;
-  __syncthreads();
-  if (wave == 0)
-    cnt[(int64_t)blockIdx.x * 64 + lane] = s_w[0][lane] + s_w[1][lane] + s_w[2][lane] + s_w[3][lane];
 }
 
 // Per super-tile (64 threads, thread t = tile t): the chunk counts become the
@@ -797,17 +821,18 @@ k_l2_scatter(const uint32_t *__restrict__ cfirst, uint32_t nst,
              int64_t held_static, const uint32_t *__restrict__ dheld,
              uint32_t *__restrict__ vals) {
   __shared__ uint2 s_stage[kWaves][kL2Stage];
+  const uint32_t held = (uint32_t)(dheld ? (int64_t)*dheld : held_static);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   Chunk ch;
   if (!chunk_of(blockIdx.x, cfirst, nst, st_ranges, SGW, st_per_view, ch)) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t q = blockIdx.x;
   const int tx = ch.tx_base + (lane & 7), ty = ch.ty_base + (lane >> 3);
   uint32_t pos = 0;
   if (tx < GW && ty < GH) {
     pos = tile_start[(int64_t)ch.view * tiles_per_view + (int64_t)ty * GW + tx] +
-          rel[(int64_t)blockIdx.x * 64 + lane];
-    for (int w = 0; w < wave; ++w) pos += wcnt[((int64_t)blockIdx.x * kWaves + w) * 64 + lane];
+          rel[(int64_t)q * 64 + lane];
+    for (int w = 0; w < wave; ++w) pos += wcnt[((int64_t)q * kWaves + w) * 64 + lane];
   }
-  const uint32_t held = (uint32_t)(dheld ? (int64_t)*dheld : held_static);
   uint32_t key[4], gid[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {  // all four rounds' loads in flight at once
@@ -920,16 +945,37 @@ bool sort_bufs(sgs_ctx *c, int64_t count, SortBufs &b, int64_t tile = kTile) {
 // Digit offsets of every block from the raw block histograms (raw counts kept
 // for the block-local placement).  Returns the digit totals the scatter must
 // add the digit bases of (column path), or null (chunked path: included).
-const uint32_t *launch_digit_offsets(sgs_ctx *c, const SortBufs &b) {
+const uint32_t *launch_digit_offsets(sgs_ctx *c, const SortBufs &b, int64_t count,
+                                     const uint32_t *dcount, int64_t tile) {
   if (b.nb <= kColRows) {
-    k_digit_cols<<<256, kThreads, 0, c->stream>>>(b.hraw, b.nb, b.hscan, b.total);
+    k_digit_cols<<<256, kThreads, 0, c->stream>>>(b.hraw, count, dcount, tile, b.hscan, b.total);
     return b.total;
   }
-  k_hist_chunk_sums<<<(unsigned)b.ng, kThreads, 0, c->stream>>>(b.hraw, b.nb, b.chunk);
-  k_hist_chunk_scan<<<256, kThreads, 0, c->stream>>>(b.chunk, b.ng, b.total);
-  k_hist_chunk_down<<<(unsigned)b.ng, kThreads, 0, c->stream>>>(b.hraw, b.nb, b.chunk, b.total,
-                                                                b.hscan);
+  k_hist_chunk_sums<<<(unsigned)b.ng, kThreads, 0, c->stream>>>(b.hraw, count, dcount, tile,
+                                                                b.chunk);
+  k_hist_chunk_scan<<<256, kThreads, 0, c->stream>>>(b.chunk, count, dcount, tile, b.total);
+  k_hist_chunk_down<<<(unsigned)b.ng, kThreads, 0, c->stream>>>(b.hraw, count, dcount, tile,
+                                                                b.chunk, b.total, b.hscan);
   return nullptr;
+}
+
+// Workgroups of a grid that loops over its blocks: all that fit on the device
+// at once (occupancy x compute units), at most `blocks`.  One instance (and
+// cached count) per kernel.
+template <auto Kernel>
+unsigned resident_blocks(int64_t blocks) {
+  static int cap = 0;
+  if (cap == 0) {
+    int dev = 0, occ = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, Kernel, kThreads, 0) == hipSuccess &&
+        occ > 0 && cus > 0)
+      cap = occ * cus;
+    else
+      cap = 1024;
+  }
+  return (unsigned)max((int64_t)1, min(blocks, (int64_t)cap));
 }
 
 }  // namespace
@@ -945,23 +991,24 @@ hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2], i
   const bool small = count <= kSmallSort;
   SortBufs b;
   if (!sort_bufs(c, count, b, radix_tile(count))) return hipErrorInvalidValue;
+  const int64_t tile = radix_tile(count);
   for (int shift = shift0; shift < bits; shift += 8) {
     const int nb = min(8, bits - shift);  // digit bits of this pass
     if (small)
-      k_radix_hist<kSmallItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
-          keys[cur], count, dcount, shift, nb, b.hraw);
+      k_radix_hist<kSmallItems><<<resident_blocks<k_radix_hist<kSmallItems>>(b.nb), kThreads, 0,
+                                  c->stream>>>(keys[cur], count, dcount, shift, nb, b.hraw);
     else
-      k_radix_hist<kItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(keys[cur], count, dcount,
-                                                                      shift, nb, b.hraw);
-    const uint32_t *dtot = launch_digit_offsets(c, b);
+      k_radix_hist<kItems><<<resident_blocks<k_radix_hist<kItems>>(b.nb), kThreads, 0,
+                             c->stream>>>(keys[cur], count, dcount, shift, nb, b.hraw);
+    const uint32_t *dtot = launch_digit_offsets(c, b, count, dcount, tile);
     if (small)
       k_radix_scatter<kSmallItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
           keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, nb,
           b.hscan, dtot);
     else
       k_radix_scatter<kItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
-          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, nb,
-          b.hscan, dtot);
+          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, nb, b.hscan,
+          dtot);
     cur ^= 1;
   }
   *which = cur;
@@ -1027,7 +1074,7 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
                                                                      nst, c->st_ranges);
     k_st_chunks<<<1, kThreads, 0, c->stream>>>(c->st_ranges, c->total_st, c->chunk_first);
     if (chunks > 0)
-      k_l2_count<<<(unsigned)chunks, kThreads, 0, c->stream>>>(
+      k_l2_count<<<resident_blocks<k_l2_count>(chunks), kThreads, 0, c->stream>>>(
           c->chunk_first, nst, c->st_ranges, c->tile_key[which], c->SGW, spv, c->l2_cnt,
           c->l2_wcnt);
     k_l2_scan<<<nst, 64, 0, c->stream>>>(c->chunk_first, c->l2_cnt, c->GW, c->GH, c->SGW, spv,
