@@ -260,7 +260,7 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   SGS_ALLOC(c->offsets, vn + 1);
   SGS_ALLOC(c->ioffsets, vn + 1);
   SGS_ALLOC(c->st_ranges, c->total_st);
-  SGS_ALLOC(c->chunk_first, c->total_st + 1);
+  SGS_ALLOC(c->chunk_first, c->total_st + 2);  // + the level-2 scatter's chunk queue
   SGS_ALLOC(c->tile_cnt, c->total_tiles);
   SGS_ALLOC(c->tile_start, c->total_tiles + 1);
   SGS_ALLOC(c->bin_rec, vn);

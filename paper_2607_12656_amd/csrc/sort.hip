@@ -583,7 +583,8 @@ k_st_ranges(const uint32_t *__restrict__ key, int64_t I_static, const uint32_t *
 constexpr int kL2Items = 1024;  // items per chunk: 4 waves x 4 rounds x 64 lanes
 
 // chunk_first[g] = sum over super-tiles g' < g of ceil(items / kL2Items);
-// chunk_first[nst] = the number of chunks (one workgroup).
+// chunk_first[nst] = the number of chunks (one workgroup); chunk_first[nst + 1]
+// (the level-2 scatter's queue of chunks) is cleared.
 __global__ void __launch_bounds__(kThreads)
 k_st_chunks(const uint2 *__restrict__ st_ranges, int64_t nst, uint32_t *__restrict__ first) {
   __shared__ uint32_t s_wave[kWaves];
@@ -600,7 +601,10 @@ k_st_chunks(const uint2 *__restrict__ st_ranges, int64_t nst, uint32_t *__restri
     if (g < nst) first[g] = carry + ex;
     carry += total;
   }
-  if (threadIdx.x == 0) first[nst] = carry;
+  if (threadIdx.x == 0) {
+    first[nst] = carry;
+    first[nst + 1] = 0;
+  }
 }
 
 // The super-tile of chunk q: the last g with first[g] <= q (q < first[nst]).
@@ -772,10 +776,11 @@ __device__ __forceinline__ void scatter_half(uint32_t u, uint32_t h, int t0, uin
   }
 }
 
-// Pairs staged per wave and round (8 B each: destination, Gaussian index).
-// A round whose pairs exceed it (about 1 % of the rounds at 3M Gaussians x 8
-// views, items of large splats) takes the ballot loop above instead.
-constexpr int kL2Stage = 1024;
+// Pairs staged per wave and round (8 B each: destination, item lane), sized
+// so that five workgroups fit a compute unit's LDS.  A round whose pairs
+// exceed it (about 1 % of the rounds at 3M Gaussians x 8 views, items of
+// large splats) takes the ballot loop above instead.
+constexpr int kL2Stage = 1020;
 
 // Lane t holds col, the round's items covering tile t (bit L = lane L's
 // item).  The tile's k-th covering item goes to pos + k; the round's pairs
@@ -802,8 +807,8 @@ __device__ __forceinline__ void scatter_staged(uint64_t col, uint32_t o, uint32_
     const bool v1 = e1 < total, v2 = e2 < total;
     // both reads unconditional (in the stage; stale entries past the total
     // are read and dropped), so that they are in flight together
-    const uint2 d1 = stage[e1 & (uint32_t)(kL2Stage - 1)];
-    const uint2 d2 = stage[e2 & (uint32_t)(kL2Stage - 1)];
+    const uint2 d1 = stage[min(e1, (uint32_t)(kL2Stage - 1))];
+    const uint2 d2 = stage[min(e2, (uint32_t)(kL2Stage - 1))];
     const uint32_t g1 = (uint32_t)__shfl((int)gid, (int)d1.y, 64);
     const uint32_t g2 = (uint32_t)__shfl((int)gid, (int)d2.y, 64);
     if (v1 && d1.x < held) vals[d1.x] = g1;
@@ -813,7 +818,7 @@ __device__ __forceinline__ void scatter_staged(uint64_t col, uint32_t o, uint32_
 }
 
 __global__ void __launch_bounds__(kThreads)
-k_l2_scatter(const uint32_t *__restrict__ cfirst, uint32_t nst,
+k_l2_scatter(const uint32_t *__restrict__ cfirst, uint32_t *__restrict__ queue, uint32_t nst,
              const uint2 *__restrict__ st_ranges, const uint32_t *__restrict__ ikey,
              const uint32_t *__restrict__ ival, int GW, int GH, uint32_t tiles_per_view, int SGW,
              uint32_t st_per_view, const uint32_t *__restrict__ rel,
@@ -821,48 +826,57 @@ k_l2_scatter(const uint32_t *__restrict__ cfirst, uint32_t nst,
              int64_t held_static, const uint32_t *__restrict__ dheld,
              uint32_t *__restrict__ vals) {
   __shared__ uint2 s_stage[kWaves][kL2Stage];
+  __shared__ uint32_t s_q[2];
   const uint32_t held = (uint32_t)(dheld ? (int64_t)*dheld : held_static);
+  const uint32_t nchunks = cfirst[nst];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   Chunk ch;
-  if (!chunk_of(blockIdx.x, cfirst, nst, st_ranges, SGW, st_per_view, ch)) return;
-  const int64_t q = blockIdx.x;
-  const int tx = ch.tx_base + (lane & 7), ty = ch.ty_base + (lane >> 3);
-  uint32_t pos = 0;
-  if (tx < GW && ty < GH) {
-    pos = tile_start[(int64_t)ch.view * tiles_per_view + (int64_t)ty * GW + tx] +
-          rel[(int64_t)q * 64 + lane];
-    for (int w = 0; w < wave; ++w) pos += wcnt[((int64_t)q * kWaves + w) * 64 + lane];
-  }
-  uint32_t key[4], gid[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {  // all four rounds' loads in flight at once
-    const uint32_t idx = ch.first + (uint32_t)(wave * 256 + r * 64 + lane);
-    const bool ok = idx < ch.end;
-    key[r] = ok ? ikey[idx] : 0u;
-    gid[r] = ok ? ival[idx] : 0u;
-    if (!ok) key[r] = 0xFFFFFFFFu;  // no item: empty mask below
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const uint64_t m = key[r] == 0xFFFFFFFFu ? 0ull : item_mask(key[r]);
-    // lane t: the round's items covering tile t
-    const uint64_t col = wave_transpose64(m, lane);
-    const uint32_t c = (uint32_t)__popcll(col);
-    uint32_t incl = c;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t v = (uint32_t)__shfl_up((int)incl, o, 64);
-      if (lane >= o) incl += v;
+  // chunks from the queue, one per workgroup at a time (their work varies
+  // with the items' footprints; a fixed share per workgroup left a tail)
+  for (uint32_t it = 0;; ++it) {
+    if (threadIdx.x == 0) s_q[it & 1] = atomicAdd(queue, 1u);
+    __syncthreads();
+    const int64_t q = s_q[it & 1];  // slot it & 1 is written again two rounds on
+    if (q >= nchunks) break;
+    chunk_of((uint32_t)q, cfirst, nst, st_ranges, SGW, st_per_view, ch);
+    const int tx = ch.tx_base + (lane & 7), ty = ch.ty_base + (lane >> 3);
+    uint32_t pos = 0;
+    if (tx < GW && ty < GH) {
+      pos = tile_start[(int64_t)ch.view * tiles_per_view + (int64_t)ty * GW + tx] +
+            rel[(int64_t)q * 64 + lane];
+      for (int w = 0; w < wave; ++w) pos += wcnt[((int64_t)q * kWaves + w) * 64 + lane];
     }
-    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    if (total <= (uint32_t)kL2Stage) {
-      scatter_staged(col, incl - c, total, gid[r], held, pos, s_stage[wave], vals);
-      pos += c;
-    } else {
-      // the tiles any lane covers: the transposed masks' non-empty columns
-      const uint64_t u = __ballot(col != 0ull);
-      scatter_half((uint32_t)u, (uint32_t)m, 0, gid[r], held, pos, vals);
-      scatter_half((uint32_t)(u >> 32), (uint32_t)(m >> 32), 32, gid[r], held, pos, vals);
+    uint32_t key[4], gid[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {  // all four rounds' loads in flight at once
+      const uint32_t idx = ch.first + (uint32_t)(wave * 256 + r * 64 + lane);
+      const bool ok = idx < ch.end;
+      key[r] = ok ? ikey[idx] : 0u;
+      gid[r] = ok ? ival[idx] : 0u;
+      if (!ok) key[r] = 0xFFFFFFFFu;  // no item: empty mask below
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint64_t m = key[r] == 0xFFFFFFFFu ? 0ull : item_mask(key[r]);
+      // lane t: the round's items covering tile t
+      const uint64_t col = wave_transpose64(m, lane);
+      const uint32_t c = (uint32_t)__popcll(col);
+      uint32_t incl = c;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)incl, o, 64);
+        if (lane >= o) incl += v;
+      }
+      const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+      if (total <= (uint32_t)kL2Stage) {
+        scatter_staged(col, incl - c, total, gid[r], held, pos, s_stage[wave], vals);
+        pos += c;
+      } else {
+        // the tiles any lane covers: the transposed masks' non-empty columns
+        const uint64_t u = __ballot(col != 0ull);
+        scatter_half((uint32_t)u, (uint32_t)m, 0, gid[r], held, pos, vals);
+        scatter_half((uint32_t)(u >> 32), (uint32_t)(m >> 32), 32, gid[r], held, pos, vals);
+      }
     }
   }
 }
@@ -1090,10 +1104,10 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
   {
     SgsProfScope ps(c, SGS_PROF_DUPLICATE);
     if (chunks > 0)
-      k_l2_scatter<<<(unsigned)chunks, kThreads, 0, c->stream>>>(
-          c->chunk_first, nst, c->st_ranges, c->tile_key[which], c->pair_val[which], c->GW,
-          c->GH, tpv, c->SGW, spv, c->l2_cnt, c->l2_wcnt, c->tile_start, P, dP,
-          c->pair_val[which ^ 1]);
+      k_l2_scatter<<<resident_blocks<k_l2_scatter>(chunks), kThreads, 0, c->stream>>>(
+          c->chunk_first, c->chunk_first + nst + 1, nst, c->st_ranges, c->tile_key[which],
+          c->pair_val[which], c->GW, c->GH, tpv, c->SGW, spv, c->l2_cnt, c->l2_wcnt,
+          c->tile_start, P, dP, c->pair_val[which ^ 1]);
   }
   c->pair_sorted_buf = which ^ 1;
   return launch_tile_order(c);
