@@ -56,7 +56,6 @@ void free_scene(sgs_ctx *c) {
     dfree(c->pair_val[k]);
   }
   dfree(c->touched);
-  dfree(c->offsets);
   dfree(c->ioffsets);
   dfree(c->st_ranges);
   dfree(c->chunk_first);
@@ -79,6 +78,9 @@ void free_scene(sgs_ctx *c) {
   dfree(c->blk_start);
   c->blk_start_words = 0;
   dfree(c->splat_grad);
+  dfree(c->big_idx);
+  dfree(c->big_list);
+  dfree(c->big_rep);
   dfree(c->det_acc);
   dfree(c->ranges);
   dfree(c->tile_order);
@@ -257,7 +259,6 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
     SGS_ALLOC(c->depth_val[k], vn);
   }
   SGS_ALLOC(c->touched, vn);
-  SGS_ALLOC(c->offsets, vn + 1);
   SGS_ALLOC(c->ioffsets, vn + 1);
   SGS_ALLOC(c->st_ranges, c->total_st);
   SGS_ALLOC(c->chunk_first, c->total_st + 2);  // + the level-2 scatter's chunk queue
@@ -270,7 +271,16 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   c->fl_tmp_words = fl_scratch_words(n);
   SGS_ALLOC(c->mlp_signs, 2 * n);
   SGS_ALLOC(c->splat_grad, vn * SGS_SGRAD);
-  if (c->deterministic) SGS_ALLOC(c->det_acc, vn * SGS_SGRAD * 3);
+  if (c->deterministic) {
+    SGS_ALLOC(c->det_acc, vn * SGS_SGRAD * 3);
+  } else {
+    SGS_ALLOC(c->big_idx, vn);
+    SGS_ALLOC(c->big_list, kBigMax + kBigRanges);
+    SGS_ALLOC(c->big_rep, kBigMax * kBigReps * SGS_SGRAD);
+    // the replicas start at zero and the fold after each blend clears them
+    e = hipMemset(c->big_rep, 0, sizeof(double) * kBigMax * kBigReps * SGS_SGRAD);
+    if (e != hipSuccess) { free_scene(c); return hip_fail(c, e, "set_scene clear"); }
+  }
   SGS_ALLOC(c->ranges, c->total_tiles);
   SGS_ALLOC(c->tile_order, c->total_tiles);
   SGS_ALLOC(c->tile_bins, SGS_TILE_BINS);

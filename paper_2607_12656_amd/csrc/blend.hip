@@ -61,6 +61,27 @@ __device__ __forceinline__ bool may_reach(const float4 &a, const float4 &b, int 
   return sgs_may_reach(a.x, a.y, a.z, a.w, b.x, -__log2f(255.0f * b.y), sx0, sy0);
 }
 
+// Where a backward sum of splat gid (record s, view offset into big_idx
+// applied) from tile `tile` goes: its record, or for a large splat with a
+// replica slot, replica tile % kBigReps of that slot.  The tile count is the
+// projection's (tiles per view row / column of the span's corners).
+template <int TW, int TH>
+__device__ __forceinline__ double *grad_dst(double *gbase, uint32_t gid, const SplatLds &s,
+                                            const uint32_t *big_idx, double *big_rep,
+                                            int tile) {
+  if (big_idx) {
+    const uint32_t sx = __float_as_uint(s.b.z), sy = __float_as_uint(s.b.w);
+    const uint32_t tw = (sx >> 16) / TW - (sx & 0xFFFFu) / TW + 1u;
+    const uint32_t th = (sy >> 16) / TH - (sy & 0xFFFFu) / TH + 1u;
+    if (tw * th >= kBigTiles) {
+      const uint32_t slot = big_idx[gid];
+      if (slot != 0xFFFFFFFFu)
+        return big_rep + ((size_t)slot * kBigReps + (uint32_t)tile % kBigReps) * SGS_SGRAD;
+    }
+  }
+  return gbase + (size_t)gid * SGS_SGRAD;
+}
+
 // A 64-bit mask read from LDS, made wave-uniform (held in scalar registers).
 __device__ __forceinline__ uint64_t uniform_mask(uint64_t m) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)m);
@@ -370,7 +391,15 @@ __device__ __forceinline__ bool det_add(unsigned long long *acc, float v) {
 // One 8x8 sub-tile of a tile's backward, by one wave: the list from the
 // wave's furthest stop towards the front, 64 entries at a time staged in LDS
 // with their Gaussian ids, walked back to front.
-template <int TW, int TH, int WPB, bool DET>
+// PRE (the WPB waves of a workgroup take the sub-tiles of one tile): the
+// waves walk the batches in step (from the workgroup's furthest stop), each
+// wave's sum of an (entry, value) goes to its own LDS slot, and once every
+// wave is through the batch the slots of an (entry, value) are added in FP64
+// in wave order and one FP64 atomic adds the total to the splat's gradient:
+// a splat met by several sub-tiles of the tile costs one atomic per value
+// instead of one per sub-tile, and the result stays independent of the
+// order in which the waves ran.
+template <int TW, int TH, int WPB, bool DET, bool PRE>
 __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, int H, int GW,
                                               int tiles_per_view,
                                               const uint2 *__restrict__ ranges,
@@ -381,10 +410,15 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
                                               const float *__restrict__ dimg,
                                               double *__restrict__ sgrad,
                                               unsigned long long *__restrict__ dacc,
-                                              uint32_t *__restrict__ dflag) {
+                                              uint32_t *__restrict__ dflag,
+                                              const uint32_t *__restrict__ big_idx,
+                                              double *__restrict__ big_rep) {
   constexpr int SUBW = TW / 8;
   __shared__ SplatLds sh_all[WPB][64];  // one region per wave of the workgroup
   __shared__ uint32_t s_gid_all[WPB][64];
+  constexpr int kSlot = SGS_SGRAD + 1;       // slots per entry (padded against bank conflicts)
+  __shared__ float s_acc[PRE ? WPB * 64 * kSlot : 1];
+  __shared__ uint32_t s_reach[PRE ? WPB : 1];
   SplatLds *sh = sh_all[WPB > 1 ? (threadIdx.x >> 6) : 0];
   uint32_t *s_gid = s_gid_all[WPB > 1 ? (threadIdx.x >> 6) : 0];
   const int lane = threadIdx.x & 63;
@@ -410,13 +444,23 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
     g1 = dimg[((int64_t)v * 3 + 1) * plane + pix];
     g2 = dimg[((int64_t)v * 3 + 2) * plane + pix];
   }
-  // furthest list position reached by any pixel of the wave
+  // furthest list position reached by any pixel of the wave (PRE: and of
+  // the workgroup, which sets the batches every wave walks)
   uint32_t reach = my_last;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) reach = max(reach, (uint32_t)__shfl_xor(reach, o, 64));
-  if (reach == 0) return;
+  uint32_t reach_all = reach;
+  if (PRE) {
+    if (lane == 0) s_reach[threadIdx.x >> 6] = reach;
+    for (int i = (int)threadIdx.x; i < WPB * 64 * kSlot; i += WPB * 64) s_acc[i] = 0.0f;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < WPB; ++w) reach_all = max(reach_all, s_reach[w]);
+    __syncthreads();  // s_reach is read before a later tile writes it
+  }
+  if (reach_all == 0) return;
   float B0 = 0.f, B1 = 0.f, B2 = 0.f;  // colour seen behind the current splat
-  const int nbatch = (int)((reach + 63) / 64);
+  const int nbatch = (int)((reach_all + 63) / 64);
   const int vidx = sum10_index(lane);
   // the lane that adds value vidx to the splat's gradient (one per value: the
   // first of its quad, and for value 5 h + 2, which 16 lanes hold, the one
@@ -433,11 +477,12 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
   // per-splat sums in FP64: a splat's terms come from many tiles and
   // cancel, and FP32 sums in arbitrary order lose the small result
   double *const gbase = sgrad + base * SGS_SGRAD;
+  const uint32_t *const bigv = big_idx ? big_idx + base : nullptr;
   float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra;
   uint32_t rgid = 0;
   auto fetch = [&](int bi) {
     const uint32_t p = (uint32_t)bi * 64 + (uint32_t)lane;
-    if (p < reach) {
+    if (p < reach_all) {
       rgid = vals[rg.x + p];
       const float4 *r = rec + 3 * (base + rgid);
       ra = r[0];
@@ -451,14 +496,15 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
     wave_lds_sync();  // the previous batch's records have been read
     uint64_t m;
     {
-      const bool valid = p0 + (uint32_t)lane < reach;
-      if (valid) {
+      const bool staged = p0 + (uint32_t)lane < reach_all;
+      if (staged) {
         s_gid[lane] = rgid;
         sh[lane].a = ra;
         sh[lane].b = rb;
         sh[lane].c = rc;
       }
       // entries before the wave's furthest stop whose span meets the sub-tile
+      const bool valid = p0 + (uint32_t)lane < reach;
       const uint32_t sx = __float_as_uint(rb.z), sy = __float_as_uint(rb.w);
       m = __ballot(valid && (int)(sx & 0xFFFF) <= sx0 + 7 && (int)(sx >> 16) >= sx0 &&
                    (int)(sy & 0xFFFF) <= sy0 + 7 && (int)(sy >> 16) >= sy0 &&
@@ -466,7 +512,7 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
     }
     wave_lds_sync();
     if (bi > 0) fetch(bi - 1);
-    if (m == 0ull) continue;
+    if (!PRE && m == 0ull) continue;
     // gradient of entry k (record cur, Gaussian gid)
     auto step = [&](const SplatLds &cur, const SplatEval &e, int k, uint32_t gid) {
       const uint32_t pos = p0 + (uint32_t)k;
@@ -512,12 +558,15 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
       const float cs = fmaf(sel_a, cur.a.z, fmaf(sel_c, cur.b.x, k_rest));
       const float co = sel_b * cur.a.w;
       const float gv = fmaf(cs, tot, co * other);
-      if (lead && gv != 0.0f) {
+      if (PRE) {
+        if (lead && gv != 0.0f) s_acc[((threadIdx.x >> 6) * 64 + k) * kSlot + vidx] = gv;
+      } else if (lead && gv != 0.0f) {
         if (DET) {
           const size_t slot = ((size_t)(base + gid) * SGS_SGRAD + vidx) * 3;
           if (!det_add(dacc + slot, gv)) atomicOr(dflag, 1u);
         } else {
-          unsafeAtomicAdd(gbase + (size_t)gid * SGS_SGRAD + vidx, (double)gv);
+          unsafeAtomicAdd(grad_dst<TW, TH>(gbase, gid, cur, bigv, big_rep, tile) + vidx,
+                          (double)gv);
         }
       }
     };
@@ -536,6 +585,27 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
       step(ra_, ea, ka, ga);
       if (two) step(rb_, eb, kb, gb);
     }
+    if (PRE) {
+      // every wave's sums of the batch are in; one atomic per nonzero slot
+      // (the slot cleared for the next batch), the Gaussian ids from wave
+      // 0's copy of the batch (every wave stages all of it)
+      __syncthreads();
+      const uint32_t *gid0 = s_gid_all[0];
+      for (int i = (int)threadIdx.x; i < 64 * SGS_SGRAD; i += WPB * 64) {
+        const int e = i / SGS_SGRAD, j = i - e * SGS_SGRAD;
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < WPB; ++w) {
+          float &slot = s_acc[(w * 64 + e) * kSlot + j];
+          v += (double)slot;
+          slot = 0.0f;
+        }
+        if (v != 0.0)
+          unsafeAtomicAdd(grad_dst<TW, TH>(gbase, gid0[e], sh_all[0][e], bigv, big_rep, tile) + j,
+                          v);
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -546,19 +616,22 @@ k_blend_bwd(int total, const uint32_t *__restrict__ order, uint32_t *__restrict_
             const uint32_t *__restrict__ vals, const float4 *__restrict__ rec,
             const float *__restrict__ final_T, const uint32_t *__restrict__ last,
             const float *__restrict__ dimg, double *__restrict__ sgrad,
-            unsigned long long *__restrict__ dacc, uint32_t *__restrict__ dflag) {
+            unsigned long long *__restrict__ dacc, uint32_t *__restrict__ dflag,
+            const uint32_t *__restrict__ big_idx, double *__restrict__ big_rep) {
   constexpr int NW = TW * TH / 64;
   if (SCHED == kTileBlock) {
     for (int q = (int)blockIdx.x; q < total; q += (int)gridDim.x)
-      blend_bwd_sub<TW, TH, NW, DET>((int)order[q], (int)(threadIdx.x >> 6), n, W, H, GW,
+      blend_bwd_sub<TW, TH, NW, DET, (NW > 1 && !DET)>((int)order[q], (int)(threadIdx.x >> 6),
+                                                      n, W, H, GW,
                                      tiles_per_view, ranges, vals, rec, final_T, last, dimg,
-                                     sgrad, dacc, dflag);
+                                     sgrad, dacc, dflag, big_idx, big_rep);
   } else {
     for (int q = first_tile<SCHED>(head, total); q >= 0; q = later_tile<SCHED>(q, head, total)) {
       const int ti = q / NW;
-      blend_bwd_sub<TW, TH, 1, DET>(SCHED == kPerTile ? ti : (int)order[ti], q - ti * NW, n, W,
+      blend_bwd_sub<TW, TH, 1, DET, false>(SCHED == kPerTile ? ti : (int)order[ti], q - ti * NW,
+                                           n, W,
                                     H, GW, tiles_per_view, ranges, vals, rec, final_T, last, dimg,
-                                    sgrad, dacc, dflag);
+                                    sgrad, dacc, dflag, big_idx, big_rep);
     }
   }
 }
@@ -668,7 +741,8 @@ hipError_t bwd_td(sgs_ctx *c, const float *final_T, const uint32_t *last, const 
   k_blend_bwd<TW, TH, SCHED, DET><<<grid, block, 0, c->stream>>>(
       items, c->tile_order, c->tile_bins + 67, (int)c->n, c->W, c->H, c->GW,
       (int)c->tiles_per_view, c->ranges, vals, c->rec, final_T, last, dimg, c->splat_grad,
-      (unsigned long long *)c->det_acc, c->d_pairs_total + 3);
+      (unsigned long long *)c->det_acc, c->d_pairs_total + 3, DET ? nullptr : c->big_idx,
+      DET ? nullptr : c->big_rep);
   return hipGetLastError();
 }
 
@@ -697,10 +771,59 @@ hipError_t bwd_s(sgs_ctx *c, const float *final_T, const uint32_t *last, const f
 }
 
 // Clears the per-splat gradients and the backward queue head.
-__global__ void k_zero_grad(double *__restrict__ p, int64_t count, uint32_t *__restrict__ head) {
+__global__ void k_zero_grad(double *__restrict__ p, int64_t count, uint32_t *__restrict__ head,
+                            uint32_t *__restrict__ big_count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = 0.0;
   if (i == 0 && head) *head = 0u;
+  if (i < kBigRanges && big_count) big_count[i] = 0u;
+}
+
+// Replica slots of the large splat-views of this step (tile rectangle of at
+// least kBigTiles tiles), from range blockIdx % kBigRanges: one counter add
+// per wave; a splat finding its range full keeps its own record (slot
+// 0xFFFFFFFF).
+__global__ void k_big_index(const uint32_t *__restrict__ touched, int64_t vn,
+                            uint32_t *__restrict__ big_idx, uint32_t *__restrict__ big_list) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool big = s < vn && touched[s] >= kBigTiles;
+  const uint64_t m = __ballot(big);
+  if (m == 0ull) return;
+  const int lane = (int)(threadIdx.x & 63);
+  const int lead = __builtin_ctzll(m);
+  const uint32_t range = blockIdx.x % kBigRanges;
+  uint32_t first = 0;
+  if (lane == lead) first = atomicAdd(big_list + kBigMax + range, (uint32_t)__popcll(m));
+  first = (uint32_t)__shfl((int)first, lead, 64);
+  if (!big) return;
+  const uint32_t local = first + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+  if (local < (uint32_t)kBigPerRange) {
+    const uint32_t slot = range * (uint32_t)kBigPerRange + local;
+    big_idx[s] = slot;
+    big_list[slot] = (uint32_t)s;
+  } else {
+    big_idx[s] = 0xFFFFFFFFu;
+  }
+}
+
+// After the blend: each taken slot's replicas summed in replica order into
+// the splat's record (one thread per record value, the only writer of it),
+// and cleared for the next step.
+__global__ void k_big_fold(const uint32_t *__restrict__ big_list, double *__restrict__ big_rep,
+                           double *__restrict__ sgrad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t slot = i / SGS_SGRAD, j = i - slot * SGS_SGRAD;
+  if (slot >= kBigMax) return;
+  const int64_t range = slot / kBigPerRange, local = slot - range * kBigPerRange;
+  if (local >= min((int64_t)big_list[kBigMax + range], kBigPerRange)) return;
+  double *r = big_rep + (size_t)slot * kBigReps * SGS_SGRAD + j;
+  double v = 0.0;
+#pragma unroll
+  for (int k = 0; k < kBigReps; ++k) {
+    v += r[k * SGS_SGRAD];
+    r[k * SGS_SGRAD] = 0.0;
+  }
+  sgrad[(size_t)big_list[slot] * SGS_SGRAD + j] += v;
 }
 
 // Deterministic mode: clears the fixed-point accumulators (three words per
@@ -756,16 +879,25 @@ hipError_t launch_blend_bwd(sgs_ctx *c, const float *final_T, const uint32_t *la
     if (c->deterministic)
       k_zero_acc<<<sgs_blocks(3 * words, 256), 256, 0, c->stream>>>(
           (unsigned long long *)c->det_acc, 3 * words, c->tile_bins + 67);
-    else
+    else {
       k_zero_grad<<<sgs_blocks(words, 256), 256, 0, c->stream>>>(c->splat_grad, words,
-                                                                  c->tile_bins + 67);
+                                                                  c->tile_bins + 67,
+                                                                  c->big_list + kBigMax);
+      k_big_index<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(c->touched, c->vn, c->big_idx,
+                                                                 c->big_list);
+    }
   }
   hipError_t e = hipErrorInvalidValue;
   if (c->TW == 16 && c->TH == 16) e = bwd_s<16, 16>(c, final_T, last, dimg);
   if (c->TW == 8 && c->TH == 8) e = bwd_s<8, 8>(c, final_T, last, dimg);
   if (c->TW == 32 && c->TH == 8) e = bwd_s<32, 8>(c, final_T, last, dimg);
-  if (e != hipSuccess || !c->deterministic) return e;
+  if (e != hipSuccess) return e;
   SgsProfScope ps(c, SGS_PROF_BLEND_BWD);
+  if (!c->deterministic) {
+    k_big_fold<<<sgs_blocks(kBigMax * SGS_SGRAD, 256), 256, 0, c->stream>>>(
+        c->big_list, c->big_rep, c->splat_grad);
+    return hipGetLastError();
+  }
   k_acc_to_grad<<<sgs_blocks(words, 256), 256, 0, c->stream>>>(
       (const unsigned long long *)c->det_acc, words, c->splat_grad);
   return hipGetLastError();

@@ -22,6 +22,20 @@
 // mask, pad, pad.
 #define SGS_SGRAD 10  // px, py, A, B, C, opacity, r, g, b, mask (five 16-byte pairs)
 
+// Large splats in the backward: every tile a splat covers adds its sums to
+// the splat's record, and FP64 atomics to one address serialize in the L2.
+// A splat-view whose tile rectangle covers at least kBigTiles tiles takes a
+// slot with kBigReps replica records, tile t adding to replica t %
+// kBigReps; the replicas are folded into the record in a fixed order after
+// the blend.  The kBigMax slots form kBigRanges ranges, each with its own
+// counter (so that taking slots is not itself one contended address); a
+// large splat finding its range full keeps its own record.
+constexpr uint32_t kBigTiles = 512;
+constexpr int kBigReps = 16;
+constexpr int64_t kBigMax = 16384;
+constexpr int kBigRanges = 64;
+constexpr int64_t kBigPerRange = kBigMax / kBigRanges;
+
 // Blend conventions (the paper does not state them).
 #define SGS_NEAR 0.2f
 #define SGS_DILATION 0.3f
@@ -65,10 +79,13 @@ struct sgs_ctx {
   uint32_t *depth_key[2] = {nullptr, nullptr};
   uint32_t *depth_val[2] = {nullptr, nullptr};
   uint32_t *touched = nullptr;    // [vn] tiles per splat (0 = culled)
-  uint32_t *offsets = nullptr;    // [vn + 1] exclusive scan in depth order
   uint4 *bin_splat = nullptr;     // [vn] (first tile id, width in tiles, Gaussian, pairs)
   uint4 *bin_rec = nullptr;       // [vn] the same records in depth order
   double *splat_grad = nullptr;   // [vn][SGS_SGRAD] per-splat gradient sums (FP64 atomics)
+  uint32_t *big_idx = nullptr;    // [vn] replica slot of a large splat (see kBigTiles)
+  uint32_t *big_list = nullptr;   // [kBigMax + kBigRanges] splat of each slot, then the
+                                  // slots taken in each range
+  double *big_rep = nullptr;      // [kBigMax][kBigReps][SGS_SGRAD] replica sums (zero between steps)
   int depth_sorted_buf = 0;       // which depth buffer holds the sorted order
 
   // super-tiles (8x8 tiles): the first level of the tile binning

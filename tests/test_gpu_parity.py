@@ -208,7 +208,11 @@ TINY = [
     dict(n=48, W=45, H=37, V=1, seed=2),
     dict(n=64, W=70, H=50, V=2, seed=3),
     dict(n=200, W=96, H=80, V=1, seed=4, logscale=-2.5),
+    # large splats: tile rectangles of 512 tiles and more take the backward's
+    # replica records (folded into the splat's record after the blend)
+    dict(n=60, W=640, H=480, V=2, seed=5, logscale=-1.8, big=True),
 ]
+BIG_TILES = 512   # the library's large-splat threshold (tiles per rectangle)
 
 
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
@@ -222,6 +226,13 @@ def test_tiny_scenes_full_step(orc, gctx, dev, tile, cfg):
     check_stats(g, r, sc)
     check_image(g, r)
     check_l1(g, r, sc)
+    if c.get("big"):
+        sp = g["spans"].reshape(-1, 4).astype(np.int64)
+        sp = sp[sp[:, 0] >= 0]
+        tiles = ((sp[:, 1] // tile[0] - sp[:, 0] // tile[0] + 1) *
+                 (sp[:, 3] // tile[1] - sp[:, 2] // tile[1] + 1))
+        assert (tiles >= BIG_TILES).sum() >= 3, "no large splats in the large-splat case"
+        assert (tiles < BIG_TILES).sum() >= 3, "no small splats in the large-splat case"
     # render backward fed the same dL/dimage
     grad_close(g["gq_render"][:, :sc.n], r["gyhat"][:, :sc.n], name="grad qparams")
     grad_close(g["gmask"], r["gmhat"], name="grad mask")
