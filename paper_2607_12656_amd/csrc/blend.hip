@@ -61,23 +61,25 @@ __device__ __forceinline__ bool may_reach(const float4 &a, const float4 &b, int 
   return sgs_may_reach(a.x, a.y, a.z, a.w, b.x, -__log2f(255.0f * b.y), sx0, sy0);
 }
 
-// Where a backward sum of splat gid (record s, view offset into big_idx
-// applied) from tile `tile` goes: its record, or for a large splat with a
-// replica slot, replica tile % kBigReps of that slot.  The tile count is the
-// projection's (tiles per view row / column of the span's corners).
+// Whether a splat is large: its tile rectangle (the projection's: tiles per
+// view row / column of the span's corners) covers kBigTiles tiles or more.
 template <int TW, int TH>
-__device__ __forceinline__ double *grad_dst(double *gbase, uint32_t gid, const SplatLds &s,
+__device__ __forceinline__ bool big_splat(uint32_t sx, uint32_t sy) {
+  const uint32_t tw = (sx >> 16) / TW - (sx & 0xFFFFu) / TW + 1u;
+  const uint32_t th = (sy >> 16) / TH - (sy & 0xFFFFu) / TH + 1u;
+  return tw * th >= kBigTiles;
+}
+
+// Where a backward sum of splat gid from tile `tile` goes: its record, or
+// for a large splat with a replica slot (big_idx offset to the view),
+// replica tile % kBigReps of that slot.
+__device__ __forceinline__ double *grad_dst(double *gbase, uint32_t gid, bool big,
                                             const uint32_t *big_idx, double *big_rep,
                                             int tile) {
-  if (big_idx) {
-    const uint32_t sx = __float_as_uint(s.b.z), sy = __float_as_uint(s.b.w);
-    const uint32_t tw = (sx >> 16) / TW - (sx & 0xFFFFu) / TW + 1u;
-    const uint32_t th = (sy >> 16) / TH - (sy & 0xFFFFu) / TH + 1u;
-    if (tw * th >= kBigTiles) {
-      const uint32_t slot = big_idx[gid];
-      if (slot != 0xFFFFFFFFu)
-        return big_rep + ((size_t)slot * kBigReps + (uint32_t)tile % kBigReps) * SGS_SGRAD;
-    }
+  if (big) {
+    const uint32_t slot = big_idx[gid];
+    if (slot != 0xFFFFFFFFu)
+      return big_rep + ((size_t)slot * kBigReps + (uint32_t)tile % kBigReps) * SGS_SGRAD;
   }
   return gbase + (size_t)gid * SGS_SGRAD;
 }
@@ -391,15 +393,7 @@ __device__ __forceinline__ bool det_add(unsigned long long *acc, float v) {
 // One 8x8 sub-tile of a tile's backward, by one wave: the list from the
 // wave's furthest stop towards the front, 64 entries at a time staged in LDS
 // with their Gaussian ids, walked back to front.
-// PRE (the WPB waves of a workgroup take the sub-tiles of one tile): the
-// waves walk the batches in step (from the workgroup's furthest stop), each
-// wave's sum of an (entry, value) goes to its own LDS slot, and once every
-// wave is through the batch the slots of an (entry, value) are added in FP64
-// in wave order and one FP64 atomic adds the total to the splat's gradient:
-// a splat met by several sub-tiles of the tile costs one atomic per value
-// instead of one per sub-tile, and the result stays independent of the
-// order in which the waves ran.
-template <int TW, int TH, int WPB, bool DET, bool PRE>
+template <int TW, int TH, int WPB, bool DET>
 __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, int H, int GW,
                                               int tiles_per_view,
                                               const uint2 *__restrict__ ranges,
@@ -416,9 +410,6 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
   constexpr int SUBW = TW / 8;
   __shared__ SplatLds sh_all[WPB][64];  // one region per wave of the workgroup
   __shared__ uint32_t s_gid_all[WPB][64];
-  constexpr int kSlot = SGS_SGRAD + 1;       // slots per entry (padded against bank conflicts)
-  __shared__ float s_acc[PRE ? WPB * 64 * kSlot : 1];
-  __shared__ uint32_t s_reach[PRE ? WPB : 1];
   SplatLds *sh = sh_all[WPB > 1 ? (threadIdx.x >> 6) : 0];
   uint32_t *s_gid = s_gid_all[WPB > 1 ? (threadIdx.x >> 6) : 0];
   const int lane = threadIdx.x & 63;
@@ -444,23 +435,13 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
     g1 = dimg[((int64_t)v * 3 + 1) * plane + pix];
     g2 = dimg[((int64_t)v * 3 + 2) * plane + pix];
   }
-  // furthest list position reached by any pixel of the wave (PRE: and of
-  // the workgroup, which sets the batches every wave walks)
+  // furthest list position reached by any pixel of the wave
   uint32_t reach = my_last;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) reach = max(reach, (uint32_t)__shfl_xor(reach, o, 64));
-  uint32_t reach_all = reach;
-  if (PRE) {
-    if (lane == 0) s_reach[threadIdx.x >> 6] = reach;
-    for (int i = (int)threadIdx.x; i < WPB * 64 * kSlot; i += WPB * 64) s_acc[i] = 0.0f;
-    __syncthreads();
-#pragma unroll
-    for (int w = 0; w < WPB; ++w) reach_all = max(reach_all, s_reach[w]);
-    __syncthreads();  // s_reach is read before a later tile writes it
-  }
-  if (reach_all == 0) return;
+  if (reach == 0) return;
   float B0 = 0.f, B1 = 0.f, B2 = 0.f;  // colour seen behind the current splat
-  const int nbatch = (int)((reach_all + 63) / 64);
+  const int nbatch = (int)((reach + 63) / 64);
   const int vidx = sum10_index(lane);
   // the lane that adds value vidx to the splat's gradient (one per value: the
   // first of its quad, and for value 5 h + 2, which 16 lanes hold, the one
@@ -482,7 +463,7 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
   uint32_t rgid = 0;
   auto fetch = [&](int bi) {
     const uint32_t p = (uint32_t)bi * 64 + (uint32_t)lane;
-    if (p < reach_all) {
+    if (p < reach) {
       rgid = vals[rg.x + p];
       const float4 *r = rec + 3 * (base + rgid);
       ra = r[0];
@@ -494,25 +475,26 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
   for (int bi = nbatch - 1; bi >= 0; --bi) {
     const uint32_t p0 = (uint32_t)bi * 64;
     wave_lds_sync();  // the previous batch's records have been read
-    uint64_t m;
+    uint64_t m, bigm;
     {
-      const bool staged = p0 + (uint32_t)lane < reach_all;
-      if (staged) {
+      const bool valid = p0 + (uint32_t)lane < reach;
+      if (valid) {
         s_gid[lane] = rgid;
         sh[lane].a = ra;
         sh[lane].b = rb;
         sh[lane].c = rc;
       }
       // entries before the wave's furthest stop whose span meets the sub-tile
-      const bool valid = p0 + (uint32_t)lane < reach;
       const uint32_t sx = __float_as_uint(rb.z), sy = __float_as_uint(rb.w);
       m = __ballot(valid && (int)(sx & 0xFFFF) <= sx0 + 7 && (int)(sx >> 16) >= sx0 &&
                    (int)(sy & 0xFFFF) <= sy0 + 7 && (int)(sy >> 16) >= sy0 &&
                    may_reach(ra, rb, sx0, sy0));
+      // the batch's large splats (tile rectangle of kBigTiles tiles or more)
+      bigm = big_idx ? __ballot(valid && big_splat<TW, TH>(sx, sy)) : 0ull;
     }
     wave_lds_sync();
     if (bi > 0) fetch(bi - 1);
-    if (!PRE && m == 0ull) continue;
+    if (m == 0ull) continue;
     // gradient of entry k (record cur, Gaussian gid)
     auto step = [&](const SplatLds &cur, const SplatEval &e, int k, uint32_t gid) {
       const uint32_t pos = p0 + (uint32_t)k;
@@ -558,14 +540,12 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
       const float cs = fmaf(sel_a, cur.a.z, fmaf(sel_c, cur.b.x, k_rest));
       const float co = sel_b * cur.a.w;
       const float gv = fmaf(cs, tot, co * other);
-      if (PRE) {
-        if (lead && gv != 0.0f) s_acc[((threadIdx.x >> 6) * 64 + k) * kSlot + vidx] = gv;
-      } else if (lead && gv != 0.0f) {
+      if (lead && gv != 0.0f) {
         if (DET) {
           const size_t slot = ((size_t)(base + gid) * SGS_SGRAD + vidx) * 3;
           if (!det_add(dacc + slot, gv)) atomicOr(dflag, 1u);
         } else {
-          unsafeAtomicAdd(grad_dst<TW, TH>(gbase, gid, cur, bigv, big_rep, tile) + vidx,
+          unsafeAtomicAdd(grad_dst(gbase, gid, (bigm >> k) & 1ull, bigv, big_rep, tile) + vidx,
                           (double)gv);
         }
       }
@@ -585,27 +565,6 @@ __device__ __forceinline__ void blend_bwd_sub(int tile, int sub, int n, int W, i
       step(ra_, ea, ka, ga);
       if (two) step(rb_, eb, kb, gb);
     }
-    if (PRE) {
-      // every wave's sums of the batch are in; one atomic per nonzero slot
-      // (the slot cleared for the next batch), the Gaussian ids from wave
-      // 0's copy of the batch (every wave stages all of it)
-      __syncthreads();
-      const uint32_t *gid0 = s_gid_all[0];
-      for (int i = (int)threadIdx.x; i < 64 * SGS_SGRAD; i += WPB * 64) {
-        const int e = i / SGS_SGRAD, j = i - e * SGS_SGRAD;
-        double v = 0.0;
-#pragma unroll
-        for (int w = 0; w < WPB; ++w) {
-          float &slot = s_acc[(w * 64 + e) * kSlot + j];
-          v += (double)slot;
-          slot = 0.0f;
-        }
-        if (v != 0.0)
-          unsafeAtomicAdd(grad_dst<TW, TH>(gbase, gid0[e], sh_all[0][e], bigv, big_rep, tile) + j,
-                          v);
-      }
-      __syncthreads();
-    }
   }
 }
 
@@ -621,15 +580,13 @@ k_blend_bwd(int total, const uint32_t *__restrict__ order, uint32_t *__restrict_
   constexpr int NW = TW * TH / 64;
   if (SCHED == kTileBlock) {
     for (int q = (int)blockIdx.x; q < total; q += (int)gridDim.x)
-      blend_bwd_sub<TW, TH, NW, DET, (NW > 1 && !DET)>((int)order[q], (int)(threadIdx.x >> 6),
-                                                      n, W, H, GW,
+      blend_bwd_sub<TW, TH, NW, DET>((int)order[q], (int)(threadIdx.x >> 6), n, W, H, GW,
                                      tiles_per_view, ranges, vals, rec, final_T, last, dimg,
                                      sgrad, dacc, dflag, big_idx, big_rep);
   } else {
     for (int q = first_tile<SCHED>(head, total); q >= 0; q = later_tile<SCHED>(q, head, total)) {
       const int ti = q / NW;
-      blend_bwd_sub<TW, TH, 1, DET, false>(SCHED == kPerTile ? ti : (int)order[ti], q - ti * NW,
-                                           n, W,
+      blend_bwd_sub<TW, TH, 1, DET>(SCHED == kPerTile ? ti : (int)order[ti], q - ti * NW, n, W,
                                     H, GW, tiles_per_view, ranges, vals, rec, final_T, last, dimg,
                                     sgrad, dacc, dflag, big_idx, big_rep);
     }
@@ -763,7 +720,6 @@ hipError_t fwd_s(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint6
 
 template <int TW, int TH>
 hipError_t bwd_s(sgs_ctx *c, const float *final_T, const uint32_t *last, const float *dimg) {
-  SgsProfScope ps(c, SGS_PROF_BLEND_BWD);
   if (c->schedule == kStride) return bwd_t<TW, TH, kStride>(c, final_T, last, dimg);
   if (c->schedule == kTileBlock) return bwd_t<TW, TH, kTileBlock>(c, final_T, last, dimg);
   if (c->schedule == kQueue) return bwd_t<TW, TH, kQueue>(c, final_T, last, dimg);
@@ -887,12 +843,13 @@ hipError_t launch_blend_bwd(sgs_ctx *c, const float *final_T, const uint32_t *la
                                                                  c->big_list);
     }
   }
+  // one profiling record per call: the blend and the fold of its sums
+  SgsProfScope ps(c, SGS_PROF_BLEND_BWD);
   hipError_t e = hipErrorInvalidValue;
   if (c->TW == 16 && c->TH == 16) e = bwd_s<16, 16>(c, final_T, last, dimg);
   if (c->TW == 8 && c->TH == 8) e = bwd_s<8, 8>(c, final_T, last, dimg);
   if (c->TW == 32 && c->TH == 8) e = bwd_s<32, 8>(c, final_T, last, dimg);
   if (e != hipSuccess) return e;
-  SgsProfScope ps(c, SGS_PROF_BLEND_BWD);
   if (!c->deterministic) {
     k_big_fold<<<sgs_blocks(kBigMax * SGS_SGRAD, 256), 256, 0, c->stream>>>(
         c->big_list, c->big_rep, c->splat_grad);

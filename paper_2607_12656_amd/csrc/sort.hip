@@ -629,22 +629,56 @@ __device__ __forceinline__ uint64_t item_mask(uint32_t key) {
   return (row * 0x0101010101010101ull) & rows;
 }
 
+// The value of lane L ^ S, moved without LDS: the half and row swaps of
+// gfx950 (each returns both halves of the pair; lanes in the upper half or
+// odd row take the first) and DPP within rows (S = 4: mirror the eight, then
+// reverse the quad).
+template <int kCtrl>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kCtrl, 0xF, 0xF, false);
+}
+template <int S>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t x, int lane) {
+  if constexpr (S == 32) {
+    const auto sw = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return (lane & 32) ? sw[0] : sw[1];
+  } else if constexpr (S == 16) {
+    const auto sw = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return (lane & 16) ? sw[0] : sw[1];
+  } else if constexpr (S == 8) {
+    return dpp_u32<0x128>(x);                  // row_ror:8
+  } else if constexpr (S == 4) {
+    return dpp_u32<0x1B>(dpp_u32<0x141>(x));   // row_half_mirror, quad_perm [3,2,1,0]
+  } else if constexpr (S == 2) {
+    return dpp_u32<0x4E>(x);                   // quad_perm [2,3,0,1]
+  } else {
+    return dpp_u32<0xB1>(x);                   // quad_perm [1,0,3,2]
+  }
+}
+
+// One butterfly stage: lanes L and L ^ S exchange the blocks of S bits that
+// belong to the other one (m: the blocks a lane with bit S clear keeps).
+template <int S>
+__device__ __forceinline__ uint64_t transpose_stage(uint64_t r, int lane, uint64_t m) {
+  const uint32_t olo = xor_lane<S>((uint32_t)r, lane);
+  const uint32_t ohi = xor_lane<S>((uint32_t)(r >> 32), lane);
+  const uint64_t o = ((uint64_t)ohi << 32) | olo;
+  const bool up = lane & S;
+  const uint64_t keep = up ? ~m : m;
+  const uint64_t in = up ? (o >> S) : (o << S);
+  return (r & keep) | (in & ~keep);
+}
+
 // 64 x 64 bit transpose over the wave: lane L holds row L (bit t set when
 // item L covers tile t); afterwards lane t holds column t (bit L set when
-// item L covers tile t).  Six butterfly stages: lanes L and L ^ s exchange
-// the blocks of s bits that belong to the other one.
+// item L covers tile t).  Six butterfly stages.
 __device__ __forceinline__ uint64_t wave_transpose64(uint64_t r, int lane) {
-  const uint64_t M[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
-                         0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const int s = 32 >> k;
-    const uint64_t m = M[k];
-    const uint32_t olo = (uint32_t)__shfl_xor((int)(uint32_t)r, s, 64);
-    const uint32_t ohi = (uint32_t)__shfl_xor((int)(uint32_t)(r >> 32), s, 64);
-    const uint64_t o = ((uint64_t)ohi << 32) | olo;
-    r = (lane & s) ? ((r & ~m) | ((o & ~m) >> s)) : ((r & m) | ((o & m) << s));
-  }
+  r = transpose_stage<32>(r, lane, 0x00000000FFFFFFFFull);
+  r = transpose_stage<16>(r, lane, 0x0000FFFF0000FFFFull);
+  r = transpose_stage<8>(r, lane, 0x00FF00FF00FF00FFull);
+  r = transpose_stage<4>(r, lane, 0x0F0F0F0F0F0F0F0Full);
+  r = transpose_stage<2>(r, lane, 0x3333333333333333ull);
+  r = transpose_stage<1>(r, lane, 0x5555555555555555ull);
   return r;
 }
 
