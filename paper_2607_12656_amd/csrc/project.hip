@@ -220,9 +220,15 @@ k_preprocess_bwd(int64_t n, int64_t npad, int V, int W, int H,
   float gm = 0.0f;
   const float opa = 1.0f / (1.0f + __expf(-y[SGS_CH_OPA]));
   const int nv = live ? V : 0;
+  // which of the first 32 views touch the splat, loaded together up front
+  // (one wait instead of one per view before its record is read)
+  uint32_t tmask = 0;
+#pragma unroll 8
+  for (int v = 0; v < min(nv, 32); ++v)
+    tmask |= touched[(int64_t)v * n + i] != 0 ? 1u << v : 0u;
   for (int v = 0; v < nv; ++v) {
     const int64_t s = (int64_t)v * n + i;
-    if (touched[s] == 0) continue;
+    if (v < 32 ? ((tmask >> v) & 1u) == 0u : touched[s] == 0) continue;
     const double2 *gs = (const double2 *)(sgrad + s * SGS_SGRAD);
     const double2 h0 = gs[0], h1 = gs[1], h2 = gs[2], h3 = gs[3], h4 = gs[4];
     const float gpx = (float)h0.x, gpy = (float)h0.y, gA = (float)h1.x, gB = (float)h1.y;

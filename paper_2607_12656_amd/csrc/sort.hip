@@ -491,16 +491,26 @@ k_gather_bins(const uint32_t *__restrict__ order, const uint32_t *__restrict__ d
   __shared__ uint64_t s_sum[kWaves];
   const int64_t base = (int64_t)blockIdx.x * kTile;
   uint64_t acc = 0;
-#pragma unroll 4
-  for (int k = 0; k < kItems; ++k) {
-    const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
-    if (i < count) {
+  // eight gathers in flight at a time (each waits on two loads before it)
+  constexpr int kHalf = kItems / 2;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    uint4 b[kHalf];
+#pragma unroll
+    for (int k = 0; k < kHalf; ++k) {
+      const int64_t i = base + (int64_t)(h * kHalf + k) * kThreads + threadIdx.x;
       // the record of an invalid splat, as the projection writes it
-      uint4 b = make_uint4(0u, 1u, 0u, 0u);
-      if (dkey[i] != 0xFFFFFFFFu) b = bin_splat[order[i]];
-      brec[i] = b;
-      acc += b.w;
-      icnt[i] = b.w ? super_tiles_met(b, tiles_per_view, GW) : 0u;
+      b[k] = make_uint4(0u, 1u, 0u, 0u);
+      if (i < count && dkey[i] != 0xFFFFFFFFu) b[k] = bin_splat[order[i]];
+    }
+#pragma unroll
+    for (int k = 0; k < kHalf; ++k) {
+      const int64_t i = base + (int64_t)(h * kHalf + k) * kThreads + threadIdx.x;
+      if (i < count) {
+        brec[i] = b[k];
+        acc += b[k].w;
+        icnt[i] = b[k].w ? super_tiles_met(b[k], tiles_per_view, GW) : 0u;
+      }
     }
   }
 #pragma unroll
