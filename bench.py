@@ -94,10 +94,10 @@ def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int, items: in
         return "hbm", n * (NCH * 4 + 1) + V * n * (48 + 12 + 16), "B"
     if g == "depth_sort":         # one read + one write of key and value
         return "hbm", V * n * 16, "B"
-    if g == "scan":               # binning records gathered into depth order (16 + 16),
-        # pair counts and offsets (4 + 4 + 4), super-tile records and counts (16 + 4),
-        # item offsets (4 + 4)
-        return "hbm", V * n * 72, "B"
+    if g == "scan":               # sorted key and index read (4 + 4), binning record
+        # gathered and written in depth order (16 + 16), item count written (4), item
+        # offsets scanned (4 + 4 read, 4 written)
+        return "hbm", V * n * 56, "B"
     if g == "duplicate":          # every pair written once (4 B); per item its key and
         # Gaussian index read (8 B)
         return "hbm", P * 4 + items * 8, "B"
@@ -111,8 +111,8 @@ def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int, items: in
         return "alu", E * FLOP_PER_EVAL_FWD, "FLOP"
     if g == "l1":
         return "hbm", pix * 3 * 12, "B"
-    if g == "grad_clear":
-        return "hbm", V * n * 80, "B"
+    if g == "grad_clear":         # records cleared, tile counts read for the large-splat slots
+        return "hbm", V * n * (80 + 4), "B"
     if g == "blend_bwd":
         return "alu", E * FLOP_PER_EVAL_BWD, "FLOP"
     if g == "preprocess_bwd":
