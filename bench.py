@@ -81,11 +81,13 @@ def _decided(decisions, use0, i):
 
 
 def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int, items: int = 0,
-               tiles: int = 0, st: int = 1):
+               tiles: int = 0, st: int = 1, kept: int | None = None):
     """(bound, algorithmic amount per launch, unit) of one kernel group; E is
     the count of evaluations the blend performs (after its reach test),
     items the (splat, super-tile) items of the binning's first level, tiles
-    and st the tile and super-tile counts."""
+    and st the tile and super-tile counts, kept the Gaussians the mask keeps
+    (the others have zero parameter gradients, which the sparse Adam
+    skips)."""
     pix = V * W * H
     if g == "fakequant":          # statistics and mask (the projection quantizes)
         return "hbm", n * (NCH * 4 + 1 + 1 + 4), "B"
@@ -119,15 +121,19 @@ def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int, items: in
         return "hbm", n * (NCH * 4 * 2 + 4 + 4) + V * n * 80, "B"
     if g == "fakequant_bwd":
         return "hbm", NCH * 8 * -(-n // 128), "B"
-    if g == "adam":               # y, m, v read + written, g read; steps and scores
-        return "hbm", n * (NCH * 4 * 7 + 4 * 7), "B"
+    if g == "adam":               # per iteration of the 16-iteration period: the rows
+        # updated (14, and the 45 higher-SH rows every 16th) read as gradients for every
+        # Gaussian, and y, m, v read + written for the kept ones; scores (4 B x 7)
+        rows = (NCH - 45) + 45 / 16
+        upd = n if kept is None else kept
+        return "hbm", int(n * rows * 4 + upd * rows * 24 + n * 4 * 7), "B"
     if g in ("mlp_fwd", "mlp_bwd"):
         return "mfma", n * MLP_FLOP_PER_ROW * (1 if g == "mlp_fwd" else 2), "FLOP"
     return "hbm", 0, "B"
 
 
-def roofline(g, ms, n, V, P, E, W, H, traffic_key=None, items=0, tiles=0, st=1):
-    bound, amount, unit = group_work(g, n, V, P, E, W, H, items, tiles, st)
+def roofline(g, ms, n, V, P, E, W, H, traffic_key=None, items=0, tiles=0, st=1, kept=None):
+    bound, amount, unit = group_work(g, n, V, P, E, W, H, items, tiles, st, kept)
     dur = ms * 1e-3
     if unit == "B":
         achieved, peak, ru = amount / dur / 1e9, HBM_PEAK_GBS, "GB/s"
@@ -483,7 +489,7 @@ def bench_formation(args, sc, ctx, stream, dev, t):
                     traffic_key=f"c5:{dom}", items=L["items_last"], **geo)
     groups = {g: roofline(g, ms, sc.n, sc.views, L["pairs_last"],
                           L["evals_after_reach_test"] // K, sc.width, sc.height,
-                          items=L["items_last"], **geo)
+                          items=L["items_last"], kept=L["kept_last"], **geo)
               for g, ms in L["kernel_ms"].items()}
     line = {
         "metric": METRIC, "value": L["value"], "unit": "Gaussian-pixel evals/s", "n_gpus": 1,
