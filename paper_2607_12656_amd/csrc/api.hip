@@ -52,6 +52,7 @@ void free_scene(sgs_ctx *c) {
   for (int k = 0; k < 2; ++k) {
     dfree(c->depth_key[k]);
     dfree(c->depth_val[k]);
+    dfree(c->depth_rect[k]);
     dfree(c->tile_key[k]);
     dfree(c->pair_val[k]);
   }
@@ -257,6 +258,7 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   for (int k = 0; k < 2; ++k) {
     SGS_ALLOC(c->depth_key[k], vn);
     SGS_ALLOC(c->depth_val[k], vn);
+    SGS_ALLOC(c->depth_rect[k], vn);
   }
   SGS_ALLOC(c->touched, vn);
   SGS_ALLOC(c->ioffsets, vn + 1);

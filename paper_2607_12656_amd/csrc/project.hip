@@ -121,7 +121,8 @@ k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
              const float *__restrict__ q, const uint8_t *__restrict__ hard,
              float4 *__restrict__ rec, uint32_t *__restrict__ depth_key,
              uint32_t *__restrict__ depth_val, uint32_t *__restrict__ touched,
-             uint4 *__restrict__ bins, int GW, int64_t tiles_per_view) {
+             uint4 *__restrict__ bins, uint32_t *__restrict__ rect, int GW,
+             int64_t tiles_per_view) {
   __shared__ float s_q[QUANT ? 64 : 1], s_rq[QUANT ? 64 : 1];
   if (QUANT) load_quant_table(q, s_q, s_rq);
   const int64_t i = (int64_t)blockIdx.x * kPThreads + threadIdx.x;
@@ -148,6 +149,7 @@ k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
       depth_key[s] = 0xFFFFFFFFu;
       touched[s] = 0;
       bins[s] = make_uint4(0u, 1u, 0u, 0u);
+      rect[s] = kNoRect;
       rec[3 * s] = make_float4(0.f, 0.f, 0.f, 0.f);
       rec[3 * s + 1] = make_float4(0.f, 0.f, __int_as_float(-1), __int_as_float(-1));
       rec[3 * s + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -159,6 +161,8 @@ k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
     // binning record: first tile id, rectangle width in tiles, Gaussian, pairs
     bins[s] = make_uint4((uint32_t)(v * tiles_per_view) + (uint32_t)((p.y0 / TH) * GW + p.x0 / TW),
                          (uint32_t)tw, (uint32_t)i, (uint32_t)(tw * th));
+    // the same rectangle in one word, which the depth sort carries along
+    rect[s] = sgs_pack_rect(p.x0 / TW, p.y0 / TH, tw, th);
     const float A = p.c / p.det, B = -p.b / p.det, C = p.a / p.det;
     float col[3];
     bool cl[3];
@@ -419,12 +423,13 @@ hipError_t launch_preprocess(sgs_ctx *c, const float *qparams, const uint8_t *ha
   if (q)
     k_preprocess<true><<<nb, kPThreads, 0, c->stream>>>(
         c->n, c->npad, c->V, c->W, c->H, c->TW, c->TH, c->d_cams, qparams, q, hard, c->rec,
-        c->depth_key[0], c->depth_val[0], c->touched, c->bin_splat, c->GW, c->tiles_per_view);
+        c->depth_key[0], c->depth_val[0], c->touched, c->bin_splat, c->depth_rect[0], c->GW,
+        c->tiles_per_view);
   else
     k_preprocess<false><<<nb, kPThreads, 0, c->stream>>>(
         c->n, c->npad, c->V, c->W, c->H, c->TW, c->TH, c->d_cams, qparams, nullptr, hard,
-        c->rec, c->depth_key[0], c->depth_val[0], c->touched, c->bin_splat, c->GW,
-        c->tiles_per_view);
+        c->rec, c->depth_key[0], c->depth_val[0], c->touched, c->bin_splat, c->depth_rect[0],
+        c->GW, c->tiles_per_view);
   return hipGetLastError();
 }
 

@@ -22,6 +22,15 @@
 // mask, pad, pad.
 #define SGS_SGRAD 10  // px, py, A, B, C, opacity, r, g, b, mask (five 16-byte pairs)
 
+// A splat's tile rectangle in one word: first column and row (10 bits each),
+// width - 1 and height - 1 (6 bits each); kNoRect when it does not fit.
+constexpr uint32_t kNoRect = 0xFFFFFFFFu;
+__host__ __device__ __forceinline__ uint32_t sgs_pack_rect(int tx0, int ty0, int tw, int th) {
+  if (tx0 >= 1024 || ty0 >= 1024 || tw > 64 || th > 64) return kNoRect;
+  return (uint32_t)tx0 | ((uint32_t)ty0 << 10) | ((uint32_t)(tw - 1) << 20) |
+         ((uint32_t)(th - 1) << 26);
+}
+
 // Large splats in the backward: every tile a splat covers adds its sums to
 // the splat's record, and FP64 atomics to one address serialize in the L2.
 // A splat-view whose tile rectangle covers at least kBigTiles tiles takes a
@@ -78,6 +87,10 @@ struct sgs_ctx {
   float4 *rec = nullptr;          // [vn][3]: (px,py,A,B) (C,opa,spanx,spany) (r,g,b,mask)
   uint32_t *depth_key[2] = {nullptr, nullptr};
   uint32_t *depth_val[2] = {nullptr, nullptr};
+  // [vn] each: the splat's tile rectangle packed for the depth sort to carry
+  // (first column and row 10 bits each, width - 1 and height - 1 6 bits
+  // each), or kNoRect when it does not fit (then the record is gathered)
+  uint32_t *depth_rect[2] = {nullptr, nullptr};
   uint32_t *touched = nullptr;    // [vn] tiles per splat (0 = culled)
   uint4 *bin_splat = nullptr;     // [vn] (first tile id, width in tiles, Gaussian, pairs)
   uint4 *bin_rec = nullptr;       // [vn] the same records in depth order
@@ -230,7 +243,7 @@ hipError_t launch_exclusive_scan(sgs_ctx *c, const uint32_t *in, uint32_t *out,
 // returns the buffer index that holds the result in *which.
 hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2],
                              int64_t count, int bits, int *which, const uint32_t *dcount,
-                             int shift0 = 0, int cur0 = 0);
+                             int shift0 = 0, int cur0 = 0, uint32_t **vals2 = nullptr);
 hipError_t launch_bin_pairs(sgs_ctx *c);   // depth order -> pairs -> tile sort -> ranges
 hipError_t launch_depth_order(sgs_ctx *c); // depth sort + scan (writes d_pairs_total)
 // blend.hip

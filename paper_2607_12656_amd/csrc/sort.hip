@@ -353,13 +353,16 @@ __device__ __forceinline__ uint32_t scanned_offset(const uint32_t *__restrict__ 
 // The block's count of each digit (the offsets inside the block) comes from
 // the ranking itself.  h_scan: this thread's digit (= tid) entry of the
 // block's scanned histogram row, loaded by the caller ahead of its other work.
-template <int IT>
+// V2: a second value array rides along (vr2 -> vout2 through s_val2).
+template <int IT, bool V2>
 __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[IT],
-                                              const uint32_t (&vr)[IT], int64_t base,
+                                              const uint32_t (&vr)[IT],
+                                              const uint32_t (&vr2)[IT], int64_t base,
                                               int64_t count, int shift, int nb, uint32_t h_scan,
                                               uint32_t *__restrict__ kout,
-                                              uint32_t *__restrict__ vout, uint32_t *s_key,
-                                              uint32_t *s_val) {
+                                              uint32_t *__restrict__ vout,
+                                              uint32_t *__restrict__ vout2, uint32_t *s_key,
+                                              uint32_t *s_val, uint32_t *s_val2) {
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_loff[256];
   __shared__ uint32_t s_cnt[kWaves][256];
@@ -407,6 +410,7 @@ __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[IT],
       const uint32_t lp = s_loff[d] + s_cnt[wave][d] + rank[r];  // < kThreads * IT
       s_key[lp] = kr[r];
       s_val[lp] = vr[r];
+      if (V2) s_val2[lp] = vr2[r];
     }
   }
   __syncthreads();
@@ -418,37 +422,42 @@ __device__ __forceinline__ void scatter_block(const uint32_t (&kr)[IT],
     const uint32_t pos = s_base[d] + ((uint32_t)p - s_loff[d]);
     kout[pos] = k;
     vout[pos] = s_val[p];
+    if (V2) vout2[pos] = s_val2[p];
   }
 }
 
 // One workgroup per block of the capacity-sized grid (a loop over the live
 // blocks would need more registers than four workgroups per compute unit
 // leave); blocks past the live count return at once.
-template <int IT>
+template <int IT, bool V2>
 __global__ void __launch_bounds__(kThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-                uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                const uint32_t *__restrict__ vin2, uint32_t *__restrict__ kout,
+                uint32_t *__restrict__ vout, uint32_t *__restrict__ vout2,
                 int64_t count_static, const uint32_t *__restrict__ dcount, int shift, int nb,
                 const uint32_t *__restrict__ hist_scanned,
                 const uint32_t *__restrict__ digit_tot) {
   constexpr int TILE = kThreads * IT;
   __shared__ uint32_t s_key[TILE];
   __shared__ uint32_t s_val[TILE];
+  __shared__ uint32_t s_val2[V2 ? TILE : 1];
   const int64_t count = dcount ? (int64_t)*dcount : count_static;
   const int64_t blk = sgs_xcd_block_live(blockIdx.x, gridDim.x, (count + TILE - 1) / TILE);
   const int64_t base = blk * TILE;
   if (base >= count) return;
   // all loads of the block in flight at once, in the wave-segment layout
   const int64_t wbase = base + (int64_t)(threadIdx.x >> 6) * IT * 64 + (threadIdx.x & 63);
-  uint32_t kr[IT], vr[IT];
+  uint32_t kr[IT], vr[IT], vr2[IT];
 #pragma unroll
   for (int r = 0; r < IT; ++r) {
     const int64_t i = wbase + (int64_t)r * 64;
     kr[r] = i < count ? kin[i] : 0u;
     vr[r] = i < count ? vin[i] : 0u;
+    vr2[r] = V2 && i < count ? vin2[i] : 0u;
   }
   const uint32_t h_scan = scanned_offset(hist_scanned, digit_tot, blk);
-  scatter_block<IT>(kr, vr, base, count, shift, nb, h_scan, kout, vout, s_key, s_val);
+  scatter_block<IT, V2>(kr, vr, vr2, base, count, shift, nb, h_scan, kout, vout, vout2, s_key,
+                        s_val, s_val2);
 }
 
 // ---------------------------------------------------------------------------
@@ -478,20 +487,24 @@ __device__ __forceinline__ uint32_t super_tiles_met(const uint4 &b, uint32_t til
   return (uint32_t)(((r.tx1 >> 3) - (r.tx0 >> 3) + 1) * ((r.ty1 >> 3) - (r.ty0 >> 3) + 1));
 }
 
-// Binning records in depth order (the only gather of splat data in that
-// order; a splat whose sorted depth key is the invalid marker has no record
-// to read and gets an empty one), the item count of every splat (input of
+// Binning records in depth order, the item count of every splat (input of
 // the item offsets scan), and the pair count of every block of kTile splats
-// (their sum is the pair total; no per-splat pair offset is needed).
+// (their sum is the pair total; no per-splat pair offset is needed).  The
+// record is rebuilt from the splat index and the tile rectangle the depth
+// sort carried along; only a splat whose rectangle did not fit the packed
+// word has its record gathered (depth order is random in splat index, and
+// every such read fetches a whole cache line), and one whose sorted depth
+// key is the invalid marker gets an empty record.
 __global__ void __launch_bounds__(kThreads)
 k_gather_bins(const uint32_t *__restrict__ order, const uint32_t *__restrict__ dkey,
-              const uint4 *__restrict__ bin_splat, int64_t count, int GW,
-              uint32_t tiles_per_view, uint32_t *__restrict__ icnt, uint4 *__restrict__ brec,
+              const uint32_t *__restrict__ rect, const uint4 *__restrict__ bin_splat,
+              int64_t count, uint32_t n, int GW, uint32_t tiles_per_view,
+              uint32_t *__restrict__ icnt, uint4 *__restrict__ brec,
               uint32_t *__restrict__ psums) {
   __shared__ uint64_t s_sum[kWaves];
   const int64_t base = (int64_t)blockIdx.x * kTile;
   uint64_t acc = 0;
-  // eight gathers in flight at a time (each waits on two loads before it)
+  // eight records at a time (a gathered one waits on two loads before it)
   constexpr int kHalf = kItems / 2;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -501,7 +514,17 @@ k_gather_bins(const uint32_t *__restrict__ order, const uint32_t *__restrict__ d
       const int64_t i = base + (int64_t)(h * kHalf + k) * kThreads + threadIdx.x;
       // the record of an invalid splat, as the projection writes it
       b[k] = make_uint4(0u, 1u, 0u, 0u);
-      if (i < count && dkey[i] != 0xFFFFFFFFu) b[k] = bin_splat[order[i]];
+      if (i < count && dkey[i] != 0xFFFFFFFFu) {
+        const uint32_t sp = order[i], r = rect[i];
+        if (r != kNoRect) {
+          const uint32_t v = sp / n, tw = ((r >> 20) & 63u) + 1u, th = (r >> 26) + 1u;
+          b[k] = make_uint4(v * tiles_per_view + ((r >> 10) & 1023u) * (uint32_t)GW +
+                                (r & 1023u),
+                            tw, sp - v * n, tw * th);
+        } else {
+          b[k] = bin_splat[sp];
+        }
+      }
     }
 #pragma unroll
     for (int k = 0; k < kHalf; ++k) {
@@ -956,12 +979,17 @@ int64_t l2_chunks_for(int64_t cap, int64_t total_st) { return cap / kL2Items + t
 // than there are compute units.
 constexpr int64_t kSmallSort = (int64_t)1 << 22;
 constexpr int kSmallItems = 4;
-int64_t radix_tile(int64_t count) {
-  return count <= kSmallSort ? (int64_t)kThreads * kSmallItems : (int64_t)kTile;
+// With a second value array a large pass takes kV2Items per thread (three
+// 4096-word LDS arrays would leave two workgroups per compute unit).
+constexpr int kV2Items = 8;
+int64_t radix_tile(int64_t count, bool v2 = false) {
+  if (count <= kSmallSort) return (int64_t)kThreads * kSmallItems;
+  return v2 ? (int64_t)kThreads * kV2Items : (int64_t)kTile;
 }
 
+// (sized for the smaller of the tiles a sort of count elements may take)
 int64_t radix_hist_words(int64_t count) {
-  const int64_t tile = radix_tile(count);
+  const int64_t tile = radix_tile(count, true);
   const int64_t nb = (count + tile - 1) / tile;
   const int64_t ng = (nb + kChunk - 1) / kChunk;
   return 2 * nb * 256 + ng * 256 + 256 + 1;
@@ -1042,31 +1070,43 @@ unsigned resident_blocks(int64_t blocks) {
 // starts in buffer cur0 and *which receives the buffer holding the result.
 hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2], int64_t count,
                              int bits, int *which, const uint32_t *dcount, int shift0,
-                             int cur0) {
+                             int cur0, uint32_t **vals2) {
   int cur = cur0;
   *which = cur0;
   if (count <= 1 || shift0 >= bits) return hipSuccess;
-  const bool small = count <= kSmallSort;
+  const bool small = count <= kSmallSort, v2 = vals2 != nullptr;
+  const int64_t tile = radix_tile(count, v2);
   SortBufs b;
-  if (!sort_bufs(c, count, b, radix_tile(count))) return hipErrorInvalidValue;
-  const int64_t tile = radix_tile(count);
+  if (!sort_bufs(c, count, b, tile)) return hipErrorInvalidValue;
   for (int shift = shift0; shift < bits; shift += 8) {
     const int nb = min(8, bits - shift);  // digit bits of this pass
     if (small)
       k_radix_hist<kSmallItems><<<resident_blocks<k_radix_hist<kSmallItems>>(b.nb), kThreads, 0,
                                   c->stream>>>(keys[cur], count, dcount, shift, nb, b.hraw);
+    else if (v2)
+      k_radix_hist<kV2Items><<<resident_blocks<k_radix_hist<kV2Items>>(b.nb), kThreads, 0,
+                               c->stream>>>(keys[cur], count, dcount, shift, nb, b.hraw);
     else
       k_radix_hist<kItems><<<resident_blocks<k_radix_hist<kItems>>(b.nb), kThreads, 0,
                              c->stream>>>(keys[cur], count, dcount, shift, nb, b.hraw);
     const uint32_t *dtot = launch_digit_offsets(c, b, count, dcount, tile);
-    if (small)
-      k_radix_scatter<kSmallItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
-          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, nb,
-          b.hscan, dtot);
+    uint32_t *in2 = v2 ? vals2[cur] : nullptr, *out2 = v2 ? vals2[cur ^ 1] : nullptr;
+    if (small && v2)
+      k_radix_scatter<kSmallItems, true><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
+          keys[cur], vals[cur], in2, keys[cur ^ 1], vals[cur ^ 1], out2, count, dcount, shift,
+          nb, b.hscan, dtot);
+    else if (small)
+      k_radix_scatter<kSmallItems, false><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
+          keys[cur], vals[cur], nullptr, keys[cur ^ 1], vals[cur ^ 1], nullptr, count, dcount,
+          shift, nb, b.hscan, dtot);
+    else if (v2)
+      k_radix_scatter<kV2Items, true><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
+          keys[cur], vals[cur], in2, keys[cur ^ 1], vals[cur ^ 1], out2, count, dcount, shift,
+          nb, b.hscan, dtot);
     else
-      k_radix_scatter<kItems><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
-          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], count, dcount, shift, nb, b.hscan,
-          dtot);
+      k_radix_scatter<kItems, false><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
+          keys[cur], vals[cur], nullptr, keys[cur ^ 1], vals[cur ^ 1], nullptr, count, dcount,
+          shift, nb, b.hscan, dtot);
     cur ^= 1;
   }
   *which = cur;
@@ -1079,7 +1119,9 @@ hipError_t launch_depth_order(sgs_ctx *c) {
   int which = 0;
   {
     SgsProfScope ps(c, SGS_PROF_DEPTH_SORT);
-    hipError_t e = launch_radix_sort(c, c->depth_key, c->depth_val, c->vn, 32, &which, nullptr);
+    // the packed tile rectangles ride along as a second value
+    hipError_t e = launch_radix_sort(c, c->depth_key, c->depth_val, c->vn, 32, &which, nullptr,
+                                     0, 0, c->depth_rect);
     if (e != hipSuccess) return e;
   }
   c->depth_sorted_buf = which;
@@ -1091,8 +1133,8 @@ hipError_t launch_depth_order(sgs_ctx *c) {
   if (nb > c->scan_tmp_words) return hipErrorInvalidValue;
   if (nb > 0)
     k_gather_bins<<<(unsigned)nb, kThreads, 0, c->stream>>>(
-        c->depth_val[which], c->depth_key[which], c->bin_splat, c->vn, c->GW,
-        (uint32_t)c->tiles_per_view, tmp, c->bin_rec, c->scan_tmp);
+        c->depth_val[which], c->depth_key[which], c->depth_rect[which], c->bin_splat, c->vn,
+        (uint32_t)c->n, c->GW, (uint32_t)c->tiles_per_view, tmp, c->bin_rec, c->scan_tmp);
   // the pair total (with a fixed pair capacity also clamped to it)
   k_scan_sums<<<1, kThreads, 0, c->stream>>>(c->scan_tmp, nb, c->d_pairs_total, nullptr,
                                              c->fixed_cap ? c->cap_limit : -1);
