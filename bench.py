@@ -94,12 +94,13 @@ def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int, items: in
     if g == "preprocess":         # splat record 48 B, depth key / value / count 12 B,
         # binning record 16 B per splat
         return "hbm", n * (NCH * 4 + 1) + V * n * (48 + 12 + 16), "B"
-    if g == "depth_sort":         # one read + one write of key and value
-        return "hbm", V * n * 16, "B"
-    if g == "scan":               # sorted key and index read (4 + 4), binning record
-        # gathered and written in depth order (16 + 16), item count written (4), item
-        # offsets scanned (4 + 4 read, 4 written)
-        return "hbm", V * n * 56, "B"
+    if g == "depth_sort":         # four 8-bit passes, each one read + one write of key,
+        # value and the packed tile rectangle carried along
+        return "hbm", V * n * 4 * 24, "B"
+    if g == "scan":               # sorted key, index and rectangle read (4 + 4 + 4), binning
+        # record written in depth order (16), item count written (4), item offsets scanned
+        # (4 + 4 read, 4 written); the few records gathered instead are not counted
+        return "hbm", V * n * 44, "B"
     if g == "duplicate":          # every pair written once (4 B); per item its key and
         # Gaussian index read (8 B)
         return "hbm", P * 4 + items * 8, "B"
