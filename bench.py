@@ -92,8 +92,8 @@ def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int, items: in
     if g == "fakequant":          # statistics and mask (the projection quantizes)
         return "hbm", n * (NCH * 4 + 1 + 1 + 4), "B"
     if g == "preprocess":         # splat record 48 B, depth key / value / count 12 B,
-        # binning record 16 B per splat
-        return "hbm", n * (NCH * 4 + 1) + V * n * (48 + 12 + 16), "B"
+        # packed tile rectangle 4 B per splat
+        return "hbm", n * (NCH * 4 + 1) + V * n * (48 + 12 + 4), "B"
     if g == "depth_sort":         # four 8-bit passes, each one read + one write of key,
         # value and the packed tile rectangle carried along
         return "hbm", V * n * 4 * 24, "B"

@@ -148,8 +148,7 @@ k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
     if (!p.valid) {
       depth_key[s] = 0xFFFFFFFFu;
       touched[s] = 0;
-      bins[s] = make_uint4(0u, 1u, 0u, 0u);
-      rect[s] = kNoRect;
+      rect[s] = kNoRect;  // (an invalid splat's record is never read)
       rec[3 * s] = make_float4(0.f, 0.f, 0.f, 0.f);
       rec[3 * s + 1] = make_float4(0.f, 0.f, __int_as_float(-1), __int_as_float(-1));
       rec[3 * s + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -159,10 +158,15 @@ k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
     const int tw = p.x1 / TW - p.x0 / TW + 1, th = p.y1 / TH - p.y0 / TH + 1;
     touched[s] = (uint32_t)(tw * th);
     // binning record: first tile id, rectangle width in tiles, Gaussian, pairs
-    bins[s] = make_uint4((uint32_t)(v * tiles_per_view) + (uint32_t)((p.y0 / TH) * GW + p.x0 / TW),
-                         (uint32_t)tw, (uint32_t)i, (uint32_t)(tw * th));
-    // the same rectangle in one word, which the depth sort carries along
-    rect[s] = sgs_pack_rect(p.x0 / TW, p.y0 / TH, tw, th);
+    // the tile rectangle in one word, which the depth sort carries along;
+    // only a rectangle that does not fit it gets the full binning record
+    // (first tile id, width in tiles, Gaussian, pairs), gathered later
+    const uint32_t packed = sgs_pack_rect(p.x0 / TW, p.y0 / TH, tw, th);
+    rect[s] = packed;
+    if (packed == kNoRect)
+      bins[s] = make_uint4((uint32_t)(v * tiles_per_view) +
+                               (uint32_t)((p.y0 / TH) * GW + p.x0 / TW),
+                           (uint32_t)tw, (uint32_t)i, (uint32_t)(tw * th));
     const float A = p.c / p.det, B = -p.b / p.det, C = p.a / p.det;
     float col[3];
     bool cl[3];

@@ -92,7 +92,8 @@ struct sgs_ctx {
   // each), or kNoRect when it does not fit (then the record is gathered)
   uint32_t *depth_rect[2] = {nullptr, nullptr};
   uint32_t *touched = nullptr;    // [vn] tiles per splat (0 = culled)
-  uint4 *bin_splat = nullptr;     // [vn] (first tile id, width in tiles, Gaussian, pairs)
+  uint4 *bin_splat = nullptr;     // [vn] (first tile id, width in tiles, Gaussian, pairs),
+                                  // written only for rectangles depth_rect cannot hold
   uint4 *bin_rec = nullptr;       // [vn] the same records in depth order
   double *splat_grad = nullptr;   // [vn][SGS_SGRAD] per-splat gradient sums (FP64 atomics)
   uint32_t *big_idx = nullptr;    // [vn] replica slot of a large splat (see kBigTiles)

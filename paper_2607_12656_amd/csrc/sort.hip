@@ -769,31 +769,53 @@ k_l2_count(const uint32_t *__restrict__ cfirst, uint32_t nst, const uint2 *__res
   }
 }
 
-// Per super-tile (64 threads, thread t = tile t): the chunk counts become the
+// Per super-tile (four waves, lane t = tile t): the chunk counts become the
 // tile's pairs in earlier chunks (in place), and the tile's total goes to
-// tile_cnt (tiles past the image edge have no pairs and no entry).
-__global__ void __launch_bounds__(64)
+// tile_cnt (tiles past the image edge have no pairs and no entry).  Wave w
+// takes the w-th quarter of the super-tile's chunks: it sums them, the four
+// sums give each quarter its start, and the wave rewrites its quarter.
+constexpr int kL2ScanWaves = 4;
+__global__ void __launch_bounds__(64 * kL2ScanWaves)
 k_l2_scan(const uint32_t *__restrict__ cfirst, uint32_t *__restrict__ cnt, int GW, int GH,
           int SGW, uint32_t st_per_view, uint32_t tiles_per_view, uint32_t *__restrict__ tile_cnt) {
+  __shared__ uint32_t s_part[kL2ScanWaves][64];
   const uint32_t g = blockIdx.x;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t q0 = cfirst[g], q1 = cfirst[g + 1];
-  uint32_t run = 0;
-  for (uint32_t qb = q0; qb < q1; qb += 32) {
+  const uint32_t per = (q1 - q0 + kL2ScanWaves - 1) / kL2ScanWaves;
+  const uint32_t a = min(q1, q0 + per * (uint32_t)w), e = min(q1, a + per);
+  uint32_t part = 0;
+  for (uint32_t qb = a; qb < e; qb += 32) {
     uint32_t c[32];
 #pragma unroll
-    for (int k = 0; k < 32; ++k) c[k] = qb + k < q1 ? cnt[(int64_t)(qb + k) * 64 + t] : 0u;
+    for (int k = 0; k < 32; ++k) c[k] = qb + k < e ? cnt[(int64_t)(qb + k) * 64 + t] : 0u;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) part += c[k];
+  }
+  s_part[w][t] = part;
+  __syncthreads();
+  uint32_t run = 0, total = 0;
+#pragma unroll
+  for (int k = 0; k < kL2ScanWaves; ++k) {
+    if (k < w) run += s_part[k][t];
+    total += s_part[k][t];
+  }
+  for (uint32_t qb = a; qb < e; qb += 32) {
+    uint32_t c[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) c[k] = qb + k < e ? cnt[(int64_t)(qb + k) * 64 + t] : 0u;
 #pragma unroll
     for (int k = 0; k < 32; ++k)
-      if (qb + k < q1) {
+      if (qb + k < e) {
         cnt[(int64_t)(qb + k) * 64 + t] = run;
         run += c[k];
       }
   }
+  if (w != 0) return;
   const uint32_t v = g / st_per_view, gs = g - v * st_per_view;
   const uint32_t sy = gs / (uint32_t)SGW, sx = gs - sy * (uint32_t)SGW;
   const int tx = 8 * (int)sx + (t & 7), ty = 8 * (int)sy + (t >> 3);
-  if (tx < GW && ty < GH) tile_cnt[(int64_t)v * tiles_per_view + (int64_t)ty * GW + tx] = run;
+  if (tx < GW && ty < GH) tile_cnt[(int64_t)v * tiles_per_view + (int64_t)ty * GW + tx] = total;
 }
 
 // Tile ranges from the tile offsets, clamped to the pairs the buffer holds
@@ -1177,8 +1199,8 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
       k_l2_count<<<resident_blocks<k_l2_count>(chunks), kThreads, 0, c->stream>>>(
           c->chunk_first, nst, c->st_ranges, c->tile_key[which], c->SGW, spv, c->l2_cnt,
           c->l2_wcnt);
-    k_l2_scan<<<nst, 64, 0, c->stream>>>(c->chunk_first, c->l2_cnt, c->GW, c->GH, c->SGW, spv,
-                                         tpv, c->tile_cnt);
+    k_l2_scan<<<nst, 64 * kL2ScanWaves, 0, c->stream>>>(c->chunk_first, c->l2_cnt, c->GW, c->GH,
+                                                         c->SGW, spv, tpv, c->tile_cnt);
   }
   {
     SgsProfScope ps(c, SGS_PROF_RANGES);
