@@ -58,6 +58,7 @@ VALU_ISSUE_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 NCH = 59
+SH_EVERY = 16      # higher-SH coefficients updated every 16th iteration (Sec. 4.1)
 # FP32 work per evaluation (counted as VALU operations, the exponential as 4):
 # forward 22 + 4 (support 4, offsets 2, quadratic 6, alpha 2, thresholds 2,
 # T test 2, colour 3, T 1); backward 70 + 4 (recompute, T recovery, dalpha,
@@ -81,13 +82,15 @@ def _decided(decisions, use0, i):
 
 
 def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int, items: int = 0,
-               tiles: int = 0, st: int = 1, kept: int | None = None):
+               tiles: int = 0, st: int = 1, kept: int | None = None, sh_every: int = 1):
     """(bound, algorithmic amount per launch, unit) of one kernel group; E is
     the count of evaluations the blend performs (after its reach test),
     items the (splat, super-tile) items of the binning's first level, tiles
     and st the tile and super-tile counts, kept the Gaussians the mask keeps
     (the others have zero parameter gradients, which the sparse Adam
-    skips)."""
+    skips), sh_every the period of the higher-SH updates (their 45 gradient
+    rows are written and read only in those iterations)."""
+    rows = (NCH - 45) + 45 / sh_every
     pix = V * W * H
     if g == "fakequant":          # statistics and mask (the projection quantizes)
         return "hbm", n * (NCH * 4 + 1 + 1 + 4), "B"
@@ -118,14 +121,14 @@ def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int, items: in
         return "hbm", V * n * (80 + 4), "B"
     if g == "blend_bwd":
         return "alu", E * FLOP_PER_EVAL_BWD, "FLOP"
-    if g == "preprocess_bwd":
-        return "hbm", n * (NCH * 4 * 2 + 4 + 4) + V * n * 80, "B"
+    if g == "preprocess_bwd":     # parameters read, gradient rows written, mask and score
+        # gradients written; per view the 80-byte splat gradient record read
+        return "hbm", int(n * (NCH * 4 + rows * 4 + 4 + 4) + V * n * 80), "B"
     if g == "fakequant_bwd":
         return "hbm", NCH * 8 * -(-n // 128), "B"
-    if g == "adam":               # per iteration of the 16-iteration period: the rows
-        # updated (14, and the 45 higher-SH rows every 16th) read as gradients for every
-        # Gaussian, and y, m, v read + written for the kept ones; scores (4 B x 7)
-        rows = (NCH - 45) + 45 / 16
+    if g == "adam":               # per iteration of the higher-SH period: the rows
+        # updated (14, and the 45 higher-SH rows every sh_every-th) read as gradients for
+        # every Gaussian, and y, m, v read + written for the kept ones; scores (4 B x 7)
         upd = n if kept is None else kept
         return "hbm", int(n * rows * 4 + upd * rows * 24 + n * 4 * 7), "B"
     if g in ("mlp_fwd", "mlp_bwd"):
@@ -133,8 +136,9 @@ def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int, items: in
     return "hbm", 0, "B"
 
 
-def roofline(g, ms, n, V, P, E, W, H, traffic_key=None, items=0, tiles=0, st=1, kept=None):
-    bound, amount, unit = group_work(g, n, V, P, E, W, H, items, tiles, st, kept)
+def roofline(g, ms, n, V, P, E, W, H, traffic_key=None, items=0, tiles=0, st=1, kept=None,
+             sh_every=1):
+    bound, amount, unit = group_work(g, n, V, P, E, W, H, items, tiles, st, kept, sh_every)
     dur = ms * 1e-3
     if unit == "B":
         achieved, peak, ru = amount / dur / 1e9, HBM_PEAK_GBS, "GB/s"
@@ -338,7 +342,8 @@ def bench_formation(args, sc, ctx, stream, dev, t):
     runs = {}
     for name, mlp in (("learned", (packed, theta)), ("plain", None)):
         p, q, s = p0.clone(), q0.clone(), s0.clone()
-        f = Formation(rd, p, q, s, target, lam, mask_mode=1, seed=5, mlp=mlp)
+        f = Formation(rd, p, q, s, target, lam, mask_mode=1, seed=5, mlp=mlp,
+                      sh_every=SH_EVERY)
         e_first = f.check_rate()                # the fallback rule's check before the run
         for _ in range(W):
             f.iterate()
@@ -487,10 +492,11 @@ def bench_formation(args, sc, ctx, stream, dev, t):
     dom = max(L["kernel_ms"], key=L["kernel_ms"].get)
     roof = roofline(dom, L["kernel_ms"][dom], sc.n, sc.views, L["pairs_last"],
                     L["evals_after_reach_test"] // K, sc.width, sc.height,
-                    traffic_key=f"c5:{dom}", items=L["items_last"], **geo)
+                    traffic_key=f"c5:{dom}", items=L["items_last"], sh_every=SH_EVERY, **geo)
     groups = {g: roofline(g, ms, sc.n, sc.views, L["pairs_last"],
                           L["evals_after_reach_test"] // K, sc.width, sc.height,
-                          items=L["items_last"], kept=L["kept_last"], **geo)
+                          items=L["items_last"], kept=L["kept_last"], sh_every=SH_EVERY,
+                          **geo)
               for g, ms in L["kernel_ms"].items()}
     line = {
         "metric": METRIC, "value": L["value"], "unit": "Gaussian-pixel evals/s", "n_gpus": 1,

@@ -235,6 +235,16 @@ sgs_status sgs_autotune(sgs_ctx *ctx, const float *params, const float *qstep,
  * without counting.  Takes effect at the next render. */
 sgs_status sgs_set_eval_count_mode(sgs_ctx *ctx, int32_t mode);
 
+/* Whether the fused backward (sgs_quant_render_bwd) and sgs_rate_mlp_bwd
+ * write the gradient rows of the higher SH coefficients (channels 6-50,
+ * degrees 1-3) into grad_params: on (1, the default) they do; off (0) they
+ * leave those rows of grad_params untouched, for a step whose optimizer
+ * update skips them (the separated higher-SH schedule of Sec. 4.1, as
+ * sgs_adam_step with sh_rest = 0).  Every other output, the step-size
+ * gradient included, is the same either way.  Takes effect at the next
+ * backward call (a captured graph keeps the value it was captured with). */
+sgs_status sgs_set_grad_sh_rest(sgs_ctx *ctx, int32_t on);
+
 /* Host-side query (synchronizes the stream): pairs of the last render and the
  * device flags word of `stats` (may be NULL).  Returns SGS_EINVAL when the
  * flags report an invalid step size, SGS_ECAPACITY (once, then cleared) when

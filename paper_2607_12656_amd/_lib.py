@@ -98,6 +98,7 @@ _SIGS = {
     "sgs_quant_render_bwd": [P, P, P, P, I32, P, P, P, P, P, P, P, P, P],
     "sgs_query": [P, P, C.POINTER(I64), C.POINTER(U64)],
     "sgs_set_eval_count_mode": [P, I32],
+    "sgs_set_grad_sh_rest": [P, I32],
     "sgs_query_items": [P, C.POINTER(I64)],
     "sgs_autotune": [P, P, P, P, P, I32, P, P],
     "sgs_copy_structure": [P, P, P, I64, P, P, P, P],
@@ -328,6 +329,11 @@ class Context:
         """0: the method's in-span evaluations (default); 1: the evaluations
         the timed blend performs after its reach test."""
         self._check(self.L.sgs_set_eval_count_mode(self.h, int(mode)), self.h)
+
+    def set_grad_sh_rest(self, on: bool):
+        """Whether the fused and learned-rate backward passes write the
+        higher-SH gradient rows (channels 6-50) of grad_params."""
+        self._check(self.L.sgs_set_grad_sh_rest(self.h, 1 if on else 0), self.h)
 
     def query(self, stats=None):
         pairs = I64()

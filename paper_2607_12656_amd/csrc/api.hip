@@ -966,6 +966,13 @@ sgs_status sgs_set_eval_count_mode(sgs_ctx *c, int32_t mode) {
   return SGS_OK;
 }
 
+sgs_status sgs_set_grad_sh_rest(sgs_ctx *c, int32_t on) {
+  if (!c) return SGS_EINVAL;
+  if (on != 0 && on != 1) return fail(c, SGS_EINVAL, "set_grad_sh_rest: on must be 0 or 1");
+  c->grad_sh_rest = on != 0;
+  return SGS_OK;
+}
+
 sgs_status sgs_query(sgs_ctx *c, const uint64_t *stats, int64_t *pairs_last, uint64_t *flags) {
   if (!c) return SGS_EINVAL;
   SGS_HIP(hipSetDevice(c->device), "hipSetDevice");

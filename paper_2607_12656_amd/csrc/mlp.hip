@@ -368,7 +368,7 @@ k_mlp_rate_bwd(int64_t n, int64_t npad, int64_t n_hat, float weight, float tau, 
                const float *__restrict__ soft, const float *__restrict__ fsave,
                const uint4 *__restrict__ signs, float *__restrict__ gparams,
                float *__restrict__ gscore, float *__restrict__ gmask,
-               double *__restrict__ qpartial) {
+               double *__restrict__ qpartial, int sh_rows) {
   __shared__ MlpLdsB L;
   __shared__ float s_min[SGS_NCH];
   __shared__ float s_rq[SGS_NCH];
@@ -433,8 +433,9 @@ k_mlp_rate_bwd(int64_t n, int64_t npad, int64_t n_hat, float weight, float tau, 
       for (int i = 0; i < 16; ++i) {
         const int j = 32 * t + drow(i, lane);
         const bool ok = valid && j < SGS_NCH;
+        const bool row = ok && (sh_rows || j < SGS_CH_REST || j >= SGS_CH_REST_END);
         yv[t][i] = ok ? y[j * npad + r] : 0.0f;
-        old[t][i] = ok ? gparams[j * npad + r] : 0.0f;
+        old[t][i] = row ? gparams[j * npad + r] : 0.0f;
       }
     nxt = row_in(tile + stride);
     if (__ballot(m) == 0ull) continue;
@@ -500,7 +501,8 @@ k_mlp_rate_bwd(int64_t n, int64_t npad, int64_t n_hat, float weight, float tau, 
           if (t == 0 || j < SGS_NCH) {
             const float uu = (yv[t][i] - s_min[j]) * s_rq[j];
             const float gp = dx[t][i] * __builtin_amdgcn_rcpf(1.0f + uu) * inv_ln2 * s_rq[j];
-            gparams[j * npad + r] = old[t][i] + gp;
+            if (sh_rows || j < SGS_CH_REST || j >= SGS_CH_REST_END)
+              gparams[j * npad + r] = old[t][i] + gp;
             gq[16 * t + i] -= gp * uu;
           }
         }
@@ -940,7 +942,8 @@ hipError_t launch_mlp_rate_bwd(sgs_ctx *c, const void *packed, const float *thet
   k_mlp_rate_bwd<<<nb, kThreads, 0, c->stream>>>(c->n, c->npad, c->n_hat, weight, c->tau, mode,
                                                  (const bf16x4 *)packed, theta, params, q, stats,
                                                  hard, soft, c->mlp_f, c->mlp_signs, gparams,
-                                                 gscore, gmask, c->red_tmp);
+                                                 gscore, gmask, c->red_tmp,
+                                                 c->grad_sh_rest ? 1 : 0);
   k_mlp_q_finish<<<SGS_NCH, 256, 0, c->stream>>>(nb, c->red_tmp, gqstep);
   return hipGetLastError();
 }

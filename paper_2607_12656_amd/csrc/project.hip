@@ -199,7 +199,7 @@ k_preprocess_bwd(int64_t n, int64_t npad, int V, int W, int H,
                  const double *__restrict__ sgrad, float *__restrict__ gout,
                  float *__restrict__ gmask, double *__restrict__ partial, int mode, float tau,
                  const float *__restrict__ soft, const float *__restrict__ rate_grad,
-                 float *__restrict__ gscore) {
+                 float *__restrict__ gscore, int sh_rows) {
   __shared__ float s_q[FUSED ? 64 : 1], s_rq[FUSED ? 64 : 1];
   // residuals k q - y of the block's Gaussians, kept for the end
   __shared__ float s_r[FUSED ? SGS_NCH : 1][kPThreads];
@@ -379,7 +379,8 @@ k_preprocess_bwd(int64_t n, int64_t npad, int V, int W, int H,
   }
   if (live) {
 #pragma unroll
-    for (int j = 0; j < SGS_NCH; ++j) gout[j * npad + i] = g[j];
+    for (int j = 0; j < SGS_NCH; ++j)
+      if (sh_rows || j < SGS_CH_REST || j >= SGS_CH_REST_END) gout[j * npad + i] = g[j];
     gmask[i] = gm;
     if (FUSED && gscore) {
       float gs = 0.0f;
@@ -442,7 +443,7 @@ hipError_t launch_preprocess_bwd(sgs_ctx *c, const float *qparams, float *grad_q
   SgsProfScope ps(c, SGS_PROF_PREPROCESS_BWD);
   k_preprocess_bwd<false><<<sgs_blocks(c->n, kPThreads), kPThreads, 0, c->stream>>>(
       c->n, c->npad, c->V, c->W, c->H, c->d_cams, qparams, nullptr, c->touched, c->splat_grad,
-      grad_qparams, grad_mask, nullptr, 0, 1.0f, nullptr, nullptr, nullptr);
+      grad_qparams, grad_mask, nullptr, 0, 1.0f, nullptr, nullptr, nullptr, 1);
   return hipGetLastError();
 }
 
@@ -456,6 +457,7 @@ hipError_t launch_preprocess_bwd_fused(sgs_ctx *c, const float *params, const fl
   *nblocks = nb;
   k_preprocess_bwd<true><<<nb, kPThreads, 0, c->stream>>>(
       c->n, c->npad, c->V, c->W, c->H, c->d_cams, params, q, c->touched, c->splat_grad,
-      grad_params, grad_mask, partial, mode, c->tau, soft, rate_grad, grad_score);
+      grad_params, grad_mask, partial, mode, c->tau, soft, rate_grad, grad_score,
+      c->grad_sh_rest ? 1 : 0);
   return hipGetLastError();
 }

@@ -335,7 +335,8 @@ __global__ void __launch_bounds__(kQThreads)
 k_fakequant_bwd_finish(int64_t nblocks, const double *__restrict__ partial, int64_t jstride,
                        int64_t bstride, const float *__restrict__ q,
                        const float *__restrict__ rate_grad, const uint64_t *__restrict__ stats,
-                       int64_t npad, float *__restrict__ gparams, float *__restrict__ gqstep) {
+                       int64_t npad, float *__restrict__ gparams, float *__restrict__ gqstep,
+                       int sh_rows) {
   __shared__ double s_w[kQWaves];
   const int j = blockIdx.x;
   // eight loads in flight per thread (a loop-carried sum would wait on each)
@@ -358,8 +359,10 @@ k_fakequant_bwd_finish(int64_t nblocks, const double *__restrict__ partial, int6
     tot += (double)rate_grad[128 + j];
     const uint32_t imin = (uint32_t)(stats[j] & 0xFFFFFFFFull);
     const uint32_t imax = 0xFFFFFFFFu - (uint32_t)(stats[SGS_NCH + j] & 0xFFFFFFFFull);
-    gparams[j * npad + imax] += rate_grad[j];
-    gparams[j * npad + imin] += rate_grad[64 + j];
+    if (sh_rows || j < SGS_CH_REST || j >= SGS_CH_REST_END) {
+      gparams[j * npad + imax] += rate_grad[j];
+      gparams[j * npad + imin] += rate_grad[64 + j];
+    }
   }
   gqstep[j] = (float)tot;
 }
@@ -431,7 +434,7 @@ hipError_t launch_fakequant_bwd(sgs_ctx *c, const float *params, const float *q,
   k_fakequant_bwd<<<dim3(nb, SGS_NCH), kQThreads, 0, c->stream>>>(c->n, c->npad, params, q,
                                                                   gq_in, gparams, c->red_tmp);
   k_fakequant_bwd_finish<<<SGS_NCH, kQThreads, 0, c->stream>>>(
-      nb, c->red_tmp, 1, SGS_NCH, q, rate_grad, stats, c->npad, gparams, gqstep);
+      nb, c->red_tmp, 1, SGS_NCH, q, rate_grad, stats, c->npad, gparams, gqstep, 1);
   k_score_bwd<<<sgs_blocks(c->n, 256), 256, 0, c->stream>>>(c->n, mode, c->tau, soft, gmask_in,
                                                             rate_grad, gscore);
   return hipGetLastError();
@@ -443,6 +446,7 @@ hipError_t launch_quant_bwd_finish(sgs_ctx *c, int64_t nblocks, const double *pa
                                    float *gparams, float *gqstep) {
   SgsProfScope ps(c, SGS_PROF_FAKEQUANT_BWD);
   k_fakequant_bwd_finish<<<SGS_NCH, kQThreads, 0, c->stream>>>(
-      nblocks, partial, jstride, bstride, q, rate_grad, stats, c->npad, gparams, gqstep);
+      nblocks, partial, jstride, bstride, q, rate_grad, stats, c->npad, gparams, gqstep,
+      c->grad_sh_rest ? 1 : 0);
   return hipGetLastError();
 }

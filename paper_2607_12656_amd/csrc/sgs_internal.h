@@ -14,6 +14,7 @@
 #define SGS_CH_MU 0
 #define SGS_CH_DC 3
 #define SGS_CH_REST 6
+#define SGS_CH_REST_END 51  // one past the last higher-SH channel
 #define SGS_CH_OPA 51
 #define SGS_CH_SCALE 52
 #define SGS_CH_ROT 55
@@ -77,6 +78,7 @@ struct sgs_ctx {
   bool deterministic = false;     // sgs_options.deterministic: fixed-point gradient sums
   uint64_t *det_acc = nullptr;    // [vn][SGS_SGRAD][3] fixed-point accumulators (that mode)
   int count_mode = 0;             // sgs_set_eval_count_mode
+  bool grad_sh_rest = true;       // sgs_set_grad_sh_rest
   bool scene_set = false;
   bool rendered = false;
   sgs_camera *d_cams = nullptr;

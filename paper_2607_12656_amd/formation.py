@@ -151,6 +151,9 @@ class Formation:
         c.l1_loss(rd.image, self.target, rd.loss, rd.dimage, 1.0 - w)
         if w > 0.0:
             c.ssim_loss(rd.image, self.target, w, rd.loss_ssim, rd.dimage)
+        # the higher-SH gradient rows only in the steps whose update takes them
+        sh_rest = k % self.sh_every == 0
+        c.set_grad_sh_rest(sh_rest)
         c.quant_render_bwd(p, q, rd.soft, mm, None if learned else rd.rate_grad,
                            None if learned else rd.stats, rd.final_T, rd.last, rd.dimage,
                            rd.grad_qparams, rd.grad_q, rd.grad_score, rd.grad_mask)
@@ -161,8 +164,8 @@ class Formation:
             c.rate_variant_bwd(p, rd.grad_qparams)
         c.adam_step(self.lr, k + 1, p, self.pm, self.pv, rd.grad_qparams, q, self.qm, self.qv,
                     rd.grad_q, s, self.sm, self.sv, rd.grad_score, lr_q=self.lr_q,
-                    lr_score=self.lr_score, sh_rest=(k % self.sh_every == 0),
-                    sparse=self.sparse)
+                    lr_score=self.lr_score, sh_rest=sh_rest, sparse=self.sparse)
+        c.set_grad_sh_rest(True)
         self.k += 1
 
     def prune(self, pair_capacity: int = 0) -> int:

@@ -194,3 +194,42 @@ def test_length_ordered_schedules_match_per_tile(gctx, dev, case):
     ga, gb = a["gparams"][:, :n].astype(np.float64), b["gparams"][:, :n].astype(np.float64)
     assert np.linalg.norm(ga - gb) <= 1e-5 * np.linalg.norm(ga)
     assert np.linalg.norm(a["gmask"] - b["gmask"]) <= 1e-5 * np.linalg.norm(a["gmask"])
+
+
+def test_fused_backward_skips_higher_sh_rows(gctx, dev):
+    """With the higher-SH gradient rows switched off (a step whose Adam update
+    skips channels 6-50), the fused backward leaves those rows of grad_params
+    as they were and writes every other output bit for bit as with them on;
+    the step-size gradient still takes all channels."""
+    from paper_2607_12656_amd.rd import RDStep
+    sc = synth.make_tiny(1500, 120, 90, seed=24)
+    rd = RDStep(gctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height)
+    params, q, score = T(sc.params, dev), T(sc.qstep, dev), T(sc.score, dev)
+    target = T(sc.target, dev)
+    c = gctx
+    c.quant_render_fwd(params, q, score, 1, None, 5, 9, rd.hard, rd.soft, rd.stats, rd.image,
+                       rd.final_T, rd.last)
+    c.rate_proxy(rd.stats, q, 0.5, rd.rate3, rd.rate_grad)
+    c.l1_loss(rd.image, target, rd.loss, rd.dimage)
+    sentinel = -1234.5
+    outs = []
+    try:
+        for on in (True, False):
+            gp = torch.full_like(params, sentinel)
+            gq, gs = torch.empty_like(q), torch.empty_like(score)
+            gm = torch.empty(sc.n, dtype=torch.float32, device=dev)
+            c.set_grad_sh_rest(on)
+            c.quant_render_bwd(params, q, rd.soft, 1, rd.rate_grad, rd.stats, rd.final_T,
+                               rd.last, rd.dimage, gp, gq, gs, gm)
+            torch.cuda.synchronize()
+            outs.append([x.cpu().numpy().copy() for x in (gp, gq, gs, gm)])
+    finally:
+        c.set_grad_sh_rest(True)
+    (pa, qa, sa, ma), (pb, qb, sb, mb) = outs
+    n, rest = sc.n, np.r_[6:51]
+    keep = np.setdiff1d(np.arange(pa.shape[0]), rest)
+    assert np.array_equal(pa[keep, :n].view(np.uint32), pb[keep, :n].view(np.uint32))
+    assert np.all(pb[rest, :n] == np.float32(sentinel)), "higher-SH rows were written"
+    assert not np.any(pa[rest, :n] == np.float32(sentinel)), "higher-SH rows were skipped"
+    for a, b in ((qa, qb), (sa, sb), (ma, mb)):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))

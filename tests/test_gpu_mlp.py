@@ -273,3 +273,45 @@ def test_feature_rows_match_oracle(orc, mlp, gctx, dev):
     assert np.all(np.abs(ref64[diff] - mid[diff]) <= 1e-5 * np.abs(ref64[diff]) + 1e-30), \
         "a differing feature is not at a BF16 rounding boundary"
     assert np.all(g[:, 59:] == 0)
+
+
+def test_learned_rate_backward_skips_higher_sh_rows(mlp, gctx, dev):
+    """The learned-rate backward with the higher-SH gradient rows off leaves
+    those rows of grad_params untouched and adds into every other row as with
+    them on; the step-size and mask gradients are unchanged."""
+    from paper_2607_12656_amd.rd import RDStep
+    sc = synth.make_tiny(4000, 32, 32, seed=31)
+    q = synth.learnable_qsteps(32)
+    theta = T(flat(random_weights(mlp, 33), mlp), dev)
+    packed = torch.empty(98304 // 4, dtype=torch.int32, device=dev)
+    gctx.rate_mlp_pack(theta, packed)
+    rd = RDStep(gctx, sc.n, sc.npad, sc.n_hat, sc.cams, sc.width, sc.height)
+    params, qd = T(sc.params, dev), T(q, dev)
+    gctx.fakequant_prune(params, qd, None, 0, T(sc.given_mask, dev), 0, 0, rd.qparams, rd.hard,
+                         rd.soft, rd.stats)
+    R = torch.empty(1, dtype=torch.float32, device=dev)
+    gctx.rate_mlp_fwd(packed, theta, params, qd, rd.stats, rd.hard, R, None)
+    g0 = torch.randn(params.shape, generator=torch.Generator().manual_seed(34)).to(dev)
+    outs = []
+    try:
+        for on in (True, False):
+            gp = g0.clone()
+            gq = torch.zeros(NCH, dtype=torch.float32, device=dev)
+            gm = torch.zeros(sc.n, dtype=torch.float32, device=dev)
+            gctx.set_grad_sh_rest(on)
+            gctx.rate_mlp_bwd(packed, theta, params, qd, rd.stats, rd.hard, rd.soft, 0, 0.7,
+                              gp, gq, None, gm)
+            torch.cuda.synchronize()
+            outs.append([x.cpu().numpy().copy() for x in (gp, gq, gm)])
+    finally:
+        gctx.set_grad_sh_rest(True)
+    (pa, qa, ma), (pb, qb, mb) = outs
+    n, rest = sc.n, np.r_[6:51]
+    keep = np.setdiff1d(np.arange(pa.shape[0]), rest)
+    init = g0.cpu().numpy()
+    assert np.array_equal(pa[keep, :n].view(np.uint32), pb[keep, :n].view(np.uint32))
+    assert np.array_equal(pb[rest, :n].view(np.uint32), init[rest, :n].view(np.uint32))
+    assert not np.array_equal(pa[rest, :n], init[rest, :n]), "rows were not added to"
+    assert np.array_equal(ma.view(np.uint32), mb.view(np.uint32))
+    d = np.abs(qa.astype(np.float64) - qb).max()
+    assert d <= 1e-6 * np.abs(qa).max(), f"grad q {d:.3e}"
