@@ -61,7 +61,6 @@ void free_scene(sgs_ctx *c) {
   dfree(c->st_ranges);
   dfree(c->chunk_first);
   dfree(c->l2_cnt);
-  dfree(c->l2_wcnt);
   c->l2_chunks = 0;
   dfree(c->tile_cnt);
   dfree(c->tile_start);
@@ -109,7 +108,6 @@ hipError_t grow_pairs(sgs_ctx *c, int64_t P) {
   dfree(c->blk_start);
   c->blk_start_words = 0;
   dfree(c->l2_cnt);
-  dfree(c->l2_wcnt);
   c->l2_chunks = 0;
   c->pair_cap = 0;
   for (int k = 0; k < 2; ++k) {
@@ -124,8 +122,6 @@ hipError_t grow_pairs(sgs_ctx *c, int64_t P) {
   c->blk_start_words = nbs;
   const int64_t chunks = l2_chunks_for(cap, c->total_st);
   eb = dalloc(&c->l2_cnt, chunks * 64);
-  if (eb != hipSuccess) return eb;
-  eb = dalloc(&c->l2_wcnt, chunks * 4 * 64);
   if (eb != hipSuccess) return eb;
   c->l2_chunks = chunks;
   const int64_t hist = radix_hist_words(cap);

@@ -112,7 +112,6 @@ struct sgs_ctx {
   uint2 *st_ranges = nullptr;     // [total_st] item range of every super-tile
   uint32_t *chunk_first = nullptr;  // [total_st + 1] first item chunk of every super-tile
   uint32_t *l2_cnt = nullptr;     // [chunks][64] per-chunk tile counts, then offsets
-  uint16_t *l2_wcnt = nullptr;    // [chunks][4][64] per-wave tile counts of every chunk
   int64_t l2_chunks = 0;          // chunks l2_cnt holds
   uint32_t *tile_cnt = nullptr;   // [total_tiles] pairs per tile
   uint32_t *tile_start = nullptr; // [total_tiles + 1] exclusive scan of tile_cnt

@@ -744,7 +744,7 @@ __device__ __forceinline__ bool chunk_of(uint32_t q, const uint32_t *__restrict_
 __global__ void __launch_bounds__(kThreads)
 k_l2_count(const uint32_t *__restrict__ cfirst, uint32_t nst, const uint2 *__restrict__ st_ranges,
            const uint32_t *__restrict__ ikey, int SGW, uint32_t st_per_view,
-           uint32_t *__restrict__ cnt, uint16_t *__restrict__ wcnt) {
+           uint32_t *__restrict__ cnt) {
   __shared__ uint32_t s_w[kWaves][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const SgsXcdWalk wk = sgs_xcd_walk(blockIdx.x, gridDim.x, cfirst[nst]);
@@ -759,8 +759,6 @@ k_l2_count(const uint32_t *__restrict__ cfirst, uint32_t nst, const uint2 *__res
       // lane t: the round's items covering tile t
       acc += (uint32_t)__popcll(wave_transpose64(m, lane));
     }
-    // a wave's count of one tile is at most its 256 items
-    wcnt[(q * kWaves + wave) * 64 + lane] = (uint16_t)acc;
     s_w[wave][lane] = acc;
     __syncthreads();
     if (wave == 0)
@@ -832,89 +830,29 @@ __global__ void k_l2_ranges(const uint32_t *__restrict__ tile_cnt,
   ranges[t] = n && a < e ? make_uint2((uint32_t)a, (uint32_t)e) : make_uint2(0u, 0u);
 }
 
-// Every pair of the chunk to its final position:
-//   tile offset + the tile's pairs in earlier chunks + in earlier waves of
-//   this chunk (counted by k_l2_count) + in earlier rounds of this wave + in
-//   earlier lanes.  Lane t of `pos` holds tile t's next position.  Ballot
-//   form (below): for every tile some item of the round covers, one ballot
-//   ranks the lanes covering it and they write consecutive positions (one
-//   coalesced store per tile).  Staged form (after it): the round's pairs are
-//   placed in LDS tile after tile, then copied out with consecutive lanes.
-__device__ __forceinline__ uint32_t lane_ge(uint32_t v, int t, uint32_t x) {
-  return (int)(threadIdx.x & 63) == t ? x : v;
-}
-
-// The tiles t0 + bit (bits of the wave-uniform u) that the 32-bit half h of
-// this lane's mask covers, scattered as above.
-__device__ __forceinline__ void scatter_half(uint32_t u, uint32_t h, int t0, uint32_t gid,
-                                             uint32_t held, uint32_t &pos,
-                                             uint32_t *__restrict__ vals) {
-  while (u) {
-    const int b = __builtin_ctz(u);
-    u &= u - 1u;
-    const bool mine = (h >> b) & 1u;
-    const uint64_t bal = __ballot(mine);
-    const int t = t0 + b;
-    const uint32_t bt = (uint32_t)__builtin_amdgcn_readlane((int)pos, t);
-    if (mine) {
-      const uint32_t p = bt + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-      if (p < held) vals[p] = gid;
-    }
-    pos = lane_ge(pos, t, bt + (uint32_t)__popcll(bal));
-  }
-}
-
-// Pairs staged per wave and round (8 B each: destination, item lane), sized
-// so that five workgroups fit a compute unit's LDS.  A round whose pairs
-// exceed it (about 1 % of the rounds at 3M Gaussians x 8 views, items of
-// large splats) takes the ballot loop above instead.
-constexpr int kL2Stage = 1020;
-
-// Lane t holds col, the round's items covering tile t (bit L = lane L's
-// item).  The tile's k-th covering item goes to pos + k; the round's pairs
-// are laid out tile after tile in the wave's LDS stage (tile t from its
-// exclusive prefix o) as (destination, item lane), and the copy-out writes
-// each tile's run with consecutive lanes, reading the Gaussian index from the
-// item's lane (every lane active there: the cross-lane read needs its source
-// lane active).
-__device__ __forceinline__ void scatter_staged(uint64_t col, uint32_t o, uint32_t total,
-                                               uint32_t gid, uint32_t held, uint32_t pos,
-                                               uint2 *__restrict__ stage,
-                                               uint32_t *__restrict__ vals) {
-  const uint32_t lane = threadIdx.x & 63u;
-  uint32_t slot = o, p = pos;
-  while (col) {
-    stage[slot] = make_uint2(p, (uint32_t)__builtin_ctzll(col));
-    col &= col - 1ull;
-    ++slot;
-    ++p;
-  }
-  __builtin_amdgcn_wave_barrier();
-  for (uint32_t e0 = 0; e0 < total; e0 += 128u) {  // wave-uniform trip count
-    const uint32_t e1 = e0 + lane, e2 = e1 + 64u;
-    const bool v1 = e1 < total, v2 = e2 < total;
-    // both reads unconditional (in the stage; stale entries past the total
-    // are read and dropped), so that they are in flight together
-    const uint2 d1 = stage[min(e1, (uint32_t)(kL2Stage - 1))];
-    const uint2 d2 = stage[min(e2, (uint32_t)(kL2Stage - 1))];
-    const uint32_t g1 = (uint32_t)__shfl((int)gid, (int)d1.y, 64);
-    const uint32_t g2 = (uint32_t)__shfl((int)gid, (int)d2.y, 64);
-    if (v1 && d1.x < held) vals[d1.x] = g1;
-    if (v2 && d2.x < held) vals[d2.x] = g2;
-  }
-  __builtin_amdgcn_wave_barrier();
-}
+// Every pair of the chunk to its final position, tile run by tile run: the
+// chunk's pairs of tile t are consecutive in the output (from the tile's
+// offset + its pairs in earlier chunks), in item order (wave, round, lane).
+// They are laid out in LDS tile after tile, as the item's slot in the chunk
+// (10 bits), and copied out run by run with consecutive lanes, which look
+// the slot's Gaussian index up, so that each output line is written whole in
+// one burst (writing each wave's and round's few dozen bytes on their own
+// left lines half written in the cache, and most were written out twice).
+// A chunk whose pairs exceed the LDS array takes its tiles in groups that
+// fit (one tile's pairs of a chunk are at most kL2Items).
+constexpr int kL2Out = 12288;
+static_assert(kL2Out >= kL2Items, "one tile's pairs of a chunk must fit");
 
 __global__ void __launch_bounds__(kThreads)
 k_l2_scatter(const uint32_t *__restrict__ cfirst, uint32_t *__restrict__ queue, uint32_t nst,
              const uint2 *__restrict__ st_ranges, const uint32_t *__restrict__ ikey,
              const uint32_t *__restrict__ ival, int GW, int GH, uint32_t tiles_per_view, int SGW,
              uint32_t st_per_view, const uint32_t *__restrict__ rel,
-             const uint16_t *__restrict__ wcnt, const uint32_t *__restrict__ tile_start,
-             int64_t held_static, const uint32_t *__restrict__ dheld,
-             uint32_t *__restrict__ vals) {
-  __shared__ uint2 s_stage[kWaves][kL2Stage];
+             const uint32_t *__restrict__ tile_start, int64_t held_static,
+             const uint32_t *__restrict__ dheld, uint32_t *__restrict__ vals) {
+  __shared__ uint16_t s_out[kL2Out];
+  __shared__ uint32_t s_gid[kL2Items];  // slot wave * 256 + round * 64 + lane
+  __shared__ uint16_t s_cnt[kWaves][4][64];  // wave, round: its items covering tile t
   __shared__ uint32_t s_q[2];
   const uint32_t held = (uint32_t)(dheld ? (int64_t)*dheld : held_static);
   const uint32_t nchunks = cfirst[nst];
@@ -929,43 +867,80 @@ k_l2_scatter(const uint32_t *__restrict__ cfirst, uint32_t *__restrict__ queue, 
     if (q >= nchunks) break;
     chunk_of((uint32_t)q, cfirst, nst, st_ranges, SGW, st_per_view, ch);
     const int tx = ch.tx_base + (lane & 7), ty = ch.ty_base + (lane >> 3);
-    uint32_t pos = 0;
-    if (tx < GW && ty < GH) {
-      pos = tile_start[(int64_t)ch.view * tiles_per_view + (int64_t)ty * GW + tx] +
-            rel[(int64_t)q * 64 + lane];
-      for (int w = 0; w < wave; ++w) pos += wcnt[((int64_t)q * kWaves + w) * 64 + lane];
-    }
+    // lane t: where tile t's pairs of this chunk start in the output
+    uint32_t dst0 = 0;
+    if (tx < GW && ty < GH)
+      dst0 = tile_start[(int64_t)ch.view * tiles_per_view + (int64_t)ty * GW + tx] +
+             rel[(int64_t)q * 64 + lane];
     uint32_t key[4], gid[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {  // all four rounds' loads in flight at once
       const uint32_t idx = ch.first + (uint32_t)(wave * 256 + r * 64 + lane);
       const bool ok = idx < ch.end;
-      key[r] = ok ? ikey[idx] : 0u;
+      key[r] = ok ? ikey[idx] : 0xFFFFFFFFu;  // no item: empty mask below
       gid[r] = ok ? ival[idx] : 0u;
-      if (!ok) key[r] = 0xFFFFFFFFu;  // no item: empty mask below
     }
+    uint64_t col[4];  // lane t: the round's items covering tile t (bit L: lane L's item)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const uint64_t m = key[r] == 0xFFFFFFFFu ? 0ull : item_mask(key[r]);
-      // lane t: the round's items covering tile t
-      const uint64_t col = wave_transpose64(m, lane);
-      const uint32_t c = (uint32_t)__popcll(col);
-      uint32_t incl = c;
+      col[r] = wave_transpose64(key[r] == 0xFFFFFFFFu ? 0ull : item_mask(key[r]), lane);
+      s_gid[wave * 256 + r * 64 + lane] = gid[r];
+      s_cnt[wave][r][lane] = (uint16_t)__popcll(col[r]);
+    }
+    __syncthreads();
+    // lane t: the tile's pairs in this chunk, and in its earlier waves
+    uint32_t tot = 0, before = 0;
 #pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t v = (uint32_t)__shfl_up((int)incl, o, 64);
-        if (lane >= o) incl += v;
+    for (int w = 0; w < kWaves; ++w)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t v = s_cnt[w][r][lane];
+        tot += v;
+        before += w < wave ? v : 0u;
       }
-      const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-      if (total <= (uint32_t)kL2Stage) {
-        scatter_staged(col, incl - c, total, gid[r], held, pos, s_stage[wave], vals);
-        pos += c;
-      } else {
-        // the tiles any lane covers: the transposed masks' non-empty columns
-        const uint64_t u = __ballot(col != 0ull);
-        scatter_half((uint32_t)u, (uint32_t)m, 0, gid[r], held, pos, vals);
-        scatter_half((uint32_t)(u >> 32), (uint32_t)(m >> 32), 32, gid[r], held, pos, vals);
+    uint32_t incl = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t v = (uint32_t)__shfl_up((int)incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    // groups of consecutive tiles whose pairs fit the LDS array (the same in
+    // every wave: each computes the same prefix)
+    uint32_t base = 0;  // pairs of the tiles in earlier groups
+    for (int t0 = 0; t0 < 64;) {
+      // incl rises with the lane: the tiles that fit are t0 .. t1 - 1
+      const uint64_t fits = __ballot(lane >= t0 && incl - base <= (uint32_t)kL2Out);
+      const int t1 = 64 - (int)__builtin_clzll(fits);
+      if (lane >= t0 && lane < t1) {
+        uint32_t lp = incl - tot - base + before;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          // the two halves of the column on their own (32-bit bit scans)
+          const uint32_t slot = (uint32_t)(wave * 256 + r * 64);
+          uint32_t lo = (uint32_t)col[r], hi = (uint32_t)(col[r] >> 32);
+          while (lo) {
+            s_out[lp++] = (uint16_t)(slot + __builtin_ctz(lo));
+            lo &= lo - 1u;
+          }
+          while (hi) {
+            s_out[lp++] = (uint16_t)(slot + 32u + __builtin_ctz(hi));
+            hi &= hi - 1u;
+          }
+        }
       }
+      __syncthreads();
+      // copy-out: the group's tiles dealt round the waves, each run with
+      // consecutive lanes
+      for (int t = t0 + wave; t < t1; t += kWaves) {
+        const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)tot, t);
+        const uint32_t src = (uint32_t)__builtin_amdgcn_readlane((int)(incl - tot), t) - base;
+        const uint32_t dst = (uint32_t)__builtin_amdgcn_readlane((int)dst0, t);
+        for (uint32_t e = lane; e < n; e += 64u)
+          if (dst + e < held) vals[dst + e] = s_gid[s_out[src + e]];
+      }
+      __syncthreads();  // the next group or chunk refills the arrays
+      base = (uint32_t)__builtin_amdgcn_readlane((int)incl, t1 - 1);
+      t0 = t1;
     }
   }
 }
@@ -1197,8 +1172,7 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
     k_st_chunks<<<1, kThreads, 0, c->stream>>>(c->st_ranges, c->total_st, c->chunk_first);
     if (chunks > 0)
       k_l2_count<<<resident_blocks<k_l2_count>(chunks), kThreads, 0, c->stream>>>(
-          c->chunk_first, nst, c->st_ranges, c->tile_key[which], c->SGW, spv, c->l2_cnt,
-          c->l2_wcnt);
+          c->chunk_first, nst, c->st_ranges, c->tile_key[which], c->SGW, spv, c->l2_cnt);
     k_l2_scan<<<nst, 64 * kL2ScanWaves, 0, c->stream>>>(c->chunk_first, c->l2_cnt, c->GW, c->GH,
                                                          c->SGW, spv, tpv, c->tile_cnt);
   }
@@ -1214,8 +1188,8 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
     if (chunks > 0)
       k_l2_scatter<<<resident_blocks<k_l2_scatter>(chunks), kThreads, 0, c->stream>>>(
           c->chunk_first, c->chunk_first + nst + 1, nst, c->st_ranges, c->tile_key[which],
-          c->pair_val[which], c->GW, c->GH, tpv, c->SGW, spv, c->l2_cnt, c->l2_wcnt,
-          c->tile_start, P, dP, c->pair_val[which ^ 1]);
+          c->pair_val[which], c->GW, c->GH, tpv, c->SGW, spv, c->l2_cnt, c->tile_start, P,
+          dP, c->pair_val[which ^ 1]);
   }
   c->pair_sorted_buf = which ^ 1;
   return launch_tile_order(c);

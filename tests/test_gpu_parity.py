@@ -211,8 +211,12 @@ TINY = [
     # large splats: tile rectangles of 512 tiles and more take the backward's
     # replica records (folded into the splat's record after the blend)
     dict(n=60, W=640, H=480, V=2, seed=5, logscale=-1.8, big=True),
+    # dense: one super-tile's chunk of items holds several times the pairs the
+    # pair scatter stages in LDS at once (its tiles are taken in groups)
+    dict(n=1500, W=128, H=128, V=1, seed=7, logscale=-1.4, dense=True),
 ]
 BIG_TILES = 512   # the library's large-splat threshold (tiles per rectangle)
+L2_OUT = 12288    # pairs the library's pair scatter stages in LDS at once
 
 
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
@@ -233,6 +237,17 @@ def test_tiny_scenes_full_step(orc, gctx, dev, tile, cfg):
                  (sp[:, 3] // tile[1] - sp[:, 2] // tile[1] + 1))
         assert (tiles >= BIG_TILES).sum() >= 3, "no large splats in the large-splat case"
         assert (tiles < BIG_TILES).sum() >= 3, "no small splats in the large-splat case"
+    if c.get("dense"):
+        # a super-tile (8 x 8 tiles) with twice the pairs the LDS array holds:
+        # its items (at most 2048) make at most two chunks of 1024, so one of
+        # them holds more pairs than the array
+        assert sc.n <= 2048
+        gw, gh = -(-sc.width // tile[0]), -(-sc.height // tile[1])
+        r0 = g["ranges"].reshape(-1, 2).astype(np.int64)
+        per = (r0[:, 1] - r0[:, 0]).reshape(sc.views, gh, gw)
+        st_pairs = max(int(per[v, y:y + 8, x:x + 8].sum()) for v in range(sc.views)
+                       for y in range(0, gh, 8) for x in range(0, gw, 8))
+        assert st_pairs > 2 * L2_OUT, "dense case not dense"
     # render backward fed the same dL/dimage
     grad_close(g["gq_render"][:, :sc.n], r["gyhat"][:, :sc.n], name="grad qparams")
     grad_close(g["gmask"], r["gmhat"], name="grad mask")
