@@ -833,11 +833,13 @@ __global__ void k_l2_ranges(const uint32_t *__restrict__ tile_cnt,
 // Every pair of the chunk to its final position, tile run by tile run: the
 // chunk's pairs of tile t are consecutive in the output (from the tile's
 // offset + its pairs in earlier chunks), in item order (wave, round, lane).
-// They are laid out in LDS tile after tile, as the item's slot in the chunk
-// (10 bits), and copied out run by run with consecutive lanes, which look
-// the slot's Gaussian index up, so that each output line is written whole in
-// one burst (writing each wave's and round's few dozen bytes on their own
-// left lines half written in the cache, and most were written out twice).
+// They are laid out in LDS tile after tile, each as the item's slot in the
+// chunk (10 bits) and the tile (6 bits), and copied out by the whole
+// workgroup with consecutive threads on consecutive entries, which look the
+// slot's Gaussian index and the tile's destination up, so that each output
+// line is written whole in one burst (writing each wave's and round's few
+// dozen bytes on their own left lines half written in the cache, and most
+// were written out twice).
 // A chunk whose pairs exceed the LDS array takes its tiles in groups that
 // fit (one tile's pairs of a chunk are at most kL2Items).
 constexpr int kL2Out = 12288;
@@ -853,6 +855,7 @@ k_l2_scatter(const uint32_t *__restrict__ cfirst, uint32_t *__restrict__ queue, 
   __shared__ uint16_t s_out[kL2Out];
   __shared__ uint32_t s_gid[kL2Items];  // slot wave * 256 + round * 64 + lane
   __shared__ uint16_t s_cnt[kWaves][4][64];  // wave, round: its items covering tile t
+  __shared__ uint32_t s_dst[64];  // tile t's entry e of the group goes to s_dst[t] + e
   __shared__ uint32_t s_q[2];
   const uint32_t held = (uint32_t)(dheld ? (int64_t)*dheld : held_static);
   const uint32_t nchunks = cfirst[nst];
@@ -912,34 +915,45 @@ k_l2_scatter(const uint32_t *__restrict__ cfirst, uint32_t *__restrict__ queue, 
       const uint64_t fits = __ballot(lane >= t0 && incl - base <= (uint32_t)kL2Out);
       const int t1 = 64 - (int)__builtin_clzll(fits);
       if (lane >= t0 && lane < t1) {
+        if (wave == 0) s_dst[lane] = dst0 - (incl - tot - base);
         uint32_t lp = incl - tot - base + before;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           // the two halves of the column on their own (32-bit bit scans)
-          const uint32_t slot = (uint32_t)(wave * 256 + r * 64);
+          const uint32_t slot = (uint32_t)(wave * 256 + r * 64) | (uint32_t)lane << 10;
           uint32_t lo = (uint32_t)col[r], hi = (uint32_t)(col[r] >> 32);
           while (lo) {
-            s_out[lp++] = (uint16_t)(slot + __builtin_ctz(lo));
+            s_out[lp++] = (uint16_t)(slot | __builtin_ctz(lo));
             lo &= lo - 1u;
           }
           while (hi) {
-            s_out[lp++] = (uint16_t)(slot + 32u + __builtin_ctz(hi));
+            s_out[lp++] = (uint16_t)(slot | (32u + __builtin_ctz(hi)));
             hi &= hi - 1u;
           }
         }
       }
       __syncthreads();
-      // copy-out: the group's tiles dealt round the waves, each run with
-      // consecutive lanes
-      for (int t = t0 + wave; t < t1; t += kWaves) {
-        const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)tot, t);
-        const uint32_t src = (uint32_t)__builtin_amdgcn_readlane((int)(incl - tot), t) - base;
-        const uint32_t dst = (uint32_t)__builtin_amdgcn_readlane((int)dst0, t);
-        for (uint32_t e = lane; e < n; e += 64u)
-          if (dst + e < held) vals[dst + e] = s_gid[s_out[src + e]];
+      // copy-out: the group's entries over the workgroup, four per thread in
+      // flight at once
+      const uint32_t end = (uint32_t)__builtin_amdgcn_readlane((int)incl, t1 - 1);
+      const uint32_t ng = end - base;
+      for (uint32_t e0 = 0; e0 < ng; e0 += 4u * kThreads) {
+        uint32_t v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t e = e0 + (uint32_t)(k * kThreads) + threadIdx.x;
+          v[k] = s_out[min(e, (uint32_t)kL2Out - 1u)];  // past the group: read, dropped
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t e = e0 + (uint32_t)(k * kThreads) + threadIdx.x;
+          const uint32_t d = s_dst[v[k] >> 10] + e;
+          const uint32_t g = s_gid[v[k] & 1023u];
+          if (e < ng && d < held) vals[d] = g;
+        }
       }
       __syncthreads();  // the next group or chunk refills the arrays
-      base = (uint32_t)__builtin_amdgcn_readlane((int)incl, t1 - 1);
+      base = end;
       t0 = t1;
     }
   }
