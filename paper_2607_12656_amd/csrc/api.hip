@@ -237,12 +237,18 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   c->SGH = (c->GH + 7) / 8;
   c->st_per_view = (int64_t)c->SGW * c->SGH;
   c->total_st = c->st_per_view * views;
-  if (c->total_st > 65536)
+  c->st_vbits = 0;
+  while ((1 << c->st_vbits) < views) ++c->st_vbits;
+  c->st_slots = c->st_per_view << c->st_vbits;
+  if (c->st_slots > 65536)
     return fail(c, SGS_ECAPACITY,
-                "set_scene: views x super-tiles (8x8 tiles) must not exceed 65536 (%lld)",
-                (long long)c->total_st);
+                "set_scene: super-tiles (8x8 tiles) per view x views rounded up to a power "
+                "of two must not exceed 65536 (%lld)", (long long)c->st_slots);
   c->vn = (int64_t)views * n;
   const int64_t vn = c->vn;
+  c->vseg = (n + kDepthSeg - 1) / kDepthSeg * kDepthSeg;
+  c->vn_pad = (int64_t)views * c->vseg;
+  const int64_t vnp = c->vn_pad;
   hipError_t e = hipSuccess;
 #define SGS_ALLOC(p, cnt)                                   \
   do {                                                      \
@@ -252,17 +258,17 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   SGS_ALLOC(c->d_cams, views);
   SGS_ALLOC(c->rec, 3 * vn);
   for (int k = 0; k < 2; ++k) {
-    SGS_ALLOC(c->depth_key[k], vn);
-    SGS_ALLOC(c->depth_val[k], vn);
-    SGS_ALLOC(c->depth_rect[k], vn);
+    SGS_ALLOC(c->depth_key[k], vnp);
+    SGS_ALLOC(c->depth_val[k], vnp);
+    SGS_ALLOC(c->depth_rect[k], vnp);
   }
   SGS_ALLOC(c->touched, vn);
-  SGS_ALLOC(c->ioffsets, vn + 1);
-  SGS_ALLOC(c->st_ranges, c->total_st);
-  SGS_ALLOC(c->chunk_first, c->total_st + 2);  // + the level-2 scatter's chunk queue
+  SGS_ALLOC(c->ioffsets, vnp + 1);
+  SGS_ALLOC(c->st_ranges, c->st_slots);
+  SGS_ALLOC(c->chunk_first, c->st_slots + 2);  // + the level-2 scatter's chunk queue
   SGS_ALLOC(c->tile_cnt, c->total_tiles);
   SGS_ALLOC(c->tile_start, c->total_tiles + 1);
-  SGS_ALLOC(c->bin_rec, vn);
+  SGS_ALLOC(c->bin_rec, vnp);
   SGS_ALLOC(c->bin_splat, vn);
   SGS_ALLOC(c->mlp_f, n);
   SGS_ALLOC(c->fl_tmp, fl_scratch_words(n));
@@ -301,9 +307,9 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   c->red_tmp_words = red;
   SGS_ALLOC(c->lap_coef, 192);
 #undef SGS_ALLOC
-  const int64_t hist = radix_hist_words(vn);
+  const int64_t hist = radix_hist_words(vnp);
   // block sums of the scans over splats and over tiles
-  const int64_t scan = ((vn > c->total_tiles ? vn : c->total_tiles) + 4095) / 4096 + 1;
+  const int64_t scan = ((vnp > c->total_tiles ? vnp : c->total_tiles) + 4095) / 4096 + 1;
   e = ensure_tmp(c, scan, hist);
   if (e != hipSuccess) { free_scene(c); return hip_fail(c, e, "set_scene alloc"); }
   // initial pair capacity: 4 tiles per splat
@@ -1276,13 +1282,14 @@ __global__ void k_fill_tile_ids(const uint2 *__restrict__ ranges, uint32_t *__re
   for (uint32_t p = r.x + threadIdx.x; p < r.y; p += blockDim.x) out[p] = blockIdx.x;
 }
 
-// depth keys in splat order: scatter the sorted (key, index) pairs back
-__global__ void k_export_depth(int64_t vn, const uint32_t *__restrict__ skey,
+// depth keys in splat order: scatter the sorted (key, index) pairs back (the
+// segments' padding, index 0xFFFFFFFF, has no splat)
+__global__ void k_export_depth(int64_t count, const uint32_t *__restrict__ skey,
                                const uint32_t *__restrict__ sval, float *__restrict__ depth) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= vn) return;
-  const uint32_t key = skey[k];
-  depth[sval[k]] = key == 0xFFFFFFFFu ? -1.0f : __uint_as_float(key);
+  if (k >= count) return;
+  const uint32_t key = skey[k], s = sval[k];
+  if (s != 0xFFFFFFFFu) depth[s] = key == 0xFFFFFFFFu ? -1.0f : __uint_as_float(key);
 }
 
 }  // namespace
@@ -1311,8 +1318,8 @@ extern "C" sgs_status sgs_copy_structure(sgs_ctx *c, uint32_t *tile_ids, uint32_
     SGS_HIP(hipGetLastError(), "copy_structure export");
   }
   if (depth) {
-    k_export_depth<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(
-        c->vn, c->depth_key[c->depth_sorted_buf], c->depth_val[c->depth_sorted_buf], depth);
+    k_export_depth<<<sgs_blocks(c->vn_pad, 256), 256, 0, c->stream>>>(
+        c->vn_pad, c->depth_key[c->depth_sorted_buf], c->depth_val[c->depth_sorted_buf], depth);
     SGS_HIP(hipGetLastError(), "copy_structure depth");
   }
   return SGS_OK;

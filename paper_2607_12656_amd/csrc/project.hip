@@ -122,11 +122,22 @@ k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
              float4 *__restrict__ rec, uint32_t *__restrict__ depth_key,
              uint32_t *__restrict__ depth_val, uint32_t *__restrict__ touched,
              uint4 *__restrict__ bins, uint32_t *__restrict__ rect, int GW,
-             int64_t tiles_per_view) {
+             int64_t tiles_per_view, int64_t vseg) {
   __shared__ float s_q[QUANT ? 64 : 1], s_rq[QUANT ? 64 : 1];
   if (QUANT) load_quant_table(q, s_q, s_rq);
   const int64_t i = (int64_t)blockIdx.x * kPThreads + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n) {
+    // the padding of each view's depth segment: sorts after every splat of
+    // the view and stands for no splat
+    if (i < vseg)
+      for (int v = 0; v < V; ++v) {
+        const int64_t ps = (int64_t)v * vseg + i;
+        depth_key[ps] = 0xFFFFFFFFu;
+        depth_val[ps] = 0xFFFFFFFFu;
+        rect[ps] = kNoRect;
+      }
+    return;
+  }
   float y[SGS_NCH];
 #pragma unroll
   for (int j = 0; j < SGS_NCH; ++j) y[j] = qp[j * npad + i];
@@ -144,17 +155,18 @@ k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
     SgsProj p;
     sgs_project(y, cam, W, H, p);
     const int64_t s = (int64_t)v * n + i;
-    depth_val[s] = (uint32_t)s;
+    const int64_t ps = (int64_t)v * vseg + i;  // its place in the depth segments
+    depth_val[ps] = (uint32_t)s;
     if (!p.valid) {
-      depth_key[s] = 0xFFFFFFFFu;
+      depth_key[ps] = 0xFFFFFFFFu;
       touched[s] = 0;
-      rect[s] = kNoRect;  // (an invalid splat's record is never read)
+      rect[ps] = kNoRect;  // (an invalid splat's record is never read)
       rec[3 * s] = make_float4(0.f, 0.f, 0.f, 0.f);
       rec[3 * s + 1] = make_float4(0.f, 0.f, __int_as_float(-1), __int_as_float(-1));
       rec[3 * s + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
       continue;
     }
-    depth_key[s] = __float_as_uint(p.tz);
+    depth_key[ps] = __float_as_uint(p.tz);
     const int tw = p.x1 / TW - p.x0 / TW + 1, th = p.y1 / TH - p.y0 / TH + 1;
     touched[s] = (uint32_t)(tw * th);
     // binning record: first tile id, rectangle width in tiles, Gaussian, pairs
@@ -162,7 +174,7 @@ k_preprocess(int64_t n, int64_t npad, int V, int W, int H, int TW, int TH,
     // only a rectangle that does not fit it gets the full binning record
     // (first tile id, width in tiles, Gaussian, pairs), gathered later
     const uint32_t packed = sgs_pack_rect(p.x0 / TW, p.y0 / TH, tw, th);
-    rect[s] = packed;
+    rect[ps] = packed;
     if (packed == kNoRect)
       bins[s] = make_uint4((uint32_t)(v * tiles_per_view) +
                                (uint32_t)((p.y0 / TH) * GW + p.x0 / TW),
@@ -424,17 +436,17 @@ int64_t proj_partial_doubles(int64_t n) { return (int64_t)SGS_NCH * sgs_blocks(n
 hipError_t launch_preprocess(sgs_ctx *c, const float *qparams, const uint8_t *hard,
                              const float *q) {
   SgsProfScope ps(c, SGS_PROF_PREPROCESS);
-  const int64_t nb = sgs_blocks(c->n, kPThreads);
+  const int64_t nb = sgs_blocks(c->vseg, kPThreads);  // the padding's threads too
   if (q)
     k_preprocess<true><<<nb, kPThreads, 0, c->stream>>>(
         c->n, c->npad, c->V, c->W, c->H, c->TW, c->TH, c->d_cams, qparams, q, hard, c->rec,
         c->depth_key[0], c->depth_val[0], c->touched, c->bin_splat, c->depth_rect[0], c->GW,
-        c->tiles_per_view);
+        c->tiles_per_view, c->vseg);
   else
     k_preprocess<false><<<nb, kPThreads, 0, c->stream>>>(
         c->n, c->npad, c->V, c->W, c->H, c->TW, c->TH, c->d_cams, qparams, nullptr, hard,
         c->rec, c->depth_key[0], c->depth_val[0], c->touched, c->bin_splat, c->depth_rect[0],
-        c->GW, c->tiles_per_view);
+        c->GW, c->tiles_per_view, c->vseg);
   return hipGetLastError();
 }
 

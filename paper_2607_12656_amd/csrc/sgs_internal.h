@@ -41,6 +41,9 @@ __host__ __device__ __forceinline__ uint32_t sgs_pack_rect(int tx0, int ty0, int
 // counter (so that taking slots is not itself one contended address); a
 // large splat finding its range full keeps its own record.
 constexpr uint32_t kBigTiles = 512;
+// Segment granularity of the depth-ordered arrays (a multiple of every radix
+// tile the depth sort uses, so that no sort block spans two views).
+constexpr int64_t kDepthSeg = 2048;
 constexpr int kBigReps = 16;
 constexpr int64_t kBigMax = 16384;
 constexpr int kBigRanges = 64;
@@ -87,16 +90,17 @@ struct sgs_ctx {
   // per (view, Gaussian): V*n entries
   int64_t vn = 0;
   float4 *rec = nullptr;          // [vn][3]: (px,py,A,B) (C,opa,spanx,spany) (r,g,b,mask)
+  // [vn_pad] each, view v's splat i at v * vseg + i (value v * n + i)
   uint32_t *depth_key[2] = {nullptr, nullptr};
   uint32_t *depth_val[2] = {nullptr, nullptr};
-  // [vn] each: the splat's tile rectangle packed for the depth sort to carry
+  // [vn_pad] each: the splat's tile rectangle packed for the depth sort to carry
   // (first column and row 10 bits each, width - 1 and height - 1 6 bits
   // each), or kNoRect when it does not fit (then the record is gathered)
   uint32_t *depth_rect[2] = {nullptr, nullptr};
   uint32_t *touched = nullptr;    // [vn] tiles per splat (0 = culled)
   uint4 *bin_splat = nullptr;     // [vn] (first tile id, width in tiles, Gaussian, pairs),
                                   // written only for rectangles depth_rect cannot hold
-  uint4 *bin_rec = nullptr;       // [vn] the same records in depth order
+  uint4 *bin_rec = nullptr;       // [vn_pad] the same records in (view, depth) order
   double *splat_grad = nullptr;   // [vn][SGS_SGRAD] per-splat gradient sums (FP64 atomics)
   uint32_t *big_idx = nullptr;    // [vn] replica slot of a large splat (see kBigTiles)
   uint32_t *big_list = nullptr;   // [kBigMax + kBigRanges] splat of each slot, then the
@@ -107,10 +111,18 @@ struct sgs_ctx {
   // super-tiles (8x8 tiles): the first level of the tile binning
   int SGW = 0, SGH = 0;           // super-tiles per view row / column
   int64_t st_per_view = 0, total_st = 0;
+  // super-tile ids: (super-tile in its view) << st_vbits | view, st_slots of
+  // them (ids of views >= V are empty)
+  int st_vbits = 0;
+  int64_t st_slots = 0;
+  // the depth-ordered arrays hold each view's splats in a segment of vseg
+  // entries (n rounded up to kDepthSeg; the padding sorts last), vn_pad in all
+  int64_t vseg = 0, vn_pad = 0;
   int64_t items = 0;              // (splat, super-tile) items of the last render (host copy)
-  uint32_t *ioffsets = nullptr;   // [vn + 1] exclusive scan of the item counts, depth order
-  uint2 *st_ranges = nullptr;     // [total_st] item range of every super-tile
-  uint32_t *chunk_first = nullptr;  // [total_st + 1] first item chunk of every super-tile
+  uint32_t *ioffsets = nullptr;   // [vn_pad + 1] exclusive scan of the item counts, in
+                                  // (view, depth) order
+  uint2 *st_ranges = nullptr;     // [st_slots] item range of every super-tile id
+  uint32_t *chunk_first = nullptr;  // [st_slots + 1] first item chunk of every super-tile id
   uint32_t *l2_cnt = nullptr;     // [chunks][64] per-chunk tile counts, then offsets
   int64_t l2_chunks = 0;          // chunks l2_cnt holds
   uint32_t *tile_cnt = nullptr;   // [total_tiles] pairs per tile
@@ -242,10 +254,13 @@ hipError_t launch_exclusive_scan(sgs_ctx *c, const uint32_t *in, uint32_t *out,
                                  int64_t count, uint32_t *total_out, int64_t cap = -1);
 // Stable LSD radix sort of 32-bit keys with 32-bit values over bits
 // [shift0, bits) starting in buffer cur0; ping-pongs between buffer 0 and 1;
-// returns the buffer index that holds the result in *which.
+// returns the buffer index that holds the result in *which.  seg_len > 0:
+// every seg_len elements are sorted on their own (a multiple of the sort's
+// block size, static count).
 hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2],
                              int64_t count, int bits, int *which, const uint32_t *dcount,
-                             int shift0 = 0, int cur0 = 0, uint32_t **vals2 = nullptr);
+                             int shift0 = 0, int cur0 = 0, uint32_t **vals2 = nullptr,
+                             int64_t seg_len = 0);
 hipError_t launch_bin_pairs(sgs_ctx *c);   // depth order -> pairs -> tile sort -> ranges
 hipError_t launch_depth_order(sgs_ctx *c); // depth sort + scan (writes d_pairs_total)
 // blend.hip

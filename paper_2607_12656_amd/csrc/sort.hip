@@ -339,6 +339,32 @@ __device__ __forceinline__ uint32_t scanned_offset(const uint32_t *__restrict__ 
   return h;
 }
 
+// The same entry for a sort of equal segments (seg_len elements, seg_blocks
+// blocks each) sorted each on its own: the digit's position in the block's
+// segment, from the global offsets (the elements of the digit in earlier
+// blocks of the segment are the difference of two of them; the segment's
+// digit counts, scanned, give the digits' bases).  total: the digit totals;
+// with_base: hist_scanned includes the digits' bases (the chunked path).
+__device__ __forceinline__ uint32_t segment_offset(const uint32_t *__restrict__ hist_scanned,
+                                                   const uint32_t *__restrict__ total,
+                                                   bool with_base, int64_t blk, int64_t nb,
+                                                   int64_t seg_blocks, int64_t seg_len) {
+  __shared__ uint32_t s_wave[kWaves];
+  const int t = threadIdx.x;
+  const int64_t sg = blk / seg_blocks, fb = sg * seg_blocks, fe = fb + seg_blocks;
+  const uint32_t hb = hist_scanned[blk * 256 + t], hf = hist_scanned[fb * 256 + t];
+  uint32_t he, tot;
+  if (fe < nb) {
+    he = hist_scanned[fe * 256 + t];
+  } else {  // the last segment ends at the digit's total (past its base)
+    const uint32_t tt = total[t];
+    const uint32_t ex = block_exclusive_scan(tt, s_wave, tot);
+    he = (with_base ? ex : 0u) + tt;
+  }
+  const uint32_t seg_ex = block_exclusive_scan(he - hf, s_wave, tot);
+  return (uint32_t)(sg * seg_len) + seg_ex + (hb - hf);
+}
+
 // Scatter of one pass for the block's elements in the wave-segment layout:
 // wave w holds elements w * IT * 64 + r * 64 + lane of the block in kr[r],
 // vr[r], so the input order is (wave, round, lane).  Each wave ranks its own
@@ -436,7 +462,8 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
                 uint32_t *__restrict__ vout, uint32_t *__restrict__ vout2,
                 int64_t count_static, const uint32_t *__restrict__ dcount, int shift, int nb,
                 const uint32_t *__restrict__ hist_scanned,
-                const uint32_t *__restrict__ digit_tot) {
+                const uint32_t *__restrict__ digit_tot, const uint32_t *__restrict__ total,
+                int64_t seg_blocks, int64_t seg_len) {
   constexpr int TILE = kThreads * IT;
   __shared__ uint32_t s_key[TILE];
   __shared__ uint32_t s_val[TILE];
@@ -455,7 +482,10 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
     vr[r] = i < count ? vin[i] : 0u;
     vr2[r] = V2 && i < count ? vin2[i] : 0u;
   }
-  const uint32_t h_scan = scanned_offset(hist_scanned, digit_tot, blk);
+  const uint32_t h_scan =
+      seg_blocks ? segment_offset(hist_scanned, total, digit_tot == nullptr, blk,
+                                  (count + TILE - 1) / TILE, seg_blocks, seg_len)
+                 : scanned_offset(hist_scanned, digit_tot, blk);
   scatter_block<IT, V2>(kr, vr, vr2, base, count, shift, nb, h_scan, kout, vout, vout2, s_key,
                         s_val, s_val2);
 }
@@ -552,20 +582,22 @@ k_gather_bins(const uint32_t *__restrict__ order, const uint32_t *__restrict__ d
 // ---------------------------------------------------------------------------
 // Level 1: super-tile items
 // ---------------------------------------------------------------------------
-// An item's key: the global super-tile id in bits [0, 16) (at most 65536
-// super-tiles; the sort's 8-bit digits stay inside these bits) and, riding
-// along above bit 20, the covered tile rectangle inside the super-tile:
-// first and last column and row, 3 bits each.
+// An item's key: the super-tile id (super-tile in its view) << vbits | view
+// in bits [0, 16) (at most 65536 ids; the sort's 8-bit digits stay inside
+// these bits) and, riding along above bit 20, the covered tile rectangle
+// inside the super-tile: first and last column and row, 3 bits each.  The
+// items come in (view, depth) order, so one stable sort on the super-tile
+// bits alone leaves each super-tile's items together and in depth order.
 constexpr int kStBits = 20;
 constexpr uint32_t kStMask = (1u << kStBits) - 1u;
 
-// The items of every splat, in depth order, at its item offset: key =
+// The items of every splat, in (view, depth) order, at its item offset: key =
 // super-tile id | covered tile rectangle inside it (see kStBits), value =
 // Gaussian index.  Items at or beyond the live item count (a capacity) are
 // not written.
 __global__ void k_emit_items(const uint4 *__restrict__ brec, const uint32_t *__restrict__ ioff,
                              int64_t vn, int64_t count_static, const uint32_t *__restrict__ dcount,
-                             int GW, uint32_t tiles_per_view, int SGW, uint32_t st_per_view,
+                             int GW, uint32_t tiles_per_view, int SGW, int vbits,
                              uint32_t *__restrict__ kout, uint32_t *__restrict__ vout) {
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= vn) return;
@@ -579,7 +611,7 @@ __global__ void k_emit_items(const uint4 *__restrict__ brec, const uint32_t *__r
       if (o >= count) return;
       const uint32_t cx0 = (uint32_t)max(r.tx0 - 8 * sx, 0), cx1 = (uint32_t)min(r.tx1 - 8 * sx, 7);
       const uint32_t cy0 = (uint32_t)max(r.ty0 - 8 * sy, 0), cy1 = (uint32_t)min(r.ty1 - 8 * sy, 7);
-      kout[o] = (r.v * st_per_view + (uint32_t)sy * (uint32_t)SGW + (uint32_t)sx) |
+      kout[o] = ((((uint32_t)sy * (uint32_t)SGW + (uint32_t)sx) << vbits) | r.v) |
                 (cx0 << kStBits) | (cx1 << (kStBits + 3)) | (cy0 << (kStBits + 6)) |
                 (cy1 << (kStBits + 9));
       vout[o] = b.z;
@@ -725,14 +757,14 @@ struct Chunk {
 
 __device__ __forceinline__ bool chunk_of(uint32_t q, const uint32_t *__restrict__ cfirst,
                                          uint32_t nst, const uint2 *__restrict__ st_ranges,
-                                         int SGW, uint32_t st_per_view, Chunk &ch) {
+                                         int SGW, int vbits, Chunk &ch) {
   if (q >= cfirst[nst]) return false;
   ch.g = chunk_super(cfirst, nst, q);
   const uint2 r = st_ranges[ch.g];
   ch.first = r.x + (q - cfirst[ch.g]) * (uint32_t)kL2Items;
   ch.end = r.y;
-  ch.view = ch.g / st_per_view;
-  const uint32_t gs = ch.g - ch.view * st_per_view;
+  ch.view = ch.g & ((1u << vbits) - 1u);
+  const uint32_t gs = ch.g >> vbits;
   const uint32_t sy = gs / (uint32_t)SGW;
   ch.ty_base = 8 * (int)sy;
   ch.tx_base = 8 * (int)(gs - sy * (uint32_t)SGW);
@@ -743,14 +775,13 @@ __device__ __forceinline__ bool chunk_of(uint32_t q, const uint32_t *__restrict_
 // size loops over the chunks (their number is on the device).
 __global__ void __launch_bounds__(kThreads)
 k_l2_count(const uint32_t *__restrict__ cfirst, uint32_t nst, const uint2 *__restrict__ st_ranges,
-           const uint32_t *__restrict__ ikey, int SGW, uint32_t st_per_view,
-           uint32_t *__restrict__ cnt) {
+           const uint32_t *__restrict__ ikey, int SGW, int vbits, uint32_t *__restrict__ cnt) {
   __shared__ uint32_t s_w[kWaves][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const SgsXcdWalk wk = sgs_xcd_walk(blockIdx.x, gridDim.x, cfirst[nst]);
   Chunk ch;
   for (int64_t q = wk.first; q < wk.end; q += wk.step) {
-    chunk_of((uint32_t)q, cfirst, nst, st_ranges, SGW, st_per_view, ch);
+    chunk_of((uint32_t)q, cfirst, nst, st_ranges, SGW, vbits, ch);
     uint32_t acc = 0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -775,7 +806,7 @@ k_l2_count(const uint32_t *__restrict__ cfirst, uint32_t nst, const uint2 *__res
 constexpr int kL2ScanWaves = 4;
 __global__ void __launch_bounds__(64 * kL2ScanWaves)
 k_l2_scan(const uint32_t *__restrict__ cfirst, uint32_t *__restrict__ cnt, int GW, int GH,
-          int SGW, uint32_t st_per_view, uint32_t tiles_per_view, uint32_t *__restrict__ tile_cnt) {
+          int SGW, int vbits, int V, uint32_t tiles_per_view, uint32_t *__restrict__ tile_cnt) {
   __shared__ uint32_t s_part[kL2ScanWaves][64];
   const uint32_t g = blockIdx.x;
   const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -809,8 +840,8 @@ k_l2_scan(const uint32_t *__restrict__ cfirst, uint32_t *__restrict__ cnt, int G
         run += c[k];
       }
   }
-  if (w != 0) return;
-  const uint32_t v = g / st_per_view, gs = g - v * st_per_view;
+  const uint32_t v = g & ((1u << vbits) - 1u), gs = g >> vbits;
+  if (w != 0 || v >= (uint32_t)V) return;  // (ids of views >= V hold no items)
   const uint32_t sy = gs / (uint32_t)SGW, sx = gs - sy * (uint32_t)SGW;
   const int tx = 8 * (int)sx + (t & 7), ty = 8 * (int)sy + (t >> 3);
   if (tx < GW && ty < GH) tile_cnt[(int64_t)v * tiles_per_view + (int64_t)ty * GW + tx] = total;
@@ -849,7 +880,7 @@ __global__ void __launch_bounds__(kThreads)
 k_l2_scatter(const uint32_t *__restrict__ cfirst, uint32_t *__restrict__ queue, uint32_t nst,
              const uint2 *__restrict__ st_ranges, const uint32_t *__restrict__ ikey,
              const uint32_t *__restrict__ ival, int GW, int GH, uint32_t tiles_per_view, int SGW,
-             uint32_t st_per_view, const uint32_t *__restrict__ rel,
+             int vbits, const uint32_t *__restrict__ rel,
              const uint32_t *__restrict__ tile_start, int64_t held_static,
              const uint32_t *__restrict__ dheld, uint32_t *__restrict__ vals) {
   __shared__ uint16_t s_out[kL2Out];
@@ -868,7 +899,7 @@ k_l2_scatter(const uint32_t *__restrict__ cfirst, uint32_t *__restrict__ queue, 
     __syncthreads();
     const int64_t q = s_q[it & 1];  // slot it & 1 is written again two rounds on
     if (q >= nchunks) break;
-    chunk_of((uint32_t)q, cfirst, nst, st_ranges, SGW, st_per_view, ch);
+    chunk_of((uint32_t)q, cfirst, nst, st_ranges, SGW, vbits, ch);
     const int tx = ch.tx_base + (lane & 7), ty = ch.ty_base + (lane >> 3);
     // lane t: where tile t's pairs of this chunk start in the output
     uint32_t dst0 = 0;
@@ -1081,12 +1112,16 @@ unsigned resident_blocks(int64_t blocks) {
 // starts in buffer cur0 and *which receives the buffer holding the result.
 hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2], int64_t count,
                              int bits, int *which, const uint32_t *dcount, int shift0,
-                             int cur0, uint32_t **vals2) {
+                             int cur0, uint32_t **vals2, int64_t seg_len) {
   int cur = cur0;
   *which = cur0;
   if (count <= 1 || shift0 >= bits) return hipSuccess;
   const bool small = count <= kSmallSort, v2 = vals2 != nullptr;
   const int64_t tile = radix_tile(count, v2);
+  // segments: whole blocks, a static count
+  if (seg_len && (seg_len % tile != 0 || count % seg_len != 0 || dcount))
+    return hipErrorInvalidValue;
+  const int64_t seg_blocks = seg_len / tile;
   SortBufs b;
   if (!sort_bufs(c, count, b, tile)) return hipErrorInvalidValue;
   for (int shift = shift0; shift < bits; shift += 8) {
@@ -1105,34 +1140,40 @@ hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2], i
     if (small && v2)
       k_radix_scatter<kSmallItems, true><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
           keys[cur], vals[cur], in2, keys[cur ^ 1], vals[cur ^ 1], out2, count, dcount, shift,
-          nb, b.hscan, dtot);
+          nb, b.hscan, dtot, b.total,
+          seg_blocks, seg_len);
     else if (small)
       k_radix_scatter<kSmallItems, false><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
           keys[cur], vals[cur], nullptr, keys[cur ^ 1], vals[cur ^ 1], nullptr, count, dcount,
-          shift, nb, b.hscan, dtot);
+          shift, nb, b.hscan, dtot, b.total,
+          seg_blocks, seg_len);
     else if (v2)
       k_radix_scatter<kV2Items, true><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
           keys[cur], vals[cur], in2, keys[cur ^ 1], vals[cur ^ 1], out2, count, dcount, shift,
-          nb, b.hscan, dtot);
+          nb, b.hscan, dtot, b.total,
+          seg_blocks, seg_len);
     else
       k_radix_scatter<kItems, false><<<(unsigned)b.nb, kThreads, 0, c->stream>>>(
           keys[cur], vals[cur], nullptr, keys[cur ^ 1], vals[cur ^ 1], nullptr, count, dcount,
-          shift, nb, b.hscan, dtot);
+          shift, nb, b.hscan, dtot, b.total,
+          seg_blocks, seg_len);
     cur ^= 1;
   }
   *which = cur;
   return hipGetLastError();
 }
 
-// Depth sort of all (view, Gaussian) splats, the binning records in depth
-// order, then the pair offsets.
+// Depth sort of all (view, Gaussian) splats (view-major: each view's segment
+// sorted on its own), the binning records in that order, then the pair
+// offsets.
 hipError_t launch_depth_order(sgs_ctx *c) {
   int which = 0;
   {
     SgsProfScope ps(c, SGS_PROF_DEPTH_SORT);
-    // the packed tile rectangles ride along as a second value
-    hipError_t e = launch_radix_sort(c, c->depth_key, c->depth_val, c->vn, 32, &which, nullptr,
-                                     0, 0, c->depth_rect);
+    // each view's segment on its own (the order is view, then depth); the
+    // packed tile rectangles ride along as a second value
+    hipError_t e = launch_radix_sort(c, c->depth_key, c->depth_val, c->vn_pad, 32, &which,
+                                     nullptr, 0, 0, c->depth_rect, c->vseg);
     if (e != hipSuccess) return e;
   }
   c->depth_sorted_buf = which;
@@ -1140,17 +1181,18 @@ hipError_t launch_depth_order(sgs_ctx *c) {
   // records and item counts in depth order (item counts -> scratch: the other
   // key buffer is free now), pair counts summed per block of kTile splats
   uint32_t *tmp = c->depth_key[which ^ 1];
-  const int64_t nb = (c->vn + kTile - 1) / kTile;
+  const int64_t nb = (c->vn_pad + kTile - 1) / kTile;
   if (nb > c->scan_tmp_words) return hipErrorInvalidValue;
   if (nb > 0)
     k_gather_bins<<<(unsigned)nb, kThreads, 0, c->stream>>>(
-        c->depth_val[which], c->depth_key[which], c->depth_rect[which], c->bin_splat, c->vn,
-        (uint32_t)c->n, c->GW, (uint32_t)c->tiles_per_view, tmp, c->bin_rec, c->scan_tmp);
+        c->depth_val[which], c->depth_key[which], c->depth_rect[which], c->bin_splat,
+        c->vn_pad, (uint32_t)c->n, c->GW, (uint32_t)c->tiles_per_view, tmp, c->bin_rec,
+        c->scan_tmp);
   // the pair total (with a fixed pair capacity also clamped to it)
   k_scan_sums<<<1, kThreads, 0, c->stream>>>(c->scan_tmp, nb, c->d_pairs_total, nullptr,
                                              c->fixed_cap ? c->cap_limit : -1);
   // the item offsets
-  return launch_exclusive_scan(c, tmp, c->ioffsets, c->vn, c->d_pairs_total + 4,
+  return launch_exclusive_scan(c, tmp, c->ioffsets, c->vn_pad, c->d_pairs_total + 4,
                                c->fixed_cap ? c->cap_limit : -1);
 }
 
@@ -1166,29 +1208,31 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
   const int64_t I = dev ? cap : c->items;   // items (bound; an item has at least one pair)
   const uint32_t *dP = dev ? c->d_pairs_total + 1 : nullptr;
   const uint32_t *dI = dev ? c->d_pairs_total + 5 : nullptr;
-  const uint32_t tpv = (uint32_t)c->tiles_per_view, spv = (uint32_t)c->st_per_view;
-  const uint32_t nst = (uint32_t)c->total_st;
-  int bits = 0;
-  while (((int64_t)1 << bits) < c->total_st) ++bits;
-  int which = 1;
+  const uint32_t tpv = (uint32_t)c->tiles_per_view;
+  const uint32_t nst = (uint32_t)c->st_slots;
+  const int vb = c->st_vbits;
+  int bits = vb;  // the super-tile bits above the view's
+  while (((int64_t)1 << (bits - vb)) < c->st_per_view) ++bits;
+  int which = 0;
   const int64_t chunks = min(c->l2_chunks, l2_chunks_for(I, c->total_st));
   {
     SgsProfScope ps(c, SGS_PROF_TILE_SORT);
-    // items in depth order (buffer 0), stably sorted by super-tile
+    // items in (view, depth) order (buffer 0), stably sorted by the super-tile
+    // in the view
     if (I > 0)
-      k_emit_items<<<sgs_blocks(c->vn, 256), 256, 0, c->stream>>>(
-          c->bin_rec, c->ioffsets, c->vn, I, dI, c->GW, tpv, c->SGW, spv, c->tile_key[0],
+      k_emit_items<<<sgs_blocks(c->vn_pad, 256), 256, 0, c->stream>>>(
+          c->bin_rec, c->ioffsets, c->vn_pad, I, dI, c->GW, tpv, c->SGW, vb, c->tile_key[0],
           c->pair_val[0]);
-    hipError_t e = launch_radix_sort(c, c->tile_key, c->pair_val, I, bits, &which, dI, 0, 0);
+    hipError_t e = launch_radix_sort(c, c->tile_key, c->pair_val, I, bits, &which, dI, vb, 0);
     if (e != hipSuccess) return e;
-    k_st_ranges<<<sgs_blocks(c->total_st, 256), 256, 0, c->stream>>>(c->tile_key[which], I, dI,
-                                                                     nst, c->st_ranges);
-    k_st_chunks<<<1, kThreads, 0, c->stream>>>(c->st_ranges, c->total_st, c->chunk_first);
+    k_st_ranges<<<sgs_blocks(nst, 256), 256, 0, c->stream>>>(c->tile_key[which], I, dI, nst,
+                                                            c->st_ranges);
+    k_st_chunks<<<1, kThreads, 0, c->stream>>>(c->st_ranges, nst, c->chunk_first);
     if (chunks > 0)
       k_l2_count<<<resident_blocks<k_l2_count>(chunks), kThreads, 0, c->stream>>>(
-          c->chunk_first, nst, c->st_ranges, c->tile_key[which], c->SGW, spv, c->l2_cnt);
+          c->chunk_first, nst, c->st_ranges, c->tile_key[which], c->SGW, vb, c->l2_cnt);
     k_l2_scan<<<nst, 64 * kL2ScanWaves, 0, c->stream>>>(c->chunk_first, c->l2_cnt, c->GW, c->GH,
-                                                         c->SGW, spv, tpv, c->tile_cnt);
+                                                         c->SGW, vb, c->V, tpv, c->tile_cnt);
   }
   {
     SgsProfScope ps(c, SGS_PROF_RANGES);
@@ -1202,7 +1246,7 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
     if (chunks > 0)
       k_l2_scatter<<<resident_blocks<k_l2_scatter>(chunks), kThreads, 0, c->stream>>>(
           c->chunk_first, c->chunk_first + nst + 1, nst, c->st_ranges, c->tile_key[which],
-          c->pair_val[which], c->GW, c->GH, tpv, c->SGW, spv, c->l2_cnt, c->tile_start, P,
+          c->pair_val[which], c->GW, c->GH, tpv, c->SGW, vb, c->l2_cnt, c->tile_start, P,
           dP, c->pair_val[which ^ 1]);
   }
   c->pair_sorted_buf = which ^ 1;
