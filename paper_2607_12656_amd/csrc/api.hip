@@ -64,7 +64,6 @@ void free_scene(sgs_ctx *c) {
   c->l2_chunks = 0;
   dfree(c->tile_cnt);
   dfree(c->tile_start);
-  dfree(c->bin_rec);
   dfree(c->bin_splat);
   dfree(c->mlp_f);
   dfree(c->fl_tmp);
@@ -268,7 +267,6 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   SGS_ALLOC(c->chunk_first, c->st_slots + 2);  // + the level-2 scatter's chunk queue
   SGS_ALLOC(c->tile_cnt, c->total_tiles);
   SGS_ALLOC(c->tile_start, c->total_tiles + 1);
-  SGS_ALLOC(c->bin_rec, vnp);
   SGS_ALLOC(c->bin_splat, vn);
   SGS_ALLOC(c->mlp_f, n);
   SGS_ALLOC(c->fl_tmp, fl_scratch_words(n));

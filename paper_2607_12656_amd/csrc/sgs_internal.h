@@ -100,7 +100,6 @@ struct sgs_ctx {
   uint32_t *touched = nullptr;    // [vn] tiles per splat (0 = culled)
   uint4 *bin_splat = nullptr;     // [vn] (first tile id, width in tiles, Gaussian, pairs),
                                   // written only for rectangles depth_rect cannot hold
-  uint4 *bin_rec = nullptr;       // [vn_pad] the same records in (view, depth) order
   double *splat_grad = nullptr;   // [vn][SGS_SGRAD] per-splat gradient sums (FP64 atomics)
   uint32_t *big_idx = nullptr;    // [vn] replica slot of a large splat (see kBigTiles)
   uint32_t *big_list = nullptr;   // [kBigMax + kBigRanges] splat of each slot, then the

@@ -517,20 +517,33 @@ __device__ __forceinline__ uint32_t super_tiles_met(const uint4 &b, uint32_t til
   return (uint32_t)(((r.tx1 >> 3) - (r.tx0 >> 3) + 1) * ((r.ty1 >> 3) - (r.ty0 >> 3) + 1));
 }
 
-// Binning records in depth order, the item count of every splat (input of
-// the item offsets scan), and the pair count of every block of kTile splats
-// (their sum is the pair total; no per-splat pair offset is needed).  The
-// record is rebuilt from the splat index and the tile rectangle the depth
-// sort carried along; only a splat whose rectangle did not fit the packed
-// word has its record gathered (depth order is random in splat index, and
-// every such read fetches a whole cache line), and one whose sorted depth
-// key is the invalid marker gets an empty record.
+// The binning record (first tile id, width in tiles, Gaussian, pairs) of the
+// splat at place i of the depth order, rebuilt from its splat index and the
+// tile rectangle the depth sort carried along; only a splat whose rectangle
+// did not fit the packed word has its record gathered (depth order is
+// random in splat index, and every such read fetches a whole cache line).
+// An invalid splat (or a segment's padding) has an empty record.
+__device__ __forceinline__ uint4 depth_record(int64_t i, const uint32_t *__restrict__ order,
+                                              const uint32_t *__restrict__ dkey,
+                                              const uint32_t *__restrict__ rect,
+                                              const uint4 *__restrict__ bin_splat, uint32_t n,
+                                              int GW, uint32_t tiles_per_view) {
+  if (dkey[i] == 0xFFFFFFFFu) return make_uint4(0u, 1u, 0u, 0u);
+  const uint32_t sp = order[i], r = rect[i];
+  if (r == kNoRect) return bin_splat[sp];
+  const uint32_t v = sp / n, tw = ((r >> 20) & 63u) + 1u, th = (r >> 26) + 1u;
+  return make_uint4(v * tiles_per_view + ((r >> 10) & 1023u) * (uint32_t)GW + (r & 1023u), tw,
+                    sp - v * n, tw * th);
+}
+
+// The item count of every splat in depth order (input of the item offsets
+// scan) and the pair count of every block of kTile splats (their sum is the
+// pair total; no per-splat pair offset is needed).
 __global__ void __launch_bounds__(kThreads)
 k_gather_bins(const uint32_t *__restrict__ order, const uint32_t *__restrict__ dkey,
               const uint32_t *__restrict__ rect, const uint4 *__restrict__ bin_splat,
               int64_t count, uint32_t n, int GW, uint32_t tiles_per_view,
-              uint32_t *__restrict__ icnt, uint4 *__restrict__ brec,
-              uint32_t *__restrict__ psums) {
+              uint32_t *__restrict__ icnt, uint32_t *__restrict__ psums) {
   __shared__ uint64_t s_sum[kWaves];
   const int64_t base = (int64_t)blockIdx.x * kTile;
   uint64_t acc = 0;
@@ -542,25 +555,13 @@ k_gather_bins(const uint32_t *__restrict__ order, const uint32_t *__restrict__ d
 #pragma unroll
     for (int k = 0; k < kHalf; ++k) {
       const int64_t i = base + (int64_t)(h * kHalf + k) * kThreads + threadIdx.x;
-      // the record of an invalid splat, as the projection writes it
-      b[k] = make_uint4(0u, 1u, 0u, 0u);
-      if (i < count && dkey[i] != 0xFFFFFFFFu) {
-        const uint32_t sp = order[i], r = rect[i];
-        if (r != kNoRect) {
-          const uint32_t v = sp / n, tw = ((r >> 20) & 63u) + 1u, th = (r >> 26) + 1u;
-          b[k] = make_uint4(v * tiles_per_view + ((r >> 10) & 1023u) * (uint32_t)GW +
-                                (r & 1023u),
-                            tw, sp - v * n, tw * th);
-        } else {
-          b[k] = bin_splat[sp];
-        }
-      }
+      b[k] = i < count ? depth_record(i, order, dkey, rect, bin_splat, n, GW, tiles_per_view)
+                       : make_uint4(0u, 1u, 0u, 0u);
     }
 #pragma unroll
     for (int k = 0; k < kHalf; ++k) {
       const int64_t i = base + (int64_t)(h * kHalf + k) * kThreads + threadIdx.x;
       if (i < count) {
-        brec[i] = b[k];
         acc += b[k].w;
         icnt[i] = b[k].w ? super_tiles_met(b[k], tiles_per_view, GW) : 0u;
       }
@@ -595,14 +596,16 @@ constexpr uint32_t kStMask = (1u << kStBits) - 1u;
 // super-tile id | covered tile rectangle inside it (see kStBits), value =
 // Gaussian index.  Items at or beyond the live item count (a capacity) are
 // not written.
-__global__ void k_emit_items(const uint4 *__restrict__ brec, const uint32_t *__restrict__ ioff,
-                             int64_t vn, int64_t count_static, const uint32_t *__restrict__ dcount,
-                             int GW, uint32_t tiles_per_view, int SGW, int vbits,
+__global__ void k_emit_items(const uint32_t *__restrict__ order, const uint32_t *__restrict__ dkey,
+                             const uint32_t *__restrict__ rect,
+                             const uint4 *__restrict__ bin_splat, uint32_t n,
+                             const uint32_t *__restrict__ ioff, int64_t vn, int64_t count_static,
+                             const uint32_t *__restrict__ dcount, int GW,
+                             uint32_t tiles_per_view, int SGW, int vbits,
                              uint32_t *__restrict__ kout, uint32_t *__restrict__ vout) {
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (d >= vn) return;
-  const uint4 b = brec[d];
-  if (b.w == 0) return;
+  if (d >= vn || dkey[d] == 0xFFFFFFFFu) return;
+  const uint4 b = depth_record(d, order, dkey, rect, bin_splat, n, GW, tiles_per_view);
   const int64_t count = dcount ? (int64_t)*dcount : count_static;
   int64_t o = ioff[d];
   const TileRect r = tile_rect(b, tiles_per_view, GW);
@@ -1164,8 +1167,8 @@ hipError_t launch_radix_sort(sgs_ctx *c, uint32_t *keys[2], uint32_t *vals[2], i
 }
 
 // Depth sort of all (view, Gaussian) splats (view-major: each view's segment
-// sorted on its own), the binning records in that order, then the pair
-// offsets.
+// sorted on its own), the item counts in that order and their offsets, and
+// the pair total.
 hipError_t launch_depth_order(sgs_ctx *c) {
   int which = 0;
   {
@@ -1178,16 +1181,15 @@ hipError_t launch_depth_order(sgs_ctx *c) {
   }
   c->depth_sorted_buf = which;
   SgsProfScope ps(c, SGS_PROF_SCAN);
-  // records and item counts in depth order (item counts -> scratch: the other
-  // key buffer is free now), pair counts summed per block of kTile splats
+  // item counts in depth order (-> scratch: the other key buffer is free
+  // now), pair counts summed per block of kTile splats
   uint32_t *tmp = c->depth_key[which ^ 1];
   const int64_t nb = (c->vn_pad + kTile - 1) / kTile;
   if (nb > c->scan_tmp_words) return hipErrorInvalidValue;
   if (nb > 0)
     k_gather_bins<<<(unsigned)nb, kThreads, 0, c->stream>>>(
         c->depth_val[which], c->depth_key[which], c->depth_rect[which], c->bin_splat,
-        c->vn_pad, (uint32_t)c->n, c->GW, (uint32_t)c->tiles_per_view, tmp, c->bin_rec,
-        c->scan_tmp);
+        c->vn_pad, (uint32_t)c->n, c->GW, (uint32_t)c->tiles_per_view, tmp, c->scan_tmp);
   // the pair total (with a fixed pair capacity also clamped to it)
   k_scan_sums<<<1, kThreads, 0, c->stream>>>(c->scan_tmp, nb, c->d_pairs_total, nullptr,
                                              c->fixed_cap ? c->cap_limit : -1);
@@ -1210,6 +1212,7 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
   const uint32_t *dI = dev ? c->d_pairs_total + 5 : nullptr;
   const uint32_t tpv = (uint32_t)c->tiles_per_view;
   const uint32_t nst = (uint32_t)c->st_slots;
+  const int ds = c->depth_sorted_buf;
   const int vb = c->st_vbits;
   int bits = vb;  // the super-tile bits above the view's
   while (((int64_t)1 << (bits - vb)) < c->st_per_view) ++bits;
@@ -1221,7 +1224,8 @@ hipError_t launch_bin_pairs(sgs_ctx *c) {
     // in the view
     if (I > 0)
       k_emit_items<<<sgs_blocks(c->vn_pad, 256), 256, 0, c->stream>>>(
-          c->bin_rec, c->ioffsets, c->vn_pad, I, dI, c->GW, tpv, c->SGW, vb, c->tile_key[0],
+          c->depth_val[ds], c->depth_key[ds], c->depth_rect[ds], c->bin_splat, (uint32_t)c->n,
+          c->ioffsets, c->vn_pad, I, dI, c->GW, tpv, c->SGW, vb, c->tile_key[0],
           c->pair_val[0]);
     hipError_t e = launch_radix_sort(c, c->tile_key, c->pair_val, I, bits, &which, dI, vb, 0);
     if (e != hipSuccess) return e;
