@@ -782,14 +782,27 @@ k_l2_count(const uint32_t *__restrict__ cfirst, uint32_t nst, const uint2 *__res
   __shared__ uint32_t s_w[kWaves][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const SgsXcdWalk wk = sgs_xcd_walk(blockIdx.x, gridDim.x, cfirst[nst]);
-  Chunk ch;
+  // a chunk's keys (0xFFFFFFFF: no item), loaded one chunk ahead
+  auto keys_of = [&](int64_t q, uint32_t (&k)[4]) {
+    Chunk ch;
+    const bool live = q < wk.end && chunk_of((uint32_t)q, cfirst, nst, st_ranges, SGW, vbits, ch);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t idx = live ? ch.first + (uint32_t)(wave * 256 + r * 64 + lane) : 0u;
+      k[r] = live && idx < ch.end ? ikey[idx] : 0xFFFFFFFFu;
+    }
+  };
+  uint32_t kn[4];
+  keys_of(wk.first, kn);
   for (int64_t q = wk.first; q < wk.end; q += wk.step) {
-    chunk_of((uint32_t)q, cfirst, nst, st_ranges, SGW, vbits, ch);
+    uint32_t kr[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) kr[r] = kn[r];
+    keys_of(q + wk.step, kn);
     uint32_t acc = 0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const uint32_t idx = ch.first + (uint32_t)(wave * 256 + r * 64 + lane);
-      const uint64_t m = idx < ch.end ? item_mask(ikey[idx]) : 0ull;
+      const uint64_t m = kr[r] == 0xFFFFFFFFu ? 0ull : item_mask(kr[r]);
       // lane t: the round's items covering tile t
       acc += (uint32_t)__popcll(wave_transpose64(m, lane));
     }
@@ -894,28 +907,41 @@ k_l2_scatter(const uint32_t *__restrict__ cfirst, uint32_t *__restrict__ queue, 
   const uint32_t held = (uint32_t)(dheld ? (int64_t)*dheld : held_static);
   const uint32_t nchunks = cfirst[nst];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  Chunk ch;
-  // chunks from the queue, one per workgroup at a time (their work varies
-  // with the items' footprints; a fixed share per workgroup left a tail)
-  for (uint32_t it = 0;; ++it) {
-    if (threadIdx.x == 0) s_q[it & 1] = atomicAdd(queue, 1u);
-    __syncthreads();
-    const int64_t q = s_q[it & 1];  // slot it & 1 is written again two rounds on
-    if (q >= nchunks) break;
-    chunk_of((uint32_t)q, cfirst, nst, st_ranges, SGW, vbits, ch);
+  // a chunk's inputs: lane t's tile start in the output (dst0) and the
+  // wave's keys (0xFFFFFFFF: no item) and Gaussian indices of its four rounds
+  auto chunk_in = [&](int64_t q, uint32_t &dst0, uint32_t (&key)[4], uint32_t (&gid)[4]) {
+    Chunk ch;
+    const bool live = q < nchunks && chunk_of((uint32_t)q, cfirst, nst, st_ranges, SGW, vbits, ch);
     const int tx = ch.tx_base + (lane & 7), ty = ch.ty_base + (lane >> 3);
-    // lane t: where tile t's pairs of this chunk start in the output
-    uint32_t dst0 = 0;
-    if (tx < GW && ty < GH)
+    dst0 = 0;
+    if (live && tx < GW && ty < GH)
       dst0 = tile_start[(int64_t)ch.view * tiles_per_view + (int64_t)ty * GW + tx] +
-             rel[(int64_t)q * 64 + lane];
-    uint32_t key[4], gid[4];
+             rel[q * 64 + lane];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {  // all four rounds' loads in flight at once
-      const uint32_t idx = ch.first + (uint32_t)(wave * 256 + r * 64 + lane);
-      const bool ok = idx < ch.end;
-      key[r] = ok ? ikey[idx] : 0xFFFFFFFFu;  // no item: empty mask below
+      const uint32_t idx = live ? ch.first + (uint32_t)(wave * 256 + r * 64 + lane) : 0u;
+      const bool ok = live && idx < ch.end;
+      key[r] = ok ? ikey[idx] : 0xFFFFFFFFu;
       gid[r] = ok ? ival[idx] : 0u;
+    }
+  };
+  // chunks from the queue, one per workgroup at a time (their work varies
+  // with the items' footprints; a fixed share per workgroup left a tail);
+  // the next chunk's ticket and inputs are fetched while one is worked on
+  if (threadIdx.x == 0) s_q[0] = atomicAdd(queue, 1u);
+  __syncthreads();
+  int64_t q = s_q[0];
+  uint32_t dst0n, keyn[4], gidn[4];
+  chunk_in(q, dst0n, keyn, gidn);
+  for (uint32_t it = 0; q < nchunks; ++it) {
+    // slot (it + 1) & 1 was last read two chunks ago, before this chunk's barriers
+    if (threadIdx.x == 0) s_q[(it + 1) & 1] = atomicAdd(queue, 1u);
+    const uint32_t dst0 = dst0n;
+    uint32_t key[4], gid[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      key[r] = keyn[r];
+      gid[r] = gidn[r];
     }
     uint64_t col[4];  // lane t: the round's items covering tile t (bit L: lane L's item)
 #pragma unroll
@@ -925,6 +951,8 @@ k_l2_scatter(const uint32_t *__restrict__ cfirst, uint32_t *__restrict__ queue, 
       s_cnt[wave][r][lane] = (uint16_t)__popcll(col[r]);
     }
     __syncthreads();
+    const int64_t qn = s_q[(it + 1) & 1];
+    chunk_in(qn, dst0n, keyn, gidn);
     // lane t: the tile's pairs in this chunk, and in its earlier waves
     uint32_t tot = 0, before = 0;
 #pragma unroll
@@ -990,6 +1018,7 @@ k_l2_scatter(const uint32_t *__restrict__ cfirst, uint32_t *__restrict__ queue, 
       base = end;
       t0 = t1;
     }
+    q = qn;
   }
 }
 
