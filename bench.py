@@ -100,17 +100,19 @@ def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int, items: in
     if g == "depth_sort":         # four 8-bit passes, each one read + one write of key,
         # value and the packed tile rectangle carried along
         return "hbm", V * n * 4 * 24, "B"
-    if g == "scan":               # sorted key, index and rectangle read (4 + 4 + 4), binning
-        # record written in depth order (16), item count written (4), item offsets scanned
-        # (4 + 4 read, 4 written); the few records gathered instead are not counted
-        return "hbm", V * n * 44, "B"
+    if g == "scan":               # sorted key, index and rectangle read (4 + 4 + 4), item
+        # count written (4), item offsets scanned (4 + 4 read, 4 written); the few records
+        # gathered instead of rebuilt are not counted
+        return "hbm", V * n * 28, "B"
     if g == "duplicate":          # every pair written once (4 B); per item its key and
         # Gaussian index read (8 B)
         return "hbm", P * 4 + items * 8, "B"
-    if g == "tile_sort":          # items generated and sorted by super-tile (8 B written,
-        # 16 B per further 8-bit pass), then read for the tile counts (4 + 16)
-        extra = max(0, (max(st - 1, 1).bit_length() - 1) // 8)
-        return "hbm", items * (8 + 16 * extra + 20), "B"
+    if g == "tile_sort":          # items emitted (sorted key, index, rectangle and item
+        # offset read per splat, 8 B written per item), sorted by the super-tile in the view
+        # (one 8-bit pass per 8 bits of it: 4 B histogram read, 16 B moved), keys read for
+        # the tile counts (4)
+        passes = max(1, -(-max(st // V - 1, 1).bit_length() // 8))
+        return "hbm", V * n * 16 + items * (8 + 20 * passes + 4), "B"
     if g == "ranges":             # tile counts read, offsets and ranges written
         return "hbm", tiles * 16, "B"
     if g == "blend_fwd":
@@ -122,8 +124,9 @@ def group_work(g: str, n: int, V: int, P: int, E: int, W: int, H: int, items: in
     if g == "blend_bwd":
         return "alu", E * FLOP_PER_EVAL_BWD, "FLOP"
     if g == "preprocess_bwd":     # parameters read, gradient rows written, mask and score
-        # gradients written; per view the 80-byte splat gradient record read
-        return "hbm", int(n * (NCH * 4 + rows * 4 + 4 + 4) + V * n * 80), "B"
+        # gradients written; per view the 80-byte splat gradient record and the tile count
+        # (whether the splat was kept) read
+        return "hbm", int(n * (NCH * 4 + rows * 4 + 4 + 4) + V * n * (80 + 4)), "B"
     if g == "fakequant_bwd":
         return "hbm", NCH * 8 * -(-n // 128), "B"
     if g == "adam":               # per iteration of the higher-SH period: the rows
@@ -162,7 +165,8 @@ def roofline(g, ms, n, V, P, E, W, H, traffic_key=None, items=0, tiles=0, st=1, 
 
 def traffic_for(key):
     """HBM bytes per launch measured with rocprofv3 counters for this kernel
-    group and workload, valid while its sources are unchanged."""
+    group, workload, tile shape and blend schedule (key "c5:group@16x16/tile"),
+    valid while its sources are unchanged."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -492,7 +496,8 @@ def bench_formation(args, sc, ctx, stream, dev, t):
     dom = max(L["kernel_ms"], key=L["kernel_ms"].get)
     roof = roofline(dom, L["kernel_ms"][dom], sc.n, sc.views, L["pairs_last"],
                     L["evals_after_reach_test"] // K, sc.width, sc.height,
-                    traffic_key=f"c5:{dom}", items=L["items_last"], sh_every=SH_EVERY, **geo)
+                    traffic_key=f"c5:{dom}@{tile[0]}x{tile[1]}/{schedule}",
+                    items=L["items_last"], sh_every=SH_EVERY, **geo)
     groups = {g: roofline(g, ms, sc.n, sc.views, L["pairs_last"],
                           L["evals_after_reach_test"] // K, sc.width, sc.height,
                           items=L["items_last"], kept=L["kept_last"], sh_every=SH_EVERY,
@@ -601,7 +606,8 @@ def bench_rd(args, sc, ctx, stream, dev, t, extras: bool, tile, schedule, tune=N
     geo = geometry(sc, tile)
     dom = max(kernels, key=kernels.get)
     roof = roofline(dom, kernels[dom], sc.n, sc.views, P, Er, sc.width, sc.height,
-                    traffic_key=f"{args.workload if args.workload != 'c5' else 'c2'}:{dom}",
+                    traffic_key=f"{args.workload if args.workload != 'c5' else 'c2'}:{dom}"
+                                f"@{tile[0]}x{tile[1]}/{schedule}",
                     items=items, **geo)
     groups = {g: roofline(g, ms, sc.n, sc.views, P, Er, sc.width, sc.height, items=items, **geo)
               for g, ms in kernels.items()}
