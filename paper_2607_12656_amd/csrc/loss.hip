@@ -46,8 +46,15 @@ k_l1(const float *__restrict__ img, const float *__restrict__ tgt, int64_t count
 __global__ void k_l1_finish(const double *__restrict__ partial, int nb, int64_t count,
                             float *__restrict__ loss) {
   __shared__ double s_w[kThreads / 64];
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kThreads) acc += partial[b];
+  // eight loads in flight per thread (a loop-carried sum would wait on each)
+  double a8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int b = threadIdx.x;
+  for (; b + 7 * kThreads < nb; b += 8 * kThreads) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a8[u] += partial[b + u * kThreads];
+  }
+  for (; b < nb; b += kThreads) a8[0] += partial[b];
+  double acc = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
   acc = sgs_wave_sum_d(acc);
   if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
   __syncthreads();

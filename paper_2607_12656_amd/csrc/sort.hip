@@ -74,16 +74,36 @@ k_scan_reduce(const uint32_t *__restrict__ in, int64_t count, uint32_t *__restri
 __global__ void __launch_bounds__(kThreads)
 k_scan_sums(uint32_t *__restrict__ sums, int64_t nb, uint32_t *__restrict__ total_out,
             uint32_t *__restrict__ tail, int64_t cap) {
-  __shared__ uint32_t s_wave[kWaves];
-  uint64_t carry = 0;  // a block sum fits in 32 bits, the total may not
-  for (int64_t base = 0; base < nb; base += kThreads) {
-    const int64_t i = base + threadIdx.x;
-    const uint32_t v = i < nb ? sums[i] : 0;
-    uint32_t total;
-    const uint32_t ex = block_exclusive_scan(v, s_wave, total);
-    if (i < nb) sums[i] = (uint32_t)(carry + ex);
-    carry += total;
+  __shared__ uint64_t s_wave[kWaves];
+  __shared__ uint64_t s_total;
+  // each thread a run of consecutive sums (its loads in flight together),
+  // the runs' totals scanned over the workgroup in 64 bits (a block sum fits
+  // in 32 bits, the total may not), then the run rewritten
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t per = (nb + kThreads - 1) / kThreads;
+  const int64_t b0 = min(nb, (int64_t)threadIdx.x * per), b1 = min(nb, b0 + per);
+  uint64_t s = 0;
+#pragma unroll 8
+  for (int64_t b = b0; b < b1; ++b) s += sums[b];
+  uint64_t x = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t t = __shfl_up(x, o, 64);
+    if (lane >= o) x += t;
   }
+  if (lane == 63) s_wave[wave] = x;
+  __syncthreads();
+  uint64_t run = x - s;
+  for (int w = 0; w < wave; ++w) run += s_wave[w];
+  if (threadIdx.x == kThreads - 1) s_total = run + s;
+#pragma unroll 8
+  for (int64_t b = b0; b < b1; ++b) {
+    const uint32_t v = sums[b];
+    sums[b] = (uint32_t)run;
+    run += v;
+  }
+  __syncthreads();
+  const uint64_t carry = s_total;
   if (threadIdx.x == 0) {
     const uint32_t t = carry >= kPairsSaturated ? kPairsSaturated : (uint32_t)carry;
     if (total_out) *total_out = t;
