@@ -307,7 +307,8 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
 #undef SGS_ALLOC
   const int64_t hist = radix_hist_words(vnp);
   // block sums of the scans over splats and over tiles
-  const int64_t scan = ((vnp > c->total_tiles ? vnp : c->total_tiles) + 4095) / 4096 + 1;
+  // (twice the splats' blocks: pair and item sums of the depth order)
+  const int64_t scan = 2 * (((vnp > c->total_tiles ? vnp : c->total_tiles) + 4095) / 4096 + 1);
   e = ensure_tmp(c, scan, hist);
   if (e != hipSuccess) { free_scene(c); return hip_fail(c, e, "set_scene alloc"); }
   // initial pair capacity: 4 tiles per splat

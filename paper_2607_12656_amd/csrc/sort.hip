@@ -557,16 +557,20 @@ __device__ __forceinline__ uint4 depth_record(int64_t i, const uint32_t *__restr
 }
 
 // The item count of every splat in depth order (input of the item offsets
-// scan) and the pair count of every block of kTile splats (their sum is the
-// pair total; no per-splat pair offset is needed).
+// scan), and per block of kTile splats the pair count (their sum is the pair
+// total; no per-splat pair offset is needed) and the item count (the block
+// sums of the item offsets scan).
 __global__ void __launch_bounds__(kThreads)
 k_gather_bins(const uint32_t *__restrict__ order, const uint32_t *__restrict__ dkey,
               const uint32_t *__restrict__ rect, const uint4 *__restrict__ bin_splat,
               int64_t count, uint32_t n, int GW, uint32_t tiles_per_view,
-              uint32_t *__restrict__ icnt, uint32_t *__restrict__ psums) {
+              uint32_t *__restrict__ icnt, uint32_t *__restrict__ psums,
+              uint32_t *__restrict__ isums) {
   __shared__ uint64_t s_sum[kWaves];
+  __shared__ uint32_t s_isum[kWaves];
   const int64_t base = (int64_t)blockIdx.x * kTile;
   uint64_t acc = 0;
+  uint32_t iacc = 0;
   // eight records at a time (a gathered one waits on two loads before it)
   constexpr int kHalf = kItems / 2;
 #pragma unroll
@@ -583,20 +587,33 @@ k_gather_bins(const uint32_t *__restrict__ order, const uint32_t *__restrict__ d
       const int64_t i = base + (int64_t)(h * kHalf + k) * kThreads + threadIdx.x;
       if (i < count) {
         acc += b[k].w;
-        icnt[i] = b[k].w ? super_tiles_met(b[k], tiles_per_view, GW) : 0u;
+        const uint32_t ic = b[k].w ? super_tiles_met(b[k], tiles_per_view, GW) : 0u;
+        icnt[i] = ic;
+        iacc += ic;
       }
     }
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = acc;
+  for (int o = 32; o > 0; o >>= 1) {
+    acc += __shfl_xor(acc, o, 64);
+    iacc += (uint32_t)__shfl_xor((int)iacc, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_sum[threadIdx.x >> 6] = acc;
+    s_isum[threadIdx.x >> 6] = iacc;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     uint64_t t = 0;
+    uint32_t it = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) t += s_sum[w];
+    for (int w = 0; w < kWaves; ++w) {
+      t += s_sum[w];
+      it += s_isum[w];
+    }
     // a saturated block sum saturates the total (k_scan_sums)
     psums[blockIdx.x] = t >= kPairsSaturated ? kPairsSaturated : (uint32_t)t;
+    isums[blockIdx.x] = it;  // at most 4096 splats x the super-tiles of a view
   }
 }
 
@@ -1234,17 +1251,19 @@ hipError_t launch_depth_order(sgs_ctx *c) {
   // now), pair counts summed per block of kTile splats
   uint32_t *tmp = c->depth_key[which ^ 1];
   const int64_t nb = (c->vn_pad + kTile - 1) / kTile;
-  if (nb > c->scan_tmp_words) return hipErrorInvalidValue;
-  if (nb > 0)
-    k_gather_bins<<<(unsigned)nb, kThreads, 0, c->stream>>>(
-        c->depth_val[which], c->depth_key[which], c->depth_rect[which], c->bin_splat,
-        c->vn_pad, (uint32_t)c->n, c->GW, (uint32_t)c->tiles_per_view, tmp, c->scan_tmp);
+  if (nb == 0 || 2 * nb > c->scan_tmp_words) return hipErrorInvalidValue;
+  uint32_t *psums = c->scan_tmp, *isums = c->scan_tmp + nb;
+  k_gather_bins<<<(unsigned)nb, kThreads, 0, c->stream>>>(
+      c->depth_val[which], c->depth_key[which], c->depth_rect[which], c->bin_splat, c->vn_pad,
+      (uint32_t)c->n, c->GW, (uint32_t)c->tiles_per_view, tmp, psums, isums);
   // the pair total (with a fixed pair capacity also clamped to it)
-  k_scan_sums<<<1, kThreads, 0, c->stream>>>(c->scan_tmp, nb, c->d_pairs_total, nullptr,
-                                             c->fixed_cap ? c->cap_limit : -1);
-  // the item offsets
-  return launch_exclusive_scan(c, tmp, c->ioffsets, c->vn_pad, c->d_pairs_total + 4,
-                               c->fixed_cap ? c->cap_limit : -1);
+  const int64_t cap = c->fixed_cap ? c->cap_limit : -1;
+  k_scan_sums<<<1, kThreads, 0, c->stream>>>(psums, nb, c->d_pairs_total, nullptr, cap);
+  // the item offsets (an exclusive scan whose block sums the gather wrote)
+  k_scan_sums<<<1, kThreads, 0, c->stream>>>(isums, nb, c->d_pairs_total + 4,
+                                             c->ioffsets + c->vn_pad, cap);
+  k_scan_down<<<(unsigned)nb, kThreads, 0, c->stream>>>(tmp, c->vn_pad, isums, c->ioffsets);
+  return hipGetLastError();
 }
 
 // Items -> super-tile sort -> per-super-tile tile counts -> tile offsets and
