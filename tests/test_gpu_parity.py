@@ -214,6 +214,10 @@ TINY = [
     # dense: one super-tile's chunk of items holds several times the pairs the
     # pair scatter stages in LDS at once (its tiles are taken in groups)
     dict(n=1500, W=128, H=128, V=1, seed=7, logscale=-1.4, dense=True),
+    # three views: the view bits of the super-tile ids leave ids with no view
+    # (view 3), and the depth order's segments are padded (n not a multiple
+    # of 2048)
+    dict(n=300, W=150, H=100, V=3, seed=12),
 ]
 BIG_TILES = 512   # the library's large-splat threshold (tiles per rectangle)
 L2_OUT = 12288    # pairs the library's pair scatter stages in LDS at once
