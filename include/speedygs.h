@@ -69,7 +69,7 @@ typedef struct {
 } sgs_camera;
 
 typedef struct {
-  int32_t tile_w, tile_h; /* blend tile: 8x8, 16x16 (default) or 32x8 */
+  int32_t tile_w, tile_h; /* blend tile: 8x8, 16x16 (default), 32x8, 32x16 or 32x32 */
   float tau;              /* Gumbel-sigmoid temperature (default 1) */
   int32_t schedule;       /* blend launch (one wave per 8x8 sub-tile): 0 one
                              workgroup per sub-tile (default), 1 resident
@@ -209,11 +209,12 @@ sgs_status sgs_quant_render_bwd(sgs_ctx *ctx, const float *params, const float *
  * `reps` (1..1000) whole RD steps (sgs_quant_render_fwd on the given mask,
  * sgs_rate_proxy, sgs_l1_loss, sgs_quant_render_bwd) per candidate with HIP
  * events on the context's stream, after one untimed step each: the tile
- * shapes 16x16, 8x8 and 32x8 with schedule 0, then schedules 1, 2 and 3 with
+ * shapes 16x16, 8x8, 32x8, 32x16 and 32x32 with schedule 0, then schedules
+ * 1, 2 and 3 with
  * the fastest shape.  *chosen (host) receives the fastest options (tau kept)
  * and the context is left bound to the same scene with them; a reserved pair
  * capacity is released (call sgs_reserve_pairs again).  ms_out (host
- * float[6], may be NULL) receives each candidate's mean step time in the
+ * float[8], may be NULL) receives each candidate's mean step time in the
  * order timed.  The images and gradients do not depend on the choice (the
  * support rule is pixel-exact, Sec. 3.1 binning).  Needs params rows 16-byte
  * aligned, target [V][3][H][W]; allocates temporary device buffers for the

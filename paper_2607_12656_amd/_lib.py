@@ -311,7 +311,7 @@ class Context:
         """sgs_autotune: returns ((tile_w, tile_h), schedule name, [ms per
         candidate in the order timed]); the context stays bound with the choice."""
         opt = sgs_options()
-        ms = (C.c_float * 6)()
+        ms = (C.c_float * 8)()
         self._check(self.L.sgs_autotune(self.h, _ptr(params), _ptr(qstep), _ptr(given_mask),
                                         _ptr(target), int(reps), C.byref(opt), ms), self.h)
         names = {v: k for k, v in SCHEDULES.items()}

@@ -20,7 +20,7 @@ from __future__ import annotations
 import json
 import os
 
-CANDIDATES = ((16, 16), (8, 8), (32, 8))
+CANDIDATES = ((16, 16), (8, 8), (32, 8), (32, 16), (32, 32))
 SCHEDULES = ("tile", "stride", "queue", "block")
 
 

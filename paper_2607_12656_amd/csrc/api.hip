@@ -210,8 +210,9 @@ sgs_status sgs_set_scene(sgs_ctx *c, int64_t n, int64_t npad, int64_t n_hat,
   }
   if (det != 0 && det != 1) return fail(c, SGS_EINVAL, "set_scene: deterministic must be 0 or 1");
   if (schedule < 0 || schedule > 3) return fail(c, SGS_EINVAL, "set_scene: schedule must be 0 to 3");
-  if (!((tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 32 && th == 8)))
-    return fail(c, SGS_EINVAL, "set_scene: tile shape must be 8x8, 16x16 or 32x8");
+  if (!((tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 32 && th == 8) ||
+        (tw == 32 && th == 16) || (tw == 32 && th == 32)))
+    return fail(c, SGS_EINVAL, "set_scene: tile shape must be 8x8, 16x16, 32x8, 32x16 or 32x32");
   if (!(tau > 0.0f)) return fail(c, SGS_EINVAL, "set_scene: tau must be > 0");
   SGS_HIP(hipSetDevice(c->device), "hipSetDevice");
   if (c->stream) SGS_HIP(hipStreamSynchronize(c->stream), "sync"); else SGS_HIP(hipDeviceSynchronize(), "sync");
@@ -863,8 +864,9 @@ sgs_status sgs_autotune(sgs_ctx *c, const float *params, const float *qstep,
   float *dimage = at(6), *gp = at(7), *gq = at(8), *gs = at(9), *gm = at(10);
   float *loss = at(11), *rate3 = at(12), *rgrad = at(13);
   struct Cand { int tw, th, sched; };
-  const Cand tiles[3] = {{16, 16, 0}, {8, 8, 0}, {32, 8, 0}};
-  float times[6] = {0};
+  constexpr int kShapes = 5;
+  const Cand tiles[kShapes] = {{16, 16, 0}, {8, 8, 0}, {32, 8, 0}, {32, 16, 0}, {32, 32, 0}};
+  float times[kShapes + 3] = {0};
   int ntimed = 0;
   hipEvent_t ea = nullptr, eb = nullptr;
   sgs_status st = SGS_OK;
@@ -903,7 +905,7 @@ sgs_status sgs_autotune(sgs_ctx *c, const float *params, const float *qstep,
   if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) {
     st = fail(c, SGS_EHIP, "autotune events");
   }
-  for (int k = 0; k < 3 && st == SGS_OK; ++k) {
+  for (int k = 0; k < kShapes && st == SGS_OK; ++k) {
     st = run(tiles[k], &times[ntimed]);
     if (st == SGS_OK && (ntimed == 0 || times[ntimed] < best_ms)) {
       best = tiles[k];
@@ -942,7 +944,7 @@ sgs_status sgs_autotune(sgs_ctx *c, const float *params, const float *qstep,
   if (rb != SGS_OK) return rb;
   *chosen = o;
   if (ms_out)
-    for (int k = 0; k < 6; ++k) ms_out[k] = times[k];
+    for (int k = 0; k < kShapes + 3; ++k) ms_out[k] = times[k];
   return SGS_OK;
 }
 

@@ -713,7 +713,11 @@ template <int TW, int TH>
 hipError_t fwd_s(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint64_t *ec) {
   SgsProfScope ps(c, SGS_PROF_BLEND_FWD);
   if (c->schedule == kStride) return fwd_t<TW, TH, kStride>(c, image, final_T, last, ec);
-  if (c->schedule == kTileBlock) return fwd_t<TW, TH, kTileBlock>(c, image, final_T, last, ec);
+  if (c->schedule == kTileBlock) {
+    // one workgroup per tile: at most 1024 pixels
+    if constexpr (TW * TH <= 1024) return fwd_t<TW, TH, kTileBlock>(c, image, final_T, last, ec);
+    return hipErrorInvalidValue;
+  }
   if (c->schedule == kQueue) return fwd_t<TW, TH, kQueue>(c, image, final_T, last, ec);
   return fwd_t<TW, TH, kPerTile>(c, image, final_T, last, ec);
 }
@@ -721,7 +725,10 @@ hipError_t fwd_s(sgs_ctx *c, float *image, float *final_T, uint32_t *last, uint6
 template <int TW, int TH>
 hipError_t bwd_s(sgs_ctx *c, const float *final_T, const uint32_t *last, const float *dimg) {
   if (c->schedule == kStride) return bwd_t<TW, TH, kStride>(c, final_T, last, dimg);
-  if (c->schedule == kTileBlock) return bwd_t<TW, TH, kTileBlock>(c, final_T, last, dimg);
+  if (c->schedule == kTileBlock) {
+    if constexpr (TW * TH <= 1024) return bwd_t<TW, TH, kTileBlock>(c, final_T, last, dimg);
+    return hipErrorInvalidValue;
+  }
   if (c->schedule == kQueue) return bwd_t<TW, TH, kQueue>(c, final_T, last, dimg);
   return bwd_t<TW, TH, kPerTile>(c, final_T, last, dimg);
 }
@@ -824,6 +831,8 @@ hipError_t launch_blend_fwd(sgs_ctx *c, float *image, float *final_T, uint32_t *
   if (c->TW == 16 && c->TH == 16) return fwd_s<16, 16>(c, image, final_T, last, eval_count);
   if (c->TW == 8 && c->TH == 8) return fwd_s<8, 8>(c, image, final_T, last, eval_count);
   if (c->TW == 32 && c->TH == 8) return fwd_s<32, 8>(c, image, final_T, last, eval_count);
+  if (c->TW == 32 && c->TH == 16) return fwd_s<32, 16>(c, image, final_T, last, eval_count);
+  if (c->TW == 32 && c->TH == 32) return fwd_s<32, 32>(c, image, final_T, last, eval_count);
   return hipErrorInvalidValue;
 }
 
@@ -849,6 +858,8 @@ hipError_t launch_blend_bwd(sgs_ctx *c, const float *final_T, const uint32_t *la
   if (c->TW == 16 && c->TH == 16) e = bwd_s<16, 16>(c, final_T, last, dimg);
   if (c->TW == 8 && c->TH == 8) e = bwd_s<8, 8>(c, final_T, last, dimg);
   if (c->TW == 32 && c->TH == 8) e = bwd_s<32, 8>(c, final_T, last, dimg);
+  if (c->TW == 32 && c->TH == 16) e = bwd_s<32, 16>(c, final_T, last, dimg);
+  if (c->TW == 32 && c->TH == 32) e = bwd_s<32, 32>(c, final_T, last, dimg);
   if (e != hipSuccess) return e;
   if (!c->deterministic) {
     k_big_fold<<<sgs_blocks(kBigMax * SGS_SGRAD, 256), 256, 0, c->stream>>>(

@@ -200,7 +200,7 @@ def test_autotuner_choice_and_cache(orc, gctx, dev, tmp_path):
 
 
 def test_native_autotuner(orc, gctx, dev):
-    """sgs_autotune: six candidates timed (three tile shapes, then three more
+    """sgs_autotune: eight candidates timed (five tile shapes, then three more
     schedules with the fastest shape), the fastest chosen, the context left
     bound with it, and that binding renders the image the oracle renders."""
     from paper_2607_12656_amd import autotune
@@ -211,7 +211,7 @@ def test_native_autotuner(orc, gctx, dev):
     res = autotune.tune_native(gctx, params, q, mask, target, sc.n, sc.views, sc.width,
                                sc.height, reps=2)
     ms = res["ms"]
-    assert len(ms) == 6 and all(v > 0 for v in ms.values())
+    assert len(ms) == 8 and all(v > 0 for v in ms.values())
     best = f"{res['tile'][0]}x{res['tile'][1]}/{res['schedule']}"
     assert ms[best] == min(ms.values())
     # the context is bound with the choice: a step renders the oracle's image

@@ -223,7 +223,7 @@ BIG_TILES = 512   # the library's large-splat threshold (tiles per rectangle)
 L2_OUT = 12288    # pairs the library's pair scatter stages in LDS at once
 
 
-@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8), (32, 16), (32, 32)])
 @pytest.mark.parametrize("cfg", range(len(TINY)))
 def test_tiny_scenes_full_step(orc, gctx, dev, tile, cfg):
     c = TINY[cfg]
@@ -234,14 +234,14 @@ def test_tiny_scenes_full_step(orc, gctx, dev, tile, cfg):
     check_stats(g, r, sc)
     check_image(g, r)
     check_l1(g, r, sc)
-    if c.get("big"):
+    if c.get("big") and tile[0] * tile[1] <= 256:  # (the case is sized for 256-pixel tiles)
         sp = g["spans"].reshape(-1, 4).astype(np.int64)
         sp = sp[sp[:, 0] >= 0]
         tiles = ((sp[:, 1] // tile[0] - sp[:, 0] // tile[0] + 1) *
                  (sp[:, 3] // tile[1] - sp[:, 2] // tile[1] + 1))
         assert (tiles >= BIG_TILES).sum() >= 3, "no large splats in the large-splat case"
         assert (tiles < BIG_TILES).sum() >= 3, "no small splats in the large-splat case"
-    if c.get("dense"):
+    if c.get("dense") and tile[0] * tile[1] <= 512:  # (sized for tiles of at most 512 pixels)
         # a super-tile (8 x 8 tiles) with twice the pairs the LDS array holds:
         # its items (at most 2048) make at most two chunks of 1024, so one of
         # them holds more pairs than the array
